@@ -1,0 +1,246 @@
+"""Python access to the serial CPU oracle (``pmp_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by ``__graft_entry__.smoke``
+and by the benchmark's CPU-baseline leg; never by the library.  It does not
+import the HIP package either: workloads are passed in duck-typed (any object
+with ``lo, n, ghost, domain, dx, state, cic, sn, sinks, limits, r_k,
+r_gauss``), particle kinds as objects with ``fields`` and ``box_off``.
+
+Modes: ``"f64"`` (double buffer, sequential sums in array order) and
+``"fix64"`` (int64 buffer on the 2^-40 grid; exact and order-free).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pmp_oracle.c")
+_LIB = os.path.join(_HERE, "libpmp_oracle.so")
+CFLAGS = ["-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math",
+          "-shared", "-fPIC"]
+
+F64, FIX64 = 0, 1
+MODES = {"f64": F64, "fix64": FIX64}
+FIX_INV = 2.0 ** -40
+
+ERRORS = {-1: "EINVAL", -2: "EOUTSIDE", -3: "EREACH", -4: "EOVERFLOW", -5: "ENOMEM",
+          -6: "EOVERLAP"}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("nbox", C.c_int32), ("lo", C.c_void_p), ("n", C.c_void_p),
+                ("ghost", C.c_int32), ("domain", C.c_int32 * 3), ("dx", C.c_double),
+                ("nfield", C.c_int32)]
+
+
+class _Cic(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("m", C.c_void_p),
+                ("box_off", C.c_void_p)]
+
+
+class _Sn(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("m", C.c_void_p),
+                ("e", C.c_void_p), ("r", C.c_void_p), ("box_off", C.c_void_p)]
+
+
+class _Sinks(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("a", C.c_void_p),
+                ("box_off", C.c_void_p), ("r_k", C.c_double), ("r_gauss", C.c_double)]
+
+
+class _Limits(C.Structure):
+    _fields_ = [("rho_floor", C.c_double), ("rho_tr", C.c_double), ("cap", C.c_double),
+                ("eint_mode", C.c_int32)]
+
+
+class Counters(C.Structure):
+    _fields_ = [("touched", C.c_int64), ("bind", C.c_int64), ("lam", C.c_int64),
+                ("fall", C.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        vp, i32 = C.c_void_p, C.c_int
+        L.orc_exp.restype = C.c_double
+        L.orc_exp.argtypes = [C.c_double]
+        L.orc_buffer_elems.restype = C.c_int64
+        L.orc_buffer_elems.argtypes = [vp]
+        L.orc_state_elems.restype = C.c_int64
+        L.orc_state_elems.argtypes = [vp]
+        L.orc_deposit.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_fold.argtypes = [vp, i32, vp]
+        L.orc_sink_update.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_apply.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed: {ERRORS.get(rc, rc)}")
+
+
+def exp(x: float) -> float:
+    return lib().orc_exp(float(x))
+
+
+class Mesh:
+    """Keeps the ctypes mesh and the arrays it points at alive together."""
+
+    def __init__(self, lo, n, ghost, domain, dx, nfield):
+        self.lo = np.ascontiguousarray(np.asarray(lo, dtype=np.int32).reshape(-1, 3))
+        self.n = np.ascontiguousarray(np.asarray(n, dtype=np.int32).reshape(-1, 3))
+        self.ghost, self.domain, self.dx, self.nfield = int(ghost), tuple(domain), float(dx), int(nfield)
+        self.c = _Mesh(self.lo.shape[0], _ptr(self.lo), _ptr(self.n), self.ghost,
+                       (C.c_int32 * 3)(*self.domain), self.dx, self.nfield)
+
+    @classmethod
+    def of(cls, w):
+        return cls(w.lo, w.n, w.ghost, w.domain, w.dx, w.nfield)
+
+    @property
+    def buffer_elems(self):
+        return lib().orc_buffer_elems(C.byref(self.c))
+
+    @property
+    def state_elems(self):
+        return lib().orc_state_elems(C.byref(self.c))
+
+    def box_buffer(self, buf, b):
+        """View of box b's buffer as [F][nz+2g][ny+2g][nx+2g]."""
+        g = self.ghost
+        pads = [(int(nx) + 2 * g) * (int(ny) + 2 * g) * (int(nz) + 2 * g) for nx, ny, nz in self.n]
+        off = sum(pads[:b]) * self.nfield
+        nx, ny, nz = (int(v) + 2 * g for v in self.n[b])
+        return buf[off: off + self.nfield * nx * ny * nz].reshape(self.nfield, nz, ny, nx)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _kind(P, names, struct):
+    if P is None or P.n == 0:
+        return None, []
+    arrs = [_f64(P.fields[k]) for k in names]
+    off = np.ascontiguousarray(np.asarray(P.box_off, dtype=np.int64))
+    return struct(*[_ptr(a) for a in arrs], _ptr(off)), arrs + [off]
+
+
+def _limits(L):
+    return _Limits(float(L.rho_floor), float(L.rho_tr), float(L.cap), int(L.eint_mode))
+
+
+def deposit(w, mode, mesh=None, state64=None):
+    """Step 1. Returns (buffer, sink_w, sink_mreq)."""
+    m = MODES[mode]
+    mesh = mesh or Mesh.of(w)
+    keep = []
+    cic, a = _kind(w.cic, ["x", "y", "z", "m"], _Cic); keep += a
+    sn, a = _kind(w.sn, ["x", "y", "z", "m", "e", "r"], _Sn); keep += a
+    sk = None
+    nsink = 0
+    if w.sinks is not None and w.sinks.n > 0:
+        s4, a = _kind(w.sinks, ["x", "y", "z", "a"], _Cic); keep += a
+        sk = _Sinks(s4.x, s4.y, s4.z, s4.m, s4.box_off, float(w.r_k), float(w.r_gauss))
+        nsink = w.sinks.n
+    if state64 is None:
+        state64 = _f64(w.state)
+    lim = _limits(w.limits)
+    buf = np.empty(mesh.buffer_elems, dtype=np.float64 if m == F64 else np.int64)
+    sw = np.zeros(max(nsink, 1))
+    sm = np.zeros(max(nsink, 1))
+    rc = lib().orc_deposit(C.byref(mesh.c), m, C.byref(cic) if cic else None,
+                           C.byref(sn) if sn else None, C.byref(sk) if sk else None,
+                           C.byref(lim), _ptr(state64), _ptr(buf), _ptr(sw), _ptr(sm))
+    _check(rc, "deposit")
+    return buf, sw[:nsink], sm[:nsink]
+
+
+def fold(w, mode, buf, mesh=None):
+    """Step 2, in place."""
+    mesh = mesh or Mesh.of(w)
+    _check(lib().orc_fold(C.byref(mesh.c), MODES[mode], _ptr(buf)), "fold")
+    return buf
+
+
+def sink_update(w, mode, buf, sink_w, sink_mreq, mesh=None, state64=None):
+    """Step 4. Returns (dm, dpx, dpy, dpz) per sink."""
+    mesh = mesh or Mesh.of(w)
+    n = w.sinks.n
+    s4, keep = _kind(w.sinks, ["x", "y", "z", "a"], _Cic)
+    sk = _Sinks(s4.x, s4.y, s4.z, s4.m, s4.box_off, float(w.r_k), float(w.r_gauss))
+    if state64 is None:
+        state64 = _f64(w.state)
+    lim = _limits(w.limits)
+    outs = [np.zeros(n) for _ in range(4)]
+    sw, sm = _f64(sink_w), _f64(sink_mreq)
+    rc = lib().orc_sink_update(C.byref(mesh.c), MODES[mode], _ptr(state64), _ptr(buf),
+                               C.byref(sk), C.byref(lim), _ptr(sw), _ptr(sm),
+                               *[_ptr(o) for o in outs])
+    _check(rc, "sink_update")
+    return tuple(outs)
+
+
+def apply(w, mode, buf, mesh=None, state64=None, want_eta=False):
+    """Steps 3 + 5. Returns (new_state_f64, eta or None, counters dict)."""
+    mesh = mesh or Mesh.of(w)
+    st = _f64(w.state).copy() if state64 is None else state64.copy()
+    eta = np.empty(st.size // 5) if want_eta else None
+    lim = _limits(w.limits)
+    cnt = Counters()
+    rc = lib().orc_apply(C.byref(mesh.c), MODES[mode], _ptr(st), _ptr(buf), C.byref(lim),
+                         _ptr(eta), C.byref(cnt))
+    _check(rc, "apply")
+    return st, eta, cnt.as_dict()
+
+
+def step(w, mode, want_eta=False):
+    """One full pass: deposit, fold, sink update (before the mesh changes),
+    limit + apply.  Returns a dict of every intermediate."""
+    mesh = Mesh.of(w)
+    s64 = _f64(w.state)
+    buf, sw, sm = deposit(w, mode, mesh, s64)
+    pre = buf.copy()
+    fold(w, mode, buf, mesh)
+    out = {"buf_deposit": pre, "buf_fold": buf, "sink_w": sw, "sink_mreq": sm}
+    if w.sinks is not None and w.sinks.n > 0:
+        out["sink_d"] = sink_update(w, mode, buf, sw, sm, mesh, s64)
+    st, eta, cnt = apply(w, mode, buf, mesh, s64, want_eta)
+    out.update(state=st, eta=eta, counters=cnt)
+    return out
+
+
+def timed_step(w, mode="f64"):
+    """Wall time of one oracle pass (seconds), single thread."""
+    t0 = time.perf_counter()
+    step(w, mode)
+    return time.perf_counter() - t0

@@ -1,0 +1,672 @@
+/*
+ * Serial CPU oracle for the particle-mesh-particle step.  TEST INFRASTRUCTURE
+ * ONLY: see pmp_oracle.h for scope, layout and units.
+ *
+ * Compiled with: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
+ */
+#include "pmp_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define FIX_SCALE 1099511627776.0        /* 2^40: fixed-point scale */
+#define FIX_INV (1.0 / 1099511627776.0)  /* 2^-40 */
+#define FIX_LIMIT 4611686018427387904.0  /* 2^62: largest magnitude accepted */
+
+/* ------------------------------------------------------------------ helpers */
+
+/* Quantise v to the 2^-40 grid, round half to even (llrint in the default
+ * rounding mode).  Fails when the scaled value leaves (-2^62, 2^62). */
+static int q40(double v, int64_t *out) {
+  double s = v * FIX_SCALE;
+  if (!(fabs(s) < FIX_LIMIT)) return ORC_EOVERFLOW;
+  *out = llrint(s);
+  return ORC_OK;
+}
+
+/* int64 add without signed-overflow undefined behaviour. */
+static int64_t iadd(int64_t a, int64_t b) { return (int64_t)((uint64_t)a + (uint64_t)b); }
+
+static int64_t imod(int64_t a, int64_t n) {
+  int64_t r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+/* exp(x) for the sink kernel weights of Sec. 3.1.1, eq. "kernel".
+ * Method: Cody & Waite (1980) argument reduction x = k ln2 + r with ln2 split
+ * into a high part on the 2^-32 grid (29 significant bits, so k*hi is exact
+ * for |k| < 2^24)
+ * and a low part, then the Taylor series of exp(r) through degree 13 in Horner
+ * form on |r| <= ln2/2, then scaling by 2^k.  Written from the method, not
+ * from any library.  Accurate to a few ulp (checked against libm). */
+double orc_exp(double x) {
+  if (x != x) return x;
+  if (x > 709.0) return HUGE_VAL;
+  if (x < -745.0) return 0.0;
+  /* ln2_hi = ln 2 rounded to a multiple of 2^-32; ln2_lo = ln 2 - ln2_hi
+   * rounded to double; inv_ln2 = 1/ln 2 rounded to double */
+  const double ln2_hi = 0x1.62e42ffp-1;
+  const double ln2_lo = -0x1.718432a1b0e26p-35;
+  const double inv_ln2 = 0x1.71547652b82fep+0;
+  double k = nearbyint(x * inv_ln2);
+  double r = (x - k * ln2_hi) - k * ln2_lo;
+  /* coefficients 1/n!, n = 13 .. 0, each one correctly rounded division */
+  double p = 1.0 / 6227020800.0;
+  p = p * r + 1.0 / 479001600.0;
+  p = p * r + 1.0 / 39916800.0;
+  p = p * r + 1.0 / 3628800.0;
+  p = p * r + 1.0 / 362880.0;
+  p = p * r + 1.0 / 40320.0;
+  p = p * r + 1.0 / 5040.0;
+  p = p * r + 1.0 / 720.0;
+  p = p * r + 1.0 / 120.0;
+  p = p * r + 1.0 / 24.0;
+  p = p * r + 1.0 / 6.0;
+  p = p * r + 0.5;
+  p = p * r + 1.0;
+  p = p * r + 1.0;
+  return ldexp(p, (int)k);
+}
+
+typedef struct {
+  int64_t *soff;   /* state offset of box b (elements) */
+  int64_t *boff;   /* buffer offset of box b (elements) */
+  int32_t *owner;  /* owner box of each domain cell, or -1; NULL until built */
+} geom;
+
+static int64_t box_cells(const orc_mesh *M, int b) {
+  return (int64_t)M->n[3 * b] * M->n[3 * b + 1] * M->n[3 * b + 2];
+}
+static int64_t box_pad_cells(const orc_mesh *M, int b) {
+  int64_t g2 = 2 * (int64_t)M->ghost;
+  return (M->n[3 * b] + g2) * (M->n[3 * b + 1] + g2) * (M->n[3 * b + 2] + g2);
+}
+
+int64_t orc_buffer_elems(const orc_mesh *M) {
+  int64_t s = 0;
+  for (int b = 0; b < M->nbox; ++b) s += (int64_t)M->nfield * box_pad_cells(M, b);
+  return s;
+}
+int64_t orc_state_elems(const orc_mesh *M) {
+  int64_t s = 0;
+  for (int b = 0; b < M->nbox; ++b) s += 5 * box_cells(M, b);
+  return s;
+}
+
+static int check_mesh(const orc_mesh *M) {
+  if (!M || M->nbox < 1 || !M->lo || !M->n || M->ghost < 0) return ORC_EINVAL;
+  if (M->nfield != 5 && M->nfield != 6) return ORC_EINVAL;
+  if (!(M->dx > 0)) return ORC_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (M->domain[a] < 1) return ORC_EINVAL;
+  for (int b = 0; b < M->nbox; ++b)
+    for (int a = 0; a < 3; ++a) {
+      if (M->n[3 * b + a] < 1 || M->lo[3 * b + a] < 0) return ORC_EINVAL;
+      if (M->lo[3 * b + a] + M->n[3 * b + a] > M->domain[a]) return ORC_EINVAL;
+    }
+  return ORC_OK;
+}
+
+static void geom_free(geom *G) {
+  free(G->soff);
+  free(G->boff);
+  free(G->owner);
+}
+
+/* Offsets of every box, and (if want_owner) the map from a domain cell to the
+ * box that owns it, painted box by box so that overlaps are detected. */
+static int geom_build(const orc_mesh *M, geom *G, int want_owner) {
+  memset(G, 0, sizeof *G);
+  G->soff = (int64_t *)malloc(sizeof(int64_t) * (size_t)M->nbox);
+  G->boff = (int64_t *)malloc(sizeof(int64_t) * (size_t)M->nbox);
+  if (!G->soff || !G->boff) { geom_free(G); return ORC_ENOMEM; }
+  int64_t s = 0, q = 0;
+  for (int b = 0; b < M->nbox; ++b) {
+    G->soff[b] = s;
+    G->boff[b] = q;
+    s += 5 * box_cells(M, b);
+    q += (int64_t)M->nfield * box_pad_cells(M, b);
+  }
+  if (!want_owner) return ORC_OK;
+  int64_t nd = (int64_t)M->domain[0] * M->domain[1] * M->domain[2];
+  G->owner = (int32_t *)malloc(sizeof(int32_t) * (size_t)nd);
+  if (!G->owner) { geom_free(G); return ORC_ENOMEM; }
+  for (int64_t c = 0; c < nd; ++c) G->owner[c] = -1;
+  for (int b = 0; b < M->nbox; ++b) {
+    const int32_t *lo = M->lo + 3 * b, *n = M->n + 3 * b;
+    for (int64_t k = lo[2]; k < lo[2] + n[2]; ++k)
+      for (int64_t j = lo[1]; j < lo[1] + n[1]; ++j)
+        for (int64_t i = lo[0]; i < lo[0] + n[0]; ++i) {
+          int64_t c = (k * M->domain[1] + j) * M->domain[0] + i;
+          if (G->owner[c] != -1) { geom_free(G); return ORC_EOVERLAP; }
+          G->owner[c] = b;
+        }
+  }
+  return ORC_OK;
+}
+
+/* Buffer element of box b, field f, at global cell (i,j,k) taken without
+ * wrapping (it may lie in the ghost zone).  -1 if outside the padded box. */
+static int64_t buf_index(const orc_mesh *M, const geom *G, int b, int f, int64_t i,
+                         int64_t j, int64_t k) {
+  const int32_t *lo = M->lo + 3 * b, *n = M->n + 3 * b;
+  int64_t g = M->ghost;
+  int64_t px = n[0] + 2 * g, py = n[1] + 2 * g, pz = n[2] + 2 * g;
+  int64_t li = i - lo[0] + g, lj = j - lo[1] + g, lk = k - lo[2] + g;
+  if (li < 0 || lj < 0 || lk < 0 || li >= px || lj >= py || lk >= pz) return -1;
+  return G->boff[b] + (int64_t)f * px * py * pz + (lk * py + lj) * px + li;
+}
+
+/* Owned buffer element (field f) and state cell of the periodic image of a
+ * global cell; returns the owning box or -1. */
+static int owner_of(const orc_mesh *M, const geom *G, int64_t i, int64_t j, int64_t k,
+                    int64_t *iw, int64_t *jw, int64_t *kw) {
+  *iw = imod(i, M->domain[0]);
+  *jw = imod(j, M->domain[1]);
+  *kw = imod(k, M->domain[2]);
+  return G->owner[(*kw * M->domain[1] + *jw) * M->domain[0] + *iw];
+}
+
+static int64_t state_index(const orc_mesh *M, const geom *G, int b, int f, int64_t iw,
+                           int64_t jw, int64_t kw) {
+  const int32_t *lo = M->lo + 3 * b, *n = M->n + 3 * b;
+  int64_t li = iw - lo[0], lj = jw - lo[1], lk = kw - lo[2];
+  return G->soff[b] + (int64_t)f * box_cells(M, b) + (lk * n[1] + lj) * n[0] + li;
+}
+
+/* Host cell floor(x) must lie in box b (particles follow the mesh
+ * decomposition, Sec. 2.1). */
+static int host_in_box(const orc_mesh *M, int b, const int64_t h[3]) {
+  for (int a = 0; a < 3; ++a)
+    if (h[a] < M->lo[3 * b + a] || h[a] >= (int64_t)M->lo[3 * b + a] + M->n[3 * b + a])
+      return 0;
+  return 1;
+}
+
+/* Distance test of Sec. 2.1: a cell takes part when its centre lies within
+ * the kernel radius (inclusive).  Fixed evaluation order. */
+static double dist2(double x, double y, double z, int64_t i, int64_t j, int64_t k) {
+  double ddx = ((double)i + 0.5) - x;
+  double ddy = ((double)j + 0.5) - y;
+  double ddz = ((double)k + 0.5) - z;
+  return (ddx * ddx + ddy * ddy) + ddz * ddz;
+}
+
+/* Candidate index range along one axis for a sphere of radius r around p:
+ * every cell whose centre can satisfy |i + 1/2 - p| <= r. */
+static void sphere_range(double p, double r, int64_t *lo, int64_t *hi) {
+  *lo = (int64_t)floor(p - r - 0.5) - 1;
+  *hi = (int64_t)floor(p + r - 0.5) + 1;
+}
+
+static void add_f64(void *buf, int64_t idx, double v) { ((double *)buf)[idx] += v; }
+static void add_fix(void *buf, int64_t idx, int64_t q) {
+  int64_t *B = (int64_t *)buf;
+  B[idx] = iadd(B[idx], q);
+}
+
+/* ---------------------------------------------------------- Step 1: deposit */
+
+/* CIC mass assignment (cloud-in-cell, cell-centred): per axis t = x - 1/2,
+ * i0 = floor(t), f = t - i0, weights (1-f, f) on cells (i0, i0+1).  The
+ * paper's PM deposit (Sec. 3.1, item 1; Sec. 2.2 "steps 1, 2 and 5") does not
+ * name its assignment scheme; CIC is the textbook one. */
+static int deposit_cic(const orc_mesh *M, const geom *G, int mode, const orc_cic *P,
+                       void *buf, double V) {
+  for (int b = 0; b < M->nbox; ++b) {
+    for (int64_t p = P->box_off[b]; p < P->box_off[b + 1]; ++p) {
+      double pos[3] = {P->x[p], P->y[p], P->z[p]};
+      double m = P->m[p];
+      int64_t h[3], i0[3];
+      double w[3][2];
+      for (int a = 0; a < 3; ++a) {
+        h[a] = (int64_t)floor(pos[a]);
+        double t = pos[a] - 0.5;
+        double fl = floor(t);
+        double f = t - fl;
+        i0[a] = (int64_t)fl;
+        w[a][0] = 1.0 - f;
+        w[a][1] = f;
+      }
+      if (!host_in_box(M, b, h)) return ORC_EOUTSIDE;
+      int64_t qsum = 0;
+      for (int dk = 0; dk < 2; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+          for (int di = 0; di < 2; ++di) {
+            double wx = w[0][di], wy = w[1][dj], wz = w[2][dk];
+            if (wx == 0.0 || wy == 0.0 || wz == 0.0) continue;
+            double c = ((m * wx) * wy) * wz / V;
+            int64_t idx = buf_index(M, G, b, 0, i0[0] + di, i0[1] + dj, i0[2] + dk);
+            if (idx < 0) return ORC_EREACH;
+            if (mode == ORC_F64) {
+              add_f64(buf, idx, c);
+            } else {
+              int64_t q;
+              if (q40(c, &q)) return ORC_EOVERFLOW;
+              add_fix(buf, idx, q);
+              qsum += q;
+            }
+          }
+      if (mode == ORC_FIX64) {
+        /* remainder rule: the particle's total lands exactly, the rounding
+         * residue goes to the host cell (always a nonzero-weight member) */
+        int64_t Q;
+        if (q40(m / V, &Q)) return ORC_EOVERFLOW;
+        add_fix(buf, buf_index(M, G, b, 0, h[0], h[1], h[2]), Q - qsum);
+      }
+    }
+  }
+  return ORC_OK;
+}
+
+/* Uniform-sphere supernova injection: mass m and energy e shared equally over
+ * the N cells whose centres lie within r (Sec. 3.2.1, eq. "du" with full
+ * coverage and no momentum term).  Fields 0 (rho) and 4 (E). */
+static int deposit_sn(const orc_mesh *M, const geom *G, int mode, const orc_sn *P, void *buf,
+                      double V) {
+  for (int b = 0; b < M->nbox; ++b) {
+    for (int64_t p = P->box_off[b]; p < P->box_off[b + 1]; ++p) {
+      double x = P->x[p], y = P->y[p], z = P->z[p], m = P->m[p], e = P->e[p], r = P->r[p];
+      double r2 = r * r;
+      int64_t h[3] = {(int64_t)floor(x), (int64_t)floor(y), (int64_t)floor(z)};
+      if (!host_in_box(M, b, h)) return ORC_EOUTSIDE;
+      int64_t lo[3], hi[3];
+      sphere_range(x, r, &lo[0], &hi[0]);
+      sphere_range(y, r, &lo[1], &hi[1]);
+      sphere_range(z, r, &lo[2], &hi[2]);
+      int64_t N = 0, first[3] = {0, 0, 0};
+      int host_member = 0;
+      for (int64_t k = lo[2]; k <= hi[2]; ++k)
+        for (int64_t j = lo[1]; j <= hi[1]; ++j)
+          for (int64_t i = lo[0]; i <= hi[0]; ++i)
+            if (dist2(x, y, z, i, j, k) <= r2) {
+              if (N == 0) { first[0] = i; first[1] = j; first[2] = k; }
+              if (i == h[0] && j == h[1] && k == h[2]) host_member = 1;
+              ++N;
+            }
+      int only_host = (N == 0);
+      if (only_host) { N = 1; host_member = 1; }
+      double cr = m / ((double)N * V);
+      double ce = e / ((double)N * V);
+      int64_t qr = 0, qe = 0;
+      if (mode == ORC_FIX64) {
+        if (q40(cr, &qr) || q40(ce, &qe)) return ORC_EOVERFLOW;
+      }
+      for (int64_t k = lo[2]; k <= hi[2]; ++k)
+        for (int64_t j = lo[1]; j <= hi[1]; ++j)
+          for (int64_t i = lo[0]; i <= hi[0]; ++i) {
+            int in = only_host ? (i == h[0] && j == h[1] && k == h[2])
+                               : (dist2(x, y, z, i, j, k) <= r2);
+            if (!in) continue;
+            int64_t i0 = buf_index(M, G, b, 0, i, j, k);
+            int64_t i4 = buf_index(M, G, b, 4, i, j, k);
+            if (i0 < 0 || i4 < 0) return ORC_EREACH;
+            if (mode == ORC_F64) {
+              add_f64(buf, i0, cr);
+              add_f64(buf, i4, ce);
+            } else {
+              add_fix(buf, i0, qr);
+              add_fix(buf, i4, qe);
+            }
+          }
+      if (mode == ORC_FIX64) {
+        int64_t Qr, Qe;
+        if (q40(m / V, &Qr) || q40(e / V, &Qe)) return ORC_EOVERFLOW;
+        const int64_t *t = host_member ? h : first;
+        add_fix(buf, buf_index(M, G, b, 0, t[0], t[1], t[2]), Qr - N * qr);
+        add_fix(buf, buf_index(M, G, b, 4, t[0], t[1], t[2]), Qe - N * qe);
+      }
+    }
+  }
+  return ORC_OK;
+}
+
+/* Sink removal request (Sec. 3.1.1).  Per sink: Gaussian weights
+ * w = exp(-d^2/r_acc^2) over the kernel (eq. "kernel"), normalised by their
+ * sum (eq. "kernel_wgt"); the requested mass is a fixed fraction a of the gas
+ * mass in the kernel (the Bondi-Hoyle rate of eq. "mdot" is replaced by this
+ * request); each cell's removal is max(request * phi / V, rho - rho_Tr)
+ * (eq. "accretion_function" with the Truelove term).  The kernel sums are
+ * taken in 2^-40 fixed point so that they do not depend on summation order.
+ * Field 5 holds the removed density K >= 0. */
+static int deposit_sinks(const orc_mesh *M, const geom *G, int mode, const orc_sinks *S,
+                         const orc_limits *L, const double *state, void *buf, double V,
+                         double *sink_w, double *sink_mreq) {
+  double r2 = S->r_k * S->r_k;
+  double g2 = S->r_gauss * S->r_gauss;
+  for (int b = 0; b < M->nbox; ++b) {
+    for (int64_t s = S->box_off[b]; s < S->box_off[b + 1]; ++s) {
+      double x = S->x[s], y = S->y[s], z = S->z[s];
+      int64_t h[3] = {(int64_t)floor(x), (int64_t)floor(y), (int64_t)floor(z)};
+      if (!host_in_box(M, b, h)) return ORC_EOUTSIDE;
+      int64_t lo[3], hi[3];
+      sphere_range(x, S->r_k, &lo[0], &hi[0]);
+      sphere_range(y, S->r_k, &lo[1], &hi[1]);
+      sphere_range(z, S->r_k, &lo[2], &hi[2]);
+      int64_t Wq = 0, Mq = 0;
+      for (int64_t k = lo[2]; k <= hi[2]; ++k)
+        for (int64_t j = lo[1]; j <= hi[1]; ++j)
+          for (int64_t i = lo[0]; i <= hi[0]; ++i) {
+            double d2 = dist2(x, y, z, i, j, k);
+            if (!(d2 <= r2)) continue;
+            int64_t iw, jw, kw;
+            int ob = owner_of(M, G, i, j, k, &iw, &jw, &kw);
+            if (ob < 0) return ORC_EINVAL;
+            double rho = state[state_index(M, G, ob, 0, iw, jw, kw)];
+            double w = orc_exp(-(d2 / g2));
+            int64_t qw, qm;
+            if (q40(w, &qw) || q40(rho * V, &qm)) return ORC_EOVERFLOW;
+            Wq += qw;
+            Mq += qm;
+          }
+      sink_w[s] = 0.0;
+      sink_mreq[s] = 0.0;
+      if (Wq <= 0) continue;
+      double W = (double)Wq * FIX_INV;
+      double Mreq = S->a[s] * ((double)Mq * FIX_INV);
+      sink_w[s] = W;
+      sink_mreq[s] = Mreq;
+      int64_t qreq_sum = 0, first[3] = {0, 0, 0};
+      int host_member = 0, nmem = 0;
+      for (int64_t k = lo[2]; k <= hi[2]; ++k)
+        for (int64_t j = lo[1]; j <= hi[1]; ++j)
+          for (int64_t i = lo[0]; i <= hi[0]; ++i) {
+            double d2 = dist2(x, y, z, i, j, k);
+            if (!(d2 <= r2)) continue;
+            if (nmem++ == 0) { first[0] = i; first[1] = j; first[2] = k; }
+            if (i == h[0] && j == h[1] && k == h[2]) host_member = 1;
+            int64_t iw, jw, kw;
+            int ob = owner_of(M, G, i, j, k, &iw, &jw, &kw);
+            double rho = state[state_index(M, G, ob, 0, iw, jw, kw)];
+            double w = orc_exp(-(d2 / g2));
+            double kreq = (Mreq * w) / (W * V);
+            double tr = rho - L->rho_tr;
+            double kc = (tr > kreq) ? tr : kreq;
+            int64_t idx = buf_index(M, G, b, 5, i, j, k);
+            if (idx < 0) return ORC_EREACH;
+            if (mode == ORC_F64) {
+              add_f64(buf, idx, kc);
+            } else {
+              int64_t qk, qr;
+              if (q40(kc, &qk) || q40(kreq, &qr)) return ORC_EOVERFLOW;
+              add_fix(buf, idx, qk);
+              qreq_sum += qr;
+            }
+          }
+      if (mode == ORC_FIX64) {
+        int64_t Q;
+        if (q40(Mreq / V, &Q)) return ORC_EOVERFLOW;
+        const int64_t *t = host_member ? h : first;
+        add_fix(buf, buf_index(M, G, b, 5, t[0], t[1], t[2]), Q - qreq_sum);
+      }
+    }
+  }
+  return ORC_OK;
+}
+
+static int check_fix_range(const void *buf, int64_t n) {
+  const int64_t *B = (const int64_t *)buf;
+  const int64_t lim = (int64_t)1 << 62;
+  for (int64_t i = 0; i < n; ++i)
+    if (B[i] >= lim || B[i] <= -lim) return ORC_EOVERFLOW;
+  return ORC_OK;
+}
+
+/* Step 1 (Sec. 2.2, eq. "delta_u_buf"): zero the buffer, then add every
+ * particle's deposition function; CIC first, then supernovae, then sinks,
+ * each in array order. */
+int orc_deposit(const orc_mesh *M, int mode, const orc_cic *cic, const orc_sn *sn,
+                const orc_sinks *sk, const orc_limits *L, const double *state, void *buf,
+                double *sink_w, double *sink_mreq) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (mode != ORC_F64 && mode != ORC_FIX64) return ORC_EINVAL;
+  if (sk && (M->nfield != 6 || !state || !L || !sink_w || !sink_mreq)) return ORC_EINVAL;
+  geom G;
+  rc = geom_build(M, &G, sk != NULL);
+  if (rc) return rc;
+  int64_t nb = orc_buffer_elems(M);
+  memset(buf, 0, (size_t)nb * 8);
+  double V = (M->dx * M->dx) * M->dx;
+  if (cic) rc = deposit_cic(M, &G, mode, cic, buf, V);
+  if (!rc && sn) rc = deposit_sn(M, &G, mode, sn, buf, V);
+  if (!rc && sk) rc = deposit_sinks(M, &G, mode, sk, L, state, buf, V, sink_w, sink_mreq);
+  if (!rc && mode == ORC_FIX64) rc = check_fix_range(buf, nb);
+  geom_free(&G);
+  return rc;
+}
+
+/* ------------------------------------------------------------- Step 2: fold */
+
+/* Sec. 2.2 Step 2: every ghost cell of every box is added into the owned cell
+ * of whichever box owns its periodic image.  Ghost cells are only read and
+ * owned cells only written, so the result is the plain sum. */
+int orc_fold(const orc_mesh *M, int mode, void *buf) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  geom G;
+  rc = geom_build(M, &G, 1);
+  if (rc) return rc;
+  int64_t g = M->ghost;
+  for (int b = 0; b < M->nbox; ++b) {
+    const int32_t *lo = M->lo + 3 * b, *n = M->n + 3 * b;
+    for (int64_t lk = 0; lk < n[2] + 2 * g; ++lk)
+      for (int64_t lj = 0; lj < n[1] + 2 * g; ++lj)
+        for (int64_t li = 0; li < n[0] + 2 * g; ++li) {
+          int interior = (li >= g && li < n[0] + g) && (lj >= g && lj < n[1] + g) &&
+                         (lk >= g && lk < n[2] + g);
+          if (interior) continue;
+          int64_t i = lo[0] + li - g, j = lo[1] + lj - g, k = lo[2] + lk - g;
+          int64_t iw, jw, kw;
+          int ob = owner_of(M, &G, i, j, k, &iw, &jw, &kw);
+          if (ob < 0) continue; /* no owner: contribution leaves this level */
+          for (int f = 0; f < M->nfield; ++f) {
+            int64_t src = buf_index(M, &G, b, f, i, j, k);
+            int64_t dst = buf_index(M, &G, ob, f, iw, jw, kw);
+            if (mode == ORC_F64)
+              ((double *)buf)[dst] += ((double *)buf)[src];
+            else
+              add_fix(buf, dst, ((int64_t *)buf)[src]);
+          }
+        }
+  }
+  if (mode == ORC_FIX64) rc = check_fix_range(buf, orc_buffer_elems(M));
+  geom_free(&G);
+  return rc;
+}
+
+/* ------------------------------------------------------- Step 3: limiters */
+
+/* Removal limiter of Sec. 3.1.1: a cell loses at most cap*rho unless the
+ * Truelove condition asks for more, and never falls below rho_floor.
+ * Returns the limited removal Kl for a requested removal K >= 0. */
+static double limited_removal(double K, double rho, const orc_limits *L) {
+  if (!(K > 0.0)) return 0.0;
+  double capped = (K < L->cap * rho) ? K : L->cap * rho;
+  double tr = rho - L->rho_tr;
+  double lim = (capped > tr) ? capped : tr;
+  double room = rho - L->rho_floor;
+  if (room < 0.0) room = 0.0;
+  return (lim < room) ? lim : room;
+}
+
+static double buf_value(int mode, const void *buf, int64_t idx) {
+  if (mode == ORC_F64) return ((const double *)buf)[idx];
+  return (double)((const int64_t *)buf)[idx] * FIX_INV;
+}
+
+/* ---------------------------------------------------- Step 4: sink update */
+
+/* Sec. 2.2 Step 4: each sink re-evaluates its deposition function and gains
+ * the limited amount, sum_c eta_c k_c V (mass) and the same times the cell
+ * velocity p/rho (momentum).  eta_c = Kl_c / K_c from the folded buffer and
+ * the state before Step 5. */
+int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void *buf,
+                    const orc_sinks *S, const orc_limits *L, const double *sink_w,
+                    const double *sink_mreq, double *dm, double *dpx, double *dpy,
+                    double *dpz) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (M->nfield != 6) return ORC_EINVAL;
+  geom G;
+  rc = geom_build(M, &G, 1);
+  if (rc) return rc;
+  double V = (M->dx * M->dx) * M->dx;
+  double r2 = S->r_k * S->r_k;
+  double g2 = S->r_gauss * S->r_gauss;
+  for (int b = 0; b < M->nbox && !rc; ++b) {
+    for (int64_t s = S->box_off[b]; s < S->box_off[b + 1]; ++s) {
+      double x = S->x[s], y = S->y[s], z = S->z[s];
+      double W = sink_w[s], Mreq = sink_mreq[s];
+      double sm = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+      int64_t qm = 0, qx = 0, qy = 0, qz = 0;
+      if (W > 0.0) {
+        int64_t lo[3], hi[3];
+        sphere_range(x, S->r_k, &lo[0], &hi[0]);
+        sphere_range(y, S->r_k, &lo[1], &hi[1]);
+        sphere_range(z, S->r_k, &lo[2], &hi[2]);
+        for (int64_t k = lo[2]; k <= hi[2]; ++k)
+          for (int64_t j = lo[1]; j <= hi[1]; ++j)
+            for (int64_t i = lo[0]; i <= hi[0]; ++i) {
+              double d2 = dist2(x, y, z, i, j, k);
+              if (!(d2 <= r2)) continue;
+              int64_t iw, jw, kw;
+              int ob = owner_of(M, &G, i, j, k, &iw, &jw, &kw);
+              double rho = state[state_index(M, &G, ob, 0, iw, jw, kw)];
+              double w = orc_exp(-(d2 / g2));
+              double kreq = (Mreq * w) / (W * V);
+              double tr = rho - L->rho_tr;
+              double kc = (tr > kreq) ? tr : kreq;
+              double K = buf_value(mode, buf, buf_index(M, &G, ob, 5, iw, jw, kw));
+              double Kl = limited_removal(K, rho, L);
+              double eta = (K > 0.0) ? Kl / K : 1.0;
+              double term = (eta * kc) * V;
+              double vx = state[state_index(M, &G, ob, 1, iw, jw, kw)] / rho;
+              double vy = state[state_index(M, &G, ob, 2, iw, jw, kw)] / rho;
+              double vz = state[state_index(M, &G, ob, 3, iw, jw, kw)] / rho;
+              if (mode == ORC_F64) {
+                sm += term;
+                sx += term * vx;
+                sy += term * vy;
+                sz += term * vz;
+              } else {
+                int64_t a, bq, c, d;
+                if (q40(term, &a) || q40(term * vx, &bq) || q40(term * vy, &c) ||
+                    q40(term * vz, &d)) {
+                  rc = ORC_EOVERFLOW;
+                  break;
+                }
+                qm += a; qx += bq; qy += c; qz += d;
+              }
+            }
+      }
+      if (mode == ORC_FIX64) {
+        sm = (double)qm * FIX_INV;
+        sx = (double)qx * FIX_INV;
+        sy = (double)qy * FIX_INV;
+        sz = (double)qz * FIX_INV;
+      }
+      dm[s] = sm;
+      dpx[s] = sx;
+      dpy[s] = sy;
+      dpz[s] = sz;
+    }
+  }
+  geom_free(&G);
+  return rc;
+}
+
+/* ------------------------------------------- Steps 3 + 5: limit and apply */
+
+/* Per owned cell, in double precision:
+ *  - sink removal K is limited to Kl (Sec. 3.1.1) and removes the fraction
+ *    Kl/rho of the cell's mass, momentum and total energy (the accretion
+ *    function removes gas at the cell's own velocity and specific energy);
+ *  - sources (CIC mass, supernova mass/energy, momentum) are added in full,
+ *    except that the momentum change is scaled by the largest lambda in [0,1]
+ *    that keeps the internal energy at or above its floor (Sec. 3.2.1,
+ *    eq. "lambda");  floor mode 0: e_int >= 0; mode 1: the specific internal
+ *    energy of the cell before the update (the paper's C_V T);
+ *  - if even lambda = 0 violates the floor, E is raised to the floor and the
+ *    cell is counted (the paper does not treat this case).
+ * Step 5 then writes U + Delta U^lim. */
+int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
+              const orc_limits *L, double *eta, orc_counters *cnt) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  geom G;
+  rc = geom_build(M, &G, 0);
+  if (rc) return rc;
+  orc_counters C = {0, 0, 0, 0};
+  int64_t ecell = 0;
+  for (int b = 0; b < M->nbox; ++b) {
+    const int32_t *lo = M->lo + 3 * b, *n = M->n + 3 * b;
+    int64_t nc = box_cells(M, b);
+    double *S = state + G.soff[b];
+    for (int64_t k = 0; k < n[2]; ++k)
+      for (int64_t j = 0; j < n[1]; ++j)
+        for (int64_t i = 0; i < n[0]; ++i) {
+          int64_t c = (k * n[1] + j) * n[0] + i;
+          int64_t gi = lo[0] + i, gj = lo[1] + j, gk = lo[2] + k;
+          double rho = S[c], px = S[nc + c], py = S[2 * nc + c], pz = S[3 * nc + c],
+                 E = S[4 * nc + c];
+          double Dr = buf_value(mode, buf, buf_index(M, &G, b, 0, gi, gj, gk));
+          double qx = buf_value(mode, buf, buf_index(M, &G, b, 1, gi, gj, gk));
+          double qy = buf_value(mode, buf, buf_index(M, &G, b, 2, gi, gj, gk));
+          double qz = buf_value(mode, buf, buf_index(M, &G, b, 3, gi, gj, gk));
+          double DE = buf_value(mode, buf, buf_index(M, &G, b, 4, gi, gj, gk));
+          double K = 0.0;
+          if (M->nfield == 6) K = buf_value(mode, buf, buf_index(M, &G, b, 5, gi, gj, gk));
+          double Kl = limited_removal(K, rho, L);
+          double et = (K > 0.0) ? Kl / K : 1.0;
+          if (K > 0.0) {
+            C.touched++;
+            if (Kl < K) C.bind++;
+          }
+          double f = 1.0 - Kl / rho;
+          double rho1 = f * rho + Dr;
+          double E1 = f * E + DE;
+          double p0x = f * px, p0y = f * py, p0z = f * pz;
+          double emin = 0.0;
+          if (L->eint_mode == 1) {
+            double eint0 = E - ((px * px + py * py) + pz * pz) / (2.0 * rho);
+            emin = rho1 * (eint0 / rho);
+          }
+          double Kc = (2.0 * rho1) * (E1 - emin);
+          double sx = p0x + qx, sy = p0y + qy, sz = p0z + qz;
+          double g1 = ((sx * sx + sy * sy) + sz * sz) - Kc;
+          double pp = (p0x * p0x + p0y * p0y) + p0z * p0z;
+          double g0 = pp - Kc;
+          double lam;
+          if (g1 <= 0.0) {
+            lam = 1.0;
+          } else if (g0 <= 0.0) {
+            /* largest root of |q|^2 l^2 + 2 (p0.q) l + (|p0|^2 - Kc) = 0,
+             * in the cancellation-free form */
+            double qq = (qx * qx + qy * qy) + qz * qz;
+            double pq = (p0x * qx + p0y * qy) + p0z * qz;
+            double disc = pq * pq - qq * g0;
+            double sq = sqrt(disc);
+            lam = (pq > 0.0) ? (-g0) / (pq + sq) : (sq - pq) / qq;
+            if (lam > 1.0) lam = 1.0;
+            if (lam < 0.0) lam = 0.0;
+          } else {
+            lam = 0.0;
+            E1 = emin + pp / (2.0 * rho1);
+            C.fall++;
+          }
+          if (lam < 1.0) C.lam++;
+          S[c] = rho1;
+          S[nc + c] = p0x + lam * qx;
+          S[2 * nc + c] = p0y + lam * qy;
+          S[3 * nc + c] = p0z + lam * qz;
+          S[4 * nc + c] = E1;
+          if (eta) eta[ecell + c] = et;
+        }
+    ecell += nc;
+  }
+  if (cnt) *cnt = C;
+  geom_free(&G);
+  return rc;
+}
