@@ -1,0 +1,242 @@
+/*
+ * libpmp — particle-mesh-particle interactions on one MI355X (gfx950).
+ *
+ * Implements the data-parallel hot path of He et al. (2025), "A GPU-optimised
+ * particle-mesh-particle algorithm" (Quokka), Sec. 2.2:
+ *
+ *   pmp_deposit      Step 1  particles -> zeroed, ghost-zoned buffer mesh
+ *                            (eq. "delta_u_buf"), atomic adds
+ *   pmp_ghost_fold   Step 2  ghost zones -> owning cells (periodic images and
+ *                            neighbouring boxes held by this GPU)
+ *   pmp_sink_update  Step 4  sinks gain the limited removal
+ *   pmp_apply        Steps 3 + 5  cell-wise limiter, then U := U + dU_lim
+ *
+ * Calling order for one step: deposit, ghost_fold, sink_update (only with
+ * sinks; it reads the state before the mesh update), apply.  pmp_step runs
+ * all of them; pmp_graph_build/pmp_graph_launch capture and replay several
+ * steps as one HIP graph.
+ *
+ * Conventions for every function:
+ *  - returns PMP_OK (0) or a negative PMP_E* code; never aborts, never throws;
+ *    pmp_last_error() returns a message for the calling thread's last error;
+ *  - pointers named "device" must be device memory (hipMalloc / PyTorch CUDA
+ *    tensors) readable and writable by the GPU the context was created on;
+ *    pointers named "host" are ordinary host memory;
+ *  - the caller owns every array it passes; the library never frees them and
+ *    keeps no pointer to them after the call returns (the graph functions
+ *    excepted, see there);
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream); work is
+ *    enqueued asynchronously and no call synchronises the stream except
+ *    pmp_get_status and pmp_autotune;
+ *  - data-dependent problems found on the GPU (a particle outside its box, a
+ *    stencil reaching beyond the ghost zone, fixed-point overflow, NaN input,
+ *    an infeasible energy floor) do not abort: the offending contribution is
+ *    skipped and a bit is set in the status word read by pmp_get_status.
+ *
+ * Units and layout (Sec. 2.1, "Formulation of the problem"):
+ *  - positions are in cell units of the global index space: a particle at x
+ *    lies in cell floor(x); cell (i,j,k) has its centre at (i+1/2, j+1/2,
+ *    k+1/2); dx is the cell edge and V = dx^3;
+ *  - box b owns global cells [lo_b, lo_b + n_b) (x, y, z); boxes must not
+ *    overlap; the domain is periodic along all three axes;
+ *  - state = concatenation over boxes, in box order, of [5][nz][ny][nx]
+ *    arrays (rho, px, py, pz, E), x fastest; float or double;
+ *  - buffer = concatenation over boxes of [F][nz+2g][ny+2g][nx+2g], F = 5
+ *    (rho, px, py, pz, E) or 6 with the sink removal channel K >= 0;
+ *    float, double, or int64 fixed point with value = q * 2^-40;
+ *  - each particle kind is a set of device float64 arrays grouped by box,
+ *    with a device int64 CSR array box_off[nbox+1] (particles of box b are
+ *    [box_off[b], box_off[b+1])); floor(x) must lie in box b.
+ */
+#ifndef PMP_H
+#define PMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PMP_OK 0
+#define PMP_EINVAL (-1)       /* bad argument (null pointer, bad enum, size mismatch) */
+#define PMP_ERANGE (-2)       /* geometry: overlapping boxes, box outside the domain,
+                                 ghost width smaller than a kernel's reach */
+#define PMP_EDEVICE (-3)      /* a HIP runtime call failed */
+#define PMP_ENOMEM (-4)       /* device or host allocation failed */
+#define PMP_EUNSUPPORTED (-5) /* valid request this build does not implement */
+
+/* status-word bits (pmp_status.flags) */
+#define PMP_FLAG_OUTSIDE 0x1u   /* particle's host cell not in its box (skipped) */
+#define PMP_FLAG_REACH 0x2u     /* stencil member outside the ghost zone (skipped) */
+#define PMP_FLAG_OVERFLOW 0x4u  /* fixed-point value outside (-2^62, 2^62) */
+#define PMP_FLAG_NAN 0x8u       /* non-finite particle or state value seen */
+#define PMP_FLAG_FLOOR 0x10u    /* energy floor infeasible: E raised (counted in fall) */
+
+typedef enum { PMP_ACC_F32 = 0, PMP_ACC_F64 = 1, PMP_ACC_FIX64 = 2 } pmp_acc_t;
+typedef enum { PMP_STATE_F32 = 0, PMP_STATE_F64 = 1 } pmp_state_t;
+
+typedef struct pmp_ctx pmp_ctx;
+
+/* Mesh description, copied into the context by pmp_create. */
+typedef struct {
+  int32_t nbox;        /* number of boxes (>= 1) */
+  const int32_t *lo;   /* host [nbox][3]: first owned global cell (x, y, z) */
+  const int32_t *n;    /* host [nbox][3]: owned cells per axis (>= 1) */
+  int32_t ghost;       /* ghost width g (>= 1 when CIC particles are deposited,
+                          >= floor(r + 1/2) for a sphere of radius r) */
+  int32_t domain[3];   /* periodic domain in cells */
+  double dx;           /* cell edge (> 0) */
+  int32_t acc;         /* pmp_acc_t: buffer accumulator type */
+  int32_t state;       /* pmp_state_t: state element type */
+  int32_t with_sinks;  /* 1: buffer has the sixth (removal) field */
+} pmp_layout;
+
+/* CIC mass particles (Sec. 2.2: PM deposit using steps 1, 2 and 5). */
+typedef struct {
+  const double *x, *y, *z, *m;  /* device [n] */
+  int64_t n;
+  const int64_t *box_off;       /* device [nbox+1] */
+} pmp_cic;
+
+/* Supernova particles: mass m and energy e spread uniformly over the cells
+ * whose centres lie within radius r (Sec. 3.2.1, eq. "du" with full coverage
+ * and no momentum term). */
+typedef struct {
+  const double *x, *y, *z, *m, *e, *r;  /* device [n] */
+  int64_t n;
+  const int64_t *box_off;               /* device [nbox+1] */
+  double r_max;                         /* host: largest r, for the ghost check */
+} pmp_sn;
+
+/* Sink particles (Sec. 3.1.1): each requests the fraction a of the gas mass
+ * within r_k, spread with Gaussian weights exp(-d^2/r_gauss^2) (eqs. "kernel",
+ * "kernel_wgt", "accretion_function").  Single-box layouts only. */
+typedef struct {
+  const double *x, *y, *z, *a;  /* device [n] */
+  int64_t n;
+  const int64_t *box_off;       /* device [nbox+1] */
+  double r_k, r_gauss;          /* host scalars, cells */
+} pmp_sinks;
+
+/* Limiter parameters (Sec. 3.1.1 removal limiter, Sec. 3.2.1 eq. "lambda"). */
+typedef struct {
+  double rho_floor;   /* density never drops below this by removal */
+  double rho_tr;      /* Truelove density (+inf disables the term) */
+  double cap;         /* largest removed fraction per step (0.25 in the paper) */
+  int32_t eint_mode;  /* 0: e_int >= 0; 1: specific e_int may not drop */
+} pmp_limits;
+
+/* Device-side diagnostics accumulated since the last reset. */
+typedef struct {
+  uint32_t flags;     /* PMP_FLAG_* */
+  uint32_t reserved;
+  int64_t touched;    /* apply: cells with K > 0 */
+  int64_t bind;       /* apply: cells where the removal limiter binds */
+  int64_t lam;        /* apply: cells with lambda < 1 */
+  int64_t fall;       /* apply: cells where the floor was infeasible */
+} pmp_status;
+
+/* Kernel tuning; pmp_create fills defaults, pmp_autotune overwrites. */
+typedef struct {
+  int32_t deposit_path;  /* 0: direct global atomics; 1: binned, dense tiles
+                            privatised in LDS, the rest direct */
+  int32_t tile;          /* tile edge in cells for binning: 4, 8 or 16 */
+  int32_t dense_min;     /* particles per tile at which a tile goes to LDS */
+  int32_t chunk;         /* largest particle count per LDS work item */
+  int32_t block;         /* threads per block of the streaming kernels */
+  int32_t grid_per_cu;   /* resident blocks per CU for persistent launches */
+  int32_t sn_lanes;      /* lanes cooperating on one supernova: 16, 32 or 64 */
+  int32_t reserved;
+} pmp_tuning;
+
+/* Create a context on the current HIP device.  Copies the layout, checks the
+ * geometry (PMP_ERANGE on overlap or boxes outside the domain) and builds the
+ * ghost-fold plan.  Allocates device memory for the box table, the fold plan
+ * and the status word. */
+int pmp_create(pmp_ctx **out, const pmp_layout *L);
+void pmp_destroy(pmp_ctx *ctx);
+
+/* Element counts of the state and buffer arrays for this layout (host out). */
+int pmp_sizes(const pmp_ctx *ctx, int64_t *state_elems, int64_t *buffer_elems,
+              int64_t *owned_cells);
+
+/* Step 1 (Sec. 2.2, eq. "delta_u_buf").  Zeroes the device buffer, then adds
+ * every particle's deposition function with atomic adds.  state (device) is
+ * read by sinks only (may be NULL without sinks).  Any of cic, sn, sinks may
+ * be NULL.  limits is read for rho_tr (Truelove term) when sinks are given.
+ * In PMP_ACC_FIX64 every contribution is rounded to the 2^-40 grid (half to
+ * even) and each particle's rounding residue goes to its host cell, so the
+ * buffer total equals the particle total exactly and the result does not
+ * depend on execution order. */
+int pmp_deposit(pmp_ctx *ctx, void *buf, const void *state, const pmp_cic *cic,
+                const pmp_sn *sn, const pmp_sinks *sinks, const pmp_limits *limits,
+                void *stream);
+
+/* Step 2 (Sec. 2.2; App. A.2).  Adds every ghost cell into the owned cell of
+ * the box that holds its periodic image; each owned cell gathers its
+ * contributions in one fixed order (source box lo z, y, x, then periodic
+ * shift z, y, x), so the fold is deterministic in every accumulator type. */
+int pmp_ghost_fold(pmp_ctx *ctx, void *buf, void *stream);
+
+/* Step 4 (Sec. 2.2).  For each sink, re-evaluates its removal k_c over its
+ * kernel and writes dm = sum_c eta_c k_c V and dp = sum_c eta_c k_c V p_c/rho_c
+ * to the device float64 arrays dm, dpx, dpy, dpz [sinks->n], where
+ * eta_c = Kl_c / K_c from the folded buffer and the state before Step 5.
+ * Must follow pmp_ghost_fold and precede pmp_apply; needs the same sinks and
+ * limits as pmp_deposit. */
+int pmp_sink_update(pmp_ctx *ctx, const void *state, const void *buf, const pmp_sinks *sinks,
+                    const pmp_limits *limits, double *dm, double *dpx, double *dpy,
+                    double *dpz, void *stream);
+
+/* Steps 3 + 5.  In place on the device state: per owned cell, in double
+ * precision, the removal K is limited to Kl = min(max(min(K, cap rho),
+ * rho - rho_tr), rho - rho_floor) (Sec. 3.1.1) and removes the fraction Kl/rho
+ * of the cell; sources are added, the momentum source scaled by the largest
+ * lambda in [0, 1] keeping e_int at its floor (Sec. 3.2.1, eq. "lambda").
+ * eta (device, may be NULL) receives Kl/K per owned cell (1 where K = 0),
+ * float64, in state cell order. */
+int pmp_apply(pmp_ctx *ctx, void *state, const void *buf, const pmp_limits *limits,
+              double *eta, void *stream);
+
+/* One whole step: deposit, fold, sink update (if sinks), apply.  sink_out
+ * (device) is four float64 arrays [4][sinks->n] (dm, dpx, dpy, dpz) or NULL
+ * without sinks. */
+int pmp_step(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic, const pmp_sn *sn,
+             const pmp_sinks *sinks, const pmp_limits *limits, double *sink_out, void *stream);
+
+/* Capture nsteps consecutive pmp_step calls into one HIP graph kept by the
+ * context (replacing any previous one).  The device pointers are baked into
+ * the graph and must stay valid until the graph is rebuilt or the context is
+ * destroyed.  Enqueues nothing on stream; uses it only to order the capture. */
+int pmp_graph_build(pmp_ctx *ctx, int nsteps, void *state, void *buf, const pmp_cic *cic,
+                    const pmp_sn *sn, const pmp_sinks *sinks, const pmp_limits *limits,
+                    double *sink_out, void *stream);
+/* Replay the captured graph on stream. */
+int pmp_graph_launch(pmp_ctx *ctx, void *stream);
+
+/* Synchronise the context's device, copy the status to *out (host), and
+ * clear it if reset != 0. */
+int pmp_get_status(pmp_ctx *ctx, pmp_status *out, int reset);
+
+int pmp_get_tuning(const pmp_ctx *ctx, pmp_tuning *out);
+int pmp_set_tuning(pmp_ctx *ctx, const pmp_tuning *t);
+
+/* Time candidate tunings on the given inputs (each candidate runs whole
+ * steps on scratch copies made from state and buf, so the caller's arrays are
+ * left as they were) and keep the fastest.  Synchronises the stream.
+ * best_ms (host, may be NULL) receives the winning step time. */
+int pmp_autotune(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic, const pmp_sn *sn,
+                 const pmp_sinks *sinks, const pmp_limits *limits, double *sink_out,
+                 void *stream, double *best_ms);
+
+/* Bandwidth calibration: copy bytes from device src to device dst with a
+ * plain streaming kernel (16-byte loads and stores). */
+int pmp_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+const char *pmp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

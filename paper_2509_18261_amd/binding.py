@@ -1,0 +1,290 @@
+"""ctypes binding for libpmp.so (include/pmp.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  Functions keep the C names (``pmp_create``, ``pmp_deposit``
+...) and take PyTorch CUDA tensors where the C side takes device pointers;
+``Context`` bundles a layout with the tensors of one workload.
+
+Importing this module loads the library and raises if it is missing: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmp.so")
+
+PMP_ACC_F32, PMP_ACC_F64, PMP_ACC_FIX64 = 0, 1, 2
+PMP_STATE_F32, PMP_STATE_F64 = 0, 1
+ACC = {"f32": PMP_ACC_F32, "f64": PMP_ACC_F64, "fix64": PMP_ACC_FIX64}
+FLAGS = {0x1: "OUTSIDE", 0x2: "REACH", 0x4: "OVERFLOW", 0x8: "NAN", 0x10: "FLOOR"}
+ERRORS = {-1: "EINVAL", -2: "ERANGE", -3: "EDEVICE", -4: "ENOMEM", -5: "EUNSUPPORTED"}
+
+
+class PmpError(RuntimeError):
+    def __init__(self, code, fn, msg):
+        super().__init__(f"{fn}: {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class pmp_layout(C.Structure):
+    _fields_ = [("nbox", C.c_int32), ("lo", C.c_void_p), ("n", C.c_void_p),
+                ("ghost", C.c_int32), ("domain", C.c_int32 * 3), ("dx", C.c_double),
+                ("acc", C.c_int32), ("state", C.c_int32), ("with_sinks", C.c_int32)]
+
+
+class pmp_cic(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("m", C.c_void_p),
+                ("n", C.c_int64), ("box_off", C.c_void_p)]
+
+
+class pmp_sn(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("m", C.c_void_p),
+                ("e", C.c_void_p), ("r", C.c_void_p), ("n", C.c_int64), ("box_off", C.c_void_p),
+                ("r_max", C.c_double)]
+
+
+class pmp_sinks(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("a", C.c_void_p),
+                ("n", C.c_int64), ("box_off", C.c_void_p), ("r_k", C.c_double),
+                ("r_gauss", C.c_double)]
+
+
+class pmp_limits(C.Structure):
+    _fields_ = [("rho_floor", C.c_double), ("rho_tr", C.c_double), ("cap", C.c_double),
+                ("eint_mode", C.c_int32)]
+
+
+class pmp_status(C.Structure):
+    _fields_ = [("flags", C.c_uint32), ("reserved", C.c_uint32), ("touched", C.c_int64),
+                ("bind", C.c_int64), ("lam", C.c_int64), ("fall", C.c_int64)]
+
+    def as_dict(self):
+        d = {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        d["flag_names"] = [v for b, v in FLAGS.items() if self.flags & b]
+        return d
+
+
+class pmp_tuning(C.Structure):
+    _fields_ = [("deposit_path", C.c_int32), ("tile", C.c_int32), ("dense_min", C.c_int32),
+                ("chunk", C.c_int32), ("block", C.c_int32), ("grid_per_cu", C.c_int32),
+                ("sn_lanes", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
+_VP, _I = C.c_void_p, C.c_int
+# (name, restype, argtypes) for every exported function of include/pmp.h
+SIGNATURES = [
+    ("pmp_create", _I, [C.POINTER(C.c_void_p), C.POINTER(pmp_layout)]),
+    ("pmp_destroy", None, [_VP]),
+    ("pmp_sizes", _I, [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("pmp_deposit", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
+                         C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP]),
+    ("pmp_ghost_fold", _I, [_VP, _VP, _VP]),
+    ("pmp_sink_update", _I, [_VP, _VP, _VP, C.POINTER(pmp_sinks), C.POINTER(pmp_limits),
+                             _VP, _VP, _VP, _VP, _VP]),
+    ("pmp_apply", _I, [_VP, _VP, _VP, C.POINTER(pmp_limits), _VP, _VP]),
+    ("pmp_step", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
+                      C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP, _VP]),
+    ("pmp_graph_build", _I, [_VP, _I, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
+                             C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP, _VP]),
+    ("pmp_graph_launch", _I, [_VP, _VP]),
+    ("pmp_get_status", _I, [_VP, C.POINTER(pmp_status), _I]),
+    ("pmp_get_tuning", _I, [_VP, C.POINTER(pmp_tuning)]),
+    ("pmp_set_tuning", _I, [_VP, C.POINTER(pmp_tuning)]),
+    ("pmp_autotune", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
+                          C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP, _VP,
+                          C.POINTER(C.c_double)]),
+    ("pmp_stream_copy", _I, [_VP, _VP, C.c_size_t, _VP]),
+    ("pmp_last_error", C.c_char_p, []),
+]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpmp.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    for name, res, args in SIGNATURES:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _call(name, *args):
+    rc = getattr(lib, name)(*args)
+    if rc != 0:
+        raise PmpError(rc, name, lib.pmp_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ objects
+
+class Context:
+    """A pmp context plus the device tensors of one workload.
+
+    ``w`` is a workload (paper_2509_18261_amd.workloads.Workload); ``acc`` is
+    "f32", "f64" or "fix64".  State type follows ``w.state.dtype``."""
+
+    def __init__(self, w, acc="fix64", device="cuda"):
+        import torch
+        self.w = w
+        self.acc = acc
+        self.device = device
+        self.lo = np.ascontiguousarray(np.asarray(w.lo, dtype=np.int32))
+        self.n = np.ascontiguousarray(np.asarray(w.n, dtype=np.int32))
+        st_dtype = np.dtype(w.state.dtype)
+        self.state_type = PMP_STATE_F32 if st_dtype == np.float32 else PMP_STATE_F64
+        self.layout = pmp_layout(w.nbox, self.lo.ctypes.data, self.n.ctypes.data, w.ghost,
+                                 (C.c_int32 * 3)(*w.domain), float(w.dx), ACC[acc],
+                                 self.state_type, 1 if w.nfield == 6 else 0)
+        h = C.c_void_p()
+        _call("pmp_create", C.byref(h), C.byref(self.layout))
+        self.h = h
+        se, be, oc = C.c_int64(), C.c_int64(), C.c_int64()
+        _call("pmp_sizes", self.h, C.byref(se), C.byref(be), C.byref(oc))
+        self.state_elems, self.buffer_elems, self.owned_cells = se.value, be.value, oc.value
+        assert self.state_elems == w.state.size, "state size does not match the layout"
+        tdt = torch.float32 if self.state_type == PMP_STATE_F32 else torch.float64
+        bdt = {"f32": torch.float32, "f64": torch.float64, "fix64": torch.int64}[acc]
+        self.state = torch.from_numpy(np.ascontiguousarray(w.state)).to(device)
+        assert self.state.dtype == tdt
+        self.buf = torch.empty(self.buffer_elems, dtype=bdt, device=device)
+        self.lim = pmp_limits(float(w.limits.rho_floor), float(w.limits.rho_tr),
+                              float(w.limits.cap), int(w.limits.eint_mode))
+        self._keep = []
+        self.cic = self._kind(w.cic, ["x", "y", "z", "m"], pmp_cic)
+        self.sn = self._kind(w.sn, ["x", "y", "z", "m", "e", "r"], pmp_sn)
+        if self.sn is not None:
+            self.sn.r_max = float(np.max(w.sn.fields["r"]))
+        self.sinks = self._kind(w.sinks, ["x", "y", "z", "a"], pmp_sinks)
+        self.sink_out = None
+        if self.sinks is not None:
+            self.sinks.r_k = float(w.r_k)
+            self.sinks.r_gauss = float(w.r_gauss)
+            self.sink_out = torch.zeros(4 * w.sinks.n, dtype=torch.float64, device=device)
+
+    def _kind(self, P, names, struct):
+        import torch
+        if P is None or P.n == 0:
+            return None
+        ts = [torch.from_numpy(np.ascontiguousarray(P.fields[k], dtype=np.float64)).to(self.device)
+              for k in names]
+        off = torch.from_numpy(np.ascontiguousarray(P.box_off, dtype=np.int64)).to(self.device)
+        self._keep += ts + [off]
+        vals = [C.c_void_p(t.data_ptr()) for t in ts]
+        s = struct()
+        for k, v in zip(names, vals):
+            setattr(s, k, v)
+        s.n = P.n
+        s.box_off = C.c_void_p(off.data_ptr())
+        return s
+
+    # -------------------------------------------------------------- calls
+    def _r(self, s):
+        return None if s is None else C.byref(s)
+
+    def reset_state(self):
+        import torch
+        self.state.copy_(torch.from_numpy(np.ascontiguousarray(self.w.state)).to(self.device))
+
+    def deposit(self, stream=None):
+        _call("pmp_deposit", self.h, _ptr(self.buf), _ptr(self.state), self._r(self.cic),
+              self._r(self.sn), self._r(self.sinks), C.byref(self.lim), _stream(stream))
+
+    def ghost_fold(self, stream=None):
+        _call("pmp_ghost_fold", self.h, _ptr(self.buf), _stream(stream))
+
+    def sink_update(self, stream=None):
+        if self.sinks is None:
+            return
+        n = self.w.sinks.n
+        o = self.sink_out
+        _call("pmp_sink_update", self.h, _ptr(self.state), _ptr(self.buf), C.byref(self.sinks),
+              C.byref(self.lim), _ptr(o[0:n]), _ptr(o[n:2 * n]), _ptr(o[2 * n:3 * n]),
+              _ptr(o[3 * n:]), _stream(stream))
+
+    def apply(self, eta=None, stream=None):
+        _call("pmp_apply", self.h, _ptr(self.state), _ptr(self.buf), C.byref(self.lim),
+              _ptr(eta), _stream(stream))
+
+    def step(self, stream=None):
+        _call("pmp_step", self.h, _ptr(self.state), _ptr(self.buf), self._r(self.cic),
+              self._r(self.sn), self._r(self.sinks), C.byref(self.lim), _ptr(self.sink_out),
+              _stream(stream))
+
+    def graph_build(self, nsteps, stream=None):
+        _call("pmp_graph_build", self.h, int(nsteps), _ptr(self.state), _ptr(self.buf),
+              self._r(self.cic), self._r(self.sn), self._r(self.sinks), C.byref(self.lim),
+              _ptr(self.sink_out), _stream(stream))
+
+    def graph_launch(self, stream=None):
+        _call("pmp_graph_launch", self.h, _stream(stream))
+
+    def status(self, reset=True):
+        st = pmp_status()
+        _call("pmp_get_status", self.h, C.byref(st), 1 if reset else 0)
+        return st.as_dict()
+
+    def tuning(self):
+        t = pmp_tuning()
+        _call("pmp_get_tuning", self.h, C.byref(t))
+        return t
+
+    def set_tuning(self, **kw):
+        t = self.tuning()
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _call("pmp_set_tuning", self.h, C.byref(t))
+        return t
+
+    def autotune(self, stream=None):
+        best = C.c_double()
+        _call("pmp_autotune", self.h, _ptr(self.state), _ptr(self.buf), self._r(self.cic),
+              self._r(self.sn), self._r(self.sinks), C.byref(self.lim), _ptr(self.sink_out),
+              _stream(stream), C.byref(best))
+        return best.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.pmp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def stream_copy(dst, src, stream=None):
+    _call("pmp_stream_copy", _ptr(dst), _ptr(src), dst.numel() * dst.element_size(),
+          _stream(stream))
+
+
+def buffer_to_numpy(ctx, t=None):
+    """Device buffer as a host numpy array (float64 view for float modes)."""
+    return (ctx.buf if t is None else t).cpu().numpy()
+
+
+INV_Q = math.ldexp(1.0, -40)

@@ -147,6 +147,15 @@ def gas_state(rng, ncell: int, dtype, sigma_lnrho=1.0, sigma_v=0.3) -> np.ndarra
     return np.concatenate([rho[None], p, E[None]], axis=0)
 
 
+def pack_by_box(fields: np.ndarray, n: np.ndarray) -> np.ndarray:
+    """Lay a [5, ncell] draw out in the packed per-box order (each box's
+    [5][nz][ny][nx] block in turn)."""
+    sizes = np.prod(np.asarray(n, dtype=np.int64), axis=1)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    return np.concatenate([fields[:, int(o): int(o + s)].reshape(-1)
+                           for o, s in zip(offs, sizes)])
+
+
 def uniform_state(ncell: int, dtype, rho=1.0, E=1.0) -> np.ndarray:
     s = np.zeros((5, ncell), dtype=dtype)
     s[0] = rho
@@ -291,12 +300,8 @@ def c5(seed: int = 5, nb: int = 16, n_total: int | None = None, emin=8, emax=64,
         n_total = int(round(8_000_000 * (nb / 16.0) ** 3))
     n_sn = int(round(n_total / 11))
     n_cic = n_total - n_sn
-    # the state is drawn per box in box order so that its layout is packed
-    sizes = np.prod(n.astype(np.int64), axis=1)
-    assert int(sizes.sum()) == ncell
-    state = gas_state(rng, ncell, dtype)  # [5, ncell] in packed box order
-    state = np.concatenate([state[:, int(o): int(o + s)].reshape(-1)
-                            for o, s in zip(np.concatenate([[0], np.cumsum(sizes)[:-1]]), sizes)])
+    assert int(np.prod(n.astype(np.int64), axis=1).sum()) == ncell
+    state = pack_by_box(gas_state(rng, ncell, dtype), n)
     cic = _group_by_box(clumped_positions(rng, n_cic, domain), cic_fields(rng, n_cic),
                         cuts, (nb, nb, nb))
     sn = _group_by_box(clumped_positions(rng, n_sn, domain), sn_fields(n_sn, 2.0),
@@ -312,7 +317,7 @@ def multibox(edges_x, edges_y, edges_z, ghost, positions_cic=None, masses=None,
     domain, lo, n, cuts = rectilinear(edges_x, edges_y, edges_z)
     nbx, nby, nbz = len(edges_x), len(edges_y), len(edges_z)
     ncell = int(np.prod(np.asarray(domain, dtype=np.int64)))
-    state = gas_state(rng, ncell, dtype).reshape(-1)
+    state = pack_by_box(gas_state(rng, ncell, dtype), n)
     cic = sn = None
     if positions_cic is not None:
         pc = np.asarray(positions_cic, dtype=np.float64).reshape(-1, 3)

@@ -1,0 +1,269 @@
+"""Parity of the HIP path against the serial oracle, through the C-ABI.
+
+Bar: int64 fixed point (buffers, folded buffers, sink sums, eta and the
+applied state) bit-exact; FP64 accumulation within 1e-12 and FP32 within
+1e-6, both as max|x - r| / max|r| per field against the FP64 oracle."""
+import dataclasses
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_18261_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_18261_amd import binding
+    return binding
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(B, w, acc, want_eta=True, tuning=None):
+    import torch
+    ctx = B.Context(w, acc)
+    if tuning:
+        ctx.set_tuning(**tuning)
+    ctx.deposit()
+    dep = ctx.buf.cpu().numpy().copy()
+    ctx.ghost_fold()
+    fold = ctx.buf.cpu().numpy().copy()
+    ctx.sink_update()
+    eta = torch.empty(ctx.owned_cells, dtype=torch.float64, device="cuda") if want_eta else None
+    ctx.apply(eta)
+    torch.cuda.synchronize()
+    out = {"buf_deposit": dep, "buf_fold": fold, "state": ctx.state.cpu().numpy(),
+           "status": ctx.status()}
+    if eta is not None:
+        out["eta"] = eta.cpu().numpy()
+    if ctx.sink_out is not None:
+        n = w.sinks.n
+        s = ctx.sink_out.cpu().numpy()
+        out["sink_d"] = (s[:n], s[n:2 * n], s[2 * n:3 * n], s[3 * n:])
+    ctx.close()
+    return out
+
+
+def field_views(w, flat, kind):
+    """Split a packed array into per-field 1-D arrays (over all boxes)."""
+    nf = w.nfield if kind == "buf" else 5
+    g = w.ghost if kind == "buf" else 0
+    sizes = [int(np.prod(n + 2 * g)) for n in w.n.astype(np.int64)]
+    out = [[] for _ in range(nf)]
+    off = 0
+    for s in sizes:
+        for f in range(nf):
+            out[f].append(flat[off + f * s: off + (f + 1) * s])
+        off += nf * s
+    return [np.concatenate(o) for o in out]
+
+
+def rel_err(x, r):
+    x = x.astype(np.float64)
+    r = r.astype(np.float64)
+    den = np.max(np.abs(r)) if r.size else 0.0
+    num = np.max(np.abs(x - r)) if r.size else 0.0
+    if den == 0.0:
+        return num
+    return num / den
+
+
+def compare(w, acc, got, ref):
+    if acc == "fix64":
+        assert np.array_equal(got["buf_deposit"], ref["buf_deposit"]), "deposit buffer differs"
+        assert np.array_equal(got["buf_fold"], ref["buf_fold"]), "folded buffer differs"
+        st_ref = ref["state"].astype(got["state"].dtype)
+        bad = np.flatnonzero(got["state"] != st_ref)
+        assert bad.size == 0, f"{bad.size} state values differ, first at {bad[:5]}"
+        assert np.array_equal(got["eta"], ref["eta"])
+        if "sink_d" in ref:
+            for a, b in zip(got["sink_d"], ref["sink_d"]):
+                assert np.array_equal(a, b)
+        return
+    tol = TOL[acc]
+    for key in ("buf_deposit", "buf_fold"):
+        for f, (x, r) in enumerate(zip(field_views(w, got[key], "buf"),
+                                       field_views(w, ref[key], "buf"))):
+            e = rel_err(x, r)
+            assert e <= tol, f"{key} field {f}: {e:.3e} > {tol}"
+    # the state is stored in its own type: compare with the oracle rounded to
+    # that type, allowing the tolerance or one unit of the stored precision
+    sdt = got["state"].dtype
+    stol = max(tol, float(np.finfo(sdt).eps))
+    for f, (x, r) in enumerate(zip(field_views(w, got["state"], "state"),
+                                   field_views(w, ref["state"].astype(sdt), "state"))):
+        e = rel_err(x, r)
+        assert e <= stol, f"state field {f}: {e:.3e} > {stol}"
+    if "sink_d" in ref:
+        for a, b in zip(got["sink_d"], ref["sink_d"]):
+            assert rel_err(a, b) <= max(tol, 1e-9)
+
+
+def check(B, orc, w, acc, **kw):
+    say(f"case {w.name} acc={acc} nbox={w.nbox} cic={w.cic.n if w.cic else 0} "
+        f"sn={w.sn.n if w.sn else 0} sinks={w.sinks.n if w.sinks else 0}")
+    got = run_gpu(B, w, acc, **kw)
+    assert got["status"]["flags"] in (0, 0x10), got["status"]
+    ref = orc.step(w, "fix64" if acc == "fix64" else "f64", want_eta=True)
+    compare(w, acc, got, ref)
+    if acc == "fix64":
+        for k in ("touched", "bind", "lam", "fall"):
+            assert got["status"][k] == ref["counters"][k], (k, got["status"], ref["counters"])
+    return got, ref
+
+
+# ------------------------------------------------------------- small configs
+
+SMALL = {
+    "c1": lambda: W.c1(),
+    "c2_40": lambda: W.c2(nx=40),
+    "c3_40": lambda: W.c3(nx=40, n_sink=48),
+    "c4_48": lambda: W.c4(nx=48),
+    "c5_4": lambda: W.c5(nb=4),
+}
+
+
+@pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
+@pytest.mark.parametrize("name", list(SMALL))
+def test_small_configs(B, orc, name, acc):
+    check(B, orc, SMALL[name](), acc)
+
+
+def test_c1_fp64_state_all_modes(B, orc):
+    w = W.c1()
+    assert w.state.dtype == np.float64
+    for acc in ("fix64", "f64", "f32"):
+        check(B, orc, w, acc)
+
+
+def edge_workloads():
+    out = []
+    edges = ([5, 7], [6, 4], [4, 6])
+    pos_c = [[5.0, 6.0, 4.0], [0.0, 0.0, 0.0], [4.99, 5.99, 3.99], [11.5, 9.5, 9.5],
+             [5.0, 2.5, 7.2], [0.25, 9.75, 4.0], [6.0, 6.0, 6.0], [11.999999, 9.999999, 9.999]]
+    pos_s = [[5.0, 6.0, 4.0], [0.1, 9.9, 9.9], [11.9, 0.2, 5.0], [3.3, 3.3, 3.3], [0.0, 0.0, 0.0]]
+    out.append(W.multibox(*edges, ghost=2, positions_cic=pos_c, positions_sn=pos_s,
+                          sn_radius=1.5, seed=3, dtype=np.float32))
+    # boxes smaller than twice the ghost width: several periodic images per cell
+    rng = np.random.default_rng(9)
+    w = W.Workload("tiny", *W.single_box(3, 4, 3), 2, 1.0,
+                   W.gas_state(rng, 36, np.float64).reshape(-1),
+                   cic=W._one_box(W.uniform_positions(rng, 9, (3, 4, 3)), W.cic_fields(rng, 9)),
+                   sn=W._one_box(W.uniform_positions(rng, 3, (3, 4, 3)), W.sn_fields(3, 1.7)))
+    out.append(w)
+    # a 3x2x1 layout with many particles on box corners and an empty box
+    edges = ([3, 8, 5], [6, 6], [9])
+    pts = [[3.0, 6.0, 0.0], [11.0, 0.0, 4.5], [0.0, 0.0, 8.999], [3.0, 6.0, 4.5]] * 5
+    out.append(W.multibox(*edges, ghost=1, positions_cic=pts, positions_sn=pts[:4],
+                          sn_radius=1.0, seed=4))
+    # no particles at all: the step must leave the state unchanged
+    out.append(dataclasses.replace(W.c2(nx=16), cic=None, sn=None, name="empty"))
+    # supernova radius 0: only the host cell (or the cell whose centre it is)
+    rng = np.random.default_rng(2)
+    out.append(W.Workload("r0", *W.single_box(8), 1, 1.0,
+                          W.gas_state(rng, 512, np.float32).reshape(-1),
+                          sn=W._one_box(W.uniform_positions(rng, 20, (8, 8, 8)),
+                                        W.sn_fields(20, 0.0))))
+    return out
+
+
+@pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
+@pytest.mark.parametrize("idx", range(5))
+def test_edge_layouts(B, orc, idx, acc):
+    w = edge_workloads()[idx]
+    got, _ = check(B, orc, w, acc)
+    if w.name == "empty":
+        assert np.array_equal(got["state"], w.state)
+
+
+def test_launch_shape_invariance_fixed_point(B, orc):
+    """Fixed point gives the same bits whatever the launch shape."""
+    w = W.c4(nx=40)
+    base = run_gpu(B, w, "fix64")
+    for tun in ({"block": 64, "sn_lanes": 16}, {"block": 1024, "sn_lanes": 32},
+                {"block": 128, "sn_lanes": 64}):
+        say("tuning", tun)
+        other = run_gpu(B, w, "fix64", tuning=tun)
+        assert np.array_equal(base["buf_fold"], other["buf_fold"])
+        assert np.array_equal(base["state"], other["state"])
+
+
+def test_run_twice_bitwise(B):
+    w = W.c3(nx=40, n_sink=48)
+    a = run_gpu(B, w, "fix64")
+    b = run_gpu(B, w, "fix64")
+    for k in ("buf_fold", "state", "eta"):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_limiter_binds_on_clustered_sinks(B, orc):
+    got, ref = check(B, orc, W.c3(nx=64, n_sink=256), "fix64")
+    st = got["status"]
+    assert st["touched"] > 0
+    assert st["bind"] / st["touched"] >= 0.10, st
+
+
+def test_outside_particle_flagged(B):
+    import torch
+    w = W.multibox([4, 4], [4], [4], ghost=1, positions_cic=[[1.5, 1.5, 1.5], [5.5, 1.5, 1.5]],
+                   seed=1)
+    w.cic.box_off[:] = [0, 0, 2]  # both claimed by box 1; the first is not in it
+    ctx = B.Context(w, "fix64")
+    ctx.step()
+    torch.cuda.synchronize()
+    st = ctx.status()
+    assert "OUTSIDE" in st["flag_names"]
+    ctx.close()
+
+
+def test_geometry_errors(B):
+    # overlapping boxes are refused at create
+    w = W.multibox([4, 4], [4], [4], ghost=1, seed=1)
+    w.lo[1, 0] = 2
+    with pytest.raises(B.PmpError, match="ERANGE"):
+        B.Context(w, "fix64")
+    # supernova reach beyond the ghost width is refused before launch
+    rng = np.random.default_rng(0)
+    w = W.Workload("reach", *W.single_box(8), 1, 1.0, W.gas_state(rng, 512, np.float32).reshape(-1),
+                   sn=W._one_box(np.array([[4.5, 4.5, 4.5]]), W.sn_fields(1, 2.0)))
+    ctx = B.Context(w, "f32")
+    with pytest.raises(B.PmpError, match="ERANGE"):
+        ctx.deposit()
+    ctx.close()
+
+
+def test_graph_replays_match_eager(B):
+    """A captured 3-step graph equals 3 eager steps, on every replay, with
+    eager work and synchronisation between replays."""
+    import torch
+    w = W.c2(nx=32)
+    eager = B.Context(w, "fix64")
+    for _ in range(3):
+        eager.step()
+    torch.cuda.synchronize()
+    ref = eager.state.cpu().numpy()
+    g = B.Context(w, "fix64")
+    g.graph_build(3)
+    for rep in range(3):
+        g.reset_state()
+        torch.cuda.synchronize()
+        g.graph_launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(g.state.cpu().numpy(), ref), f"replay {rep}"
+        eager.reset_state()
+        eager.step()
+        torch.cuda.synchronize()
+    eager.close()
+    g.close()
