@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Throughput of the particle-mesh-particle hot path on one MI355X.
+
+One step = Step 1 (zero the buffer, CIC and supernova deposits with atomic
+adds), Step 2 (ghost fold), Steps 3 + 5 (limiter + apply), run through the
+C-ABI of libpmp.so on the 256^3 periodic workload: log-normal gas in FP32,
+1e6 uniform CIC particles, 1e5 uniform supernovae of radius 4 cells, ghost
+width 4.  Inputs are resident in HBM before timing starts.  Prints one JSON
+line.
+
+  python bench.py [--steps K] [--warmup W] [--acc f32|f64|fix64]
+                  [--workload c2|c3|c4|c5] [--no-cpu] [--no-modes]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published
+PHASE_ORDER = ["zero", "cic", "sn", "sink_deposit", "fold", "sink_update", "apply"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def acc_bytes(acc):
+    return 4 if acc == "f32" else 8
+
+
+def algorithmic_bytes(w, acc, counts):
+    """Bytes per launch each phase must move at minimum (no scratch, no
+    re-reads): buffer writes for the zero fill, particle records plus a
+    read-modify-write of every touched (cell, field) for deposits, the owned
+    shell and its ghost images for the fold, and state in/out plus buffer in
+    for apply."""
+    import numpy as np
+    ba = acc_bytes(acc)
+    bs = np.dtype(w.state.dtype).itemsize
+    F = w.nfield
+    n = w.n.astype(np.int64)
+    g = w.ghost
+    owned = int(np.prod(n, axis=1).sum())
+    padded = int(np.prod(n + 2 * g, axis=1).sum())
+    ghost_cells = padded - owned
+    inner = np.maximum(n - 2 * g, 0)
+    shell = owned - int(np.prod(inner, axis=1).sum())
+    out = {
+        "zero": padded * F * ba,
+        "fold": F * ba * (2 * shell + ghost_cells),
+        "apply": owned * (2 * 5 * bs + F * ba),
+    }
+    if w.cic is not None and w.cic.n:
+        out["cic"] = w.cic.n * 32 + 2 * ba * counts["cic"]
+    if w.sn is not None and w.sn.n:
+        out["sn"] = w.sn.n * 48 + 2 * ba * counts["sn"]
+    if w.sinks is not None and w.sinks.n:
+        out["sink_deposit"] = w.sinks.n * 32 + 2 * ba * counts["sink"] + bs * counts["sink"]
+        out["sink_update"] = w.sinks.n * 64 + counts["sink"] * (4 * bs + ba)
+    return out
+
+
+def touched_counts(B, w, acc):
+    """Unique (cell, field) pairs each particle kind writes, counted as the
+    nonzero buffer entries after depositing that kind alone (all
+    contributions are positive)."""
+    import dataclasses
+    import torch
+    counts = {}
+    for kind in ("cic", "sn", "sinks"):
+        P = getattr(w, kind)
+        if P is None or P.n == 0:
+            continue
+        kw = {"cic": None, "sn": None, "sinks": None}
+        kw[kind] = P
+        wk = dataclasses.replace(w, **kw)
+        if kind != "sinks" and w.sinks is not None:
+            wk = dataclasses.replace(wk, sinks=None)
+        ctx = B.Context(wk, acc)
+        ctx.deposit()
+        torch.cuda.synchronize()
+        counts["sink" if kind == "sinks" else kind] = int(torch.count_nonzero(ctx.buf).item())
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    return counts
+
+
+def run_steps(ctx, steps, warmup, profile=True):
+    import torch
+    for _ in range(warmup):
+        ctx.step()
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile_begin(steps)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        ctx.step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    phases = ctx.profile_end() if profile else {}
+    return ms, phases
+
+
+def stream_copy_gbps(B, nbytes=1 << 30, reps=10):
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    B.stream_copy(b, a)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        B.stream_copy(b, a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9, ms
+
+
+def traffic_for(workload, kernel):
+    """Measured HBM bytes per launch from committed rocprofv3 counter runs,
+    if they were taken on the current kernel source; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if kernel not in rec.get("kernels", {}):
+        return None
+    src = os.path.join(ROOT, "paper_2509_18261_amd", "csrc", "pmp_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("kernel_source_sha256_16") != h:
+        return None
+    return rec["kernels"][kernel]["hbm_bytes_per_launch"]
+
+
+def cpu_baseline(w, n_particles, target_s=10.0):
+    import oracle
+    ncores = 1
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        times.append(oracle.timed_step(w, "f64"))
+        if time.perf_counter() - t_start >= target_s or len(times) >= 5:
+            break
+    t = min(times)
+    return {"value": n_particles / t, "unit": "particles/s", "cores": ncores, "kind": "oracle",
+            "sample": f"{len(times)} full serial FP64 oracle steps of the same workload "
+                      f"(deposit, fold, apply; {t:.2f} s each, best taken)",
+            "cells_per_s": w.owned_cells / t, "s_per_step": t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--acc", default="f32", choices=["f32", "f64", "fix64"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--no-calib", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "single-GPU build: bench.py measures one MI355X only; "
+                                   f"--gpus {args.gpus} is not supported"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2509_18261_amd import binding as B
+    from paper_2509_18261_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"bench: workload {args.workload}, acc {args.acc}, steps {args.steps}")
+    w = W.CONFIGS[args.workload]()
+    nparts = sum(P.n for P in (w.cic, w.sn, w.sinks) if P is not None)
+    counts = touched_counts(B, w, args.acc)
+    log("touched (cell, field) pairs:", counts)
+    ctx = B.Context(w, args.acc)
+    ms, phases = run_steps(ctx, args.steps, args.warmup)
+    st = ctx.status()
+    log(f"step {ms:.4f} ms; status {st}")
+    tun = ctx.tuning().as_dict()
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+
+    algo = algorithmic_bytes(w, args.acc, counts)
+    per_phase = {}
+    for name in PHASE_ORDER:
+        if name not in phases:
+            continue
+        tot_ms, nl = phases[name]
+        avg = tot_ms / nl
+        b = algo.get(name, 0)
+        per_phase[name] = {"avg_ms": round(avg, 5), "launches": nl,
+                           "algo_bytes": int(b),
+                           "GBps": round(b / (avg * 1e-3) / 1e9, 1) if avg > 0 else None}
+    dom = max(per_phase, key=lambda k: per_phase[k]["avg_ms"])
+    kernel_names = {"zero": "k_zero", "cic": "k_cic_direct", "sn": "k_sn_direct",
+                    "sink_deposit": "k_sink_deposit", "fold": "k_fold",
+                    "sink_update": "k_sink_update", "apply": "k_apply"}
+    d = per_phase[dom]
+    achieved = d["algo_bytes"] / (d["avg_ms"] * 1e-3) / 1e9
+    step_bytes = sum(algo.get(k, 0) for k in per_phase)
+    out = {
+        "metric": "particle-deposits/s and mesh cells applied/s; % HBM roofline vs plain FP64",
+        "value": nparts / (ms * 1e-3),
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.acc,
+        "data": "synthetic (seeded; stands in for the paper's AGORA galaxy run)",
+        "config": {"workload": w.name, "cells": w.owned_cells,
+                   "cic": w.cic.n if w.cic else 0, "sn": w.sn.n if w.sn else 0,
+                   "sinks": w.sinks.n if w.sinks else 0, "ghost": w.ghost,
+                   "state": str(np.dtype(w.state.dtype)), "acc": args.acc,
+                   "limiter": "f64", "boxes": w.nbox},
+        "cells_per_s": w.owned_cells / (ms * 1e-3),
+        "step_algo_bytes": int(step_bytes),
+        "step_hbm_frac": step_bytes / (ms * 1e-3) / (HBM_PEAK_GBPS * 1e9),
+        "roofline": {"bound": "hbm", "kernel": kernel_names[dom], "phase": dom,
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic_for(args.workload, kernel_names[dom]),
+                     "algo_bytes_per_launch": d["algo_bytes"],
+                     "avg_launch_ms": d["avg_ms"]},
+        "phases": per_phase,
+        "tuning": tun,
+        "status_flags": st["flag_names"],
+    }
+    if not args.no_calib:
+        gbps, cms = stream_copy_gbps(B)
+        out["stream_copy_GBps"] = round(gbps, 1)
+        log(f"stream copy {gbps:.0f} GB/s")
+    if not args.no_modes:
+        modes = {}
+        for acc, dt in (("fix64", None), ("f64", np.float64)):
+            wm = w.with_state(w.state.astype(dt)) if dt is not None else w
+            c2 = B.Context(wm, acc)
+            mms, _ = run_steps(c2, max(5, args.steps // 2), 2, profile=False)
+            c2.close()
+            del c2
+            torch.cuda.empty_cache()
+            modes[acc if dt is None else "f64_plain"] = {
+                "ms_per_step": mms, "particles_per_s": nparts / (mms * 1e-3),
+                "cells_per_s": w.owned_cells / (mms * 1e-3),
+                "state": "f64" if dt is not None else str(np.dtype(w.state.dtype))}
+            log(f"mode {acc}: {mms:.4f} ms/step")
+        out["modes"] = modes
+        out["speedup_vs_plain_f64"] = modes["f64_plain"]["ms_per_step"] / ms
+    if not args.no_cpu:
+        log("cpu baseline (serial oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(w, nparts)
+        log(f"oracle {out['cpu_baseline']['s_per_step']:.2f} s/step")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -230,6 +230,24 @@ int pmp_autotune(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic, const
                  const pmp_sinks *sinks, const pmp_limits *limits, double *sink_out,
                  void *stream, double *best_ms);
 
+/* Phase profiler (the per-routine timers of Sec. 4.6, on the GPU): after
+ * pmp_profile_begin, every kernel the context launches outside graph capture
+ * is bracketed by HIP events on its stream, for up to max_launches launches
+ * per phase.  pmp_profile_end synchronises, writes the summed kernel time in
+ * milliseconds and the launch count of each phase to the host arrays ms and
+ * launches [PMP_NPHASE] (either may be NULL) and stops profiling. */
+#define PMP_NPHASE 8
+#define PMP_PHASE_ZERO 0
+#define PMP_PHASE_CIC 1
+#define PMP_PHASE_SN 2
+#define PMP_PHASE_SINK_DEPOSIT 3
+#define PMP_PHASE_FOLD 4
+#define PMP_PHASE_SINK_UPDATE 5
+#define PMP_PHASE_APPLY 6
+#define PMP_PHASE_BIN 7
+int pmp_profile_begin(pmp_ctx *ctx, int max_launches);
+int pmp_profile_end(pmp_ctx *ctx, double *ms, int64_t *launches);
+
 /* Bandwidth calibration: copy bytes from device src to device dst with a
  * plain streaming kernel (16-byte loads and stores). */
 int pmp_stream_copy(void *dst, const void *src, size_t bytes, void *stream);

@@ -240,7 +240,18 @@ def step(w, mode, want_eta=False):
 
 
 def timed_step(w, mode="f64"):
-    """Wall time of one oracle pass (seconds), single thread."""
+    """Wall time (seconds, single thread) of one oracle pass: deposit, fold,
+    sink update (if sinks), limit + apply; without the copies step() keeps."""
+    mesh = Mesh.of(w)
+    s64 = _f64(w.state)
     t0 = time.perf_counter()
-    step(w, mode)
+    buf, sw, sm = deposit(w, mode, mesh, s64)
+    fold(w, mode, buf, mesh)
+    if w.sinks is not None and w.sinks.n > 0:
+        sink_update(w, mode, buf, sw, sm, mesh, s64)
+    lim = _limits(w.limits)
+    cnt = Counters()
+    rc = lib().orc_apply(C.byref(mesh.c), MODES[mode], _ptr(s64), _ptr(buf), C.byref(lim),
+                         None, C.byref(cnt))
+    _check(rc, "apply")
     return time.perf_counter() - t0

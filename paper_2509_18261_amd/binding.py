@@ -79,6 +79,9 @@ class pmp_tuning(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
+NPHASE = 8
+PHASES = ["zero", "cic", "sn", "sink_deposit", "fold", "sink_update", "apply", "bin"]
+
 _VP, _I = C.c_void_p, C.c_int
 # (name, restype, argtypes) for every exported function of include/pmp.h
 SIGNATURES = [
@@ -102,6 +105,8 @@ SIGNATURES = [
     ("pmp_autotune", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
                           C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP, _VP,
                           C.POINTER(C.c_double)]),
+    ("pmp_profile_begin", _I, [_VP, _I]),
+    ("pmp_profile_end", _I, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("pmp_stream_copy", _I, [_VP, _VP, C.c_size_t, _VP]),
     ("pmp_last_error", C.c_char_p, []),
 ]
@@ -264,6 +269,16 @@ class Context:
               self._r(self.sn), self._r(self.sinks), C.byref(self.lim), _ptr(self.sink_out),
               _stream(stream), C.byref(best))
         return best.value
+
+    def profile_begin(self, max_launches):
+        _call("pmp_profile_begin", self.h, int(max_launches))
+
+    def profile_end(self):
+        """Summed kernel ms and launch count per phase, as a dict."""
+        ms = (C.c_double * NPHASE)()
+        cnt = (C.c_int64 * NPHASE)()
+        _call("pmp_profile_end", self.h, ms, cnt)
+        return {PHASES[p]: (ms[p], cnt[p]) for p in range(NPHASE) if cnt[p] > 0}
 
     def close(self):
         if getattr(self, "h", None):

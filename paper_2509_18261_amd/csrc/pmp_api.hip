@@ -128,6 +128,11 @@ struct pmp_ctx {
   pmp_tuning tune{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // phase profiler: events[phase][2 * launch + {0: start, 1: stop}]
+  bool prof_on = false;
+  int prof_max = 0;
+  int prof_count[PMP_NPHASE] = {0};
+  std::vector<hipEvent_t> prof_events[PMP_NPHASE];
 
   Mesh mesh() const {
     Mesh M;
@@ -155,7 +160,38 @@ struct pmp_ctx {
 
 namespace {
 
+void prof_free(pmp_ctx* c) {
+  for (int p = 0; p < PMP_NPHASE; ++p) {
+    for (hipEvent_t e : c->prof_events[p]) (void)hipEventDestroy(e);
+    c->prof_events[p].clear();
+    c->prof_count[p] = 0;
+  }
+  c->prof_on = false;
+  c->prof_max = 0;
+}
+
+bool capturing(hipStream_t s);
+
+// Bracket one kernel launch with events when profiling (never under capture).
+struct PhaseTimer {
+  pmp_ctx* c;
+  int phase;
+  hipStream_t s;
+  bool on;
+  PhaseTimer(pmp_ctx* c_, int p, hipStream_t s_) : c(c_), phase(p), s(s_) {
+    on = c->prof_on && c->prof_count[p] < c->prof_max && !capturing(s);
+    if (on) (void)hipEventRecord(c->prof_events[p][2 * c->prof_count[p]], s);
+  }
+  ~PhaseTimer() {
+    if (on) {
+      (void)hipEventRecord(c->prof_events[phase][2 * c->prof_count[phase] + 1], s);
+      ++c->prof_count[phase];
+    }
+  }
+};
+
 void release(pmp_ctx* c) {
+  prof_free(c);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   (void)hipFree(c->d_boxes);
@@ -331,12 +367,23 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
     if (rc) return rc;
   }
   const Mesh M = c->mesh();
-  PMP_HIP(launch_zero(buf, c->buffer_elems * (long long)c->acc_bytes(), c->tune.block, s));
-  if (has_cic) PMP_HIP(launch_cic_direct(M, from_cic(cic), buf, nullptr, 0, c->tune.block, s));
-  if (has_sn) PMP_HIP(launch_sn_direct(M, from_sn(sn), buf, c->tune.sn_lanes, s));
-  if (has_sink)
+  {
+    PhaseTimer t(c, PMP_PHASE_ZERO, s);
+    PMP_HIP(launch_zero(buf, c->buffer_elems * (long long)c->acc_bytes(), c->tune.block, s));
+  }
+  if (has_cic) {
+    PhaseTimer t(c, PMP_PHASE_CIC, s);
+    PMP_HIP(launch_cic_direct(M, from_cic(cic), buf, nullptr, 0, c->tune.block, s));
+  }
+  if (has_sn) {
+    PhaseTimer t(c, PMP_PHASE_SN, s);
+    PMP_HIP(launch_sn_direct(M, from_sn(sn), buf, c->tune.sn_lanes, s));
+  }
+  if (has_sink) {
+    PhaseTimer t(c, PMP_PHASE_SINK_DEPOSIT, s);
     PMP_HIP(launch_sink_deposit(M, from_sinks(sinks), state, buf, c->d_sink_scratch,
                                 sinks->r_k, sinks->r_gauss, to_limits(limits), s));
+  }
   return PMP_OK;
 }
 
@@ -352,6 +399,7 @@ int do_sink_update(pmp_ctx* c, const void* state, const void* buf, const pmp_sin
     return fail(PMP_EINVAL, "sink update: NULL array");
   if (sinks->n > c->sink_cap)
     return fail(PMP_EINVAL, "sink update before a deposit with these sinks");
+  PhaseTimer t(c, PMP_PHASE_SINK_UPDATE, s);
   PMP_HIP(launch_sink_update(c->mesh(), from_sinks(sinks), state, buf, c->d_sink_scratch,
                              sinks->r_k, sinks->r_gauss, to_limits(limits), dm, dpx, dpy, dpz,
                              s));
@@ -363,7 +411,14 @@ int do_apply(pmp_ctx* c, void* state, const void* buf, const pmp_limits* limits,
   if (!state || !buf) return fail(PMP_EINVAL, "apply: state or buffer is NULL");
   int rc = check_limits(limits);
   if (rc) return rc;
+  PhaseTimer t(c, PMP_PHASE_APPLY, s);
   PMP_HIP(launch_apply(c->mesh(), state, buf, to_limits(limits), eta, c->tune.block, s));
+  return PMP_OK;
+}
+
+int do_fold(pmp_ctx* c, void* buf, hipStream_t s) {
+  PhaseTimer t(c, PMP_PHASE_FOLD, s);
+  PMP_HIP(launch_fold(c->mesh(), buf, c->tune.block, s));
   return PMP_OK;
 }
 
@@ -371,7 +426,8 @@ int do_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn
             const pmp_sinks* sinks, const pmp_limits* limits, double* sink_out, hipStream_t s) {
   int rc = do_deposit(c, buf, state, cic, sn, sinks, limits, s);
   if (rc) return rc;
-  PMP_HIP(launch_fold(c->mesh(), buf, c->tune.block, s));
+  rc = do_fold(c, buf, s);
+  if (rc) return rc;
   if (sinks && sinks->n > 0) {
     if (!sink_out) return fail(PMP_EINVAL, "sinks given but sink_out is NULL");
     const long long n = sinks->n;
@@ -547,8 +603,7 @@ int pmp_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, co
 
 int pmp_ghost_fold(pmp_ctx* c, void* buf, void* stream) {
   if (!c || !buf) return fail(PMP_EINVAL, "NULL argument");
-  PMP_HIP(launch_fold(c->mesh(), buf, c->tune.block, (hipStream_t)stream));
-  return PMP_OK;
+  return do_fold(c, buf, (hipStream_t)stream);
 }
 
 int pmp_sink_update(pmp_ctx* c, const void* state, const void* buf, const pmp_sinks* sinks,
@@ -669,6 +724,43 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
   (void)c; (void)state; (void)buf; (void)cic; (void)sn; (void)sinks; (void)limits;
   (void)sink_out; (void)stream; (void)best_ms;
   return fail(PMP_EUNSUPPORTED, "autotune not built yet");
+}
+
+int pmp_profile_begin(pmp_ctx* c, int max_launches) {
+  if (!c || max_launches < 1) return fail(PMP_EINVAL, "profile_begin: bad argument");
+  prof_free(c);
+  for (int p = 0; p < PMP_NPHASE; ++p) {
+    c->prof_events[p].resize(2 * (size_t)max_launches, nullptr);
+    for (auto& e : c->prof_events[p]) {
+      hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) {
+        e = nullptr;
+        prof_free(c);
+        return fail(PMP_EDEVICE, "hipEventCreate: %s", hipGetErrorString(err));
+      }
+    }
+  }
+  c->prof_max = max_launches;
+  c->prof_on = true;
+  return PMP_OK;
+}
+
+int pmp_profile_end(pmp_ctx* c, double* ms, int64_t* launches) {
+  if (!c) return fail(PMP_EINVAL, "NULL context");
+  if (!c->prof_on) return fail(PMP_EINVAL, "profiling was not started");
+  PMP_HIP(hipDeviceSynchronize());
+  for (int p = 0; p < PMP_NPHASE; ++p) {
+    double sum = 0.0;
+    for (int i = 0; i < c->prof_count[p]; ++i) {
+      float t = 0.f;
+      PMP_HIP(hipEventElapsedTime(&t, c->prof_events[p][2 * i], c->prof_events[p][2 * i + 1]));
+      sum += t;
+    }
+    if (ms) ms[p] = sum;
+    if (launches) launches[p] = c->prof_count[p];
+  }
+  prof_free(c);
+  return PMP_OK;
 }
 
 int pmp_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
