@@ -24,7 +24,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published
-PHASE_ORDER = ["zero", "cic", "sn", "sink_deposit", "fold", "sink_update", "apply"]
+PHASE_ORDER = ["bin", "tile", "zero", "cic", "sn", "sink_deposit", "fold", "sink_update",
+               "apply"]
 
 
 def log(*a):
@@ -52,8 +53,16 @@ def algorithmic_bytes(w, acc, counts):
     ghost_cells = padded - owned
     inner = np.maximum(n - 2 * g, 0)
     shell = owned - int(np.prod(inner, axis=1).sum())
+    parts = 0
+    if w.cic is not None:
+        parts += w.cic.n * 32
+    if w.sn is not None:
+        parts += w.sn.n * 48
     out = {
         "zero": padded * F * ba,
+        # binned path: every buffer cell stored once plus the particle records
+        "tile": padded * F * ba + parts,
+        "bin": 0,
         "fold": F * ba * (2 * shell + ghost_cells),
         "apply": owned * (2 * 5 * bs + F * ba),
     }
@@ -149,6 +158,44 @@ def traffic_for(workload, kernel):
     return rec["kernels"][kernel]["hbm_bytes_per_launch"]
 
 
+def batched_comparison(ctx, args, eager_ms):
+    """Multi-box layouts: the batched step (one launch per kernel over every
+    box), the same steps captured in one HIP graph, and the per-box launch
+    baseline (every kernel launched once per box)."""
+    import torch
+    n = args.graph_steps
+    ctx.graph_build(n)
+    ctx.graph_launch()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    reps = 3
+    t0.record()
+    for _ in range(reps):
+        ctx.graph_launch()
+    t1.record()
+    torch.cuda.synchronize()
+    graph_ms = t0.elapsed_time(t1) / (reps * n)
+    log(f"graph: {graph_ms:.4f} ms/step ({n} steps per graph)")
+    tun = ctx.tuning()
+    pb_steps = 3
+    ctx.step_per_box()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(pb_steps):
+        ctx.step_per_box()
+    t1.record()
+    torch.cuda.synchronize()
+    per_box_ms = t0.elapsed_time(t1) / pb_steps
+    log(f"per-box launches: {per_box_ms:.3f} ms/step")
+    return {"boxes": ctx.w.nbox, "eager_batched_ms_per_step": eager_ms,
+            "graph_ms_per_step": graph_ms, "graph_steps": n,
+            "per_box_launch_ms_per_step": per_box_ms,
+            "per_box_launches_per_step": 5 * ctx.w.nbox,
+            "speedup_graph_vs_per_box": per_box_ms / graph_ms,
+            "tuning": tun.as_dict()}
+
+
 def cpu_baseline(w, n_particles, target_s=10.0):
     import oracle
     ncores = 1
@@ -175,6 +222,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--no-calib", action="store_true")
+    ap.add_argument("--set", default="", help="tuning overrides, e.g. deposit_path=0,tile_x=32")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the library's autotuner (default: tune, cached per shape)")
+    ap.add_argument("--graph-steps", type=int, default=10,
+                    help="steps per captured graph in the batched comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: bench.py measures one MI355X only; "
@@ -193,11 +245,26 @@ def main():
     nparts = sum(P.n for P in (w.cic, w.sn, w.sinks) if P is not None)
     counts = touched_counts(B, w, args.acc)
     log("touched (cell, field) pairs:", counts)
+    overrides = {}
+    for kv in filter(None, args.set.split(",")):
+        k, v = kv.split("=")
+        overrides[k.strip()] = int(v)
     ctx = B.Context(w, args.acc)
+    tuned = None
+    if not args.no_autotune and not overrides:
+        from paper_2509_18261_amd import autotune
+        cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+        tuned = autotune.tune(ctx, cache_path=cache)
+        log(f"autotune: {tuned}")
+    if overrides:
+        ctx.set_tuning(**overrides)
     ms, phases = run_steps(ctx, args.steps, args.warmup)
     st = ctx.status()
     log(f"step {ms:.4f} ms; status {st}")
     tun = ctx.tuning().as_dict()
+    batched = None
+    if w.nbox > 1:
+        batched = batched_comparison(ctx, args, ms)
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -213,8 +280,12 @@ def main():
         per_phase[name] = {"avg_ms": round(avg, 5), "launches": nl,
                            "algo_bytes": int(b),
                            "GBps": round(b / (avg * 1e-3) / 1e9, 1) if avg > 0 else None}
-    dom = max(per_phase, key=lambda k: per_phase[k]["avg_ms"])
-    kernel_names = {"zero": "k_zero", "cic": "k_cic_direct", "sn": "k_sn_direct",
+    # dominant kernel: the longest single kernel that moves algorithmic bytes
+    # (the binning phase is several small launches of scratch traffic)
+    dom = max((k for k in per_phase if per_phase[k]["algo_bytes"] > 0),
+              key=lambda k: per_phase[k]["avg_ms"])
+    kernel_names = {"bin": "k_bin_cic+k_bin_sn+k_scan+k_fill", "tile": "k_tile_deposit",
+                    "zero": "k_zero", "cic": "k_cic_direct", "sn": "k_sn_direct",
                     "sink_deposit": "k_sink_deposit", "fold": "k_fold",
                     "sink_update": "k_sink_update", "apply": "k_apply"}
     d = per_phase[dom]
@@ -249,8 +320,11 @@ def main():
                      "avg_launch_ms": d["avg_ms"]},
         "phases": per_phase,
         "tuning": tun,
+        "autotune": tuned,
         "status_flags": st["flag_names"],
     }
+    if batched is not None:
+        out["batched"] = batched
     if not args.no_calib:
         gbps, cms = stream_copy_gbps(B)
         out["stream_copy_GBps"] = round(gbps, 1)
@@ -260,6 +334,8 @@ def main():
         for acc, dt in (("fix64", None), ("f64", np.float64)):
             wm = w.with_state(w.state.astype(dt)) if dt is not None else w
             c2 = B.Context(wm, acc)
+            if overrides:
+                c2.set_tuning(**overrides)
             mms, _ = run_steps(c2, max(5, args.steps // 2), 2, profile=False)
             c2.close()
             del c2

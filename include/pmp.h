@@ -72,6 +72,7 @@ extern "C" {
 #define PMP_FLAG_OVERFLOW 0x4u  /* fixed-point value outside (-2^62, 2^62) */
 #define PMP_FLAG_NAN 0x8u       /* non-finite particle or state value seen */
 #define PMP_FLAG_FLOOR 0x10u    /* energy floor infeasible: E raised (counted in fall) */
+#define PMP_FLAG_CAPACITY 0x20u /* binned path: tile entry list full (entries skipped) */
 
 typedef enum { PMP_ACC_F32 = 0, PMP_ACC_F64 = 1, PMP_ACC_FIX64 = 2 } pmp_acc_t;
 typedef enum { PMP_STATE_F32 = 0, PMP_STATE_F64 = 1 } pmp_state_t;
@@ -139,14 +140,21 @@ typedef struct {
 
 /* Kernel tuning; pmp_create fills defaults, pmp_autotune overwrites. */
 typedef struct {
-  int32_t deposit_path;  /* 0: direct global atomics; 1: binned, dense tiles
-                            privatised in LDS, the rest direct */
-  int32_t tile;          /* tile edge in cells for binning: 4, 8 or 16 */
-  int32_t dense_min;     /* particles per tile at which a tile goes to LDS */
-  int32_t chunk;         /* largest particle count per LDS work item */
+  int32_t deposit_path;  /* 0: zero fill, then direct global atomic adds;
+                            1: particles binned into tiles of the padded box
+                            their stencil touches, each tile accumulated in
+                            LDS by one workgroup and stored once (no global
+                            atomics, no separate zero fill) */
+  int32_t tile_x;        /* tile edge along x: 16, 32 or 64 cells */
+  int32_t tile_yz;       /* tile edge along y and z: 2, 4 or 8 cells */
+  int32_t tile_block;    /* threads per tile workgroup: 64 .. 1024 */
   int32_t block;         /* threads per block of the streaming kernels */
-  int32_t grid_per_cu;   /* resident blocks per CU for persistent launches */
+  int32_t grid_per_cu;   /* cap on blocks per CU for grid-stride launches */
   int32_t sn_lanes;      /* lanes cooperating on one supernova: 16, 32 or 64 */
+  int32_t tile_grid_per_cu; /* cap on tile workgroups per CU (0: one per tile) */
+  int32_t fuse_fold;     /* 1: pmp_step without sinks folds ghosts inside the
+                            apply kernel (same fixed gather order); 0: separate
+                            pmp_ghost_fold launch */
   int32_t reserved;
 } pmp_tuning;
 
@@ -205,6 +213,16 @@ int pmp_apply(pmp_ctx *ctx, void *state, const void *buf, const pmp_limits *limi
 int pmp_step(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic, const pmp_sn *sn,
              const pmp_sinks *sinks, const pmp_limits *limits, double *sink_out, void *stream);
 
+/* The per-box launch form of pmp_step, kept as the baseline the batched
+ * launches are measured against: every kernel is launched once per box over
+ * that box's cells and particles only (zero fill, direct CIC and supernova
+ * atomics, fold, apply), as a code without batching would.  Same results as
+ * pmp_step with deposit_path 0.  cic_off and sn_off are host copies of the
+ * kinds' box_off arrays (NULL when the kind is absent).  No sinks. */
+int pmp_step_per_box(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic,
+                     const pmp_sn *sn, const pmp_limits *limits, const int64_t *cic_off,
+                     const int64_t *sn_off, void *stream);
+
 /* Capture nsteps consecutive pmp_step calls into one HIP graph kept by the
  * context (replacing any previous one).  The device pointers are baked into
  * the graph and must stay valid until the graph is rebuilt or the context is
@@ -222,10 +240,13 @@ int pmp_get_status(pmp_ctx *ctx, pmp_status *out, int reset);
 int pmp_get_tuning(const pmp_ctx *ctx, pmp_tuning *out);
 int pmp_set_tuning(pmp_ctx *ctx, const pmp_tuning *t);
 
-/* Time candidate tunings on the given inputs (each candidate runs whole
- * steps on scratch copies made from state and buf, so the caller's arrays are
- * left as they were) and keep the fastest.  Synchronises the stream.
- * best_ms (host, may be NULL) receives the winning step time. */
+/* Autotuner: times whole steps (2 warm-up, 5 timed, HIP events) for each
+ * candidate tuning -- the direct path, and the binned path with a set of tile
+ * shapes, workgroup sizes and a persistent tile grid -- on the given inputs,
+ * and keeps the fastest.  The steps run on a scratch copy of the state (the
+ * caller's state is left as it was; the buffer and sink_out are overwritten).
+ * Synchronises the stream; allocates and frees the scratch copy.  best_ms
+ * (host, may be NULL) receives the winning step time. */
 int pmp_autotune(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic, const pmp_sn *sn,
                  const pmp_sinks *sinks, const pmp_limits *limits, double *sink_out,
                  void *stream, double *best_ms);
@@ -236,15 +257,16 @@ int pmp_autotune(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic, const
  * per phase.  pmp_profile_end synchronises, writes the summed kernel time in
  * milliseconds and the launch count of each phase to the host arrays ms and
  * launches [PMP_NPHASE] (either may be NULL) and stops profiling. */
-#define PMP_NPHASE 8
-#define PMP_PHASE_ZERO 0
-#define PMP_PHASE_CIC 1
-#define PMP_PHASE_SN 2
+#define PMP_NPHASE 9
+#define PMP_PHASE_ZERO 0          /* direct path: zero fill of the buffer */
+#define PMP_PHASE_CIC 1           /* direct path: CIC atomics */
+#define PMP_PHASE_SN 2            /* direct path: supernova atomics */
 #define PMP_PHASE_SINK_DEPOSIT 3
 #define PMP_PHASE_FOLD 4
 #define PMP_PHASE_SINK_UPDATE 5
 #define PMP_PHASE_APPLY 6
-#define PMP_PHASE_BIN 7
+#define PMP_PHASE_BIN 7           /* binned path: count, scan, fill (6 launches) */
+#define PMP_PHASE_TILE 8          /* binned path: LDS tile accumulation and store */
 int pmp_profile_begin(pmp_ctx *ctx, int max_launches);
 int pmp_profile_end(pmp_ctx *ctx, double *ms, int64_t *launches);
 

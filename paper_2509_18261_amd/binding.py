@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libpmp.so")
 PMP_ACC_F32, PMP_ACC_F64, PMP_ACC_FIX64 = 0, 1, 2
 PMP_STATE_F32, PMP_STATE_F64 = 0, 1
 ACC = {"f32": PMP_ACC_F32, "f64": PMP_ACC_F64, "fix64": PMP_ACC_FIX64}
-FLAGS = {0x1: "OUTSIDE", 0x2: "REACH", 0x4: "OVERFLOW", 0x8: "NAN", 0x10: "FLOOR"}
+FLAGS = {0x1: "OUTSIDE", 0x2: "REACH", 0x4: "OVERFLOW", 0x8: "NAN", 0x10: "FLOOR",
+         0x20: "CAPACITY"}
 ERRORS = {-1: "EINVAL", -2: "ERANGE", -3: "EDEVICE", -4: "ENOMEM", -5: "EUNSUPPORTED"}
 
 
@@ -71,16 +72,17 @@ class pmp_status(C.Structure):
 
 
 class pmp_tuning(C.Structure):
-    _fields_ = [("deposit_path", C.c_int32), ("tile", C.c_int32), ("dense_min", C.c_int32),
-                ("chunk", C.c_int32), ("block", C.c_int32), ("grid_per_cu", C.c_int32),
-                ("sn_lanes", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("deposit_path", C.c_int32), ("tile_x", C.c_int32), ("tile_yz", C.c_int32),
+                ("tile_block", C.c_int32), ("block", C.c_int32), ("grid_per_cu", C.c_int32),
+                ("sn_lanes", C.c_int32), ("tile_grid_per_cu", C.c_int32),
+                ("fuse_fold", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
-NPHASE = 8
-PHASES = ["zero", "cic", "sn", "sink_deposit", "fold", "sink_update", "apply", "bin"]
+NPHASE = 9
+PHASES = ["zero", "cic", "sn", "sink_deposit", "fold", "sink_update", "apply", "bin", "tile"]
 
 _VP, _I = C.c_void_p, C.c_int
 # (name, restype, argtypes) for every exported function of include/pmp.h
@@ -96,6 +98,8 @@ SIGNATURES = [
     ("pmp_apply", _I, [_VP, _VP, _VP, C.POINTER(pmp_limits), _VP, _VP]),
     ("pmp_step", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
                       C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP, _VP]),
+    ("pmp_step_per_box", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
+                              C.POINTER(pmp_limits), _VP, _VP, _VP]),
     ("pmp_graph_build", _I, [_VP, _I, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
                              C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP, _VP]),
     ("pmp_graph_launch", _I, [_VP, _VP]),
@@ -237,6 +241,18 @@ class Context:
         _call("pmp_step", self.h, _ptr(self.state), _ptr(self.buf), self._r(self.cic),
               self._r(self.sn), self._r(self.sinks), C.byref(self.lim), _ptr(self.sink_out),
               _stream(stream))
+
+    def step_per_box(self, stream=None):
+        """The per-box launch baseline (one launch per box per kernel)."""
+        if not hasattr(self, "_host_off"):
+            self._host_off = [None if P is None or P.n == 0 else
+                              np.ascontiguousarray(P.box_off, dtype=np.int64)
+                              for P in (self.w.cic, self.w.sn)]
+        co, so = self._host_off
+        _call("pmp_step_per_box", self.h, _ptr(self.state), _ptr(self.buf), self._r(self.cic),
+              self._r(self.sn), C.byref(self.lim),
+              None if co is None else C.c_void_p(co.ctypes.data),
+              None if so is None else C.c_void_p(so.ctypes.data), _stream(stream))
 
     def graph_build(self, nsteps, stream=None):
         _call("pmp_graph_build", self.h, int(nsteps), _ptr(self.state), _ptr(self.buf),

@@ -128,15 +128,29 @@ struct pmp_ctx {
   pmp_tuning tune{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // binned deposit: tiles of the padded boxes and their scratch
+  int tile_dims[3] = {0, 0, 0};
+  long long ntiles = 0;
+  long long* d_tile_prefix = nullptr;
+  int* d_tiles_axis = nullptr;
+  BinWork bw{};
+  long long bw_tiles = 0, bw_ncic = 0, bw_nsn = 0, bw_sn_slots = 0;
+  int bw_blocks = 0;
   // phase profiler: events[phase][2 * launch + {0: start, 1: stop}]
   bool prof_on = false;
   int prof_max = 0;
   int prof_count[PMP_NPHASE] = {0};
   std::vector<hipEvent_t> prof_events[PMP_NPHASE];
 
+  int* d_zone_off = nullptr;   // [28 nbox]
+  int* d_zone_seg = nullptr;
+  int2* d_apply_chunks = nullptr;
+  int2* d_fold_chunks = nullptr;
+  std::vector<long long> apply_chunk_off, fold_chunk_off;  // [nbox+1] host
   Mesh mesh() const {
     Mesh M;
     M.boxes = d_boxes;
+    M.all_boxes = d_boxes;
     M.nbox = nbox;
     M.ghost = ghost;
     for (int a = 0; a < 3; ++a) M.domain[a] = domain[a];
@@ -150,12 +164,26 @@ struct pmp_ctx {
     M.shell_prefix = d_shell_prefix;
     M.seg_off = d_seg_off;
     M.segs = d_segs;
+    M.zone_off = d_zone_off;
+    M.zone_seg = d_zone_seg;
+    M.apply_chunks = d_apply_chunks;
+    M.n_apply_chunks = apply_chunk_off.empty() ? 0 : apply_chunk_off.back();
+    M.fold_chunks = d_fold_chunks;
+    M.n_fold_chunks = fold_chunk_off.empty() ? 0 : fold_chunk_off.back();
     M.shell_cells = shell_cells;
     M.status = d_status;
     M.num_cu = num_cu;
     return M;
   }
   size_t acc_bytes() const { return acc == PMP_ACC_F32 ? 4 : 8; }
+  TileGrid tiles() const {
+    TileGrid T;
+    for (int a = 0; a < 3; ++a) T.t[a] = tile_dims[a];
+    T.tile_prefix = d_tile_prefix;
+    T.tiles_axis = d_tiles_axis;
+    T.ntiles = ntiles;
+    return T;
+  }
 };
 
 namespace {
@@ -201,6 +229,59 @@ void release(pmp_ctx* c) {
   (void)hipFree(c->d_segs);
   (void)hipFree(c->d_status);
   (void)hipFree(c->d_sink_scratch);
+  (void)hipFree(c->d_tile_prefix);
+  (void)hipFree(c->d_tiles_axis);
+  (void)hipFree(c->d_zone_off);
+  (void)hipFree(c->d_zone_seg);
+  (void)hipFree(c->d_apply_chunks);
+  (void)hipFree(c->d_fold_chunks);
+  (void)hipFree(c->bw.count);
+  (void)hipFree(c->bw.offset);
+  (void)hipFree(c->bw.block_sums);
+  (void)hipFree(c->bw.cic_rec);
+  (void)hipFree(c->bw.sn_rec);
+  (void)hipFree(c->bw.cic_slot);
+  (void)hipFree(c->bw.sn_slot);
+  (void)hipFree(c->bw.sn_n);
+  (void)hipFree(c->bw.sn_target);
+}
+
+// Tiles of edge (tx, tyz, tyz) over every padded box.
+int build_tiles(pmp_ctx* c, int tx, int tyz) {
+  const int t[3] = {tx, tyz, tyz};
+  std::vector<long long> prefix(c->nbox + 1, 0);
+  std::vector<int> axis(3 * (size_t)c->nbox);
+  for (int b = 0; b < c->nbox; ++b) {
+    long long n = 1;
+    for (int a = 0; a < 3; ++a) {
+      const int p = c->dboxes[b].p[a];
+      axis[3 * b + a] = (p + t[a] - 1) / t[a];
+      n *= axis[3 * b + a];
+    }
+    prefix[b + 1] = prefix[b] + n;
+  }
+  if (2 * prefix[c->nbox] + 1 >= (1ll << 31))
+    return fail(PMP_ERANGE, "too many tiles (%lld); use larger tiles", prefix[c->nbox]);
+  long long* dp = nullptr;
+  int* da = nullptr;
+  hipError_t e = dev_alloc(&dp, prefix.size());
+  if (e == hipSuccess) e = dev_alloc(&da, axis.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(dp, prefix.data(), sizeof(long long) * prefix.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(da, axis.data(), sizeof(int) * axis.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dp);
+    (void)hipFree(da);
+    return fail(PMP_EDEVICE, "tile grid: %s", hipGetErrorString(e));
+  }
+  (void)hipFree(c->d_tile_prefix);
+  (void)hipFree(c->d_tiles_axis);
+  c->d_tile_prefix = dp;
+  c->d_tiles_axis = da;
+  for (int a = 0; a < 3; ++a) c->tile_dims[a] = t[a];
+  c->ntiles = prefix[c->nbox];
+  return PMP_OK;
 }
 
 // Fold plan (Sec. 2.2 Step 2): for every destination box b and every source
@@ -265,6 +346,51 @@ int build_fold_plan(pmp_ctx* c, std::vector<int>& seg_off, std::vector<DevSeg>& 
   return PMP_OK;
 }
 
+// Zone lists: per box and per zone (3 x 3 x 3 split of each axis into
+// [0, g), [g, n - g), [n - g, n)), the plan's segments that reach the zone, in
+// plan order.  A shell cell only tests the segments of its own zone.
+void build_zones(const pmp_ctx* c, const std::vector<int>& seg_off,
+                 const std::vector<DevSeg>& segs, std::vector<int>& zone_off,
+                 std::vector<int>& zone_seg) {
+  zone_off.assign(28 * (size_t)c->nbox, 0);
+  zone_seg.clear();
+  for (int b = 0; b < c->nbox; ++b) {
+    int zl[3][3], zh[3][3];
+    for (int a = 0; a < 3; ++a) {
+      const int n = c->hboxes[b].n[a];
+      const int gl = std::min(c->ghost, n), hs = std::max(gl, n - c->ghost);
+      zl[a][0] = 0;  zh[a][0] = gl;
+      zl[a][1] = gl; zh[a][1] = hs;
+      zl[a][2] = hs; zh[a][2] = n;
+    }
+    for (int z = 0; z < 27; ++z) {
+      zone_off[28 * (size_t)b + z] = (int)zone_seg.size();
+      const int zz[3] = {z % 3, (z / 3) % 3, z / 9};
+      for (int q = seg_off[b]; q < seg_off[b + 1]; ++q) {
+        bool hit = true;
+        for (int a = 0; a < 3; ++a) {
+          const int l = std::max(segs[q].lo[a], zl[a][zz[a]]);
+          const int h = std::min(segs[q].hi[a], zh[a][zz[a]]);
+          if (l >= h) hit = false;
+        }
+        if (hit) zone_seg.push_back(q);
+      }
+    }
+    zone_off[28 * (size_t)b + 27] = (int)zone_seg.size();
+  }
+}
+
+// Chunks of kChunk cells per box for counts[b] cells; off[b] is box b's first chunk.
+void build_chunks(const std::vector<long long>& counts, std::vector<int2>& chunks,
+                  std::vector<long long>& off) {
+  chunks.clear();
+  off.assign(counts.size() + 1, 0);
+  for (size_t b = 0; b < counts.size(); ++b) {
+    for (long long c0 = 0; c0 < counts[b]; c0 += kChunk) chunks.push_back(make_int2((int)b, (int)c0));
+    off[b + 1] = (long long)chunks.size();
+  }
+}
+
 bool capturing(hipStream_t s) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
@@ -281,6 +407,77 @@ int ensure_sink_scratch(pmp_ctx* c, long long n, hipStream_t s) {
   PMP_HIP(dev_alloc(&c->d_sink_scratch, (size_t)(2 * n)));
   c->sink_cap = n;
   return PMP_OK;
+}
+
+// Most tiles a cell range of `len` cells can touch along an axis of tile edge t.
+long long tiles_for(long long len, int t) { return (len + t - 1) / t + 1; }
+
+// Size the binned-deposit scratch for these particle counts (never while a
+// graph is being captured).  Record arrays are sized for the most tiles a
+// particle can touch (8 for CIC; for a sphere, from its largest reach).
+template <class T> int regrow(T** p, long long have, long long need) {
+  if (need <= have) return PMP_OK;
+  (void)hipFree(*p);
+  *p = nullptr;
+  PMP_HIP(dev_alloc(p, (size_t)need));
+  return PMP_OK;
+}
+
+int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, hipStream_t s) {
+  const int* t = c->tile_dims;
+  const long long span = 2 * (long long)std::ceil(std::max(r_max, 0.0)) + 3;
+  const int maxt = (int)(tiles_for(span, t[0]) * tiles_for(span, t[1]) * tiles_for(span, t[2]));
+  const long long n2 = 2 * c->ntiles;
+  const int nblocks = (int)((n2 + 1023) / 1024);
+  const long long cic_cap = std::max<long long>(8 * n_cic, 1);
+  const long long sn_slots = std::max<long long>((long long)maxt * n_sn, 1);
+  if (cic_cap >= (1ll << 31) || sn_slots >= (1ll << 31))
+    return fail(PMP_ERANGE, "binned deposit: too many tile entries");
+  const bool grow = n2 > c->bw_tiles || nblocks > c->bw_blocks || cic_cap > c->bw.cic_cap ||
+                    n_cic > c->bw_ncic || sn_slots > c->bw_sn_slots || n_sn > c->bw_nsn;
+  c->bw.sn_maxt = maxt;
+  if (!grow) return PMP_OK;
+  if (capturing(s)) return fail(PMP_EINVAL, "binned-deposit scratch must be sized before capture");
+  PMP_HIP(hipStreamSynchronize(s));
+  int rc = PMP_OK;
+  if (!rc && n2 > c->bw_tiles) {
+    rc = regrow(&c->bw.count, 0, n2);
+    if (!rc) rc = regrow(&c->bw.offset, 0, n2 + 1);
+    if (!rc) c->bw_tiles = n2;
+  }
+  if (!rc && nblocks > c->bw_blocks) {
+    rc = regrow(&c->bw.block_sums, 0, (long long)nblocks + 1);
+    if (!rc) c->bw_blocks = nblocks;
+  }
+  if (!rc && cic_cap > c->bw.cic_cap) {
+    rc = regrow(&c->bw.cic_rec, 0, cic_cap);
+    if (!rc) rc = regrow(&c->bw.cic_slot, 0, cic_cap);
+    if (!rc) c->bw.cic_cap = cic_cap;
+  }
+  if (!rc && sn_slots > c->bw_sn_slots) {
+    rc = regrow(&c->bw.sn_rec, 0, sn_slots);
+    if (!rc) rc = regrow(&c->bw.sn_slot, 0, sn_slots);
+    if (!rc) {
+      c->bw.sn_cap = sn_slots;
+      c->bw_sn_slots = sn_slots;
+    }
+  }
+  if (!rc && n_sn > c->bw_nsn) {
+    rc = regrow(&c->bw.sn_n, 0, n_sn);
+    if (!rc) rc = regrow(&c->bw.sn_target, 0, n_sn);
+    if (!rc) c->bw_nsn = n_sn;
+  }
+  if (!rc && n_cic > c->bw_ncic) c->bw_ncic = n_cic;
+  if (rc) {
+    // a failed allocation leaves the scratch unusable: drop it all
+    (void)hipFree(c->bw.count); (void)hipFree(c->bw.offset); (void)hipFree(c->bw.block_sums);
+    (void)hipFree(c->bw.cic_rec); (void)hipFree(c->bw.cic_slot); (void)hipFree(c->bw.sn_rec);
+    (void)hipFree(c->bw.sn_slot); (void)hipFree(c->bw.sn_n); (void)hipFree(c->bw.sn_target);
+    c->bw = BinWork{};
+    c->bw_tiles = c->bw_ncic = c->bw_nsn = c->bw_sn_slots = 0;
+    c->bw_blocks = 0;
+  }
+  return rc;
 }
 
 Limits to_limits(const pmp_limits* L) {
@@ -367,17 +564,36 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
     if (rc) return rc;
   }
   const Mesh M = c->mesh();
-  {
-    PhaseTimer t(c, PMP_PHASE_ZERO, s);
-    PMP_HIP(launch_zero(buf, c->buffer_elems * (long long)c->acc_bytes(), c->tune.block, s));
-  }
-  if (has_cic) {
-    PhaseTimer t(c, PMP_PHASE_CIC, s);
-    PMP_HIP(launch_cic_direct(M, from_cic(cic), buf, nullptr, 0, c->tune.block, s));
-  }
-  if (has_sn) {
-    PhaseTimer t(c, PMP_PHASE_SN, s);
-    PMP_HIP(launch_sn_direct(M, from_sn(sn), buf, c->tune.sn_lanes, s));
+  if (c->tune.deposit_path == 1 && (has_cic || has_sn)) {
+    int rc = ensure_bin_work(c, has_cic ? cic->n : 0, has_sn ? sn->n : 0,
+                             has_sn ? sn->r_max : 0.0, s);
+    if (rc) return rc;
+    const Particles pc = has_cic ? from_cic(cic) : Particles{};
+    const Particles ps = has_sn ? from_sn(sn) : Particles{};
+    const TileGrid T = c->tiles();
+    {
+      PhaseTimer t(c, PMP_PHASE_BIN, s);
+      PMP_HIP(launch_bin(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
+                         c->tune.block, s));
+    }
+    {
+      PhaseTimer t(c, PMP_PHASE_TILE, s);
+      PMP_HIP(launch_tile_deposit(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
+                                  buf, c->tune, s));
+    }
+  } else {
+    {
+      PhaseTimer t(c, PMP_PHASE_ZERO, s);
+      PMP_HIP(launch_zero(buf, c->buffer_elems * (long long)c->acc_bytes(), c->tune.block, s));
+    }
+    if (has_cic) {
+      PhaseTimer t(c, PMP_PHASE_CIC, s);
+      PMP_HIP(launch_cic_direct(M, from_cic(cic), buf, c->tune.block, s));
+    }
+    if (has_sn) {
+      PhaseTimer t(c, PMP_PHASE_SN, s);
+      PMP_HIP(launch_sn_direct(M, from_sn(sn), buf, c->tune.sn_lanes, s));
+    }
   }
   if (has_sink) {
     PhaseTimer t(c, PMP_PHASE_SINK_DEPOSIT, s);
@@ -412,7 +628,18 @@ int do_apply(pmp_ctx* c, void* state, const void* buf, const pmp_limits* limits,
   int rc = check_limits(limits);
   if (rc) return rc;
   PhaseTimer t(c, PMP_PHASE_APPLY, s);
-  PMP_HIP(launch_apply(c->mesh(), state, buf, to_limits(limits), eta, c->tune.block, s));
+  PMP_HIP(launch_apply(c->mesh(), state, buf, to_limits(limits), eta, c->tune.block, 0, s));
+  return PMP_OK;
+}
+
+// Steps 2 + 3 + 5 in one kernel (no sinks): the apply gathers the ghost images
+// of its shell cells itself.
+int do_fold_apply(pmp_ctx* c, void* state, const void* buf, const pmp_limits* limits,
+                  hipStream_t s) {
+  int rc = check_limits(limits);
+  if (rc) return rc;
+  PhaseTimer t(c, PMP_PHASE_APPLY, s);
+  PMP_HIP(launch_apply(c->mesh(), state, buf, to_limits(limits), nullptr, c->tune.block, 1, s));
   return PMP_OK;
 }
 
@@ -426,6 +653,8 @@ int do_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn
             const pmp_sinks* sinks, const pmp_limits* limits, double* sink_out, hipStream_t s) {
   int rc = do_deposit(c, buf, state, cic, sn, sinks, limits, s);
   if (rc) return rc;
+  const bool has_sinks = sinks && sinks->n > 0;
+  if (!has_sinks && c->tune.fuse_fold) return do_fold_apply(c, state, buf, limits, s);
   rc = do_fold(c, buf, s);
   if (rc) return rc;
   if (sinks && sinks->n > 0) {
@@ -448,7 +677,7 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   if (!out || !L) return fail(PMP_EINVAL, "pmp_create: NULL argument");
   *out = nullptr;
   if (L->nbox < 1 || !L->lo || !L->n) return fail(PMP_EINVAL, "layout needs nbox >= 1 and boxes");
-  if (L->ghost < 0) return fail(PMP_EINVAL, "ghost width must be >= 0");
+  if (L->ghost < 0 || L->ghost > 64) return fail(PMP_EINVAL, "ghost width must be 0..64");
   if (!(L->dx > 0.0)) return fail(PMP_EINVAL, "dx must be > 0");
   if (L->acc < PMP_ACC_F32 || L->acc > PMP_ACC_FIX64) return fail(PMP_EINVAL, "bad acc type");
   if (L->state != PMP_STATE_F32 && L->state != PMP_STATE_F64)
@@ -541,6 +770,17 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   std::vector<DevSeg> segs;
   build_fold_plan(c, seg_off, segs);
   c->nseg = (int)segs.size();
+  std::vector<int> zone_off, zone_seg;
+  build_zones(c, seg_off, segs, zone_off, zone_seg);
+  std::vector<long long> owned_counts(c->nbox), shell_counts(c->nbox);
+  for (int b = 0; b < c->nbox; ++b) {
+    owned_counts[b] = owned_prefix[b + 1] - owned_prefix[b];
+    shell_counts[b] = shell_prefix[b + 1] - shell_prefix[b];
+    c->dboxes[b].shell = (int)shell_counts[b];
+  }
+  std::vector<int2> apply_chunks, fold_chunks;
+  build_chunks(owned_counts, apply_chunks, c->apply_chunk_off);
+  build_chunks(shell_counts, fold_chunks, c->fold_chunk_off);
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = dev_alloc(&c->d_boxes, c->nbox);
   if (e == hipSuccess) e = dev_alloc(&c->d_owned_prefix, c->nbox + 1);
@@ -561,6 +801,15 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
                   hipMemcpyHostToDevice);
   if (e == hipSuccess && !segs.empty())
     e = hipMemcpy(c->d_segs, segs.data(), sizeof(DevSeg) * segs.size(), hipMemcpyHostToDevice);
+  auto upload = [&](auto** dst, const auto& v) {
+    if (e == hipSuccess) e = dev_alloc(dst, v.size());
+    if (e == hipSuccess && !v.empty())
+      e = hipMemcpy(*dst, v.data(), sizeof(v[0]) * v.size(), hipMemcpyHostToDevice);
+  };
+  upload(&c->d_zone_off, zone_off);
+  upload(&c->d_zone_seg, zone_seg);
+  upload(&c->d_apply_chunks, apply_chunks);
+  upload(&c->d_fold_chunks, fold_chunks);
   if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(DevStatus));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -568,13 +817,24 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
     delete c;
     return fail(PMP_EDEVICE, "pmp_create: %s", hipGetErrorString(e));
   }
-  c->tune.deposit_path = 0;
-  c->tune.tile = 8;
-  c->tune.dense_min = 64;
-  c->tune.chunk = 4096;
+  c->tune.deposit_path = 1;
+  c->tune.tile_x = 64;
+  c->tune.tile_yz = 4;
+  c->tune.tile_block = 256;
   c->tune.block = 256;
   c->tune.grid_per_cu = 32;
   c->tune.sn_lanes = 64;
+  c->tune.tile_grid_per_cu = 0;
+  c->tune.fuse_fold = 0;
+  c->tune.reserved = 0;
+  {
+    int rc = build_tiles(c, c->tune.tile_x, c->tune.tile_yz);
+    if (rc) {
+      release(c);
+      delete c;
+      return rc;
+    }
+  }
   *out = c;
   return PMP_OK;
 }
@@ -625,6 +885,62 @@ int pmp_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_s
   return do_step(c, state, buf, cic, sn, sinks, limits, sink_out, (hipStream_t)stream);
 }
 
+int pmp_step_per_box(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn* sn,
+                     const pmp_limits* limits, const int64_t* cic_off, const int64_t* sn_off,
+                     void* stream) {
+  if (!c || !state || !buf) return fail(PMP_EINVAL, "per-box step: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const bool has_cic = cic && cic->n > 0, has_sn = sn && sn->n > 0;
+  if (has_cic && !cic_off) return fail(PMP_EINVAL, "per-box step: cic_off (host) is NULL");
+  if (has_sn && !sn_off) return fail(PMP_EINVAL, "per-box step: sn_off (host) is NULL");
+  if (has_cic && c->ghost < 1) return fail(PMP_ERANGE, "CIC deposits need ghost width >= 1");
+  if (has_sn && (!(sn->r_max >= 0.0) || std::floor(sn->r_max + 0.5) > c->ghost))
+    return fail(PMP_ERANGE, "supernova reach exceeds the ghost width");
+  int rc = check_limits(limits);
+  if (rc) return rc;
+  const Mesh all = c->mesh();
+  const Limits L = to_limits(limits);
+  const size_t ab = c->acc_bytes();
+  // Step 1 for every box, then Step 2 for every box (the fold reads other
+  // boxes' ghosts), then Steps 3 + 5 for every box.
+  for (int b = 0; b < c->nbox; ++b) {
+    Mesh M = all;
+    M.boxes = c->d_boxes + b;
+    M.nbox = 1;
+    char* base = (char*)buf;
+    const DevBox& D = c->dboxes[b];
+    PMP_HIP(launch_zero(base + D.boff * ab, (long long)(c->nfield * D.npad) * (long long)ab,
+                        c->tune.block, s));
+    if (has_cic && cic_off[b + 1] > cic_off[b]) {
+      Particles P = from_cic(cic);
+      const long long o = cic_off[b];
+      P.x += o; P.y += o; P.z += o; P.a += o;
+      P.n = cic_off[b + 1] - o;
+      PMP_HIP(launch_cic_direct(M, P, buf, c->tune.block, s));
+    }
+    if (has_sn && sn_off[b + 1] > sn_off[b]) {
+      Particles P = from_sn(sn);
+      const long long o = sn_off[b];
+      P.x += o; P.y += o; P.z += o; P.b += o; P.c += o; P.r += o;
+      P.n = sn_off[b + 1] - o;
+      PMP_HIP(launch_sn_direct(M, P, buf, c->tune.sn_lanes, s));
+    }
+  }
+  for (int b = 0; b < c->nbox; ++b) {
+    Mesh M = all;
+    M.fold_chunks = c->d_fold_chunks + c->fold_chunk_off[b];
+    M.n_fold_chunks = c->fold_chunk_off[b + 1] - c->fold_chunk_off[b];
+    PMP_HIP(launch_fold(M, buf, c->tune.block, s));
+  }
+  for (int b = 0; b < c->nbox; ++b) {
+    Mesh M = all;
+    M.apply_chunks = c->d_apply_chunks + c->apply_chunk_off[b];
+    M.n_apply_chunks = c->apply_chunk_off[b + 1] - c->apply_chunk_off[b];
+    PMP_HIP(launch_apply(M, state, buf, L, nullptr, c->tune.block, 0, s));
+  }
+  return PMP_OK;
+}
+
 int pmp_graph_build(pmp_ctx* c, int nsteps, void* state, void* buf, const pmp_cic* cic,
                     const pmp_sn* sn, const pmp_sinks* sinks, const pmp_limits* limits,
                     double* sink_out, void* stream) {
@@ -633,6 +949,11 @@ int pmp_graph_build(pmp_ctx* c, int nsteps, void* state, void* buf, const pmp_ci
   // size every scratch array before capture (no allocation inside a graph)
   if (sinks && sinks->n > 0) {
     int rc = ensure_sink_scratch(c, sinks->n, caller);
+    if (rc) return rc;
+  }
+  if (c->tune.deposit_path == 1) {
+    const long long nc = cic ? cic->n : 0, ns = sn ? sn->n : 0;
+    int rc = ensure_bin_work(c, nc, ns, (sn && sn->n > 0) ? sn->r_max : 0.0, caller);
     if (rc) return rc;
   }
   if (c->graph_exec) {
@@ -705,15 +1026,24 @@ int pmp_get_tuning(const pmp_ctx* c, pmp_tuning* out) {
 
 int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
   if (!c || !t) return fail(PMP_EINVAL, "NULL argument");
+  auto pow2_in = [](int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; };
   if (t->deposit_path < 0 || t->deposit_path > 1) return fail(PMP_EINVAL, "deposit_path 0 or 1");
-  if (t->tile != 4 && t->tile != 8 && t->tile != 16) return fail(PMP_EINVAL, "tile 4, 8 or 16");
-  if (t->dense_min < 1 || t->chunk < 64) return fail(PMP_EINVAL, "dense_min >= 1, chunk >= 64");
-  if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512 &&
-      t->block != 1024)
-    return fail(PMP_EINVAL, "block must be 64..1024, a power of two");
+  if (!pow2_in(t->tile_x, 16, 64)) return fail(PMP_EINVAL, "tile_x must be 16, 32 or 64");
+  if (!pow2_in(t->tile_yz, 2, 8)) return fail(PMP_EINVAL, "tile_yz must be 2, 4 or 8");
+  if (!pow2_in(t->tile_block, 64, 1024)) return fail(PMP_EINVAL, "tile_block 64..1024, power of 2");
+  if (!pow2_in(t->block, 64, 1024)) return fail(PMP_EINVAL, "block 64..1024, power of 2");
   if (t->grid_per_cu < 1 || t->grid_per_cu > 64) return fail(PMP_EINVAL, "grid_per_cu 1..64");
   if (t->sn_lanes != 16 && t->sn_lanes != 32 && t->sn_lanes != 64)
     return fail(PMP_EINVAL, "sn_lanes 16, 32 or 64");
+  if (t->tile_grid_per_cu < 0 || t->tile_grid_per_cu > 64)
+    return fail(PMP_EINVAL, "tile_grid_per_cu 0..64");
+  if (t->fuse_fold != 0 && t->fuse_fold != 1) return fail(PMP_EINVAL, "fuse_fold 0 or 1");
+  if (t->tile_x != c->tile_dims[0] || t->tile_yz != c->tile_dims[1]) {
+    if (c->graph_exec) return fail(PMP_EINVAL, "changing tiles would invalidate the built graph");
+    PMP_HIP(hipDeviceSynchronize());
+    int rc = build_tiles(c, t->tile_x, t->tile_yz);
+    if (rc) return rc;
+  }
   c->tune = *t;
   return PMP_OK;
 }
@@ -721,9 +1051,76 @@ int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
 int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn* sn,
                  const pmp_sinks* sinks, const pmp_limits* limits, double* sink_out,
                  void* stream, double* best_ms) {
-  (void)c; (void)state; (void)buf; (void)cic; (void)sn; (void)sinks; (void)limits;
-  (void)sink_out; (void)stream; (void)best_ms;
-  return fail(PMP_EUNSUPPORTED, "autotune not built yet");
+  if (!c || !state || !buf) return fail(PMP_EINVAL, "autotune: NULL argument");
+  if (c->graph_exec) return fail(PMP_EINVAL, "autotune would invalidate the built graph");
+  hipStream_t s = (hipStream_t)stream;
+  const bool has_sn = sn && sn->n > 0;
+  // candidates: the direct path and a set of tile shapes for the binned path
+  std::vector<pmp_tuning> cand;
+  const pmp_tuning base = c->tune;
+  auto add = [&](int path, int tx, int tyz, int tb, int lanes, int tgrid) {
+    pmp_tuning t = base;
+    t.deposit_path = path;
+    t.tile_x = tx;
+    t.tile_yz = tyz;
+    t.tile_block = tb;
+    t.sn_lanes = lanes;
+    t.tile_grid_per_cu = tgrid;
+    t.fuse_fold = 0;
+    cand.push_back(t);
+  };
+  add(0, base.tile_x, base.tile_yz, base.tile_block, 64, 0);
+  if (has_sn) add(0, base.tile_x, base.tile_yz, base.tile_block, 16, 0);
+  const int shapes[][3] = {{64, 4, 128}, {64, 4, 256}, {32, 4, 128}, {32, 8, 256},
+                           {16, 8, 256}, {64, 2, 128}, {16, 4, 128}};
+  for (const auto& sh : shapes) add(1, sh[0], sh[1], sh[2], 64, 0);
+  add(1, 64, 4, 128, 64, 8);
+  // the caller's state is left as it was: candidates run on a copy
+  const size_t sbytes = (size_t)c->state_elems * (c->state == PMP_STATE_F32 ? 4 : 8);
+  void* work = nullptr;
+  PMP_HIP(hipMalloc(&work, sbytes));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = PMP_OK;
+  double best = 1e300;
+  pmp_tuning best_t = base;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = fail(PMP_EDEVICE, "autotune: hipEventCreate failed");
+  for (size_t i = 0; i < cand.size() && rc == PMP_OK; ++i) {
+    rc = pmp_set_tuning(c, &cand[i]);
+    if (rc) break;
+    if (launch_copy(work, state, (long long)sbytes, s) != hipSuccess) {
+      rc = fail(PMP_EDEVICE, "autotune: state copy failed");
+      break;
+    }
+    for (int w = 0; w < 2 && rc == PMP_OK; ++w)
+      rc = do_step(c, work, buf, cic, sn, sinks, limits, sink_out, s);
+    if (rc) break;
+    const int reps = 5;
+    if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(PMP_EDEVICE, "event"); break; }
+    for (int r = 0; r < reps && rc == PMP_OK; ++r)
+      rc = do_step(c, work, buf, cic, sn, sinks, limits, sink_out, s);
+    if (rc) break;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      rc = fail(PMP_EDEVICE, "autotune: event timing failed");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double per = ms / reps;
+    if (per < best) {
+      best = per;
+      best_t = cand[i];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(work);
+  const int rc2 = pmp_set_tuning(c, rc == PMP_OK ? &best_t : &base);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (best_ms) *best_ms = best;
+  return PMP_OK;
 }
 
 int pmp_profile_begin(pmp_ctx* c, int max_launches) {

@@ -9,6 +9,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "pmp_internal.h"
@@ -117,9 +118,21 @@ __device__ __forceinline__ void sphere_range(double p, double r, int& lo, int& h
   hi = (int)floor(p + r - 0.5) + 1;
 }
 
+
 __device__ __forceinline__ int imod(int a, int n) {
   int r = a % n;
   return r < 0 ? r + n : r;
+}
+
+// Exact t / d for 0 <= t < 2^22 and d >= 1, from the float reciprocal inv =
+// 1/d: the estimate is within one of the quotient, and one correction step
+// settles it (far cheaper than an integer division, which gfx950 lacks).
+__device__ __forceinline__ int small_div(int t, int d, float inv) {
+  int q = (int)((float)t * inv);
+  const int r = t - q * d;
+  q += (r >= d) ? 1 : 0;
+  q -= (r < 0) ? 1 : 0;
+  return q;
 }
 
 // accumulator element types
@@ -158,6 +171,94 @@ template <int W> __device__ __forceinline__ int group_max(int v) {
   for (int o = W / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, W));
   return v;
 }
+
+// Sphere rows.  Fix a row (j, k) of the candidate box: the rounded test value
+// dist2(i) is non-increasing up to the row's nearest cell i = floor(x) and
+// non-decreasing after it (the rounded offset ((double)i + 0.5) - x is
+// monotone in i and rounding is monotone), so the cells passing
+// dist2 <= r^2 form one run [a, b].  row_members finds it from the
+// real-arithmetic half-width and settles both ends with the exact test, which
+// yields exactly the cells that testing every candidate would.
+struct Sphere {
+  double x, y, z, r2;
+  int lo[3], hi[3];  // candidate range (global cells), a superset of the members
+  int cy;            // candidate rows along y
+  int nrows;         // candidate rows (j, k), k-major
+};
+
+__device__ __forceinline__ void sphere_init(Sphere& S, double x, double y, double z, double r) {
+  S.x = x;
+  S.y = y;
+  S.z = z;
+  S.r2 = r * r;
+  sphere_range(x, r, S.lo[0], S.hi[0]);
+  sphere_range(y, r, S.lo[1], S.hi[1]);
+  sphere_range(z, r, S.lo[2], S.hi[2]);
+  S.cy = S.hi[1] - S.lo[1] + 1;
+  S.nrows = S.cy * (S.hi[2] - S.lo[2] + 1);
+}
+
+__device__ __forceinline__ void sphere_row(const Sphere& S, int t, int& j, int& k) {
+  const int kk = t / S.cy;
+  k = S.lo[2] + kk;
+  j = S.lo[1] + (t - kk * S.cy);
+}
+
+// Members [a, b] of row (j, k); empty when a > b.
+__device__ __forceinline__ void row_members(const Sphere& S, int j, int k, int& a, int& b) {
+  const int c = (int)floor(S.x);
+  if (!(dist2(S.x, S.y, S.z, c, j, k) <= S.r2)) {
+    a = 1;
+    b = 0;
+    return;
+  }
+  const double dy = ((double)j + 0.5) - S.y, dz = ((double)k + 0.5) - S.z;
+  const double w2 = S.r2 - (dy * dy + dz * dz);
+  const double w = w2 > 0.0 ? sqrt(w2) : 0.0;
+  int aa = (int)ceil(S.x - 0.5 - w), bb = (int)floor(S.x - 0.5 + w);
+  aa = min(max(aa, S.lo[0]), c);
+  bb = max(min(bb, S.hi[0]), c);
+  while (aa > S.lo[0] && dist2(S.x, S.y, S.z, aa - 1, j, k) <= S.r2) --aa;
+  while (aa < c && !(dist2(S.x, S.y, S.z, aa, j, k) <= S.r2)) ++aa;
+  while (bb < S.hi[0] && dist2(S.x, S.y, S.z, bb + 1, j, k) <= S.r2) ++bb;
+  while (bb > c && !(dist2(S.x, S.y, S.z, bb, j, k) <= S.r2)) --bb;
+  a = aa;
+  b = bb;
+}
+
+// Count of a sphere over a group of L lanes (lanes over rows): member count
+// N, the first member in (k, j, i) order packed as (row << 12) | (i - lo_x),
+// whether the host cell h is a member, and whether a member falls outside
+// the padded box B.
+template <int L>
+__device__ __forceinline__ void sphere_count(const Sphere& S, const DevBox& B, int g,
+                                             const int h[3], int lane, int& N, int& first,
+                                             int& hostm, int& outside) {
+  int cnt = 0, key = 0x7fffffff, hm = 0, out = 0;
+  for (int t = lane; t < S.nrows; t += L) {
+    int j, k, a, b;
+    sphere_row(S, t, j, k);
+    row_members(S, j, k, a, b);
+    if (a > b) continue;
+    cnt += b - a + 1;
+    key = min(key, (t << 12) | (a - S.lo[0]));
+    hm |= (j == h[1] && k == h[2] && a <= h[0] && h[0] <= b);
+    long long idx;
+    out |= !pad_index(B, g, a, j, k, idx) || !pad_index(B, g, b, j, k, idx);
+  }
+  N = group_sum<L>(cnt);
+  first = group_min<L>(key);
+  hostm = group_max<L>(hm);
+  outside = group_max<L>(out);
+}
+
+// Global cell of a packed first-member key.
+__device__ __forceinline__ void sphere_key_cell(const Sphere& S, int key, int& i, int& j,
+                                                int& k) {
+  sphere_row(S, key >> 12, j, k);
+  i = S.lo[0] + (key & 4095);
+}
+
 
 // ---------------------------------------------------------- zero and copy
 
@@ -239,18 +340,11 @@ __device__ __forceinline__ bool cic_one(double x, double y, double z, double m, 
 
 template <int ACC>
 __global__ __launch_bounds__(1024) void k_cic_direct(Mesh M, Particles P,
-                                                    typename AccT<ACC>::T* __restrict__ buf,
-                                                    const int* __restrict__ key,
-                                                    const int* __restrict__ tile_count,
-                                                    int dense_min) {
+                                                    typename AccT<ACC>::T* __restrict__ buf) {
   using T = typename AccT<ACC>::T;
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += stride) {
-    if (key) {
-      const int kt = key[p];
-      if (kt >= 0 && tile_count[kt] >= dense_min) continue;  // done in LDS
-    }
     const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
     const DevBox B = M.boxes[b];
     const double x = P.x[p], y = P.y[p], z = P.z[p], m = P.a[p];
@@ -272,10 +366,10 @@ __global__ __launch_bounds__(1024) void k_cic_direct(Mesh M, Particles P,
 
 // Uniform-sphere injection (Sec. 3.2.1, eq. "du" with full coverage, no
 // momentum term): the N cells whose centres lie within r get m/(N V) and
-// e/(N V).  A group of L lanes handles one particle: first it counts the
-// members, then it adds.  If no centre lies within r the host cell takes the
-// whole deposit.  Fixed point: residue to the host cell if it is a member,
-// else to the first member in (k, j, i) order.
+// e/(N V).  A group of L lanes handles one particle, lanes over the sphere's
+// rows: first the members are counted, then added.  If no centre lies within
+// r the host cell takes the whole deposit.  Fixed point: residue to the host
+// cell if it is a member, else to the first member in (k, j, i) order.
 template <int ACC, int L>
 __global__ __launch_bounds__(256) void k_sn_direct(Mesh M, Particles P,
                                                    typename AccT<ACC>::T* __restrict__ buf) {
@@ -302,27 +396,10 @@ __global__ __launch_bounds__(256) void k_sn_direct(Mesh M, Particles P,
       if (lane == 0) raise_flag(M.status, PMP_FLAG_REACH);
       continue;
     }
-    const double r2 = r * r;
-    int lo[3], hi[3];
-    sphere_range(x, r, lo[0], hi[0]);
-    sphere_range(y, r, lo[1], hi[1]);
-    sphere_range(z, r, lo[2], hi[2]);
-    const int cx = hi[0] - lo[0] + 1, cy = hi[1] - lo[1] + 1;
-    const int cxy = cx * cy;
-    const int total = cxy * (hi[2] - lo[2] + 1);
-    int cnt = 0, first = 0x7fffffff, hostm = 0;
-    for (int t = lane; t < total; t += L) {
-      const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
-      const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
-      if (dist2(x, y, z, i, j, k) <= r2) {
-        ++cnt;
-        first = min(first, t);
-        hostm |= (i == h[0] && j == h[1] && k == h[2]);
-      }
-    }
-    int N = group_sum<L>(cnt);
-    first = group_min<L>(first);
-    hostm = group_max<L>(hostm);
+    Sphere S;
+    sphere_init(S, x, y, z, r);
+    int N, first, hostm, outside;
+    sphere_count<L>(S, B, g, h, lane, N, first, hostm, outside);
     const bool only_host = (N == 0);
     if (only_host) { N = 1; hostm = 1; }
     const double cr = m / ((double)N * M.V);
@@ -337,15 +414,9 @@ __global__ __launch_bounds__(256) void k_sn_direct(Mesh M, Particles P,
     using T = typename AccT<ACC>::T;
     T* f0 = buf + B.boff;
     T* f4 = buf + B.boff + 4 * B.npad;
-    bool reach_bad = false;
-    for (int t = lane; t < total; t += L) {
-      const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
-      const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
-      const bool in = only_host ? (i == h[0] && j == h[1] && k == h[2])
-                                : (dist2(x, y, z, i, j, k) <= r2);
-      if (!in) continue;
+    auto put = [&](int i, int j, int k) {
       long long idx;
-      if (!pad_index(B, g, i, j, k, idx)) { reach_bad = true; continue; }
+      if (!pad_index(B, g, i, j, k, idx)) return;
       if constexpr (FIXED) {
         gadd_fix(f0 + idx, qr);
         gadd_fix(f4 + idx, qe);
@@ -353,17 +424,29 @@ __global__ __launch_bounds__(256) void k_sn_direct(Mesh M, Particles P,
         gadd(f0 + idx, cr);
         gadd(f4 + idx, ce);
       }
+    };
+    if (only_host) {
+      if (lane == 0) put(h[0], h[1], h[2]);
+    } else {
+      // candidates in (k, j, i) order, i fastest, so that the atomics of
+      // adjacent lanes land in adjacent cells
+      const int cx = S.hi[0] - S.lo[0] + 1, cxy = cx * S.cy;
+      const int total = cxy * (S.hi[2] - S.lo[2] + 1);
+      const float icx = 1.0f / (float)cx, icxy = 1.0f / (float)cxy;
+      for (int t = lane; t < total; t += L) {
+        const int kk = small_div(t, cxy, icxy), rem = t - kk * cxy;
+        const int jj = small_div(rem, cx, icx), ii = rem - jj * cx;
+        const int i = S.lo[0] + ii, j = S.lo[1] + jj, k = S.lo[2] + kk;
+        if (dist2(x, y, z, i, j, k) <= S.r2) put(i, j, k);
+      }
     }
-    if (reach_bad) raise_flag(M.status, PMP_FLAG_REACH);
+    if (lane == 0 && outside) raise_flag(M.status, PMP_FLAG_REACH);
     if constexpr (FIXED) {
       if (lane == 0) {
         long long Qr, Qe;
         if (quantise(m / M.V, Qr) && quantise(e / M.V, Qe)) {
           int ti = h[0], tj = h[1], tk = h[2];
-          if (!hostm) {
-            const int kk = first / cxy, rem = first - kk * cxy, jj = rem / cx;
-            ti = lo[0] + (rem - jj * cx); tj = lo[1] + jj; tk = lo[2] + kk;
-          }
+          if (!hostm) sphere_key_cell(S, first, ti, tj, tk);
           long long idx;
           if (pad_index(B, g, ti, tj, tk, idx)) {
             gadd_fix(f0 + idx, Qr - (long long)N * qr);
@@ -608,74 +691,99 @@ __global__ __launch_bounds__(64) void k_sink_update(Mesh M, Particles P,
 // within g of a face.  Order: z bands (low then high) whole planes, then in
 // the interior z layers the y bands whole rows, then in the interior rows the
 // x bands.
-__device__ __forceinline__ void shell_cell(const int n[3], int g, long long t, int& i, int& j,
+__device__ __forceinline__ void shell_cell(const int n[3], int g, unsigned t, int& i, int& j,
                                            int& k) {
   const int glz = min(g, n[2]), hsz = max(glz, n[2] - g), nbz = glz + (n[2] - hsz);
-  const long long plane = (long long)n[0] * n[1];
-  const long long cz = (long long)nbz * plane;
+  const unsigned nx = (unsigned)n[0];
+  const unsigned plane = nx * (unsigned)n[1];
+  const unsigned cz = (unsigned)nbz * plane;
   if (t < cz) {
-    const int kk = (int)(t / plane);
-    const long long r = t - (long long)kk * plane;
-    k = kk < glz ? kk : hsz + (kk - glz);
-    j = (int)(r / n[0]);
-    i = (int)(r - (long long)j * n[0]);
+    const unsigned kk = t / plane;
+    const unsigned r = t - kk * plane;
+    k = (int)kk < glz ? (int)kk : hsz + ((int)kk - glz);
+    const unsigned jj = r / nx;
+    j = (int)jj;
+    i = (int)(r - jj * nx);
     return;
   }
   t -= cz;
   const int gly = min(g, n[1]), hsy = max(gly, n[1] - g), nby = gly + (n[1] - hsy);
-  const long long cyc = (long long)(hsz - glz) * nby * n[0];
+  const unsigned cyc = (unsigned)(hsz - glz) * (unsigned)nby * nx;
   if (t < cyc) {
-    const long long row = t / n[0];
-    i = (int)(t - row * n[0]);
-    const int jj = (int)(row % nby);
-    k = glz + (int)(row / nby);
+    const unsigned row = t / nx;
+    i = (int)(t - row * nx);
+    const unsigned kq = row / (unsigned)nby;
+    const int jj = (int)(row - kq * (unsigned)nby);
+    k = glz + (int)kq;
     j = jj < gly ? jj : hsy + (jj - gly);
     return;
   }
   t -= cyc;
   const int glx = min(g, n[0]), hsx = max(glx, n[0] - g), nbx = glx + (n[0] - hsx);
-  const int ii = (int)(t % nbx);
-  const long long r = t / nbx;
-  const int midy = hsy - gly;
-  j = gly + (int)(r % midy);
-  k = glz + (int)(r / midy);
+  const unsigned r = t / (unsigned)nbx;
+  const int ii = (int)(t - r * (unsigned)nbx);
+  const unsigned midy = (unsigned)(hsy - gly);
+  const unsigned kq = r / midy;
+  j = gly + (int)(r - kq * midy);
+  k = glz + (int)kq;
   i = ii < glx ? ii : hsx + (ii - glx);
 }
+
+// Adds to acc every ghost cell (of any box) whose periodic image is owned
+// cell (i, j, k) of box b, in the fixed order of the plan (App. A.2).
+template <int ACC, int F, class Sum>
+__device__ __forceinline__ bool fold_gather(const Mesh& M, int b, int i, int j, int k,
+                                            const typename AccT<ACC>::T* __restrict__ buf,
+                                            Sum acc[F]) {
+  bool any = false;
+  const DevBox& Bd = M.all_boxes[b];
+  const int g = M.ghost;
+  auto zone = [&](int v, int a) {
+    const int gl = min(g, Bd.n[a]), hs = max(gl, Bd.n[a] - g);
+    return v < gl ? 0 : (v < hs ? 1 : 2);
+  };
+  const int z = zone(i, 0) + 3 * zone(j, 1) + 9 * zone(k, 2);
+  const int* zo = M.zone_off + 28 * b;
+  const int q1 = zo[z + 1];
+  for (int q = zo[z]; q < q1; ++q) {
+    const DevSeg S = M.segs[M.zone_seg[q]];
+    if (i < S.lo[0] || i >= S.hi[0] || j < S.lo[1] || j >= S.hi[1] || k < S.lo[2] ||
+        k >= S.hi[2])
+      continue;
+    const DevBox& Bs = M.all_boxes[S.src];
+    const long long src = Bs.boff + ((long long)(k + S.off[2]) * Bs.p[1] + (j + S.off[1])) *
+                                        Bs.p[0] + (i + S.off[0]);
+#pragma unroll
+    for (int f = 0; f < F; ++f) acc[f] += (Sum)buf[src + f * Bs.npad];
+    any = true;
+  }
+  return any;
+}
+
+template <int ACC>
+using SumT = typename std::conditional<ACC == PMP_ACC_FIX64, long long, double>::type;
 
 // Step 2 (Sec. 2.2; App. A.2): each owned shell cell gathers every ghost cell
 // whose periodic image it is, in the fixed order of the plan, and writes the
 // sum once.  Float buffers sum in double and round once.
 template <int ACC, int F>
-__global__ __launch_bounds__(1024) void k_fold(Mesh M, typename AccT<ACC>::T* __restrict__ buf) {
+__global__ __launch_bounds__(kChunk) void k_fold(Mesh M, typename AccT<ACC>::T* __restrict__ buf) {
   using T = typename AccT<ACC>::T;
-  using Sum = typename std::conditional<ACC == PMP_ACC_FIX64, long long, double>::type;
-  const long long stride = (long long)gridDim.x * blockDim.x;
+  using Sum = SumT<ACC>;
   const int g = M.ghost;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < M.shell_cells;
-       t += stride) {
-    const int b = (M.nbox == 1) ? 0 : find_box(M.shell_prefix, M.nbox, t);
-    const DevBox B = M.boxes[b];
+  for (long long ch = blockIdx.x; ch < M.n_fold_chunks; ch += gridDim.x) {
+    const int2 C = M.fold_chunks[ch];
+    const int b = C.x;
+    const DevBox B = M.all_boxes[b];
+    const int t = C.y + (int)threadIdx.x;
+    if (t >= B.shell) continue;
     int i, j, k;
-    shell_cell(B.n, g, t - M.shell_prefix[b], i, j, k);
+    shell_cell(B.n, g, (unsigned)t, i, j, k);
     const long long dst = B.boff + ((long long)(k + g) * B.p[1] + (j + g)) * B.p[0] + (i + g);
     Sum acc[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) acc[f] = (Sum)buf[dst + f * B.npad];
-    bool any = false;
-    const int s1 = M.seg_off[b + 1];
-    for (int s = M.seg_off[b]; s < s1; ++s) {
-      const DevSeg S = M.segs[s];
-      if (i < S.lo[0] || i >= S.hi[0] || j < S.lo[1] || j >= S.hi[1] || k < S.lo[2] ||
-          k >= S.hi[2])
-        continue;
-      const DevBox& Bs = M.boxes[S.src];
-      const long long src = Bs.boff + ((long long)(k + S.off[2]) * Bs.p[1] + (j + S.off[1])) *
-                                          Bs.p[0] + (i + S.off[0]);
-#pragma unroll
-      for (int f = 0; f < F; ++f) acc[f] += (Sum)buf[src + f * Bs.npad];
-      any = true;
-    }
-    if (any) {
+    if (fold_gather<ACC, F>(M, b, i, j, k, buf, acc)) {
 #pragma unroll
       for (int f = 0; f < F; ++f) buf[dst + f * B.npad] = (T)acc[f];
     }
@@ -685,23 +793,27 @@ __global__ __launch_bounds__(1024) void k_fold(Mesh M, typename AccT<ACC>::T* __
 // ------------------------------------------------------------------ apply
 
 // Steps 3 + 5 per owned cell, in double precision (see pmp_apply).
-template <class S, int ACC, int F>
-__global__ __launch_bounds__(1024) void k_apply(Mesh M, S* __restrict__ state,
-                                               const typename AccT<ACC>::T* __restrict__ buf,
-                                               Limits L, double* __restrict__ eta) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
+template <class S, int ACC, int F, bool FOLD>
+__global__ __launch_bounds__(kChunk) void k_apply(Mesh M, S* __restrict__ state,
+                                                 const typename AccT<ACC>::T* __restrict__ buf,
+                                                 Limits L, double* __restrict__ eta) {
+  using T = typename AccT<ACC>::T;
   const int g = M.ghost;
   unsigned long long touched = 0, bind = 0, lamc = 0, fall = 0;
   bool bad = false;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < M.owned_cells;
-       t += stride) {
-    const int b = (M.nbox == 1) ? 0 : find_box(M.owned_prefix, M.nbox, t);
-    const DevBox B = M.boxes[b];
-    const long long c = t - M.owned_prefix[b];
-    const long long row = c / B.n[0];
-    const int i = (int)(c - row * B.n[0]);
-    const int j = (int)(row % B.n[1]);
-    const int k = (int)(row / B.n[1]);
+  for (long long ch = blockIdx.x; ch < M.n_apply_chunks; ch += gridDim.x) {
+    const int2 C = M.apply_chunks[ch];
+    const int b = C.x;
+    const DevBox B = M.all_boxes[b];
+    const long long c = (long long)C.y + threadIdx.x;
+    if (c >= B.ncell) continue;
+    // box cells < 2^31: 32-bit index arithmetic
+    const unsigned cu = (unsigned)c, nx = (unsigned)B.n[0], ny = (unsigned)B.n[1];
+    const unsigned row = cu / nx;
+    const int i = (int)(cu - row * nx);
+    const unsigned kq = row / ny;
+    const int j = (int)(row - kq * ny);
+    const int k = (int)kq;
     const long long bi = B.boff + ((long long)(k + g) * B.p[1] + (j + g)) * B.p[0] + (i + g);
     S* st = state + B.soff + c;
     const double rho = (double)st[0];
@@ -709,12 +821,29 @@ __global__ __launch_bounds__(1024) void k_apply(Mesh M, S* __restrict__ state,
     const double py = (double)st[2 * B.ncell];
     const double pz = (double)st[3 * B.ncell];
     const double E = (double)st[4 * B.ncell];
-    const double Dr = to_f64(buf[bi]);
-    const double qx = to_f64(buf[bi + B.npad]);
-    const double qy = to_f64(buf[bi + 2 * B.npad]);
-    const double qz = to_f64(buf[bi + 3 * B.npad]);
-    const double DE = to_f64(buf[bi + 4 * B.npad]);
-    const double K = (F == 6) ? to_f64(buf[bi + 5 * B.npad]) : 0.0;
+    T v[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) v[f] = buf[bi + f * B.npad];
+    if constexpr (FOLD) {
+      // shell cells take their ghost images first, summed exactly as the
+      // separate fold kernel sums them
+      if (i < g || j < g || k < g || i >= B.n[0] - g || j >= B.n[1] - g || k >= B.n[2] - g) {
+        SumT<ACC> acc[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) acc[f] = (SumT<ACC>)v[f];
+        if (fold_gather<ACC, F>(M, b, i, j, k, buf, acc)) {
+#pragma unroll
+          for (int f = 0; f < F; ++f) v[f] = (T)acc[f];
+        }
+      }
+    }
+    const double Dr = to_f64(v[0]);
+    const double qx = to_f64(v[1]);
+    const double qy = to_f64(v[2]);
+    const double qz = to_f64(v[3]);
+    const double DE = to_f64(v[4]);
+    double K = 0.0;
+    if constexpr (F == 6) K = to_f64(v[5]);
     const double Kl = limited_removal(K, rho, L);
     if (K > 0.0) {
       ++touched;
@@ -777,6 +906,448 @@ __global__ __launch_bounds__(1024) void k_apply(Mesh M, S* __restrict__ state,
   }
 }
 
+
+// ------------------------------------------------------------- binned path
+//
+// Particles are binned into tiles of the padded box their stencil touches
+// (a counting sort: count, scan, fill).  One workgroup then owns one tile:
+// it accumulates every contribution to its cells in LDS (FP64 for the float
+// buffers, int64 for fixed point) and stores each field of each cell once.
+// No global atomics, and no separate zero fill: cells nobody touches are
+// stored as zero.
+
+// Padded-local cell range [lo, hi] of the CIC stencil of a particle.
+__device__ __forceinline__ void cic_box(const DevBox& B, int g, double x, double y, double z,
+                                        int lo[3], int hi[3]) {
+  const double p[3] = {x, y, z};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = (int)floor(p[a] - 0.5) - B.lo[a] + g;
+    hi[a] = lo[a] + 1;
+  }
+}
+
+// Padded-local cell range holding every cell whose centre can pass the
+// sphere test (the 1e-6 margin covers rounding of the test at the edge).
+__device__ __forceinline__ void sphere_box(const DevBox& B, int g, double x, double y, double z,
+                                           double r, int lo[3], int hi[3]) {
+  const double p[3] = {x, y, z};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = (int)floor(p[a] - r - 0.5 - 1e-6) - B.lo[a] + g;
+    hi[a] = (int)floor(p[a] + r - 0.5 + 1e-6) - B.lo[a] + g;
+  }
+}
+
+// Tiles overlapped by padded-local cells [lo, hi] clipped to the padded box.
+__device__ __forceinline__ bool tile_range(const DevBox& B, const TileGrid& T, const int lo[3],
+                                           const int hi[3], int tlo[3], int thi[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int l = max(lo[a], 0), h = min(hi[a], B.p[a] - 1);
+    if (l > h) return false;
+    tlo[a] = l / T.t[a];
+    thi[a] = h / T.t[a];
+  }
+  return true;
+}
+
+__device__ __forceinline__ long long tile_id(const TileGrid& T, int b, int tx, int ty, int tz) {
+  const int* ta = T.tiles_axis + 3 * b;
+  return T.tile_prefix[b] + ((long long)tz * ta[1] + ty) * ta[0] + tx;
+}
+
+// Count pass (FILL = false): every CIC particle takes a slot in each tile its
+// stencil touches and records it; fill pass (FILL = true): the particle's
+// record is written to each of those slots.  At most 8 tiles per particle.
+template <bool FILL>
+__global__ __launch_bounds__(1024) void k_bin_cic(Mesh M, TileGrid T, Particles P,
+                                                  int* __restrict__ count,
+                                                  const int* __restrict__ offset,
+                                                  int* __restrict__ slot,
+                                                  double4* __restrict__ rec, long long cap) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const int g = M.ghost;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += stride) {
+    const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
+    const DevBox B = M.boxes[b];
+    const double x = P.x[p], y = P.y[p], z = P.z[p], m = P.a[p];
+    int h[3];
+    if (!host_cell(B, x, y, z, h)) {
+      if (!FILL) raise_flag(M.status, PMP_FLAG_OUTSIDE);
+      continue;
+    }
+    if (!isfinite(m)) {
+      if (!FILL) raise_flag(M.status, PMP_FLAG_NAN);
+      continue;
+    }
+    int lo[3], hi[3], tlo[3], thi[3];
+    cic_box(B, g, x, y, z, lo, hi);
+    if (!tile_range(B, T, lo, hi, tlo, thi)) continue;
+    int q = 0;
+    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
+      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
+        for (int tx = tlo[0]; tx <= thi[0]; ++tx, ++q) {
+          const long long t = tile_id(T, b, tx, ty, tz);
+          if (!FILL) {
+            slot[8 * p + q] = atomicAdd(count + t, 1);
+          } else {
+            const long long pos = (long long)offset[t] + slot[8 * p + q];
+            if (pos < cap) rec[pos] = make_double4(x, y, z, m);
+            else raise_flag(M.status, PMP_FLAG_CAPACITY);
+          }
+        }
+  }
+}
+
+// Supernova count pass: a group of L lanes per particle counts the sphere's
+// members N (sn_n = N; -1 when no centre lies within r and the host cell takes
+// the deposit; 0 when the particle is skipped), finds the fixed-point
+// remainder cell (host if a member, else the first member in (k, j, i) order),
+// and takes a slot in every tile its sphere touches.
+template <int L>
+__global__ __launch_bounds__(256) void k_bin_sn(Mesh M, TileGrid T, Particles P,
+                                                int* __restrict__ count, int* __restrict__ slot,
+                                                int maxt, int* __restrict__ sn_n,
+                                                int* __restrict__ sn_target) {
+  const int lane = threadIdx.x % L;
+  const long long ngroups = ((long long)gridDim.x * blockDim.x) / L;
+  const int g = M.ghost;
+  for (long long p = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / L; p < P.n;
+       p += ngroups) {
+    const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
+    const DevBox B = M.boxes[b];
+    const double x = P.x[p], y = P.y[p], z = P.z[p];
+    const double m = P.b[p], e = P.c[p], r = P.r[p];
+    int h[3];
+    if (!host_cell(B, x, y, z, h)) {
+      if (lane == 0) { raise_flag(M.status, PMP_FLAG_OUTSIDE); sn_n[p] = 0; }
+      continue;
+    }
+    if (!isfinite(m) || !isfinite(e) || !isfinite(r) || !(r >= 0.0)) {
+      if (lane == 0) { raise_flag(M.status, PMP_FLAG_NAN); sn_n[p] = 0; }
+      continue;
+    }
+    if (floor(r + 0.5) > (double)g) {
+      if (lane == 0) { raise_flag(M.status, PMP_FLAG_REACH); sn_n[p] = 0; }
+      continue;
+    }
+    Sphere Sp;
+    sphere_init(Sp, x, y, z, r);
+    int N, first, hostm, outside;
+    sphere_count<L>(Sp, B, g, h, lane, N, first, hostm, outside);
+    const bool only_host = (N == 0);
+    int slo[3], shi[3], tlo[3], thi[3];
+    if (only_host) {
+      for (int a = 0; a < 3; ++a) slo[a] = shi[a] = h[a] - B.lo[a] + g;
+    } else {
+      sphere_box(B, g, x, y, z, r, slo, shi);
+    }
+    if (lane == 0) {
+      if (outside) raise_flag(M.status, PMP_FLAG_REACH);
+      int ti = h[0], tj = h[1], tk = h[2];
+      if (!only_host && !hostm) sphere_key_cell(Sp, first, ti, tj, tk);
+      long long idx;
+      sn_target[p] = pad_index(B, g, ti, tj, tk, idx) ? (int)idx : -1;
+      sn_n[p] = only_host ? -1 : N;
+    }
+    if (!tile_range(B, T, slo, shi, tlo, thi)) continue;
+    const int nx = thi[0] - tlo[0] + 1, ny = thi[1] - tlo[1] + 1;
+    const int nt = nx * ny * (thi[2] - tlo[2] + 1);
+    if (nt > maxt) {  // cannot happen for reach <= ghost; guarded all the same
+      if (lane == 0) raise_flag(M.status, PMP_FLAG_CAPACITY);
+      continue;
+    }
+    for (int t = lane; t < nt; t += L) {
+      const int tz = tlo[2] + t / (nx * ny), rem = t % (nx * ny);
+      const long long id = T.ntiles + tile_id(T, b, tlo[0] + rem % nx, tlo[1] + rem / nx, tz);
+      slot[(long long)maxt * p + t] = atomicAdd(count + id, 1);
+    }
+  }
+}
+
+// Supernova fill pass: one thread per particle writes its record to every
+// slot it took.
+__global__ __launch_bounds__(1024) void k_fill_sn(Mesh M, TileGrid T, Particles P,
+                                                  const int* __restrict__ offset,
+                                                  const int* __restrict__ slot, int maxt,
+                                                  const int* __restrict__ sn_n,
+                                                  const int* __restrict__ sn_target,
+                                                  SnRec* __restrict__ rec, long long cap) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const int g = M.ghost;
+  const long long base = offset[T.ntiles];
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += stride) {
+    const int N = sn_n[p];
+    if (N == 0) continue;
+    const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
+    const DevBox B = M.boxes[b];
+    SnRec R;
+    R.x = P.x[p];
+    R.y = P.y[p];
+    R.z = P.z[p];
+    R.m = P.b[p];
+    R.e = P.c[p];
+    R.r = P.r[p];
+    R.n = N;
+    R.target = sn_target[p];
+    int slo[3], shi[3], tlo[3], thi[3];
+    if (N < 0) {
+      const double q[3] = {R.x, R.y, R.z};
+      for (int a = 0; a < 3; ++a) slo[a] = shi[a] = (int)floor(q[a]) - B.lo[a] + g;
+    } else {
+      sphere_box(B, g, R.x, R.y, R.z, R.r, slo, shi);
+    }
+    if (!tile_range(B, T, slo, shi, tlo, thi)) continue;
+    const int nx = thi[0] - tlo[0] + 1, ny = thi[1] - tlo[1] + 1;
+    const int nt = nx * ny * (thi[2] - tlo[2] + 1);
+    if (nt > maxt) continue;
+    for (int t = 0; t < nt; ++t) {
+      const int tz = tlo[2] + t / (nx * ny), rem = t % (nx * ny);
+      const long long id = T.ntiles + tile_id(T, b, tlo[0] + rem % nx, tlo[1] + rem / nx, tz);
+      const long long pos = (long long)offset[id] - base + slot[(long long)maxt * p + t];
+      if (pos < cap) rec[pos] = R;
+      else raise_flag(M.status, PMP_FLAG_CAPACITY);
+    }
+  }
+}
+
+// Exclusive scan of count[0, n) into offset[0, n] (offset[n] = total) in
+// three launches; count is cleared on the way (it becomes the fill cursor).
+constexpr int kScanBlock = 1024;
+
+__device__ __forceinline__ int block_inclusive_scan(int v, int* sh) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(v, o, kWave);
+    if (lane >= o) v += u;
+  }
+  if (lane == kWave - 1) sh[wave] = v;
+  __syncthreads();
+  if (wave == 0) {
+    int w = (lane < (int)(blockDim.x / kWave)) ? sh[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int u = __shfl_up(w, o, kWave);
+      if (lane >= o) w += u;
+    }
+    sh[lane] = w;
+  }
+  __syncthreads();
+  if (wave > 0) v += sh[wave - 1];
+  __syncthreads();
+  return v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_local(int* __restrict__ count,
+                                                            int* __restrict__ offset,
+                                                            int* __restrict__ block_sums,
+                                                            long long n) {
+  __shared__ int sh[kWave];
+  const long long i = (long long)blockIdx.x * kScanBlock + threadIdx.x;
+  const int v = (i < n) ? count[i] : 0;
+  if (i < n) count[i] = 0;
+  const int inc = block_inclusive_scan(v, sh);
+  if (i < n) offset[i] = inc - v;
+  if (threadIdx.x == kScanBlock - 1) block_sums[blockIdx.x] = inc;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_top(int* __restrict__ block_sums,
+                                                          int nblocks, int* __restrict__ offset,
+                                                          long long n) {
+  __shared__ int sh[kWave];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nblocks; base += kScanBlock) {
+    const int i = base + threadIdx.x;
+    const int v = (i < nblocks) ? block_sums[i] : 0;
+    const int inc = block_inclusive_scan(v, sh);
+    const int c = carry;
+    if (i < nblocks) block_sums[i] = c + inc - v;
+    __syncthreads();
+    if (threadIdx.x == kScanBlock - 1) carry = c + inc;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) offset[n] = carry;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_add(int* __restrict__ offset,
+                                                          const int* __restrict__ block_sums,
+                                                          long long n) {
+  const long long i = (long long)blockIdx.x * kScanBlock + threadIdx.x;
+  if (i < n) offset[i] += block_sums[blockIdx.x];
+}
+
+template <bool FIXED> struct LdsT;
+template <> struct LdsT<true> { using T = unsigned long long; };
+template <> struct LdsT<false> { using T = double; };
+
+__device__ __forceinline__ void lds_add(unsigned long long* p, long long q) {
+  atomicAdd(p, (unsigned long long)q);
+}
+__device__ __forceinline__ void lds_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+template <class T> __device__ __forceinline__ T from_lds(unsigned long long v);
+template <> __device__ __forceinline__ long long from_lds<long long>(unsigned long long v) {
+  return (long long)v;
+}
+template <class T> __device__ __forceinline__ T from_lds(double v) { return (T)v; }
+
+// One workgroup per tile: CIC entries one per thread, supernova entries one
+// per wavefront with lanes over the tile's share of the sphere; then every
+// field of every cell of the tile is stored once (fields without sources as
+// zero).  Sphere membership, shares and fixed-point remainders are the same
+// as in the direct kernels.
+template <int ACC>
+__global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
+                                                      const int* __restrict__ offset,
+                                                      const double4* __restrict__ crec,
+                                                      long long ccap,
+                                                      const SnRec* __restrict__ srec,
+                                                      long long scap,
+                                                      typename AccT<ACC>::T* __restrict__ buf) {
+  using OutT = typename AccT<ACC>::T;
+  constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
+  using LT = typename LdsT<FIXED>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int TX = T.t[0], TY = T.t[1], TZ = T.t[2];
+  const int tcells = TX * TY * TZ;
+  LT* a0 = reinterpret_cast<LT*>(smem);
+  LT* a4 = a0 + tcells;
+  const int nwave = blockDim.x / kWave, wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int g = M.ghost;
+  for (long long tile = blockIdx.x; tile < T.ntiles; tile += gridDim.x) {
+    const int b = (M.nbox == 1) ? 0 : find_box(T.tile_prefix, M.nbox, tile);
+    const DevBox B = M.boxes[b];
+    const int* ta = T.tiles_axis + 3 * b;
+    const long long lt = tile - T.tile_prefix[b];
+    const int tx = (int)(lt % ta[0]);
+    const long long rr = lt / ta[0];
+    const int ty = (int)(rr % ta[1]), tz = (int)(rr / ta[1]);
+    const int o[3] = {tx * TX, ty * TY, tz * TZ};
+    const int ext[3] = {min(TX, B.p[0] - o[0]), min(TY, B.p[1] - o[1]), min(TZ, B.p[2] - o[2])};
+    for (int c = threadIdx.x; c < tcells; c += blockDim.x) {
+      a0[c] = (LT)0;
+      a4[c] = (LT)0;
+    }
+    __syncthreads();
+    // global cell -> tile cell, if the tile holds it
+    auto tcell = [&](int i, int j, int k, int& c) -> bool {
+      const int u = i - B.lo[0] + g - o[0], v = j - B.lo[1] + g - o[1], w = k - B.lo[2] + g - o[2];
+      if ((unsigned)u >= (unsigned)ext[0] || (unsigned)v >= (unsigned)ext[1] ||
+          (unsigned)w >= (unsigned)ext[2])
+        return false;
+      c = (w * TY + v) * TX + u;
+      return true;
+    };
+    bool ovf = false;
+    // entries past the capacity were never written (flagged in the fill)
+    const long long e0 = offset[tile], e1 = min((long long)offset[tile + 1], ccap);
+    for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      const double4 R = crec[e];
+      const double x = R.x, y = R.y, z = R.z, m = R.w;
+      const int h[3] = {(int)floor(x), (int)floor(y), (int)floor(z)};
+      auto add = [&](int i, int j, int k, auto v) {
+        int c;
+        if (tcell(i, j, k, c)) lds_add(a0 + c, v);
+      };
+      if (!cic_one<FIXED>(x, y, z, m, M.V, h, add)) ovf = true;
+    }
+    // supernovae: G lanes per entry (one lane per row of the tile), 64/G
+    // entries per wavefront at a time
+    const long long sbase = offset[T.ntiles];
+    const long long s0 = offset[T.ntiles + tile] - sbase;
+    const long long s1 = min((long long)offset[T.ntiles + tile + 1] - sbase, scap);
+    const int G = TY * TZ < kWave ? TY * TZ : kWave;
+    const int per_wave = kWave / G;
+    for (long long e = s0 + wave * per_wave + lane / G; e < s1; e += nwave * per_wave) {
+      const int row = lane % G;
+      const SnRec& R = srec[e];
+      const double x = R.x, y = R.y, z = R.z, m = R.m, en = R.e, r = R.r;
+      int N = R.n;
+      const bool only_host = (N < 0);
+      if (only_host) N = 1;
+      const double cr = m / ((double)N * M.V);
+      const double ce = en / ((double)N * M.V);
+      long long qr = 0, qe = 0;
+      if constexpr (FIXED) {
+        if (!quantise(cr, qr) || !quantise(ce, qe)) { ovf = true; continue; }
+      }
+      Sphere Sp;
+      if (!only_host) sphere_init(Sp, x, y, z, r);
+      // tile rows handled by this lane: (ry, rz) and, for tiles with more
+      // than 64 rows, every G-th row after it
+      for (int rr = row; rr < TY * TZ; rr += G) {
+        const int ry = rr % TY, rz = rr / TY;
+        if (ry >= ext[1] || rz >= ext[2]) continue;
+        const int j = o[1] + ry - g + B.lo[1], k = o[2] + rz - g + B.lo[2];
+        int a, bb;
+        if (only_host) {
+          const int hx = (int)floor(x);
+          if (j != (int)floor(y) || k != (int)floor(z)) continue;
+          a = bb = hx;
+        } else {
+          if (j < Sp.lo[1] || j > Sp.hi[1] || k < Sp.lo[2] || k > Sp.hi[2]) continue;
+          row_members(Sp, j, k, a, bb);
+        }
+        // clip to the tile's x range (global)
+        const int xlo = o[0] - g + B.lo[0], xhi = xlo + ext[0] - 1;
+        a = max(a, xlo);
+        bb = min(bb, xhi);
+        const int cbase = (rz * TY + ry) * TX - xlo;
+        for (int i = a; i <= bb; ++i) {
+          if constexpr (FIXED) {
+            lds_add(a0 + cbase + i, qr);
+            lds_add(a4 + cbase + i, qe);
+          } else {
+            lds_add(a0 + cbase + i, cr);
+            lds_add(a4 + cbase + i, ce);
+          }
+        }
+      }
+      if constexpr (FIXED) {
+        const int tgt = R.target;
+        if (row == 0 && tgt >= 0) {
+          const int li = tgt % B.p[0], rest = tgt / B.p[0];
+          const int lj = rest % B.p[1], lk = rest / B.p[1];
+          const int u = li - o[0], v = lj - o[1], w = lk - o[2];
+          if ((unsigned)u < (unsigned)ext[0] && (unsigned)v < (unsigned)ext[1] &&
+              (unsigned)w < (unsigned)ext[2]) {
+            long long Qr, Qe;
+            if (quantise(m / M.V, Qr) && quantise(en / M.V, Qe)) {
+              const int c = (w * TY + v) * TX + u;
+              lds_add(a0 + c, Qr - (long long)N * qr);
+              lds_add(a4 + c, Qe - (long long)N * qe);
+            } else {
+              ovf = true;
+            }
+          }
+        }
+      }
+    }
+    if (ovf) raise_flag(M.status, PMP_FLAG_OVERFLOW);
+    __syncthreads();
+    OutT* f0 = buf + B.boff;
+    const long long np = B.npad;
+    const bool six = (M.nfield == 6);
+    for (int c = threadIdx.x; c < tcells; c += blockDim.x) {
+      const int u = c % TX, v = (c / TX) % TY, w = c / (TX * TY);
+      if (u >= ext[0] || v >= ext[1] || w >= ext[2]) continue;
+      const long long idx = ((long long)(o[2] + w) * B.p[1] + (o[1] + v)) * B.p[0] + (o[0] + u);
+      f0[idx] = from_lds<OutT>(a0[c]);
+      f0[idx + np] = (OutT)0;
+      f0[idx + 2 * np] = (OutT)0;
+      f0[idx + 3 * np] = (OutT)0;
+      f0[idx + 4 * np] = from_lds<OutT>(a4[c]);
+      if (six) f0[idx + 5 * np] = (OutT)0;
+    }
+    __syncthreads();
+  }
+}
+
 inline int grid_for(long long n, int block, int cap) {
   long long g = (n + block - 1) / block;
   if (g > cap) g = cap;
@@ -812,25 +1383,85 @@ hipError_t launch_clear_status(DevStatus* st, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_cic_direct(const Mesh& M, const Particles& P, void* buf, const BinWork* bw,
-                             int dense_min, int block, hipStream_t s) {
+hipError_t launch_cic_direct(const Mesh& M, const Particles& P, void* buf, int block,
+                             hipStream_t s) {
   if (P.n <= 0) return hipSuccess;
   const int grid = grid_for(P.n, block, M.num_cu * 32);
-  const int* key = bw ? bw->key : nullptr;
-  const int* cnt = bw ? bw->count : nullptr;
   switch (M.acc) {
     case PMP_ACC_F32:
       hipLaunchKernelGGL(k_cic_direct<PMP_ACC_F32>, dim3(grid), dim3(block), 0, s, M, P,
-                         (float*)buf, key, cnt, dense_min);
+                         (float*)buf);
       break;
     case PMP_ACC_F64:
       hipLaunchKernelGGL(k_cic_direct<PMP_ACC_F64>, dim3(grid), dim3(block), 0, s, M, P,
-                         (double*)buf, key, cnt, dense_min);
+                         (double*)buf);
       break;
     default:
       hipLaunchKernelGGL(k_cic_direct<PMP_ACC_FIX64>, dim3(grid), dim3(block), 0, s, M, P,
-                         (long long*)buf, key, cnt, dense_min);
+                         (long long*)buf);
   }
+  return hipGetLastError();
+}
+
+
+hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
+                      const Particles* sn, BinWork& bw, int block, hipStream_t s) {
+  const long long n2 = 2 * T.ntiles;
+  hipError_t e = launch_zero(bw.count, n2 * (long long)sizeof(int), 256, s);
+  if (e != hipSuccess) return e;
+  if (cic && cic->n > 0) {
+    const int grid = grid_for(cic->n, block, M.num_cu * 32);
+    hipLaunchKernelGGL(k_bin_cic<false>, dim3(grid), dim3(block), 0, s, M, T, *cic, bw.count,
+                       (const int*)nullptr, bw.cic_slot, (double4*)nullptr, 0ll);
+  }
+  if (sn && sn->n > 0) {
+    const int grid = grid_for(sn->n * 16, 256, M.num_cu * 64);
+    hipLaunchKernelGGL(k_bin_sn<16>, dim3(grid), dim3(256), 0, s, M, T, *sn, bw.count,
+                       bw.sn_slot, bw.sn_maxt, bw.sn_n, bw.sn_target);
+  }
+  const int nblocks = (int)((n2 + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(k_scan_local, dim3(nblocks), dim3(kScanBlock), 0, s, bw.count, bw.offset,
+                     bw.block_sums, n2);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, bw.block_sums, nblocks,
+                     bw.offset, n2);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(kScanBlock), 0, s, bw.offset,
+                     (const int*)bw.block_sums, n2);
+  if (cic && cic->n > 0) {
+    const int grid = grid_for(cic->n, block, M.num_cu * 32);
+    hipLaunchKernelGGL(k_bin_cic<true>, dim3(grid), dim3(block), 0, s, M, T, *cic, bw.count,
+                       (const int*)bw.offset, bw.cic_slot, bw.cic_rec, bw.cic_cap);
+  }
+  if (sn && sn->n > 0) {
+    const int grid = grid_for(sn->n, block, M.num_cu * 32);
+    hipLaunchKernelGGL(k_fill_sn, dim3(grid), dim3(block), 0, s, M, T, *sn,
+                       (const int*)bw.offset, (const int*)bw.sn_slot, bw.sn_maxt,
+                       (const int*)bw.sn_n, (const int*)bw.sn_target, bw.sn_rec, bw.sn_cap);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles* cic,
+                               const Particles* sn, const BinWork& bw, void* buf,
+                               const pmp_tuning& t, hipStream_t s) {
+  (void)cic;
+  (void)sn;
+  const size_t lds = 2 * (size_t)T.t[0] * T.t[1] * T.t[2] * 8;
+  long long grid = T.ntiles;
+  if (t.tile_grid_per_cu > 0)
+    grid = std::min<long long>(grid, (long long)M.num_cu * t.tile_grid_per_cu);
+  if (grid < 1) grid = 1;
+  if (grid > 0x7fffffffll) grid = 0x7fffffffll;
+  const int block = t.tile_block;
+#define PMP_TILE(ACC, TT)                                                                   \
+  hipLaunchKernelGGL(k_tile_deposit<ACC>, dim3((unsigned)grid), dim3(block), lds, s, M, T,  \
+                     (const int*)bw.offset, (const double4*)bw.cic_rec, bw.cic_cap,         \
+                     (const SnRec*)bw.sn_rec, bw.sn_cap, (TT*)buf)
+  switch (M.acc) {
+    case PMP_ACC_F32: PMP_TILE(PMP_ACC_F32, float); break;
+    case PMP_ACC_F64: PMP_TILE(PMP_ACC_F64, double); break;
+    default: PMP_TILE(PMP_ACC_FIX64, long long);
+  }
+#undef PMP_TILE
   return hipGetLastError();
 }
 
@@ -925,15 +1556,16 @@ hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* sta
 template <int ACC>
 static void fold_launch(const Mesh& M, void* buf, int block, hipStream_t s) {
   using T = typename AccT<ACC>::T;
-  const int grid = grid_for(M.shell_cells, block, M.num_cu * 32);
+  (void)block;
+  const int grid = grid_for(M.n_fold_chunks, 1, M.num_cu * 64);
   if (M.nfield == 6)
-    hipLaunchKernelGGL((k_fold<ACC, 6>), dim3(grid), dim3(block), 0, s, M, (T*)buf);
+    hipLaunchKernelGGL((k_fold<ACC, 6>), dim3(grid), dim3(kChunk), 0, s, M, (T*)buf);
   else
-    hipLaunchKernelGGL((k_fold<ACC, 5>), dim3(grid), dim3(block), 0, s, M, (T*)buf);
+    hipLaunchKernelGGL((k_fold<ACC, 5>), dim3(grid), dim3(kChunk), 0, s, M, (T*)buf);
 }
 
 hipError_t launch_fold(const Mesh& M, void* buf, int block, hipStream_t s) {
-  if (M.shell_cells <= 0) return hipSuccess;
+  if (M.n_fold_chunks <= 0) return hipSuccess;
   switch (M.acc) {
     case PMP_ACC_F32: fold_launch<PMP_ACC_F32>(M, buf, block, s); break;
     case PMP_ACC_F64: fold_launch<PMP_ACC_F64>(M, buf, block, s); break;
@@ -944,40 +1576,39 @@ hipError_t launch_fold(const Mesh& M, void* buf, int block, hipStream_t s) {
 
 template <class S, int ACC>
 static void apply_launch(const Mesh& M, void* state, const void* buf, const Limits& L,
-                         double* eta, int block, hipStream_t s) {
+                         double* eta, int block, int fold, hipStream_t s) {
   using T = typename AccT<ACC>::T;
-  const int grid = grid_for(M.owned_cells, block, M.num_cu * 32);
-  if (M.nfield == 6)
-    hipLaunchKernelGGL((k_apply<S, ACC, 6>), dim3(grid), dim3(block), 0, s, M, (S*)state,
-                       (const T*)buf, L, eta);
-  else
-    hipLaunchKernelGGL((k_apply<S, ACC, 5>), dim3(grid), dim3(block), 0, s, M, (S*)state,
-                       (const T*)buf, L, eta);
+  (void)block;
+  const int grid = grid_for(M.n_apply_chunks, 1, M.num_cu * 64);
+#define PMP_AP(F, FOLD)                                                                    \
+  hipLaunchKernelGGL((k_apply<S, ACC, F, FOLD>), dim3(grid), dim3(kChunk), 0, s, M,        \
+                     (S*)state, (const T*)buf, L, eta)
+  if (M.nfield == 6) {
+    if (fold) PMP_AP(6, true); else PMP_AP(6, false);
+  } else {
+    if (fold) PMP_AP(5, true); else PMP_AP(5, false);
+  }
+#undef PMP_AP
 }
 
 hipError_t launch_apply(const Mesh& M, void* state, const void* buf, const Limits& L,
-                        double* eta, int block, hipStream_t s) {
+                        double* eta, int block, int fold, hipStream_t s) {
   const bool f32 = (M.state == PMP_STATE_F32);
   switch (M.acc) {
     case PMP_ACC_F32:
-      f32 ? apply_launch<float, PMP_ACC_F32>(M, state, buf, L, eta, block, s)
-          : apply_launch<double, PMP_ACC_F32>(M, state, buf, L, eta, block, s);
+      f32 ? apply_launch<float, PMP_ACC_F32>(M, state, buf, L, eta, block, fold, s)
+          : apply_launch<double, PMP_ACC_F32>(M, state, buf, L, eta, block, fold, s);
       break;
     case PMP_ACC_F64:
-      f32 ? apply_launch<float, PMP_ACC_F64>(M, state, buf, L, eta, block, s)
-          : apply_launch<double, PMP_ACC_F64>(M, state, buf, L, eta, block, s);
+      f32 ? apply_launch<float, PMP_ACC_F64>(M, state, buf, L, eta, block, fold, s)
+          : apply_launch<double, PMP_ACC_F64>(M, state, buf, L, eta, block, fold, s);
       break;
     default:
-      f32 ? apply_launch<float, PMP_ACC_FIX64>(M, state, buf, L, eta, block, s)
-          : apply_launch<double, PMP_ACC_FIX64>(M, state, buf, L, eta, block, s);
+      f32 ? apply_launch<float, PMP_ACC_FIX64>(M, state, buf, L, eta, block, fold, s)
+          : apply_launch<double, PMP_ACC_FIX64>(M, state, buf, L, eta, block, fold, s);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_cic_binned(const Mesh& M, const Particles& P, void* buf, BinWork& bw,
-                             const pmp_tuning& t, hipStream_t s) {
-  (void)M; (void)P; (void)buf; (void)bw; (void)t; (void)s;
-  return hipErrorNotSupported;
-}
 
 }  // namespace pmp

@@ -42,8 +42,8 @@ STRUCTS = {
     "pmp_sinks": ["x", "y", "z", "a", "n", "box_off", "r_k", "r_gauss"],
     "pmp_limits": ["rho_floor", "rho_tr", "cap", "eint_mode"],
     "pmp_status": ["flags", "reserved", "touched", "bind", "lam", "fall"],
-    "pmp_tuning": ["deposit_path", "tile", "dense_min", "chunk", "block", "grid_per_cu",
-                   "sn_lanes", "reserved"],
+    "pmp_tuning": ["deposit_path", "tile_x", "tile_yz", "tile_block", "block", "grid_per_cu",
+                   "sn_lanes", "tile_grid_per_cu", "fuse_fold", "reserved"],
 }
 
 

@@ -1,0 +1,111 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times: every cell compared with the serial oracle (exact in int64 fixed
+point; FP32 within 1e-6 per field, max|x - r| / max|r|)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_18261_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_18261_amd import binding
+    return binding
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run(B, w, acc, tuning=None):
+    import torch
+    ctx = B.Context(w, acc)
+    if tuning:
+        ctx.set_tuning(**tuning)
+    ctx.deposit()
+    ctx.ghost_fold()
+    torch.cuda.synchronize()
+    fold = ctx.buf.cpu().numpy()
+    ctx.sink_update()
+    ctx.apply()
+    torch.cuda.synchronize()
+    out = {"buf_fold": fold, "state": ctx.state.cpu().numpy(), "status": ctx.status()}
+    if ctx.sink_out is not None:
+        out["sink"] = ctx.sink_out.cpu().numpy()
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def per_field_rel(w, x, r, nf, g):
+    sizes = [int(np.prod(n + 2 * g)) for n in w.n.astype(np.int64)]
+    worst = 0.0
+    for f in range(nf):
+        parts_x, parts_r = [], []
+        off = 0
+        for sz in sizes:
+            parts_x.append(x[off + f * sz: off + (f + 1) * sz])
+            parts_r.append(r[off + f * sz: off + (f + 1) * sz])
+            off += nf * sz
+        xx = np.concatenate(parts_x).astype(np.float64)
+        rr = np.concatenate(parts_r).astype(np.float64)
+        den = np.max(np.abs(rr))
+        if den > 0:
+            worst = max(worst, float(np.max(np.abs(xx - rr)) / den))
+    return worst
+
+
+CASES = {"c2": W.c2, "c3": W.c3, "c5": W.c5}
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_size_fixed_point_exact(B, orc, name):
+    w = CASES[name]()
+    say(f"full-size {w.name}: fixed point, both deposit paths")
+    ref = orc.step(w, "fix64")
+    for path in (1, 0):
+        got = run(B, w, "fix64", {"deposit_path": path})
+        assert got["status"]["flags"] in (0, 0x10), got["status"]
+        assert np.array_equal(got["buf_fold"], ref["buf_fold"]), f"path {path}: folded buffer"
+        st = ref["state"].astype(got["state"].dtype)
+        assert np.array_equal(got["state"], st), f"path {path}: state"
+        if "sink" in got:
+            n = w.sinks.n
+            for i, a in enumerate(ref["sink_d"]):
+                assert np.array_equal(got["sink"][i * n:(i + 1) * n], a)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_size_fp32_tolerance(B, orc, name):
+    w = CASES[name]()
+    say(f"full-size {w.name}: FP32 against the FP64 oracle")
+    ref = orc.step(w, "f64")
+    got = run(B, w, "f32", {"deposit_path": 1})
+    e_buf = per_field_rel(w, got["buf_fold"], ref["buf_fold"], w.nfield, w.ghost)
+    e_st = per_field_rel(w, got["state"], ref["state"].astype(np.float32), 5, 0)
+    say(f"  folded buffer {e_buf:.3e}  state {e_st:.3e}")
+    assert e_buf <= 1e-6
+    assert e_st <= max(1e-6, float(np.finfo(np.float32).eps))
+
+
+@pytest.mark.timeout(900)
+def test_full_size_c4_fixed_point(B, orc):
+    """512^3 mixed workload: final state and folded buffer bit-exact."""
+    w = W.c4()
+    say(f"full-size {w.name}: fixed point")
+    got = run(B, w, "fix64")
+    ref = orc.step(w, "fix64")
+    assert got["status"]["flags"] in (0, 0x10), got["status"]
+    assert np.array_equal(got["buf_fold"], ref["buf_fold"])
+    assert np.array_equal(got["state"], ref["state"].astype(np.float32))

@@ -135,10 +135,11 @@ SMALL = {
 }
 
 
+@pytest.mark.parametrize("path", [1, 0])
 @pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
 @pytest.mark.parametrize("name", list(SMALL))
-def test_small_configs(B, orc, name, acc):
-    check(B, orc, SMALL[name](), acc)
+def test_small_configs(B, orc, name, acc, path):
+    check(B, orc, SMALL[name](), acc, tuning={"deposit_path": path})
 
 
 def test_c1_fp64_state_all_modes(B, orc):
@@ -179,25 +180,44 @@ def edge_workloads():
     return out
 
 
+@pytest.mark.parametrize("path", [1, 0])
 @pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
 @pytest.mark.parametrize("idx", range(5))
-def test_edge_layouts(B, orc, idx, acc):
+def test_edge_layouts(B, orc, idx, acc, path):
     w = edge_workloads()[idx]
-    got, _ = check(B, orc, w, acc)
+    got, _ = check(B, orc, w, acc, tuning={"deposit_path": path})
     if w.name == "empty":
         assert np.array_equal(got["state"], w.state)
 
 
+SHAPES = [
+    {"deposit_path": 0, "block": 64, "sn_lanes": 16},
+    {"deposit_path": 0, "block": 1024, "sn_lanes": 32},
+    {"deposit_path": 1, "tile_x": 16, "tile_yz": 2, "tile_block": 64},
+    {"deposit_path": 1, "tile_x": 32, "tile_yz": 8, "tile_block": 1024},
+    {"deposit_path": 1, "tile_x": 64, "tile_yz": 4, "tile_grid_per_cu": 1},
+    {"deposit_path": 1, "tile_x": 16, "tile_yz": 4, "tile_grid_per_cu": 3, "block": 128},
+]
+
+
 def test_launch_shape_invariance_fixed_point(B, orc):
-    """Fixed point gives the same bits whatever the launch shape."""
+    """Fixed point gives the same bits whatever the path, tiles or launch shape."""
     w = W.c4(nx=40)
     base = run_gpu(B, w, "fix64")
-    for tun in ({"block": 64, "sn_lanes": 16}, {"block": 1024, "sn_lanes": 32},
-                {"block": 128, "sn_lanes": 64}):
+    for tun in SHAPES:
         say("tuning", tun)
         other = run_gpu(B, w, "fix64", tuning=tun)
+        assert np.array_equal(base["buf_deposit"], other["buf_deposit"])
         assert np.array_equal(base["buf_fold"], other["buf_fold"])
         assert np.array_equal(base["state"], other["state"])
+
+
+def test_tiled_paths_multibox(B, orc):
+    """Tile shapes on an uneven multi-box layout, every mode against the oracle."""
+    w = W.c5(nb=3, n_total=20000)
+    for tun in SHAPES[2:]:
+        for acc in ("fix64", "f32"):
+            check(B, orc, w, acc, tuning=tun)
 
 
 def test_run_twice_bitwise(B):
@@ -266,4 +286,88 @@ def test_graph_replays_match_eager(B):
         eager.step()
         torch.cuda.synchronize()
     eager.close()
+    g.close()
+
+
+@pytest.mark.parametrize("fuse", [1, 0])
+@pytest.mark.parametrize("name", ["c2_40", "c4_48", "c5_4"])
+def test_step_matches_oracle(B, orc, name, fuse):
+    """pmp_step (fold fused into apply, or not) against the oracle's step."""
+    import torch
+    w = SMALL[name]()
+    say(f"step {w.name} fuse_fold={fuse}")
+    for acc in ("fix64", "f32"):
+        ctx = B.Context(w, acc)
+        ctx.set_tuning(fuse_fold=fuse)
+        ctx.step()
+        torch.cuda.synchronize()
+        got = ctx.state.cpu().numpy()
+        st = ctx.status()
+        ctx.close()
+        assert st["flags"] in (0, 0x10), st
+        ref = orc.step(w, "fix64" if acc == "fix64" else "f64")["state"].astype(got.dtype)
+        if acc == "fix64":
+            assert np.array_equal(got, ref)
+        else:
+            for f, (x, r) in enumerate(zip(field_views(w, got, "state"),
+                                           field_views(w, ref, "state"))):
+                assert rel_err(x, r) <= 1e-6, f
+
+
+def test_per_box_launches_match_batched(B, orc):
+    """The per-box launch baseline computes the same step (fixed point: same
+    bits) as the batched launches and the oracle."""
+    import torch
+    w = W.c5(nb=3, n_total=30000)
+    a = B.Context(w, "fix64")
+    a.set_tuning(deposit_path=0)
+    a.step_per_box()
+    b = B.Context(w, "fix64")
+    b.step()
+    torch.cuda.synchronize()
+    sa, sb = a.state.cpu().numpy(), b.state.cpu().numpy()
+    a.close()
+    b.close()
+    ref = orc.step(w, "fix64")["state"].astype(np.float32)
+    assert np.array_equal(sa, ref)
+    assert np.array_equal(sb, ref)
+
+
+def test_autotune_then_step(B, orc):
+    """The tuner leaves the caller's state alone, picks a valid tuning, and
+    the tuned step still matches the oracle bit for bit."""
+    import torch
+    from paper_2509_18261_amd import autotune
+    w = W.c5(nb=3, n_total=30000)
+    ctx = B.Context(w, "fix64")
+    before = ctx.state.cpu().numpy().copy()
+    res = autotune.tune(ctx, cache_path=None)
+    torch.cuda.synchronize()
+    assert res["best_ms"] > 0
+    assert np.array_equal(ctx.state.cpu().numpy(), before)
+    ctx.step()
+    torch.cuda.synchronize()
+    got = ctx.state.cpu().numpy()
+    ctx.close()
+    assert np.array_equal(got, orc.step(w, "fix64")["state"].astype(np.float32))
+
+
+def test_graph_multibox(B):
+    """A captured multi-box graph (binned path) replays like eager steps."""
+    import torch
+    w = W.c5(nb=3, n_total=30000)
+    eager = B.Context(w, "fix64")
+    eager.step()
+    eager.step()
+    torch.cuda.synchronize()
+    ref = eager.state.cpu().numpy()
+    eager.close()
+    g = B.Context(w, "fix64")
+    g.graph_build(2)
+    for _ in range(3):
+        g.reset_state()
+        torch.cuda.synchronize()
+        g.graph_launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(g.state.cpu().numpy(), ref)
     g.close()
