@@ -36,16 +36,15 @@ def acc_bytes(acc):
     return 4 if acc == "f32" else 8
 
 
-def algorithmic_bytes(w, acc, counts):
+def algorithmic_bytes(w, acc, counts, F):
     """Bytes per launch each phase must move at minimum (no scratch, no
     re-reads): buffer writes for the zero fill, particle records plus a
     read-modify-write of every touched (cell, field) for deposits, the owned
     shell and its ghost images for the fold, and state in/out plus buffer in
-    for apply."""
+    for apply.  F = buffer channels of the timed layout."""
     import numpy as np
     ba = acc_bytes(acc)
     bs = np.dtype(w.state.dtype).itemsize
-    F = w.nfield
     n = w.n.astype(np.int64)
     g = w.ghost
     owned = int(np.prod(n, axis=1).sum())
@@ -225,6 +224,8 @@ def main():
     ap.add_argument("--set", default="", help="tuning overrides, e.g. deposit_path=0,tile_x=32")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the library's autotuner (default: tune, cached per shape)")
+    ap.add_argument("--channels", default="auto",
+                    help='buffer channels: "auto" (only those deposited into) or "all"')
     ap.add_argument("--graph-steps", type=int, default=10,
                     help="steps per captured graph in the batched comparison")
     args = ap.parse_args()
@@ -249,7 +250,9 @@ def main():
     for kv in filter(None, args.set.split(",")):
         k, v = kv.split("=")
         overrides[k.strip()] = int(v)
-    ctx = B.Context(w, args.acc)
+    ctx = B.Context(w, args.acc, channels=args.channels)
+    nchan = len(ctx.fields)
+    log(f"buffer channels {ctx.fields}")
     tuned = None
     if not args.no_autotune and not overrides:
         from paper_2509_18261_amd import autotune
@@ -269,7 +272,7 @@ def main():
     del ctx
     torch.cuda.empty_cache()
 
-    algo = algorithmic_bytes(w, args.acc, counts)
+    algo = algorithmic_bytes(w, args.acc, counts, nchan)
     per_phase = {}
     for name in PHASE_ORDER:
         if name not in phases:
@@ -308,7 +311,7 @@ def main():
                    "cic": w.cic.n if w.cic else 0, "sn": w.sn.n if w.sn else 0,
                    "sinks": w.sinks.n if w.sinks else 0, "ghost": w.ghost,
                    "state": str(np.dtype(w.state.dtype)), "acc": args.acc,
-                   "limiter": "f64", "boxes": w.nbox},
+                   "limiter": "f64", "boxes": w.nbox, "buffer_channels": nchan},
         "cells_per_s": w.owned_cells / (ms * 1e-3),
         "step_algo_bytes": int(step_bytes),
         "step_hbm_frac": step_bytes / (ms * 1e-3) / (HBM_PEAK_GBPS * 1e9),
@@ -333,7 +336,7 @@ def main():
         modes = {}
         for acc, dt in (("fix64", None), ("f64", np.float64)):
             wm = w.with_state(w.state.astype(dt)) if dt is not None else w
-            c2 = B.Context(wm, acc)
+            c2 = B.Context(wm, acc, channels=args.channels)
             if overrides:
                 c2.set_tuning(**overrides)
             mms, _ = run_steps(c2, max(5, args.steps // 2), 2, profile=False)

@@ -41,9 +41,10 @@
  *    overlap; the domain is periodic along all three axes;
  *  - state = concatenation over boxes, in box order, of [5][nz][ny][nx]
  *    arrays (rho, px, py, pz, E), x fastest; float or double;
- *  - buffer = concatenation over boxes of [F][nz+2g][ny+2g][nx+2g], F = 5
- *    (rho, px, py, pz, E) or 6 with the sink removal channel K >= 0;
- *    float, double, or int64 fixed point with value = q * 2^-40;
+ *  - buffer = concatenation over boxes of [F][nz+2g][ny+2g][nx+2g]: the F
+ *    channels present (pmp_layout.channels) in the order rho, px, py, pz, E,
+ *    K (sink removal, >= 0); float, double, or int64 fixed point with
+ *    value = q * 2^-40;
  *  - each particle kind is a set of device float64 arrays grouped by box,
  *    with a device int64 CSR array box_off[nbox+1] (particles of box b are
  *    [box_off[b], box_off[b+1])); floor(x) must lie in box b.
@@ -90,8 +91,18 @@ typedef struct {
   double dx;           /* cell edge (> 0) */
   int32_t acc;         /* pmp_acc_t: buffer accumulator type */
   int32_t state;       /* pmp_state_t: state element type */
-  int32_t with_sinks;  /* 1: buffer has the sixth (removal) field */
+  int32_t with_sinks;  /* 1: buffer has the removal channel K */
+  int32_t channels;    /* buffer channels present, PMP_CH_* bits; 0 = rho, p and E
+                          (+ K with sinks).  A channel no particle kind deposits
+                          into is identically zero and need not be stored:
+                          CIC needs RHO, supernovae RHO | E, sinks K; absent
+                          channels read as zero in the apply. */
 } pmp_layout;
+
+#define PMP_CH_RHO 0x1
+#define PMP_CH_MOM 0xe   /* px, py, pz together */
+#define PMP_CH_E 0x10
+#define PMP_CH_K 0x20
 
 /* CIC mass particles (Sec. 2.2: PM deposit using steps 1, 2 and 5). */
 typedef struct {
@@ -152,10 +163,8 @@ typedef struct {
   int32_t grid_per_cu;   /* cap on blocks per CU for grid-stride launches */
   int32_t sn_lanes;      /* lanes cooperating on one supernova: 16, 32 or 64 */
   int32_t tile_grid_per_cu; /* cap on tile workgroups per CU (0: one per tile) */
-  int32_t fuse_fold;     /* 1: pmp_step without sinks folds ghosts inside the
-                            apply kernel (same fixed gather order); 0: separate
-                            pmp_ghost_fold launch */
-  int32_t reserved;
+  int32_t reserved0;     /* must be 0 */
+  int32_t reserved1;     /* must be 0 */
 } pmp_tuning;
 
 /* Create a context on the current HIP device.  Copies the layout, checks the

@@ -19,7 +19,7 @@ def shape_key(ctx) -> str:
     arch = torch.cuda.get_device_properties(ctx.state.device).gcnArchName
     desc = {
         "arch": arch, "acc": ctx.acc, "state": str(np.dtype(w.state.dtype)),
-        "domain": list(w.domain), "nbox": w.nbox, "ghost": w.ghost, "nfield": w.nfield,
+        "domain": list(w.domain), "nbox": w.nbox, "ghost": w.ghost, "fields": list(ctx.fields),
         "box_cells": int(w.owned_cells),
         "cic": w.cic.n if w.cic else 0, "sn": w.sn.n if w.sn else 0,
         "sink": w.sinks.n if w.sinks else 0,

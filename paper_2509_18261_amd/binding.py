@@ -36,7 +36,12 @@ class PmpError(RuntimeError):
 class pmp_layout(C.Structure):
     _fields_ = [("nbox", C.c_int32), ("lo", C.c_void_p), ("n", C.c_void_p),
                 ("ghost", C.c_int32), ("domain", C.c_int32 * 3), ("dx", C.c_double),
-                ("acc", C.c_int32), ("state", C.c_int32), ("with_sinks", C.c_int32)]
+                ("acc", C.c_int32), ("state", C.c_int32), ("with_sinks", C.c_int32),
+                ("channels", C.c_int32)]
+
+
+# buffer channel bits (pmp_layout.channels): bit f is channel f of rho, px, py, pz, E, K
+PMP_CH_RHO, PMP_CH_MOM, PMP_CH_E, PMP_CH_K = 0x1, 0xE, 0x10, 0x20
 
 
 class pmp_cic(C.Structure):
@@ -75,10 +80,10 @@ class pmp_tuning(C.Structure):
     _fields_ = [("deposit_path", C.c_int32), ("tile_x", C.c_int32), ("tile_yz", C.c_int32),
                 ("tile_block", C.c_int32), ("block", C.c_int32), ("grid_per_cu", C.c_int32),
                 ("sn_lanes", C.c_int32), ("tile_grid_per_cu", C.c_int32),
-                ("fuse_fold", C.c_int32), ("reserved", C.c_int32)]
+                ("reserved0", C.c_int32), ("reserved1", C.c_int32)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if not k.startswith("reserved")}
 
 
 NPHASE = 9
@@ -153,9 +158,13 @@ class Context:
     """A pmp context plus the device tensors of one workload.
 
     ``w`` is a workload (paper_2509_18261_amd.workloads.Workload); ``acc`` is
-    "f32", "f64" or "fix64".  State type follows ``w.state.dtype``."""
+    "f32", "f64" or "fix64".  State type follows ``w.state.dtype``.
+    ``channels``: "all" (rho, p, E, and K with sinks), "auto" (only the
+    channels the workload's particle kinds deposit into) or PMP_CH_* bits.
+    ``fields`` lists the channels present, in buffer order, as indices
+    0..5 = rho, px, py, pz, E, K."""
 
-    def __init__(self, w, acc="fix64", device="cuda"):
+    def __init__(self, w, acc="fix64", device="cuda", channels="all"):
         import torch
         self.w = w
         self.acc = acc
@@ -164,9 +173,13 @@ class Context:
         self.n = np.ascontiguousarray(np.asarray(w.n, dtype=np.int32))
         st_dtype = np.dtype(w.state.dtype)
         self.state_type = PMP_STATE_F32 if st_dtype == np.float32 else PMP_STATE_F64
+        with_sinks = 1 if w.nfield == 6 else 0
+        ch = channel_bits(w, channels)
+        full = ch if ch else (0x1F | (PMP_CH_K if with_sinks else 0))
+        self.fields = [f for f in range(6) if full >> f & 1]
         self.layout = pmp_layout(w.nbox, self.lo.ctypes.data, self.n.ctypes.data, w.ghost,
                                  (C.c_int32 * 3)(*w.domain), float(w.dx), ACC[acc],
-                                 self.state_type, 1 if w.nfield == 6 else 0)
+                                 self.state_type, with_sinks, ch)
         h = C.c_void_p()
         _call("pmp_create", C.byref(h), C.byref(self.layout))
         self.h = h
@@ -306,6 +319,23 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def channel_bits(w, channels):
+    """pmp_layout.channels for a workload: "all" -> 0, "auto" -> the channels
+    its particle kinds deposit into (CIC rho; supernovae rho and E; sinks K)."""
+    if channels == "all":
+        return 0
+    if channels != "auto":
+        return int(channels)
+    ch = 0
+    if w.cic is not None and w.cic.n > 0:
+        ch |= PMP_CH_RHO
+    if w.sn is not None and w.sn.n > 0:
+        ch |= PMP_CH_RHO | PMP_CH_E
+    if w.nfield == 6:
+        ch |= PMP_CH_K
+    return ch or PMP_CH_RHO
 
 
 def stream_copy(dst, src, stream=None):

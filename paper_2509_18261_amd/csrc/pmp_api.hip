@@ -111,6 +111,8 @@ struct pmp_ctx {
   int nbox = 0, ghost = 0, domain[3] = {0, 0, 0};
   double dx = 1.0, V = 1.0;
   int acc = 0, state = 0, nfield = 5;
+  int channels = 0;                     // PMP_CH_* bits present
+  int slot[6] = {0, 1, 2, 3, 4, -1};  // buffer slot per channel, -1 absent
   std::vector<HostBox> hboxes;
   std::vector<DevBox> dboxes;
   long long state_elems = 0, buffer_elems = 0, owned_cells = 0, shell_cells = 0;
@@ -134,8 +136,8 @@ struct pmp_ctx {
   long long* d_tile_prefix = nullptr;
   int* d_tiles_axis = nullptr;
   BinWork bw{};
-  long long bw_tiles = 0, bw_ncic = 0, bw_nsn = 0, bw_sn_slots = 0;
-  int bw_blocks = 0;
+  long long bw_hist = 0, bw_blocks = 0, bw_tiles = 0, bw_nsn = 0, bw_hist2 = 0,
+            bw_slice_base = 0;
   // phase profiler: events[phase][2 * launch + {0: start, 1: stop}]
   bool prof_on = false;
   int prof_max = 0;
@@ -156,6 +158,7 @@ struct pmp_ctx {
     for (int a = 0; a < 3; ++a) M.domain[a] = domain[a];
     M.V = V;
     M.nfield = nfield;
+    for (int f = 0; f < 6; ++f) M.slot[f] = slot[f];
     M.acc = acc;
     M.state = state;
     M.buffer_elems = buffer_elems;
@@ -187,6 +190,28 @@ struct pmp_ctx {
 };
 
 namespace {
+
+void free_bin_work(pmp_ctx* c) {
+  BinWork& w = c->bw;
+  (void)hipFree(w.hist);
+  (void)hipFree(w.block_sums);
+  (void)hipFree(w.cic_tmp);
+  (void)hipFree(w.cic_tmp_tile);
+  (void)hipFree(w.cic_rec);
+  (void)hipFree(w.cic_off);
+  (void)hipFree(w.sn_tmp);
+  (void)hipFree(w.sn_tmp_tile);
+  (void)hipFree(w.sn_rec);
+  (void)hipFree(w.sn_off);
+  (void)hipFree(w.sn_n);
+  (void)hipFree(w.sn_target);
+  (void)hipFree(w.sn_rows);
+  (void)hipFree(w.slice_base);
+  (void)hipFree(w.hist2);
+  (void)hipFree(w.block_sums2);
+  w = BinWork{};
+  c->bw_hist = c->bw_blocks = c->bw_tiles = c->bw_nsn = c->bw_hist2 = c->bw_slice_base = 0;
+}
 
 void prof_free(pmp_ctx* c) {
   for (int p = 0; p < PMP_NPHASE; ++p) {
@@ -235,15 +260,7 @@ void release(pmp_ctx* c) {
   (void)hipFree(c->d_zone_seg);
   (void)hipFree(c->d_apply_chunks);
   (void)hipFree(c->d_fold_chunks);
-  (void)hipFree(c->bw.count);
-  (void)hipFree(c->bw.offset);
-  (void)hipFree(c->bw.block_sums);
-  (void)hipFree(c->bw.cic_rec);
-  (void)hipFree(c->bw.sn_rec);
-  (void)hipFree(c->bw.cic_slot);
-  (void)hipFree(c->bw.sn_slot);
-  (void)hipFree(c->bw.sn_n);
-  (void)hipFree(c->bw.sn_target);
+  free_bin_work(c);
 }
 
 // Tiles of edge (tx, tyz, tyz) over every padded box.
@@ -426,57 +443,80 @@ template <class T> int regrow(T** p, long long have, long long need) {
 int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, hipStream_t s) {
   const int* t = c->tile_dims;
   const long long span = 2 * (long long)std::ceil(std::max(r_max, 0.0)) + 3;
-  const int maxt = (int)(tiles_for(span, t[0]) * tiles_for(span, t[1]) * tiles_for(span, t[2]));
-  const long long n2 = 2 * c->ntiles;
-  const int nblocks = (int)((n2 + 1023) / 1024);
+  const long long maxt = tiles_for(span, t[0]) * tiles_for(span, t[1]) * tiles_for(span, t[2]);
+  // coarse buckets: at most 1024, each 2^shift consecutive tiles
+  int shift = 0;
+  while (((c->ntiles + (1ll << shift) - 1) >> shift) > 1024) ++shift;
+  const int nb = (int)((c->ntiles + (1ll << shift) - 1) >> shift);
+  const long long nbc = (n_cic + kBinChunkCic - 1) / kBinChunkCic;
+  const long long nbs = (n_sn + kBinChunkSn - 1) / kBinChunkSn;
+  const long long hist = (long long)nb * (nbc + nbs) + 1;
+  const long long blocks = (hist + 1023) / 1024 + 1;
   const long long cic_cap = std::max<long long>(8 * n_cic, 1);
-  const long long sn_slots = std::max<long long>((long long)maxt * n_sn, 1);
-  if (cic_cap >= (1ll << 31) || sn_slots >= (1ll << 31))
+  const long long sn_cap = std::max<long long>(maxt * n_sn, 1);
+  // every bucket can add one partial slice to the full ones
+  const long long max_slices = (cic_cap + kSlice - 1) / kSlice + (sn_cap + kSlice - 1) / kSlice +
+                               2 * (long long)nb;
+  const long long hist2 = (max_slices << shift) + 1;
+  const long long blocks2 = (hist2 + 1023) / 1024 + 1;
+  if (cic_cap >= (1ll << 31) || sn_cap >= (1ll << 31) || hist >= (1ll << 31) ||
+      hist2 >= (1ll << 31))
     return fail(PMP_ERANGE, "binned deposit: too many tile entries");
-  const bool grow = n2 > c->bw_tiles || nblocks > c->bw_blocks || cic_cap > c->bw.cic_cap ||
-                    n_cic > c->bw_ncic || sn_slots > c->bw_sn_slots || n_sn > c->bw_nsn;
-  c->bw.sn_maxt = maxt;
-  if (!grow) return PMP_OK;
+  c->bw.shift = shift;
+  c->bw.nbuckets = nb;
+  const bool grow = hist > c->bw_hist || blocks > c->bw_blocks || c->ntiles + 1 > c->bw_tiles ||
+                    cic_cap > c->bw.cic_cap || sn_cap > c->bw.sn_cap || n_sn > c->bw_nsn ||
+                    hist2 > c->bw_hist2 || 2 * nb + 1 > c->bw_slice_base;
+  if (!grow) {
+    c->bw.max_slices = (c->bw_hist2 - 1) >> shift;
+    return PMP_OK;
+  }
   if (capturing(s)) return fail(PMP_EINVAL, "binned-deposit scratch must be sized before capture");
   PMP_HIP(hipStreamSynchronize(s));
+  BinWork& w = c->bw;
   int rc = PMP_OK;
-  if (!rc && n2 > c->bw_tiles) {
-    rc = regrow(&c->bw.count, 0, n2);
-    if (!rc) rc = regrow(&c->bw.offset, 0, n2 + 1);
-    if (!rc) c->bw_tiles = n2;
+  if (!rc && hist > c->bw_hist) {
+    rc = regrow(&w.hist, 0, hist);
+    if (!rc) c->bw_hist = hist;
   }
-  if (!rc && nblocks > c->bw_blocks) {
-    rc = regrow(&c->bw.block_sums, 0, (long long)nblocks + 1);
-    if (!rc) c->bw_blocks = nblocks;
+  if (!rc && blocks > c->bw_blocks) {
+    rc = regrow(&w.block_sums, 0, blocks);
+    if (!rc) c->bw_blocks = blocks;
   }
-  if (!rc && cic_cap > c->bw.cic_cap) {
-    rc = regrow(&c->bw.cic_rec, 0, cic_cap);
-    if (!rc) rc = regrow(&c->bw.cic_slot, 0, cic_cap);
-    if (!rc) c->bw.cic_cap = cic_cap;
+  if (!rc && c->ntiles + 1 > c->bw_tiles) {
+    rc = regrow(&w.cic_off, 0, c->ntiles + 1);
+    if (!rc) rc = regrow(&w.sn_off, 0, c->ntiles + 1);
+    if (!rc) c->bw_tiles = c->ntiles + 1;
   }
-  if (!rc && sn_slots > c->bw_sn_slots) {
-    rc = regrow(&c->bw.sn_rec, 0, sn_slots);
-    if (!rc) rc = regrow(&c->bw.sn_slot, 0, sn_slots);
-    if (!rc) {
-      c->bw.sn_cap = sn_slots;
-      c->bw_sn_slots = sn_slots;
-    }
+  if (!rc && cic_cap > w.cic_cap) {
+    rc = regrow(&w.cic_tmp, 0, cic_cap);
+    if (!rc) rc = regrow(&w.cic_tmp_tile, 0, cic_cap);
+    if (!rc) rc = regrow(&w.cic_rec, 0, cic_cap);
+    if (!rc) w.cic_cap = cic_cap;
+  }
+  if (!rc && sn_cap > w.sn_cap) {
+    rc = regrow(&w.sn_tmp, 0, sn_cap);
+    if (!rc) rc = regrow(&w.sn_tmp_tile, 0, sn_cap);
+    if (!rc) rc = regrow(&w.sn_rec, 0, sn_cap);
+    if (!rc) w.sn_cap = sn_cap;
+  }
+  if (!rc && hist2 > c->bw_hist2) {
+    rc = regrow(&w.hist2, 0, hist2);
+    if (!rc) rc = regrow(&w.block_sums2, 0, blocks2);
+    if (!rc) c->bw_hist2 = hist2;
+  }
+  if (!rc && 2 * nb + 1 > c->bw_slice_base) {
+    rc = regrow(&w.slice_base, 0, 2 * (long long)nb + 1);
+    if (!rc) c->bw_slice_base = 2 * nb + 1;
   }
   if (!rc && n_sn > c->bw_nsn) {
-    rc = regrow(&c->bw.sn_n, 0, n_sn);
-    if (!rc) rc = regrow(&c->bw.sn_target, 0, n_sn);
+    rc = regrow(&w.sn_n, 0, n_sn);
+    if (!rc) rc = regrow(&w.sn_target, 0, n_sn);
+    if (!rc) rc = regrow(&w.sn_rows, 0, n_sn * (long long)kRowCap);
     if (!rc) c->bw_nsn = n_sn;
   }
-  if (!rc && n_cic > c->bw_ncic) c->bw_ncic = n_cic;
-  if (rc) {
-    // a failed allocation leaves the scratch unusable: drop it all
-    (void)hipFree(c->bw.count); (void)hipFree(c->bw.offset); (void)hipFree(c->bw.block_sums);
-    (void)hipFree(c->bw.cic_rec); (void)hipFree(c->bw.cic_slot); (void)hipFree(c->bw.sn_rec);
-    (void)hipFree(c->bw.sn_slot); (void)hipFree(c->bw.sn_n); (void)hipFree(c->bw.sn_target);
-    c->bw = BinWork{};
-    c->bw_tiles = c->bw_ncic = c->bw_nsn = c->bw_sn_slots = 0;
-    c->bw_blocks = 0;
-  }
+  if (rc) free_bin_work(c);  // a failed allocation leaves no half-sized scratch behind
+  else c->bw.max_slices = (c->bw_hist2 - 1) >> shift;
   return rc;
 }
 
@@ -502,8 +542,8 @@ int check_limits(const pmp_limits* L) {
 int check_sinks(const pmp_ctx* c, const pmp_sinks* k) {
   if (!k->x || !k->y || !k->z || !k->a || !k->box_off)
     return fail(PMP_EINVAL, "sink arrays must be non-NULL");
-  if (!c->nfield || c->nfield != 6)
-    return fail(PMP_EINVAL, "sinks need a layout created with with_sinks = 1");
+  if (c->slot[5] < 0)
+    return fail(PMP_EINVAL, "sinks need a layout with the removal channel K (with_sinks = 1)");
   if (c->nbox != 1)
     return fail(PMP_EUNSUPPORTED, "sinks are supported on single-box layouts only");
   for (int a = 0; a < 3; ++a)
@@ -546,6 +586,7 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
     if (!cic->x || !cic->y || !cic->z || !cic->m || !cic->box_off)
       return fail(PMP_EINVAL, "CIC arrays must be non-NULL");
     if (c->ghost < 1) return fail(PMP_ERANGE, "CIC deposits need ghost width >= 1");
+    if (c->slot[0] < 0) return fail(PMP_EINVAL, "CIC deposits need the rho channel");
   }
   if (has_sn) {
     if (!sn->x || !sn->y || !sn->z || !sn->m || !sn->e || !sn->r || !sn->box_off)
@@ -553,6 +594,8 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
     if (!(sn->r_max >= 0.0) || std::floor(sn->r_max + 0.5) > c->ghost)
       return fail(PMP_ERANGE, "supernova reach floor(r_max + 1/2) exceeds ghost width %d",
                   c->ghost);
+    if (c->slot[0] < 0 || c->slot[4] < 0)
+      return fail(PMP_EINVAL, "supernova deposits need the rho and E channels");
   }
   if (has_sink) {
     int rc = check_sinks(c, sinks);
@@ -628,18 +671,7 @@ int do_apply(pmp_ctx* c, void* state, const void* buf, const pmp_limits* limits,
   int rc = check_limits(limits);
   if (rc) return rc;
   PhaseTimer t(c, PMP_PHASE_APPLY, s);
-  PMP_HIP(launch_apply(c->mesh(), state, buf, to_limits(limits), eta, c->tune.block, 0, s));
-  return PMP_OK;
-}
-
-// Steps 2 + 3 + 5 in one kernel (no sinks): the apply gathers the ghost images
-// of its shell cells itself.
-int do_fold_apply(pmp_ctx* c, void* state, const void* buf, const pmp_limits* limits,
-                  hipStream_t s) {
-  int rc = check_limits(limits);
-  if (rc) return rc;
-  PhaseTimer t(c, PMP_PHASE_APPLY, s);
-  PMP_HIP(launch_apply(c->mesh(), state, buf, to_limits(limits), nullptr, c->tune.block, 1, s));
+  PMP_HIP(launch_apply(c->mesh(), state, buf, to_limits(limits), eta, c->tune.block, s));
   return PMP_OK;
 }
 
@@ -653,8 +685,6 @@ int do_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn
             const pmp_sinks* sinks, const pmp_limits* limits, double* sink_out, hipStream_t s) {
   int rc = do_deposit(c, buf, state, cic, sn, sinks, limits, s);
   if (rc) return rc;
-  const bool has_sinks = sinks && sinks->n > 0;
-  if (!has_sinks && c->tune.fuse_fold) return do_fold_apply(c, state, buf, limits, s);
   rc = do_fold(c, buf, s);
   if (rc) return rc;
   if (sinks && sinks->n > 0) {
@@ -701,7 +731,30 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   c->V = (L->dx * L->dx) * L->dx;
   c->acc = L->acc;
   c->state = L->state;
-  c->nfield = L->with_sinks ? 6 : 5;
+  {
+    const int all = PMP_CH_RHO | PMP_CH_MOM | PMP_CH_E | PMP_CH_K;
+    int ch = L->channels;
+    if (ch == 0) ch = PMP_CH_RHO | PMP_CH_MOM | PMP_CH_E | (L->with_sinks ? PMP_CH_K : 0);
+    if (ch & ~all) {
+      delete c;
+      return fail(PMP_EINVAL, "channels 0x%x has unknown bits", L->channels);
+    }
+    if ((ch & PMP_CH_MOM) != 0 && (ch & PMP_CH_MOM) != PMP_CH_MOM) {
+      delete c;
+      return fail(PMP_EINVAL, "the momentum channels come together (PMP_CH_MOM)");
+    }
+    if (L->with_sinks ? !(ch & PMP_CH_K) : (ch & PMP_CH_K) != 0) {
+      delete c;
+      return fail(PMP_EINVAL, "PMP_CH_K is present exactly when with_sinks = 1");
+    }
+    c->channels = ch;
+    c->nfield = 0;
+    for (int f = 0; f < 6; ++f) c->slot[f] = (ch >> f) & 1 ? c->nfield++ : -1;
+    if (c->nfield == 0) {
+      delete c;
+      return fail(PMP_EINVAL, "layout has no buffer channel");
+    }
+  }
   c->hboxes.resize(c->nbox);
   c->dboxes.resize(c->nbox);
   std::vector<long long> owned_prefix(c->nbox + 1, 0), shell_prefix(c->nbox + 1, 0);
@@ -825,8 +878,8 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   c->tune.grid_per_cu = 32;
   c->tune.sn_lanes = 64;
   c->tune.tile_grid_per_cu = 0;
-  c->tune.fuse_fold = 0;
-  c->tune.reserved = 0;
+  c->tune.reserved0 = 0;
+  c->tune.reserved1 = 0;
   {
     int rc = build_tiles(c, c->tune.tile_x, c->tune.tile_yz);
     if (rc) {
@@ -936,7 +989,7 @@ int pmp_step_per_box(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, con
     Mesh M = all;
     M.apply_chunks = c->d_apply_chunks + c->apply_chunk_off[b];
     M.n_apply_chunks = c->apply_chunk_off[b + 1] - c->apply_chunk_off[b];
-    PMP_HIP(launch_apply(M, state, buf, L, nullptr, c->tune.block, 0, s));
+    PMP_HIP(launch_apply(M, state, buf, L, nullptr, c->tune.block, s));
   }
   return PMP_OK;
 }
@@ -1037,7 +1090,7 @@ int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
     return fail(PMP_EINVAL, "sn_lanes 16, 32 or 64");
   if (t->tile_grid_per_cu < 0 || t->tile_grid_per_cu > 64)
     return fail(PMP_EINVAL, "tile_grid_per_cu 0..64");
-  if (t->fuse_fold != 0 && t->fuse_fold != 1) return fail(PMP_EINVAL, "fuse_fold 0 or 1");
+  if (t->reserved0 != 0 || t->reserved1 != 0) return fail(PMP_EINVAL, "reserved fields must be 0");
   if (t->tile_x != c->tile_dims[0] || t->tile_yz != c->tile_dims[1]) {
     if (c->graph_exec) return fail(PMP_EINVAL, "changing tiles would invalidate the built graph");
     PMP_HIP(hipDeviceSynchronize());
@@ -1066,7 +1119,6 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
     t.tile_block = tb;
     t.sn_lanes = lanes;
     t.tile_grid_per_cu = tgrid;
-    t.fuse_fold = 0;
     cand.push_back(t);
   };
   add(0, base.tile_x, base.tile_yz, base.tile_block, 64, 0);

@@ -52,7 +52,8 @@ struct Mesh {
   int ghost;
   int domain[3];
   double V;
-  int nfield;
+  int nfield;   // buffer channels present
+  int slot[6];  // buffer slot of rho, px, py, pz, E, K, or -1 when absent
   int acc;    // pmp_acc_t
   int state;  // pmp_state_t
   long long buffer_elems;
@@ -104,24 +105,49 @@ struct SnRec {
   double x, y, z, m, e, r;
   int n;       // sphere members (-1: host cell only)
   int target;  // padded-local index of the fixed-point remainder cell, or -1
+  int p;       // particle index (row table)
+  int rows;    // 1: the particle's row table holds its member runs
 };
 
-// Scratch for the binned deposit, owned by the context.  The count pass
-// records each (particle, tile) pair's slot in its tile, so the fill pass
-// writes packed particle records without atomics.
+// Member runs of a supernova's sphere rows, stored once per particle by the
+// binning pass: entry (j - lo_y) + cy (k - lo_z) of the candidate box holds
+// (a - lo_x) | (b - lo_x) << 8, or 0x00ff for an empty row.
+constexpr int kRowCap = 256;
+
+// Scratch for the binned deposit, owned by the context.  (particle, tile)
+// pairs are bucket-sorted in two levels with LDS-only ranking: level 1 moves
+// each pair's record into its coarse bucket (tile >> shift) through per-block
+// histograms and a global scan; level 2 sorts each bucket by tile and writes
+// the per-tile offsets.
 struct BinWork {
-  int* count;         // [2 * ntiles]: entries per tile, CIC tiles then supernova tiles
-  int* offset;        // [2 * ntiles + 1]: exclusive scan of count
-  int* block_sums;    // scan scratch [nblocks + 1]
-  double4* cic_rec;   // [cic_cap] (x, y, z, m) grouped by tile
-  SnRec* sn_rec;      // [sn_cap] grouped by tile
-  int* cic_slot;      // [n_cic * 8] slot of each (particle, tile) pair
-  int* sn_slot;       // [n_sn * sn_maxt]
-  int* sn_n;          // [n_sn] members of each sphere (-1 host only, 0 skipped)
-  int* sn_target;     // [n_sn]
+  int shift;            // coarse bucket = tile >> shift
+  int nbuckets;         // ceil(ntiles / 2^shift) <= 1024
+  int nblk_cic, nblk_sn;  // level-1 blocks per kind
+  int* hist;            // [nbuckets * (nblk_cic + nblk_sn) + 1]: histograms, then scanned
+  int* block_sums;      // scan scratch
+  double4* cic_tmp;     // level-1 output, grouped by bucket
+  int* cic_tmp_tile;
+  double4* cic_rec;     // level-2 output, grouped by tile
+  int* cic_off;         // [ntiles + 1]
+  SnRec* sn_tmp;
+  int* sn_tmp_tile;
+  SnRec* sn_rec;
+  int* sn_off;          // [ntiles + 1]
+  int* sn_n;            // [n_sn] members of each sphere (-1 host only, 0 skipped)
+  int* sn_target;       // [n_sn]
+  unsigned short* sn_rows;  // [n_sn * kRowCap]
   long long cic_cap, sn_cap;
-  int sn_maxt;        // most tiles one supernova can touch
+  // level 2 works on slices of at most kSlice records of one bucket
+  int* slice_base;      // [2 * nbuckets + 1]: first slice of each (kind, bucket)
+  int* hist2;           // [2^shift * max_slices + 1]: per (bucket, tile, slice), then scanned
+  int* block_sums2;
+  long long max_slices;
 };
+
+constexpr int kSlice = 4096;
+
+constexpr int kBinChunkCic = 2048;  // CIC particles per level-1 block
+constexpr int kBinChunkSn = 64;     // supernovae per level-1 block
 
 // Kernel launchers: all enqueue on `s` and return hipError_t of the launch.
 hipError_t launch_zero(void* buf, long long bytes, int block, hipStream_t s);
@@ -146,9 +172,8 @@ hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* sta
                               double r_gauss, const Limits& L, double* dm, double* dpx,
                               double* dpy, double* dpz, hipStream_t s);
 hipError_t launch_fold(const Mesh& M, void* buf, int block, hipStream_t s);
-// fold != 0: the ghost fold is done inside the apply (buffer left unfolded).
 hipError_t launch_apply(const Mesh& M, void* state, const void* buf, const Limits& L,
-                        double* eta, int block, int fold, hipStream_t s);
+                        double* eta, int block, hipStream_t s);
 hipError_t launch_clear_status(DevStatus* st, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, long long bytes, hipStream_t s);
 

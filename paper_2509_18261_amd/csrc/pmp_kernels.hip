@@ -184,6 +184,7 @@ struct Sphere {
   int lo[3], hi[3];  // candidate range (global cells), a superset of the members
   int cy;            // candidate rows along y
   int nrows;         // candidate rows (j, k), k-major
+  float icy;         // 1 / cy
 };
 
 __device__ __forceinline__ void sphere_init(Sphere& S, double x, double y, double z, double r) {
@@ -196,10 +197,13 @@ __device__ __forceinline__ void sphere_init(Sphere& S, double x, double y, doubl
   sphere_range(z, r, S.lo[2], S.hi[2]);
   S.cy = S.hi[1] - S.lo[1] + 1;
   S.nrows = S.cy * (S.hi[2] - S.lo[2] + 1);
+  S.icy = 1.0f / (float)S.cy;
 }
 
+__device__ __forceinline__ int small_div(int t, int d, float inv);
+
 __device__ __forceinline__ void sphere_row(const Sphere& S, int t, int& j, int& k) {
-  const int kk = t / S.cy;
+  const int kk = small_div(t, S.cy, S.icy);
   k = S.lo[2] + kk;
   j = S.lo[1] + (t - kk * S.cy);
 }
@@ -212,10 +216,12 @@ __device__ __forceinline__ void row_members(const Sphere& S, int j, int k, int& 
     b = 0;
     return;
   }
+  // the run's ends are estimated in single precision and settled exactly below
   const double dy = ((double)j + 0.5) - S.y, dz = ((double)k + 0.5) - S.z;
-  const double w2 = S.r2 - (dy * dy + dz * dz);
-  const double w = w2 > 0.0 ? sqrt(w2) : 0.0;
-  int aa = (int)ceil(S.x - 0.5 - w), bb = (int)floor(S.x - 0.5 + w);
+  const float w2 = (float)(S.r2 - (dy * dy + dz * dz));
+  const float w = w2 > 0.0f ? sqrtf(w2) : 0.0f;
+  const float xc = (float)(S.x - 0.5);
+  int aa = (int)ceilf(xc - w), bb = (int)floorf(xc + w);
   aa = min(max(aa, S.lo[0]), c);
   bb = max(min(bb, S.hi[0]), c);
   while (aa > S.lo[0] && dist2(S.x, S.y, S.z, aa - 1, j, k) <= S.r2) --aa;
@@ -233,12 +239,16 @@ __device__ __forceinline__ void row_members(const Sphere& S, int j, int k, int& 
 template <int L>
 __device__ __forceinline__ void sphere_count(const Sphere& S, const DevBox& B, int g,
                                              const int h[3], int lane, int& N, int& first,
-                                             int& hostm, int& outside) {
+                                             int& hostm, int& outside,
+                                             unsigned short* rows = nullptr) {
   int cnt = 0, key = 0x7fffffff, hm = 0, out = 0;
   for (int t = lane; t < S.nrows; t += L) {
     int j, k, a, b;
     sphere_row(S, t, j, k);
     row_members(S, j, k, a, b);
+    if (rows)
+      rows[t] = (a > b) ? (unsigned short)0x00ff
+                        : (unsigned short)((a - S.lo[0]) | ((b - S.lo[0]) << 8));
     if (a > b) continue;
     cnt += b - a + 1;
     key = min(key, (t << 12) | (a - S.lo[0]));
@@ -351,7 +361,7 @@ __global__ __launch_bounds__(1024) void k_cic_direct(Mesh M, Particles P,
     int h[3];
     if (!host_cell(B, x, y, z, h)) { raise_flag(M.status, PMP_FLAG_OUTSIDE); continue; }
     if (!isfinite(m)) { raise_flag(M.status, PMP_FLAG_NAN); continue; }
-    T* base = buf + B.boff;
+    T* base = buf + B.boff + M.slot[0] * B.npad;
     const int g = M.ghost;
     auto add = [&](int i, int j, int k, auto v) {
       long long idx;
@@ -412,8 +422,8 @@ __global__ __launch_bounds__(256) void k_sn_direct(Mesh M, Particles P,
       }
     }
     using T = typename AccT<ACC>::T;
-    T* f0 = buf + B.boff;
-    T* f4 = buf + B.boff + 4 * B.npad;
+    T* f0 = buf + B.boff + M.slot[0] * B.npad;
+    T* f4 = buf + B.boff + M.slot[4] * B.npad;
     auto put = [&](int i, int j, int k) {
       long long idx;
       if (!pad_index(B, g, i, j, k, idx)) return;
@@ -530,7 +540,7 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
     const double Mreq = a * ((double)mq * kFixInv);
     if (lane == 0) { scratch[2 * s] = W; scratch[2 * s + 1] = Mreq; }
     using T = typename AccT<ACC>::T;
-    T* f5 = buf + B.boff + 5 * B.npad;
+    T* f5 = buf + B.boff + M.slot[5] * B.npad;
     long long qreq = 0;
     int first = 0x7fffffff, hostm = 0;
     bool reach_bad = false;
@@ -640,7 +650,7 @@ __global__ __launch_bounds__(64) void k_sink_update(Mesh M, Particles P,
         const double kc = (tr > kreq) ? tr : kreq;
         const long long bidx = ((long long)(kw - B.lo[2] + g) * B.p[1] + (jw - B.lo[1] + g)) *
                                    B.p[0] + (iw - B.lo[0] + g);
-        const double K = to_f64(buf[B.boff + 5 * B.npad + bidx]);
+        const double K = to_f64(buf[B.boff + M.slot[5] * B.npad + bidx]);
         const double Kl = limited_removal(K, rho, L);
         const double eta = (K > 0.0) ? Kl / K : 1.0;
         const double term = (eta * kc) * M.V;
@@ -793,14 +803,16 @@ __global__ __launch_bounds__(kChunk) void k_fold(Mesh M, typename AccT<ACC>::T* 
 // ------------------------------------------------------------------ apply
 
 // Steps 3 + 5 per owned cell, in double precision (see pmp_apply).
-template <class S, int ACC, int F, bool FOLD>
+template <class S, int ACC>
 __global__ __launch_bounds__(kChunk) void k_apply(Mesh M, S* __restrict__ state,
                                                  const typename AccT<ACC>::T* __restrict__ buf,
                                                  Limits L, double* __restrict__ eta) {
-  using T = typename AccT<ACC>::T;
   const int g = M.ghost;
   unsigned long long touched = 0, bind = 0, lamc = 0, fall = 0;
   bool bad = false;
+  // absent channels are identically zero (uniform branches)
+  const int s0 = M.slot[0], s1 = M.slot[1], s2 = M.slot[2], s3 = M.slot[3], s4 = M.slot[4],
+            s5 = M.slot[5];
   for (long long ch = blockIdx.x; ch < M.n_apply_chunks; ch += gridDim.x) {
     const int2 C = M.apply_chunks[ch];
     const int b = C.x;
@@ -821,29 +833,13 @@ __global__ __launch_bounds__(kChunk) void k_apply(Mesh M, S* __restrict__ state,
     const double py = (double)st[2 * B.ncell];
     const double pz = (double)st[3 * B.ncell];
     const double E = (double)st[4 * B.ncell];
-    T v[F];
-#pragma unroll
-    for (int f = 0; f < F; ++f) v[f] = buf[bi + f * B.npad];
-    if constexpr (FOLD) {
-      // shell cells take their ghost images first, summed exactly as the
-      // separate fold kernel sums them
-      if (i < g || j < g || k < g || i >= B.n[0] - g || j >= B.n[1] - g || k >= B.n[2] - g) {
-        SumT<ACC> acc[F];
-#pragma unroll
-        for (int f = 0; f < F; ++f) acc[f] = (SumT<ACC>)v[f];
-        if (fold_gather<ACC, F>(M, b, i, j, k, buf, acc)) {
-#pragma unroll
-          for (int f = 0; f < F; ++f) v[f] = (T)acc[f];
-        }
-      }
-    }
-    const double Dr = to_f64(v[0]);
-    const double qx = to_f64(v[1]);
-    const double qy = to_f64(v[2]);
-    const double qz = to_f64(v[3]);
-    const double DE = to_f64(v[4]);
-    double K = 0.0;
-    if constexpr (F == 6) K = to_f64(v[5]);
+    const long long np = B.npad;
+    const double Dr = s0 >= 0 ? to_f64(buf[bi + s0 * np]) : 0.0;
+    const double qx = s1 >= 0 ? to_f64(buf[bi + s1 * np]) : 0.0;
+    const double qy = s2 >= 0 ? to_f64(buf[bi + s2 * np]) : 0.0;
+    const double qz = s3 >= 0 ? to_f64(buf[bi + s3 * np]) : 0.0;
+    const double DE = s4 >= 0 ? to_f64(buf[bi + s4 * np]) : 0.0;
+    const double K = s5 >= 0 ? to_f64(buf[bi + s5 * np]) : 0.0;
     const double Kl = limited_removal(K, rho, L);
     if (K > 0.0) {
       ++touched;
@@ -957,161 +953,6 @@ __device__ __forceinline__ long long tile_id(const TileGrid& T, int b, int tx, i
   return T.tile_prefix[b] + ((long long)tz * ta[1] + ty) * ta[0] + tx;
 }
 
-// Count pass (FILL = false): every CIC particle takes a slot in each tile its
-// stencil touches and records it; fill pass (FILL = true): the particle's
-// record is written to each of those slots.  At most 8 tiles per particle.
-template <bool FILL>
-__global__ __launch_bounds__(1024) void k_bin_cic(Mesh M, TileGrid T, Particles P,
-                                                  int* __restrict__ count,
-                                                  const int* __restrict__ offset,
-                                                  int* __restrict__ slot,
-                                                  double4* __restrict__ rec, long long cap) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  const int g = M.ghost;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += stride) {
-    const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
-    const DevBox B = M.boxes[b];
-    const double x = P.x[p], y = P.y[p], z = P.z[p], m = P.a[p];
-    int h[3];
-    if (!host_cell(B, x, y, z, h)) {
-      if (!FILL) raise_flag(M.status, PMP_FLAG_OUTSIDE);
-      continue;
-    }
-    if (!isfinite(m)) {
-      if (!FILL) raise_flag(M.status, PMP_FLAG_NAN);
-      continue;
-    }
-    int lo[3], hi[3], tlo[3], thi[3];
-    cic_box(B, g, x, y, z, lo, hi);
-    if (!tile_range(B, T, lo, hi, tlo, thi)) continue;
-    int q = 0;
-    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
-      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
-        for (int tx = tlo[0]; tx <= thi[0]; ++tx, ++q) {
-          const long long t = tile_id(T, b, tx, ty, tz);
-          if (!FILL) {
-            slot[8 * p + q] = atomicAdd(count + t, 1);
-          } else {
-            const long long pos = (long long)offset[t] + slot[8 * p + q];
-            if (pos < cap) rec[pos] = make_double4(x, y, z, m);
-            else raise_flag(M.status, PMP_FLAG_CAPACITY);
-          }
-        }
-  }
-}
-
-// Supernova count pass: a group of L lanes per particle counts the sphere's
-// members N (sn_n = N; -1 when no centre lies within r and the host cell takes
-// the deposit; 0 when the particle is skipped), finds the fixed-point
-// remainder cell (host if a member, else the first member in (k, j, i) order),
-// and takes a slot in every tile its sphere touches.
-template <int L>
-__global__ __launch_bounds__(256) void k_bin_sn(Mesh M, TileGrid T, Particles P,
-                                                int* __restrict__ count, int* __restrict__ slot,
-                                                int maxt, int* __restrict__ sn_n,
-                                                int* __restrict__ sn_target) {
-  const int lane = threadIdx.x % L;
-  const long long ngroups = ((long long)gridDim.x * blockDim.x) / L;
-  const int g = M.ghost;
-  for (long long p = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / L; p < P.n;
-       p += ngroups) {
-    const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
-    const DevBox B = M.boxes[b];
-    const double x = P.x[p], y = P.y[p], z = P.z[p];
-    const double m = P.b[p], e = P.c[p], r = P.r[p];
-    int h[3];
-    if (!host_cell(B, x, y, z, h)) {
-      if (lane == 0) { raise_flag(M.status, PMP_FLAG_OUTSIDE); sn_n[p] = 0; }
-      continue;
-    }
-    if (!isfinite(m) || !isfinite(e) || !isfinite(r) || !(r >= 0.0)) {
-      if (lane == 0) { raise_flag(M.status, PMP_FLAG_NAN); sn_n[p] = 0; }
-      continue;
-    }
-    if (floor(r + 0.5) > (double)g) {
-      if (lane == 0) { raise_flag(M.status, PMP_FLAG_REACH); sn_n[p] = 0; }
-      continue;
-    }
-    Sphere Sp;
-    sphere_init(Sp, x, y, z, r);
-    int N, first, hostm, outside;
-    sphere_count<L>(Sp, B, g, h, lane, N, first, hostm, outside);
-    const bool only_host = (N == 0);
-    int slo[3], shi[3], tlo[3], thi[3];
-    if (only_host) {
-      for (int a = 0; a < 3; ++a) slo[a] = shi[a] = h[a] - B.lo[a] + g;
-    } else {
-      sphere_box(B, g, x, y, z, r, slo, shi);
-    }
-    if (lane == 0) {
-      if (outside) raise_flag(M.status, PMP_FLAG_REACH);
-      int ti = h[0], tj = h[1], tk = h[2];
-      if (!only_host && !hostm) sphere_key_cell(Sp, first, ti, tj, tk);
-      long long idx;
-      sn_target[p] = pad_index(B, g, ti, tj, tk, idx) ? (int)idx : -1;
-      sn_n[p] = only_host ? -1 : N;
-    }
-    if (!tile_range(B, T, slo, shi, tlo, thi)) continue;
-    const int nx = thi[0] - tlo[0] + 1, ny = thi[1] - tlo[1] + 1;
-    const int nt = nx * ny * (thi[2] - tlo[2] + 1);
-    if (nt > maxt) {  // cannot happen for reach <= ghost; guarded all the same
-      if (lane == 0) raise_flag(M.status, PMP_FLAG_CAPACITY);
-      continue;
-    }
-    for (int t = lane; t < nt; t += L) {
-      const int tz = tlo[2] + t / (nx * ny), rem = t % (nx * ny);
-      const long long id = T.ntiles + tile_id(T, b, tlo[0] + rem % nx, tlo[1] + rem / nx, tz);
-      slot[(long long)maxt * p + t] = atomicAdd(count + id, 1);
-    }
-  }
-}
-
-// Supernova fill pass: one thread per particle writes its record to every
-// slot it took.
-__global__ __launch_bounds__(1024) void k_fill_sn(Mesh M, TileGrid T, Particles P,
-                                                  const int* __restrict__ offset,
-                                                  const int* __restrict__ slot, int maxt,
-                                                  const int* __restrict__ sn_n,
-                                                  const int* __restrict__ sn_target,
-                                                  SnRec* __restrict__ rec, long long cap) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  const int g = M.ghost;
-  const long long base = offset[T.ntiles];
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += stride) {
-    const int N = sn_n[p];
-    if (N == 0) continue;
-    const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
-    const DevBox B = M.boxes[b];
-    SnRec R;
-    R.x = P.x[p];
-    R.y = P.y[p];
-    R.z = P.z[p];
-    R.m = P.b[p];
-    R.e = P.c[p];
-    R.r = P.r[p];
-    R.n = N;
-    R.target = sn_target[p];
-    int slo[3], shi[3], tlo[3], thi[3];
-    if (N < 0) {
-      const double q[3] = {R.x, R.y, R.z};
-      for (int a = 0; a < 3; ++a) slo[a] = shi[a] = (int)floor(q[a]) - B.lo[a] + g;
-    } else {
-      sphere_box(B, g, R.x, R.y, R.z, R.r, slo, shi);
-    }
-    if (!tile_range(B, T, slo, shi, tlo, thi)) continue;
-    const int nx = thi[0] - tlo[0] + 1, ny = thi[1] - tlo[1] + 1;
-    const int nt = nx * ny * (thi[2] - tlo[2] + 1);
-    if (nt > maxt) continue;
-    for (int t = 0; t < nt; ++t) {
-      const int tz = tlo[2] + t / (nx * ny), rem = t % (nx * ny);
-      const long long id = T.ntiles + tile_id(T, b, tlo[0] + rem % nx, tlo[1] + rem / nx, tz);
-      const long long pos = (long long)offset[id] - base + slot[(long long)maxt * p + t];
-      if (pos < cap) rec[pos] = R;
-      else raise_flag(M.status, PMP_FLAG_CAPACITY);
-    }
-  }
-}
-
 // Exclusive scan of count[0, n) into offset[0, n] (offset[n] = total) in
 // three launches; count is cleared on the way (it becomes the fill cursor).
 constexpr int kScanBlock = 1024;
@@ -1181,6 +1022,328 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(int* __restrict__ offse
   if (i < n) offset[i] += block_sums[blockIdx.x];
 }
 
+// Level 1 of the bucket sort, CIC.  Block k handles particles
+// [k * kBinChunkCic, (k + 1) * kBinChunkCic).  Histogram pass (SCATTER =
+// false): LDS counts of (particle, tile) pairs per coarse bucket, written to
+// hist[bucket * nblk + k].  Scatter pass: hist holds the scanned positions;
+// LDS cursors hand out slots and each pair's record (x, y, z, m) and tile are
+// written there, so a block writes runs of consecutive slots per bucket.
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void k_l1_cic(Mesh M, TileGrid T, Particles P, int shift,
+                                               int nb, int* __restrict__ hist, int nblk,
+                                               double4* __restrict__ tmp,
+                                               int* __restrict__ tmp_tile, long long cap) {
+  extern __shared__ int h[];
+  const int g = M.ghost;
+  // hist is this kind's segment of the scanned histograms: positions are
+  // taken relative to its first entry
+  for (int c = threadIdx.x; c < nb; c += blockDim.x)
+    h[c] = SCATTER ? hist[(long long)c * nblk + blockIdx.x] - hist[0] : 0;
+  __syncthreads();
+  const long long p0 = (long long)blockIdx.x * kBinChunkCic;
+  const long long p1 = min(p0 + kBinChunkCic, P.n);
+  bool outside = false, nan = false, full = false;
+  for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
+    const DevBox B = M.boxes[b];
+    const double x = P.x[p], y = P.y[p], z = P.z[p], m = P.a[p];
+    int hc[3];
+    if (!host_cell(B, x, y, z, hc)) { outside = true; continue; }
+    if (!isfinite(m)) { nan = true; continue; }
+    int lo[3], hi[3], tlo[3], thi[3];
+    cic_box(B, g, x, y, z, lo, hi);
+    if (!tile_range(B, T, lo, hi, tlo, thi)) continue;
+    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
+      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
+        for (int tx = tlo[0]; tx <= thi[0]; ++tx) {
+          const int t = (int)tile_id(T, b, tx, ty, tz);
+          const int pos = atomicAdd(h + (t >> shift), 1);
+          if (SCATTER) {
+            if (pos < cap) {
+              tmp[pos] = make_double4(x, y, z, m);
+              tmp_tile[pos] = t;
+            } else {
+              full = true;
+            }
+          }
+        }
+  }
+  if (!SCATTER) {
+    if (outside) raise_flag(M.status, PMP_FLAG_OUTSIDE);
+    if (nan) raise_flag(M.status, PMP_FLAG_NAN);
+    __syncthreads();
+    for (int c = threadIdx.x; c < nb; c += blockDim.x)
+      hist[(long long)c * nblk + blockIdx.x] = h[c];
+  } else if (full) {
+    raise_flag(M.status, PMP_FLAG_CAPACITY);
+  }
+}
+
+// Level 1, supernovae.  Histogram pass: a group of 16 lanes per particle
+// counts the sphere's members N (sn_n = N; -1 when no centre lies within r
+// and the host cell takes the deposit; 0 when the particle is skipped) and
+// finds the fixed-point remainder cell (host if a member, else the first
+// member in (k, j, i) order), then counts the particle into the buckets of
+// every tile its sphere touches.  Scatter pass: one thread per particle.
+__device__ __forceinline__ bool sn_tiles(const Mesh& M, const TileGrid& T, const DevBox& B,
+                                         double x, double y, double z, double r, int N,
+                                         int tlo[3], int thi[3]) {
+  const int g = M.ghost;
+  int slo[3], shi[3];
+  if (N < 0) {
+    const double q[3] = {x, y, z};
+    for (int a = 0; a < 3; ++a) slo[a] = shi[a] = (int)floor(q[a]) - B.lo[a] + g;
+  } else {
+    sphere_box(B, g, x, y, z, r, slo, shi);
+  }
+  return tile_range(B, T, slo, shi, tlo, thi);
+}
+
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void k_l1_sn(Mesh M, TileGrid T, Particles P, int shift,
+                                              int nb, int* __restrict__ hist, int nblk,
+                                              int* __restrict__ sn_n, int* __restrict__ sn_target,
+                                              unsigned short* __restrict__ sn_rows,
+                                              SnRec* __restrict__ tmp,
+                                              int* __restrict__ tmp_tile, long long cap) {
+  constexpr int L = 16;
+  extern __shared__ int h[];
+  const int g = M.ghost;
+  for (int c = threadIdx.x; c < nb; c += blockDim.x)
+    h[c] = SCATTER ? hist[(long long)c * nblk + blockIdx.x] - hist[0] : 0;
+  __syncthreads();
+  const long long p0 = (long long)blockIdx.x * kBinChunkSn;
+  const long long p1 = min(p0 + kBinChunkSn, P.n);
+  if (!SCATTER) {
+    const int lane = threadIdx.x % L;
+    for (long long p = p0 + threadIdx.x / L; p < p1; p += blockDim.x / L) {
+      const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
+      const DevBox B = M.boxes[b];
+      const double x = P.x[p], y = P.y[p], z = P.z[p];
+      const double m = P.b[p], e = P.c[p], r = P.r[p];
+      int hc[3];
+      if (!host_cell(B, x, y, z, hc)) {
+        if (lane == 0) { raise_flag(M.status, PMP_FLAG_OUTSIDE); sn_n[p] = 0; }
+        continue;
+      }
+      if (!isfinite(m) || !isfinite(e) || !isfinite(r) || !(r >= 0.0)) {
+        if (lane == 0) { raise_flag(M.status, PMP_FLAG_NAN); sn_n[p] = 0; }
+        continue;
+      }
+      if (floor(r + 0.5) > (double)g) {
+        if (lane == 0) { raise_flag(M.status, PMP_FLAG_REACH); sn_n[p] = 0; }
+        continue;
+      }
+      Sphere Sp;
+      sphere_init(Sp, x, y, z, r);
+      const bool table = Sp.nrows <= kRowCap && Sp.hi[0] - Sp.lo[0] < 255;
+      int N, first, hostm, outside;
+      sphere_count<L>(Sp, B, g, hc, lane, N, first, hostm, outside,
+                      table ? sn_rows + (long long)kRowCap * p : nullptr);
+      if (N == 0) N = -1;
+      if (lane == 0) {
+        if (outside) raise_flag(M.status, PMP_FLAG_REACH);
+        int ti = hc[0], tj = hc[1], tk = hc[2];
+        if (N > 0 && !hostm) sphere_key_cell(Sp, first, ti, tj, tk);
+        long long idx;
+        sn_target[p] = pad_index(B, g, ti, tj, tk, idx) ? (int)idx : -1;
+        sn_n[p] = N;
+      }
+      int tlo[3], thi[3];
+      if (!sn_tiles(M, T, B, x, y, z, r, N, tlo, thi)) continue;
+      const int nx = thi[0] - tlo[0] + 1, ny = thi[1] - tlo[1] + 1;
+      const int nt = nx * ny * (thi[2] - tlo[2] + 1);
+      for (int t = lane; t < nt; t += L) {
+        const int tz = tlo[2] + t / (nx * ny), rem = t % (nx * ny);
+        const int id = (int)tile_id(T, b, tlo[0] + rem % nx, tlo[1] + rem / nx, tz);
+        atomicAdd(h + (id >> shift), 1);
+      }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < nb; c += blockDim.x)
+      hist[(long long)c * nblk + blockIdx.x] = h[c];
+  } else {
+    bool full = false;
+    for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+      const int N = sn_n[p];
+      if (N == 0) continue;
+      const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
+      const DevBox B = M.boxes[b];
+      SnRec R;
+      R.x = P.x[p];
+      R.y = P.y[p];
+      R.z = P.z[p];
+      R.m = P.b[p];
+      R.e = P.c[p];
+      R.r = P.r[p];
+      R.n = N;
+      R.target = sn_target[p];
+      R.p = (int)p;
+      {
+        int lo0, hi0, lo1, hi1, lo2, hi2;
+        sphere_range(R.x, R.r, lo0, hi0);
+        sphere_range(R.y, R.r, lo1, hi1);
+        sphere_range(R.z, R.r, lo2, hi2);
+        R.rows = ((hi1 - lo1 + 1) * (hi2 - lo2 + 1) <= kRowCap && hi0 - lo0 < 255) ? 1 : 0;
+      }
+      int tlo[3], thi[3];
+      if (!sn_tiles(M, T, B, R.x, R.y, R.z, R.r, N, tlo, thi)) continue;
+      for (int tz = tlo[2]; tz <= thi[2]; ++tz)
+        for (int ty = tlo[1]; ty <= thi[1]; ++ty)
+          for (int tx = tlo[0]; tx <= thi[0]; ++tx) {
+            const int id = (int)tile_id(T, b, tx, ty, tz);
+            const int pos = atomicAdd(h + (id >> shift), 1);
+            if (pos < cap) {
+              tmp[pos] = R;
+              tmp_tile[pos] = id;
+            } else {
+              full = true;
+            }
+          }
+    }
+    if (full) raise_flag(M.status, PMP_FLAG_CAPACITY);
+  }
+}
+
+// Level 2: one workgroup per coarse bucket sorts the bucket's records by
+// tile (LDS histogram, scan, cursors), writes the final records grouped by
+// tile and the tile offsets off[tile] (off[ntiles] = total).
+// Level 2 works on slices of at most kSlice records of one coarse bucket,
+// for both kinds at once (buckets cc = kind * nb + c).  hist1 holds the
+// scanned level-1 histograms: kind 0 (CIC, nblk0 blocks) then kind 1
+// (supernovae, nblk1 blocks), then the grand total.
+struct L2Geom {
+  const int* hist1;
+  int nb, nblk0, nblk1, shift;
+  long long ntiles;
+};
+
+__device__ __forceinline__ void bucket_range(const L2Geom& G, int cc, long long& start,
+                                             long long& end) {
+  const int kind = cc >= G.nb;
+  const int c = cc - kind * G.nb;
+  const int* H = kind ? G.hist1 + (long long)G.nb * G.nblk0 : G.hist1;
+  const int nblk = kind ? G.nblk1 : G.nblk0;
+  const long long base = H[0];
+  start = (long long)H[(long long)c * nblk] - base;
+  end = (long long)H[(long long)(c + 1) * nblk] - base;
+}
+
+// One block: slices per bucket, their exclusive prefix (slice_base), and the
+// tile offsets of empty buckets and the kinds' totals.
+__global__ __launch_bounds__(1024) void k_l2_plan(L2Geom G, int* __restrict__ slice_base,
+                                                  int* __restrict__ off0,
+                                                  int* __restrict__ off1) {
+  __shared__ int sh[kWave];
+  __shared__ int carry;
+  const int n = 2 * G.nb;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base_c = 0; base_c < n; base_c += blockDim.x) {
+    const int cc = base_c + threadIdx.x;
+    int ns = 0;
+    if (cc < n) {
+      long long start, end;
+      bucket_range(G, cc, start, end);
+      ns = (int)((end - start + kSlice - 1) / kSlice);
+      const int kind = cc >= G.nb, c = cc - kind * G.nb;
+      int* off = kind ? off1 : off0;
+      if (ns == 0) {
+        const long long t0 = (long long)c << G.shift;
+        const int nf = (int)min((long long)1 << G.shift, G.ntiles - t0);
+        for (int f = 0; f < nf; ++f) off[t0 + f] = (int)start;
+      }
+      if (c == G.nb - 1) off[G.ntiles] = (int)end;
+    }
+    const int inc = block_inclusive_scan(ns, sh);
+    const int cv = carry;
+    if (cc < n) slice_base[cc] = cv + inc - ns;
+    __syncthreads();
+    if (threadIdx.x == blockDim.x - 1) carry = cv + inc;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) slice_base[n] = carry;
+}
+
+__device__ __forceinline__ int find_slice(const int* slice_base, int n, int q) {
+  int lo = 0, hi = n;  // largest cc with slice_base[cc] <= q
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (slice_base[mid] <= q) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Per slice: LDS histogram of the slice's records over its bucket's tiles,
+// written to hist2[2^shift * slice_base[cc] + f * ns + q] (bucket, tile,
+// slice order), so that one exclusive scan of hist2 gives final positions.
+__global__ __launch_bounds__(256) void k_l2_hist(L2Geom G, const int* __restrict__ slice_base,
+                                                const int* __restrict__ tile0,
+                                                const int* __restrict__ tile1, long long cap0,
+                                                long long cap1, int* __restrict__ hist2) {
+  extern __shared__ int h[];
+  const int nf_max = 1 << G.shift;
+  const int total = slice_base[2 * G.nb];
+  for (int qg = blockIdx.x; qg < total; qg += gridDim.x) {
+    const int cc = find_slice(slice_base, 2 * G.nb, qg);
+    const int q = qg - slice_base[cc], ns = slice_base[cc + 1] - slice_base[cc];
+    const int kind = cc >= G.nb, c = cc - kind * G.nb;
+    long long start, end;
+    bucket_range(G, cc, start, end);
+    // records past the capacity were never written (flagged by level 1)
+    const long long e0 = start + (long long)q * kSlice;
+    const long long e1 = min(min(e0 + kSlice, end), kind ? cap1 : cap0);
+    const int* tt = kind ? tile1 : tile0;
+    const int t0 = c << G.shift;
+    for (int f = threadIdx.x; f < nf_max; f += blockDim.x) h[f] = 0;
+    __syncthreads();
+    for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(h + (tt[e] - t0), 1);
+    __syncthreads();
+    const long long o = (long long)nf_max * slice_base[cc];
+    for (int f = threadIdx.x; f < nf_max; f += blockDim.x) hist2[o + (long long)f * ns + q] = h[f];
+    __syncthreads();
+  }
+}
+
+// Per slice of one kind: LDS cursors from the scanned hist2 place every
+// record at its final position, grouped by tile; slice 0 of a bucket writes
+// the offsets of the bucket's tiles.
+template <class Rec>
+__global__ __launch_bounds__(256) void k_l2_scatter(L2Geom G, int kind,
+                                                   const int* __restrict__ slice_base,
+                                                   const int* __restrict__ hist2,
+                                                   const Rec* __restrict__ tmp,
+                                                   const int* __restrict__ tmp_tile,
+                                                   Rec* __restrict__ rec, int* __restrict__ off,
+                                                   long long cap) {
+  extern __shared__ int h[];
+  const int nf_max = 1 << G.shift;
+  const int q_begin = slice_base[kind * G.nb], q_end = slice_base[(kind + 1) * G.nb];
+  const long long kbase = hist2[(long long)nf_max * q_begin];  // first position of this kind
+  for (int qg = q_begin + blockIdx.x; qg < q_end; qg += gridDim.x) {
+    const int cc = find_slice(slice_base, 2 * G.nb, qg);
+    const int q = qg - slice_base[cc], ns = slice_base[cc + 1] - slice_base[cc];
+    const int c = cc - kind * G.nb;
+    long long start, end;
+    bucket_range(G, cc, start, end);
+    const long long e0 = start + (long long)q * kSlice, e1 = min(min(e0 + kSlice, end), cap);
+    const int t0 = c << G.shift;
+    const int nf = (int)min((long long)nf_max, G.ntiles - t0);
+    const long long o = (long long)nf_max * slice_base[cc];
+    for (int f = threadIdx.x; f < nf_max; f += blockDim.x) {
+      const int v = (int)(hist2[o + (long long)f * ns + q] - kbase);
+      h[f] = v;
+      if (q == 0 && f < nf) off[t0 + f] = v;
+    }
+    __syncthreads();
+    for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      const int pos = atomicAdd(h + (tmp_tile[e] - t0), 1);
+      if (pos < cap) rec[pos] = tmp[e];
+    }
+    __syncthreads();
+  }
+}
+
 template <bool FIXED> struct LdsT;
 template <> struct LdsT<true> { using T = unsigned long long; };
 template <> struct LdsT<false> { using T = double; };
@@ -1203,11 +1366,13 @@ template <class T> __device__ __forceinline__ T from_lds(double v) { return (T)v
 // as in the direct kernels.
 template <int ACC>
 __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
-                                                      const int* __restrict__ offset,
+                                                      const int* __restrict__ coff,
                                                       const double4* __restrict__ crec,
                                                       long long ccap,
+                                                      const int* __restrict__ soff,
                                                       const SnRec* __restrict__ srec,
                                                       long long scap,
+                                                      const unsigned short* __restrict__ rows,
                                                       typename AccT<ACC>::T* __restrict__ buf) {
   using OutT = typename AccT<ACC>::T;
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
@@ -1217,7 +1382,6 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
   const int tcells = TX * TY * TZ;
   LT* a0 = reinterpret_cast<LT*>(smem);
   LT* a4 = a0 + tcells;
-  const int nwave = blockDim.x / kWave, wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int g = M.ghost;
   for (long long tile = blockIdx.x; tile < T.ntiles; tile += gridDim.x) {
     const int b = (M.nbox == 1) ? 0 : find_box(T.tile_prefix, M.nbox, tile);
@@ -1245,7 +1409,11 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
     };
     bool ovf = false;
     // entries past the capacity were never written (flagged in the fill)
-    const long long e0 = offset[tile], e1 = min((long long)offset[tile + 1], ccap);
+    long long e0 = 0, e1 = 0;
+    if (coff) {
+      e0 = coff[tile];
+      e1 = min((long long)coff[tile + 1], ccap);
+    }
     for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       const double4 R = crec[e];
       const double x = R.x, y = R.y, z = R.z, m = R.w;
@@ -1256,68 +1424,72 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
       };
       if (!cic_one<FIXED>(x, y, z, m, M.V, h, add)) ovf = true;
     }
-    // supernovae: G lanes per entry (one lane per row of the tile), 64/G
-    // entries per wavefront at a time
-    const long long sbase = offset[T.ntiles];
-    const long long s0 = offset[T.ntiles + tile] - sbase;
-    const long long s1 = min((long long)offset[T.ntiles + tile + 1] - sbase, scap);
-    const int G = TY * TZ < kWave ? TY * TZ : kWave;
-    const int per_wave = kWave / G;
-    for (long long e = s0 + wave * per_wave + lane / G; e < s1; e += nwave * per_wave) {
-      const int row = lane % G;
-      const SnRec& R = srec[e];
-      const double x = R.x, y = R.y, z = R.z, m = R.m, en = R.e, r = R.r;
+    // supernovae: one lane per entry, walking the tile's rows that meet the
+    // sphere's candidate box (row runs from the particle's table when there
+    // is one), so that a wavefront has 64 entries' loads in flight at once
+    long long s0 = 0, s1 = 0;
+    if (soff) {
+      s0 = soff[tile];
+      s1 = min((long long)soff[tile + 1], scap);
+    }
+    const int xlo = o[0] - g + B.lo[0], xhi = xlo + ext[0] - 1;  // tile range, global
+    const int ylo = o[1] - g + B.lo[1], yhi = ylo + ext[1] - 1;
+    const int zlo = o[2] - g + B.lo[2], zhi = zlo + ext[2] - 1;
+    for (long long e = s0 + threadIdx.x; e < s1; e += blockDim.x) {
+      const SnRec R = srec[e];
       int N = R.n;
       const bool only_host = (N < 0);
       if (only_host) N = 1;
-      const double cr = m / ((double)N * M.V);
-      const double ce = en / ((double)N * M.V);
+      const double cr = R.m / ((double)N * M.V);
+      const double ce = R.e / ((double)N * M.V);
       long long qr = 0, qe = 0;
       if constexpr (FIXED) {
         if (!quantise(cr, qr) || !quantise(ce, qe)) { ovf = true; continue; }
       }
-      Sphere Sp;
-      if (!only_host) sphere_init(Sp, x, y, z, r);
-      // tile rows handled by this lane: (ry, rz) and, for tiles with more
-      // than 64 rows, every G-th row after it
-      for (int rr = row; rr < TY * TZ; rr += G) {
-        const int ry = rr % TY, rz = rr / TY;
-        if (ry >= ext[1] || rz >= ext[2]) continue;
-        const int j = o[1] + ry - g + B.lo[1], k = o[2] + rz - g + B.lo[2];
-        int a, bb;
-        if (only_host) {
-          const int hx = (int)floor(x);
-          if (j != (int)floor(y) || k != (int)floor(z)) continue;
-          a = bb = hx;
+      auto put = [&](int c) {
+        if constexpr (FIXED) {
+          lds_add(a0 + c, qr);
+          lds_add(a4 + c, qe);
         } else {
-          if (j < Sp.lo[1] || j > Sp.hi[1] || k < Sp.lo[2] || k > Sp.hi[2]) continue;
-          row_members(Sp, j, k, a, bb);
+          lds_add(a0 + c, cr);
+          lds_add(a4 + c, ce);
         }
-        // clip to the tile's x range (global)
-        const int xlo = o[0] - g + B.lo[0], xhi = xlo + ext[0] - 1;
-        a = max(a, xlo);
-        bb = min(bb, xhi);
-        const int cbase = (rz * TY + ry) * TX - xlo;
-        for (int i = a; i <= bb; ++i) {
-          if constexpr (FIXED) {
-            lds_add(a0 + cbase + i, qr);
-            lds_add(a4 + cbase + i, qe);
-          } else {
-            lds_add(a0 + cbase + i, cr);
-            lds_add(a4 + cbase + i, ce);
+      };
+      if (only_host) {
+        int c;
+        if (tcell((int)floor(R.x), (int)floor(R.y), (int)floor(R.z), c)) put(c);
+      } else {
+        Sphere Sp;
+        sphere_init(Sp, R.x, R.y, R.z, R.r);
+        const unsigned short* rtab = R.rows ? rows + (long long)kRowCap * R.p : nullptr;
+        const int j0 = max(ylo, Sp.lo[1]), j1 = min(yhi, Sp.hi[1]);
+        const int k0 = max(zlo, Sp.lo[2]), k1 = min(zhi, Sp.hi[2]);
+        for (int k = k0; k <= k1; ++k)
+          for (int j = j0; j <= j1; ++j) {
+            int a, bb;
+            if (rtab) {
+              const unsigned v = rtab[(j - Sp.lo[1]) + Sp.cy * (k - Sp.lo[2])];
+              a = Sp.lo[0] + (int)(v & 255u);
+              bb = Sp.lo[0] + (int)(v >> 8);
+            } else {
+              row_members(Sp, j, k, a, bb);
+            }
+            a = max(a, xlo);
+            bb = min(bb, xhi);
+            const int cbase = ((k - zlo) * TY + (j - ylo)) * TX - xlo;
+            for (int i = a; i <= bb; ++i) put(cbase + i);
           }
-        }
       }
       if constexpr (FIXED) {
         const int tgt = R.target;
-        if (row == 0 && tgt >= 0) {
+        if (tgt >= 0) {
           const int li = tgt % B.p[0], rest = tgt / B.p[0];
           const int lj = rest % B.p[1], lk = rest / B.p[1];
           const int u = li - o[0], v = lj - o[1], w = lk - o[2];
           if ((unsigned)u < (unsigned)ext[0] && (unsigned)v < (unsigned)ext[1] &&
               (unsigned)w < (unsigned)ext[2]) {
             long long Qr, Qe;
-            if (quantise(m / M.V, Qr) && quantise(en / M.V, Qe)) {
+            if (quantise(R.m / M.V, Qr) && quantise(R.e / M.V, Qe)) {
               const int c = (w * TY + v) * TX + u;
               lds_add(a0 + c, Qr - (long long)N * qr);
               lds_add(a4 + c, Qe - (long long)N * qe);
@@ -1330,19 +1502,21 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
     }
     if (ovf) raise_flag(M.status, PMP_FLAG_OVERFLOW);
     __syncthreads();
+    // every present channel of every cell is stored once: rho and E from
+    // LDS, the others (no source in this pass) as zero
     OutT* f0 = buf + B.boff;
     const long long np = B.npad;
-    const bool six = (M.nfield == 6);
+    const int sr = M.slot[0], se = M.slot[4];
     for (int c = threadIdx.x; c < tcells; c += blockDim.x) {
       const int u = c % TX, v = (c / TX) % TY, w = c / (TX * TY);
       if (u >= ext[0] || v >= ext[1] || w >= ext[2]) continue;
       const long long idx = ((long long)(o[2] + w) * B.p[1] + (o[1] + v)) * B.p[0] + (o[0] + u);
-      f0[idx] = from_lds<OutT>(a0[c]);
-      f0[idx + np] = (OutT)0;
-      f0[idx + 2 * np] = (OutT)0;
-      f0[idx + 3 * np] = (OutT)0;
-      f0[idx + 4 * np] = from_lds<OutT>(a4[c]);
-      if (six) f0[idx + 5 * np] = (OutT)0;
+      for (int f = 0; f < M.nfield; ++f) {
+        OutT val = (OutT)0;
+        if (f == sr) val = from_lds<OutT>(a0[c]);
+        else if (f == se) val = from_lds<OutT>(a4[c]);
+        f0[idx + f * np] = val;
+      }
     }
     __syncthreads();
   }
@@ -1406,45 +1580,79 @@ hipError_t launch_cic_direct(const Mesh& M, const Particles& P, void* buf, int b
 
 hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
                       const Particles* sn, BinWork& bw, int block, hipStream_t s) {
-  const long long n2 = 2 * T.ntiles;
-  hipError_t e = launch_zero(bw.count, n2 * (long long)sizeof(int), 256, s);
-  if (e != hipSuccess) return e;
-  if (cic && cic->n > 0) {
-    const int grid = grid_for(cic->n, block, M.num_cu * 32);
-    hipLaunchKernelGGL(k_bin_cic<false>, dim3(grid), dim3(block), 0, s, M, T, *cic, bw.count,
-                       (const int*)nullptr, bw.cic_slot, (double4*)nullptr, 0ll);
-  }
-  if (sn && sn->n > 0) {
-    const int grid = grid_for(sn->n * 16, 256, M.num_cu * 64);
-    hipLaunchKernelGGL(k_bin_sn<16>, dim3(grid), dim3(256), 0, s, M, T, *sn, bw.count,
-                       bw.sn_slot, bw.sn_maxt, bw.sn_n, bw.sn_target);
-  }
-  const int nblocks = (int)((n2 + kScanBlock - 1) / kScanBlock);
-  hipLaunchKernelGGL(k_scan_local, dim3(nblocks), dim3(kScanBlock), 0, s, bw.count, bw.offset,
-                     bw.block_sums, n2);
+  (void)block;
+  const int nb = bw.nbuckets, S = bw.shift;
+  const bool has_c = cic && cic->n > 0, has_s = sn && sn->n > 0;
+  const int nbc = has_c ? (int)((cic->n + kBinChunkCic - 1) / kBinChunkCic) : 0;
+  const int nbs = has_s ? (int)((sn->n + kBinChunkSn - 1) / kBinChunkSn) : 0;
+  int* hc = bw.hist;
+  int* hs = bw.hist + (long long)nb * nbc;
+  const long long n = (long long)nb * (nbc + nbs);
+  const size_t lds1 = (size_t)nb * sizeof(int);
+  if (has_c)
+    hipLaunchKernelGGL(k_l1_cic<false>, dim3(nbc), dim3(256), lds1, s, M, T, *cic, S, nb, hc,
+                       nbc, (double4*)nullptr, (int*)nullptr, 0ll);
+  if (has_s)
+    hipLaunchKernelGGL(k_l1_sn<false>, dim3(nbs), dim3(256), lds1, s, M, T, *sn, S, nb, hs, nbs,
+                       bw.sn_n, bw.sn_target, bw.sn_rows, (SnRec*)nullptr, (int*)nullptr, 0ll);
+  // exclusive scan of both kinds' histograms, in place; hist[n] = total
+  const int nblocks = (int)((n + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(k_scan_local, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist, bw.hist,
+                     bw.block_sums, n);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, bw.block_sums, nblocks,
-                     bw.offset, n2);
-  hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(kScanBlock), 0, s, bw.offset,
-                     (const int*)bw.block_sums, n2);
-  if (cic && cic->n > 0) {
-    const int grid = grid_for(cic->n, block, M.num_cu * 32);
-    hipLaunchKernelGGL(k_bin_cic<true>, dim3(grid), dim3(block), 0, s, M, T, *cic, bw.count,
-                       (const int*)bw.offset, bw.cic_slot, bw.cic_rec, bw.cic_cap);
-  }
-  if (sn && sn->n > 0) {
-    const int grid = grid_for(sn->n, block, M.num_cu * 32);
-    hipLaunchKernelGGL(k_fill_sn, dim3(grid), dim3(block), 0, s, M, T, *sn,
-                       (const int*)bw.offset, (const int*)bw.sn_slot, bw.sn_maxt,
-                       (const int*)bw.sn_n, (const int*)bw.sn_target, bw.sn_rec, bw.sn_cap);
-  }
+                     bw.hist, n);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist,
+                     (const int*)bw.block_sums, n);
+  if (has_c)
+    hipLaunchKernelGGL(k_l1_cic<true>, dim3(nbc), dim3(256), lds1, s, M, T, *cic, S, nb, hc, nbc,
+                       bw.cic_tmp, bw.cic_tmp_tile, bw.cic_cap);
+  if (has_s)
+    hipLaunchKernelGGL(k_l1_sn<true>, dim3(nbs), dim3(kBinChunkSn), lds1, s, M, T, *sn, S, nb,
+                       hs, nbs, bw.sn_n, bw.sn_target, bw.sn_rows, bw.sn_tmp, bw.sn_tmp_tile,
+                       bw.sn_cap);
+  // level 2: balanced slices of every bucket, both kinds
+  L2Geom G;
+  G.hist1 = bw.hist;
+  G.nb = nb;
+  G.nblk0 = nbc;
+  G.nblk1 = nbs;
+  G.shift = S;
+  G.ntiles = T.ntiles;
+  hipLaunchKernelGGL(k_l2_plan, dim3(1), dim3(1024), 0, s, G, bw.slice_base, bw.cic_off,
+                     bw.sn_off);
+  const long long n2 = ((long long)1 << S) * bw.max_slices;
+  hipError_t e = launch_zero(bw.hist2, n2 * (long long)sizeof(int), 256, s);
+  if (e != hipSuccess) return e;
+  const size_t lds2 = ((size_t)1 << S) * sizeof(int);
+  const int grid2 = (int)std::min<long long>(bw.max_slices, (long long)M.num_cu * 8);
+  hipLaunchKernelGGL(k_l2_hist, dim3(grid2), dim3(256), lds2, s, G, (const int*)bw.slice_base,
+                     (const int*)bw.cic_tmp_tile, (const int*)bw.sn_tmp_tile, bw.cic_cap,
+                     bw.sn_cap, bw.hist2);
+  const int nblocks2 = (int)((n2 + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(k_scan_local, dim3(nblocks2), dim3(kScanBlock), 0, s, bw.hist2, bw.hist2,
+                     bw.block_sums2, n2);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, bw.block_sums2, nblocks2,
+                     bw.hist2, n2);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblocks2), dim3(kScanBlock), 0, s, bw.hist2,
+                     (const int*)bw.block_sums2, n2);
+  if (has_c)
+    hipLaunchKernelGGL(k_l2_scatter<double4>, dim3(grid2), dim3(256), lds2, s, G, 0,
+                       (const int*)bw.slice_base, (const int*)bw.hist2,
+                       (const double4*)bw.cic_tmp, (const int*)bw.cic_tmp_tile, bw.cic_rec,
+                       bw.cic_off, bw.cic_cap);
+  if (has_s)
+    hipLaunchKernelGGL(k_l2_scatter<SnRec>, dim3(grid2), dim3(256), lds2, s, G, 1,
+                       (const int*)bw.slice_base, (const int*)bw.hist2,
+                       (const SnRec*)bw.sn_tmp, (const int*)bw.sn_tmp_tile, bw.sn_rec,
+                       bw.sn_off, bw.sn_cap);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles* cic,
                                const Particles* sn, const BinWork& bw, void* buf,
                                const pmp_tuning& t, hipStream_t s) {
-  (void)cic;
-  (void)sn;
+  const int* coff = (cic && cic->n > 0) ? bw.cic_off : nullptr;
+  const int* soff = (sn && sn->n > 0) ? bw.sn_off : nullptr;
   const size_t lds = 2 * (size_t)T.t[0] * T.t[1] * T.t[2] * 8;
   long long grid = T.ntiles;
   if (t.tile_grid_per_cu > 0)
@@ -1454,8 +1662,9 @@ hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles
   const int block = t.tile_block;
 #define PMP_TILE(ACC, TT)                                                                   \
   hipLaunchKernelGGL(k_tile_deposit<ACC>, dim3((unsigned)grid), dim3(block), lds, s, M, T,  \
-                     (const int*)bw.offset, (const double4*)bw.cic_rec, bw.cic_cap,         \
-                     (const SnRec*)bw.sn_rec, bw.sn_cap, (TT*)buf)
+                     coff, (const double4*)bw.cic_rec, bw.cic_cap, soff,                    \
+                     (const SnRec*)bw.sn_rec, bw.sn_cap, (const unsigned short*)bw.sn_rows, \
+                     (TT*)buf)
   switch (M.acc) {
     case PMP_ACC_F32: PMP_TILE(PMP_ACC_F32, float); break;
     case PMP_ACC_F64: PMP_TILE(PMP_ACC_F64, double); break;
@@ -1558,10 +1767,17 @@ static void fold_launch(const Mesh& M, void* buf, int block, hipStream_t s) {
   using T = typename AccT<ACC>::T;
   (void)block;
   const int grid = grid_for(M.n_fold_chunks, 1, M.num_cu * 64);
-  if (M.nfield == 6)
-    hipLaunchKernelGGL((k_fold<ACC, 6>), dim3(grid), dim3(kChunk), 0, s, M, (T*)buf);
-  else
-    hipLaunchKernelGGL((k_fold<ACC, 5>), dim3(grid), dim3(kChunk), 0, s, M, (T*)buf);
+#define PMP_FOLD(F) \
+  hipLaunchKernelGGL((k_fold<ACC, F>), dim3(grid), dim3(kChunk), 0, s, M, (T*)buf)
+  switch (M.nfield) {
+    case 1: PMP_FOLD(1); break;
+    case 2: PMP_FOLD(2); break;
+    case 3: PMP_FOLD(3); break;
+    case 4: PMP_FOLD(4); break;
+    case 5: PMP_FOLD(5); break;
+    default: PMP_FOLD(6);
+  }
+#undef PMP_FOLD
 }
 
 hipError_t launch_fold(const Mesh& M, void* buf, int block, hipStream_t s) {
@@ -1576,36 +1792,29 @@ hipError_t launch_fold(const Mesh& M, void* buf, int block, hipStream_t s) {
 
 template <class S, int ACC>
 static void apply_launch(const Mesh& M, void* state, const void* buf, const Limits& L,
-                         double* eta, int block, int fold, hipStream_t s) {
+                         double* eta, hipStream_t s) {
   using T = typename AccT<ACC>::T;
-  (void)block;
   const int grid = grid_for(M.n_apply_chunks, 1, M.num_cu * 64);
-#define PMP_AP(F, FOLD)                                                                    \
-  hipLaunchKernelGGL((k_apply<S, ACC, F, FOLD>), dim3(grid), dim3(kChunk), 0, s, M,        \
-                     (S*)state, (const T*)buf, L, eta)
-  if (M.nfield == 6) {
-    if (fold) PMP_AP(6, true); else PMP_AP(6, false);
-  } else {
-    if (fold) PMP_AP(5, true); else PMP_AP(5, false);
-  }
-#undef PMP_AP
+  hipLaunchKernelGGL((k_apply<S, ACC>), dim3(grid), dim3(kChunk), 0, s, M, (S*)state,
+                     (const T*)buf, L, eta);
 }
 
 hipError_t launch_apply(const Mesh& M, void* state, const void* buf, const Limits& L,
-                        double* eta, int block, int fold, hipStream_t s) {
+                        double* eta, int block, hipStream_t s) {
+  (void)block;
   const bool f32 = (M.state == PMP_STATE_F32);
   switch (M.acc) {
     case PMP_ACC_F32:
-      f32 ? apply_launch<float, PMP_ACC_F32>(M, state, buf, L, eta, block, fold, s)
-          : apply_launch<double, PMP_ACC_F32>(M, state, buf, L, eta, block, fold, s);
+      f32 ? apply_launch<float, PMP_ACC_F32>(M, state, buf, L, eta, s)
+          : apply_launch<double, PMP_ACC_F32>(M, state, buf, L, eta, s);
       break;
     case PMP_ACC_F64:
-      f32 ? apply_launch<float, PMP_ACC_F64>(M, state, buf, L, eta, block, fold, s)
-          : apply_launch<double, PMP_ACC_F64>(M, state, buf, L, eta, block, fold, s);
+      f32 ? apply_launch<float, PMP_ACC_F64>(M, state, buf, L, eta, s)
+          : apply_launch<double, PMP_ACC_F64>(M, state, buf, L, eta, s);
       break;
     default:
-      f32 ? apply_launch<float, PMP_ACC_FIX64>(M, state, buf, L, eta, block, fold, s)
-          : apply_launch<double, PMP_ACC_FIX64>(M, state, buf, L, eta, block, fold, s);
+      f32 ? apply_launch<float, PMP_ACC_FIX64>(M, state, buf, L, eta, s)
+          : apply_launch<double, PMP_ACC_FIX64>(M, state, buf, L, eta, s);
   }
   return hipGetLastError();
 }

@@ -36,14 +36,15 @@ def test_nm_exports():
 
 
 STRUCTS = {
-    "pmp_layout": ["nbox", "lo", "n", "ghost", "domain", "dx", "acc", "state", "with_sinks"],
+    "pmp_layout": ["nbox", "lo", "n", "ghost", "domain", "dx", "acc", "state", "with_sinks",
+                   "channels"],
     "pmp_cic": ["x", "y", "z", "m", "n", "box_off"],
     "pmp_sn": ["x", "y", "z", "m", "e", "r", "n", "box_off", "r_max"],
     "pmp_sinks": ["x", "y", "z", "a", "n", "box_off", "r_k", "r_gauss"],
     "pmp_limits": ["rho_floor", "rho_tr", "cap", "eint_mode"],
     "pmp_status": ["flags", "reserved", "touched", "bind", "lam", "fall"],
     "pmp_tuning": ["deposit_path", "tile_x", "tile_yz", "tile_block", "block", "grid_per_cu",
-                   "sn_lanes", "tile_grid_per_cu", "fuse_fold", "reserved"],
+                   "sn_lanes", "tile_grid_per_cu", "reserved0", "reserved1"],
 }
 
 

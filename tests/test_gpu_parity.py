@@ -12,6 +12,8 @@ import pytest
 
 from paper_2509_18261_amd import workloads as W
 
+from buffers import expand_channels
+
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 1e-6}
@@ -31,15 +33,15 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run_gpu(B, w, acc, want_eta=True, tuning=None):
+def run_gpu(B, w, acc, want_eta=True, tuning=None, channels="all"):
     import torch
-    ctx = B.Context(w, acc)
+    ctx = B.Context(w, acc, channels=channels)
     if tuning:
         ctx.set_tuning(**tuning)
     ctx.deposit()
-    dep = ctx.buf.cpu().numpy().copy()
+    dep = expand_channels(w, ctx.buf.cpu().numpy().copy(), ctx.fields)
     ctx.ghost_fold()
-    fold = ctx.buf.cpu().numpy().copy()
+    fold = expand_channels(w, ctx.buf.cpu().numpy().copy(), ctx.fields)
     ctx.sink_update()
     eta = torch.empty(ctx.owned_cells, dtype=torch.float64, device="cuda") if want_eta else None
     ctx.apply(eta)
@@ -289,16 +291,16 @@ def test_graph_replays_match_eager(B):
     g.close()
 
 
-@pytest.mark.parametrize("fuse", [1, 0])
-@pytest.mark.parametrize("name", ["c2_40", "c4_48", "c5_4"])
-def test_step_matches_oracle(B, orc, name, fuse):
-    """pmp_step (fold fused into apply, or not) against the oracle's step."""
+@pytest.mark.parametrize("channels", ["auto", "all"])
+@pytest.mark.parametrize("name", ["c2_40", "c3_40", "c4_48", "c5_4"])
+def test_step_matches_oracle(B, orc, name, channels):
+    """pmp_step (all buffer channels, or only the deposited ones) against the
+    oracle's step."""
     import torch
     w = SMALL[name]()
-    say(f"step {w.name} fuse_fold={fuse}")
+    say(f"step {w.name} channels={channels}")
     for acc in ("fix64", "f32"):
-        ctx = B.Context(w, acc)
-        ctx.set_tuning(fuse_fold=fuse)
+        ctx = B.Context(w, acc, channels=channels)
         ctx.step()
         torch.cuda.synchronize()
         got = ctx.state.cpu().numpy()
@@ -312,6 +314,34 @@ def test_step_matches_oracle(B, orc, name, fuse):
             for f, (x, r) in enumerate(zip(field_views(w, got, "state"),
                                            field_views(w, ref, "state"))):
                 assert rel_err(x, r) <= 1e-6, f
+
+
+@pytest.mark.parametrize("path", [1, 0])
+@pytest.mark.parametrize("acc", ["fix64", "f32"])
+@pytest.mark.parametrize("name", list(SMALL))
+def test_deposited_channels_only(B, orc, name, acc, path):
+    """Layouts holding only the channels the particle kinds deposit into (the
+    others are zero in the oracle's buffer and read as zero in the apply)."""
+    check(B, orc, SMALL[name](), acc, tuning={"deposit_path": path}, channels="auto")
+
+
+def test_channel_errors(B):
+    w = W.c2(nx=16)
+    # supernovae need rho and E
+    ctx = B.Context(w, "f32", channels=B.PMP_CH_RHO)
+    with pytest.raises(B.PmpError, match="EINVAL"):
+        ctx.deposit()
+    ctx.close()
+    # momentum channels come together; unknown bits are refused
+    for ch in (0x2, 0x40):
+        with pytest.raises(B.PmpError, match="EINVAL"):
+            B.Context(w, "f32", channels=ch | B.PMP_CH_RHO)
+    # K is present exactly when the layout has sinks
+    with pytest.raises(B.PmpError, match="EINVAL"):
+        B.Context(w, "f32", channels=B.PMP_CH_RHO | B.PMP_CH_K)
+    w3 = W.c3(nx=16, n_sink=4)
+    with pytest.raises(B.PmpError, match="EINVAL"):
+        B.Context(w3, "f32", channels=B.PMP_CH_RHO)
 
 
 def test_per_box_launches_match_batched(B, orc):
