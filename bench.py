@@ -121,6 +121,24 @@ def run_steps(ctx, steps, warmup, profile=True):
     return ms, phases
 
 
+def run_graph(ctx, steps, warmup):
+    """ms per step of a captured one-step HIP graph, replayed `steps` times
+    after `warmup` untimed replays."""
+    import torch
+    ctx.graph_build(1)
+    for _ in range(warmup):
+        ctx.graph_launch()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        ctx.graph_launch()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
 def stream_copy_gbps(B, nbytes=1 << 30, reps=10):
     import torch
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -261,13 +279,17 @@ def main():
         log(f"autotune: {tuned}")
     if overrides:
         ctx.set_tuning(**overrides)
-    ms, phases = run_steps(ctx, args.steps, args.warmup)
+    # headline: the step replayed from a captured HIP graph; eager launches
+    # and the per-phase profile (events between phases) in runs of their own
+    eager_ms, _ = run_steps(ctx, args.steps, args.warmup, profile=False)
+    ms = run_graph(ctx, args.steps, args.warmup)
+    _, phases = run_steps(ctx, args.steps, 2, profile=True)
     st = ctx.status()
-    log(f"step {ms:.4f} ms; status {st}")
+    log(f"step {ms:.4f} ms (graph), {eager_ms:.4f} ms (eager); status {st}")
     tun = ctx.tuning().as_dict()
     batched = None
     if w.nbox > 1:
-        batched = batched_comparison(ctx, args, ms)
+        batched = batched_comparison(ctx, args, eager_ms)
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -302,6 +324,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "eager_ms_per_step": eager_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -339,7 +362,7 @@ def main():
             c2 = B.Context(wm, acc, channels=args.channels)
             if overrides:
                 c2.set_tuning(**overrides)
-            mms, _ = run_steps(c2, max(5, args.steps // 2), 2, profile=False)
+            mms = run_graph(c2, max(5, args.steps // 2), 2)
             c2.close()
             del c2
             torch.cuda.empty_cache()

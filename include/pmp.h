@@ -163,8 +163,12 @@ typedef struct {
   int32_t grid_per_cu;   /* cap on blocks per CU for grid-stride launches */
   int32_t sn_lanes;      /* lanes cooperating on one supernova: 16, 32 or 64 */
   int32_t tile_grid_per_cu; /* cap on tile workgroups per CU (0: one per tile) */
-  int32_t reserved0;     /* must be 0 */
-  int32_t reserved1;     /* must be 0 */
+  int32_t chunk_cic;     /* binned path: a tile holding more CIC entries than
+                            this (64 .. 2^24) is split into chunks of at most
+                            this many, each accumulated in LDS by its own
+                            workgroup; the last chunk to finish sums the
+                            chunks' partial tiles in chunk order and stores */
+  int32_t chunk_sn;      /* the same threshold for supernova entries (16 .. 2^24) */
 } pmp_tuning;
 
 /* Create a context on the current HIP device.  Copies the layout, checks the

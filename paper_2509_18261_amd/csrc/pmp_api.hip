@@ -127,6 +127,7 @@ struct pmp_ctx {
   double* d_sink_scratch = nullptr;
   long long sink_cap = 0;
   int num_cu = 256;
+  int max_lds = 65536;  // LDS bytes one workgroup may use
   pmp_tuning tune{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -135,9 +136,10 @@ struct pmp_ctx {
   long long ntiles = 0;
   long long* d_tile_prefix = nullptr;
   int* d_tiles_axis = nullptr;
+  int* d_tile_box = nullptr;
   BinWork bw{};
   long long bw_hist = 0, bw_blocks = 0, bw_tiles = 0, bw_nsn = 0, bw_hist2 = 0,
-            bw_slice_base = 0;
+            bw_slice_base = 0, bw_partial = 0;
   // phase profiler: events[phase][2 * launch + {0: start, 1: stop}]
   bool prof_on = false;
   int prof_max = 0;
@@ -184,6 +186,7 @@ struct pmp_ctx {
     for (int a = 0; a < 3; ++a) T.t[a] = tile_dims[a];
     T.tile_prefix = d_tile_prefix;
     T.tiles_axis = d_tiles_axis;
+    T.tile_box = d_tile_box;
     T.ntiles = ntiles;
     return T;
   }
@@ -203,14 +206,19 @@ void free_bin_work(pmp_ctx* c) {
   (void)hipFree(w.sn_tmp_tile);
   (void)hipFree(w.sn_rec);
   (void)hipFree(w.sn_off);
-  (void)hipFree(w.sn_n);
-  (void)hipFree(w.sn_target);
+  (void)hipFree(w.sn_pk);
   (void)hipFree(w.sn_rows);
   (void)hipFree(w.slice_base);
   (void)hipFree(w.hist2);
   (void)hipFree(w.block_sums2);
+  (void)hipFree(w.heavy_base);
+  (void)hipFree(w.heavy_unit);
+  (void)hipFree(w.heavy_count);
+  (void)hipFree(w.arrive);
+  (void)hipFree(w.partial);
   w = BinWork{};
   c->bw_hist = c->bw_blocks = c->bw_tiles = c->bw_nsn = c->bw_hist2 = c->bw_slice_base = 0;
+  c->bw_partial = 0;
 }
 
 void prof_free(pmp_ctx* c) {
@@ -256,6 +264,7 @@ void release(pmp_ctx* c) {
   (void)hipFree(c->d_sink_scratch);
   (void)hipFree(c->d_tile_prefix);
   (void)hipFree(c->d_tiles_axis);
+  (void)hipFree(c->d_tile_box);
   (void)hipFree(c->d_zone_off);
   (void)hipFree(c->d_zone_seg);
   (void)hipFree(c->d_apply_chunks);
@@ -279,23 +288,33 @@ int build_tiles(pmp_ctx* c, int tx, int tyz) {
   }
   if (2 * prefix[c->nbox] + 1 >= (1ll << 31))
     return fail(PMP_ERANGE, "too many tiles (%lld); use larger tiles", prefix[c->nbox]);
+  std::vector<int> tbox((size_t)prefix[c->nbox]);
+  for (int b = 0; b < c->nbox; ++b)
+    for (long long q = prefix[b]; q < prefix[b + 1]; ++q) tbox[(size_t)q] = b;
   long long* dp = nullptr;
   int* da = nullptr;
+  int* dt = nullptr;
   hipError_t e = dev_alloc(&dp, prefix.size());
   if (e == hipSuccess) e = dev_alloc(&da, axis.size());
+  if (e == hipSuccess) e = dev_alloc(&dt, std::max<size_t>(tbox.size(), 1));
   if (e == hipSuccess)
     e = hipMemcpy(dp, prefix.data(), sizeof(long long) * prefix.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(da, axis.data(), sizeof(int) * axis.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !tbox.empty())
+    e = hipMemcpy(dt, tbox.data(), sizeof(int) * tbox.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(dp);
     (void)hipFree(da);
+    (void)hipFree(dt);
     return fail(PMP_EDEVICE, "tile grid: %s", hipGetErrorString(e));
   }
   (void)hipFree(c->d_tile_prefix);
   (void)hipFree(c->d_tiles_axis);
+  (void)hipFree(c->d_tile_box);
   c->d_tile_prefix = dp;
   c->d_tiles_axis = da;
+  c->d_tile_box = dt;
   for (int a = 0; a < 3; ++a) c->tile_dims[a] = t[a];
   c->ntiles = prefix[c->nbox];
   return PMP_OK;
@@ -444,21 +463,38 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
   const int* t = c->tile_dims;
   const long long span = 2 * (long long)std::ceil(std::max(r_max, 0.0)) + 3;
   const long long maxt = tiles_for(span, t[0]) * tiles_for(span, t[1]) * tiles_for(span, t[2]);
-  // coarse buckets: at most 1024, each 2^shift consecutive tiles
-  int shift = 0;
-  while (((c->ntiles + (1ll << shift) - 1) >> shift) > 1024) ++shift;
-  const int nb = (int)((c->ntiles + (1ll << shift) - 1) >> shift);
   const long long nbc = (n_cic + kBinChunkCic - 1) / kBinChunkCic;
   const long long nbs = (n_sn + kBinChunkSn - 1) / kBinChunkSn;
-  const long long hist = (long long)nb * (nbc + nbs) + 1;
-  const long long blocks = (hist + 1023) / 1024 + 1;
   const long long cic_cap = std::max<long long>(8 * n_cic, 1);
   const long long sn_cap = std::max<long long>(maxt * n_sn, 1);
+  const long long full_slices = (cic_cap + kSlice - 1) / kSlice + (sn_cap + kSlice - 1) / kSlice;
+  // coarse buckets of 2^shift consecutive tiles (at most 1024 buckets, at
+  // most 8192 tiles per bucket): the shift that minimises the histogram work,
+  // level 1 (nb x blocks counts, written one cache line apart, weighted 4)
+  // plus level 2 (2^shift x slices counts, zeroed and scanned)
+  int shift = -1;
+  double best = 0.0;
+  for (int sh = 0; sh <= 13; ++sh) {
+    const long long nbs_ = (c->ntiles + (1ll << sh) - 1) >> sh;
+    if (nbs_ > 1024) continue;
+    const double cost = 4.0 * (double)nbs_ * (double)(nbc + nbs) +
+                        (double)(1ll << sh) * (double)(full_slices + 2 * nbs_);
+    if (shift < 0 || cost < best) {
+      shift = sh;
+      best = cost;
+    }
+  }
+  if (shift < 0) return fail(PMP_ERANGE, "binned deposit: too many tiles (%lld)", c->ntiles);
+  const int nb = (int)((c->ntiles + (1ll << shift) - 1) >> shift);
+  const long long hist = (long long)nb * (nbc + nbs) + 1;
+  const long long blocks = (hist + 1023) / 1024 + 1;
   // every bucket can add one partial slice to the full ones
-  const long long max_slices = (cic_cap + kSlice - 1) / kSlice + (sn_cap + kSlice - 1) / kSlice +
-                               2 * (long long)nb;
+  const long long max_slices = full_slices + 2 * (long long)nb;
   const long long hist2 = (max_slices << shift) + 1;
   const long long blocks2 = (hist2 + 1023) / 1024 + 1;
+  // chunk slots for split tiles, each holding two channels of a padded LDS tile
+  const long long slot_cap = 4ll * c->num_cu;
+  const long long partial = slot_cap * 2 * (long long)(t[0] + 1) * t[1] * t[2];
   if (cic_cap >= (1ll << 31) || sn_cap >= (1ll << 31) || hist >= (1ll << 31) ||
       hist2 >= (1ll << 31))
     return fail(PMP_ERANGE, "binned deposit: too many tile entries");
@@ -466,7 +502,8 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
   c->bw.nbuckets = nb;
   const bool grow = hist > c->bw_hist || blocks > c->bw_blocks || c->ntiles + 1 > c->bw_tiles ||
                     cic_cap > c->bw.cic_cap || sn_cap > c->bw.sn_cap || n_sn > c->bw_nsn ||
-                    hist2 > c->bw_hist2 || 2 * nb + 1 > c->bw_slice_base;
+                    hist2 > c->bw_hist2 || 2 * nb + 1 > c->bw_slice_base ||
+                    partial > c->bw_partial;
   if (!grow) {
     c->bw.max_slices = (c->bw_hist2 - 1) >> shift;
     return PMP_OK;
@@ -486,7 +523,18 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
   if (!rc && c->ntiles + 1 > c->bw_tiles) {
     rc = regrow(&w.cic_off, 0, c->ntiles + 1);
     if (!rc) rc = regrow(&w.sn_off, 0, c->ntiles + 1);
+    if (!rc) rc = regrow(&w.heavy_base, 0, c->ntiles + 1);
     if (!rc) c->bw_tiles = c->ntiles + 1;
+  }
+  if (!rc && partial > c->bw_partial) {
+    rc = regrow(reinterpret_cast<double**>(&w.partial), 0, partial);
+    if (!rc && !w.heavy_unit) rc = regrow(&w.heavy_unit, 0, slot_cap);
+    if (!rc && !w.arrive) rc = regrow(&w.arrive, 0, slot_cap);
+    if (!rc && !w.heavy_count) rc = regrow(&w.heavy_count, 0, 1);
+    if (!rc) {
+      w.slot_cap = slot_cap;
+      c->bw_partial = partial;
+    }
   }
   if (!rc && cic_cap > w.cic_cap) {
     rc = regrow(&w.cic_tmp, 0, cic_cap);
@@ -510,8 +558,7 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
     if (!rc) c->bw_slice_base = 2 * nb + 1;
   }
   if (!rc && n_sn > c->bw_nsn) {
-    rc = regrow(&w.sn_n, 0, n_sn);
-    if (!rc) rc = regrow(&w.sn_target, 0, n_sn);
+    rc = regrow(&w.sn_pk, 0, n_sn);
     if (!rc) rc = regrow(&w.sn_rows, 0, n_sn * (long long)kRowCap);
     if (!rc) c->bw_nsn = n_sn;
   }
@@ -724,6 +771,10 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) ==
           hipSuccess && ncu > 0)
     c->num_cu = ncu;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) ==
+          hipSuccess && lds > 0)
+    c->max_lds = lds;
   c->nbox = L->nbox;
   c->ghost = L->ghost;
   for (int a = 0; a < 3; ++a) c->domain[a] = L->domain[a];
@@ -878,8 +929,8 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   c->tune.grid_per_cu = 32;
   c->tune.sn_lanes = 64;
   c->tune.tile_grid_per_cu = 0;
-  c->tune.reserved0 = 0;
-  c->tune.reserved1 = 0;
+  c->tune.chunk_cic = 4096;
+  c->tune.chunk_sn = 512;
   {
     int rc = build_tiles(c, c->tune.tile_x, c->tune.tile_yz);
     if (rc) {
@@ -1090,7 +1141,15 @@ int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
     return fail(PMP_EINVAL, "sn_lanes 16, 32 or 64");
   if (t->tile_grid_per_cu < 0 || t->tile_grid_per_cu > 64)
     return fail(PMP_EINVAL, "tile_grid_per_cu 0..64");
-  if (t->reserved0 != 0 || t->reserved1 != 0) return fail(PMP_EINVAL, "reserved fields must be 0");
+  if (t->chunk_cic < 64 || t->chunk_cic > (1 << 24)) return fail(PMP_EINVAL, "chunk_cic 64..2^24");
+  if (t->chunk_sn < 16 || t->chunk_sn > (1 << 24)) return fail(PMP_EINVAL, "chunk_sn 16..2^24");
+  {
+    const long long lds = tile_lds_bytes(t->tile_x, t->tile_yz, t->tile_block,
+                                         c->acc == PMP_ACC_FIX64);
+    if (lds > c->max_lds)
+      return fail(PMP_EINVAL, "tile %d x %d x %d needs %lld B of LDS, more than the %d B available",
+                  t->tile_x, t->tile_yz, t->tile_yz, lds, c->max_lds);
+  }
   if (t->tile_x != c->tile_dims[0] || t->tile_yz != c->tile_dims[1]) {
     if (c->graph_exec) return fail(PMP_EINVAL, "changing tiles would invalidate the built graph");
     PMP_HIP(hipDeviceSynchronize());

@@ -97,16 +97,20 @@ struct TileGrid {
   int t[3];                       // tile edge per axis (TX, TY, TZ)
   const long long* tile_prefix;   // [nbox+1] device
   const int* tiles_axis;          // [nbox][3] device: tiles per axis
+  const int* tile_box;            // [ntiles] device: box of each tile
   long long ntiles;
 };
 
-// A supernova as stored in its tiles' entry lists.
-struct SnRec {
-  double x, y, z, m, e, r;
-  int n;       // sphere members (-1: host cell only)
-  int target;  // padded-local index of the fixed-point remainder cell, or -1
-  int p;       // particle index (row table)
-  int rows;    // 1: the particle's row table holds its member runs
+// A supernova as prepared once by the binning pass; tile entry lists hold
+// particle indices into an array of these.
+struct SnPk {
+  double x, y, z, r;
+  // share of each member cell: m / (N V) and e / (N V) as doubles, or, for
+  // the fixed-point buffer, their 2^-40 quanta (int64 bits)
+  double vr, ve;
+  long long remr, reme;  // fixed point: Q(m / V) - N Q(m / (N V)), same for e
+  int n;                 // sphere members (-1: host cell only, 0: skipped)
+  int ti, tj, tk;        // padded-local remainder cell (ti < 0: none in the box)
 };
 
 // Member runs of a supernova's sphere rows, stored once per particle by the
@@ -129,12 +133,11 @@ struct BinWork {
   int* cic_tmp_tile;
   double4* cic_rec;     // level-2 output, grouped by tile
   int* cic_off;         // [ntiles + 1]
-  SnRec* sn_tmp;
+  int* sn_tmp;           // supernova entries: particle indices
   int* sn_tmp_tile;
-  SnRec* sn_rec;
+  int* sn_rec;
   int* sn_off;          // [ntiles + 1]
-  int* sn_n;            // [n_sn] members of each sphere (-1 host only, 0 skipped)
-  int* sn_target;       // [n_sn]
+  SnPk* sn_pk;          // [n_sn]
   unsigned short* sn_rows;  // [n_sn * kRowCap]
   long long cic_cap, sn_cap;
   // level 2 works on slices of at most kSlice records of one bucket
@@ -142,11 +145,31 @@ struct BinWork {
   int* hist2;           // [2^shift * max_slices + 1]: per (bucket, tile, slice), then scanned
   int* block_sums2;
   long long max_slices;
+  // tiles with more entries than a chunk threshold are split over several
+  // workgroups (chunk slots); each chunk leaves its LDS partial tile in
+  // `partial` and the last one to finish combines them in chunk order
+  int* heavy_base;      // [ntiles] first chunk slot of a split tile, or -1
+  int2* heavy_unit;     // [slot_cap] (tile, chunk) of each slot; tile -1: unused
+  int* heavy_count;     // [1] chunk slots claimed this step (may exceed slot_cap)
+  int* arrive;          // [slot_cap] finished chunks, at the tile's first slot
+  void* partial;        // [slot_cap][2][lcells] 8-byte partial sums
+  long long slot_cap;
 };
 
 constexpr int kSlice = 4096;
 
-constexpr int kBinChunkCic = 2048;  // CIC particles per level-1 block
+// LDS of one tile workgroup: two accumulator channels of the tile with rows
+// padded to tx + 1 cells, then, per batch of supernova entries, the runs of
+// the tile's tyz^2 rows clipped to the tile and the per-entry values.
+__host__ __device__ constexpr int tile_batch(int block, int slots) {
+  return block < 1024 / slots ? block : 1024 / slots;
+}
+__host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz, int block, bool fixed) {
+  return 2ll * (tx + 1) * tyz * tyz * 8 +
+         (long long)tile_batch(block, tyz * tyz) * (tyz * tyz * 2 + 16 + (fixed ? 24 : 0));
+}
+
+constexpr int kBinChunkCic = 1024;  // CIC particles per level-1 block
 constexpr int kBinChunkSn = 64;     // supernovae per level-1 block
 
 // Kernel launchers: all enqueue on `s` and return hipError_t of the launch.

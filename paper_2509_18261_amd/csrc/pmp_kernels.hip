@@ -1028,6 +1028,15 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(int* __restrict__ offse
 // hist[bucket * nblk + k].  Scatter pass: hist holds the scanned positions;
 // LDS cursors hand out slots and each pair's record (x, y, z, m) and tile are
 // written there, so a block writes runs of consecutive slots per bucket.
+// Column of level-1 block blk in a bucket's row of the histogram: blocks
+// grouped by XCD (block i runs on XCD i mod 8), so that the counts sharing a
+// cache line come from one XCD and merge in its L2.  A bijection on
+// [0, nblk); positions within a bucket follow this order.
+__device__ __forceinline__ int hist_col(int blk, int nblk) {
+  const int x = blk & 7, k = nblk >> 3, r = nblk & 7;
+  return x * k + min(x, r) + (blk >> 3);
+}
+
 template <bool SCATTER>
 __global__ __launch_bounds__(256) void k_l1_cic(Mesh M, TileGrid T, Particles P, int shift,
                                                int nb, int* __restrict__ hist, int nblk,
@@ -1035,10 +1044,11 @@ __global__ __launch_bounds__(256) void k_l1_cic(Mesh M, TileGrid T, Particles P,
                                                int* __restrict__ tmp_tile, long long cap) {
   extern __shared__ int h[];
   const int g = M.ghost;
+  const int col = hist_col(blockIdx.x, nblk);
   // hist is this kind's segment of the scanned histograms: positions are
   // taken relative to its first entry
   for (int c = threadIdx.x; c < nb; c += blockDim.x)
-    h[c] = SCATTER ? hist[(long long)c * nblk + blockIdx.x] - hist[0] : 0;
+    h[c] = SCATTER ? hist[(long long)c * nblk + col] - hist[0] : 0;
   __syncthreads();
   const long long p0 = (long long)blockIdx.x * kBinChunkCic;
   const long long p1 = min(p0 + kBinChunkCic, P.n);
@@ -1073,18 +1083,19 @@ __global__ __launch_bounds__(256) void k_l1_cic(Mesh M, TileGrid T, Particles P,
     if (nan) raise_flag(M.status, PMP_FLAG_NAN);
     __syncthreads();
     for (int c = threadIdx.x; c < nb; c += blockDim.x)
-      hist[(long long)c * nblk + blockIdx.x] = h[c];
+      hist[(long long)c * nblk + col] = h[c];
   } else if (full) {
     raise_flag(M.status, PMP_FLAG_CAPACITY);
   }
 }
 
 // Level 1, supernovae.  Histogram pass: a group of 16 lanes per particle
-// counts the sphere's members N (sn_n = N; -1 when no centre lies within r
-// and the host cell takes the deposit; 0 when the particle is skipped) and
-// finds the fixed-point remainder cell (host if a member, else the first
-// member in (k, j, i) order), then counts the particle into the buckets of
-// every tile its sphere touches.  Scatter pass: one thread per particle.
+// counts the sphere's members N (-1 when no centre lies within r and the host
+// cell takes the deposit; 0 when the particle is skipped), fills its row
+// table, finds the fixed-point remainder cell (host if a member, else the
+// first member in (k, j, i) order), writes the particle's SnPk and counts it
+// into the buckets of every tile its sphere touches.  Scatter pass: one
+// thread per particle writes (particle, tile) entries.
 __device__ __forceinline__ bool sn_tiles(const Mesh& M, const TileGrid& T, const DevBox& B,
                                          double x, double y, double z, double r, int N,
                                          int tlo[3], int thi[3]) {
@@ -1099,18 +1110,24 @@ __device__ __forceinline__ bool sn_tiles(const Mesh& M, const TileGrid& T, const
   return tile_range(B, T, slo, shi, tlo, thi);
 }
 
+// Whether a sphere's member runs fit a row table.
+__device__ __forceinline__ bool sn_has_table(const Sphere& S) {
+  return S.nrows <= kRowCap && S.hi[0] - S.lo[0] < 255;
+}
+
 template <bool SCATTER>
 __global__ __launch_bounds__(256) void k_l1_sn(Mesh M, TileGrid T, Particles P, int shift,
                                               int nb, int* __restrict__ hist, int nblk,
-                                              int* __restrict__ sn_n, int* __restrict__ sn_target,
+                                              SnPk* __restrict__ pk,
                                               unsigned short* __restrict__ sn_rows,
-                                              SnRec* __restrict__ tmp,
+                                              int* __restrict__ tmp,
                                               int* __restrict__ tmp_tile, long long cap) {
   constexpr int L = 16;
   extern __shared__ int h[];
   const int g = M.ghost;
+  const int col = hist_col(blockIdx.x, nblk);
   for (int c = threadIdx.x; c < nb; c += blockDim.x)
-    h[c] = SCATTER ? hist[(long long)c * nblk + blockIdx.x] - hist[0] : 0;
+    h[c] = SCATTER ? hist[(long long)c * nblk + col] - hist[0] : 0;
   __syncthreads();
   const long long p0 = (long long)blockIdx.x * kBinChunkSn;
   const long long p1 = min(p0 + kBinChunkSn, P.n);
@@ -1121,33 +1138,69 @@ __global__ __launch_bounds__(256) void k_l1_sn(Mesh M, TileGrid T, Particles P, 
       const DevBox B = M.boxes[b];
       const double x = P.x[p], y = P.y[p], z = P.z[p];
       const double m = P.b[p], e = P.c[p], r = P.r[p];
+      SnPk R;
+      R.x = x;
+      R.y = y;
+      R.z = z;
+      R.r = r;
+      R.n = 0;
+      R.ti = R.tj = R.tk = -1;
+      R.vr = R.ve = 0.0;
+      R.remr = R.reme = 0;
       int hc[3];
-      if (!host_cell(B, x, y, z, hc)) {
-        if (lane == 0) { raise_flag(M.status, PMP_FLAG_OUTSIDE); sn_n[p] = 0; }
-        continue;
-      }
-      if (!isfinite(m) || !isfinite(e) || !isfinite(r) || !(r >= 0.0)) {
-        if (lane == 0) { raise_flag(M.status, PMP_FLAG_NAN); sn_n[p] = 0; }
-        continue;
-      }
-      if (floor(r + 0.5) > (double)g) {
-        if (lane == 0) { raise_flag(M.status, PMP_FLAG_REACH); sn_n[p] = 0; }
+      unsigned flag = 0;
+      if (!host_cell(B, x, y, z, hc)) flag = PMP_FLAG_OUTSIDE;
+      else if (!isfinite(m) || !isfinite(e) || !isfinite(r) || !(r >= 0.0)) flag = PMP_FLAG_NAN;
+      else if (floor(r + 0.5) > (double)g) flag = PMP_FLAG_REACH;
+      if (flag) {
+        if (lane == 0) {
+          raise_flag(M.status, flag);
+          pk[p] = R;
+        }
         continue;
       }
       Sphere Sp;
       sphere_init(Sp, x, y, z, r);
-      const bool table = Sp.nrows <= kRowCap && Sp.hi[0] - Sp.lo[0] < 255;
       int N, first, hostm, outside;
       sphere_count<L>(Sp, B, g, hc, lane, N, first, hostm, outside,
-                      table ? sn_rows + (long long)kRowCap * p : nullptr);
+                      sn_has_table(Sp) ? sn_rows + (long long)kRowCap * p : nullptr);
       if (N == 0) N = -1;
+      // member share, and for fixed point the remainder that makes the
+      // deposited total exactly Q(m / V)
+      const int NN = N < 0 ? 1 : N;
+      const double cr = m / ((double)NN * M.V), ce = e / ((double)NN * M.V);
+      bool ok = true;
+      if (M.acc == PMP_ACC_FIX64) {
+        long long qr = 0, qe = 0, Qr = 0, Qe = 0;
+        ok = quantise(cr, qr) && quantise(ce, qe) && quantise(m / M.V, Qr) &&
+             quantise(e / M.V, Qe);
+        R.vr = __longlong_as_double(qr);
+        R.ve = __longlong_as_double(qe);
+        R.remr = Qr - (long long)NN * qr;
+        R.reme = Qe - (long long)NN * qe;
+      } else {
+        R.vr = cr;
+        R.ve = ce;
+      }
+      if (!ok) {
+        if (lane == 0) {
+          raise_flag(M.status, PMP_FLAG_OVERFLOW);
+          pk[p] = R;  // n = 0: skipped
+        }
+        continue;
+      }
+      R.n = N;
+      int ti = hc[0], tj = hc[1], tk = hc[2];
+      if (N > 0 && !hostm) sphere_key_cell(Sp, first, ti, tj, tk);
+      long long idx;
+      if (pad_index(B, g, ti, tj, tk, idx)) {
+        R.ti = ti - B.lo[0] + g;
+        R.tj = tj - B.lo[1] + g;
+        R.tk = tk - B.lo[2] + g;
+      }
       if (lane == 0) {
         if (outside) raise_flag(M.status, PMP_FLAG_REACH);
-        int ti = hc[0], tj = hc[1], tk = hc[2];
-        if (N > 0 && !hostm) sphere_key_cell(Sp, first, ti, tj, tk);
-        long long idx;
-        sn_target[p] = pad_index(B, g, ti, tj, tk, idx) ? (int)idx : -1;
-        sn_n[p] = N;
+        pk[p] = R;
       }
       int tlo[3], thi[3];
       if (!sn_tiles(M, T, B, x, y, z, r, N, tlo, thi)) continue;
@@ -1161,31 +1214,15 @@ __global__ __launch_bounds__(256) void k_l1_sn(Mesh M, TileGrid T, Particles P, 
     }
     __syncthreads();
     for (int c = threadIdx.x; c < nb; c += blockDim.x)
-      hist[(long long)c * nblk + blockIdx.x] = h[c];
+      hist[(long long)c * nblk + col] = h[c];
   } else {
     bool full = false;
     for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-      const int N = sn_n[p];
+      const SnPk& R = pk[p];
+      const int N = R.n;
       if (N == 0) continue;
       const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
       const DevBox B = M.boxes[b];
-      SnRec R;
-      R.x = P.x[p];
-      R.y = P.y[p];
-      R.z = P.z[p];
-      R.m = P.b[p];
-      R.e = P.c[p];
-      R.r = P.r[p];
-      R.n = N;
-      R.target = sn_target[p];
-      R.p = (int)p;
-      {
-        int lo0, hi0, lo1, hi1, lo2, hi2;
-        sphere_range(R.x, R.r, lo0, hi0);
-        sphere_range(R.y, R.r, lo1, hi1);
-        sphere_range(R.z, R.r, lo2, hi2);
-        R.rows = ((hi1 - lo1 + 1) * (hi2 - lo2 + 1) <= kRowCap && hi0 - lo0 < 255) ? 1 : 0;
-      }
       int tlo[3], thi[3];
       if (!sn_tiles(M, T, B, R.x, R.y, R.z, R.r, N, tlo, thi)) continue;
       for (int tz = tlo[2]; tz <= thi[2]; ++tz)
@@ -1194,7 +1231,7 @@ __global__ __launch_bounds__(256) void k_l1_sn(Mesh M, TileGrid T, Particles P, 
             const int id = (int)tile_id(T, b, tx, ty, tz);
             const int pos = atomicAdd(h + (id >> shift), 1);
             if (pos < cap) {
-              tmp[pos] = R;
+              tmp[pos] = (int)p;
               tmp_tile[pos] = id;
             } else {
               full = true;
@@ -1233,11 +1270,15 @@ __device__ __forceinline__ void bucket_range(const L2Geom& G, int cc, long long&
 // tile offsets of empty buckets and the kinds' totals.
 __global__ __launch_bounds__(1024) void k_l2_plan(L2Geom G, int* __restrict__ slice_base,
                                                   int* __restrict__ off0,
-                                                  int* __restrict__ off1) {
+                                                  int* __restrict__ off1,
+                                                  int* __restrict__ heavy_count) {
   __shared__ int sh[kWave];
   __shared__ int carry;
   const int n = 2 * G.nb;
-  if (threadIdx.x == 0) carry = 0;
+  if (threadIdx.x == 0) {
+    carry = 0;
+    *heavy_count = 0;  // chunk slots are claimed afresh after the sort
+  }
   __syncthreads();
   for (int base_c = 0; base_c < n; base_c += blockDim.x) {
     const int cc = base_c + threadIdx.x;
@@ -1344,6 +1385,57 @@ __global__ __launch_bounds__(256) void k_l2_scatter(L2Geom G, int kind,
   }
 }
 
+// Chunks a tile's entries are split into: at most cc CIC and cs supernova
+// entries per chunk.
+__device__ __forceinline__ int tile_chunks(long long nc, long long ns, int cc, int cs) {
+  const long long a = (nc + cc - 1) / cc, b = (ns + cs - 1) / cs;
+  return (int)max(1ll, max(a, b));
+}
+
+// Entry range [e0, e1) of tile t in a sorted list (entries past the
+// capacity were never written: the fill flagged them).
+__device__ __forceinline__ void tile_entries(const int* off, long long cap, long long t,
+                                             long long& e0, long long& e1) {
+  e0 = 0;
+  e1 = 0;
+  if (off) {
+    e0 = min((long long)off[t], cap);
+    e1 = min((long long)off[t + 1], cap);
+  }
+}
+
+// One thread per tile: tiles with more entries than a chunk holds claim
+// consecutive chunk slots (when slots remain) and list their chunks.
+__global__ __launch_bounds__(256) void k_units(TileGrid T, const int* __restrict__ coff,
+                                              long long ccap, const int* __restrict__ soff,
+                                              long long scap, int cc, int cs,
+                                              int* __restrict__ heavy_base,
+                                              int2* __restrict__ heavy_unit,
+                                              int* __restrict__ heavy_count,
+                                              int* __restrict__ arrive, long long slot_cap) {
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < T.ntiles;
+       t += (long long)gridDim.x * blockDim.x) {
+    long long c0, c1, s0, s1;
+    tile_entries(coff, ccap, t, c0, c1);
+    tile_entries(soff, scap, t, s0, s1);
+    const int chunks = tile_chunks(c1 - c0, s1 - s0, cc, cs);
+    int base = -1;
+    if (chunks > 1) {
+      const int b0 = atomicAdd(heavy_count, chunks);
+      if ((long long)b0 + chunks <= slot_cap) {
+        base = b0;
+        for (int j = 0; j < chunks; ++j) heavy_unit[b0 + j] = make_int2((int)t, j);
+        arrive[b0] = 0;
+      } else {
+        // out of slots: the tile stays whole; mark the slots it claimed unused
+        for (long long j = b0; j < min((long long)b0 + chunks, slot_cap); ++j)
+          heavy_unit[j] = make_int2(-1, 0);
+      }
+    }
+    heavy_base[t] = base;
+  }
+}
+
 template <bool FIXED> struct LdsT;
 template <> struct LdsT<true> { using T = unsigned long long; };
 template <> struct LdsT<false> { using T = double; };
@@ -1359,151 +1451,272 @@ template <> __device__ __forceinline__ long long from_lds<long long>(unsigned lo
 }
 template <class T> __device__ __forceinline__ T from_lds(double v) { return (T)v; }
 
-// One workgroup per tile: CIC entries one per thread, supernova entries one
-// per wavefront with lanes over the tile's share of the sphere; then every
-// field of every cell of the tile is stored once (fields without sources as
-// zero).  Sphere membership, shares and fixed-point remainders are the same
-// as in the direct kernels.
-template <int ACC>
+// One workgroup per work unit (a whole tile, or one chunk of a split tile).
+// Phase A, one thread per entry: CIC entries deposit straight into the LDS
+// accumulators; each supernova entry loads its particle's record and the
+// row-table entries of the tile's TYZ x TYZ rows (independent loads, issued
+// together) and leaves the runs clipped to the tile in LDS.  Phase B, one
+// thread per (supernova entry, tile row): adds the run's cells.  Then every
+// present channel of every cell of the tile is stored once (channels without
+// sources as zero).  Membership, shares and fixed-point remainders are the
+// same as in the direct kernels.
+template <int ACC, int TYZ>
 __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
                                                       const int* __restrict__ coff,
                                                       const double4* __restrict__ crec,
                                                       long long ccap,
                                                       const int* __restrict__ soff,
-                                                      const SnRec* __restrict__ srec,
+                                                      const int* __restrict__ sidx,
+                                                      const SnPk* __restrict__ pk,
                                                       long long scap,
                                                       const unsigned short* __restrict__ rows,
+                                                      int cc, int cs,
+                                                      const int* __restrict__ heavy_base,
+                                                      const int2* __restrict__ heavy_unit,
+                                                      const int* __restrict__ heavy_count,
+                                                      int* __restrict__ arrive,
+                                                      void* __restrict__ partial_v,
+                                                      long long slot_cap,
                                                       typename AccT<ACC>::T* __restrict__ buf) {
   using OutT = typename AccT<ACC>::T;
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
   using LT = typename LdsT<FIXED>::T;
+  constexpr int TY = TYZ, TZ = TYZ, S = TYZ * TYZ;
+  constexpr int YSH = (TYZ == 2) ? 1 : (TYZ == 4) ? 2 : 3;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int TX = T.t[0], TY = T.t[1], TZ = T.t[2];
+  __shared__ int s_last;
+  LT* partial = reinterpret_cast<LT*>(partial_v);
+  const int TX = T.t[0];
   const int tcells = TX * TY * TZ;
+  // LDS rows of TX + 1 elements: the rows of one x column fall in different
+  // banks, so lanes working on neighbouring rows do not conflict
+  const int TXP = TX + 1;
+  const int lcells = TXP * TY * TZ;
+  const int NB = tile_batch(blockDim.x, S);
   LT* a0 = reinterpret_cast<LT*>(smem);
-  LT* a4 = a0 + tcells;
+  LT* a4 = a0 + lcells;
+  double* bval = reinterpret_cast<double*>(a4 + lcells);  // [NB][2] shares
+  long long* brem = reinterpret_cast<long long*>(bval + 2 * NB);  // [NB][2] (fixed)
+  int* btgt = reinterpret_cast<int*>(brem + (FIXED ? 2 * NB : 0));  // [NB] (fixed)
+  unsigned short* bruns = reinterpret_cast<unsigned short*>(btgt + (FIXED ? NB : 0));
   const int g = M.ghost;
-  for (long long tile = blockIdx.x; tile < T.ntiles; tile += gridDim.x) {
-    const int b = (M.nbox == 1) ? 0 : find_box(T.tile_prefix, M.nbox, tile);
+  // work units: every tile that is not split, whole, in tile order; then
+  // the chunks of split tiles
+  const long long nheavy = min((long long)*heavy_count, slot_cap);
+  for (long long unit = blockIdx.x; unit < T.ntiles + nheavy; unit += gridDim.x) {
+    int tile;
+    int chunk = 0, base = -1;
+    if (unit < T.ntiles) {
+      tile = (int)unit;
+      if (heavy_base[tile] >= 0) continue;
+    } else {
+      const int2 hu = heavy_unit[unit - T.ntiles];
+      if (hu.x < 0) continue;
+      tile = hu.x;
+      chunk = hu.y;
+      base = heavy_base[tile];
+    }
+    const int b = T.tile_box[tile];
     const DevBox B = M.boxes[b];
     const int* ta = T.tiles_axis + 3 * b;
-    const long long lt = tile - T.tile_prefix[b];
-    const int tx = (int)(lt % ta[0]);
-    const long long rr = lt / ta[0];
-    const int ty = (int)(rr % ta[1]), tz = (int)(rr / ta[1]);
+    // tiles per box < 2^31: 32-bit coordinates
+    const unsigned lt = (unsigned)(tile - T.tile_prefix[b]);
+    const unsigned ntx = (unsigned)ta[0], nty = (unsigned)ta[1];
+    const unsigned rr = lt / ntx;
+    const int tx = (int)(lt - rr * ntx);
+    const unsigned tzq = rr / nty;
+    const int ty = (int)(rr - tzq * nty), tz = (int)tzq;
     const int o[3] = {tx * TX, ty * TY, tz * TZ};
     const int ext[3] = {min(TX, B.p[0] - o[0]), min(TY, B.p[1] - o[1]), min(TZ, B.p[2] - o[2])};
-    for (int c = threadIdx.x; c < tcells; c += blockDim.x) {
+    for (int c = threadIdx.x; c < lcells; c += blockDim.x) {
       a0[c] = (LT)0;
       a4[c] = (LT)0;
     }
+    long long e0, e1, s0, s1;
+    tile_entries(coff, ccap, tile, e0, e1);
+    tile_entries(soff, scap, tile, s0, s1);
+    int chunks = 1;
+    if (base >= 0) {
+      // this chunk's share of the tile's entries
+      chunks = tile_chunks(e1 - e0, s1 - s0, cc, cs);
+      const long long nc = e1 - e0, ns = s1 - s0;
+      e1 = e0 + nc * (chunk + 1) / chunks;
+      e0 = e0 + nc * chunk / chunks;
+      s1 = s0 + ns * (chunk + 1) / chunks;
+      s0 = s0 + ns * chunk / chunks;
+    }
     __syncthreads();
-    // global cell -> tile cell, if the tile holds it
+    // global cell -> LDS cell, if the tile holds it
     auto tcell = [&](int i, int j, int k, int& c) -> bool {
       const int u = i - B.lo[0] + g - o[0], v = j - B.lo[1] + g - o[1], w = k - B.lo[2] + g - o[2];
       if ((unsigned)u >= (unsigned)ext[0] || (unsigned)v >= (unsigned)ext[1] ||
           (unsigned)w >= (unsigned)ext[2])
         return false;
-      c = (w * TY + v) * TX + u;
+      c = (w * TY + v) * TXP + u;
       return true;
     };
+    const int xlo = o[0] - g + B.lo[0];  // tile origin, global cells
+    const int ylo = o[1] - g + B.lo[1];
+    const int zlo = o[2] - g + B.lo[2];
     bool ovf = false;
-    // entries past the capacity were never written (flagged in the fill)
-    long long e0 = 0, e1 = 0;
-    if (coff) {
-      e0 = coff[tile];
-      e1 = min((long long)coff[tile + 1], ccap);
-    }
-    for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-      const double4 R = crec[e];
-      const double x = R.x, y = R.y, z = R.z, m = R.w;
-      const int h[3] = {(int)floor(x), (int)floor(y), (int)floor(z)};
-      auto add = [&](int i, int j, int k, auto v) {
-        int c;
-        if (tcell(i, j, k, c)) lds_add(a0 + c, v);
-      };
-      if (!cic_one<FIXED>(x, y, z, m, M.V, h, add)) ovf = true;
-    }
-    // supernovae: one lane per entry, walking the tile's rows that meet the
-    // sphere's candidate box (row runs from the particle's table when there
-    // is one), so that a wavefront has 64 entries' loads in flight at once
-    long long s0 = 0, s1 = 0;
-    if (soff) {
-      s0 = soff[tile];
-      s1 = min((long long)soff[tile + 1], scap);
-    }
-    const int xlo = o[0] - g + B.lo[0], xhi = xlo + ext[0] - 1;  // tile range, global
-    const int ylo = o[1] - g + B.lo[1], yhi = ylo + ext[1] - 1;
-    const int zlo = o[2] - g + B.lo[2], zhi = zlo + ext[2] - 1;
-    for (long long e = s0 + threadIdx.x; e < s1; e += blockDim.x) {
-      const SnRec R = srec[e];
-      int N = R.n;
-      const bool only_host = (N < 0);
-      if (only_host) N = 1;
-      const double cr = R.m / ((double)N * M.V);
-      const double ce = R.e / ((double)N * M.V);
-      long long qr = 0, qe = 0;
-      if constexpr (FIXED) {
-        if (!quantise(cr, qr) || !quantise(ce, qe)) { ovf = true; continue; }
+    long long cpos = e0, spos = s0;
+    while (cpos < e1 || spos < s1) {
+      const int nq = (int)min((long long)NB, s1 - spos);
+      // phase A
+      {
+        const long long ce = cpos + threadIdx.x;
+        const bool has_c = ce < e1;
+        const bool has_s = (int)threadIdx.x < nq;
+        double4 CR = make_double4(0.0, 0.0, 0.0, 0.0);
+        int p = 0;
+        if (has_c) CR = crec[ce];
+        if (has_s) p = sidx[spos + threadIdx.x];
+        if (has_c) {
+          const int h[3] = {(int)floor(CR.x), (int)floor(CR.y), (int)floor(CR.z)};
+          auto add = [&](int i, int j, int k, auto v) {
+            int c;
+            if (tcell(i, j, k, c)) lds_add(a0 + c, v);
+          };
+          if (!cic_one<FIXED>(CR.x, CR.y, CR.z, CR.w, M.V, h, add)) ovf = true;
+        }
+        if (has_s) {
+          const int q = threadIdx.x;
+          const SnPk& R = pk[p];
+          const double rx = R.x, ry = R.y, rz = R.z, rr_ = R.r;
+          const int N = R.n;
+          bval[2 * q] = R.vr;
+          bval[2 * q + 1] = R.ve;
+          if constexpr (FIXED) {
+            const int lu = R.ti - o[0], lv = R.tj - o[1], lw = R.tk - o[2];
+            const bool in = R.ti >= 0 && (unsigned)lu < (unsigned)ext[0] &&
+                            (unsigned)lv < (unsigned)ext[1] && (unsigned)lw < (unsigned)ext[2];
+            btgt[q] = in ? (lw * TY + lv) * TXP + lu : -1;
+            brem[2 * q] = R.remr;
+            brem[2 * q + 1] = R.reme;
+          }
+          unsigned short* runs = bruns + q * S;
+          if (N < 0) {
+            // host cell only
+            const int hi = (int)floor(rx), hj = (int)floor(ry), hk = (int)floor(rz);
+#pragma unroll
+            for (int sl = 0; sl < S; ++sl) {
+              const int v = sl & (TY - 1), w = sl >> YSH;
+              const int u = hi - xlo;
+              const bool on = (ylo + v == hj) && (zlo + w == hk) && (unsigned)u < (unsigned)ext[0];
+              runs[sl] = on ? (unsigned short)(u | (u << 8)) : (unsigned short)0x00ff;
+            }
+          } else {
+            Sphere Sp;
+            sphere_init(Sp, rx, ry, rz, rr_);
+            if (sn_has_table(Sp)) {
+              const unsigned short* rt = rows + (long long)kRowCap * p;
+              // the row-table entries of the tile's rows, loaded together in
+              // groups of up to 16, then clipped to the tile
+              constexpr int GS = S < 16 ? S : 16;
+#pragma unroll
+              for (int g0 = 0; g0 < S; g0 += GS) {
+                unsigned raw[GS];
+#pragma unroll
+                for (int sl = 0; sl < GS; ++sl) {
+                  const int v = (g0 + sl) & (TY - 1), w = (g0 + sl) >> YSH;
+                  const int j = ylo + v, k = zlo + w;
+                  const bool cand = v < ext[1] && w < ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] &&
+                                    k >= Sp.lo[2] && k <= Sp.hi[2];
+                  raw[sl] = cand ? rt[(j - Sp.lo[1]) + Sp.cy * (k - Sp.lo[2])] : 0x00ffu;
+                }
+#pragma unroll
+                for (int sl = 0; sl < GS; ++sl) {
+                  const int ua = max(Sp.lo[0] + (int)(raw[sl] & 255u) - xlo, 0);
+                  const int ub = min(Sp.lo[0] + (int)(raw[sl] >> 8) - xlo, ext[0] - 1);
+                  runs[g0 + sl] = (ua <= ub) ? (unsigned short)(ua | (ub << 8))
+                                             : (unsigned short)0x00ff;
+                }
+              }
+            } else {
+              // a sphere too large for a row table: runs found row by row
+#pragma unroll 1
+              for (int sl = 0; sl < S; ++sl) {
+                const int v = sl & (TY - 1), w = sl >> YSH;
+                const int j = ylo + v, k = zlo + w;
+                int a = 1, bb = 0;
+                if (v < ext[1] && w < ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] &&
+                    k >= Sp.lo[2] && k <= Sp.hi[2])
+                  row_members(Sp, j, k, a, bb);
+                const int ua = max(a - xlo, 0), ub = min(bb - xlo, ext[0] - 1);
+                runs[sl] = (a <= bb && ua <= ub) ? (unsigned short)(ua | (ub << 8))
+                                                 : (unsigned short)0x00ff;
+              }
+            }
+          }
+        }
+        cpos += blockDim.x;
       }
-      auto put = [&](int c) {
+      __syncthreads();
+      // phase B
+      for (int it = threadIdx.x; it < nq * S; it += blockDim.x) {
+        const int q = it / S, sl = it & (S - 1);
+        const unsigned run = bruns[q * S + sl];
+        const int ua = (int)(run & 255u), ub = (int)(run >> 8);
+        if (ua > ub) continue;
+        const int v = sl & (TY - 1), w = sl >> YSH;
+        LT* r0 = a0 + (w * TY + v) * TXP;
+        LT* r4 = a4 + (w * TY + v) * TXP;
         if constexpr (FIXED) {
-          lds_add(a0 + c, qr);
-          lds_add(a4 + c, qe);
-        } else {
-          lds_add(a0 + c, cr);
-          lds_add(a4 + c, ce);
-        }
-      };
-      if (only_host) {
-        int c;
-        if (tcell((int)floor(R.x), (int)floor(R.y), (int)floor(R.z), c)) put(c);
-      } else {
-        Sphere Sp;
-        sphere_init(Sp, R.x, R.y, R.z, R.r);
-        const unsigned short* rtab = R.rows ? rows + (long long)kRowCap * R.p : nullptr;
-        const int j0 = max(ylo, Sp.lo[1]), j1 = min(yhi, Sp.hi[1]);
-        const int k0 = max(zlo, Sp.lo[2]), k1 = min(zhi, Sp.hi[2]);
-        for (int k = k0; k <= k1; ++k)
-          for (int j = j0; j <= j1; ++j) {
-            int a, bb;
-            if (rtab) {
-              const unsigned v = rtab[(j - Sp.lo[1]) + Sp.cy * (k - Sp.lo[2])];
-              a = Sp.lo[0] + (int)(v & 255u);
-              bb = Sp.lo[0] + (int)(v >> 8);
-            } else {
-              row_members(Sp, j, k, a, bb);
-            }
-            a = max(a, xlo);
-            bb = min(bb, xhi);
-            const int cbase = ((k - zlo) * TY + (j - ylo)) * TX - xlo;
-            for (int i = a; i <= bb; ++i) put(cbase + i);
+          const long long qr = __double_as_longlong(bval[2 * q]);
+          const long long qe = __double_as_longlong(bval[2 * q + 1]);
+          for (int u = ua; u <= ub; ++u) {
+            lds_add(r0 + u, qr);
+            lds_add(r4 + u, qe);
           }
+        } else {
+          const double cr = bval[2 * q], ce = bval[2 * q + 1];
+          for (int u = ua; u <= ub; ++u) {
+            lds_add(r0 + u, cr);
+            lds_add(r4 + u, ce);
+          }
+        }
       }
       if constexpr (FIXED) {
-        const int tgt = R.target;
-        if (tgt >= 0) {
-          const int li = tgt % B.p[0], rest = tgt / B.p[0];
-          const int lj = rest % B.p[1], lk = rest / B.p[1];
-          const int u = li - o[0], v = lj - o[1], w = lk - o[2];
-          if ((unsigned)u < (unsigned)ext[0] && (unsigned)v < (unsigned)ext[1] &&
-              (unsigned)w < (unsigned)ext[2]) {
-            long long Qr, Qe;
-            if (quantise(R.m / M.V, Qr) && quantise(R.e / M.V, Qe)) {
-              const int c = (w * TY + v) * TX + u;
-              lds_add(a0 + c, Qr - (long long)N * qr);
-              lds_add(a4 + c, Qe - (long long)N * qe);
-            } else {
-              ovf = true;
-            }
+        // fixed-point remainders, at the target cell when it is in the tile
+        for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+          const int c = btgt[q];
+          if (c >= 0) {
+            lds_add(a0 + c, brem[2 * q]);
+            lds_add(a4 + c, brem[2 * q + 1]);
           }
         }
       }
+      spos += nq;
+      __syncthreads();
     }
     if (ovf) raise_flag(M.status, PMP_FLAG_OVERFLOW);
     __syncthreads();
+    const LT* src0 = a0;
+    const LT* src4 = a4;
+    int nsum = 1;
+    long long sstride = 0;
+    if (base >= 0) {
+      // a chunk of a split tile: leave the partial tile, and the last chunk
+      // to finish (device-scope fence + arrival count) combines them
+      LT* part = partial + (long long)(base + chunk) * 2 * lcells;
+      for (int c = threadIdx.x; c < lcells; c += blockDim.x) {
+        part[c] = a0[c];
+        part[lcells + c] = a4[c];
+      }
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0) s_last = (atomicAdd(arrive + base, 1) == chunks - 1);
+      __syncthreads();
+      if (!s_last) continue;
+      __threadfence();
+      src0 = partial + (long long)base * 2 * lcells;
+      src4 = src0 + lcells;
+      nsum = chunks;
+      sstride = 2ll * lcells;
+    }
     // every present channel of every cell is stored once: rho and E from
-    // LDS, the others (no source in this pass) as zero
+    // the accumulators (summed over the chunks in chunk order), the others
+    // (no source in this pass) as zero
     OutT* f0 = buf + B.boff;
     const long long np = B.npad;
     const int sr = M.slot[0], se = M.slot[4];
@@ -1511,10 +1724,16 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
       const int u = c % TX, v = (c / TX) % TY, w = c / (TX * TY);
       if (u >= ext[0] || v >= ext[1] || w >= ext[2]) continue;
       const long long idx = ((long long)(o[2] + w) * B.p[1] + (o[1] + v)) * B.p[0] + (o[0] + u);
+      const int lc = (w * TY + v) * TXP + u;
+      LT r0 = src0[lc], r4 = src4[lc];
+      for (int q = 1; q < nsum; ++q) {
+        r0 += src0[q * sstride + lc];
+        r4 += src4[q * sstride + lc];
+      }
       for (int f = 0; f < M.nfield; ++f) {
         OutT val = (OutT)0;
-        if (f == sr) val = from_lds<OutT>(a0[c]);
-        else if (f == se) val = from_lds<OutT>(a4[c]);
+        if (f == sr) val = from_lds<OutT>(r0);
+        else if (f == se) val = from_lds<OutT>(r4);
         f0[idx + f * np] = val;
       }
     }
@@ -1594,7 +1813,7 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
                        nbc, (double4*)nullptr, (int*)nullptr, 0ll);
   if (has_s)
     hipLaunchKernelGGL(k_l1_sn<false>, dim3(nbs), dim3(256), lds1, s, M, T, *sn, S, nb, hs, nbs,
-                       bw.sn_n, bw.sn_target, bw.sn_rows, (SnRec*)nullptr, (int*)nullptr, 0ll);
+                       bw.sn_pk, bw.sn_rows, (int*)nullptr, (int*)nullptr, 0ll);
   // exclusive scan of both kinds' histograms, in place; hist[n] = total
   const int nblocks = (int)((n + kScanBlock - 1) / kScanBlock);
   hipLaunchKernelGGL(k_scan_local, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist, bw.hist,
@@ -1608,8 +1827,7 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
                        bw.cic_tmp, bw.cic_tmp_tile, bw.cic_cap);
   if (has_s)
     hipLaunchKernelGGL(k_l1_sn<true>, dim3(nbs), dim3(kBinChunkSn), lds1, s, M, T, *sn, S, nb,
-                       hs, nbs, bw.sn_n, bw.sn_target, bw.sn_rows, bw.sn_tmp, bw.sn_tmp_tile,
-                       bw.sn_cap);
+                       hs, nbs, bw.sn_pk, bw.sn_rows, bw.sn_tmp, bw.sn_tmp_tile, bw.sn_cap);
   // level 2: balanced slices of every bucket, both kinds
   L2Geom G;
   G.hist1 = bw.hist;
@@ -1619,7 +1837,7 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
   G.shift = S;
   G.ntiles = T.ntiles;
   hipLaunchKernelGGL(k_l2_plan, dim3(1), dim3(1024), 0, s, G, bw.slice_base, bw.cic_off,
-                     bw.sn_off);
+                     bw.sn_off, bw.heavy_count);
   const long long n2 = ((long long)1 << S) * bw.max_slices;
   hipError_t e = launch_zero(bw.hist2, n2 * (long long)sizeof(int), 256, s);
   if (e != hipSuccess) return e;
@@ -1641,9 +1859,9 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
                        (const double4*)bw.cic_tmp, (const int*)bw.cic_tmp_tile, bw.cic_rec,
                        bw.cic_off, bw.cic_cap);
   if (has_s)
-    hipLaunchKernelGGL(k_l2_scatter<SnRec>, dim3(grid2), dim3(256), lds2, s, G, 1,
+    hipLaunchKernelGGL(k_l2_scatter<int>, dim3(grid2), dim3(256), lds2, s, G, 1,
                        (const int*)bw.slice_base, (const int*)bw.hist2,
-                       (const SnRec*)bw.sn_tmp, (const int*)bw.sn_tmp_tile, bw.sn_rec,
+                       (const int*)bw.sn_tmp, (const int*)bw.sn_tmp_tile, bw.sn_rec,
                        bw.sn_off, bw.sn_cap);
   return hipGetLastError();
 }
@@ -1653,23 +1871,36 @@ hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles
                                const pmp_tuning& t, hipStream_t s) {
   const int* coff = (cic && cic->n > 0) ? bw.cic_off : nullptr;
   const int* soff = (sn && sn->n > 0) ? bw.sn_off : nullptr;
-  const size_t lds = 2 * (size_t)T.t[0] * T.t[1] * T.t[2] * 8;
+  const int block = t.tile_block;
+  const size_t lds = (size_t)tile_lds_bytes(T.t[0], T.t[1], block, M.acc == PMP_ACC_FIX64);
   long long grid = T.ntiles;
   if (t.tile_grid_per_cu > 0)
     grid = std::min<long long>(grid, (long long)M.num_cu * t.tile_grid_per_cu);
   if (grid < 1) grid = 1;
   if (grid > 0x7fffffffll) grid = 0x7fffffffll;
-  const int block = t.tile_block;
-#define PMP_TILE(ACC, TT)                                                                   \
-  hipLaunchKernelGGL(k_tile_deposit<ACC>, dim3((unsigned)grid), dim3(block), lds, s, M, T,  \
-                     coff, (const double4*)bw.cic_rec, bw.cic_cap, soff,                    \
-                     (const SnRec*)bw.sn_rec, bw.sn_cap, (const unsigned short*)bw.sn_rows, \
+  hipLaunchKernelGGL(k_units, dim3(grid_for(T.ntiles, 256, M.num_cu * 16)), dim3(256), 0, s, T,
+                     coff, bw.cic_cap, soff, bw.sn_cap, t.chunk_cic, t.chunk_sn, bw.heavy_base,
+                     bw.heavy_unit, bw.heavy_count, bw.arrive, bw.slot_cap);
+#define PMP_TILE(ACC, TT, TYZ)                                                                \
+  hipLaunchKernelGGL((k_tile_deposit<ACC, TYZ>), dim3((unsigned)grid), dim3(block), lds, s, M, \
+                     T, coff, (const double4*)bw.cic_rec, bw.cic_cap, soff,                   \
+                     (const int*)bw.sn_rec, (const SnPk*)bw.sn_pk, bw.sn_cap,                \
+                     (const unsigned short*)bw.sn_rows, t.chunk_cic, t.chunk_sn,              \
+                     (const int*)bw.heavy_base, (const int2*)bw.heavy_unit,                   \
+                     (const int*)bw.heavy_count, bw.arrive, bw.partial, bw.slot_cap,          \
                      (TT*)buf)
-  switch (M.acc) {
-    case PMP_ACC_F32: PMP_TILE(PMP_ACC_F32, float); break;
-    case PMP_ACC_F64: PMP_TILE(PMP_ACC_F64, double); break;
-    default: PMP_TILE(PMP_ACC_FIX64, long long);
+#define PMP_TILE_ACC(TYZ)                                      \
+  switch (M.acc) {                                             \
+    case PMP_ACC_F32: PMP_TILE(PMP_ACC_F32, float, TYZ); break; \
+    case PMP_ACC_F64: PMP_TILE(PMP_ACC_F64, double, TYZ); break; \
+    default: PMP_TILE(PMP_ACC_FIX64, long long, TYZ);          \
   }
+  switch (T.t[1]) {
+    case 2: PMP_TILE_ACC(2); break;
+    case 4: PMP_TILE_ACC(4); break;
+    default: PMP_TILE_ACC(8);
+  }
+#undef PMP_TILE_ACC
 #undef PMP_TILE
   return hipGetLastError();
 }

@@ -199,6 +199,10 @@ SHAPES = [
     {"deposit_path": 1, "tile_x": 32, "tile_yz": 8, "tile_block": 1024},
     {"deposit_path": 1, "tile_x": 64, "tile_yz": 4, "tile_grid_per_cu": 1},
     {"deposit_path": 1, "tile_x": 16, "tile_yz": 4, "tile_grid_per_cu": 3, "block": 128},
+    # split tiles: small chunk thresholds put most tiles through the chunked path
+    {"deposit_path": 1, "chunk_cic": 64, "chunk_sn": 16},
+    {"deposit_path": 1, "tile_x": 16, "tile_yz": 2, "chunk_cic": 64, "chunk_sn": 16,
+     "tile_grid_per_cu": 1},
 ]
 
 
@@ -220,6 +224,22 @@ def test_tiled_paths_multibox(B, orc):
     for tun in SHAPES[2:]:
         for acc in ("fix64", "f32"):
             check(B, orc, w, acc, tuning=tun)
+
+
+@pytest.mark.parametrize("acc", ["fix64", "f32", "f64"])
+def test_split_tiles_clustered(B, orc, acc):
+    """Clustered particles with small chunk thresholds: split tiles combine
+    their chunks exactly (fixed point) or within tolerance."""
+    w = W.c3(nx=48, n_sink=16)
+    check(B, orc, w, acc, tuning={"deposit_path": 1, "chunk_cic": 64, "chunk_sn": 16})
+
+
+def test_split_tiles_out_of_slots(B, orc):
+    """More chunks than chunk slots: the tiles that find no slots stay whole,
+    and the result is unchanged."""
+    w = W.c3(nx=128, n_sink=16)
+    assert w.cic.n / 64 > 4 * 256
+    check(B, orc, w, "fix64", tuning={"deposit_path": 1, "chunk_cic": 64, "chunk_sn": 16})
 
 
 def test_run_twice_bitwise(B):
