@@ -36,12 +36,15 @@ def acc_bytes(acc):
     return 4 if acc == "f32" else 8
 
 
-def algorithmic_bytes(w, acc, counts, F):
+def algorithmic_bytes(w, acc, counts, F, fused=False):
     """Bytes per launch each phase must move at minimum (no scratch, no
     re-reads): buffer writes for the zero fill, particle records plus a
     read-modify-write of every touched (cell, field) for deposits, the owned
     shell and its ghost images for the fold, and state in/out plus buffer in
-    for apply.  F = buffer channels of the timed layout."""
+    for apply.  F = buffer channels of the timed layout.  fused: the step
+    applies the interior cells (owned, at least g from every face) in the
+    tile pass, which stores the buffer only for the other cells, and the
+    shell cells are folded and applied in one pass."""
     import numpy as np
     ba = acc_bytes(acc)
     bs = np.dtype(w.state.dtype).itemsize
@@ -57,6 +60,7 @@ def algorithmic_bytes(w, acc, counts, F):
         parts += w.cic.n * 32
     if w.sn is not None:
         parts += w.sn.n * 48
+    interior = int(np.prod(np.maximum(n - 2 * g, 0), axis=1).sum())
     out = {
         "zero": padded * F * ba,
         # binned path: every buffer cell stored once plus the particle records
@@ -65,6 +69,12 @@ def algorithmic_bytes(w, acc, counts, F):
         "fold": F * ba * (2 * shell + ghost_cells),
         "apply": owned * (2 * 5 * bs + F * ba),
     }
+    if fused:
+        # tile: buffer for the non-interior cells, records, interior state in/out
+        out["tile"] = (padded - interior) * F * ba + parts + interior * 2 * 5 * bs
+        # fold: shell values and their ghost images in, shell state in/out
+        out["fold"] = F * ba * (shell + ghost_cells) + shell * 2 * 5 * bs
+        out["apply"] = 0
     if w.cic is not None and w.cic.n:
         out["cic"] = w.cic.n * 32 + 2 * ba * counts["cic"]
     if w.sn is not None and w.sn.n:
@@ -294,7 +304,9 @@ def main():
     del ctx
     torch.cuda.empty_cache()
 
-    algo = algorithmic_bytes(w, args.acc, counts, nchan)
+    fused = bool(tun.get("fuse_apply", 0)) and tun.get("deposit_path", 0) == 1 and \
+        (w.sinks is None or w.sinks.n == 0) and nparts > 0
+    algo = algorithmic_bytes(w, args.acc, counts, nchan, fused)
     per_phase = {}
     for name in PHASE_ORDER:
         if name not in phases:
@@ -309,9 +321,9 @@ def main():
     # (the binning phase is several small launches of scratch traffic)
     dom = max((k for k in per_phase if per_phase[k]["algo_bytes"] > 0),
               key=lambda k: per_phase[k]["avg_ms"])
-    kernel_names = {"bin": "k_bin_cic+k_bin_sn+k_scan+k_fill", "tile": "k_tile_deposit",
+    kernel_names = {"bin": "k_l1_*+k_scan_*+k_l2_*", "tile": "k_tile_deposit",
                     "zero": "k_zero", "cic": "k_cic_direct", "sn": "k_sn_direct",
-                    "sink_deposit": "k_sink_deposit", "fold": "k_fold",
+                    "sink_deposit": "k_sink_deposit", "fold": "k_fold_apply" if fused else "k_fold",
                     "sink_update": "k_sink_update", "apply": "k_apply"}
     d = per_phase[dom]
     achieved = d["algo_bytes"] / (d["avg_ms"] * 1e-3) / 1e9
@@ -334,7 +346,8 @@ def main():
                    "cic": w.cic.n if w.cic else 0, "sn": w.sn.n if w.sn else 0,
                    "sinks": w.sinks.n if w.sinks else 0, "ghost": w.ghost,
                    "state": str(np.dtype(w.state.dtype)), "acc": args.acc,
-                   "limiter": "f64", "boxes": w.nbox, "buffer_channels": nchan},
+                   "limiter": "f64", "boxes": w.nbox, "buffer_channels": nchan,
+                   "fused_apply": fused},
         "cells_per_s": w.owned_cells / (ms * 1e-3),
         "step_algo_bytes": int(step_bytes),
         "step_hbm_frac": step_bytes / (ms * 1e-3) / (HBM_PEAK_GBPS * 1e9),

@@ -169,6 +169,13 @@ typedef struct {
                             workgroup; the last chunk to finish sums the
                             chunks' partial tiles in chunk order and stores */
   int32_t chunk_sn;      /* the same threshold for supernova entries (16 .. 2^24) */
+  int32_t fuse_apply;    /* 1: pmp_step without sinks on the binned path applies
+                            Steps 3 + 5 inside the tile pass for owned cells at
+                            least g from every box face (no ghost image reaches
+                            them), then folds and applies the shell cells in one
+                            kernel; results are those of the separate calls.
+                            The buffer's interior cells are left unwritten. */
+  int32_t reserved;      /* must be 0 */
 } pmp_tuning;
 
 /* Create a context on the current HIP device.  Copies the layout, checks the

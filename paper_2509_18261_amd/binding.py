@@ -80,10 +80,11 @@ class pmp_tuning(C.Structure):
     _fields_ = [("deposit_path", C.c_int32), ("tile_x", C.c_int32), ("tile_yz", C.c_int32),
                 ("tile_block", C.c_int32), ("block", C.c_int32), ("grid_per_cu", C.c_int32),
                 ("sn_lanes", C.c_int32), ("tile_grid_per_cu", C.c_int32),
-                ("chunk_cic", C.c_int32), ("chunk_sn", C.c_int32)]
+                ("chunk_cic", C.c_int32), ("chunk_sn", C.c_int32),
+                ("fuse_apply", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
 NPHASE = 9

@@ -136,7 +136,7 @@ struct pmp_ctx {
   long long ntiles = 0;
   long long* d_tile_prefix = nullptr;
   int* d_tiles_axis = nullptr;
-  int* d_tile_box = nullptr;
+  TileGeo* d_tile_geo = nullptr;
   BinWork bw{};
   long long bw_hist = 0, bw_blocks = 0, bw_tiles = 0, bw_nsn = 0, bw_hist2 = 0,
             bw_slice_base = 0, bw_partial = 0;
@@ -186,7 +186,7 @@ struct pmp_ctx {
     for (int a = 0; a < 3; ++a) T.t[a] = tile_dims[a];
     T.tile_prefix = d_tile_prefix;
     T.tiles_axis = d_tiles_axis;
-    T.tile_box = d_tile_box;
+    T.geo = d_tile_geo;
     T.ntiles = ntiles;
     return T;
   }
@@ -205,6 +205,8 @@ void free_bin_work(pmp_ctx* c) {
   (void)hipFree(w.sn_tmp);
   (void)hipFree(w.sn_tmp_tile);
   (void)hipFree(w.sn_rec);
+  (void)hipFree(w.sn_rec_tile);
+  (void)hipFree(w.sn_ent);
   (void)hipFree(w.sn_off);
   (void)hipFree(w.sn_pk);
   (void)hipFree(w.sn_rows);
@@ -264,7 +266,7 @@ void release(pmp_ctx* c) {
   (void)hipFree(c->d_sink_scratch);
   (void)hipFree(c->d_tile_prefix);
   (void)hipFree(c->d_tiles_axis);
-  (void)hipFree(c->d_tile_box);
+  (void)hipFree(c->d_tile_geo);
   (void)hipFree(c->d_zone_off);
   (void)hipFree(c->d_zone_seg);
   (void)hipFree(c->d_apply_chunks);
@@ -288,21 +290,41 @@ int build_tiles(pmp_ctx* c, int tx, int tyz) {
   }
   if (2 * prefix[c->nbox] + 1 >= (1ll << 31))
     return fail(PMP_ERANGE, "too many tiles (%lld); use larger tiles", prefix[c->nbox]);
-  std::vector<int> tbox((size_t)prefix[c->nbox]);
-  for (int b = 0; b < c->nbox; ++b)
-    for (long long q = prefix[b]; q < prefix[b + 1]; ++q) tbox[(size_t)q] = b;
+  // per-tile geometry, in tile order (x fastest within a box)
+  std::vector<TileGeo> geo((size_t)prefix[c->nbox]);
+  for (int b = 0; b < c->nbox; ++b) {
+    const DevBox& d = c->dboxes[b];
+    const int* ax = &axis[3 * (size_t)b];
+    long long q = prefix[b];
+    for (int tz = 0; tz < ax[2]; ++tz)
+      for (int ty = 0; ty < ax[1]; ++ty)
+        for (int tx = 0; tx < ax[0]; ++tx, ++q) {
+          TileGeo& G = geo[(size_t)q];
+          std::memset(&G, 0, sizeof G);
+          const int tc[3] = {tx, ty, tz};
+          G.boff = d.boff;
+          G.soff = d.soff;
+          G.b = b;
+          for (int a = 0; a < 3; ++a) {
+            G.p[a] = d.p[a];
+            G.o[a] = tc[a] * t[a];
+            G.ext[a] = std::min(t[a], d.p[a] - G.o[a]);
+            G.glo[a] = G.o[a] - c->ghost + d.lo[a];
+          }
+        }
+  }
   long long* dp = nullptr;
   int* da = nullptr;
-  int* dt = nullptr;
+  TileGeo* dt = nullptr;
   hipError_t e = dev_alloc(&dp, prefix.size());
   if (e == hipSuccess) e = dev_alloc(&da, axis.size());
-  if (e == hipSuccess) e = dev_alloc(&dt, std::max<size_t>(tbox.size(), 1));
+  if (e == hipSuccess) e = dev_alloc(&dt, std::max<size_t>(geo.size(), 1));
   if (e == hipSuccess)
     e = hipMemcpy(dp, prefix.data(), sizeof(long long) * prefix.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(da, axis.data(), sizeof(int) * axis.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !tbox.empty())
-    e = hipMemcpy(dt, tbox.data(), sizeof(int) * tbox.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !geo.empty())
+    e = hipMemcpy(dt, geo.data(), sizeof(TileGeo) * geo.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(dp);
     (void)hipFree(da);
@@ -311,10 +333,10 @@ int build_tiles(pmp_ctx* c, int tx, int tyz) {
   }
   (void)hipFree(c->d_tile_prefix);
   (void)hipFree(c->d_tiles_axis);
-  (void)hipFree(c->d_tile_box);
+  (void)hipFree(c->d_tile_geo);
   c->d_tile_prefix = dp;
   c->d_tiles_axis = da;
-  c->d_tile_box = dt;
+  c->d_tile_geo = dt;
   for (int a = 0; a < 3; ++a) c->tile_dims[a] = t[a];
   c->ntiles = prefix[c->nbox];
   return PMP_OK;
@@ -494,6 +516,8 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
   const long long blocks2 = (hist2 + 1023) / 1024 + 1;
   // chunk slots for split tiles, each holding two channels of a padded LDS tile
   const long long slot_cap = 4ll * c->num_cu;
+  // supernova tile entries for the current tile shape
+  const long long ent_bytes = std::max<long long>(sn_cap, 1) * sn_ent_bytes(t[1]);
   const long long partial = slot_cap * 2 * (long long)(t[0] + 1) * t[1] * t[2];
   if (cic_cap >= (1ll << 31) || sn_cap >= (1ll << 31) || hist >= (1ll << 31) ||
       hist2 >= (1ll << 31))
@@ -503,7 +527,7 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
   const bool grow = hist > c->bw_hist || blocks > c->bw_blocks || c->ntiles + 1 > c->bw_tiles ||
                     cic_cap > c->bw.cic_cap || sn_cap > c->bw.sn_cap || n_sn > c->bw_nsn ||
                     hist2 > c->bw_hist2 || 2 * nb + 1 > c->bw_slice_base ||
-                    partial > c->bw_partial;
+                    partial > c->bw_partial || ent_bytes > c->bw.sn_ent_bytes;
   if (!grow) {
     c->bw.max_slices = (c->bw_hist2 - 1) >> shift;
     return PMP_OK;
@@ -546,7 +570,12 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
     rc = regrow(&w.sn_tmp, 0, sn_cap);
     if (!rc) rc = regrow(&w.sn_tmp_tile, 0, sn_cap);
     if (!rc) rc = regrow(&w.sn_rec, 0, sn_cap);
+    if (!rc) rc = regrow(&w.sn_rec_tile, 0, sn_cap);
     if (!rc) w.sn_cap = sn_cap;
+  }
+  if (!rc && ent_bytes > w.sn_ent_bytes) {
+    rc = regrow(reinterpret_cast<double**>(&w.sn_ent), 0, ent_bytes / 8);
+    if (!rc) w.sn_ent_bytes = ent_bytes;
   }
   if (!rc && hist2 > c->bw_hist2) {
     rc = regrow(&w.hist2, 0, hist2);
@@ -623,8 +652,12 @@ Particles from_sinks(const pmp_sinks* p) {
   return P;
 }
 
+// fuse_state non-null (a step without sinks): the binned path also applies
+// the interior cells; *fused tells whether it did.
 int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, const pmp_sn* sn,
-               const pmp_sinks* sinks, const pmp_limits* limits, hipStream_t s) {
+               const pmp_sinks* sinks, const pmp_limits* limits, hipStream_t s,
+               void* fuse_state = nullptr, bool* fused = nullptr) {
+  if (fused) *fused = false;
   if (!buf) return fail(PMP_EINVAL, "buffer is NULL");
   const bool has_cic = cic && cic->n > 0;
   const bool has_sn = sn && sn->n > 0;
@@ -668,8 +701,15 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
     }
     {
       PhaseTimer t(c, PMP_PHASE_TILE, s);
+      Limits L{};
+      if (fuse_state) {
+        const int rc2 = check_limits(limits);
+        if (rc2) return rc2;
+        L = to_limits(limits);
+      }
       PMP_HIP(launch_tile_deposit(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
-                                  buf, c->tune, s));
+                                  buf, c->tune, fuse_state, L, s));
+      if (fused) *fused = fuse_state != nullptr;
     }
   } else {
     {
@@ -730,8 +770,17 @@ int do_fold(pmp_ctx* c, void* buf, hipStream_t s) {
 
 int do_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn* sn,
             const pmp_sinks* sinks, const pmp_limits* limits, double* sink_out, hipStream_t s) {
-  int rc = do_deposit(c, buf, state, cic, sn, sinks, limits, s);
+  const bool has_sinks = sinks && sinks->n > 0;
+  bool fused = false;
+  int rc = do_deposit(c, buf, state, cic, sn, sinks, limits, s,
+                      (!has_sinks && c->tune.fuse_apply && state) ? state : nullptr, &fused);
   if (rc) return rc;
+  if (fused) {
+    // interior cells are done; fold and apply the shell
+    PhaseTimer t(c, PMP_PHASE_FOLD, s);
+    PMP_HIP(launch_fold_apply(c->mesh(), state, buf, to_limits(limits), s));
+    return PMP_OK;
+  }
   rc = do_fold(c, buf, s);
   if (rc) return rc;
   if (sinks && sinks->n > 0) {
@@ -931,6 +980,8 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   c->tune.tile_grid_per_cu = 0;
   c->tune.chunk_cic = 4096;
   c->tune.chunk_sn = 512;
+  c->tune.fuse_apply = 1;
+  c->tune.reserved = 0;
   {
     int rc = build_tiles(c, c->tune.tile_x, c->tune.tile_yz);
     if (rc) {
@@ -1143,9 +1194,10 @@ int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
     return fail(PMP_EINVAL, "tile_grid_per_cu 0..64");
   if (t->chunk_cic < 64 || t->chunk_cic > (1 << 24)) return fail(PMP_EINVAL, "chunk_cic 64..2^24");
   if (t->chunk_sn < 16 || t->chunk_sn > (1 << 24)) return fail(PMP_EINVAL, "chunk_sn 16..2^24");
+  if (t->fuse_apply != 0 && t->fuse_apply != 1) return fail(PMP_EINVAL, "fuse_apply 0 or 1");
+  if (t->reserved != 0) return fail(PMP_EINVAL, "reserved must be 0");
   {
-    const long long lds = tile_lds_bytes(t->tile_x, t->tile_yz, t->tile_block,
-                                         c->acc == PMP_ACC_FIX64);
+    const long long lds = tile_lds_bytes(t->tile_x, t->tile_yz);
     if (lds > c->max_lds)
       return fail(PMP_EINVAL, "tile %d x %d x %d needs %lld B of LDS, more than the %d B available",
                   t->tile_x, t->tile_yz, t->tile_yz, lds, c->max_lds);
@@ -1170,7 +1222,8 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
   // candidates: the direct path and a set of tile shapes for the binned path
   std::vector<pmp_tuning> cand;
   const pmp_tuning base = c->tune;
-  auto add = [&](int path, int tx, int tyz, int tb, int lanes, int tgrid) {
+  const bool has_sinks = sinks && sinks->n > 0;
+  auto add = [&](int path, int tx, int tyz, int tb, int lanes, int tgrid, int fuse) {
     pmp_tuning t = base;
     t.deposit_path = path;
     t.tile_x = tx;
@@ -1178,14 +1231,16 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
     t.tile_block = tb;
     t.sn_lanes = lanes;
     t.tile_grid_per_cu = tgrid;
+    t.fuse_apply = fuse;
     cand.push_back(t);
   };
-  add(0, base.tile_x, base.tile_yz, base.tile_block, 64, 0);
-  if (has_sn) add(0, base.tile_x, base.tile_yz, base.tile_block, 16, 0);
+  add(0, base.tile_x, base.tile_yz, base.tile_block, 64, 0, 0);
+  if (has_sn) add(0, base.tile_x, base.tile_yz, base.tile_block, 16, 0, 0);
   const int shapes[][3] = {{64, 4, 128}, {64, 4, 256}, {32, 4, 128}, {32, 8, 256},
-                           {16, 8, 256}, {64, 2, 128}, {16, 4, 128}};
-  for (const auto& sh : shapes) add(1, sh[0], sh[1], sh[2], 64, 0);
-  add(1, 64, 4, 128, 64, 8);
+                           {16, 8, 256}, {64, 2, 128}, {16, 4, 128}, {32, 4, 256}};
+  // the fused apply only applies to steps without sinks
+  for (int fuse = has_sinks ? 0 : 1; fuse >= 0; --fuse)
+    for (const auto& sh : shapes) add(1, sh[0], sh[1], sh[2], 64, 0, fuse);
   // the caller's state is left as it was: candidates run on a copy
   const size_t sbytes = (size_t)c->state_elems * (c->state == PMP_STATE_F32 ? 4 : 8);
   void* work = nullptr;
@@ -1197,8 +1252,8 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     rc = fail(PMP_EDEVICE, "autotune: hipEventCreate failed");
   for (size_t i = 0; i < cand.size() && rc == PMP_OK; ++i) {
-    rc = pmp_set_tuning(c, &cand[i]);
-    if (rc) break;
+    // a shape this device cannot run (LDS) is skipped
+    if (pmp_set_tuning(c, &cand[i]) != PMP_OK) continue;
     if (launch_copy(work, state, (long long)sbytes, s) != hipSuccess) {
       rc = fail(PMP_EDEVICE, "autotune: state copy failed");
       break;

@@ -93,11 +93,23 @@ struct Particles {
 // Tiles covering the padded (ghost-zoned) box of every box: tile (tx,ty,tz)
 // of box b covers padded local cells [tx*TX, (tx+1)*TX) x ... clipped to the
 // padded extent.  Global tile id = tile_prefix[b] + (tz*nty + ty)*ntx + tx.
+// Geometry of one tile, fixed by the layout and the tile shape.
+struct alignas(16) TileGeo {
+  long long boff;  // buffer offset of the tile's box
+  long long soff;  // state offset of the tile's box
+  int p[3];        // padded extent of the box
+  int o[3];        // tile origin, padded-local
+  int ext[3];      // cells of the tile inside the padded box
+  int b;           // box
+  int glo[3];      // global cell of the tile origin
+  int pad;
+};
+
 struct TileGrid {
   int t[3];                       // tile edge per axis (TX, TY, TZ)
   const long long* tile_prefix;   // [nbox+1] device
   const int* tiles_axis;          // [nbox][3] device: tiles per axis
-  const int* tile_box;            // [ntiles] device: box of each tile
+  const TileGeo* geo;             // [ntiles] device
   long long ntiles;
 };
 
@@ -111,6 +123,17 @@ struct SnPk {
   long long remr, reme;  // fixed point: Q(m / V) - N Q(m / (N V)), same for e
   int n;                 // sphere members (-1: host cell only, 0: skipped)
   int ti, tj, tk;        // padded-local remainder cell (ti < 0: none in the box)
+};
+
+// A supernova's share of one tile, prepared for the tile pass: the runs of
+// the tile's S = TY * TZ rows (row s: v = s mod TY, w = s / TY) clipped to
+// the tile, as ua | ub << 8 in tile-local x (0x00ff: none).
+template <int S> struct alignas(16) SnEnt {
+  double vr, ve;         // member share (for fixed point: the quanta's bits)
+  long long remr, reme;  // fixed point: remainder, added at cell tgt
+  int tgt;               // LDS cell of the remainder in this tile, or -1
+  int pad;
+  unsigned short runs[S];
 };
 
 // Member runs of a supernova's sphere rows, stored once per particle by the
@@ -135,7 +158,10 @@ struct BinWork {
   int* cic_off;         // [ntiles + 1]
   int* sn_tmp;           // supernova entries: particle indices
   int* sn_tmp_tile;
-  int* sn_rec;
+  int* sn_rec;           // sorted by tile: particle index
+  int* sn_rec_tile;      // sorted by tile: tile
+  void* sn_ent;          // sorted by tile: SnEnt<S> records
+  long long sn_ent_bytes;
   int* sn_off;          // [ntiles + 1]
   SnPk* sn_pk;          // [n_sn]
   unsigned short* sn_rows;  // [n_sn * kRowCap]
@@ -158,15 +184,19 @@ struct BinWork {
 
 constexpr int kSlice = 4096;
 
-// LDS of one tile workgroup: two accumulator channels of the tile with rows
-// padded to tx + 1 cells, then, per batch of supernova entries, the runs of
-// the tile's tyz^2 rows clipped to the tile and the per-entry values.
-__host__ __device__ constexpr int tile_batch(int block, int slots) {
-  return block < 1024 / slots ? block : 1024 / slots;
+// Bytes of one supernova tile entry for tiles of edge tyz along y and z
+// (a multiple of 16, so that batches of entries copy as 16-byte vectors).
+__host__ __device__ constexpr long long sn_ent_bytes(int tyz) {
+  return (40 + 2ll * tyz * tyz + 15) / 16 * 16;
 }
-__host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz, int block, bool fixed) {
-  return 2ll * (tx + 1) * tyz * tyz * 8 +
-         (long long)tile_batch(block, tyz * tyz) * (tyz * tyz * 2 + 16 + (fixed ? 24 : 0));
+// Supernova entries per batch of the tile pass: about 8 KB of records.
+__host__ __device__ constexpr int tile_sn_batch(int tx, int tyz) {
+  return (void)tx, (int)(8192 / sn_ent_bytes(tyz));
+}
+// LDS of one tile workgroup: two accumulator channels of the tile with rows
+// padded to tx + 1 cells, then one batch of supernova entries.
+__host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz) {
+  return 2ll * (tx + 1) * tyz * tyz * 8 + tile_sn_batch(tx, tyz) * sn_ent_bytes(tyz);
 }
 
 constexpr int kBinChunkCic = 1024;  // CIC particles per level-1 block
@@ -182,9 +212,17 @@ hipError_t launch_cic_direct(const Mesh& M, const Particles& P, void* buf, int b
 // bracket the two halves for the profiler.
 hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
                       const Particles* sn, BinWork& bw, int block, hipStream_t s);
+// state non-null: the step's Steps 3 + 5 are fused in for owned cells at
+// least g from every face of their box (no ghost image reaches them); those
+// cells' buffer entries are left unwritten, and launch_fold_apply finishes
+// the shell cells.
 hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles* cic,
                                const Particles* sn, const BinWork& bw, void* buf,
-                               const pmp_tuning& t, hipStream_t s);
+                               const pmp_tuning& t, void* state, const Limits& L,
+                               hipStream_t s);
+// Steps 2 + 3 + 5 for the shell cells only (after a fused tile pass).
+hipError_t launch_fold_apply(const Mesh& M, void* state, const void* buf, const Limits& L,
+                             hipStream_t s);
 hipError_t launch_sn_direct(const Mesh& M, const Particles& P, void* buf, int lanes,
                             hipStream_t s);
 hipError_t launch_sink_deposit(const Mesh& M, const Particles& P, const void* state,

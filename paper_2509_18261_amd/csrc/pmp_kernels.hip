@@ -77,6 +77,33 @@ __device__ __forceinline__ int find_box(const long long* off, int nbox, long lon
   return lo;
 }
 
+// Box of particle p when it is known to lie in boxes [lo, hi].
+__device__ __forceinline__ int find_box_in(const long long* off, int lo, int hi, long long p) {
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Boxes holding particles [p0, p1) of a block (shared by the block): two
+// searches per block, after which each particle's search is over the few
+// boxes in between.  Call from every thread of the block.
+__device__ __forceinline__ void block_box_range(const long long* off, int nbox, long long p0,
+                                                long long p1, int& b0, int& b1) {
+  __shared__ int sb[2];
+  if (nbox == 1) {
+    b0 = b1 = 0;
+    return;
+  }
+  if (threadIdx.x == 0) sb[0] = find_box(off, nbox, p0);
+  if (threadIdx.x == 1 || (blockDim.x == 1 && threadIdx.x == 0))
+    sb[1] = find_box(off, nbox, max(p0, p1 - 1));
+  __syncthreads();
+  b0 = sb[0];
+  b1 = sb[1];
+}
+
 // Host cell floor(x) of a particle; false for a position outside the box
 // (or NaN), which the caller skips and flags.
 __device__ __forceinline__ bool host_cell(const DevBox& B, double x, double y, double z,
@@ -802,14 +829,132 @@ __global__ __launch_bounds__(kChunk) void k_fold(Mesh M, typename AccT<ACC>::T* 
 
 // ------------------------------------------------------------------ apply
 
+// Limiter counters of one thread, reduced per wavefront before the atomics.
+struct ApplyCounts {
+  unsigned long long touched = 0, bind = 0, lam = 0, fall = 0;
+  bool bad = false;
+};
+
+// Steps 3 + 5 for one owned cell, in double precision: st points at the
+// cell's rho, the other state fields follow at multiples of stride; (Dr, q,
+// DE, K) is the folded buffer.  Returns eta = Kl / K (1 when K = 0).
+template <class S>
+__device__ __forceinline__ double apply_cell(S* st, long long stride, double Dr, double qx,
+                                             double qy, double qz, double DE, double K,
+                                             const Limits& L, ApplyCounts& cnt) {
+  const double rho = (double)st[0];
+  const double px = (double)st[stride];
+  const double py = (double)st[2 * stride];
+  const double pz = (double)st[3 * stride];
+  const double E = (double)st[4 * stride];
+  const double Kl = limited_removal(K, rho, L);
+  if (K > 0.0) {
+    ++cnt.touched;
+    if (Kl < K) ++cnt.bind;
+  }
+  const double f = 1.0 - Kl / rho;
+  const double rho1 = f * rho + Dr;
+  double E1 = f * E + DE;
+  const double p0x = f * px, p0y = f * py, p0z = f * pz;
+  double emin = 0.0;
+  if (L.eint_mode == 1) {
+    const double eint0 = E - ((px * px + py * py) + pz * pz) / (2.0 * rho);
+    emin = rho1 * (eint0 / rho);
+  }
+  const double Kc = (2.0 * rho1) * (E1 - emin);
+  const double sx = p0x + qx, sy = p0y + qy, sz = p0z + qz;
+  const double g1 = ((sx * sx + sy * sy) + sz * sz) - Kc;
+  const double pp = (p0x * p0x + p0y * p0y) + p0z * p0z;
+  const double g0 = pp - Kc;
+  double lam;
+  if (g1 <= 0.0) {
+    lam = 1.0;
+  } else if (g0 <= 0.0) {
+    const double qq = (qx * qx + qy * qy) + qz * qz;
+    const double pq = (p0x * qx + p0y * qy) + p0z * qz;
+    const double disc = pq * pq - qq * g0;
+    const double sq = sqrt(disc);
+    lam = (pq > 0.0) ? (-g0) / (pq + sq) : (sq - pq) / qq;
+    if (lam > 1.0) lam = 1.0;
+    if (lam < 0.0) lam = 0.0;
+  } else {
+    lam = 0.0;
+    E1 = emin + pp / (2.0 * rho1);
+    ++cnt.fall;
+  }
+  if (lam < 1.0) ++cnt.lam;
+  if (!(rho > 0.0) || !isfinite(E1) || !isfinite(rho1)) cnt.bad = true;
+  st[0] = (S)rho1;
+  st[stride] = (S)(p0x + lam * qx);
+  st[2 * stride] = (S)(p0y + lam * qy);
+  st[3 * stride] = (S)(p0z + lam * qz);
+  st[4 * stride] = (S)E1;
+  return (K > 0.0) ? Kl / K : 1.0;
+}
+
+// One atomic per wavefront and counter (call from every lane of the wave).
+__device__ __forceinline__ void flush_counts(const Mesh& M, ApplyCounts& cnt) {
+  const unsigned long long touched = group_sum<kWave>(cnt.touched);
+  const unsigned long long bind = group_sum<kWave>(cnt.bind);
+  const unsigned long long lamc = group_sum<kWave>(cnt.lam);
+  const unsigned long long fall = group_sum<kWave>(cnt.fall);
+  const unsigned long long nbad = group_sum<kWave>((unsigned long long)cnt.bad);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (touched) atomicAdd(&M.status->touched, touched);
+    if (bind) atomicAdd(&M.status->bind, bind);
+    if (lamc) atomicAdd(&M.status->lam, lamc);
+    if (fall) {
+      atomicAdd(&M.status->fall, fall);
+      atomicOr(&M.status->flags, PMP_FLAG_FLOOR);
+    }
+    if (nbad) atomicOr(&M.status->flags, PMP_FLAG_NAN);
+  }
+}
+
+// Steps 2 + 3 + 5 for the shell cells of a fused step: each shell cell
+// gathers its ghost images in the plan's order (as k_fold) and is applied
+// at once; the interior cells were applied by the tile pass.
+template <int ACC, int F>
+__global__ __launch_bounds__(kChunk) void k_fold_apply(Mesh M, void* __restrict__ state,
+                                                      const typename AccT<ACC>::T* __restrict__ buf,
+                                                      Limits L) {
+  using Sum = SumT<ACC>;
+  using T = typename AccT<ACC>::T;
+  const int g = M.ghost;
+  ApplyCounts cnt;
+  for (long long ch = blockIdx.x; ch < M.n_fold_chunks; ch += gridDim.x) {
+    const int2 C = M.fold_chunks[ch];
+    const int b = C.x;
+    const DevBox B = M.all_boxes[b];
+    const int t = C.y + (int)threadIdx.x;
+    if (t >= B.shell) continue;
+    int i, j, k;
+    shell_cell(B.n, g, (unsigned)t, i, j, k);
+    const long long dst = B.boff + ((long long)(k + g) * B.p[1] + (j + g)) * B.p[0] + (i + g);
+    Sum acc[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) acc[f] = (Sum)buf[dst + f * B.npad];
+    fold_gather<ACC, F>(M, b, i, j, k, buf, acc);
+    // the folded values as the buffer would hold them
+    double v[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v[q] = M.slot[q] >= 0 ? to_f64((T)acc[M.slot[q]]) : 0.0;
+    const long long si = B.soff + ((long long)k * B.n[1] + j) * B.n[0] + i;
+    if (M.state == PMP_STATE_F32)
+      apply_cell((float*)state + si, B.ncell, v[0], v[1], v[2], v[3], v[4], v[5], L, cnt);
+    else
+      apply_cell((double*)state + si, B.ncell, v[0], v[1], v[2], v[3], v[4], v[5], L, cnt);
+  }
+  flush_counts(M, cnt);
+}
+
 // Steps 3 + 5 per owned cell, in double precision (see pmp_apply).
 template <class S, int ACC>
 __global__ __launch_bounds__(kChunk) void k_apply(Mesh M, S* __restrict__ state,
                                                  const typename AccT<ACC>::T* __restrict__ buf,
                                                  Limits L, double* __restrict__ eta) {
   const int g = M.ghost;
-  unsigned long long touched = 0, bind = 0, lamc = 0, fall = 0;
-  bool bad = false;
+  ApplyCounts cnt;
   // absent channels are identically zero (uniform branches)
   const int s0 = M.slot[0], s1 = M.slot[1], s2 = M.slot[2], s3 = M.slot[3], s4 = M.slot[4],
             s5 = M.slot[5];
@@ -827,12 +972,6 @@ __global__ __launch_bounds__(kChunk) void k_apply(Mesh M, S* __restrict__ state,
     const int j = (int)(row - kq * ny);
     const int k = (int)kq;
     const long long bi = B.boff + ((long long)(k + g) * B.p[1] + (j + g)) * B.p[0] + (i + g);
-    S* st = state + B.soff + c;
-    const double rho = (double)st[0];
-    const double px = (double)st[B.ncell];
-    const double py = (double)st[2 * B.ncell];
-    const double pz = (double)st[3 * B.ncell];
-    const double E = (double)st[4 * B.ncell];
     const long long np = B.npad;
     const double Dr = s0 >= 0 ? to_f64(buf[bi + s0 * np]) : 0.0;
     const double qx = s1 >= 0 ? to_f64(buf[bi + s1 * np]) : 0.0;
@@ -840,66 +979,10 @@ __global__ __launch_bounds__(kChunk) void k_apply(Mesh M, S* __restrict__ state,
     const double qz = s3 >= 0 ? to_f64(buf[bi + s3 * np]) : 0.0;
     const double DE = s4 >= 0 ? to_f64(buf[bi + s4 * np]) : 0.0;
     const double K = s5 >= 0 ? to_f64(buf[bi + s5 * np]) : 0.0;
-    const double Kl = limited_removal(K, rho, L);
-    if (K > 0.0) {
-      ++touched;
-      if (Kl < K) ++bind;
-    }
-    const double f = 1.0 - Kl / rho;
-    const double rho1 = f * rho + Dr;
-    double E1 = f * E + DE;
-    const double p0x = f * px, p0y = f * py, p0z = f * pz;
-    double emin = 0.0;
-    if (L.eint_mode == 1) {
-      const double eint0 = E - ((px * px + py * py) + pz * pz) / (2.0 * rho);
-      emin = rho1 * (eint0 / rho);
-    }
-    const double Kc = (2.0 * rho1) * (E1 - emin);
-    const double sx = p0x + qx, sy = p0y + qy, sz = p0z + qz;
-    const double g1 = ((sx * sx + sy * sy) + sz * sz) - Kc;
-    const double pp = (p0x * p0x + p0y * p0y) + p0z * p0z;
-    const double g0 = pp - Kc;
-    double lam;
-    if (g1 <= 0.0) {
-      lam = 1.0;
-    } else if (g0 <= 0.0) {
-      const double qq = (qx * qx + qy * qy) + qz * qz;
-      const double pq = (p0x * qx + p0y * qy) + p0z * qz;
-      const double disc = pq * pq - qq * g0;
-      const double sq = sqrt(disc);
-      lam = (pq > 0.0) ? (-g0) / (pq + sq) : (sq - pq) / qq;
-      if (lam > 1.0) lam = 1.0;
-      if (lam < 0.0) lam = 0.0;
-    } else {
-      lam = 0.0;
-      E1 = emin + pp / (2.0 * rho1);
-      ++fall;
-    }
-    if (lam < 1.0) ++lamc;
-    if (!(rho > 0.0) || !isfinite(E1) || !isfinite(rho1)) bad = true;
-    st[0] = (S)rho1;
-    st[B.ncell] = (S)(p0x + lam * qx);
-    st[2 * B.ncell] = (S)(p0y + lam * qy);
-    st[3 * B.ncell] = (S)(p0z + lam * qz);
-    st[4 * B.ncell] = (S)E1;
-    if (eta) eta[M.owned_prefix[b] + c] = (K > 0.0) ? Kl / K : 1.0;
+    const double e = apply_cell(state + B.soff + c, B.ncell, Dr, qx, qy, qz, DE, K, L, cnt);
+    if (eta) eta[M.owned_prefix[b] + c] = e;
   }
-  // one atomic per wavefront and counter
-  touched = group_sum<kWave>(touched);
-  bind = group_sum<kWave>(bind);
-  lamc = group_sum<kWave>(lamc);
-  fall = group_sum<kWave>(fall);
-  const unsigned long long nbad = group_sum<kWave>((unsigned long long)bad);
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    if (touched) atomicAdd(&M.status->touched, touched);
-    if (bind) atomicAdd(&M.status->bind, bind);
-    if (lamc) atomicAdd(&M.status->lam, lamc);
-    if (fall) {
-      atomicAdd(&M.status->fall, fall);
-      atomicOr(&M.status->flags, PMP_FLAG_FLOOR);
-    }
-    if (nbad) atomicOr(&M.status->flags, PMP_FLAG_NAN);
-  }
+  flush_counts(M, cnt);
 }
 
 
@@ -1052,9 +1135,11 @@ __global__ __launch_bounds__(256) void k_l1_cic(Mesh M, TileGrid T, Particles P,
   __syncthreads();
   const long long p0 = (long long)blockIdx.x * kBinChunkCic;
   const long long p1 = min(p0 + kBinChunkCic, P.n);
+  int bb0, bb1;
+  block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
   bool outside = false, nan = false, full = false;
   for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-    const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
+    const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
     const DevBox B = M.boxes[b];
     const double x = P.x[p], y = P.y[p], z = P.z[p], m = P.a[p];
     int hc[3];
@@ -1115,131 +1200,198 @@ __device__ __forceinline__ bool sn_has_table(const Sphere& S) {
   return S.nrows <= kRowCap && S.hi[0] - S.lo[0] < 255;
 }
 
-template <bool SCATTER>
-__global__ __launch_bounds__(256) void k_l1_sn(Mesh M, TileGrid T, Particles P, int shift,
-                                              int nb, int* __restrict__ hist, int nblk,
-                                              SnPk* __restrict__ pk,
-                                              unsigned short* __restrict__ sn_rows,
-                                              int* __restrict__ tmp,
-                                              int* __restrict__ tmp_tile, long long cap) {
-  constexpr int L = 16;
+// Level 1, supernovae, histogram pass: one lane per particle (blocks of one
+// wavefront, kBinChunkSn particles).  The lane walks its sphere's candidate
+// rows in (k, j) order: it counts the members N (-1 when no centre lies
+// within r and the host cell takes the deposit; 0 when the particle is
+// skipped), finds the fixed-point remainder cell (host if a member, else the
+// first member in (k, j, i) order) and fills its row table through an LDS
+// chunk written out as 16-byte vectors; then it writes the particle's SnPk
+// and counts it into the buckets of every tile its sphere touches.
+__global__ __launch_bounds__(kBinChunkSn) void k_l1_sn_hist(Mesh M, TileGrid T, Particles P,
+                                                            int shift, int nb,
+                                                            int* __restrict__ hist, int nblk,
+                                                            SnPk* __restrict__ pk,
+                                                            unsigned short* __restrict__ sn_rows) {
+  constexpr int CH = 32;  // rows per staged chunk
   extern __shared__ int h[];
+  __shared__ unsigned short st[CH][kBinChunkSn];
   const int g = M.ghost;
   const int col = hist_col(blockIdx.x, nblk);
-  for (int c = threadIdx.x; c < nb; c += blockDim.x)
-    h[c] = SCATTER ? hist[(long long)c * nblk + col] - hist[0] : 0;
-  __syncthreads();
+  for (int c = threadIdx.x; c < nb; c += blockDim.x) h[c] = 0;
   const long long p0 = (long long)blockIdx.x * kBinChunkSn;
   const long long p1 = min(p0 + kBinChunkSn, P.n);
-  if (!SCATTER) {
-    const int lane = threadIdx.x % L;
-    for (long long p = p0 + threadIdx.x / L; p < p1; p += blockDim.x / L) {
-      const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
-      const DevBox B = M.boxes[b];
-      const double x = P.x[p], y = P.y[p], z = P.z[p];
-      const double m = P.b[p], e = P.c[p], r = P.r[p];
-      SnPk R;
-      R.x = x;
-      R.y = y;
-      R.z = z;
-      R.r = r;
-      R.n = 0;
-      R.ti = R.tj = R.tk = -1;
-      R.vr = R.ve = 0.0;
-      R.remr = R.reme = 0;
-      int hc[3];
-      unsigned flag = 0;
-      if (!host_cell(B, x, y, z, hc)) flag = PMP_FLAG_OUTSIDE;
-      else if (!isfinite(m) || !isfinite(e) || !isfinite(r) || !(r >= 0.0)) flag = PMP_FLAG_NAN;
-      else if (floor(r + 0.5) > (double)g) flag = PMP_FLAG_REACH;
-      if (flag) {
-        if (lane == 0) {
-          raise_flag(M.status, flag);
-          pk[p] = R;
+  int bb0, bb1;
+  block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
+  const long long p = p0 + threadIdx.x;
+  const bool live = p < p1;
+  const int b = !live ? 0 : (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
+  const DevBox B = M.boxes[b];
+  double x = 0.5, y = 0.5, z = 0.5, m = 0.0, e = 0.0, r = 0.0;
+  if (live) {
+    x = P.x[p];
+    y = P.y[p];
+    z = P.z[p];
+    m = P.b[p];
+    e = P.c[p];
+    r = P.r[p];
+  }
+  SnPk R;
+  R.x = x;
+  R.y = y;
+  R.z = z;
+  R.r = r;
+  R.n = 0;
+  R.ti = R.tj = R.tk = -1;
+  R.vr = R.ve = 0.0;
+  R.remr = R.reme = 0;
+  int hc[3] = {0, 0, 0};
+  unsigned flag = 0;
+  if (live) {
+    if (!host_cell(B, x, y, z, hc)) flag = PMP_FLAG_OUTSIDE;
+    else if (!isfinite(m) || !isfinite(e) || !isfinite(r) || !(r >= 0.0)) flag = PMP_FLAG_NAN;
+    else if (floor(r + 0.5) > (double)g) flag = PMP_FLAG_REACH;
+  }
+  const bool ok = live && !flag;
+  Sphere Sp;
+  sphere_init(Sp, x, y, z, ok ? r : 0.0);
+  const int nrows = ok ? Sp.nrows : 0;
+  const bool table = ok && sn_has_table(Sp);
+  unsigned short* rt = sn_rows + (long long)kRowCap * (live ? p : 0);
+  // a row whose rounded dy^2 + dz^2 exceeds r^2 holds no member: the
+  // rounded test value of each of its cells is at least that sum (the terms
+  // are non-negative and rounding is monotone)
+  int cnt = 0, key = 0x7fffffff, hm = 0, out = 0;
+  int maxrows = nrows;
+  maxrows = group_max<kWave>(maxrows);
+  int jj = 0, kk = 0;  // row t = jj + cy * kk
+  for (int t0 = 0; t0 < maxrows; t0 += CH) {
+    for (int dt = 0; dt < CH; ++dt) {
+      const int t = t0 + dt;
+      unsigned short v = 0x00ff;
+      if (t < nrows) {
+        const int j = Sp.lo[1] + jj, k = Sp.lo[2] + kk;
+        const double dy = ((double)j + 0.5) - Sp.y, dz = ((double)k + 0.5) - Sp.z;
+        if (dy * dy + dz * dz <= Sp.r2) {
+          int a, bb;
+          row_members(Sp, j, k, a, bb);
+          if (a <= bb) {
+            v = (unsigned short)((a - Sp.lo[0]) | ((bb - Sp.lo[0]) << 8));
+            cnt += bb - a + 1;
+            if (key == 0x7fffffff) key = (t << 12) | (a - Sp.lo[0]);
+            hm |= (j == hc[1] && k == hc[2] && a <= hc[0] && hc[0] <= bb);
+            long long idx;
+            out |= !pad_index(B, g, a, j, k, idx) || !pad_index(B, g, bb, j, k, idx);
+          }
         }
-        continue;
-      }
-      Sphere Sp;
-      sphere_init(Sp, x, y, z, r);
-      int N, first, hostm, outside;
-      sphere_count<L>(Sp, B, g, hc, lane, N, first, hostm, outside,
-                      sn_has_table(Sp) ? sn_rows + (long long)kRowCap * p : nullptr);
-      if (N == 0) N = -1;
-      // member share, and for fixed point the remainder that makes the
-      // deposited total exactly Q(m / V)
-      const int NN = N < 0 ? 1 : N;
-      const double cr = m / ((double)NN * M.V), ce = e / ((double)NN * M.V);
-      bool ok = true;
-      if (M.acc == PMP_ACC_FIX64) {
-        long long qr = 0, qe = 0, Qr = 0, Qe = 0;
-        ok = quantise(cr, qr) && quantise(ce, qe) && quantise(m / M.V, Qr) &&
-             quantise(e / M.V, Qe);
-        R.vr = __longlong_as_double(qr);
-        R.ve = __longlong_as_double(qe);
-        R.remr = Qr - (long long)NN * qr;
-        R.reme = Qe - (long long)NN * qe;
-      } else {
-        R.vr = cr;
-        R.ve = ce;
-      }
-      if (!ok) {
-        if (lane == 0) {
-          raise_flag(M.status, PMP_FLAG_OVERFLOW);
-          pk[p] = R;  // n = 0: skipped
+        if (++jj == Sp.cy) {
+          jj = 0;
+          ++kk;
         }
-        continue;
       }
-      R.n = N;
-      int ti = hc[0], tj = hc[1], tk = hc[2];
-      if (N > 0 && !hostm) sphere_key_cell(Sp, first, ti, tj, tk);
-      long long idx;
-      if (pad_index(B, g, ti, tj, tk, idx)) {
-        R.ti = ti - B.lo[0] + g;
-        R.tj = tj - B.lo[1] + g;
-        R.tk = tk - B.lo[2] + g;
-      }
-      if (lane == 0) {
-        if (outside) raise_flag(M.status, PMP_FLAG_REACH);
-        pk[p] = R;
-      }
-      int tlo[3], thi[3];
-      if (!sn_tiles(M, T, B, x, y, z, r, N, tlo, thi)) continue;
-      const int nx = thi[0] - tlo[0] + 1, ny = thi[1] - tlo[1] + 1;
-      const int nt = nx * ny * (thi[2] - tlo[2] + 1);
-      for (int t = lane; t < nt; t += L) {
-        const int tz = tlo[2] + t / (nx * ny), rem = t % (nx * ny);
-        const int id = (int)tile_id(T, b, tlo[0] + rem % nx, tlo[1] + rem / nx, tz);
-        atomicAdd(h + (id >> shift), 1);
-      }
+      st[dt][threadIdx.x] = v;
     }
-    __syncthreads();
-    for (int c = threadIdx.x; c < nb; c += blockDim.x)
-      hist[(long long)c * nblk + col] = h[c];
-  } else {
-    bool full = false;
-    for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-      const SnPk& R = pk[p];
-      const int N = R.n;
-      if (N == 0) continue;
-      const int b = (M.nbox == 1) ? 0 : find_box(P.box_off, M.nbox, p);
-      const DevBox B = M.boxes[b];
-      int tlo[3], thi[3];
-      if (!sn_tiles(M, T, B, R.x, R.y, R.z, R.r, N, tlo, thi)) continue;
+    // the lane's own 32 entries, out as four 16-byte stores (own table only)
+    if (table && t0 < nrows) {
+      unsigned w[CH / 2];
+#pragma unroll
+      for (int q = 0; q < CH / 2; ++q)
+        w[q] = (unsigned)st[2 * q][threadIdx.x] | ((unsigned)st[2 * q + 1][threadIdx.x] << 16);
+      uint4* dst = reinterpret_cast<uint4*>(rt + t0);
+#pragma unroll
+      for (int q = 0; q < CH / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+    }
+  }
+  int N = cnt;
+  if (ok && N == 0) N = -1;
+  bool okq = ok;
+  if (ok) {
+    // member share, and for fixed point the remainder that makes the
+    // deposited total exactly Q(m / V)
+    const int NN = N < 0 ? 1 : N;
+    const double cr = m / ((double)NN * M.V), ce = e / ((double)NN * M.V);
+    if (M.acc == PMP_ACC_FIX64) {
+      long long qr = 0, qe = 0, Qr = 0, Qe = 0;
+      okq = quantise(cr, qr) && quantise(ce, qe) && quantise(m / M.V, Qr) &&
+            quantise(e / M.V, Qe);
+      R.vr = __longlong_as_double(qr);
+      R.ve = __longlong_as_double(qe);
+      R.remr = Qr - (long long)NN * qr;
+      R.reme = Qe - (long long)NN * qe;
+    } else {
+      R.vr = cr;
+      R.ve = ce;
+    }
+    if (!okq) flag = PMP_FLAG_OVERFLOW;
+  }
+  if (okq) {
+    R.n = N;
+    int ti = hc[0], tj = hc[1], tk = hc[2];
+    if (N > 0 && !hm) sphere_key_cell(Sp, key, ti, tj, tk);
+    long long idx;
+    if (pad_index(B, g, ti, tj, tk, idx)) {
+      R.ti = ti - B.lo[0] + g;
+      R.tj = tj - B.lo[1] + g;
+      R.tk = tk - B.lo[2] + g;
+    }
+    if (out) raise_flag(M.status, PMP_FLAG_REACH);
+  }
+  if (flag) raise_flag(M.status, flag);
+  if (live) pk[p] = R;
+  __syncthreads();  // h cleared
+  if (okq) {
+    int tlo[3], thi[3];
+    if (sn_tiles(M, T, B, x, y, z, r, N, tlo, thi))
       for (int tz = tlo[2]; tz <= thi[2]; ++tz)
         for (int ty = tlo[1]; ty <= thi[1]; ++ty)
-          for (int tx = tlo[0]; tx <= thi[0]; ++tx) {
-            const int id = (int)tile_id(T, b, tx, ty, tz);
-            const int pos = atomicAdd(h + (id >> shift), 1);
-            if (pos < cap) {
-              tmp[pos] = (int)p;
-              tmp_tile[pos] = id;
-            } else {
-              full = true;
-            }
-          }
-    }
-    if (full) raise_flag(M.status, PMP_FLAG_CAPACITY);
+          for (int tx = tlo[0]; tx <= thi[0]; ++tx)
+            atomicAdd(h + ((int)tile_id(T, b, tx, ty, tz) >> shift), 1);
   }
+  __syncthreads();
+  for (int c = threadIdx.x; c < nb; c += blockDim.x) hist[(long long)c * nblk + col] = h[c];
+}
+
+// Level 1, supernovae, scatter pass: one thread per particle writes its
+// (particle, tile) entries at the positions the scanned histograms give.
+__global__ __launch_bounds__(kBinChunkSn) void k_l1_sn_scatter(Mesh M, TileGrid T, Particles P,
+                                                               int shift, int nb,
+                                                               int* __restrict__ hist, int nblk,
+                                                               const SnPk* __restrict__ pk,
+                                                               int* __restrict__ tmp,
+                                                               int* __restrict__ tmp_tile,
+                                                               long long cap) {
+  extern __shared__ int h[];
+  const int col = hist_col(blockIdx.x, nblk);
+  for (int c = threadIdx.x; c < nb; c += blockDim.x)
+    h[c] = hist[(long long)c * nblk + col] - hist[0];
+  const long long p0 = (long long)blockIdx.x * kBinChunkSn;
+  const long long p1 = min(p0 + kBinChunkSn, P.n);
+  int bb0, bb1;
+  block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
+  __syncthreads();
+  bool full = false;
+  for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    const SnPk& R = pk[p];
+    const int N = R.n;
+    if (N == 0) continue;
+    const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
+    const DevBox B = M.boxes[b];
+    int tlo[3], thi[3];
+    if (!sn_tiles(M, T, B, R.x, R.y, R.z, R.r, N, tlo, thi)) continue;
+    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
+      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
+        for (int tx = tlo[0]; tx <= thi[0]; ++tx) {
+          const int id = (int)tile_id(T, b, tx, ty, tz);
+          const int pos = atomicAdd(h + (id >> shift), 1);
+          if (pos < cap) {
+            tmp[pos] = (int)p;
+            tmp_tile[pos] = id;
+          } else {
+            full = true;
+          }
+        }
+  }
+  if (full) raise_flag(M.status, PMP_FLAG_CAPACITY);
 }
 
 // Level 2: one workgroup per coarse bucket sorts the bucket's records by
@@ -1355,8 +1507,9 @@ __global__ __launch_bounds__(256) void k_l2_scatter(L2Geom G, int kind,
                                                    const int* __restrict__ hist2,
                                                    const Rec* __restrict__ tmp,
                                                    const int* __restrict__ tmp_tile,
-                                                   Rec* __restrict__ rec, int* __restrict__ off,
-                                                   long long cap) {
+                                                   Rec* __restrict__ rec,
+                                                   int* __restrict__ rec_tile,
+                                                   int* __restrict__ off, long long cap) {
   extern __shared__ int h[];
   const int nf_max = 1 << G.shift;
   const int q_begin = slice_base[kind * G.nb], q_end = slice_base[(kind + 1) * G.nb];
@@ -1378,10 +1531,103 @@ __global__ __launch_bounds__(256) void k_l2_scatter(L2Geom G, int kind,
     }
     __syncthreads();
     for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-      const int pos = atomicAdd(h + (tmp_tile[e] - t0), 1);
-      if (pos < cap) rec[pos] = tmp[e];
+      const int tl = tmp_tile[e];
+      const int pos = atomicAdd(h + (tl - t0), 1);
+      if (pos < cap) {
+        rec[pos] = tmp[e];
+        if (rec_tile) rec_tile[pos] = tl;
+      }
     }
     __syncthreads();
+  }
+}
+
+// One thread per sorted supernova entry (particle p in tile t): the share,
+// the fixed-point remainder and its cell when the cell is in t, and the runs
+// of t's rows clipped to t (from the particle's row table, or found row by
+// row for a sphere too large for one).
+template <int TYZ>
+__global__ __launch_bounds__(256) void k_sn_ent(TileGrid T, const int* __restrict__ soff,
+                                               long long cap, const int* __restrict__ sidx,
+                                               const int* __restrict__ stile,
+                                               const SnPk* __restrict__ pk,
+                                               const unsigned short* __restrict__ rows,
+                                               SnEnt<TYZ * TYZ>* __restrict__ ent) {
+  constexpr int TY = TYZ, S = TYZ * TYZ;
+  constexpr int YSH = (TYZ == 2) ? 1 : (TYZ == 4) ? 2 : 3;
+  const int TXP = T.t[0] + 1;
+  const long long n = min((long long)soff[T.ntiles], cap);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int p = sidx[e];
+    const TileGeo G = T.geo[stile[e]];
+    const SnPk R = pk[p];
+    const int xlo = G.glo[0], ylo = G.glo[1], zlo = G.glo[2];
+    SnEnt<S> E;
+    E.vr = R.vr;
+    E.ve = R.ve;
+    E.remr = R.remr;
+    E.reme = R.reme;
+    E.pad = 0;
+    {
+      const int lu = R.ti - G.o[0], lv = R.tj - G.o[1], lw = R.tk - G.o[2];
+      const bool in = R.ti >= 0 && (unsigned)lu < (unsigned)G.ext[0] &&
+                      (unsigned)lv < (unsigned)G.ext[1] && (unsigned)lw < (unsigned)G.ext[2];
+      E.tgt = in ? (lw * TY + lv) * TXP + lu : -1;
+    }
+    if (R.n < 0) {
+      // host cell only
+      const int hi = (int)floor(R.x), hj = (int)floor(R.y), hk = (int)floor(R.z);
+#pragma unroll
+      for (int sl = 0; sl < S; ++sl) {
+        const int v = sl & (TY - 1), w = sl >> YSH;
+        const int u = hi - xlo;
+        const bool on = (ylo + v == hj) && (zlo + w == hk) && (unsigned)u < (unsigned)G.ext[0];
+        E.runs[sl] = on ? (unsigned short)(u | (u << 8)) : (unsigned short)0x00ff;
+      }
+    } else {
+      Sphere Sp;
+      sphere_init(Sp, R.x, R.y, R.z, R.r);
+      if (sn_has_table(Sp)) {
+        const unsigned short* rt = rows + (long long)kRowCap * p;
+        // the row-table entries of the tile's rows, loaded together in
+        // groups of up to 16, then clipped to the tile
+        constexpr int GS = S < 16 ? S : 16;
+#pragma unroll
+        for (int g0 = 0; g0 < S; g0 += GS) {
+          unsigned raw[GS];
+#pragma unroll
+          for (int sl = 0; sl < GS; ++sl) {
+            const int v = (g0 + sl) & (TY - 1), w = (g0 + sl) >> YSH;
+            const int j = ylo + v, k = zlo + w;
+            const bool cand = v < G.ext[1] && w < G.ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] &&
+                              k >= Sp.lo[2] && k <= Sp.hi[2];
+            raw[sl] = cand ? rt[(j - Sp.lo[1]) + Sp.cy * (k - Sp.lo[2])] : 0x00ffu;
+          }
+#pragma unroll
+          for (int sl = 0; sl < GS; ++sl) {
+            const int ua = max(Sp.lo[0] + (int)(raw[sl] & 255u) - xlo, 0);
+            const int ub = min(Sp.lo[0] + (int)(raw[sl] >> 8) - xlo, G.ext[0] - 1);
+            E.runs[g0 + sl] = (ua <= ub) ? (unsigned short)(ua | (ub << 8))
+                                         : (unsigned short)0x00ff;
+          }
+        }
+      } else {
+#pragma unroll 1
+        for (int sl = 0; sl < S; ++sl) {
+          const int v = sl & (TY - 1), w = sl >> YSH;
+          const int j = ylo + v, k = zlo + w;
+          int a = 1, bb = 0;
+          if (v < G.ext[1] && w < G.ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] &&
+              k >= Sp.lo[2] && k <= Sp.hi[2])
+            row_members(Sp, j, k, a, bb);
+          const int ua = max(a - xlo, 0), ub = min(bb - xlo, G.ext[0] - 1);
+          E.runs[sl] = (a <= bb && ua <= ub) ? (unsigned short)(ua | (ub << 8))
+                                             : (unsigned short)0x00ff;
+        }
+      }
+    }
+    ent[e] = E;
   }
 }
 
@@ -1451,38 +1697,36 @@ template <> __device__ __forceinline__ long long from_lds<long long>(unsigned lo
 }
 template <class T> __device__ __forceinline__ T from_lds(double v) { return (T)v; }
 
-// One workgroup per work unit (a whole tile, or one chunk of a split tile).
-// Phase A, one thread per entry: CIC entries deposit straight into the LDS
-// accumulators; each supernova entry loads its particle's record and the
-// row-table entries of the tile's TYZ x TYZ rows (independent loads, issued
-// together) and leaves the runs clipped to the tile in LDS.  Phase B, one
-// thread per (supernova entry, tile row): adds the run's cells.  Then every
-// present channel of every cell of the tile is stored once (channels without
-// sources as zero).  Membership, shares and fixed-point remainders are the
-// same as in the direct kernels.
+// One workgroup per work unit (a whole tile, or one chunk of a split tile):
+// CIC entries one per thread, supernova work one thread per (entry, tile
+// row) adding the row's run from the entry's record; every addition goes to
+// the LDS accumulators.  Then every present channel of every cell of the
+// tile is stored once (channels without sources as zero).  Membership,
+// shares and fixed-point remainders are the same as in the direct kernels.
 template <int ACC, int TYZ>
 __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
                                                       const int* __restrict__ coff,
                                                       const double4* __restrict__ crec,
                                                       long long ccap,
                                                       const int* __restrict__ soff,
-                                                      const int* __restrict__ sidx,
-                                                      const SnPk* __restrict__ pk,
-                                                      long long scap,
-                                                      const unsigned short* __restrict__ rows,
-                                                      int cc, int cs,
+                                                      const SnEnt<TYZ * TYZ>* __restrict__ ent,
+                                                      long long scap, int cc, int cs,
                                                       const int* __restrict__ heavy_base,
                                                       const int2* __restrict__ heavy_unit,
                                                       const int* __restrict__ heavy_count,
                                                       int* __restrict__ arrive,
                                                       void* __restrict__ partial_v,
                                                       long long slot_cap,
-                                                      typename AccT<ACC>::T* __restrict__ buf) {
+                                                      typename AccT<ACC>::T* __restrict__ buf,
+                                                      void* __restrict__ state, Limits L) {
   using OutT = typename AccT<ACC>::T;
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
   using LT = typename LdsT<FIXED>::T;
   constexpr int TY = TYZ, TZ = TYZ, S = TYZ * TYZ;
+  ApplyCounts cnt;
+  const int g = M.ghost;
   constexpr int YSH = (TYZ == 2) ? 1 : (TYZ == 4) ? 2 : 3;
+  constexpr int SSH = 2 * YSH;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_last;
   LT* partial = reinterpret_cast<LT*>(partial_v);
@@ -1492,49 +1736,35 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
   // banks, so lanes working on neighbouring rows do not conflict
   const int TXP = TX + 1;
   const int lcells = TXP * TY * TZ;
-  const int NB = tile_batch(blockDim.x, S);
   LT* a0 = reinterpret_cast<LT*>(smem);
   LT* a4 = a0 + lcells;
-  double* bval = reinterpret_cast<double*>(a4 + lcells);  // [NB][2] shares
-  long long* brem = reinterpret_cast<long long*>(bval + 2 * NB);  // [NB][2] (fixed)
-  int* btgt = reinterpret_cast<int*>(brem + (FIXED ? 2 * NB : 0));  // [NB] (fixed)
-  unsigned short* bruns = reinterpret_cast<unsigned short*>(btgt + (FIXED ? NB : 0));
-  const int g = M.ghost;
-  // work units: every tile that is not split, whole, in tile order; then
-  // the chunks of split tiles
+  // the current batch of the tile's supernova records, copied from global
+  SnEnt<S>* bent = reinterpret_cast<SnEnt<S>*>(a4 + lcells);
+  const int NB = tile_sn_batch(TX, TYZ);
+  // work units: the chunks of split tiles first (the longest units), then
+  // every other tile whole, in tile order
   const long long nheavy = min((long long)*heavy_count, slot_cap);
   for (long long unit = blockIdx.x; unit < T.ntiles + nheavy; unit += gridDim.x) {
     int tile;
     int chunk = 0, base = -1;
-    if (unit < T.ntiles) {
-      tile = (int)unit;
-      if (heavy_base[tile] >= 0) continue;
-    } else {
-      const int2 hu = heavy_unit[unit - T.ntiles];
+    if (unit < nheavy) {
+      const int2 hu = heavy_unit[unit];
       if (hu.x < 0) continue;
       tile = hu.x;
       chunk = hu.y;
       base = heavy_base[tile];
+    } else {
+      tile = (int)(unit - nheavy);
+      if (heavy_base[tile] >= 0) continue;
     }
-    const int b = T.tile_box[tile];
-    const DevBox B = M.boxes[b];
-    const int* ta = T.tiles_axis + 3 * b;
-    // tiles per box < 2^31: 32-bit coordinates
-    const unsigned lt = (unsigned)(tile - T.tile_prefix[b]);
-    const unsigned ntx = (unsigned)ta[0], nty = (unsigned)ta[1];
-    const unsigned rr = lt / ntx;
-    const int tx = (int)(lt - rr * ntx);
-    const unsigned tzq = rr / nty;
-    const int ty = (int)(rr - tzq * nty), tz = (int)tzq;
-    const int o[3] = {tx * TX, ty * TY, tz * TZ};
-    const int ext[3] = {min(TX, B.p[0] - o[0]), min(TY, B.p[1] - o[1]), min(TZ, B.p[2] - o[2])};
+    const TileGeo G = T.geo[tile];
+    long long e0, e1, s0, s1;
+    tile_entries(coff, ccap, tile, e0, e1);
+    tile_entries(soff, scap, tile, s0, s1);
     for (int c = threadIdx.x; c < lcells; c += blockDim.x) {
       a0[c] = (LT)0;
       a4[c] = (LT)0;
     }
-    long long e0, e1, s0, s1;
-    tile_entries(coff, ccap, tile, e0, e1);
-    tile_entries(soff, scap, tile, s0, s1);
     int chunks = 1;
     if (base >= 0) {
       // this chunk's share of the tile's entries
@@ -1546,143 +1776,58 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
       s0 = s0 + ns * chunk / chunks;
     }
     __syncthreads();
-    // global cell -> LDS cell, if the tile holds it
-    auto tcell = [&](int i, int j, int k, int& c) -> bool {
-      const int u = i - B.lo[0] + g - o[0], v = j - B.lo[1] + g - o[1], w = k - B.lo[2] + g - o[2];
-      if ((unsigned)u >= (unsigned)ext[0] || (unsigned)v >= (unsigned)ext[1] ||
-          (unsigned)w >= (unsigned)ext[2])
-        return false;
-      c = (w * TY + v) * TXP + u;
-      return true;
-    };
-    const int xlo = o[0] - g + B.lo[0];  // tile origin, global cells
-    const int ylo = o[1] - g + B.lo[1];
-    const int zlo = o[2] - g + B.lo[2];
     bool ovf = false;
-    long long cpos = e0, spos = s0;
-    while (cpos < e1 || spos < s1) {
+    long long spos = s0;
+    bool first = true;
+    while (first || spos < s1) {
+      // the batch's records are contiguous: one cooperative 16-byte copy
       const int nq = (int)min((long long)NB, s1 - spos);
-      // phase A
       {
-        const long long ce = cpos + threadIdx.x;
-        const bool has_c = ce < e1;
-        const bool has_s = (int)threadIdx.x < nq;
-        double4 CR = make_double4(0.0, 0.0, 0.0, 0.0);
-        int p = 0;
-        if (has_c) CR = crec[ce];
-        if (has_s) p = sidx[spos + threadIdx.x];
-        if (has_c) {
+        const uint4* src = reinterpret_cast<const uint4*>(ent + spos);
+        uint4* dst = reinterpret_cast<uint4*>(bent);
+        const int n16 = nq * (int)(sizeof(SnEnt<S>) / 16);
+        for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+      }
+      if (first) {
+        // CIC entries (their loads overlap the copy)
+        for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+          const double4 CR = crec[e];
           const int h[3] = {(int)floor(CR.x), (int)floor(CR.y), (int)floor(CR.z)};
           auto add = [&](int i, int j, int k, auto v) {
-            int c;
-            if (tcell(i, j, k, c)) lds_add(a0 + c, v);
+            const int u = i - G.glo[0], vv = j - G.glo[1], w = k - G.glo[2];
+            if ((unsigned)u < (unsigned)G.ext[0] && (unsigned)vv < (unsigned)G.ext[1] &&
+                (unsigned)w < (unsigned)G.ext[2])
+              lds_add(a0 + (w * TY + vv) * TXP + u, v);
           };
           if (!cic_one<FIXED>(CR.x, CR.y, CR.z, CR.w, M.V, h, add)) ovf = true;
         }
-        if (has_s) {
-          const int q = threadIdx.x;
-          const SnPk& R = pk[p];
-          const double rx = R.x, ry = R.y, rz = R.z, rr_ = R.r;
-          const int N = R.n;
-          bval[2 * q] = R.vr;
-          bval[2 * q + 1] = R.ve;
-          if constexpr (FIXED) {
-            const int lu = R.ti - o[0], lv = R.tj - o[1], lw = R.tk - o[2];
-            const bool in = R.ti >= 0 && (unsigned)lu < (unsigned)ext[0] &&
-                            (unsigned)lv < (unsigned)ext[1] && (unsigned)lw < (unsigned)ext[2];
-            btgt[q] = in ? (lw * TY + lv) * TXP + lu : -1;
-            brem[2 * q] = R.remr;
-            brem[2 * q + 1] = R.reme;
-          }
-          unsigned short* runs = bruns + q * S;
-          if (N < 0) {
-            // host cell only
-            const int hi = (int)floor(rx), hj = (int)floor(ry), hk = (int)floor(rz);
-#pragma unroll
-            for (int sl = 0; sl < S; ++sl) {
-              const int v = sl & (TY - 1), w = sl >> YSH;
-              const int u = hi - xlo;
-              const bool on = (ylo + v == hj) && (zlo + w == hk) && (unsigned)u < (unsigned)ext[0];
-              runs[sl] = on ? (unsigned short)(u | (u << 8)) : (unsigned short)0x00ff;
-            }
-          } else {
-            Sphere Sp;
-            sphere_init(Sp, rx, ry, rz, rr_);
-            if (sn_has_table(Sp)) {
-              const unsigned short* rt = rows + (long long)kRowCap * p;
-              // the row-table entries of the tile's rows, loaded together in
-              // groups of up to 16, then clipped to the tile
-              constexpr int GS = S < 16 ? S : 16;
-#pragma unroll
-              for (int g0 = 0; g0 < S; g0 += GS) {
-                unsigned raw[GS];
-#pragma unroll
-                for (int sl = 0; sl < GS; ++sl) {
-                  const int v = (g0 + sl) & (TY - 1), w = (g0 + sl) >> YSH;
-                  const int j = ylo + v, k = zlo + w;
-                  const bool cand = v < ext[1] && w < ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] &&
-                                    k >= Sp.lo[2] && k <= Sp.hi[2];
-                  raw[sl] = cand ? rt[(j - Sp.lo[1]) + Sp.cy * (k - Sp.lo[2])] : 0x00ffu;
-                }
-#pragma unroll
-                for (int sl = 0; sl < GS; ++sl) {
-                  const int ua = max(Sp.lo[0] + (int)(raw[sl] & 255u) - xlo, 0);
-                  const int ub = min(Sp.lo[0] + (int)(raw[sl] >> 8) - xlo, ext[0] - 1);
-                  runs[g0 + sl] = (ua <= ub) ? (unsigned short)(ua | (ub << 8))
-                                             : (unsigned short)0x00ff;
-                }
-              }
-            } else {
-              // a sphere too large for a row table: runs found row by row
-#pragma unroll 1
-              for (int sl = 0; sl < S; ++sl) {
-                const int v = sl & (TY - 1), w = sl >> YSH;
-                const int j = ylo + v, k = zlo + w;
-                int a = 1, bb = 0;
-                if (v < ext[1] && w < ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] &&
-                    k >= Sp.lo[2] && k <= Sp.hi[2])
-                  row_members(Sp, j, k, a, bb);
-                const int ua = max(a - xlo, 0), ub = min(bb - xlo, ext[0] - 1);
-                runs[sl] = (a <= bb && ua <= ub) ? (unsigned short)(ua | (ub << 8))
-                                                 : (unsigned short)0x00ff;
-              }
-            }
-          }
-        }
-        cpos += blockDim.x;
+        first = false;
       }
       __syncthreads();
-      // phase B
-      for (int it = threadIdx.x; it < nq * S; it += blockDim.x) {
-        const int q = it / S, sl = it & (S - 1);
-        const unsigned run = bruns[q * S + sl];
+      // supernova rows, from LDS
+      for (int it = threadIdx.x; it < (nq << SSH); it += blockDim.x) {
+        const SnEnt<S>& E = bent[it >> SSH];
+        const int sl = it & (S - 1);
+        const unsigned run = E.runs[sl];
         const int ua = (int)(run & 255u), ub = (int)(run >> 8);
-        if (ua > ub) continue;
         const int v = sl & (TY - 1), w = sl >> YSH;
         LT* r0 = a0 + (w * TY + v) * TXP;
         LT* r4 = a4 + (w * TY + v) * TXP;
         if constexpr (FIXED) {
-          const long long qr = __double_as_longlong(bval[2 * q]);
-          const long long qe = __double_as_longlong(bval[2 * q + 1]);
+          const long long qr = __double_as_longlong(E.vr), qe = __double_as_longlong(E.ve);
           for (int u = ua; u <= ub; ++u) {
             lds_add(r0 + u, qr);
             lds_add(r4 + u, qe);
           }
+          if (sl == 0 && E.tgt >= 0) {
+            lds_add(a0 + E.tgt, E.remr);
+            lds_add(a4 + E.tgt, E.reme);
+          }
         } else {
-          const double cr = bval[2 * q], ce = bval[2 * q + 1];
+          const double cr = E.vr, ce = E.ve;
           for (int u = ua; u <= ub; ++u) {
             lds_add(r0 + u, cr);
             lds_add(r4 + u, ce);
-          }
-        }
-      }
-      if constexpr (FIXED) {
-        // fixed-point remainders, at the target cell when it is in the tile
-        for (int q = threadIdx.x; q < nq; q += blockDim.x) {
-          const int c = btgt[q];
-          if (c >= 0) {
-            lds_add(a0 + c, brem[2 * q]);
-            lds_add(a4 + c, brem[2 * q + 1]);
           }
         }
       }
@@ -1716,29 +1861,49 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
     }
     // every present channel of every cell is stored once: rho and E from
     // the accumulators (summed over the chunks in chunk order), the others
-    // (no source in this pass) as zero
-    OutT* f0 = buf + B.boff;
-    const long long np = B.npad;
+    // (no source in this pass) as zero.  In a fused step, owned cells at
+    // least g from every face are applied here instead (their buffer value,
+    // rounded to the buffer type, is final: no ghost image reaches them)
+    OutT* f0 = buf + G.boff;
+    const long long np = (long long)G.p[0] * G.p[1] * G.p[2];
+    const int n0 = G.p[0] - 2 * g, n1 = G.p[1] - 2 * g, n2 = G.p[2] - 2 * g;
+    const long long ncell = (long long)n0 * n1 * n2;
     const int sr = M.slot[0], se = M.slot[4];
     for (int c = threadIdx.x; c < tcells; c += blockDim.x) {
-      const int u = c % TX, v = (c / TX) % TY, w = c / (TX * TY);
-      if (u >= ext[0] || v >= ext[1] || w >= ext[2]) continue;
-      const long long idx = ((long long)(o[2] + w) * B.p[1] + (o[1] + v)) * B.p[0] + (o[0] + u);
+      const int u = c % TX, v = (c / TX) & (TY - 1), w = c / (TX * TY);
+      if (u >= G.ext[0] || v >= G.ext[1] || w >= G.ext[2]) continue;
+      const int px = G.o[0] + u, py = G.o[1] + v, pz = G.o[2] + w;
       const int lc = (w * TY + v) * TXP + u;
       LT r0 = src0[lc], r4 = src4[lc];
       for (int q = 1; q < nsum; ++q) {
         r0 += src0[q * sstride + lc];
         r4 += src4[q * sstride + lc];
       }
+      const OutT vr = sr >= 0 ? from_lds<OutT>(r0) : (OutT)0;
+      const OutT ve = se >= 0 ? from_lds<OutT>(r4) : (OutT)0;
+      // owned-local coordinates: interior when g <= . < n - g on every axis
+      const int ox = px - g, oy = py - g, oz = pz - g;
+      if (state && ox >= g && ox < n0 - g && oy >= g && oy < n1 - g && oz >= g && oz < n2 - g) {
+        const long long si = G.soff + ((long long)oz * n1 + oy) * n0 + ox;
+        if (M.state == PMP_STATE_F32)
+          apply_cell((float*)state + si, ncell, to_f64(vr), 0.0, 0.0, 0.0, to_f64(ve), 0.0, L,
+                     cnt);
+        else
+          apply_cell((double*)state + si, ncell, to_f64(vr), 0.0, 0.0, 0.0, to_f64(ve), 0.0, L,
+                     cnt);
+        continue;
+      }
+      const long long idx = ((long long)pz * G.p[1] + py) * G.p[0] + px;
       for (int f = 0; f < M.nfield; ++f) {
         OutT val = (OutT)0;
-        if (f == sr) val = from_lds<OutT>(r0);
-        else if (f == se) val = from_lds<OutT>(r4);
+        if (f == sr) val = vr;
+        else if (f == se) val = ve;
         f0[idx + f * np] = val;
       }
     }
     __syncthreads();
   }
+  if (state) flush_counts(M, cnt);
 }
 
 inline int grid_for(long long n, int block, int cap) {
@@ -1812,8 +1977,8 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
     hipLaunchKernelGGL(k_l1_cic<false>, dim3(nbc), dim3(256), lds1, s, M, T, *cic, S, nb, hc,
                        nbc, (double4*)nullptr, (int*)nullptr, 0ll);
   if (has_s)
-    hipLaunchKernelGGL(k_l1_sn<false>, dim3(nbs), dim3(256), lds1, s, M, T, *sn, S, nb, hs, nbs,
-                       bw.sn_pk, bw.sn_rows, (int*)nullptr, (int*)nullptr, 0ll);
+    hipLaunchKernelGGL(k_l1_sn_hist, dim3(nbs), dim3(kBinChunkSn), lds1, s, M, T, *sn, S, nb, hs,
+                       nbs, bw.sn_pk, bw.sn_rows);
   // exclusive scan of both kinds' histograms, in place; hist[n] = total
   const int nblocks = (int)((n + kScanBlock - 1) / kScanBlock);
   hipLaunchKernelGGL(k_scan_local, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist, bw.hist,
@@ -1826,8 +1991,8 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
     hipLaunchKernelGGL(k_l1_cic<true>, dim3(nbc), dim3(256), lds1, s, M, T, *cic, S, nb, hc, nbc,
                        bw.cic_tmp, bw.cic_tmp_tile, bw.cic_cap);
   if (has_s)
-    hipLaunchKernelGGL(k_l1_sn<true>, dim3(nbs), dim3(kBinChunkSn), lds1, s, M, T, *sn, S, nb,
-                       hs, nbs, bw.sn_pk, bw.sn_rows, bw.sn_tmp, bw.sn_tmp_tile, bw.sn_cap);
+    hipLaunchKernelGGL(k_l1_sn_scatter, dim3(nbs), dim3(kBinChunkSn), lds1, s, M, T, *sn, S, nb,
+                       hs, nbs, (const SnPk*)bw.sn_pk, bw.sn_tmp, bw.sn_tmp_tile, bw.sn_cap);
   // level 2: balanced slices of every bucket, both kinds
   L2Geom G;
   G.hist1 = bw.hist;
@@ -1857,38 +2022,51 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
     hipLaunchKernelGGL(k_l2_scatter<double4>, dim3(grid2), dim3(256), lds2, s, G, 0,
                        (const int*)bw.slice_base, (const int*)bw.hist2,
                        (const double4*)bw.cic_tmp, (const int*)bw.cic_tmp_tile, bw.cic_rec,
-                       bw.cic_off, bw.cic_cap);
+                       (int*)nullptr, bw.cic_off, bw.cic_cap);
   if (has_s)
     hipLaunchKernelGGL(k_l2_scatter<int>, dim3(grid2), dim3(256), lds2, s, G, 1,
                        (const int*)bw.slice_base, (const int*)bw.hist2,
                        (const int*)bw.sn_tmp, (const int*)bw.sn_tmp_tile, bw.sn_rec,
-                       bw.sn_off, bw.sn_cap);
+                       bw.sn_rec_tile, bw.sn_off, bw.sn_cap);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles* cic,
                                const Particles* sn, const BinWork& bw, void* buf,
-                               const pmp_tuning& t, hipStream_t s) {
+                               const pmp_tuning& t, void* state, const Limits& L,
+                               hipStream_t s) {
   const int* coff = (cic && cic->n > 0) ? bw.cic_off : nullptr;
   const int* soff = (sn && sn->n > 0) ? bw.sn_off : nullptr;
   const int block = t.tile_block;
-  const size_t lds = (size_t)tile_lds_bytes(T.t[0], T.t[1], block, M.acc == PMP_ACC_FIX64);
+  const size_t lds = (size_t)tile_lds_bytes(T.t[0], T.t[1]);  // includes the record batch
   long long grid = T.ntiles;
   if (t.tile_grid_per_cu > 0)
     grid = std::min<long long>(grid, (long long)M.num_cu * t.tile_grid_per_cu);
   if (grid < 1) grid = 1;
   if (grid > 0x7fffffffll) grid = 0x7fffffffll;
+  const int egrid = grid_for(bw.sn_cap, 256, M.num_cu * 32);
+#define PMP_ENT(TYZ)                                                                        \
+  if (soff)                                                                                 \
+    hipLaunchKernelGGL((k_sn_ent<TYZ>), dim3(egrid), dim3(256), 0, s, T, soff, bw.sn_cap,   \
+                       (const int*)bw.sn_rec, (const int*)bw.sn_rec_tile,                   \
+                       (const SnPk*)bw.sn_pk, (const unsigned short*)bw.sn_rows,            \
+                       (SnEnt<TYZ * TYZ>*)bw.sn_ent)
+  switch (T.t[1]) {
+    case 2: PMP_ENT(2); break;
+    case 4: PMP_ENT(4); break;
+    default: PMP_ENT(8);
+  }
+#undef PMP_ENT
   hipLaunchKernelGGL(k_units, dim3(grid_for(T.ntiles, 256, M.num_cu * 16)), dim3(256), 0, s, T,
                      coff, bw.cic_cap, soff, bw.sn_cap, t.chunk_cic, t.chunk_sn, bw.heavy_base,
                      bw.heavy_unit, bw.heavy_count, bw.arrive, bw.slot_cap);
 #define PMP_TILE(ACC, TT, TYZ)                                                                \
   hipLaunchKernelGGL((k_tile_deposit<ACC, TYZ>), dim3((unsigned)grid), dim3(block), lds, s, M, \
                      T, coff, (const double4*)bw.cic_rec, bw.cic_cap, soff,                   \
-                     (const int*)bw.sn_rec, (const SnPk*)bw.sn_pk, bw.sn_cap,                \
-                     (const unsigned short*)bw.sn_rows, t.chunk_cic, t.chunk_sn,              \
+                     (const SnEnt<TYZ * TYZ>*)bw.sn_ent, bw.sn_cap, t.chunk_cic, t.chunk_sn,  \
                      (const int*)bw.heavy_base, (const int2*)bw.heavy_unit,                   \
                      (const int*)bw.heavy_count, bw.arrive, bw.partial, bw.slot_cap,          \
-                     (TT*)buf)
+                     (TT*)buf, state, L)
 #define PMP_TILE_ACC(TYZ)                                      \
   switch (M.acc) {                                             \
     case PMP_ACC_F32: PMP_TILE(PMP_ACC_F32, float, TYZ); break; \
@@ -2009,6 +2187,35 @@ static void fold_launch(const Mesh& M, void* buf, int block, hipStream_t s) {
     default: PMP_FOLD(6);
   }
 #undef PMP_FOLD
+}
+
+template <int ACC>
+static void fold_apply_launch(const Mesh& M, void* state, const void* buf, const Limits& L,
+                              hipStream_t s) {
+  using T = typename AccT<ACC>::T;
+  const int grid = grid_for(M.n_fold_chunks, 1, M.num_cu * 64);
+#define PMP_FA(F)                                                                           \
+  hipLaunchKernelGGL((k_fold_apply<ACC, F>), dim3(grid), dim3(kChunk), 0, s, M, state,      \
+                     (const T*)buf, L)
+  switch (M.nfield) {
+    case 1: PMP_FA(1); break;
+    case 2: PMP_FA(2); break;
+    case 3: PMP_FA(3); break;
+    case 4: PMP_FA(4); break;
+    case 5: PMP_FA(5); break;
+    default: PMP_FA(6);
+  }
+#undef PMP_FA
+}
+
+hipError_t launch_fold_apply(const Mesh& M, void* state, const void* buf, const Limits& L,
+                             hipStream_t s) {
+  switch (M.acc) {
+    case PMP_ACC_F32: fold_apply_launch<PMP_ACC_F32>(M, state, buf, L, s); break;
+    case PMP_ACC_F64: fold_apply_launch<PMP_ACC_F64>(M, state, buf, L, s); break;
+    default: fold_apply_launch<PMP_ACC_FIX64>(M, state, buf, L, s);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_fold(const Mesh& M, void* buf, int block, hipStream_t s) {

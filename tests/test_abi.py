@@ -44,7 +44,8 @@ STRUCTS = {
     "pmp_limits": ["rho_floor", "rho_tr", "cap", "eint_mode"],
     "pmp_status": ["flags", "reserved", "touched", "bind", "lam", "fall"],
     "pmp_tuning": ["deposit_path", "tile_x", "tile_yz", "tile_block", "block", "grid_per_cu",
-                   "sn_lanes", "tile_grid_per_cu", "chunk_cic", "chunk_sn"],
+                   "sn_lanes", "tile_grid_per_cu", "chunk_cic", "chunk_sn",
+                   "fuse_apply", "reserved"],
 }
 
 

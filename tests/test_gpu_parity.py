@@ -311,6 +311,49 @@ def test_graph_replays_match_eager(B):
     g.close()
 
 
+def step_vs_oracle(B, orc, w, acc, channels="all", tuning=None):
+    import torch
+    ctx = B.Context(w, acc, channels=channels)
+    if tuning:
+        ctx.set_tuning(**tuning)
+    ctx.step()
+    torch.cuda.synchronize()
+    got = ctx.state.cpu().numpy()
+    st = ctx.status()
+    ctx.close()
+    assert st["flags"] in (0, 0x10), st
+    ref = orc.step(w, "fix64" if acc == "fix64" else "f64", want_eta=True)
+    if acc == "fix64":
+        assert np.array_equal(got, ref["state"].astype(got.dtype))
+        for k in ("touched", "bind", "lam", "fall"):
+            assert st[k] == ref["counters"][k], (k, st, ref["counters"])
+    else:
+        for f, (x, r) in enumerate(zip(field_views(w, got, "state"),
+                                       field_views(w, ref["state"].astype(got.dtype), "state"))):
+            assert rel_err(x, r) <= max(TOL[acc], float(np.finfo(got.dtype).eps)), f
+
+
+@pytest.mark.parametrize("fuse", [1, 0])
+@pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
+@pytest.mark.parametrize("idx", range(5))
+def test_step_edge_layouts(B, orc, idx, acc, fuse):
+    """pmp_step on the edge layouts, with the apply fused into the tile pass
+    (interior cells) and the shell folded and applied together, or not."""
+    w = edge_workloads()[idx]
+    say(f"step edge {w.name} acc={acc} fuse={fuse}")
+    step_vs_oracle(B, orc, w, acc, tuning={"deposit_path": 1, "fuse_apply": fuse})
+
+
+@pytest.mark.parametrize("fuse", [1, 0])
+@pytest.mark.parametrize("name", list(SMALL))
+def test_step_fused_split_tiles(B, orc, name, fuse):
+    """Fused step with split tiles and small tiles."""
+    w = SMALL[name]()
+    for tun in ({"chunk_cic": 64, "chunk_sn": 16}, {"tile_x": 16, "tile_yz": 2}):
+        say(f"step {w.name} fuse={fuse} {tun}")
+        step_vs_oracle(B, orc, w, "fix64", tuning={"deposit_path": 1, "fuse_apply": fuse, **tun})
+
+
 @pytest.mark.parametrize("channels", ["auto", "all"])
 @pytest.mark.parametrize("name", ["c2_40", "c3_40", "c4_48", "c5_4"])
 def test_step_matches_oracle(B, orc, name, channels):
