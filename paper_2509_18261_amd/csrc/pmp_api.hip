@@ -1237,7 +1237,8 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
   add(0, base.tile_x, base.tile_yz, base.tile_block, 64, 0, 0);
   if (has_sn) add(0, base.tile_x, base.tile_yz, base.tile_block, 16, 0, 0);
   const int shapes[][3] = {{64, 4, 128}, {64, 4, 256}, {32, 4, 128}, {32, 8, 256},
-                           {16, 8, 256}, {64, 2, 128}, {16, 4, 128}, {32, 4, 256}};
+                           {16, 8, 256}, {64, 2, 128}, {16, 4, 128}, {32, 4, 256},
+                           {64, 8, 256}, {64, 8, 512}};
   // the fused apply only applies to steps without sinks
   for (int fuse = has_sinks ? 0 : 1; fuse >= 0; --fuse)
     for (const auto& sh : shapes) add(1, sh[0], sh[1], sh[2], 64, 0, fuse);

@@ -129,11 +129,11 @@ struct SnPk {
 // the tile's S = TY * TZ rows (row s: v = s mod TY, w = s / TY) clipped to
 // the tile, as ua | ub << 8 in tile-local x (0x00ff: none).
 template <int S> struct alignas(16) SnEnt {
-  double vr, ve;         // member share (for fixed point: the quanta's bits)
-  long long remr, reme;  // fixed point: remainder, added at cell tgt
-  int tgt;               // LDS cell of the remainder in this tile, or -1
+  double vr, ve;          // member share (for fixed point: the quanta's bits)
+  long long remr, reme;   // fixed point: remainder, added at cell tgt
+  unsigned short runs[S];  // 16-byte aligned
+  int tgt;                // LDS cell of the remainder in this tile, or -1
   int pad;
-  unsigned short runs[S];
 };
 
 // Member runs of a supernova's sphere rows, stored once per particle by the

@@ -236,27 +236,41 @@ __device__ __forceinline__ void sphere_row(const Sphere& S, int t, int& j, int& 
 }
 
 // Members [a, b] of row (j, k); empty when a > b.
-__device__ __forceinline__ void row_members(const Sphere& S, int j, int k, int& a, int& b) {
+// The test value of cell i of a row whose rounded squared y and z offsets
+// are y2 and z2: the same rounded operations, in the same order, as dist2.
+__device__ __forceinline__ double row_d2(const Sphere& S, int i, double y2, double z2) {
+  const double ddx = ((double)i + 0.5) - S.x;
+  return (ddx * ddx + y2) + z2;
+}
+
+// Members [a, b] of the row with rounded squared offsets y2, z2.
+__device__ __forceinline__ void row_members_yz(const Sphere& S, double y2, double z2, int& a,
+                                               int& b) {
   const int c = (int)floor(S.x);
-  if (!(dist2(S.x, S.y, S.z, c, j, k) <= S.r2)) {
+  if (!(row_d2(S, c, y2, z2) <= S.r2)) {
     a = 1;
     b = 0;
     return;
   }
   // the run's ends are estimated in single precision and settled exactly below
-  const double dy = ((double)j + 0.5) - S.y, dz = ((double)k + 0.5) - S.z;
-  const float w2 = (float)(S.r2 - (dy * dy + dz * dz));
+  const float w2 = (float)(S.r2 - (y2 + z2));
   const float w = w2 > 0.0f ? sqrtf(w2) : 0.0f;
   const float xc = (float)(S.x - 0.5);
   int aa = (int)ceilf(xc - w), bb = (int)floorf(xc + w);
   aa = min(max(aa, S.lo[0]), c);
   bb = max(min(bb, S.hi[0]), c);
-  while (aa > S.lo[0] && dist2(S.x, S.y, S.z, aa - 1, j, k) <= S.r2) --aa;
-  while (aa < c && !(dist2(S.x, S.y, S.z, aa, j, k) <= S.r2)) ++aa;
-  while (bb < S.hi[0] && dist2(S.x, S.y, S.z, bb + 1, j, k) <= S.r2) ++bb;
-  while (bb > c && !(dist2(S.x, S.y, S.z, bb, j, k) <= S.r2)) --bb;
+  while (aa > S.lo[0] && row_d2(S, aa - 1, y2, z2) <= S.r2) --aa;
+  while (aa < c && !(row_d2(S, aa, y2, z2) <= S.r2)) ++aa;
+  while (bb < S.hi[0] && row_d2(S, bb + 1, y2, z2) <= S.r2) ++bb;
+  while (bb > c && !(row_d2(S, bb, y2, z2) <= S.r2)) --bb;
   a = aa;
   b = bb;
+}
+
+// Members [a, b] of row (j, k); empty when a > b.
+__device__ __forceinline__ void row_members(const Sphere& S, int j, int k, int& a, int& b) {
+  const double dy = ((double)j + 0.5) - S.y, dz = ((double)k + 0.5) - S.z;
+  row_members_yz(S, dy * dy, dz * dz, a, b);
 }
 
 // Count of a sphere over a group of L lanes (lanes over rows): member count
@@ -1138,10 +1152,26 @@ __global__ __launch_bounds__(256) void k_l1_cic(Mesh M, TileGrid T, Particles P,
   int bb0, bb1;
   block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
   bool outside = false, nan = false, full = false;
-  for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+  // the thread's particles are loaded together, then binned one by one
+  constexpr int UNR = kBinChunkCic / 256;
+  double px[UNR], py[UNR], pz[UNR], pm[UNR];
+#pragma unroll
+  for (int u = 0; u < UNR; ++u) {
+    const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
+    if (p < p1) {
+      px[u] = P.x[p];
+      py[u] = P.y[p];
+      pz[u] = P.z[p];
+      pm[u] = P.a[p];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UNR; ++u) {
+    const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
+    if (p >= p1) continue;
     const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
     const DevBox B = M.boxes[b];
-    const double x = P.x[p], y = P.y[p], z = P.z[p], m = P.a[p];
+    const double x = px[u], y = py[u], z = pz[u], m = pm[u];
     int hc[3];
     if (!host_cell(B, x, y, z, hc)) { outside = true; continue; }
     if (!isfinite(m)) { nan = true; continue; }
@@ -1174,13 +1204,8 @@ __global__ __launch_bounds__(256) void k_l1_cic(Mesh M, TileGrid T, Particles P,
   }
 }
 
-// Level 1, supernovae.  Histogram pass: a group of 16 lanes per particle
-// counts the sphere's members N (-1 when no centre lies within r and the host
-// cell takes the deposit; 0 when the particle is skipped), fills its row
-// table, finds the fixed-point remainder cell (host if a member, else the
-// first member in (k, j, i) order), writes the particle's SnPk and counts it
-// into the buckets of every tile its sphere touches.  Scatter pass: one
-// thread per particle writes (particle, tile) entries.
+// Tiles a supernova's deposit touches: those of its sphere's candidate box,
+// or of the host cell alone when N < 0.
 __device__ __forceinline__ bool sn_tiles(const Mesh& M, const TileGrid& T, const DevBox& B,
                                          double x, double y, double z, double r, int N,
                                          int tlo[3], int thi[3]) {
@@ -1262,6 +1287,10 @@ __global__ __launch_bounds__(kBinChunkSn) void k_l1_sn_hist(Mesh M, TileGrid T, 
   // rounded test value of each of its cells is at least that sum (the terms
   // are non-negative and rounding is monotone)
   int cnt = 0, key = 0x7fffffff, hm = 0, out = 0;
+  // padded box of B, global cells
+  const int plo[3] = {B.lo[0] - g, B.lo[1] - g, B.lo[2] - g};
+  const int phi[3] = {B.lo[0] + B.n[0] + g - 1, B.lo[1] + B.n[1] + g - 1,
+                      B.lo[2] + B.n[2] + g - 1};
   int maxrows = nrows;
   maxrows = group_max<kWave>(maxrows);
   int jj = 0, kk = 0;  // row t = jj + cy * kk
@@ -1272,16 +1301,18 @@ __global__ __launch_bounds__(kBinChunkSn) void k_l1_sn_hist(Mesh M, TileGrid T, 
       if (t < nrows) {
         const int j = Sp.lo[1] + jj, k = Sp.lo[2] + kk;
         const double dy = ((double)j + 0.5) - Sp.y, dz = ((double)k + 0.5) - Sp.z;
-        if (dy * dy + dz * dz <= Sp.r2) {
+        const double y2 = dy * dy, z2 = dz * dz;
+        if (y2 + z2 <= Sp.r2) {
           int a, bb;
-          row_members(Sp, j, k, a, bb);
+          row_members_yz(Sp, y2, z2, a, bb);
           if (a <= bb) {
             v = (unsigned short)((a - Sp.lo[0]) | ((bb - Sp.lo[0]) << 8));
             cnt += bb - a + 1;
             if (key == 0x7fffffff) key = (t << 12) | (a - Sp.lo[0]);
             hm |= (j == hc[1] && k == hc[2] && a <= hc[0] && hc[0] <= bb);
-            long long idx;
-            out |= !pad_index(B, g, a, j, k, idx) || !pad_index(B, g, bb, j, k, idx);
+            // a member outside the padded box
+            out |= a < plo[0] || bb > phi[0] || j < plo[1] || j > phi[1] || k < plo[2] ||
+                   k > phi[2];
           }
         }
         if (++jj == Sp.cy) {
@@ -1555,6 +1586,7 @@ __global__ __launch_bounds__(256) void k_sn_ent(TileGrid T, const int* __restric
                                                SnEnt<TYZ * TYZ>* __restrict__ ent) {
   constexpr int TY = TYZ, S = TYZ * TYZ;
   constexpr int YSH = (TYZ == 2) ? 1 : (TYZ == 4) ? 2 : 3;
+  constexpr int GS = S < 16 ? S : 16;  // runs per group, stored as GS / 8 16-byte vectors
   const int TXP = T.t[0] + 1;
   const long long n = min((long long)soff[T.ntiles], cap);
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
@@ -1563,71 +1595,77 @@ __global__ __launch_bounds__(256) void k_sn_ent(TileGrid T, const int* __restric
     const TileGeo G = T.geo[stile[e]];
     const SnPk R = pk[p];
     const int xlo = G.glo[0], ylo = G.glo[1], zlo = G.glo[2];
-    SnEnt<S> E;
-    E.vr = R.vr;
-    E.ve = R.ve;
-    E.remr = R.remr;
-    E.reme = R.reme;
-    E.pad = 0;
+    SnEnt<S>& E = ent[e];
+    int tgt;
     {
       const int lu = R.ti - G.o[0], lv = R.tj - G.o[1], lw = R.tk - G.o[2];
       const bool in = R.ti >= 0 && (unsigned)lu < (unsigned)G.ext[0] &&
                       (unsigned)lv < (unsigned)G.ext[1] && (unsigned)lw < (unsigned)G.ext[2];
-      E.tgt = in ? (lw * TY + lv) * TXP + lu : -1;
+      tgt = in ? (lw * TY + lv) * TXP + lu : -1;
     }
-    if (R.n < 0) {
-      // host cell only
-      const int hi = (int)floor(R.x), hj = (int)floor(R.y), hk = (int)floor(R.z);
+    *reinterpret_cast<double4*>(&E.vr) = make_double4(R.vr, R.ve, __longlong_as_double(R.remr),
+                                                      __longlong_as_double(R.reme));
+    Sphere Sp;
+    sphere_init(Sp, R.x, R.y, R.z, R.n < 0 ? 0.0 : R.r);
+    const bool table = R.n >= 0 && sn_has_table(Sp);
+    const unsigned short* rt = rows + (long long)kRowCap * p;
+    const int hi = (int)floor(R.x), hj = (int)floor(R.y), hk = (int)floor(R.z);
+    // runs of the tile's rows, GS at a time: from the row table (entries
+    // loaded together), found row by row for a sphere too large for one, or
+    // the host cell alone
 #pragma unroll
+    for (int g0 = 0; g0 < S; g0 += GS) {
+      unsigned raw[GS];
+#pragma unroll
+      for (int sl = 0; sl < GS; ++sl) {
+        const int v = (g0 + sl) & (TY - 1), w = (g0 + sl) >> YSH;
+        const int j = ylo + v, k = zlo + w;
+        const bool cand = v < G.ext[1] && w < G.ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] &&
+                          k >= Sp.lo[2] && k <= Sp.hi[2];
+        raw[sl] = (cand && table) ? rt[(j - Sp.lo[1]) + Sp.cy * (k - Sp.lo[2])] : 0x00ffu;
+      }
+      unsigned packed[GS / 2];
+#pragma unroll
+      for (int sl = 0; sl < GS; ++sl) {
+        const int v = (g0 + sl) & (TY - 1), w = (g0 + sl) >> YSH;
+        int a = 1, bb = 0;
+        if (R.n < 0) {
+          if (ylo + v == hj && zlo + w == hk && v < G.ext[1] && w < G.ext[2]) a = bb = hi;
+        } else if (raw[sl] != 0x00ffu) {
+          a = Sp.lo[0] + (int)(raw[sl] & 255u);
+          bb = Sp.lo[0] + (int)(raw[sl] >> 8);
+        }
+        const int ua = max(a - xlo, 0), ub = min(bb - xlo, G.ext[0] - 1);
+        const unsigned run = (a <= bb && ua <= ub) ? (unsigned)(ua | (ub << 8)) : 0x00ffu;
+        if (sl & 1) packed[sl / 2] |= run << 16;
+        else packed[sl / 2] = run;
+      }
+      if constexpr (GS >= 8) {
+#pragma unroll
+        for (int q = 0; q < GS / 8; ++q)
+          *reinterpret_cast<uint4*>(&E.runs[g0 + 8 * q]) =
+              make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
+      } else {
+        *reinterpret_cast<uint2*>(&E.runs[g0]) = make_uint2(packed[0], packed[1]);
+      }
+    }
+    if (R.n >= 0 && !table) {
+      // a sphere too large for a row table: runs found row by row
+#pragma unroll 1
       for (int sl = 0; sl < S; ++sl) {
         const int v = sl & (TY - 1), w = sl >> YSH;
-        const int u = hi - xlo;
-        const bool on = (ylo + v == hj) && (zlo + w == hk) && (unsigned)u < (unsigned)G.ext[0];
-        E.runs[sl] = on ? (unsigned short)(u | (u << 8)) : (unsigned short)0x00ff;
-      }
-    } else {
-      Sphere Sp;
-      sphere_init(Sp, R.x, R.y, R.z, R.r);
-      if (sn_has_table(Sp)) {
-        const unsigned short* rt = rows + (long long)kRowCap * p;
-        // the row-table entries of the tile's rows, loaded together in
-        // groups of up to 16, then clipped to the tile
-        constexpr int GS = S < 16 ? S : 16;
-#pragma unroll
-        for (int g0 = 0; g0 < S; g0 += GS) {
-          unsigned raw[GS];
-#pragma unroll
-          for (int sl = 0; sl < GS; ++sl) {
-            const int v = (g0 + sl) & (TY - 1), w = (g0 + sl) >> YSH;
-            const int j = ylo + v, k = zlo + w;
-            const bool cand = v < G.ext[1] && w < G.ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] &&
-                              k >= Sp.lo[2] && k <= Sp.hi[2];
-            raw[sl] = cand ? rt[(j - Sp.lo[1]) + Sp.cy * (k - Sp.lo[2])] : 0x00ffu;
-          }
-#pragma unroll
-          for (int sl = 0; sl < GS; ++sl) {
-            const int ua = max(Sp.lo[0] + (int)(raw[sl] & 255u) - xlo, 0);
-            const int ub = min(Sp.lo[0] + (int)(raw[sl] >> 8) - xlo, G.ext[0] - 1);
-            E.runs[g0 + sl] = (ua <= ub) ? (unsigned short)(ua | (ub << 8))
-                                         : (unsigned short)0x00ff;
-          }
-        }
-      } else {
-#pragma unroll 1
-        for (int sl = 0; sl < S; ++sl) {
-          const int v = sl & (TY - 1), w = sl >> YSH;
-          const int j = ylo + v, k = zlo + w;
-          int a = 1, bb = 0;
-          if (v < G.ext[1] && w < G.ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] &&
-              k >= Sp.lo[2] && k <= Sp.hi[2])
-            row_members(Sp, j, k, a, bb);
-          const int ua = max(a - xlo, 0), ub = min(bb - xlo, G.ext[0] - 1);
-          E.runs[sl] = (a <= bb && ua <= ub) ? (unsigned short)(ua | (ub << 8))
-                                             : (unsigned short)0x00ff;
-        }
+        const int j = ylo + v, k = zlo + w;
+        int a = 1, bb = 0;
+        if (v < G.ext[1] && w < G.ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] && k >= Sp.lo[2] &&
+            k <= Sp.hi[2])
+          row_members(Sp, j, k, a, bb);
+        const int ua = max(a - xlo, 0), ub = min(bb - xlo, G.ext[0] - 1);
+        E.runs[sl] = (a <= bb && ua <= ub) ? (unsigned short)(ua | (ub << 8))
+                                           : (unsigned short)0x00ff;
       }
     }
-    ent[e] = E;
+    E.tgt = tgt;
+    E.pad = 0;
   }
 }
 
