@@ -200,7 +200,7 @@ __host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz) {
 }
 
 constexpr int kBinChunkCic = 1024;  // CIC particles per level-1 block
-constexpr int kBinChunkSn = 64;     // supernovae per level-1 block
+constexpr int kBinChunkSn = 256;    // supernovae per level-1 block (one per thread)
 
 // Kernel launchers: all enqueue on `s` and return hipError_t of the launch.
 hipError_t launch_zero(void* buf, long long bytes, int block, hipStream_t s);

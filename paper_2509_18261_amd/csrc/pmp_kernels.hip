@@ -1079,44 +1079,51 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int* sh) {
   return v;
 }
 
+// Exclusive scan in two launches.  The length is n, or, when dcount is
+// given, min(n, *dcount << dshift) (a length known only on the device).
+__device__ __forceinline__ long long scan_len(long long n, const int* dcount, int dshift) {
+  return dcount ? min(n, (long long)(*dcount) << dshift) : n;
+}
+
+// Each block scans its kScanBlock values and leaves its total.
 __global__ __launch_bounds__(kScanBlock) void k_scan_local(int* __restrict__ count,
                                                             int* __restrict__ offset,
                                                             int* __restrict__ block_sums,
-                                                            long long n) {
+                                                            long long n,
+                                                            const int* __restrict__ dcount,
+                                                            int dshift) {
   __shared__ int sh[kWave];
+  n = scan_len(n, dcount, dshift);
+  if ((long long)blockIdx.x * kScanBlock >= n) return;
   const long long i = (long long)blockIdx.x * kScanBlock + threadIdx.x;
   const int v = (i < n) ? count[i] : 0;
-  if (i < n) count[i] = 0;
   const int inc = block_inclusive_scan(v, sh);
   if (i < n) offset[i] = inc - v;
   if (threadIdx.x == kScanBlock - 1) block_sums[blockIdx.x] = inc;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_top(int* __restrict__ block_sums,
-                                                          int nblocks, int* __restrict__ offset,
-                                                          long long n) {
+// Each block adds the total of the blocks before it, summed here (there are
+// few); the last block writes offset[n], the grand total.
+__global__ __launch_bounds__(kScanBlock) void k_scan_finish(int* __restrict__ offset,
+                                                             const int* __restrict__ block_sums,
+                                                             long long n,
+                                                             const int* __restrict__ dcount,
+                                                             int dshift) {
   __shared__ int sh[kWave];
-  __shared__ int carry;
-  if (threadIdx.x == 0) carry = 0;
+  n = scan_len(n, dcount, dshift);
+  const int nbe = (int)((n + kScanBlock - 1) / kScanBlock);
+  const int b = blockIdx.x;
+  if (b >= max(nbe, 1)) return;
+  int part = 0;
+  for (int i = threadIdx.x; i < b; i += blockDim.x) part += block_sums[i];
+  part = group_sum<kWave>(part);
+  if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = part;
   __syncthreads();
-  for (int base = 0; base < nblocks; base += kScanBlock) {
-    const int i = base + threadIdx.x;
-    const int v = (i < nblocks) ? block_sums[i] : 0;
-    const int inc = block_inclusive_scan(v, sh);
-    const int c = carry;
-    if (i < nblocks) block_sums[i] = c + inc - v;
-    __syncthreads();
-    if (threadIdx.x == kScanBlock - 1) carry = c + inc;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) offset[n] = carry;
-}
-
-__global__ __launch_bounds__(kScanBlock) void k_scan_add(int* __restrict__ offset,
-                                                          const int* __restrict__ block_sums,
-                                                          long long n) {
-  const long long i = (long long)blockIdx.x * kScanBlock + threadIdx.x;
-  if (i < n) offset[i] += block_sums[blockIdx.x];
+  int pre = 0;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) pre += sh[w];
+  const long long i = (long long)b * kScanBlock + threadIdx.x;
+  if (i < n) offset[i] += pre;
+  if (b == max(nbe, 1) - 1 && threadIdx.x == 0) offset[n] = pre + (nbe > 0 ? block_sums[b] : 0);
 }
 
 // Level 1 of the bucket sort, CIC.  Block k handles particles
@@ -1135,19 +1142,20 @@ __device__ __forceinline__ int hist_col(int blk, int nblk) {
 }
 
 template <bool SCATTER>
-__global__ __launch_bounds__(256) void k_l1_cic(Mesh M, TileGrid T, Particles P, int shift,
-                                               int nb, int* __restrict__ hist, int nblk,
-                                               double4* __restrict__ tmp,
-                                               int* __restrict__ tmp_tile, long long cap) {
+__device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T,
+                                       const Particles& P, int shift, int nb,
+                                       int* __restrict__ hist, int nblk,
+                                       double4* __restrict__ tmp, int* __restrict__ tmp_tile,
+                                       long long cap) {
   extern __shared__ int h[];
   const int g = M.ghost;
-  const int col = hist_col(blockIdx.x, nblk);
+  const int col = hist_col(blk, nblk);
   // hist is this kind's segment of the scanned histograms: positions are
   // taken relative to its first entry
   for (int c = threadIdx.x; c < nb; c += blockDim.x)
     h[c] = SCATTER ? hist[(long long)c * nblk + col] - hist[0] : 0;
   __syncthreads();
-  const long long p0 = (long long)blockIdx.x * kBinChunkCic;
+  const long long p0 = (long long)blk * kBinChunkCic;
   const long long p1 = min(p0 + kBinChunkCic, P.n);
   int bb0, bb1;
   block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
@@ -1233,18 +1241,18 @@ __device__ __forceinline__ bool sn_has_table(const Sphere& S) {
 // first member in (k, j, i) order) and fills its row table through an LDS
 // chunk written out as 16-byte vectors; then it writes the particle's SnPk
 // and counts it into the buckets of every tile its sphere touches.
-__global__ __launch_bounds__(kBinChunkSn) void k_l1_sn_hist(Mesh M, TileGrid T, Particles P,
-                                                            int shift, int nb,
-                                                            int* __restrict__ hist, int nblk,
-                                                            SnPk* __restrict__ pk,
-                                                            unsigned short* __restrict__ sn_rows) {
+__device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGrid& T,
+                                           const Particles& P, int shift, int nb,
+                                           int* __restrict__ hist, int nblk,
+                                           SnPk* __restrict__ pk,
+                                           unsigned short* __restrict__ sn_rows) {
   constexpr int CH = 32;  // rows per staged chunk
   extern __shared__ int h[];
   __shared__ unsigned short st[CH][kBinChunkSn];
   const int g = M.ghost;
-  const int col = hist_col(blockIdx.x, nblk);
+  const int col = hist_col(blk, nblk);
   for (int c = threadIdx.x; c < nb; c += blockDim.x) h[c] = 0;
-  const long long p0 = (long long)blockIdx.x * kBinChunkSn;
+  const long long p0 = (long long)blk * kBinChunkSn;
   const long long p1 = min(p0 + kBinChunkSn, P.n);
   int bb0, bb1;
   block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
@@ -1384,18 +1392,16 @@ __global__ __launch_bounds__(kBinChunkSn) void k_l1_sn_hist(Mesh M, TileGrid T, 
 
 // Level 1, supernovae, scatter pass: one thread per particle writes its
 // (particle, tile) entries at the positions the scanned histograms give.
-__global__ __launch_bounds__(kBinChunkSn) void k_l1_sn_scatter(Mesh M, TileGrid T, Particles P,
-                                                               int shift, int nb,
-                                                               int* __restrict__ hist, int nblk,
-                                                               const SnPk* __restrict__ pk,
-                                                               int* __restrict__ tmp,
-                                                               int* __restrict__ tmp_tile,
-                                                               long long cap) {
+__device__ __forceinline__ void l1_sn_scatter(int blk, const Mesh& M, const TileGrid& T,
+                                              const Particles& P, int shift, int nb,
+                                              int* __restrict__ hist, int nblk,
+                                              const SnPk* __restrict__ pk, int* __restrict__ tmp,
+                                              int* __restrict__ tmp_tile, long long cap) {
   extern __shared__ int h[];
-  const int col = hist_col(blockIdx.x, nblk);
+  const int col = hist_col(blk, nblk);
   for (int c = threadIdx.x; c < nb; c += blockDim.x)
     h[c] = hist[(long long)c * nblk + col] - hist[0];
-  const long long p0 = (long long)blockIdx.x * kBinChunkSn;
+  const long long p0 = (long long)blk * kBinChunkSn;
   const long long p1 = min(p0 + kBinChunkSn, P.n);
   int bb0, bb1;
   block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
@@ -1423,6 +1429,34 @@ __global__ __launch_bounds__(kBinChunkSn) void k_l1_sn_scatter(Mesh M, TileGrid 
         }
   }
   if (full) raise_flag(M.status, PMP_FLAG_CAPACITY);
+}
+
+// Level 1 for both kinds in one launch: blocks [0, nbc) take CIC chunks,
+// the rest supernova chunks.
+__global__ __launch_bounds__(256) void k_l1_hist(Mesh M, TileGrid T, Particles C, Particles Sn,
+                                                int shift, int nb, int* __restrict__ hc, int nbc,
+                                                int* __restrict__ hs, int nbs,
+                                                SnPk* __restrict__ pk,
+                                                unsigned short* __restrict__ rows) {
+  if ((int)blockIdx.x < nbc)
+    l1_cic<false>(blockIdx.x, M, T, C, shift, nb, hc, nbc, nullptr, nullptr, 0);
+  else
+    l1_sn_hist(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk, rows);
+}
+
+__global__ __launch_bounds__(256) void k_l1_scatter(Mesh M, TileGrid T, Particles C,
+                                                   Particles Sn, int shift, int nb,
+                                                   int* __restrict__ hc, int nbc,
+                                                   int* __restrict__ hs, int nbs,
+                                                   double4* __restrict__ ctmp,
+                                                   int* __restrict__ ctmp_tile, long long ccap,
+                                                   const SnPk* __restrict__ pk,
+                                                   int* __restrict__ stmp,
+                                                   int* __restrict__ stmp_tile, long long scap) {
+  if ((int)blockIdx.x < nbc)
+    l1_cic<true>(blockIdx.x, M, T, C, shift, nb, hc, nbc, ctmp, ctmp_tile, ccap);
+  else
+    l1_sn_scatter(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk, stmp, stmp_tile, scap);
 }
 
 // Level 2: one workgroup per coarse bucket sorts the bucket's records by
@@ -1533,43 +1567,65 @@ __global__ __launch_bounds__(256) void k_l2_hist(L2Geom G, const int* __restrict
 // record at its final position, grouped by tile; slice 0 of a bucket writes
 // the offsets of the bucket's tiles.
 template <class Rec>
-__global__ __launch_bounds__(256) void k_l2_scatter(L2Geom G, int kind,
-                                                   const int* __restrict__ slice_base,
-                                                   const int* __restrict__ hist2,
-                                                   const Rec* __restrict__ tmp,
-                                                   const int* __restrict__ tmp_tile,
-                                                   Rec* __restrict__ rec,
-                                                   int* __restrict__ rec_tile,
-                                                   int* __restrict__ off, long long cap) {
+__device__ __forceinline__ void l2_scatter_slice(int qg, int kind, const L2Geom& G,
+                                                 const int* __restrict__ slice_base,
+                                                 const int* __restrict__ hist2,
+                                                 const Rec* __restrict__ tmp,
+                                                 const int* __restrict__ tmp_tile,
+                                                 Rec* __restrict__ rec, int* __restrict__ rec_tile,
+                                                 int* __restrict__ off, long long cap) {
   extern __shared__ int h[];
   const int nf_max = 1 << G.shift;
-  const int q_begin = slice_base[kind * G.nb], q_end = slice_base[(kind + 1) * G.nb];
-  const long long kbase = hist2[(long long)nf_max * q_begin];  // first position of this kind
-  for (int qg = q_begin + blockIdx.x; qg < q_end; qg += gridDim.x) {
-    const int cc = find_slice(slice_base, 2 * G.nb, qg);
-    const int q = qg - slice_base[cc], ns = slice_base[cc + 1] - slice_base[cc];
-    const int c = cc - kind * G.nb;
-    long long start, end;
-    bucket_range(G, cc, start, end);
-    const long long e0 = start + (long long)q * kSlice, e1 = min(min(e0 + kSlice, end), cap);
-    const int t0 = c << G.shift;
-    const int nf = (int)min((long long)nf_max, G.ntiles - t0);
-    const long long o = (long long)nf_max * slice_base[cc];
-    for (int f = threadIdx.x; f < nf_max; f += blockDim.x) {
-      const int v = (int)(hist2[o + (long long)f * ns + q] - kbase);
-      h[f] = v;
-      if (q == 0 && f < nf) off[t0 + f] = v;
+  // first position of this kind
+  const long long kbase = hist2[(long long)nf_max * slice_base[kind * G.nb]];
+  const int cc = find_slice(slice_base, 2 * G.nb, qg);
+  const int q = qg - slice_base[cc], ns = slice_base[cc + 1] - slice_base[cc];
+  const int c = cc - kind * G.nb;
+  long long start, end;
+  bucket_range(G, cc, start, end);
+  const long long e0 = start + (long long)q * kSlice, e1 = min(min(e0 + kSlice, end), cap);
+  const int t0 = c << G.shift;
+  const int nf = (int)min((long long)nf_max, G.ntiles - t0);
+  const long long o = (long long)nf_max * slice_base[cc];
+  for (int f = threadIdx.x; f < nf_max; f += blockDim.x) {
+    const int v = (int)(hist2[o + (long long)f * ns + q] - kbase);
+    h[f] = v;
+    if (q == 0 && f < nf) off[t0 + f] = v;
+  }
+  __syncthreads();
+  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int tl = tmp_tile[e];
+    const int pos = atomicAdd(h + (tl - t0), 1);
+    if (pos < cap) {
+      rec[pos] = tmp[e];
+      if (rec_tile) rec_tile[pos] = tl;
     }
-    __syncthreads();
-    for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-      const int tl = tmp_tile[e];
-      const int pos = atomicAdd(h + (tl - t0), 1);
-      if (pos < cap) {
-        rec[pos] = tmp[e];
-        if (rec_tile) rec_tile[pos] = tl;
-      }
-    }
-    __syncthreads();
+  }
+  __syncthreads();
+}
+
+// Per slice (both kinds in one launch): LDS cursors from the scanned hist2
+// place every entry at its final position, grouped by tile; slice 0 of a
+// bucket writes the offsets of the bucket's tiles.
+__global__ __launch_bounds__(256) void k_l2_scatter(L2Geom G, const int* __restrict__ slice_base,
+                                                   const int* __restrict__ hist2,
+                                                   const double4* __restrict__ ctmp,
+                                                   const int* __restrict__ ctmp_tile,
+                                                   double4* __restrict__ crec,
+                                                   int* __restrict__ coff, long long ccap,
+                                                   const int* __restrict__ stmp,
+                                                   const int* __restrict__ stmp_tile,
+                                                   int* __restrict__ srec,
+                                                   int* __restrict__ srec_tile,
+                                                   int* __restrict__ soff, long long scap) {
+  const int split = slice_base[G.nb], total = slice_base[2 * G.nb];
+  for (int qg = blockIdx.x; qg < total; qg += gridDim.x) {
+    if (qg < split)
+      l2_scatter_slice<double4>(qg, 0, G, slice_base, hist2, ctmp, ctmp_tile, crec, nullptr,
+                                coff, ccap);
+    else
+      l2_scatter_slice<int>(qg, 1, G, slice_base, hist2, stmp, stmp_tile, srec, srec_tile, soff,
+                            scap);
   }
 }
 
@@ -2011,26 +2067,21 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
   int* hs = bw.hist + (long long)nb * nbc;
   const long long n = (long long)nb * (nbc + nbs);
   const size_t lds1 = (size_t)nb * sizeof(int);
-  if (has_c)
-    hipLaunchKernelGGL(k_l1_cic<false>, dim3(nbc), dim3(256), lds1, s, M, T, *cic, S, nb, hc,
-                       nbc, (double4*)nullptr, (int*)nullptr, 0ll);
-  if (has_s)
-    hipLaunchKernelGGL(k_l1_sn_hist, dim3(nbs), dim3(kBinChunkSn), lds1, s, M, T, *sn, S, nb, hs,
+  if (has_c || has_s)
+    hipLaunchKernelGGL(k_l1_hist, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
+                       has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc, hs,
                        nbs, bw.sn_pk, bw.sn_rows);
   // exclusive scan of both kinds' histograms, in place; hist[n] = total
   const int nblocks = (int)((n + kScanBlock - 1) / kScanBlock);
   hipLaunchKernelGGL(k_scan_local, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist, bw.hist,
-                     bw.block_sums, n);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, bw.block_sums, nblocks,
-                     bw.hist, n);
-  hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist,
-                     (const int*)bw.block_sums, n);
-  if (has_c)
-    hipLaunchKernelGGL(k_l1_cic<true>, dim3(nbc), dim3(256), lds1, s, M, T, *cic, S, nb, hc, nbc,
-                       bw.cic_tmp, bw.cic_tmp_tile, bw.cic_cap);
-  if (has_s)
-    hipLaunchKernelGGL(k_l1_sn_scatter, dim3(nbs), dim3(kBinChunkSn), lds1, s, M, T, *sn, S, nb,
-                       hs, nbs, (const SnPk*)bw.sn_pk, bw.sn_tmp, bw.sn_tmp_tile, bw.sn_cap);
+                     bw.block_sums, n, (const int*)nullptr, 0);
+  hipLaunchKernelGGL(k_scan_finish, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist,
+                     (const int*)bw.block_sums, n, (const int*)nullptr, 0);
+  if (has_c || has_s)
+    hipLaunchKernelGGL(k_l1_scatter, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
+                       has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc, hs,
+                       nbs, bw.cic_tmp, bw.cic_tmp_tile, bw.cic_cap, (const SnPk*)bw.sn_pk,
+                       bw.sn_tmp, bw.sn_tmp_tile, bw.sn_cap);
   // level 2: balanced slices of every bucket, both kinds
   L2Geom G;
   G.hist1 = bw.hist;
@@ -2041,9 +2092,10 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
   G.ntiles = T.ntiles;
   hipLaunchKernelGGL(k_l2_plan, dim3(1), dim3(1024), 0, s, G, bw.slice_base, bw.cic_off,
                      bw.sn_off, bw.heavy_count);
+  // hist2 is written in full for the slices in use ((slices in use) << S
+  // entries, known on the device), and only that much is scanned
   const long long n2 = ((long long)1 << S) * bw.max_slices;
-  hipError_t e = launch_zero(bw.hist2, n2 * (long long)sizeof(int), 256, s);
-  if (e != hipSuccess) return e;
+  const int* used = bw.slice_base + 2 * nb;
   const size_t lds2 = ((size_t)1 << S) * sizeof(int);
   const int grid2 = (int)std::min<long long>(bw.max_slices, (long long)M.num_cu * 8);
   hipLaunchKernelGGL(k_l2_hist, dim3(grid2), dim3(256), lds2, s, G, (const int*)bw.slice_base,
@@ -2051,21 +2103,14 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
                      bw.sn_cap, bw.hist2);
   const int nblocks2 = (int)((n2 + kScanBlock - 1) / kScanBlock);
   hipLaunchKernelGGL(k_scan_local, dim3(nblocks2), dim3(kScanBlock), 0, s, bw.hist2, bw.hist2,
-                     bw.block_sums2, n2);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, bw.block_sums2, nblocks2,
-                     bw.hist2, n2);
-  hipLaunchKernelGGL(k_scan_add, dim3(nblocks2), dim3(kScanBlock), 0, s, bw.hist2,
-                     (const int*)bw.block_sums2, n2);
-  if (has_c)
-    hipLaunchKernelGGL(k_l2_scatter<double4>, dim3(grid2), dim3(256), lds2, s, G, 0,
-                       (const int*)bw.slice_base, (const int*)bw.hist2,
-                       (const double4*)bw.cic_tmp, (const int*)bw.cic_tmp_tile, bw.cic_rec,
-                       (int*)nullptr, bw.cic_off, bw.cic_cap);
-  if (has_s)
-    hipLaunchKernelGGL(k_l2_scatter<int>, dim3(grid2), dim3(256), lds2, s, G, 1,
-                       (const int*)bw.slice_base, (const int*)bw.hist2,
-                       (const int*)bw.sn_tmp, (const int*)bw.sn_tmp_tile, bw.sn_rec,
-                       bw.sn_rec_tile, bw.sn_off, bw.sn_cap);
+                     bw.block_sums2, n2, used, S);
+  hipLaunchKernelGGL(k_scan_finish, dim3(nblocks2), dim3(kScanBlock), 0, s, bw.hist2,
+                     (const int*)bw.block_sums2, n2, used, S);
+  hipLaunchKernelGGL(k_l2_scatter, dim3(grid2), dim3(256), lds2, s, G, (const int*)bw.slice_base,
+                     (const int*)bw.hist2, (const double4*)bw.cic_tmp,
+                     (const int*)bw.cic_tmp_tile, bw.cic_rec, bw.cic_off, bw.cic_cap,
+                     (const int*)bw.sn_tmp, (const int*)bw.sn_tmp_tile, bw.sn_rec, bw.sn_rec_tile,
+                     bw.sn_off, bw.sn_cap);
   return hipGetLastError();
 }
 
