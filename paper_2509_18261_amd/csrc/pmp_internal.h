@@ -189,9 +189,9 @@ constexpr int kSlice = 4096;
 __host__ __device__ constexpr long long sn_ent_bytes(int tyz) {
   return (40 + 2ll * tyz * tyz + 15) / 16 * 16;
 }
-// Supernova entries per batch of the tile pass: about 8 KB of records.
+// Supernova entries per batch of the tile pass: about 6 KB of records.
 __host__ __device__ constexpr int tile_sn_batch(int tx, int tyz) {
-  return (void)tx, (int)(8192 / sn_ent_bytes(tyz));
+  return (void)tx, (int)(6144 / sn_ent_bytes(tyz));
 }
 // LDS of one tile workgroup: two accumulator channels of the tile with rows
 // padded to tx + 1 cells, then one batch of supernova entries.
