@@ -282,11 +282,16 @@ int pmp_autotune(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic, const
 #define PMP_PHASE_CIC 1           /* direct path: CIC atomics */
 #define PMP_PHASE_SN 2            /* direct path: supernova atomics */
 #define PMP_PHASE_SINK_DEPOSIT 3
-#define PMP_PHASE_FOLD 4
+#define PMP_PHASE_FOLD 4          /* ghost fold; in a fused step (fuse_apply), the
+                                     shell cells' fold + limiter + apply */
 #define PMP_PHASE_SINK_UPDATE 5
 #define PMP_PHASE_APPLY 6
-#define PMP_PHASE_BIN 7           /* binned path: count, scan, fill (6 launches) */
-#define PMP_PHASE_TILE 8          /* binned path: LDS tile accumulation and store */
+#define PMP_PHASE_BIN 7           /* binned path: two-level sort of (particle, tile)
+                                     pairs, supernova row tables and tile records,
+                                     chunk table of split tiles (several launches) */
+#define PMP_PHASE_TILE 8          /* binned path: the tile kernel alone (LDS
+                                     accumulation and store; in a fused step also
+                                     the interior cells' limiter + apply) */
 int pmp_profile_begin(pmp_ctx *ctx, int max_launches);
 int pmp_profile_end(pmp_ctx *ctx, double *ms, int64_t *launches);
 

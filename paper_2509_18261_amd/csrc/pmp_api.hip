@@ -698,6 +698,8 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
       PhaseTimer t(c, PMP_PHASE_BIN, s);
       PMP_HIP(launch_bin(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
                          c->tune.block, s));
+      PMP_HIP(launch_tile_prep(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
+                               c->tune, s));
     }
     {
       PhaseTimer t(c, PMP_PHASE_TILE, s);

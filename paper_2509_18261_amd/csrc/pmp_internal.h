@@ -212,6 +212,10 @@ hipError_t launch_cic_direct(const Mesh& M, const Particles& P, void* buf, int b
 // bracket the two halves for the profiler.
 hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
                       const Particles* sn, BinWork& bw, int block, hipStream_t s);
+// Supernova tile records and the chunk table of split tiles (after launch_bin).
+hipError_t launch_tile_prep(const Mesh& M, const TileGrid& T, const Particles* cic,
+                            const Particles* sn, const BinWork& bw, const pmp_tuning& t,
+                            hipStream_t s);
 // state non-null: the step's Steps 3 + 5 are fused in for owned cells at
 // least g from every face of their box (no ghost image reaches them); those
 // cells' buffer entries are left unwritten, and launch_fold_apply finishes

@@ -2114,19 +2114,11 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
   return hipGetLastError();
 }
 
-hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles* cic,
-                               const Particles* sn, const BinWork& bw, void* buf,
-                               const pmp_tuning& t, void* state, const Limits& L,
-                               hipStream_t s) {
+hipError_t launch_tile_prep(const Mesh& M, const TileGrid& T, const Particles* cic,
+                            const Particles* sn, const BinWork& bw, const pmp_tuning& t,
+                            hipStream_t s) {
   const int* coff = (cic && cic->n > 0) ? bw.cic_off : nullptr;
   const int* soff = (sn && sn->n > 0) ? bw.sn_off : nullptr;
-  const int block = t.tile_block;
-  const size_t lds = (size_t)tile_lds_bytes(T.t[0], T.t[1]);  // includes the record batch
-  long long grid = T.ntiles;
-  if (t.tile_grid_per_cu > 0)
-    grid = std::min<long long>(grid, (long long)M.num_cu * t.tile_grid_per_cu);
-  if (grid < 1) grid = 1;
-  if (grid > 0x7fffffffll) grid = 0x7fffffffll;
   const int egrid = grid_for(bw.sn_cap, 256, M.num_cu * 32);
 #define PMP_ENT(TYZ)                                                                        \
   if (soff)                                                                                 \
@@ -2143,6 +2135,22 @@ hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles
   hipLaunchKernelGGL(k_units, dim3(grid_for(T.ntiles, 256, M.num_cu * 16)), dim3(256), 0, s, T,
                      coff, bw.cic_cap, soff, bw.sn_cap, t.chunk_cic, t.chunk_sn, bw.heavy_base,
                      bw.heavy_unit, bw.heavy_count, bw.arrive, bw.slot_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles* cic,
+                               const Particles* sn, const BinWork& bw, void* buf,
+                               const pmp_tuning& t, void* state, const Limits& L,
+                               hipStream_t s) {
+  const int* coff = (cic && cic->n > 0) ? bw.cic_off : nullptr;
+  const int* soff = (sn && sn->n > 0) ? bw.sn_off : nullptr;
+  const int block = t.tile_block;
+  const size_t lds = (size_t)tile_lds_bytes(T.t[0], T.t[1]);  // includes the record batch
+  long long grid = T.ntiles;
+  if (t.tile_grid_per_cu > 0)
+    grid = std::min<long long>(grid, (long long)M.num_cu * t.tile_grid_per_cu);
+  if (grid < 1) grid = 1;
+  if (grid > 0x7fffffffll) grid = 0x7fffffffll;
 #define PMP_TILE(ACC, TT, TYZ)                                                                \
   hipLaunchKernelGGL((k_tile_deposit<ACC, TYZ>), dim3((unsigned)grid), dim3(block), lds, s, M, \
                      T, coff, (const double4*)bw.cic_rec, bw.cic_cap, soff,                   \
