@@ -261,9 +261,11 @@ int pmp_get_tuning(const pmp_ctx *ctx, pmp_tuning *out);
 int pmp_set_tuning(pmp_ctx *ctx, const pmp_tuning *t);
 
 /* Autotuner: times whole steps (2 warm-up, 5 timed, HIP events) for each
- * candidate tuning -- the direct path, and the binned path with a set of tile
- * shapes, workgroup sizes and a persistent tile grid -- on the given inputs,
- * and keeps the fastest.  The steps run on a scratch copy of the state (the
+ * candidate tuning on the given inputs and keeps the fastest.  Stage 1: the
+ * direct (global atomic) path and the binned (LDS-privatised) path with a set
+ * of tile shapes and workgroup sizes, with and without the fused apply (steps
+ * without sinks).  Stage 2, if the binned path won: the split thresholds
+ * chunk_cic / chunk_sn and the persistent tile grid cap around the winner.  The steps run on a scratch copy of the state (the
  * caller's state is left as it was; the buffer and sink_out are overwritten).
  * Synchronises the stream; allocates and frees the scratch copy.  best_ms
  * (host, may be NULL) receives the winning step time. */

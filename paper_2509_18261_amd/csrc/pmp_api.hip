@@ -1254,31 +1254,56 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
   pmp_tuning best_t = base;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     rc = fail(PMP_EDEVICE, "autotune: hipEventCreate failed");
-  for (size_t i = 0; i < cand.size() && rc == PMP_OK; ++i) {
-    // a shape this device cannot run (LDS) is skipped
-    if (pmp_set_tuning(c, &cand[i]) != PMP_OK) continue;
+  // time one candidate (2 warm steps, 5 timed); a shape this device cannot
+  // run (LDS) is skipped
+  auto time_one = [&](const pmp_tuning& cand_t) {
+    if (rc != PMP_OK || pmp_set_tuning(c, &cand_t) != PMP_OK) return;
     if (launch_copy(work, state, (long long)sbytes, s) != hipSuccess) {
       rc = fail(PMP_EDEVICE, "autotune: state copy failed");
-      break;
+      return;
     }
     for (int w = 0; w < 2 && rc == PMP_OK; ++w)
       rc = do_step(c, work, buf, cic, sn, sinks, limits, sink_out, s);
-    if (rc) break;
+    if (rc) return;
     const int reps = 5;
-    if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(PMP_EDEVICE, "event"); break; }
+    if (hipEventRecord(e0, s) != hipSuccess) {
+      rc = fail(PMP_EDEVICE, "event");
+      return;
+    }
     for (int r = 0; r < reps && rc == PMP_OK; ++r)
       rc = do_step(c, work, buf, cic, sn, sinks, limits, sink_out, s);
-    if (rc) break;
+    if (rc) return;
     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
       rc = fail(PMP_EDEVICE, "autotune: event timing failed");
-      break;
+      return;
     }
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     const double per = ms / reps;
     if (per < best) {
       best = per;
-      best_t = cand[i];
+      best_t = cand_t;
+    }
+  };
+  // stage 1: path, tile shape, workgroup size, fused apply
+  for (size_t i = 0; i < cand.size() && rc == PMP_OK; ++i) time_one(cand[i]);
+  // stage 2, binned path: the split thresholds (clustered inputs) and the
+  // persistent grid cap, around the stage-1 winner
+  if (rc == PMP_OK && best_t.deposit_path == 1) {
+    const pmp_tuning w1 = best_t;
+    const int chunks[][2] = {{1024, 128}, {16384, 2048}};
+    for (const auto& ch : chunks) {
+      pmp_tuning t = w1;
+      t.chunk_cic = ch[0];
+      t.chunk_sn = ch[1];
+      time_one(t);
+    }
+    const int grids[] = {4, 16};
+    const pmp_tuning w2 = best_t;
+    for (int gpc : grids) {
+      pmp_tuning t = w2;
+      t.tile_grid_per_cu = gpc;
+      time_one(t);
     }
   }
   if (e0) (void)hipEventDestroy(e0);
