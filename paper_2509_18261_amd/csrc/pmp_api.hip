@@ -188,6 +188,8 @@ struct pmp_ctx {
     T.tiles_axis = d_tiles_axis;
     T.geo = d_tile_geo;
     T.ntiles = ntiles;
+    T.gx = ghost;
+    T.wx = tile_dims[0] + 2 * ghost;
     return T;
   }
 };
@@ -283,7 +285,8 @@ int build_tiles(pmp_ctx* c, int tx, int tyz) {
     long long n = 1;
     for (int a = 0; a < 3; ++a) {
       const int p = c->dboxes[b].p[a];
-      axis[3 * b + a] = (p + t[a] - 1) / t[a];
+      // x: boundaries on owned cells g + k t (first and last take the ghosts)
+      axis[3 * b + a] = (a == 0) ? (c->dboxes[b].n[0] + t[0] - 1) / t[0] : (p + t[a] - 1) / t[a];
       n *= axis[3 * b + a];
     }
     prefix[b + 1] = prefix[b] + n;
@@ -307,8 +310,15 @@ int build_tiles(pmp_ctx* c, int tx, int tyz) {
           G.b = b;
           for (int a = 0; a < 3; ++a) {
             G.p[a] = d.p[a];
-            G.o[a] = tc[a] * t[a];
-            G.ext[a] = std::min(t[a], d.p[a] - G.o[a]);
+            if (a == 0) {
+              const int g0 = c->ghost;
+              G.o[0] = (tx == 0) ? 0 : g0 + tx * t[0];
+              const int end = (tx == ax[0] - 1) ? d.p[0] : g0 + (tx + 1) * t[0];
+              G.ext[0] = end - G.o[0];
+            } else {
+              G.o[a] = tc[a] * t[a];
+              G.ext[a] = std::min(t[a], d.p[a] - G.o[a]);
+            }
             G.glo[a] = G.o[a] - c->ghost + d.lo[a];
           }
         }
@@ -518,7 +528,7 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
   const long long slot_cap = 4ll * c->num_cu;
   // supernova tile entries for the current tile shape
   const long long ent_bytes = std::max<long long>(sn_cap, 1) * sn_ent_bytes(t[1]);
-  const long long partial = slot_cap * 2 * (long long)(t[0] + 1) * t[1] * t[2];
+  const long long partial = slot_cap * 2 * (long long)(t[0] + 2 * c->ghost + 1) * t[1] * t[2];
   if (cic_cap >= (1ll << 31) || sn_cap >= (1ll << 31) || hist >= (1ll << 31) ||
       hist2 >= (1ll << 31))
     return fail(PMP_ERANGE, "binned deposit: too many tile entries");
@@ -1199,7 +1209,7 @@ int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
   if (t->fuse_apply != 0 && t->fuse_apply != 1) return fail(PMP_EINVAL, "fuse_apply 0 or 1");
   if (t->reserved != 0) return fail(PMP_EINVAL, "reserved must be 0");
   {
-    const long long lds = tile_lds_bytes(t->tile_x, t->tile_yz);
+    const long long lds = tile_lds_bytes(t->tile_x, t->tile_yz, c->ghost);
     if (lds > c->max_lds)
       return fail(PMP_EINVAL, "tile %d x %d x %d needs %lld B of LDS, more than the %d B available",
                   t->tile_x, t->tile_yz, t->tile_yz, lds, c->max_lds);

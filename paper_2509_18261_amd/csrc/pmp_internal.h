@@ -90,9 +90,13 @@ struct Particles {
   const long long* box_off;
 };
 
-// Tiles covering the padded (ghost-zoned) box of every box: tile (tx,ty,tz)
-// of box b covers padded local cells [tx*TX, (tx+1)*TX) x ... clipped to the
-// padded extent.  Global tile id = tile_prefix[b] + (tz*nty + ty)*ntx + tx.
+// Tiles covering the padded (ghost-zoned) box of every box.  Along y and z,
+// tile t covers padded cells [t*T, (t+1)*T) clipped to the padded extent.
+// Along x the tile boundaries sit on owned cells, g + k*TX, so that a tile's
+// owned x rows start on the state's cache-line boundaries: tile k covers
+// [k == 0 ? 0 : g + k*TX, k == ntx-1 ? p : g + (k+1)*TX) with ntx =
+// ceil(n/TX), so the first and last take the ghost slabs (width <= TX + 2g).
+// Global tile id = tile_prefix[b] + (tz*nty + ty)*ntx + tx.
 // Geometry of one tile, fixed by the layout and the tile shape.
 struct alignas(16) TileGeo {
   long long boff;  // buffer offset of the tile's box
@@ -111,6 +115,8 @@ struct TileGrid {
   const int* tiles_axis;          // [nbox][3] device: tiles per axis
   const TileGeo* geo;             // [ntiles] device
   long long ntiles;
+  int gx;                         // ghost width (x tile boundaries at gx + k*TX)
+  int wx;                         // widest x tile, TX + 2 gx (LDS row width)
 };
 
 // A supernova as prepared once by the binning pass; tile entry lists hold
@@ -193,10 +199,11 @@ __host__ __device__ constexpr long long sn_ent_bytes(int tyz) {
 __host__ __device__ constexpr int tile_sn_batch(int tx, int tyz) {
   return (void)tx, (int)(6144 / sn_ent_bytes(tyz));
 }
-// LDS of one tile workgroup: two accumulator channels of the tile with rows
-// padded to tx + 1 cells, then one batch of supernova entries.
-__host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz) {
-  return 2ll * (tx + 1) * tyz * tyz * 8 + tile_sn_batch(tx, tyz) * sn_ent_bytes(tyz);
+// LDS of one tile workgroup: two accumulator channels of the widest tile
+// (tx + 2g cells along x) with rows padded by one cell, then one batch of
+// supernova entries.
+__host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz, int g) {
+  return 2ll * (tx + 2 * g + 1) * tyz * tyz * 8 + tile_sn_batch(tx, tyz) * sn_ent_bytes(tyz);
 }
 
 constexpr int kBinChunkCic = 1024;  // CIC particles per level-1 block

@@ -1039,8 +1039,15 @@ __device__ __forceinline__ bool tile_range(const DevBox& B, const TileGrid& T, c
   for (int a = 0; a < 3; ++a) {
     const int l = max(lo[a], 0), h = min(hi[a], B.p[a] - 1);
     if (l > h) return false;
-    tlo[a] = l / T.t[a];
-    thi[a] = h / T.t[a];
+    if (a == 0) {
+      // x boundaries at gx + k TX; the first and last tiles take the ghosts
+      const int ntx = (B.n[0] + T.t[0] - 1) / T.t[0];
+      tlo[0] = min(max(l - T.gx, 0) / T.t[0], ntx - 1);
+      thi[0] = min(max(h - T.gx, 0) / T.t[0], ntx - 1);
+    } else {
+      tlo[a] = l / T.t[a];
+      thi[a] = h / T.t[a];
+    }
   }
   return true;
 }
@@ -1643,7 +1650,7 @@ __global__ __launch_bounds__(256) void k_sn_ent(TileGrid T, const int* __restric
   constexpr int TY = TYZ, S = TYZ * TYZ;
   constexpr int YSH = (TYZ == 2) ? 1 : (TYZ == 4) ? 2 : 3;
   constexpr int GS = S < 16 ? S : 16;  // runs per group, stored as GS / 8 16-byte vectors
-  const int TXP = T.t[0] + 1;
+  const int TXP = T.wx + 1;
   const long long n = min((long long)soff[T.ntiles], cap);
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x) {
@@ -1824,8 +1831,9 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_last;
   LT* partial = reinterpret_cast<LT*>(partial_v);
-  const int TX = T.t[0];
+  const int TX = T.wx;  // widest tile along x (LDS rows); a tile's own width is G.ext[0]
   const int tcells = TX * TY * TZ;
+  const float inv_tx = 1.0f / (float)TX;
   // LDS rows of TX + 1 elements: the rows of one x column fall in different
   // banks, so lanes working on neighbouring rows do not conflict
   const int TXP = TX + 1;
@@ -1964,7 +1972,8 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
     const long long ncell = (long long)n0 * n1 * n2;
     const int sr = M.slot[0], se = M.slot[4];
     for (int c = threadIdx.x; c < tcells; c += blockDim.x) {
-      const int u = c % TX, v = (c / TX) & (TY - 1), w = c / (TX * TY);
+      const int row = small_div(c, TX, inv_tx);
+      const int u = c - row * TX, v = row & (TY - 1), w = row >> YSH;
       if (u >= G.ext[0] || v >= G.ext[1] || w >= G.ext[2]) continue;
       const int px = G.o[0] + u, py = G.o[1] + v, pz = G.o[2] + w;
       const int lc = (w * TY + v) * TXP + u;
@@ -2145,7 +2154,7 @@ hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles
   const int* coff = (cic && cic->n > 0) ? bw.cic_off : nullptr;
   const int* soff = (sn && sn->n > 0) ? bw.sn_off : nullptr;
   const int block = t.tile_block;
-  const size_t lds = (size_t)tile_lds_bytes(T.t[0], T.t[1]);  // includes the record batch
+  const size_t lds = (size_t)tile_lds_bytes(T.t[0], T.t[1], M.ghost);  // with the record batch
   long long grid = T.ntiles;
   if (t.tile_grid_per_cu > 0)
     grid = std::min<long long>(grid, (long long)M.num_cu * t.tile_grid_per_cu);
