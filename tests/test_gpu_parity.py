@@ -344,6 +344,21 @@ def test_step_edge_layouts(B, orc, idx, acc, fuse):
     step_vs_oracle(B, orc, w, acc, tuning={"deposit_path": 1, "fuse_apply": fuse})
 
 
+@pytest.mark.parametrize("acc", ["fix64", "f32"])
+def test_ghost_width_zero(B, orc, acc):
+    """g = 0: supernovae of radius below 1/2 (one cell each), every owned cell
+    interior; separate calls and the (fused and unfused) step."""
+    rng = np.random.default_rng(11)
+    dom = (70, 9, 6)
+    w = W.Workload("g0", *W.single_box(*dom), 0, 1.0,
+                   W.gas_state(rng, int(np.prod(dom)), np.float32).reshape(-1),
+                   sn=W._one_box(W.uniform_positions(rng, 300, dom), W.sn_fields(300, 0.4)))
+    for path in (1, 0):
+        check(B, orc, w, acc, tuning={"deposit_path": path})
+    for fuse in (1, 0):
+        step_vs_oracle(B, orc, w, acc, tuning={"deposit_path": 1, "fuse_apply": fuse})
+
+
 @pytest.mark.parametrize("fuse", [1, 0])
 @pytest.mark.parametrize("name", list(SMALL))
 def test_step_fused_split_tiles(B, orc, name, fuse):
