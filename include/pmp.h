@@ -289,7 +289,7 @@ int pmp_autotune(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic, const
 #define PMP_PHASE_SINK_UPDATE 5
 #define PMP_PHASE_APPLY 6
 #define PMP_PHASE_BIN 7           /* binned path: two-level sort of (particle, tile)
-                                     pairs, supernova row tables and tile records,
+                                     pairs, supernova member counts and shares,
                                      chunk table of split tiles (several launches) */
 #define PMP_PHASE_TILE 8          /* binned path: the tile kernel alone (LDS
                                      accumulation and store; in a fused step also

@@ -207,11 +207,8 @@ void free_bin_work(pmp_ctx* c) {
   (void)hipFree(w.sn_tmp);
   (void)hipFree(w.sn_tmp_tile);
   (void)hipFree(w.sn_rec);
-  (void)hipFree(w.sn_rec_tile);
-  (void)hipFree(w.sn_ent);
   (void)hipFree(w.sn_off);
   (void)hipFree(w.sn_pk);
-  (void)hipFree(w.sn_rows);
   (void)hipFree(w.slice_base);
   (void)hipFree(w.hist2);
   (void)hipFree(w.block_sums2);
@@ -526,8 +523,6 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
   const long long blocks2 = (hist2 + 1023) / 1024 + 1;
   // chunk slots for split tiles, each holding two channels of a padded LDS tile
   const long long slot_cap = 4ll * c->num_cu;
-  // supernova tile entries for the current tile shape
-  const long long ent_bytes = std::max<long long>(sn_cap, 1) * sn_ent_bytes(t[1]);
   const long long partial = slot_cap * 2 * (long long)(t[0] + 2 * c->ghost + 1) * t[1] * t[2];
   if (cic_cap >= (1ll << 31) || sn_cap >= (1ll << 31) || hist >= (1ll << 31) ||
       hist2 >= (1ll << 31))
@@ -537,7 +532,7 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
   const bool grow = hist > c->bw_hist || blocks > c->bw_blocks || c->ntiles + 1 > c->bw_tiles ||
                     cic_cap > c->bw.cic_cap || sn_cap > c->bw.sn_cap || n_sn > c->bw_nsn ||
                     hist2 > c->bw_hist2 || 2 * nb + 1 > c->bw_slice_base ||
-                    partial > c->bw_partial || ent_bytes > c->bw.sn_ent_bytes;
+                    partial > c->bw_partial;
   if (!grow) {
     c->bw.max_slices = (c->bw_hist2 - 1) >> shift;
     return PMP_OK;
@@ -580,12 +575,7 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
     rc = regrow(&w.sn_tmp, 0, sn_cap);
     if (!rc) rc = regrow(&w.sn_tmp_tile, 0, sn_cap);
     if (!rc) rc = regrow(&w.sn_rec, 0, sn_cap);
-    if (!rc) rc = regrow(&w.sn_rec_tile, 0, sn_cap);
     if (!rc) w.sn_cap = sn_cap;
-  }
-  if (!rc && ent_bytes > w.sn_ent_bytes) {
-    rc = regrow(reinterpret_cast<double**>(&w.sn_ent), 0, ent_bytes / 8);
-    if (!rc) w.sn_ent_bytes = ent_bytes;
   }
   if (!rc && hist2 > c->bw_hist2) {
     rc = regrow(&w.hist2, 0, hist2);
@@ -598,7 +588,6 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
   }
   if (!rc && n_sn > c->bw_nsn) {
     rc = regrow(&w.sn_pk, 0, n_sn);
-    if (!rc) rc = regrow(&w.sn_rows, 0, n_sn * (long long)kRowCap);
     if (!rc) c->bw_nsn = n_sn;
   }
   if (rc) free_bin_work(c);  // a failed allocation leaves no half-sized scratch behind

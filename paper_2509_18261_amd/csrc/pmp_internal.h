@@ -131,21 +131,15 @@ struct SnPk {
   int ti, tj, tk;        // padded-local remainder cell (ti < 0: none in the box)
 };
 
-// A supernova's share of one tile, prepared for the tile pass: the runs of
-// the tile's S = TY * TZ rows (row s: v = s mod TY, w = s / TY) clipped to
-// the tile, as ua | ub << 8 in tile-local x (0x00ff: none).
-template <int S> struct alignas(16) SnEnt {
+// A supernova entry of one tile as the tile pass holds it in LDS: the row
+// test's inputs and the member share.
+struct alignas(16) SnTile {
+  double x, y, z, r2;     // centre and r^2
   double vr, ve;          // member share (for fixed point: the quanta's bits)
-  long long remr, reme;   // fixed point: remainder, added at cell tgt
-  unsigned short runs[S];  // 16-byte aligned
-  int tgt;                // LDS cell of the remainder in this tile, or -1
-  int pad;
+  int lo, hi;             // candidate cells along x, global (host cell alone: that cell)
+  int host;               // the host cell alone takes the deposit
+  unsigned rows;          // candidate tile rows: vlo | vhi << 8 | wlo << 16 | whi << 24
 };
-
-// Member runs of a supernova's sphere rows, stored once per particle by the
-// binning pass: entry (j - lo_y) + cy (k - lo_z) of the candidate box holds
-// (a - lo_x) | (b - lo_x) << 8, or 0x00ff for an empty row.
-constexpr int kRowCap = 256;
 
 // Scratch for the binned deposit, owned by the context.  (particle, tile)
 // pairs are bucket-sorted in two levels with LDS-only ranking: level 1 moves
@@ -165,12 +159,8 @@ struct BinWork {
   int* sn_tmp;           // supernova entries: particle indices
   int* sn_tmp_tile;
   int* sn_rec;           // sorted by tile: particle index
-  int* sn_rec_tile;      // sorted by tile: tile
-  void* sn_ent;          // sorted by tile: SnEnt<S> records
-  long long sn_ent_bytes;
   int* sn_off;          // [ntiles + 1]
   SnPk* sn_pk;          // [n_sn]
-  unsigned short* sn_rows;  // [n_sn * kRowCap]
   long long cic_cap, sn_cap;
   // level 2 works on slices of at most kSlice records of one bucket
   int* slice_base;      // [2 * nbuckets + 1]: first slice of each (kind, bucket)
@@ -190,20 +180,13 @@ struct BinWork {
 
 constexpr int kSlice = 4096;
 
-// Bytes of one supernova tile entry for tiles of edge tyz along y and z
-// (a multiple of 16, so that batches of entries copy as 16-byte vectors).
-__host__ __device__ constexpr long long sn_ent_bytes(int tyz) {
-  return (40 + 2ll * tyz * tyz + 15) / 16 * 16;
-}
-// Supernova entries per batch of the tile pass: about 6 KB of records.
-__host__ __device__ constexpr int tile_sn_batch(int tx, int tyz) {
-  return (void)tx, (int)(6144 / sn_ent_bytes(tyz));
-}
+// Supernova entries per batch of the tile pass: one per lane of a wavefront.
+constexpr int kTileSnBatch = 64;
 // LDS of one tile workgroup: two accumulator channels of the widest tile
 // (tx + 2g cells along x) with rows padded by one cell, then one batch of
 // supernova entries.
 __host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz, int g) {
-  return 2ll * (tx + 2 * g + 1) * tyz * tyz * 8 + tile_sn_batch(tx, tyz) * sn_ent_bytes(tyz);
+  return 2ll * (tx + 2 * g + 1) * tyz * tyz * 8 + (long long)kTileSnBatch * (long long)sizeof(SnTile);
 }
 
 constexpr int kBinChunkCic = 1024;  // CIC particles per level-1 block

@@ -137,12 +137,15 @@ __device__ __forceinline__ double dist2(double x, double y, double z, int i, int
   return (ddx * ddx + ddy * ddy) + ddz * ddz;
 }
 
-// Candidate range along one axis for a sphere of radius r centred at p: a
-// superset of the cells with |i + 1/2 - p| <= r (membership is decided by
-// dist2 alone).
+// Candidate range along one axis for a sphere of radius r >= 0 centred at p:
+// a superset of the cells whose centre passes the test dist2 <= r^2, which
+// alone decides membership.  A member i has |i + 1/2 - p| <= r (1 + 3 eps)
+// (every rounding in the test is relative), so it lies in
+// [p - r - 1/2, p + r - 1/2] up to far less than the 1e-6 margin, which also
+// covers rounding of the bounds.  The range may be empty (hi = lo - 1).
 __device__ __forceinline__ void sphere_range(double p, double r, int& lo, int& hi) {
-  lo = (int)floor(p - r - 0.5) - 1;
-  hi = (int)floor(p + r - 0.5) + 1;
+  lo = (int)ceil(p - r - 0.5 - 1e-6);
+  hi = (int)floor(p + r - 0.5 + 1e-6);
 }
 
 
@@ -243,28 +246,55 @@ __device__ __forceinline__ double row_d2(const Sphere& S, int i, double y2, doub
   return (ddx * ddx + y2) + z2;
 }
 
-// Members [a, b] of the row with rounded squared offsets y2, z2.
-__device__ __forceinline__ void row_members_yz(const Sphere& S, double y2, double z2, int& a,
-                                               int& b) {
-  const int c = (int)floor(S.x);
-  if (!(row_d2(S, c, y2, z2) <= S.r2)) {
+// Members [a, b] of the row with rounded squared offsets y2, z2 of a sphere
+// centred at x along the row, with r2 = r^2 and candidate cells [lo, hi].
+// The run's ends are estimated in single precision; the exact test at the
+// nearest cell c, at both estimated ends and at their outer neighbours runs
+// as five independent evaluations, and only an estimate that is off (rare)
+// walks further.
+__device__ __forceinline__ void row_run(double x, double r2, int lo, int hi, double y2,
+                                        double z2, int& a, int& b) {
+  auto d2 = [&](int i) {
+    const double ddx = ((double)i + 0.5) - x;
+    return (ddx * ddx + y2) + z2;
+  };
+  const int c = (int)floor(x);
+  const float w2 = (float)(r2 - (y2 + z2));
+  const float w = w2 > 0.0f ? sqrtf(w2) : 0.0f;
+  const float xc = (float)(x - 0.5);
+  int aa = (int)ceilf(xc - w), bb = (int)floorf(xc + w);
+  aa = min(max(aa, lo), c);
+  bb = max(min(bb, hi), c);
+  const bool in_c = d2(c) <= r2;
+  const bool in_a = d2(aa) <= r2, out_a = !(aa > lo && d2(aa - 1) <= r2);
+  const bool in_b = d2(bb) <= r2, out_b = !(bb < hi && d2(bb + 1) <= r2);
+  if (!in_c) {
     a = 1;
     b = 0;
     return;
   }
-  // the run's ends are estimated in single precision and settled exactly below
-  const float w2 = (float)(S.r2 - (y2 + z2));
-  const float w = w2 > 0.0f ? sqrtf(w2) : 0.0f;
-  const float xc = (float)(S.x - 0.5);
-  int aa = (int)ceilf(xc - w), bb = (int)floorf(xc + w);
-  aa = min(max(aa, S.lo[0]), c);
-  bb = max(min(bb, S.hi[0]), c);
-  while (aa > S.lo[0] && row_d2(S, aa - 1, y2, z2) <= S.r2) --aa;
-  while (aa < c && !(row_d2(S, aa, y2, z2) <= S.r2)) ++aa;
-  while (bb < S.hi[0] && row_d2(S, bb + 1, y2, z2) <= S.r2) ++bb;
-  while (bb > c && !(row_d2(S, bb, y2, z2) <= S.r2)) --bb;
+  // c is a member, so aa < c when aa is not, and bb > c when bb is not
+  if (!out_a) {
+    --aa;
+    while (aa > lo && d2(aa - 1) <= r2) --aa;
+  } else if (!in_a) {
+    ++aa;
+    while (aa < c && !(d2(aa) <= r2)) ++aa;
+  }
+  if (!out_b) {
+    ++bb;
+    while (bb < hi && d2(bb + 1) <= r2) ++bb;
+  } else if (!in_b) {
+    --bb;
+    while (bb > c && !(d2(bb) <= r2)) --bb;
+  }
   a = aa;
   b = bb;
+}
+
+__device__ __forceinline__ void row_members_yz(const Sphere& S, double y2, double z2, int& a,
+                                               int& b) {
+  row_run(S.x, S.r2, S.lo[0], S.hi[0], y2, z2, a, b);
 }
 
 // Members [a, b] of row (j, k); empty when a > b.
@@ -1021,13 +1051,15 @@ __device__ __forceinline__ void cic_box(const DevBox& B, int g, double x, double
 }
 
 // Padded-local cell range holding every cell whose centre can pass the
-// sphere test (the 1e-6 margin covers rounding of the test at the edge).
+// sphere test: a member i has |i + 1/2 - p| <= r (1 + 3 eps) (each rounding
+// in the test is relative), so i lies in [p - r - 1/2, p + r - 1/2] up to far
+// less than the 1e-6 margin, which also covers rounding of the bounds.
 __device__ __forceinline__ void sphere_box(const DevBox& B, int g, double x, double y, double z,
                                            double r, int lo[3], int hi[3]) {
   const double p[3] = {x, y, z};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    lo[a] = (int)floor(p[a] - r - 0.5 - 1e-6) - B.lo[a] + g;
+    lo[a] = (int)ceil(p[a] - r - 0.5 - 1e-6) - B.lo[a] + g;
     hi[a] = (int)floor(p[a] + r - 0.5 + 1e-6) - B.lo[a] + g;
   }
 }
@@ -1235,27 +1267,18 @@ __device__ __forceinline__ bool sn_tiles(const Mesh& M, const TileGrid& T, const
   return tile_range(B, T, slo, shi, tlo, thi);
 }
 
-// Whether a sphere's member runs fit a row table.
-__device__ __forceinline__ bool sn_has_table(const Sphere& S) {
-  return S.nrows <= kRowCap && S.hi[0] - S.lo[0] < 255;
-}
-
-// Level 1, supernovae, histogram pass: one lane per particle (blocks of one
-// wavefront, kBinChunkSn particles).  The lane walks its sphere's candidate
-// rows in (k, j) order: it counts the members N (-1 when no centre lies
-// within r and the host cell takes the deposit; 0 when the particle is
-// skipped), finds the fixed-point remainder cell (host if a member, else the
-// first member in (k, j, i) order) and fills its row table through an LDS
-// chunk written out as 16-byte vectors; then it writes the particle's SnPk
-// and counts it into the buckets of every tile its sphere touches.
+// Level 1, supernovae, histogram pass: one lane per particle (kBinChunkSn
+// particles per block).  The lane walks its sphere's candidate rows in (k, j)
+// order: it counts the members N (-1 when no centre lies within r and the
+// host cell takes the deposit; 0 when the particle is skipped) and finds the
+// fixed-point remainder cell (host if a member, else the first member in
+// (k, j, i) order); then it writes the particle's SnPk and counts it into the
+// buckets of every tile its sphere touches.
 __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGrid& T,
                                            const Particles& P, int shift, int nb,
                                            int* __restrict__ hist, int nblk,
-                                           SnPk* __restrict__ pk,
-                                           unsigned short* __restrict__ sn_rows) {
-  constexpr int CH = 32;  // rows per staged chunk
+                                           SnPk* __restrict__ pk) {
   extern __shared__ int h[];
-  __shared__ unsigned short st[CH][kBinChunkSn];
   const int g = M.ghost;
   const int col = hist_col(blk, nblk);
   for (int c = threadIdx.x; c < nb; c += blockDim.x) h[c] = 0;
@@ -1296,8 +1319,6 @@ __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGri
   Sphere Sp;
   sphere_init(Sp, x, y, z, ok ? r : 0.0);
   const int nrows = ok ? Sp.nrows : 0;
-  const bool table = ok && sn_has_table(Sp);
-  unsigned short* rt = sn_rows + (long long)kRowCap * (live ? p : 0);
   // a row whose rounded dy^2 + dz^2 exceeds r^2 holds no member: the
   // rounded test value of each of its cells is at least that sum (the terms
   // are non-negative and rounding is monotone)
@@ -1306,46 +1327,26 @@ __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGri
   const int plo[3] = {B.lo[0] - g, B.lo[1] - g, B.lo[2] - g};
   const int phi[3] = {B.lo[0] + B.n[0] + g - 1, B.lo[1] + B.n[1] + g - 1,
                       B.lo[2] + B.n[2] + g - 1};
-  int maxrows = nrows;
-  maxrows = group_max<kWave>(maxrows);
   int jj = 0, kk = 0;  // row t = jj + cy * kk
-  for (int t0 = 0; t0 < maxrows; t0 += CH) {
-    for (int dt = 0; dt < CH; ++dt) {
-      const int t = t0 + dt;
-      unsigned short v = 0x00ff;
-      if (t < nrows) {
-        const int j = Sp.lo[1] + jj, k = Sp.lo[2] + kk;
-        const double dy = ((double)j + 0.5) - Sp.y, dz = ((double)k + 0.5) - Sp.z;
-        const double y2 = dy * dy, z2 = dz * dz;
-        if (y2 + z2 <= Sp.r2) {
-          int a, bb;
-          row_members_yz(Sp, y2, z2, a, bb);
-          if (a <= bb) {
-            v = (unsigned short)((a - Sp.lo[0]) | ((bb - Sp.lo[0]) << 8));
-            cnt += bb - a + 1;
-            if (key == 0x7fffffff) key = (t << 12) | (a - Sp.lo[0]);
-            hm |= (j == hc[1] && k == hc[2] && a <= hc[0] && hc[0] <= bb);
-            // a member outside the padded box
-            out |= a < plo[0] || bb > phi[0] || j < plo[1] || j > phi[1] || k < plo[2] ||
-                   k > phi[2];
-          }
-        }
-        if (++jj == Sp.cy) {
-          jj = 0;
-          ++kk;
-        }
+  for (int t = 0; t < nrows; ++t) {
+    const int j = Sp.lo[1] + jj, k = Sp.lo[2] + kk;
+    const double dy = ((double)j + 0.5) - Sp.y, dz = ((double)k + 0.5) - Sp.z;
+    const double y2 = dy * dy, z2 = dz * dz;
+    if (y2 + z2 <= Sp.r2) {
+      int a, bb;
+      row_members_yz(Sp, y2, z2, a, bb);
+      if (a <= bb) {
+        cnt += bb - a + 1;
+        if (key == 0x7fffffff) key = (t << 12) | (a - Sp.lo[0]);
+        hm |= (j == hc[1] && k == hc[2] && a <= hc[0] && hc[0] <= bb);
+        // a member outside the padded box
+        out |= a < plo[0] || bb > phi[0] || j < plo[1] || j > phi[1] || k < plo[2] ||
+               k > phi[2];
       }
-      st[dt][threadIdx.x] = v;
     }
-    // the lane's own 32 entries, out as four 16-byte stores (own table only)
-    if (table && t0 < nrows) {
-      unsigned w[CH / 2];
-#pragma unroll
-      for (int q = 0; q < CH / 2; ++q)
-        w[q] = (unsigned)st[2 * q][threadIdx.x] | ((unsigned)st[2 * q + 1][threadIdx.x] << 16);
-      uint4* dst = reinterpret_cast<uint4*>(rt + t0);
-#pragma unroll
-      for (int q = 0; q < CH / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+    if (++jj == Sp.cy) {
+      jj = 0;
+      ++kk;
     }
   }
   int N = cnt;
@@ -1443,12 +1444,11 @@ __device__ __forceinline__ void l1_sn_scatter(int blk, const Mesh& M, const Tile
 __global__ __launch_bounds__(256) void k_l1_hist(Mesh M, TileGrid T, Particles C, Particles Sn,
                                                 int shift, int nb, int* __restrict__ hc, int nbc,
                                                 int* __restrict__ hs, int nbs,
-                                                SnPk* __restrict__ pk,
-                                                unsigned short* __restrict__ rows) {
+                                                SnPk* __restrict__ pk) {
   if ((int)blockIdx.x < nbc)
     l1_cic<false>(blockIdx.x, M, T, C, shift, nb, hc, nbc, nullptr, nullptr, 0);
   else
-    l1_sn_hist(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk, rows);
+    l1_sn_hist(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk);
 }
 
 __global__ __launch_bounds__(256) void k_l1_scatter(Mesh M, TileGrid T, Particles C,
@@ -1579,8 +1579,8 @@ __device__ __forceinline__ void l2_scatter_slice(int qg, int kind, const L2Geom&
                                                  const int* __restrict__ hist2,
                                                  const Rec* __restrict__ tmp,
                                                  const int* __restrict__ tmp_tile,
-                                                 Rec* __restrict__ rec, int* __restrict__ rec_tile,
-                                                 int* __restrict__ off, long long cap) {
+                                                 Rec* __restrict__ rec, int* __restrict__ off,
+                                                 long long cap) {
   extern __shared__ int h[];
   const int nf_max = 1 << G.shift;
   // first position of this kind
@@ -1603,10 +1603,7 @@ __device__ __forceinline__ void l2_scatter_slice(int qg, int kind, const L2Geom&
   for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int tl = tmp_tile[e];
     const int pos = atomicAdd(h + (tl - t0), 1);
-    if (pos < cap) {
-      rec[pos] = tmp[e];
-      if (rec_tile) rec_tile[pos] = tl;
-    }
+    if (pos < cap) rec[pos] = tmp[e];
   }
   __syncthreads();
 }
@@ -1623,112 +1620,13 @@ __global__ __launch_bounds__(256) void k_l2_scatter(L2Geom G, const int* __restr
                                                    const int* __restrict__ stmp,
                                                    const int* __restrict__ stmp_tile,
                                                    int* __restrict__ srec,
-                                                   int* __restrict__ srec_tile,
                                                    int* __restrict__ soff, long long scap) {
   const int split = slice_base[G.nb], total = slice_base[2 * G.nb];
   for (int qg = blockIdx.x; qg < total; qg += gridDim.x) {
     if (qg < split)
-      l2_scatter_slice<double4>(qg, 0, G, slice_base, hist2, ctmp, ctmp_tile, crec, nullptr,
-                                coff, ccap);
+      l2_scatter_slice<double4>(qg, 0, G, slice_base, hist2, ctmp, ctmp_tile, crec, coff, ccap);
     else
-      l2_scatter_slice<int>(qg, 1, G, slice_base, hist2, stmp, stmp_tile, srec, srec_tile, soff,
-                            scap);
-  }
-}
-
-// One thread per sorted supernova entry (particle p in tile t): the share,
-// the fixed-point remainder and its cell when the cell is in t, and the runs
-// of t's rows clipped to t (from the particle's row table, or found row by
-// row for a sphere too large for one).
-template <int TYZ>
-__global__ __launch_bounds__(256) void k_sn_ent(TileGrid T, const int* __restrict__ soff,
-                                               long long cap, const int* __restrict__ sidx,
-                                               const int* __restrict__ stile,
-                                               const SnPk* __restrict__ pk,
-                                               const unsigned short* __restrict__ rows,
-                                               SnEnt<TYZ * TYZ>* __restrict__ ent) {
-  constexpr int TY = TYZ, S = TYZ * TYZ;
-  constexpr int YSH = (TYZ == 2) ? 1 : (TYZ == 4) ? 2 : 3;
-  constexpr int GS = S < 16 ? S : 16;  // runs per group, stored as GS / 8 16-byte vectors
-  const int TXP = T.wx + 1;
-  const long long n = min((long long)soff[T.ntiles], cap);
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int p = sidx[e];
-    const TileGeo G = T.geo[stile[e]];
-    const SnPk R = pk[p];
-    const int xlo = G.glo[0], ylo = G.glo[1], zlo = G.glo[2];
-    SnEnt<S>& E = ent[e];
-    int tgt;
-    {
-      const int lu = R.ti - G.o[0], lv = R.tj - G.o[1], lw = R.tk - G.o[2];
-      const bool in = R.ti >= 0 && (unsigned)lu < (unsigned)G.ext[0] &&
-                      (unsigned)lv < (unsigned)G.ext[1] && (unsigned)lw < (unsigned)G.ext[2];
-      tgt = in ? (lw * TY + lv) * TXP + lu : -1;
-    }
-    *reinterpret_cast<double4*>(&E.vr) = make_double4(R.vr, R.ve, __longlong_as_double(R.remr),
-                                                      __longlong_as_double(R.reme));
-    Sphere Sp;
-    sphere_init(Sp, R.x, R.y, R.z, R.n < 0 ? 0.0 : R.r);
-    const bool table = R.n >= 0 && sn_has_table(Sp);
-    const unsigned short* rt = rows + (long long)kRowCap * p;
-    const int hi = (int)floor(R.x), hj = (int)floor(R.y), hk = (int)floor(R.z);
-    // runs of the tile's rows, GS at a time: from the row table (entries
-    // loaded together), found row by row for a sphere too large for one, or
-    // the host cell alone
-#pragma unroll
-    for (int g0 = 0; g0 < S; g0 += GS) {
-      unsigned raw[GS];
-#pragma unroll
-      for (int sl = 0; sl < GS; ++sl) {
-        const int v = (g0 + sl) & (TY - 1), w = (g0 + sl) >> YSH;
-        const int j = ylo + v, k = zlo + w;
-        const bool cand = v < G.ext[1] && w < G.ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] &&
-                          k >= Sp.lo[2] && k <= Sp.hi[2];
-        raw[sl] = (cand && table) ? rt[(j - Sp.lo[1]) + Sp.cy * (k - Sp.lo[2])] : 0x00ffu;
-      }
-      unsigned packed[GS / 2];
-#pragma unroll
-      for (int sl = 0; sl < GS; ++sl) {
-        const int v = (g0 + sl) & (TY - 1), w = (g0 + sl) >> YSH;
-        int a = 1, bb = 0;
-        if (R.n < 0) {
-          if (ylo + v == hj && zlo + w == hk && v < G.ext[1] && w < G.ext[2]) a = bb = hi;
-        } else if (raw[sl] != 0x00ffu) {
-          a = Sp.lo[0] + (int)(raw[sl] & 255u);
-          bb = Sp.lo[0] + (int)(raw[sl] >> 8);
-        }
-        const int ua = max(a - xlo, 0), ub = min(bb - xlo, G.ext[0] - 1);
-        const unsigned run = (a <= bb && ua <= ub) ? (unsigned)(ua | (ub << 8)) : 0x00ffu;
-        if (sl & 1) packed[sl / 2] |= run << 16;
-        else packed[sl / 2] = run;
-      }
-      if constexpr (GS >= 8) {
-#pragma unroll
-        for (int q = 0; q < GS / 8; ++q)
-          *reinterpret_cast<uint4*>(&E.runs[g0 + 8 * q]) =
-              make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
-      } else {
-        *reinterpret_cast<uint2*>(&E.runs[g0]) = make_uint2(packed[0], packed[1]);
-      }
-    }
-    if (R.n >= 0 && !table) {
-      // a sphere too large for a row table: runs found row by row
-#pragma unroll 1
-      for (int sl = 0; sl < S; ++sl) {
-        const int v = sl & (TY - 1), w = sl >> YSH;
-        const int j = ylo + v, k = zlo + w;
-        int a = 1, bb = 0;
-        if (v < G.ext[1] && w < G.ext[2] && j >= Sp.lo[1] && j <= Sp.hi[1] && k >= Sp.lo[2] &&
-            k <= Sp.hi[2])
-          row_members(Sp, j, k, a, bb);
-        const int ua = max(a - xlo, 0), ub = min(bb - xlo, G.ext[0] - 1);
-        E.runs[sl] = (a <= bb && ua <= ub) ? (unsigned short)(ua | (ub << 8))
-                                           : (unsigned short)0x00ff;
-      }
-    }
-    E.tgt = tgt;
-    E.pad = 0;
+      l2_scatter_slice<int>(qg, 1, G, slice_base, hist2, stmp, stmp_tile, srec, soff, scap);
   }
 }
 
@@ -1799,9 +1697,11 @@ template <> __device__ __forceinline__ long long from_lds<long long>(unsigned lo
 template <class T> __device__ __forceinline__ T from_lds(double v) { return (T)v; }
 
 // One workgroup per work unit (a whole tile, or one chunk of a split tile):
-// CIC entries one per thread, supernova work one thread per (entry, tile
-// row) adding the row's run from the entry's record; every addition goes to
-// the LDS accumulators.  Then every present channel of every cell of the
+// CIC entries one per thread; supernovae in batches of up to one wavefront:
+// one lane per entry gathers its particle's record, clips the sphere's
+// candidate rows to the tile and adds the fixed-point remainder; then one
+// thread per (entry, tile row) finds the row's member run with the exact row
+// test and adds it.  Every addition goes to the LDS accumulators.  Then every present channel of every cell of the
 // tile is stored once (channels without sources as zero).  Membership,
 // shares and fixed-point remainders are the same as in the direct kernels.
 template <int ACC, int TYZ>
@@ -1810,7 +1710,8 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
                                                       const double4* __restrict__ crec,
                                                       long long ccap,
                                                       const int* __restrict__ soff,
-                                                      const SnEnt<TYZ * TYZ>* __restrict__ ent,
+                                                      const int* __restrict__ sidx,
+                                                      const SnPk* __restrict__ pk,
                                                       long long scap, int cc, int cs,
                                                       const int* __restrict__ heavy_base,
                                                       const int2* __restrict__ heavy_unit,
@@ -1840,9 +1741,10 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
   const int lcells = TXP * TY * TZ;
   LT* a0 = reinterpret_cast<LT*>(smem);
   LT* a4 = a0 + lcells;
-  // the current batch of the tile's supernova records, copied from global
-  SnEnt<S>* bent = reinterpret_cast<SnEnt<S>*>(a4 + lcells);
-  const int NB = tile_sn_batch(TX, TYZ);
+  // the current batch of the tile's supernovae
+  constexpr int NB = kTileSnBatch;
+  static_assert(NB <= kWave && sizeof(SnTile) % 16 == 0, "one batch entry per lane of a wave");
+  SnTile* bent = reinterpret_cast<SnTile*>(a4 + lcells);
   // work units: the chunks of split tiles first (the longest units), then
   // every other tile whole, in tile order
   const long long nheavy = min((long long)*heavy_count, slot_cap);
@@ -1882,16 +1784,54 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
     long long spos = s0;
     bool first = true;
     while (first || spos < s1) {
-      // the batch's records are contiguous: one cooperative 16-byte copy
+      // the batch's supernovae, one lane of the first wavefront each
       const int nq = (int)min((long long)NB, s1 - spos);
-      {
-        const uint4* src = reinterpret_cast<const uint4*>(ent + spos);
-        uint4* dst = reinterpret_cast<uint4*>(bent);
-        const int n16 = nq * (int)(sizeof(SnEnt<S>) / 16);
-        for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+      if (threadIdx.x < kWave) {
+        const int q = threadIdx.x;
+        if (q < nq) {
+          const SnPk& R = pk[sidx[spos + q]];
+          Sphere Sp;
+          sphere_init(Sp, R.x, R.y, R.z, R.r);
+          SnTile E;
+          E.x = R.x;
+          E.y = R.y;
+          E.z = R.z;
+          E.r2 = Sp.r2;
+          E.vr = R.vr;
+          E.ve = R.ve;
+          E.lo = Sp.lo[0];
+          E.hi = Sp.hi[0];
+          E.host = R.n < 0;
+          int lo1 = Sp.lo[1], hi1 = Sp.hi[1], lo2 = Sp.lo[2], hi2 = Sp.hi[2];
+          if (E.host) {
+            // the host cell alone
+            E.lo = E.hi = (int)floor(R.x);
+            lo1 = hi1 = (int)floor(R.y);
+            lo2 = hi2 = (int)floor(R.z);
+          } else if (R.n == 0) {
+            hi1 = lo1 - 1;
+          }
+          // candidate rows inside the tile: v in [vlo, vhi], w in [wlo, whi]
+          const int vlo = max(lo1 - G.glo[1], 0), vhi = min(hi1 - G.glo[1], G.ext[1] - 1);
+          const int wlo = max(lo2 - G.glo[2], 0), whi = min(hi2 - G.glo[2], G.ext[2] - 1);
+          E.rows = (vlo <= vhi && wlo <= whi)
+                       ? (unsigned)(vlo | (vhi << 8) | (wlo << 16) | (whi << 24))
+                       : 0x000000ffu;
+          bent[q] = E;
+          if constexpr (FIXED) {
+            // the remainder, at its cell when the cell is in this tile
+            const int lu = R.ti - G.o[0], lv = R.tj - G.o[1], lw = R.tk - G.o[2];
+            if (R.ti >= 0 && (unsigned)lu < (unsigned)G.ext[0] &&
+                (unsigned)lv < (unsigned)G.ext[1] && (unsigned)lw < (unsigned)G.ext[2]) {
+              const int tgt = (lw * TY + lv) * TXP + lu;
+              lds_add(a0 + tgt, R.remr);
+              lds_add(a4 + tgt, R.reme);
+            }
+          }
+        }
       }
       if (first) {
-        // CIC entries (their loads overlap the copy)
+        // CIC entries
         for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
           const double4 CR = crec[e];
           const int h[3] = {(int)floor(CR.x), (int)floor(CR.y), (int)floor(CR.z)};
@@ -1906,13 +1846,26 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
         first = false;
       }
       __syncthreads();
-      // supernova rows, from LDS
+      // supernova rows: the member run of tile row (v, w), clipped to the tile
       for (int it = threadIdx.x; it < (nq << SSH); it += blockDim.x) {
-        const SnEnt<S>& E = bent[it >> SSH];
+        const SnTile& E = bent[it >> SSH];
         const int sl = it & (S - 1);
-        const unsigned run = E.runs[sl];
-        const int ua = (int)(run & 255u), ub = (int)(run >> 8);
         const int v = sl & (TY - 1), w = sl >> YSH;
+        const unsigned rr = E.rows;
+        int a = 1, b = 0;
+        if (v < (int)(rr & 255u) || v > (int)((rr >> 8) & 255u) || w < (int)((rr >> 16) & 255u) ||
+            w > (int)(rr >> 24)) {
+          // not a candidate row (an empty range is stored as vlo = 255 > vhi)
+        } else if (E.host) {
+          a = b = E.lo;
+        } else {
+          // rows whose rounded dy^2 + dz^2 exceeds r^2 hold no member
+          const double dy = ((double)(G.glo[1] + v) + 0.5) - E.y;
+          const double dz = ((double)(G.glo[2] + w) + 0.5) - E.z;
+          const double y2 = dy * dy, z2 = dz * dz;
+          if (y2 + z2 <= E.r2) row_run(E.x, E.r2, E.lo, E.hi, y2, z2, a, b);
+        }
+        const int ua = max(a - G.glo[0], 0), ub = min(b - G.glo[0], G.ext[0] - 1);
         LT* r0 = a0 + (w * TY + v) * TXP;
         LT* r4 = a4 + (w * TY + v) * TXP;
         if constexpr (FIXED) {
@@ -1920,10 +1873,6 @@ __global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
           for (int u = ua; u <= ub; ++u) {
             lds_add(r0 + u, qr);
             lds_add(r4 + u, qe);
-          }
-          if (sl == 0 && E.tgt >= 0) {
-            lds_add(a0 + E.tgt, E.remr);
-            lds_add(a4 + E.tgt, E.reme);
           }
         } else {
           const double cr = E.vr, ce = E.ve;
@@ -2079,7 +2028,7 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
   if (has_c || has_s)
     hipLaunchKernelGGL(k_l1_hist, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
                        has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc, hs,
-                       nbs, bw.sn_pk, bw.sn_rows);
+                       nbs, bw.sn_pk);
   // exclusive scan of both kinds' histograms, in place; hist[n] = total
   const int nblocks = (int)((n + kScanBlock - 1) / kScanBlock);
   hipLaunchKernelGGL(k_scan_local, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist, bw.hist,
@@ -2118,8 +2067,8 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
   hipLaunchKernelGGL(k_l2_scatter, dim3(grid2), dim3(256), lds2, s, G, (const int*)bw.slice_base,
                      (const int*)bw.hist2, (const double4*)bw.cic_tmp,
                      (const int*)bw.cic_tmp_tile, bw.cic_rec, bw.cic_off, bw.cic_cap,
-                     (const int*)bw.sn_tmp, (const int*)bw.sn_tmp_tile, bw.sn_rec, bw.sn_rec_tile,
-                     bw.sn_off, bw.sn_cap);
+                     (const int*)bw.sn_tmp, (const int*)bw.sn_tmp_tile, bw.sn_rec, bw.sn_off,
+                     bw.sn_cap);
   return hipGetLastError();
 }
 
@@ -2128,19 +2077,6 @@ hipError_t launch_tile_prep(const Mesh& M, const TileGrid& T, const Particles* c
                             hipStream_t s) {
   const int* coff = (cic && cic->n > 0) ? bw.cic_off : nullptr;
   const int* soff = (sn && sn->n > 0) ? bw.sn_off : nullptr;
-  const int egrid = grid_for(bw.sn_cap, 256, M.num_cu * 32);
-#define PMP_ENT(TYZ)                                                                        \
-  if (soff)                                                                                 \
-    hipLaunchKernelGGL((k_sn_ent<TYZ>), dim3(egrid), dim3(256), 0, s, T, soff, bw.sn_cap,   \
-                       (const int*)bw.sn_rec, (const int*)bw.sn_rec_tile,                   \
-                       (const SnPk*)bw.sn_pk, (const unsigned short*)bw.sn_rows,            \
-                       (SnEnt<TYZ * TYZ>*)bw.sn_ent)
-  switch (T.t[1]) {
-    case 2: PMP_ENT(2); break;
-    case 4: PMP_ENT(4); break;
-    default: PMP_ENT(8);
-  }
-#undef PMP_ENT
   hipLaunchKernelGGL(k_units, dim3(grid_for(T.ntiles, 256, M.num_cu * 16)), dim3(256), 0, s, T,
                      coff, bw.cic_cap, soff, bw.sn_cap, t.chunk_cic, t.chunk_sn, bw.heavy_base,
                      bw.heavy_unit, bw.heavy_count, bw.arrive, bw.slot_cap);
@@ -2163,7 +2099,8 @@ hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles
 #define PMP_TILE(ACC, TT, TYZ)                                                                \
   hipLaunchKernelGGL((k_tile_deposit<ACC, TYZ>), dim3((unsigned)grid), dim3(block), lds, s, M, \
                      T, coff, (const double4*)bw.cic_rec, bw.cic_cap, soff,                   \
-                     (const SnEnt<TYZ * TYZ>*)bw.sn_ent, bw.sn_cap, t.chunk_cic, t.chunk_sn,  \
+                     (const int*)bw.sn_rec, (const SnPk*)bw.sn_pk, bw.sn_cap, t.chunk_cic,    \
+                     t.chunk_sn,                                                              \
                      (const int*)bw.heavy_base, (const int2*)bw.heavy_unit,                   \
                      (const int*)bw.heavy_count, bw.arrive, bw.partial, bw.slot_cap,          \
                      (TT*)buf, state, L)
