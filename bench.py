@@ -321,7 +321,7 @@ def main():
     # (the binning phase is several small launches of scratch traffic)
     dom = max((k for k in per_phase if per_phase[k]["algo_bytes"] > 0),
               key=lambda k: per_phase[k]["avg_ms"])
-    kernel_names = {"bin": "k_l1_*+k_scan_*+k_l2_*+k_units", "tile": "k_tile_deposit",
+    kernel_names = {"bin": "k_sn_count+k_l1_*+k_scan_*+k_l2_*+k_units", "tile": "k_tile_deposit",
                     "zero": "k_zero", "cic": "k_cic_direct", "sn": "k_sn_direct",
                     "sink_deposit": "k_sink_deposit", "fold": "k_fold_apply" if fused else "k_fold",
                     "sink_update": "k_sink_update", "apply": "k_apply"}

@@ -175,7 +175,9 @@ typedef struct {
                             them), then folds and applies the shell cells in one
                             kernel; results are those of the separate calls.
                             The buffer's interior cells are left unwritten. */
-  int32_t reserved;      /* must be 0 */
+  int32_t count_lanes;   /* binned path: lanes counting one supernova's sphere
+                            members (its candidate rows dealt round them):
+                            1, 2, 4 or 8 */
 } pmp_tuning;
 
 /* Create a context on the current HIP device.  Copies the layout, checks the
@@ -265,7 +267,9 @@ int pmp_set_tuning(pmp_ctx *ctx, const pmp_tuning *t);
  * direct (global atomic) path and the binned (LDS-privatised) path with a set
  * of tile shapes and workgroup sizes, with and without the fused apply (steps
  * without sinks).  Stage 2, if the binned path won: the split thresholds
- * chunk_cic / chunk_sn and the persistent tile grid cap around the winner.  The steps run on a scratch copy of the state (the
+ * chunk_cic / chunk_sn, the persistent tile grid cap and (with supernovae)
+ * count_lanes, each around the winner so far.  The steps run on a scratch
+ * copy of the state (the
  * caller's state is left as it was; the buffer and sink_out are overwritten).
  * Synchronises the stream; allocates and frees the scratch copy.  best_ms
  * (host, may be NULL) receives the winning step time. */

@@ -24,6 +24,8 @@ def shape_key(ctx) -> str:
         "cic": w.cic.n if w.cic else 0, "sn": w.sn.n if w.sn else 0,
         "sink": w.sinks.n if w.sinks else 0,
         "sn_r": float(np.max(w.sn.fields["r"])) if w.sn is not None and w.sn.n else 0.0,
+        # a cached tuning is only reused for the tuning struct it was made with
+        "tuning_fields": [k for k, _ in type(ctx.tuning())._fields_],
     }
     return hashlib.sha256(json.dumps(desc, sort_keys=True).encode()).hexdigest()[:20]
 

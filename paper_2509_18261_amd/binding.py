@@ -81,10 +81,10 @@ class pmp_tuning(C.Structure):
                 ("tile_block", C.c_int32), ("block", C.c_int32), ("grid_per_cu", C.c_int32),
                 ("sn_lanes", C.c_int32), ("tile_grid_per_cu", C.c_int32),
                 ("chunk_cic", C.c_int32), ("chunk_sn", C.c_int32),
-                ("fuse_apply", C.c_int32), ("reserved", C.c_int32)]
+                ("fuse_apply", C.c_int32), ("count_lanes", C.c_int32)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 NPHASE = 9

@@ -696,7 +696,7 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
     {
       PhaseTimer t(c, PMP_PHASE_BIN, s);
       PMP_HIP(launch_bin(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
-                         c->tune.block, s));
+                         c->tune.count_lanes, s));
       PMP_HIP(launch_tile_prep(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
                                c->tune, s));
     }
@@ -982,7 +982,7 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   c->tune.chunk_cic = 4096;
   c->tune.chunk_sn = 512;
   c->tune.fuse_apply = 1;
-  c->tune.reserved = 0;
+  c->tune.count_lanes = 4;
   {
     int rc = build_tiles(c, c->tune.tile_x, c->tune.tile_yz);
     if (rc) {
@@ -1196,7 +1196,8 @@ int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
   if (t->chunk_cic < 64 || t->chunk_cic > (1 << 24)) return fail(PMP_EINVAL, "chunk_cic 64..2^24");
   if (t->chunk_sn < 16 || t->chunk_sn > (1 << 24)) return fail(PMP_EINVAL, "chunk_sn 16..2^24");
   if (t->fuse_apply != 0 && t->fuse_apply != 1) return fail(PMP_EINVAL, "fuse_apply 0 or 1");
-  if (t->reserved != 0) return fail(PMP_EINVAL, "reserved must be 0");
+  if (t->count_lanes != 1 && t->count_lanes != 2 && t->count_lanes != 4 && t->count_lanes != 8)
+    return fail(PMP_EINVAL, "count_lanes 1, 2, 4 or 8");
   {
     const long long lds = tile_lds_bytes(t->tile_x, t->tile_yz, c->ghost);
     if (lds > c->max_lds)
@@ -1303,6 +1304,16 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
       pmp_tuning t = w2;
       t.tile_grid_per_cu = gpc;
       time_one(t);
+    }
+    if (has_sn) {
+      // lanes per supernova in the member count (large spheres want more)
+      const pmp_tuning w3 = best_t;
+      for (int lanes : {1, 2, 8}) {
+        if (lanes == w3.count_lanes) continue;
+        pmp_tuning t = w3;
+        t.count_lanes = lanes;
+        time_one(t);
+      }
     }
   }
   if (e0) (void)hipEventDestroy(e0);

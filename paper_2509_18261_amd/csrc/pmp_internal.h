@@ -201,7 +201,7 @@ hipError_t launch_cic_direct(const Mesh& M, const Particles& P, void* buf, int b
 // cic or sn may be null.  Replaces the zero fill.  phase_bin/phase_tile
 // bracket the two halves for the profiler.
 hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
-                      const Particles* sn, BinWork& bw, int block, hipStream_t s);
+                      const Particles* sn, BinWork& bw, int count_lanes, hipStream_t s);
 // Supernova tile records and the chunk table of split tiles (after launch_bin).
 hipError_t launch_tile_prep(const Mesh& M, const TileGrid& T, const Particles* cic,
                             const Particles* sn, const BinWork& bw, const pmp_tuning& t,

@@ -239,12 +239,6 @@ __device__ __forceinline__ void sphere_row(const Sphere& S, int t, int& j, int& 
 }
 
 // Members [a, b] of row (j, k); empty when a > b.
-// The test value of cell i of a row whose rounded squared y and z offsets
-// are y2 and z2: the same rounded operations, in the same order, as dist2.
-__device__ __forceinline__ double row_d2(const Sphere& S, int i, double y2, double z2) {
-  const double ddx = ((double)i + 0.5) - S.x;
-  return (ddx * ddx + y2) + z2;
-}
 
 // Members [a, b] of the row with rounded squared offsets y2, z2 of a sphere
 // centred at x along the row, with r2 = r^2 and candidate cells [lo, hi].
@@ -254,6 +248,8 @@ __device__ __forceinline__ double row_d2(const Sphere& S, int i, double y2, doub
 // walks further.
 __device__ __forceinline__ void row_run(double x, double r2, int lo, int hi, double y2,
                                         double z2, int& a, int& b) {
+  // the test value of cell i: the same rounded operations, in the same
+  // order, as dist2 with dy^2 = y2 and dz^2 = z2
   auto d2 = [&](int i) {
     const double ddx = ((double)i + 0.5) - x;
     return (ddx * ddx + y2) + z2;
@@ -1267,26 +1263,22 @@ __device__ __forceinline__ bool sn_tiles(const Mesh& M, const TileGrid& T, const
   return tile_range(B, T, slo, shi, tlo, thi);
 }
 
-// Level 1, supernovae, histogram pass: one lane per particle (kBinChunkSn
-// particles per block).  The lane walks its sphere's candidate rows in (k, j)
-// order: it counts the members N (-1 when no centre lies within r and the
-// host cell takes the deposit; 0 when the particle is skipped) and finds the
-// fixed-point remainder cell (host if a member, else the first member in
-// (k, j, i) order); then it writes the particle's SnPk and counts it into the
-// buckets of every tile its sphere touches.
-__device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGrid& T,
-                                           const Particles& P, int shift, int nb,
-                                           int* __restrict__ hist, int nblk,
-                                           SnPk* __restrict__ pk) {
-  extern __shared__ int h[];
+// Supernova members, before binning: L lanes per particle (256 / L particles
+// per block).  The lanes walk the sphere's candidate rows in (k, j) order,
+// row t on lane t mod L: they count the members N (-1
+// when no centre lies within r and the host cell takes the deposit; 0 when
+// the particle is skipped) and find the fixed-point remainder cell (host if a
+// member, else the first member in (k, j, i) order); the first lane writes
+// the particle's SnPk.
+template <int L>
+__global__ __launch_bounds__(256) void k_sn_count(Mesh M, Particles P, SnPk* __restrict__ pk) {
   const int g = M.ghost;
-  const int col = hist_col(blk, nblk);
-  for (int c = threadIdx.x; c < nb; c += blockDim.x) h[c] = 0;
-  const long long p0 = (long long)blk * kBinChunkSn;
-  const long long p1 = min(p0 + kBinChunkSn, P.n);
+  const long long p0 = (long long)blockIdx.x * (256 / L);
+  const long long p1 = min(p0 + 256 / L, P.n);
   int bb0, bb1;
   block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
-  const long long p = p0 + threadIdx.x;
+  const int sub = threadIdx.x & (L - 1);
+  const long long p = p0 + threadIdx.x / L;
   const bool live = p < p1;
   const int b = !live ? 0 : (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
   const DevBox B = M.boxes[b];
@@ -1327,8 +1319,12 @@ __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGri
   const int plo[3] = {B.lo[0] - g, B.lo[1] - g, B.lo[2] - g};
   const int phi[3] = {B.lo[0] + B.n[0] + g - 1, B.lo[1] + B.n[1] + g - 1,
                       B.lo[2] + B.n[2] + g - 1};
-  int jj = 0, kk = 0;  // row t = jj + cy * kk
-  for (int t = 0; t < nrows; ++t) {
+  int jj = sub, kk = 0;  // row t = jj + cy * kk (cy >= 1 when there are rows)
+  for (int t = sub; t < nrows; t += L) {
+    while (jj >= Sp.cy) {
+      jj -= Sp.cy;
+      ++kk;
+    }
     const int j = Sp.lo[1] + jj, k = Sp.lo[2] + kk;
     const double dy = ((double)j + 0.5) - Sp.y, dz = ((double)k + 0.5) - Sp.z;
     const double y2 = dy * dy, z2 = dz * dz;
@@ -1337,18 +1333,19 @@ __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGri
       row_members_yz(Sp, y2, z2, a, bb);
       if (a <= bb) {
         cnt += bb - a + 1;
-        if (key == 0x7fffffff) key = (t << 12) | (a - Sp.lo[0]);
+        if (key == 0x7fffffff) key = (t << 12) | (a - Sp.lo[0]);  // the lane's first
         hm |= (j == hc[1] && k == hc[2] && a <= hc[0] && hc[0] <= bb);
         // a member outside the padded box
         out |= a < plo[0] || bb > phi[0] || j < plo[1] || j > phi[1] || k < plo[2] ||
                k > phi[2];
       }
     }
-    if (++jj == Sp.cy) {
-      jj = 0;
-      ++kk;
-    }
+    jj += L;
   }
+  cnt = group_sum<L>(cnt);
+  key = group_min<L>(key);
+  hm = group_max<L>(hm);
+  out = group_max<L>(out);
   int N = cnt;
   if (ok && N == 0) N = -1;
   bool okq = ok;
@@ -1381,18 +1378,39 @@ __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGri
       R.tj = tj - B.lo[1] + g;
       R.tk = tk - B.lo[2] + g;
     }
-    if (out) raise_flag(M.status, PMP_FLAG_REACH);
+    if (out && sub == 0) raise_flag(M.status, PMP_FLAG_REACH);
   }
-  if (flag) raise_flag(M.status, flag);
-  if (live) pk[p] = R;
-  __syncthreads();  // h cleared
-  if (okq) {
+  if (flag && sub == 0) raise_flag(M.status, flag);
+  if (live && sub == 0) pk[p] = R;
+}
+
+// Level 1, supernovae, histogram pass: one thread per particle counts it
+// into the buckets of every tile its sphere touches (kBinChunkSn particles
+// per block; skipped particles have n = 0).
+__device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGrid& T,
+                                           const Particles& P, int shift, int nb,
+                                           int* __restrict__ hist, int nblk,
+                                           const SnPk* __restrict__ pk) {
+  extern __shared__ int h[];
+  const int col = hist_col(blk, nblk);
+  for (int c = threadIdx.x; c < nb; c += blockDim.x) h[c] = 0;
+  const long long p0 = (long long)blk * kBinChunkSn;
+  const long long p1 = min(p0 + kBinChunkSn, P.n);
+  int bb0, bb1;
+  block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
+  __syncthreads();
+  for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    const SnPk& R = pk[p];
+    const int N = R.n;
+    if (N == 0) continue;
+    const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
+    const DevBox B = M.boxes[b];
     int tlo[3], thi[3];
-    if (sn_tiles(M, T, B, x, y, z, r, N, tlo, thi))
-      for (int tz = tlo[2]; tz <= thi[2]; ++tz)
-        for (int ty = tlo[1]; ty <= thi[1]; ++ty)
-          for (int tx = tlo[0]; tx <= thi[0]; ++tx)
-            atomicAdd(h + ((int)tile_id(T, b, tx, ty, tz) >> shift), 1);
+    if (!sn_tiles(M, T, B, R.x, R.y, R.z, R.r, N, tlo, thi)) continue;
+    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
+      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
+        for (int tx = tlo[0]; tx <= thi[0]; ++tx)
+          atomicAdd(h + ((int)tile_id(T, b, tx, ty, tz) >> shift), 1);
   }
   __syncthreads();
   for (int c = threadIdx.x; c < nb; c += blockDim.x) hist[(long long)c * nblk + col] = h[c];
@@ -1444,7 +1462,7 @@ __device__ __forceinline__ void l1_sn_scatter(int blk, const Mesh& M, const Tile
 __global__ __launch_bounds__(256) void k_l1_hist(Mesh M, TileGrid T, Particles C, Particles Sn,
                                                 int shift, int nb, int* __restrict__ hc, int nbc,
                                                 int* __restrict__ hs, int nbs,
-                                                SnPk* __restrict__ pk) {
+                                                const SnPk* __restrict__ pk) {
   if ((int)blockIdx.x < nbc)
     l1_cic<false>(blockIdx.x, M, T, C, shift, nb, hc, nbc, nullptr, nullptr, 0);
   else
@@ -2015,8 +2033,7 @@ hipError_t launch_cic_direct(const Mesh& M, const Particles& P, void* buf, int b
 
 
 hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
-                      const Particles* sn, BinWork& bw, int block, hipStream_t s) {
-  (void)block;
+                      const Particles* sn, BinWork& bw, int count_lanes, hipStream_t s) {
   const int nb = bw.nbuckets, S = bw.shift;
   const bool has_c = cic && cic->n > 0, has_s = sn && sn->n > 0;
   const int nbc = has_c ? (int)((cic->n + kBinChunkCic - 1) / kBinChunkCic) : 0;
@@ -2025,10 +2042,19 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
   int* hs = bw.hist + (long long)nb * nbc;
   const long long n = (long long)nb * (nbc + nbs);
   const size_t lds1 = (size_t)nb * sizeof(int);
+  if (has_s) {
+    const unsigned grid = (unsigned)((sn->n * count_lanes + 255) / 256);
+    switch (count_lanes) {
+      case 1: hipLaunchKernelGGL(k_sn_count<1>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk); break;
+      case 2: hipLaunchKernelGGL(k_sn_count<2>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk); break;
+      case 8: hipLaunchKernelGGL(k_sn_count<8>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk); break;
+      default: hipLaunchKernelGGL(k_sn_count<4>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk);
+    }
+  }
   if (has_c || has_s)
     hipLaunchKernelGGL(k_l1_hist, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
                        has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc, hs,
-                       nbs, bw.sn_pk);
+                       nbs, (const SnPk*)bw.sn_pk);
   // exclusive scan of both kinds' histograms, in place; hist[n] = total
   const int nblocks = (int)((n + kScanBlock - 1) / kScanBlock);
   hipLaunchKernelGGL(k_scan_local, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist, bw.hist,

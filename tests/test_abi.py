@@ -45,7 +45,7 @@ STRUCTS = {
     "pmp_status": ["flags", "reserved", "touched", "bind", "lam", "fall"],
     "pmp_tuning": ["deposit_path", "tile_x", "tile_yz", "tile_block", "block", "grid_per_cu",
                    "sn_lanes", "tile_grid_per_cu", "chunk_cic", "chunk_sn",
-                   "fuse_apply", "reserved"],
+                   "fuse_apply", "count_lanes"],
 }
 
 
