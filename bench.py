@@ -40,11 +40,13 @@ def algorithmic_bytes(w, acc, counts, F, fused=False):
     """Bytes per launch each phase must move at minimum (no scratch, no
     re-reads): buffer writes for the zero fill, particle records plus a
     read-modify-write of every touched (cell, field) for deposits, the owned
-    shell and its ghost images for the fold, and state in/out plus buffer in
-    for apply.  F = buffer channels of the timed layout.  fused: the step
-    applies the interior cells (owned, at least g from every face) in the
-    tile pass, which stores the buffer only for the other cells, and the
-    shell cells are folded and applied in one pass."""
+    shell and its ghost images for the fold, and for apply the buffer in, the
+    five state fields in and rho and E out (the momentum is written back only
+    where a sink removes mass: no kind deposits momentum).  F = buffer
+    channels of the timed layout.  fused: the step applies the interior cells
+    (owned, at least g from every face) in the tile pass, which stores the
+    buffer only for the other cells, and the shell cells are folded and
+    applied in one pass."""
     import numpy as np
     ba = acc_bytes(acc)
     bs = np.dtype(w.state.dtype).itemsize
@@ -61,19 +63,21 @@ def algorithmic_bytes(w, acc, counts, F, fused=False):
     if w.sn is not None:
         parts += w.sn.n * 48
     interior = int(np.prod(np.maximum(n - 2 * g, 0), axis=1).sum())
+    st = 7 * bs  # per applied cell: 5 fields in, rho and E out
+    removed = counts.get("sink", 0) if w.sinks is not None else 0  # cells with a removal
     out = {
         "zero": padded * F * ba,
         # binned path: every buffer cell stored once plus the particle records
         "tile": padded * F * ba + parts,
         "bin": 0,
         "fold": F * ba * (2 * shell + ghost_cells),
-        "apply": owned * (2 * 5 * bs + F * ba),
+        "apply": owned * (st + F * ba) + 3 * bs * removed,
     }
     if fused:
         # tile: buffer for the non-interior cells, records, interior state in/out
-        out["tile"] = (padded - interior) * F * ba + parts + interior * 2 * 5 * bs
+        out["tile"] = (padded - interior) * F * ba + parts + interior * st
         # fold: shell values and their ghost images in, shell state in/out
-        out["fold"] = F * ba * (shell + ghost_cells) + shell * 2 * 5 * bs
+        out["fold"] = F * ba * (shell + ghost_cells) + shell * st
         out["apply"] = 0
     if w.cic is not None and w.cic.n:
         out["cic"] = w.cic.n * 32 + 2 * ba * counts["cic"]

@@ -877,7 +877,9 @@ struct ApplyCounts {
 
 // Steps 3 + 5 for one owned cell, in double precision: st points at the
 // cell's rho, the other state fields follow at multiples of stride; (Dr, q,
-// DE, K) is the folded buffer.  Returns eta = Kl / K (1 when K = 0).
+// DE, K) is the folded buffer.  Returns eta = Kl / K (1 when K = 0).  Reads
+// all five fields (the energy limiter needs |p|^2); writes rho and E, and
+// the momentum only where it changes.
 template <class S>
 __device__ __forceinline__ double apply_cell(S* st, long long stride, double Dr, double qx,
                                              double qy, double qz, double DE, double K,
@@ -925,9 +927,13 @@ __device__ __forceinline__ double apply_cell(S* st, long long stride, double Dr,
   if (lam < 1.0) ++cnt.lam;
   if (!(rho > 0.0) || !isfinite(E1) || !isfinite(rho1)) cnt.bad = true;
   st[0] = (S)rho1;
-  st[stride] = (S)(p0x + lam * qx);
-  st[2 * stride] = (S)(p0y + lam * qy);
-  st[3 * stride] = (S)(p0z + lam * qz);
+  // momentum changes only through the removal (f < 1) or a momentum deposit:
+  // otherwise the new value equals the stored one and is not written again
+  if (f != 1.0 || qx != 0.0 || qy != 0.0 || qz != 0.0) {
+    st[stride] = (S)(p0x + lam * qx);
+    st[2 * stride] = (S)(p0y + lam * qy);
+    st[3 * stride] = (S)(p0z + lam * qz);
+  }
   st[4 * stride] = (S)E1;
   return (K > 0.0) ? Kl / K : 1.0;
 }
