@@ -894,7 +894,9 @@ __device__ __forceinline__ double apply_cell(S* st, long long stride, double Dr,
     ++cnt.touched;
     if (Kl < K) ++cnt.bind;
   }
-  const double f = 1.0 - Kl / rho;
+  // no removal: f = 1 - 0 / rho is exactly 1 for any nonzero, non-NaN rho
+  double f = 1.0;
+  if (!(Kl == 0.0 && rho != 0.0 && rho == rho)) f = 1.0 - Kl / rho;
   const double rho1 = f * rho + Dr;
   double E1 = f * E + DE;
   const double p0x = f * px, p0y = f * py, p0z = f * pz;
@@ -959,9 +961,10 @@ __device__ __forceinline__ void flush_counts(const Mesh& M, ApplyCounts& cnt) {
 
 // Steps 2 + 3 + 5 for the shell cells of a fused step: each shell cell
 // gathers its ghost images in the plan's order (as k_fold) and is applied
-// at once; the interior cells were applied by the tile pass.
+// at once; the interior cells were applied by the tile pass.  (Register
+// budget for 7 waves per SIMD; the apply kernel below fits 8.)
 template <int ACC, int F>
-__global__ __launch_bounds__(kChunk) void k_fold_apply(Mesh M, void* __restrict__ state,
+__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(7))) void k_fold_apply(Mesh M, void* __restrict__ state,
                                                       const typename AccT<ACC>::T* __restrict__ buf,
                                                       Limits L) {
   using Sum = SumT<ACC>;
@@ -996,7 +999,7 @@ __global__ __launch_bounds__(kChunk) void k_fold_apply(Mesh M, void* __restrict_
 
 // Steps 3 + 5 per owned cell, in double precision (see pmp_apply).
 template <class S, int ACC>
-__global__ __launch_bounds__(kChunk) void k_apply(Mesh M, S* __restrict__ state,
+__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(8))) void k_apply(Mesh M, S* __restrict__ state,
                                                  const typename AccT<ACC>::T* __restrict__ buf,
                                                  Limits L, double* __restrict__ eta) {
   const int g = M.ghost;
@@ -1728,8 +1731,10 @@ template <class T> __device__ __forceinline__ T from_lds(double v) { return (T)v
 // test and adds it.  Every addition goes to the LDS accumulators.  Then every present channel of every cell of the
 // tile is stored once (channels without sources as zero).  Membership,
 // shares and fixed-point remainders are the same as in the direct kernels.
+// (7 waves per SIMD: the register budget that keeps the LDS-limited
+// occupancy of the common tile shapes without spilling)
 template <int ACC, int TYZ>
-__global__ __launch_bounds__(1024) void k_tile_deposit(Mesh M, TileGrid T,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void k_tile_deposit(Mesh M, TileGrid T,
                                                       const int* __restrict__ coff,
                                                       const double4* __restrict__ crec,
                                                       long long ccap,
