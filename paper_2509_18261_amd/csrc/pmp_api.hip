@@ -279,6 +279,11 @@ int build_tiles(pmp_ctx* c, int tx, int tyz) {
   std::vector<long long> prefix(c->nbox + 1, 0);
   std::vector<int> axis(3 * (size_t)c->nbox);
   for (int b = 0; b < c->nbox; ++b) {
+    // the tile pass indexes a tile's cells by 32-bit offsets from its origin
+    const DevBox& db = c->dboxes[b];
+    if ((long long)db.p[0] * db.p[1] * tyz >= (1ll << 31))
+      return fail(PMP_ERANGE, "box %d: %d padded planes of %d x %d cells reach 2^31; use tile_yz < %d",
+                  b, tyz, db.p[0], db.p[1], tyz);
     long long n = 1;
     for (int a = 0; a < 3; ++a) {
       const int p = c->dboxes[b].p[a];

@@ -940,6 +940,39 @@ __device__ __forceinline__ double apply_cell(S* st, long long stride, double Dr,
   return (K > 0.0) ? Kl / K : 1.0;
 }
 
+// apply_cell for a cell without removal (K = 0) or momentum deposit (q = 0),
+// with the same rounded operations: f = 1 - 0 / rho is exactly 1 for any
+// nonzero, non-NaN rho, so rho1 = rho + Dr, E1 = E + DE, the momentum is
+// unchanged (p + 0 squares to p^2), and the energy test reduces to
+// |p|^2 - 2 rho1 E1 (e_int >= 0 mode): lam = 1, or the floor.  A zero or
+// NaN rho, and the specific-e_int mode, take apply_cell itself.
+template <class S>
+__device__ __forceinline__ void apply_cell_nosrc(S* st, long long stride, double Dr, double DE,
+                                                 const Limits& L, ApplyCounts& cnt) {
+  const double rho = (double)st[0];
+  if (!(rho != 0.0 && rho == rho) || L.eint_mode != 0) {
+    apply_cell(st, stride, Dr, 0.0, 0.0, 0.0, DE, 0.0, L, cnt);
+    return;
+  }
+  const double px = (double)st[stride];
+  const double py = (double)st[2 * stride];
+  const double pz = (double)st[3 * stride];
+  const double E = (double)st[4 * stride];
+  const double rho1 = rho + Dr;
+  double E1 = E + DE;
+  const double Kc = (2.0 * rho1) * E1;
+  const double pp = (px * px + py * py) + pz * pz;
+  if (!(pp - Kc <= 0.0)) {
+    // lam = 0: the kinetic part stays, e_int at its floor
+    E1 = 0.0 + pp / (2.0 * rho1);
+    ++cnt.fall;
+    ++cnt.lam;
+  }
+  if (!(rho > 0.0) || !isfinite(E1) || !isfinite(rho1)) cnt.bad = true;
+  st[0] = (S)rho1;
+  st[4 * stride] = (S)E1;
+}
+
 // One atomic per wavefront and counter (call from every lane of the wave).
 __device__ __forceinline__ void flush_counts(const Mesh& M, ApplyCounts& cnt) {
   const unsigned long long touched = group_sum<kWave>(cnt.touched);
@@ -1788,12 +1821,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
       base = heavy_base[tile];
     } else {
       tile = (int)(unit - nheavy);
-      if (heavy_base[tile] >= 0) continue;
     }
+    // the tile's metadata, loaded together; a tile split into chunks is
+    // done by its chunk units
+    const int hb = heavy_base[tile];
     const TileGeo G = T.geo[tile];
     long long e0, e1, s0, s1;
     tile_entries(coff, ccap, tile, e0, e1);
     tile_entries(soff, scap, tile, s0, s1);
+    if (unit >= nheavy && hb >= 0) continue;
     for (int c = threadIdx.x; c < lcells; c += blockDim.x) {
       a0[c] = (LT)0;
       a4[c] = (LT)0;
@@ -1916,13 +1952,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
     }
     if (ovf) raise_flag(M.status, PMP_FLAG_OVERFLOW);
     __syncthreads();
-    const LT* src0 = a0;
-    const LT* src4 = a4;
-    int nsum = 1;
-    long long sstride = 0;
     if (base >= 0) {
       // a chunk of a split tile: leave the partial tile, and the last chunk
-      // to finish (device-scope fence + arrival count) combines them
+      // to finish (device-scope fence + arrival count) sums the chunks'
+      // partial tiles in chunk order back into the accumulators
       LT* part = partial + (long long)(base + chunk) * 2 * lcells;
       for (int c = threadIdx.x; c < lcells; c += blockDim.x) {
         part[c] = a0[c];
@@ -1934,52 +1967,68 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
       __syncthreads();
       if (!s_last) continue;
       __threadfence();
-      src0 = partial + (long long)base * 2 * lcells;
-      src4 = src0 + lcells;
-      nsum = chunks;
-      sstride = 2ll * lcells;
+      const LT* p0 = partial + (long long)base * 2 * lcells;
+      for (int c = threadIdx.x; c < lcells; c += blockDim.x) {
+        LT r0 = p0[c], r4 = p0[lcells + c];
+        for (int q = 1; q < chunks; ++q) {
+          r0 += p0[2ll * q * lcells + c];
+          r4 += p0[2ll * q * lcells + lcells + c];
+        }
+        a0[c] = r0;
+        a4[c] = r4;
+      }
+      __syncthreads();
     }
     // every present channel of every cell is stored once: rho and E from
-    // the accumulators (summed over the chunks in chunk order), the others
-    // (no source in this pass) as zero.  In a fused step, owned cells at
-    // least g from every face are applied here instead (their buffer value,
-    // rounded to the buffer type, is final: no ghost image reaches them)
+    // the accumulators, the others (no source in this pass) as zero.  In a
+    // fused step, owned cells at least g from every face are applied here
+    // instead (their buffer value, rounded to the buffer type, is final: no
+    // ghost image reaches them)
     OutT* f0 = buf + G.boff;
     const long long np = (long long)G.p[0] * G.p[1] * G.p[2];
     const int n0 = G.p[0] - 2 * g, n1 = G.p[1] - 2 * g, n2 = G.p[2] - 2 * g;
     const long long ncell = (long long)n0 * n1 * n2;
     const int sr = M.slot[0], se = M.slot[4];
+    // owned-local origin of the tile and its state offset; a cell's offset
+    // from it fits 32 bits (at most TZ planes of the box)
+    const int ox0 = G.o[0] - g, oy0 = G.o[1] - g, oz0 = G.o[2] - g;
+    const long long tso = G.soff + ((long long)oz0 * n1 + oy0) * n0 + ox0;
+    const long long tbo = ((long long)G.o[2] * G.p[1] + G.o[1]) * G.p[0] + G.o[0];
+    // cell c = u + TX row of the LDS tile, advanced by blockDim per step
+    const int drow = small_div((int)blockDim.x, TX, inv_tx), du = (int)blockDim.x - drow * TX;
+    int row = small_div((int)threadIdx.x, TX, inv_tx);
+    int u = (int)threadIdx.x - row * TX;
     for (int c = threadIdx.x; c < tcells; c += blockDim.x) {
-      const int row = small_div(c, TX, inv_tx);
-      const int u = c - row * TX, v = row & (TY - 1), w = row >> YSH;
-      if (u >= G.ext[0] || v >= G.ext[1] || w >= G.ext[2]) continue;
-      const int px = G.o[0] + u, py = G.o[1] + v, pz = G.o[2] + w;
-      const int lc = (w * TY + v) * TXP + u;
-      LT r0 = src0[lc], r4 = src4[lc];
-      for (int q = 1; q < nsum; ++q) {
-        r0 += src0[q * sstride + lc];
-        r4 += src4[q * sstride + lc];
+      const int v = row & (TY - 1), w = row >> YSH;
+      if (u < G.ext[0] && v < G.ext[1] && w < G.ext[2]) {
+        const int lc = (w * TY + v) * TXP + u;
+        const LT r0 = a0[lc], r4 = a4[lc];
+        const OutT vr = sr >= 0 ? from_lds<OutT>(r0) : (OutT)0;
+        const OutT ve = se >= 0 ? from_lds<OutT>(r4) : (OutT)0;
+        // owned-local coordinates: interior when g <= . < n - g on every axis
+        const int ox = ox0 + u, oy = oy0 + v, oz = oz0 + w;
+        if (state && ox >= g && ox < n0 - g && oy >= g && oy < n1 - g && oz >= g &&
+            oz < n2 - g) {
+          const long long si = tso + ((w * n1 + v) * n0 + u);
+          if (M.state == PMP_STATE_F32)
+            apply_cell_nosrc((float*)state + si, ncell, to_f64(vr), to_f64(ve), L, cnt);
+          else
+            apply_cell_nosrc((double*)state + si, ncell, to_f64(vr), to_f64(ve), L, cnt);
+        } else {
+          const long long idx = tbo + ((w * G.p[1] + v) * G.p[0] + u);
+          for (int f = 0; f < M.nfield; ++f) {
+            OutT val = (OutT)0;
+            if (f == sr) val = vr;
+            else if (f == se) val = ve;
+            f0[idx + f * np] = val;
+          }
+        }
       }
-      const OutT vr = sr >= 0 ? from_lds<OutT>(r0) : (OutT)0;
-      const OutT ve = se >= 0 ? from_lds<OutT>(r4) : (OutT)0;
-      // owned-local coordinates: interior when g <= . < n - g on every axis
-      const int ox = px - g, oy = py - g, oz = pz - g;
-      if (state && ox >= g && ox < n0 - g && oy >= g && oy < n1 - g && oz >= g && oz < n2 - g) {
-        const long long si = G.soff + ((long long)oz * n1 + oy) * n0 + ox;
-        if (M.state == PMP_STATE_F32)
-          apply_cell((float*)state + si, ncell, to_f64(vr), 0.0, 0.0, 0.0, to_f64(ve), 0.0, L,
-                     cnt);
-        else
-          apply_cell((double*)state + si, ncell, to_f64(vr), 0.0, 0.0, 0.0, to_f64(ve), 0.0, L,
-                     cnt);
-        continue;
-      }
-      const long long idx = ((long long)pz * G.p[1] + py) * G.p[0] + px;
-      for (int f = 0; f < M.nfield; ++f) {
-        OutT val = (OutT)0;
-        if (f == sr) val = vr;
-        else if (f == se) val = ve;
-        f0[idx + f * np] = val;
+      u += du;
+      row += drow;
+      if (u >= TX) {
+        u -= TX;
+        ++row;
       }
     }
     __syncthreads();
