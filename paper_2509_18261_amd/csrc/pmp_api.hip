@@ -147,7 +147,7 @@ struct pmp_ctx {
   std::vector<hipEvent_t> prof_events[PMP_NPHASE];
 
   int* d_zone_off = nullptr;   // [28 nbox]
-  int* d_zone_seg = nullptr;
+  ZoneSeg* d_zone_seg = nullptr;
   int2* d_apply_chunks = nullptr;
   int2* d_fold_chunks = nullptr;
   std::vector<long long> apply_chunk_off, fold_chunk_off;  // [nbox+1] host
@@ -421,7 +421,7 @@ int build_fold_plan(pmp_ctx* c, std::vector<int>& seg_off, std::vector<DevSeg>& 
 // plan order.  A shell cell only tests the segments of its own zone.
 void build_zones(const pmp_ctx* c, const std::vector<int>& seg_off,
                  const std::vector<DevSeg>& segs, std::vector<int>& zone_off,
-                 std::vector<int>& zone_seg) {
+                 std::vector<ZoneSeg>& zone_seg) {
   zone_off.assign(28 * (size_t)c->nbox, 0);
   zone_seg.clear();
   for (int b = 0; b < c->nbox; ++b) {
@@ -443,7 +443,20 @@ void build_zones(const pmp_ctx* c, const std::vector<int>& seg_off,
           const int h = std::min(segs[q].hi[a], zh[a][zz[a]]);
           if (l >= h) hit = false;
         }
-        if (hit) zone_seg.push_back(q);
+        if (hit) {
+          const DevSeg& S = segs[q];
+          const DevBox& src = c->dboxes[S.src];
+          ZoneSeg Z;
+          for (int a = 0; a < 3; ++a) {
+            Z.lo[a] = S.lo[a];
+            Z.hi[a] = S.hi[a];
+          }
+          Z.p0 = src.p[0];
+          Z.p1 = src.p[1];
+          Z.base = src.boff + ((long long)S.off[2] * src.p[1] + S.off[1]) * src.p[0] + S.off[0];
+          Z.npad = src.npad;
+          zone_seg.push_back(Z);
+        }
       }
     }
     zone_off[28 * (size_t)b + 27] = (int)zone_seg.size();
@@ -929,7 +942,8 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   std::vector<DevSeg> segs;
   build_fold_plan(c, seg_off, segs);
   c->nseg = (int)segs.size();
-  std::vector<int> zone_off, zone_seg;
+  std::vector<int> zone_off;
+  std::vector<ZoneSeg> zone_seg;
   build_zones(c, seg_off, segs, zone_off, zone_seg);
   std::vector<long long> owned_counts(c->nbox), shell_counts(c->nbox);
   for (int b = 0; b < c->nbox; ++b) {

@@ -32,6 +32,16 @@ struct DevSeg {
   int off[3];
 };
 
+// A fold segment as one zone lists it: the destination range and the source
+// addressing folded in, so that the ghost image of owned cell (i, j, k) is
+// buffer element base + (k p1 + j) p0 + i (field stride npad).
+struct alignas(16) ZoneSeg {
+  int lo[3], hi[3];  // owned cells [lo, hi) of the destination box
+  int p0, p1;        // padded extents of the source box
+  long long base;    // source boff + ((off_z p1) + off_y) p0 + off_x
+  long long npad;    // padded cells of the source box
+};
+
 // Device status word and counters (mirrors pmp_status).
 struct DevStatus {
   unsigned int flags;
@@ -64,9 +74,10 @@ struct Mesh {
   const DevSeg* segs;
   // Each box splits along every axis into [0, g), [g, n - g), [n - g, n) (27
   // zones); zone_off[28 b + z] .. zone_off[28 b + z + 1] index zone_seg, the
-  // segments (in plan order) that reach zone z of box b.
+  // segments (in plan order) that reach zone z of box b, with their source
+  // addressing.
   const int* zone_off;
-  const int* zone_seg;
+  const ZoneSeg* zone_seg;
   // Work chunks of kChunk cells that never cross a box: (global box, first
   // cell) for the apply (owned cells) and for the fold (shell cells).
   const int2* apply_chunks;

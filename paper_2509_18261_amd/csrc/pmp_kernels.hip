@@ -823,15 +823,13 @@ __device__ __forceinline__ bool fold_gather(const Mesh& M, int b, int i, int j, 
   const int* zo = M.zone_off + 28 * b;
   const int q1 = zo[z + 1];
   for (int q = zo[z]; q < q1; ++q) {
-    const DevSeg S = M.segs[M.zone_seg[q]];
+    const ZoneSeg& S = M.zone_seg[q];
     if (i < S.lo[0] || i >= S.hi[0] || j < S.lo[1] || j >= S.hi[1] || k < S.lo[2] ||
         k >= S.hi[2])
       continue;
-    const DevBox& Bs = M.all_boxes[S.src];
-    const long long src = Bs.boff + ((long long)(k + S.off[2]) * Bs.p[1] + (j + S.off[1])) *
-                                        Bs.p[0] + (i + S.off[0]);
+    const long long src = S.base + ((long long)k * S.p1 + j) * S.p0 + i;
 #pragma unroll
-    for (int f = 0; f < F; ++f) acc[f] += (Sum)buf[src + f * Bs.npad];
+    for (int f = 0; f < F; ++f) acc[f] += (Sum)buf[src + f * S.npad];
     any = true;
   }
   return any;
@@ -1022,10 +1020,15 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(7))) voi
 #pragma unroll
     for (int q = 0; q < 6; ++q) v[q] = M.slot[q] >= 0 ? to_f64((T)acc[M.slot[q]]) : 0.0;
     const long long si = B.soff + ((long long)k * B.n[1] + j) * B.n[0] + i;
-    if (M.state == PMP_STATE_F32)
-      apply_cell((float*)state + si, B.ncell, v[0], v[1], v[2], v[3], v[4], v[5], L, cnt);
-    else
-      apply_cell((double*)state + si, B.ncell, v[0], v[1], v[2], v[3], v[4], v[5], L, cnt);
+    // without momentum or removal channels (uniform): the source-free apply
+    const bool nosrc = M.slot[1] < 0 && M.slot[2] < 0 && M.slot[3] < 0 && M.slot[5] < 0;
+    if (M.state == PMP_STATE_F32) {
+      if (nosrc) apply_cell_nosrc((float*)state + si, B.ncell, v[0], v[4], L, cnt);
+      else apply_cell((float*)state + si, B.ncell, v[0], v[1], v[2], v[3], v[4], v[5], L, cnt);
+    } else {
+      if (nosrc) apply_cell_nosrc((double*)state + si, B.ncell, v[0], v[4], L, cnt);
+      else apply_cell((double*)state + si, B.ncell, v[0], v[1], v[2], v[3], v[4], v[5], L, cnt);
+    }
   }
   flush_counts(M, cnt);
 }
