@@ -191,6 +191,32 @@ void pmp_destroy(pmp_ctx *ctx);
 int pmp_sizes(const pmp_ctx *ctx, int64_t *state_elems, int64_t *buffer_elems,
               int64_t *owned_cells);
 
+/* Scratch of the deposits (the binned path's two-level sort, supernova
+ * records and split-tile partials; the sinks' kernel sums), which the
+ * context otherwise allocates itself on first use.  pmp_workspace_size
+ * writes to *bytes (host) the device bytes (a multiple of 256) a caller-owned workspace needs
+ * for deposits of at most max_cic CIC particles, max_sn supernovae of
+ * radius at most max_sn_radius (cells) and max_sinks sinks, for the current
+ * tuning (the tile shape changes it: call again after pmp_set_tuning or
+ * pmp_autotune).  PMP_EINVAL on negative counts, PMP_ERANGE where the
+ * deposit itself would be out of range. */
+int pmp_workspace_size(const pmp_ctx *ctx, int64_t max_cic, int64_t max_sn,
+                       double max_sn_radius, int64_t max_sinks, size_t *bytes);
+
+/* Hand the context a caller-owned device workspace (dev_ptr: 256-byte
+ * aligned, at least 256 bytes; the caller keeps ownership and keeps it alive
+ * while the context uses it).  The context frees its own scratch and from
+ * then on carves every scratch array from the workspace: pmp_deposit,
+ * pmp_sink_update, pmp_step, pmp_step_per_box and pmp_graph_build allocate
+ * nothing, and a deposit whose scratch does not fit returns PMP_ERANGE with
+ * the bytes it needs.  Calls on one context share the workspace (as they
+ * share the buffer).  dev_ptr NULL returns to library-owned scratch.
+ * PMP_EINVAL on misalignment or while a built graph exists (it holds scratch
+ * addresses).  pmp_set_tuning (a new tile shape) and pmp_autotune (a state
+ * copy) still allocate; the tuner skips tile shapes whose scratch does not
+ * fit the workspace.  Synchronises the device. */
+int pmp_set_workspace(pmp_ctx *ctx, void *dev_ptr, size_t bytes);
+
 /* Step 1 (Sec. 2.2, eq. "delta_u_buf").  Zeroes the device buffer, then adds
  * every particle's deposition function with atomic adds.  state (device) is
  * read by sinks only (may be NULL without sinks).  Any of cic, sn, sinks may

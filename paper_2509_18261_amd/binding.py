@@ -96,6 +96,9 @@ SIGNATURES = [
     ("pmp_create", _I, [C.POINTER(C.c_void_p), C.POINTER(pmp_layout)]),
     ("pmp_destroy", None, [_VP]),
     ("pmp_sizes", _I, [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("pmp_workspace_size", _I, [_VP, C.c_int64, C.c_int64, C.c_double, C.c_int64,
+                                C.POINTER(C.c_size_t)]),
+    ("pmp_set_workspace", _I, [_VP, _VP, C.c_size_t]),
     ("pmp_deposit", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
                          C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP]),
     ("pmp_ghost_fold", _I, [_VP, _VP, _VP]),
@@ -222,6 +225,27 @@ class Context:
         s.n = P.n
         s.box_off = C.c_void_p(off.data_ptr())
         return s
+
+    # ---------------------------------------------------------- workspace
+    def workspace_size(self, max_cic=None, max_sn=None, max_sn_radius=None, max_sinks=None):
+        """Device bytes a caller-owned workspace needs (default: this workload)."""
+        w = self.w
+        nc = (w.cic.n if w.cic is not None else 0) if max_cic is None else max_cic
+        ns = (w.sn.n if w.sn is not None else 0) if max_sn is None else max_sn
+        r = (self.sn.r_max if self.sn is not None else 0.0) if max_sn_radius is None else max_sn_radius
+        nk = (w.sinks.n if w.sinks is not None else 0) if max_sinks is None else max_sinks
+        out = C.c_size_t()
+        _call("pmp_workspace_size", self.h, int(nc), int(ns), float(r), int(nk), C.byref(out))
+        return out.value
+
+    def set_workspace(self, ws):
+        """Carve every scratch array from ``ws`` (a CUDA tensor, kept alive
+        here), or return to library-owned scratch with None."""
+        if ws is None:
+            _call("pmp_set_workspace", self.h, None, 0)
+        else:
+            _call("pmp_set_workspace", self.h, _ptr(ws), ws.numel() * ws.element_size())
+        self.workspace = ws
 
     # -------------------------------------------------------------- calls
     def _r(self, s):

@@ -121,8 +121,6 @@ struct pmp_ctx {
   DevBox* d_boxes = nullptr;
   long long* d_owned_prefix = nullptr;
   long long* d_shell_prefix = nullptr;
-  int* d_seg_off = nullptr;
-  DevSeg* d_segs = nullptr;
   DevStatus* d_status = nullptr;
   double* d_sink_scratch = nullptr;
   long long sink_cap = 0;
@@ -140,6 +138,11 @@ struct pmp_ctx {
   BinWork bw{};
   long long bw_hist = 0, bw_blocks = 0, bw_tiles = 0, bw_nsn = 0, bw_hist2 = 0,
             bw_slice_base = 0, bw_partial = 0;
+  // caller-owned workspace (pmp_set_workspace): every scratch array is carved
+  // from it, sink scratch first, and nothing is allocated by the library
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_sink_bytes = 0;  // sink scratch of the current deposit
   // phase profiler: events[phase][2 * launch + {0: start, 1: stop}]
   bool prof_on = false;
   int prof_max = 0;
@@ -167,8 +170,6 @@ struct pmp_ctx {
     M.owned_cells = owned_cells;
     M.owned_prefix = d_owned_prefix;
     M.shell_prefix = d_shell_prefix;
-    M.seg_off = d_seg_off;
-    M.segs = d_segs;
     M.zone_off = d_zone_off;
     M.zone_seg = d_zone_seg;
     M.apply_chunks = d_apply_chunks;
@@ -259,10 +260,8 @@ void release(pmp_ctx* c) {
   (void)hipFree(c->d_boxes);
   (void)hipFree(c->d_owned_prefix);
   (void)hipFree(c->d_shell_prefix);
-  (void)hipFree(c->d_seg_off);
-  (void)hipFree(c->d_segs);
   (void)hipFree(c->d_status);
-  (void)hipFree(c->d_sink_scratch);
+  if (!c->ws) (void)hipFree(c->d_sink_scratch);  // in a workspace: the caller's memory
   (void)hipFree(c->d_tile_prefix);
   (void)hipFree(c->d_tiles_axis);
   (void)hipFree(c->d_tile_geo);
@@ -270,7 +269,7 @@ void release(pmp_ctx* c) {
   (void)hipFree(c->d_zone_seg);
   (void)hipFree(c->d_apply_chunks);
   (void)hipFree(c->d_fold_chunks);
-  free_bin_work(c);
+  if (!c->ws) free_bin_work(c);
 }
 
 // Tiles of edge (tx, tyz, tyz) over every padded box.
@@ -480,7 +479,18 @@ bool capturing(hipStream_t s) {
   return st == hipStreamCaptureStatusActive;
 }
 
+size_t sink_scratch_bytes(long long n);
+
 int ensure_sink_scratch(pmp_ctx* c, long long n, hipStream_t s) {
+  if (c->ws) {
+    const size_t need = sink_scratch_bytes(n);
+    if (need > c->ws_bytes)
+      return fail(PMP_ERANGE, "workspace of %zu bytes is too small for %lld sinks", c->ws_bytes, n);
+    c->d_sink_scratch = reinterpret_cast<double*>(c->ws);
+    c->sink_cap = n;
+    c->ws_sink_bytes = need;
+    return PMP_OK;
+  }
   if (n <= c->sink_cap) return PMP_OK;
   if (capturing(s))
     return fail(PMP_EINVAL, "sink scratch must be sized before graph capture");
@@ -506,7 +516,15 @@ template <class T> int regrow(T** p, long long have, long long need) {
   return PMP_OK;
 }
 
-int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, hipStream_t s) {
+// Sizes (elements) of the binned-deposit scratch arrays for these particle
+// counts and the current tiles.
+struct BinSizes {
+  int shift = 0, nb = 0;
+  long long hist = 0, blocks = 0, tiles1 = 0, partial = 0, slot_cap = 0, cic_cap = 0,
+            sn_cap = 0, hist2 = 0, blocks2 = 0, slice_base = 0, n_sn = 0;
+};
+
+int bin_sizes(const pmp_ctx* c, long long n_cic, long long n_sn, double r_max, BinSizes& z) {
   const int* t = c->tile_dims;
   const long long span = 2 * (long long)std::ceil(std::max(r_max, 0.0)) + 3;
   const long long maxt = tiles_for(span, t[0]) * tiles_for(span, t[1]) * tiles_for(span, t[2]);
@@ -532,19 +550,92 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
     }
   }
   if (shift < 0) return fail(PMP_ERANGE, "binned deposit: too many tiles (%lld)", c->ntiles);
-  const int nb = (int)((c->ntiles + (1ll << shift) - 1) >> shift);
-  const long long hist = (long long)nb * (nbc + nbs) + 1;
-  const long long blocks = (hist + 1023) / 1024 + 1;
+  z.shift = shift;
+  z.nb = (int)((c->ntiles + (1ll << shift) - 1) >> shift);
+  z.hist = (long long)z.nb * (nbc + nbs) + 1;
+  z.blocks = (z.hist + 1023) / 1024 + 1;
+  z.tiles1 = c->ntiles + 1;
   // every bucket can add one partial slice to the full ones
-  const long long max_slices = full_slices + 2 * (long long)nb;
-  const long long hist2 = (max_slices << shift) + 1;
-  const long long blocks2 = (hist2 + 1023) / 1024 + 1;
+  const long long max_slices = full_slices + 2 * (long long)z.nb;
+  z.hist2 = (max_slices << shift) + 1;
+  z.blocks2 = (z.hist2 + 1023) / 1024 + 1;
   // chunk slots for split tiles, each holding two channels of a padded LDS tile
-  const long long slot_cap = 4ll * c->num_cu;
-  const long long partial = slot_cap * 2 * (long long)(t[0] + 2 * c->ghost + 1) * t[1] * t[2];
-  if (cic_cap >= (1ll << 31) || sn_cap >= (1ll << 31) || hist >= (1ll << 31) ||
-      hist2 >= (1ll << 31))
+  z.slot_cap = 4ll * c->num_cu;
+  z.partial = z.slot_cap * 2 * (long long)(t[0] + 2 * c->ghost + 1) * t[1] * t[2];
+  z.cic_cap = cic_cap;
+  z.sn_cap = sn_cap;
+  z.slice_base = 2 * (long long)z.nb + 1;
+  z.n_sn = std::max<long long>(n_sn, 1);
+  if (cic_cap >= (1ll << 31) || sn_cap >= (1ll << 31) || z.hist >= (1ll << 31) ||
+      z.hist2 >= (1ll << 31))
     return fail(PMP_ERANGE, "binned deposit: too many tile entries");
+  return PMP_OK;
+}
+
+// The scratch arrays laid out one after another from base, each 256-byte
+// aligned; returns the bytes used.  With w non-null, w's arrays point there.
+size_t carve_bin(const BinSizes& z, char* base, BinWork* w) {
+  size_t off = 0;
+  BinWork tmp{};
+  BinWork& W = w ? *w : tmp;
+  auto take = [&](auto*& p, long long count) {
+    using T = typename std::remove_reference<decltype(*p)>::type;
+    off = (off + 255) & ~(size_t)255;
+    p = reinterpret_cast<T*>(base + off);
+    off += (size_t)std::max<long long>(count, 1) * sizeof(T);
+  };
+  double* partial = nullptr;
+  take(W.hist, z.hist);
+  take(W.block_sums, z.blocks);
+  take(W.cic_off, z.tiles1);
+  take(W.sn_off, z.tiles1);
+  take(W.heavy_base, z.tiles1);
+  take(partial, z.partial);
+  W.partial = partial;
+  take(W.heavy_unit, z.slot_cap);
+  take(W.arrive, z.slot_cap);
+  take(W.heavy_count, 1);
+  take(W.cic_tmp, z.cic_cap);
+  take(W.cic_tmp_tile, z.cic_cap);
+  take(W.cic_rec, z.cic_cap);
+  take(W.sn_tmp, z.sn_cap);
+  take(W.sn_tmp_tile, z.sn_cap);
+  take(W.sn_rec, z.sn_cap);
+  take(W.hist2, z.hist2);
+  take(W.block_sums2, z.blocks2);
+  take(W.slice_base, z.slice_base);
+  take(W.sn_pk, z.n_sn);
+  if (w) {
+    W.cic_cap = z.cic_cap;
+    W.sn_cap = z.sn_cap;
+    W.slot_cap = z.slot_cap;
+    W.shift = z.shift;
+    W.nbuckets = z.nb;
+    W.max_slices = (z.hist2 - 1) >> z.shift;
+  }
+  return off;
+}
+
+size_t sink_scratch_bytes(long long n) {
+  return ((size_t)std::max<long long>(2 * n, 1) * sizeof(double) + 255) & ~(size_t)255;
+}
+
+int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, hipStream_t s) {
+  BinSizes z;
+  if (int rc = bin_sizes(c, n_cic, n_sn, r_max, z)) return rc;
+  if (c->ws) {
+    // caller-owned workspace: carve, after the sink scratch of this deposit
+    const size_t need = c->ws_sink_bytes + carve_bin(z, nullptr, nullptr);
+    if (need > c->ws_bytes)
+      return fail(PMP_ERANGE, "workspace of %zu bytes is too small: this deposit needs %zu",
+                  c->ws_bytes, need);
+    carve_bin(z, c->ws + c->ws_sink_bytes, &c->bw);
+    return PMP_OK;
+  }
+  const int shift = z.shift, nb = z.nb;
+  const long long hist = z.hist, blocks = z.blocks, hist2 = z.hist2, blocks2 = z.blocks2;
+  const long long slot_cap = z.slot_cap, partial = z.partial, cic_cap = z.cic_cap,
+                  sn_cap = z.sn_cap;
   c->bw.shift = shift;
   c->bw.nbuckets = nb;
   const bool grow = hist > c->bw_hist || blocks > c->bw_blocks || c->ntiles + 1 > c->bw_tiles ||
@@ -676,6 +767,7 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
                void* fuse_state = nullptr, bool* fused = nullptr) {
   if (fused) *fused = false;
   if (!buf) return fail(PMP_EINVAL, "buffer is NULL");
+  c->ws_sink_bytes = 0;  // a workspace holds this deposit's sink scratch first, if any
   const bool has_cic = cic && cic->n > 0;
   const bool has_sn = sn && sn->n > 0;
   const bool has_sink = sinks && sinks->n > 0;
@@ -958,8 +1050,6 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   if (e == hipSuccess) e = dev_alloc(&c->d_boxes, c->nbox);
   if (e == hipSuccess) e = dev_alloc(&c->d_owned_prefix, c->nbox + 1);
   if (e == hipSuccess) e = dev_alloc(&c->d_shell_prefix, c->nbox + 1);
-  if (e == hipSuccess) e = dev_alloc(&c->d_seg_off, c->nbox + 1);
-  if (e == hipSuccess) e = dev_alloc(&c->d_segs, segs.size());
   if (e == hipSuccess) e = dev_alloc(&c->d_status, 1);
   if (e == hipSuccess)
     e = hipMemcpy(c->d_boxes, c->dboxes.data(), sizeof(DevBox) * c->nbox, hipMemcpyHostToDevice);
@@ -969,11 +1059,6 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   if (e == hipSuccess)
     e = hipMemcpy(c->d_shell_prefix, shell_prefix.data(), sizeof(long long) * (c->nbox + 1),
                   hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(c->d_seg_off, seg_off.data(), sizeof(int) * (c->nbox + 1),
-                  hipMemcpyHostToDevice);
-  if (e == hipSuccess && !segs.empty())
-    e = hipMemcpy(c->d_segs, segs.data(), sizeof(DevSeg) * segs.size(), hipMemcpyHostToDevice);
   auto upload = [&](auto** dst, const auto& v) {
     if (e == hipSuccess) e = dev_alloc(dst, v.size());
     if (e == hipSuccess && !v.empty())
@@ -1019,6 +1104,44 @@ void pmp_destroy(pmp_ctx* c) {
   (void)hipDeviceSynchronize();
   release(c);
   delete c;
+}
+
+int pmp_workspace_size(const pmp_ctx* c, int64_t max_cic, int64_t max_sn, double max_sn_radius,
+                       int64_t max_sinks, size_t* bytes) {
+  if (!c || !bytes) return fail(PMP_EINVAL, "NULL argument");
+  if (max_cic < 0 || max_sn < 0 || max_sinks < 0 || !(max_sn_radius >= 0.0))
+    return fail(PMP_EINVAL, "workspace_size: negative count or radius");
+  size_t total = max_sinks > 0 ? sink_scratch_bytes(max_sinks) : 0;
+  if (max_cic > 0 || max_sn > 0) {
+    BinSizes z;
+    if (int rc = bin_sizes(c, max_cic, max_sn, max_sn_radius, z)) return rc;
+    total += carve_bin(z, nullptr, nullptr);
+  }
+  *bytes = std::max<size_t>((total + 255) & ~(size_t)255, 256);
+  return PMP_OK;
+}
+
+int pmp_set_workspace(pmp_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c) return fail(PMP_EINVAL, "NULL context");
+  if (dev_ptr && ((uintptr_t)dev_ptr & 255))
+    return fail(PMP_EINVAL, "workspace must be 256-byte aligned");
+  if (dev_ptr && bytes < 256) return fail(PMP_EINVAL, "workspace smaller than 256 bytes");
+  if (c->graph_exec)
+    return fail(PMP_EINVAL, "a built graph holds scratch addresses: set the workspace first");
+  PMP_HIP(hipDeviceSynchronize());
+  // the library's own scratch is released, or, leaving a workspace, forgotten
+  if (!c->ws) {
+    free_bin_work(c);
+    (void)hipFree(c->d_sink_scratch);
+  } else {
+    c->bw = BinWork{};
+  }
+  c->d_sink_scratch = nullptr;
+  c->sink_cap = 0;
+  c->ws = static_cast<char*>(dev_ptr);
+  c->ws_bytes = dev_ptr ? bytes : 0;
+  c->ws_sink_bytes = 0;
+  return PMP_OK;
 }
 
 int pmp_sizes(const pmp_ctx* c, int64_t* state_elems, int64_t* buffer_elems,
@@ -1277,6 +1400,15 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
   // run (LDS) is skipped
   auto time_one = [&](const pmp_tuning& cand_t) {
     if (rc != PMP_OK || pmp_set_tuning(c, &cand_t) != PMP_OK) return;
+    if (c->ws && cand_t.deposit_path == 1) {
+      // a caller's workspace: skip tile shapes whose scratch does not fit it
+      size_t need = 0;
+      if (pmp_workspace_size(c, cic ? cic->n : 0, sn ? sn->n : 0,
+                             (sn && sn->n > 0) ? sn->r_max : 0.0, sinks ? sinks->n : 0,
+                             &need) != PMP_OK ||
+          need > c->ws_bytes)
+        return;
+    }
     if (launch_copy(work, state, (long long)sbytes, s) != hipSuccess) {
       rc = fail(PMP_EDEVICE, "autotune: state copy failed");
       return;

@@ -70,8 +70,6 @@ struct Mesh {
   long long owned_cells;
   const long long* owned_prefix;  // [nbox+1] cumulative owned cells
   const long long* shell_prefix;  // [nbox+1] cumulative shell cells
-  const int* seg_off;             // [nbox+1] fold segments per destination box
-  const DevSeg* segs;
   // Each box splits along every axis into [0, g), [g, n - g), [n - g, n) (27
   // zones); zone_off[28 b + z] .. zone_off[28 b + z + 1] index zone_seg, the
   // segments (in plan order) that reach zone z of box b, with their source

@@ -510,3 +510,55 @@ def test_graph_multibox(B):
         torch.cuda.synchronize()
         assert np.array_equal(g.state.cpu().numpy(), ref)
     g.close()
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_workspace_caller_owned(B, name):
+    """Scratch carved from a caller-owned workspace gives the results of the
+    library's own scratch, bit for bit in fixed point, for the step and for a
+    graph of it (CIC + supernovae fused; CIC + sinks); a workspace too small
+    for the deposit is refused with PMP_ERANGE, and None returns to the
+    library's own scratch."""
+    import torch
+    w = W.c2(nx=32) if name == "c2" else W.c3(nx=32, n_sink=16)
+    say(f"workspace {name}")
+
+    def run(ctx, graph=False):
+        ctx.reset_state()
+        if graph:
+            ctx.graph_build(1)
+            ctx.graph_launch()
+        else:
+            ctx.step()
+        torch.cuda.synchronize()
+        return ctx.state.cpu().numpy().copy(), ctx.status()
+
+    ref = B.Context(w, "fix64", channels="auto")
+    ref.set_tuning(deposit_path=1)
+    want, st_ref = run(ref)
+    ref.close()
+    ctx = B.Context(w, "fix64", channels="auto")
+    ctx.set_tuning(deposit_path=1)
+    nbytes = ctx.workspace_size()
+    assert nbytes >= 256 and nbytes % 256 == 0
+    ws = torch.full((nbytes,), 0xAB, dtype=torch.uint8, device="cuda")
+    ctx.set_workspace(ws)
+    for graph in (False, True):
+        got, st = run(ctx, graph)
+        assert st["flags"] in (0, 0x10), st
+        assert np.array_equal(got, want), graph
+        for k in ("touched", "bind", "lam", "fall"):
+            assert st[k] == st_ref[k], (k, st, st_ref)
+    ctx.close()
+    # too small: refused, nothing launched
+    ctx = B.Context(w, "fix64", channels="auto")
+    ctx.set_tuning(deposit_path=1)
+    small = torch.empty(max(256, (nbytes // 2) // 256 * 256), dtype=torch.uint8, device="cuda")
+    ctx.set_workspace(small)
+    with pytest.raises(B.PmpError) as e:
+        ctx.step()
+    assert "workspace" in str(e.value)
+    ctx.set_workspace(None)
+    got, _ = run(ctx)
+    assert np.array_equal(got, want)
+    ctx.close()
