@@ -89,6 +89,28 @@ def algorithmic_bytes(w, acc, counts, F, fused=False):
     return out
 
 
+def nominal_step_bytes(w, acc, counts):
+    """The method's nominal bytes per step, counted as if every phase ran
+    separately with the full channel set (5 fields, 6 with sinks): zero fill,
+    particle records, a read-modify-write of every touched (cell, field), the
+    sinks' state reads, three accesses per ghost cell and field for the fold,
+    and state in/out plus buffer in for the apply.  A yardstick for the whole
+    step; the fused path moves far fewer bytes than this."""
+    import numpy as np
+    ba = acc_bytes(acc)
+    bs = np.dtype(w.state.dtype).itemsize
+    n = w.n.astype(np.int64)
+    g = w.ghost
+    owned = int(np.prod(n, axis=1).sum())
+    padded = int(np.prod(n + 2 * g, axis=1).sum())
+    F = 6 if (w.sinks is not None and w.sinks.n) else 5
+    parts = (w.cic.n * 32 if w.cic is not None else 0) + (w.sn.n * 48 if w.sn is not None else 0) + \
+        (w.sinks.n * 32 if w.sinks is not None else 0)
+    touched = counts.get("cic", 0) + counts.get("sn", 0) + counts.get("sink", 0)
+    return (padded * F * ba + parts + 2 * ba * touched + 5 * bs * counts.get("sink", 0)
+            + 3 * ba * F * (padded - owned) + owned * F * (2 * bs + ba))
+
+
 def touched_counts(B, w, acc):
     """Unique (cell, field) pairs each particle kind writes, counted as the
     nonzero buffer entries after depositing that kind alone (all
@@ -355,6 +377,10 @@ def main():
         "cells_per_s": w.owned_cells / (ms * 1e-3),
         "step_algo_bytes": int(step_bytes),
         "step_hbm_frac": step_bytes / (ms * 1e-3) / (HBM_PEAK_GBPS * 1e9),
+        # the unfused, full-channel count of the same step (a yardstick, not traffic)
+        "step_nominal_bytes": int(nominal_step_bytes(w, args.acc, counts)),
+        "step_nominal_frac": nominal_step_bytes(w, args.acc, counts) / (ms * 1e-3) /
+                             (HBM_PEAK_GBPS * 1e9),
         "roofline": {"bound": "hbm", "kernel": kernel_names[dom], "phase": dom,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
