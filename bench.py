@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -157,9 +158,12 @@ def run_steps(ctx, steps, warmup, profile=True):
     return ms, phases
 
 
-def run_graph(ctx, steps, warmup):
+def run_graph(ctx, steps, warmup, spread=None):
     """ms per step of a captured one-step HIP graph, replayed `steps` times
-    after `warmup` untimed replays."""
+    after `warmup` untimed replays, with one event on each side of the timed
+    replays.  `spread`, a dict, receives the median, min and max of a second
+    pass of as many replays with an event between every two."""
+    import statistics
     import torch
     ctx.graph_build(1)
     for _ in range(warmup):
@@ -172,7 +176,17 @@ def run_graph(ctx, steps, warmup):
         ctx.graph_launch()
     t1.record()
     torch.cuda.synchronize()
-    return t0.elapsed_time(t1) / steps
+    ms = t0.elapsed_time(t1) / steps
+    if spread is not None:
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record()
+        for i in range(steps):
+            ctx.graph_launch()
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+        spread.update({"median": statistics.median(per), "min": min(per), "max": max(per)})
+    return ms
 
 
 def stream_copy_gbps(B, nbytes=1 << 30, reps=10):
@@ -259,7 +273,14 @@ def cpu_baseline(w, n_particles, target_s=10.0):
         if time.perf_counter() - t_start >= target_s or len(times) >= 5:
             break
     t = min(times)
+    cpu = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": n_particles / t, "unit": "particles/s", "cores": ncores, "kind": "oracle",
+            "host_cpu": cpu, "host_cpus_visible": os.cpu_count(),
             "sample": f"{len(times)} full serial FP64 oracle steps of the same workload "
                       f"(deposit, fold, apply; {t:.2f} s each, best taken)",
             "cells_per_s": w.owned_cells / t, "s_per_step": t}
@@ -318,7 +339,8 @@ def main():
     # headline: the step replayed from a captured HIP graph; eager launches
     # and the per-phase profile (events between phases) in runs of their own
     eager_ms, _ = run_steps(ctx, args.steps, args.warmup, profile=False)
-    ms = run_graph(ctx, args.steps, args.warmup)
+    spread = {}
+    ms = run_graph(ctx, args.steps, args.warmup, spread)
     _, phases = run_steps(ctx, args.steps, 2, profile=True)
     st = ctx.status()
     log(f"step {ms:.4f} ms (graph), {eager_ms:.4f} ms (eager); status {st}")
@@ -362,6 +384,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_spread": {k: round(v, 5) for k, v in spread.items()},
         "eager_ms_per_step": eager_ms,
         "higher_is_better": True,
         "scaling": "weak",
