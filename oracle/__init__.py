@@ -6,8 +6,11 @@ import the HIP package either: workloads are passed in duck-typed (any object
 with ``lo, n, ghost, domain, dx, state, cic, sn, sinks, limits, r_k,
 r_gauss``), particle kinds as objects with ``fields`` and ``box_off``.
 
-Modes: ``"f64"`` (double buffer, sequential sums in array order) and
-``"fix64"`` (int64 buffer on the 2^-40 grid; exact and order-free).
+Modes: ``"f64"`` (double buffer, sequential sums in array order),
+``"fix64"`` (int64 buffer on the 2^-40 grid; exact and order-free) and
+``"f64r"`` (double sums with the error bound of App. A.1, each buffer element
+truncated after the deposit; margin ``M`` from the workload's
+``margin_bits``, default 28).
 """
 from __future__ import annotations
 
@@ -24,8 +27,9 @@ _LIB = os.path.join(_HERE, "libpmp_oracle.so")
 CFLAGS = ["-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math",
           "-shared", "-fPIC"]
 
-F64, FIX64 = 0, 1
-MODES = {"f64": F64, "fix64": FIX64}
+F64, FIX64, F64R = 0, 1, 2
+MODES = {"f64": F64, "fix64": FIX64, "f64r": F64R}
+MARGIN_DEFAULT = 28
 FIX_INV = 2.0 ** -40
 
 ERRORS = {-1: "EINVAL", -2: "EOUTSIDE", -3: "EREACH", -4: "EOVERFLOW", -5: "ENOMEM",
@@ -92,6 +96,9 @@ def lib():
         L.orc_state_elems.restype = C.c_int64
         L.orc_state_elems.argtypes = [vp]
         L.orc_deposit.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_deposit_r.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]
+        L.orc_truncate_err.restype = C.c_double
+        L.orc_truncate_err.argtypes = [C.c_double, C.c_double, i32]
         L.orc_fold.argtypes = [vp, i32, vp]
         L.orc_sink_update.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_apply.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -175,14 +182,29 @@ def deposit(w, mode, mesh=None, state64=None):
     if state64 is None:
         state64 = _f64(w.state)
     lim = _limits(w.limits)
-    buf = np.empty(mesh.buffer_elems, dtype=np.float64 if m == F64 else np.int64)
+    buf = np.empty(mesh.buffer_elems, dtype=np.int64 if m == FIX64 else np.float64)
     sw = np.zeros(max(nsink, 1))
     sm = np.zeros(max(nsink, 1))
-    rc = lib().orc_deposit(C.byref(mesh.c), m, C.byref(cic) if cic else None,
-                           C.byref(sn) if sn else None, C.byref(sk) if sk else None,
-                           C.byref(lim), _ptr(state64), _ptr(buf), _ptr(sw), _ptr(sm))
+    args = (C.byref(cic) if cic else None, C.byref(sn) if sn else None,
+            C.byref(sk) if sk else None, C.byref(lim), _ptr(state64), _ptr(buf))
+    if m == F64R:
+        err = np.empty(mesh.buffer_elems)
+        rc = lib().orc_deposit_r(C.byref(mesh.c), *args, _ptr(err), margin_of(w), _ptr(sw),
+                                 _ptr(sm))
+    else:
+        rc = lib().orc_deposit(C.byref(mesh.c), m, *args, _ptr(sw), _ptr(sm))
     _check(rc, "deposit")
     return buf, sw[:nsink], sm[:nsink]
+
+
+def margin_of(w):
+    """The reproducibility mode's safety margin M (bits) of a workload."""
+    return int(getattr(w, "margin_bits", MARGIN_DEFAULT))
+
+
+def truncate_err(v, err, margin):
+    """The oracle's App. A.1 truncation of one value (for checks)."""
+    return lib().orc_truncate_err(float(v), float(err), int(margin))
 
 
 def fold(w, mode, buf, mesh=None):

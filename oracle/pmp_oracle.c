@@ -200,7 +200,14 @@ static void sphere_range(double p, double r, int64_t *lo, int64_t *hi) {
   *hi = (int64_t)floor(p + r - 0.5) + 1;
 }
 
-static void add_f64(void *buf, int64_t idx, double v) { ((double *)buf)[idx] += v; }
+/* Double-precision accumulation.  With err (mode ORC_F64R, App. A.1 item 2)
+ * the cell's error bound also grows by eps |sum after the addition|. */
+#define ORC_EPS 0x1p-52 /* double machine epsilon */
+static void add_f64(void *buf, double *err, int64_t idx, double v) {
+  double *B = (double *)buf;
+  B[idx] += v;
+  if (err) err[idx] += ORC_EPS * fabs(B[idx]);
+}
 static void add_fix(void *buf, int64_t idx, int64_t q) {
   int64_t *B = (int64_t *)buf;
   B[idx] = iadd(B[idx], q);
@@ -213,7 +220,7 @@ static void add_fix(void *buf, int64_t idx, int64_t q) {
  * paper's PM deposit (Sec. 3.1, item 1; Sec. 2.2 "steps 1, 2 and 5") does not
  * name its assignment scheme; CIC is the textbook one. */
 static int deposit_cic(const orc_mesh *M, const geom *G, int mode, const orc_cic *P,
-                       void *buf, double V) {
+                       void *buf, double *err, double V) {
   for (int b = 0; b < M->nbox; ++b) {
     for (int64_t p = P->box_off[b]; p < P->box_off[b + 1]; ++p) {
       double pos[3] = {P->x[p], P->y[p], P->z[p]};
@@ -239,8 +246,8 @@ static int deposit_cic(const orc_mesh *M, const geom *G, int mode, const orc_cic
             double c = ((m * wx) * wy) * wz / V;
             int64_t idx = buf_index(M, G, b, 0, i0[0] + di, i0[1] + dj, i0[2] + dk);
             if (idx < 0) return ORC_EREACH;
-            if (mode == ORC_F64) {
-              add_f64(buf, idx, c);
+            if (mode != ORC_FIX64) {
+              add_f64(buf, err, idx, c);
             } else {
               int64_t q;
               if (q40(c, &q)) return ORC_EOVERFLOW;
@@ -264,7 +271,7 @@ static int deposit_cic(const orc_mesh *M, const geom *G, int mode, const orc_cic
  * the N cells whose centres lie within r (Sec. 3.2.1, eq. "du" with full
  * coverage and no momentum term).  Fields 0 (rho) and 4 (E). */
 static int deposit_sn(const orc_mesh *M, const geom *G, int mode, const orc_sn *P, void *buf,
-                      double V) {
+                      double *err, double V) {
   for (int b = 0; b < M->nbox; ++b) {
     for (int64_t p = P->box_off[b]; p < P->box_off[b + 1]; ++p) {
       double x = P->x[p], y = P->y[p], z = P->z[p], m = P->m[p], e = P->e[p], r = P->r[p];
@@ -302,9 +309,9 @@ static int deposit_sn(const orc_mesh *M, const geom *G, int mode, const orc_sn *
             int64_t i0 = buf_index(M, G, b, 0, i, j, k);
             int64_t i4 = buf_index(M, G, b, 4, i, j, k);
             if (i0 < 0 || i4 < 0) return ORC_EREACH;
-            if (mode == ORC_F64) {
-              add_f64(buf, i0, cr);
-              add_f64(buf, i4, ce);
+            if (mode != ORC_FIX64) {
+              add_f64(buf, err, i0, cr);
+              add_f64(buf, err, i4, ce);
             } else {
               add_fix(buf, i0, qr);
               add_fix(buf, i4, qe);
@@ -331,8 +338,8 @@ static int deposit_sn(const orc_mesh *M, const geom *G, int mode, const orc_sn *
  * taken in 2^-40 fixed point so that they do not depend on summation order.
  * Field 5 holds the removed density K >= 0. */
 static int deposit_sinks(const orc_mesh *M, const geom *G, int mode, const orc_sinks *S,
-                         const orc_limits *L, const double *state, void *buf, double V,
-                         double *sink_w, double *sink_mreq) {
+                         const orc_limits *L, const double *state, void *buf, double *err,
+                         double V, double *sink_w, double *sink_mreq) {
   double r2 = S->r_k * S->r_k;
   double g2 = S->r_gauss * S->r_gauss;
   for (int b = 0; b < M->nbox; ++b) {
@@ -385,8 +392,8 @@ static int deposit_sinks(const orc_mesh *M, const geom *G, int mode, const orc_s
             double kc = (tr > kreq) ? tr : kreq;
             int64_t idx = buf_index(M, G, b, 5, i, j, k);
             if (idx < 0) return ORC_EREACH;
-            if (mode == ORC_F64) {
-              add_f64(buf, idx, kc);
+            if (mode != ORC_FIX64) {
+              add_f64(buf, err, idx, kc);
             } else {
               int64_t qk, qr;
               if (q40(kc, &qk) || q40(kreq, &qr)) return ORC_EOVERFLOW;
@@ -413,29 +420,74 @@ static int check_fix_range(const void *buf, int64_t n) {
   return ORC_OK;
 }
 
-/* Step 1 (Sec. 2.2, eq. "delta_u_buf"): zero the buffer, then add every
- * particle's deposition function; CIC first, then supernovae, then sinks,
- * each in array order. */
-int orc_deposit(const orc_mesh *M, int mode, const orc_cic *cic, const orc_sn *sn,
-                const orc_sinks *sk, const orc_limits *L, const double *state, void *buf,
-                double *sink_w, double *sink_mreq) {
+/* App. A.1 items 3-4: the relative error bound r = err / |v| of a summed
+ * cell, then v with its lowest nb = 52 + M + ceil(log2 r) mantissa bits
+ * cleared (nb clamped to [0, 52]).  ceil(log2 r) is read off frexp exactly:
+ * r = m 2^k with m in [1/2, 1), so it is k - 1 when m = 1/2 and k otherwise.
+ * Zero and non-finite sums, and cells nothing was added to, stay as they are. */
+static double truncate_err(double v, double err, int margin) {
+  if (v == 0.0 || !isfinite(v) || !(err > 0.0)) return v;
+  int k;
+  const double m = frexp(err / fabs(v), &k);
+  int nb = 52 + margin + ((m == 0.5) ? k - 1 : k);
+  if (nb <= 0) return v;
+  if (nb > 52) nb = 52;
+  uint64_t bits;
+  memcpy(&bits, &v, sizeof bits);
+  bits &= ~((((uint64_t)1) << nb) - 1);
+  memcpy(&v, &bits, sizeof v);
+  return v;
+}
+
+static int deposit_all(const orc_mesh *M, int mode, const orc_cic *cic, const orc_sn *sn,
+                       const orc_sinks *sk, const orc_limits *L, const double *state,
+                       void *buf, double *err, double *sink_w, double *sink_mreq) {
   int rc = check_mesh(M);
   if (rc) return rc;
-  if (mode != ORC_F64 && mode != ORC_FIX64) return ORC_EINVAL;
   if (sk && (M->nfield != 6 || !state || !L || !sink_w || !sink_mreq)) return ORC_EINVAL;
   geom G;
   rc = geom_build(M, &G, sk != NULL);
   if (rc) return rc;
   int64_t nb = orc_buffer_elems(M);
   memset(buf, 0, (size_t)nb * 8);
+  if (err) memset(err, 0, (size_t)nb * 8);
   double V = (M->dx * M->dx) * M->dx;
-  if (cic) rc = deposit_cic(M, &G, mode, cic, buf, V);
-  if (!rc && sn) rc = deposit_sn(M, &G, mode, sn, buf, V);
-  if (!rc && sk) rc = deposit_sinks(M, &G, mode, sk, L, state, buf, V, sink_w, sink_mreq);
+  if (cic) rc = deposit_cic(M, &G, mode, cic, buf, err, V);
+  if (!rc && sn) rc = deposit_sn(M, &G, mode, sn, buf, err, V);
+  if (!rc && sk)
+    rc = deposit_sinks(M, &G, mode, sk, L, state, buf, err, V, sink_w, sink_mreq);
   if (!rc && mode == ORC_FIX64) rc = check_fix_range(buf, nb);
   geom_free(&G);
   return rc;
 }
+
+/* Step 1 (Sec. 2.2, eq. "delta_u_buf"): zero the buffer, then add every
+ * particle's deposition function; CIC first, then supernovae, then sinks,
+ * each in array order. */
+int orc_deposit(const orc_mesh *M, int mode, const orc_cic *cic, const orc_sn *sn,
+                const orc_sinks *sk, const orc_limits *L, const double *state, void *buf,
+                double *sink_w, double *sink_mreq) {
+  if (mode != ORC_F64 && mode != ORC_FIX64) return ORC_EINVAL;
+  return deposit_all(M, mode, cic, sn, sk, L, state, buf, NULL, sink_w, sink_mreq);
+}
+
+/* Step 1 in the reproducibility mode of App. A.1: the double-precision sums
+ * of orc_deposit (same order) with an error bound per buffer element, then
+ * every element truncated by truncate_err.  err (same size as buf) receives
+ * the bounds. */
+int orc_deposit_r(const orc_mesh *M, const orc_cic *cic, const orc_sn *sn,
+                  const orc_sinks *sk, const orc_limits *L, const double *state, double *buf,
+                  double *err, int margin, double *sink_w, double *sink_mreq) {
+  if (!err || margin < 0 || margin > 52) return ORC_EINVAL;
+  int rc = deposit_all(M, ORC_F64R, cic, sn, sk, L, state, buf, err, sink_w, sink_mreq);
+  if (rc) return rc;
+  const int64_t nb = orc_buffer_elems(M);
+  for (int64_t i = 0; i < nb; ++i) buf[i] = truncate_err(buf[i], err[i], margin);
+  return ORC_OK;
+}
+
+/* The truncation alone, for checks. */
+double orc_truncate_err(double v, double err, int margin) { return truncate_err(v, err, margin); }
 
 /* ------------------------------------------------------------- Step 2: fold */
 
@@ -464,7 +516,7 @@ int orc_fold(const orc_mesh *M, int mode, void *buf) {
           for (int f = 0; f < M->nfield; ++f) {
             int64_t src = buf_index(M, &G, b, f, i, j, k);
             int64_t dst = buf_index(M, &G, ob, f, iw, jw, kw);
-            if (mode == ORC_F64)
+            if (mode != ORC_FIX64)
               ((double *)buf)[dst] += ((double *)buf)[src];
             else
               add_fix(buf, dst, ((int64_t *)buf)[src]);
@@ -492,7 +544,7 @@ static double limited_removal(double K, double rho, const orc_limits *L) {
 }
 
 static double buf_value(int mode, const void *buf, int64_t idx) {
-  if (mode == ORC_F64) return ((const double *)buf)[idx];
+  if (mode != ORC_FIX64) return ((const double *)buf)[idx];
   return (double)((const int64_t *)buf)[idx] * FIX_INV;
 }
 
@@ -545,7 +597,7 @@ int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void
               double vx = state[state_index(M, &G, ob, 1, iw, jw, kw)] / rho;
               double vy = state[state_index(M, &G, ob, 2, iw, jw, kw)] / rho;
               double vz = state[state_index(M, &G, ob, 3, iw, jw, kw)] / rho;
-              if (mode == ORC_F64) {
+              if (mode != ORC_FIX64) {
                 sm += term;
                 sx += term * vx;
                 sy += term * vy;

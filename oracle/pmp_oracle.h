@@ -42,7 +42,9 @@
 extern "C" {
 #endif
 
-enum { ORC_F64 = 0, ORC_FIX64 = 1 };
+/* ORC_F64R: double sums with the error bound and truncation of App. A.1
+ * (orc_deposit_r); fold, sink update and apply treat its buffer as ORC_F64. */
+enum { ORC_F64 = 0, ORC_FIX64 = 1, ORC_F64R = 2 };
 
 enum {
   ORC_OK = 0,
@@ -87,6 +89,10 @@ double  orc_exp(double x);
 int orc_deposit(const orc_mesh *M, int mode, const orc_cic *cic, const orc_sn *sn,
                 const orc_sinks *sk, const orc_limits *L, const double *state, void *buf,
                 double *sink_w, double *sink_mreq);
+int orc_deposit_r(const orc_mesh *M, const orc_cic *cic, const orc_sn *sn,
+                  const orc_sinks *sk, const orc_limits *L, const double *state, double *buf,
+                  double *err, int margin, double *sink_w, double *sink_mreq);
+double orc_truncate_err(double v, double err, int margin);
 int orc_fold(const orc_mesh *M, int mode, void *buf);
 int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void *buf,
                     const orc_sinks *sk, const orc_limits *L, const double *sink_w,

@@ -260,6 +260,84 @@ def test_fixed_point_permutation_invariant(orc):
     assert np.array_equal(bq, b2)
 
 
+# ------------------------------------ reproducibility mode (App. A.1, error bound)
+
+def _bits(a):
+    return np.ascontiguousarray(a, dtype=np.float64).view(np.uint64)
+
+
+def test_truncation_closed_forms(orc):
+    """One contribution: err = eps |v| exactly, so nb = M and 52 - M mantissa
+    bits stay; two same-sign contributions: err / |v| lies strictly between
+    eps and 2 eps, so nb = M + 1; zero, and err = 0, pass unchanged."""
+    eps = 2.0 ** -52
+    for v in (1.2345678901234567, -3.75e-7, 6.02e23):
+        for M in (0, 10, 28, 40):
+            got = orc.truncate_err(v, eps * abs(v), M)
+            want = (_bits([v]) & ~np.uint64((1 << M) - 1)).view(np.float64)[0]
+            assert got == want, (v, M)
+    a, b = 0.7, 0.3001
+    s = a + b
+    err = eps * abs(a) + eps * abs(s)
+    got = orc.truncate_err(s, err, 28)
+    assert got == (_bits([s]) & ~np.uint64((1 << 29) - 1)).view(np.float64)[0]
+    assert orc.truncate_err(0.0, 1e-30, 28) == 0.0
+    assert orc.truncate_err(5.0, 0.0, 28) == 5.0
+    # nb never exceeds the 52 mantissa bits: a huge bound leaves the leading power of two
+    assert orc.truncate_err(1.9999, 1.0, 28) == 1.0
+
+
+def test_f64r_is_f64_with_low_bits_cleared(orc):
+    """The reproducibility mode sums in the order of the plain FP64 mode, so
+    every buffer element equals the FP64 one with low mantissa bits cleared,
+    at least M of them wherever anything was deposited (a single-contribution
+    cell exactly M)."""
+    M = 28
+    w = W.c2(nx=32)
+    b64, _, _ = orc.deposit(w, "f64")
+    br, _, _ = orc.deposit(w, "f64r")
+    x, y = _bits(b64), _bits(br)
+    nz = b64 != 0.0
+    assert np.array_equal(br[~nz], b64[~nz])
+    cleared = x[nz] ^ y[nz]
+    assert np.all((y[nz] & ~x[nz]) == 0)  # only bits of x cleared, none set
+    # the cleared bits are low bits: x with its low k bits cleared equals y for
+    # the k of its highest cleared bit
+    hi = np.where(cleared == 0, 0, np.floor(np.log2(np.maximum(cleared, 1).astype(np.float64))) + 1)
+    assert np.all(hi <= 52)
+    keep = x[nz] & ~((np.uint64(1) << hi.astype(np.uint64)) - np.uint64(1))
+    assert np.array_equal(keep, y[nz])
+    # an isolated CIC particle at a cell centre: one contribution, exactly M bits cleared
+    w1 = one_box(8, 1, cic=([[4.5, 4.5, 4.5]], {"m": [0.8123456789]}))
+    b1, _, _ = orc.deposit(w1, "f64")
+    r1, _, _ = orc.deposit(w1, "f64r")
+    i = int(np.flatnonzero(b1)[0])
+    assert np.count_nonzero(b1) == 1
+    assert _bits([r1[i]])[0] == _bits([b1[i]])[0] & ~np.uint64((1 << M) - 1)
+
+
+def test_f64r_mostly_permutation_invariant(orc):
+    """The property App. A.1 claims: re-ordering the contributions moves the
+    truncated sums only where a sum lies within its error of a truncation
+    boundary, or where the bound itself crosses a power of two (cells with
+    three or more contributions); most cells keep their bits, and every cell
+    stays within one truncation interval."""
+    w = W.c2(nx=32)
+    br, _, _ = orc.deposit(w, "f64r")
+    rng = np.random.default_rng(7)
+    perm_c = rng.permutation(w.cic.n)
+    perm_s = rng.permutation(w.sn.n)
+    cic = W.Particles({k: v[perm_c] for k, v in w.cic.fields.items()}, w.cic.box_off)
+    sn = W.Particles({k: v[perm_s] for k, v in w.sn.fields.items()}, w.sn.box_off)
+    import dataclasses
+    b2, _, _ = orc.deposit(dataclasses.replace(w, cic=cic, sn=sn), "f64r")
+    nz = (br != 0.0) | (b2 != 0.0)
+    same = np.mean(br[nz] == b2[nz])
+    assert same > 0.9, same
+    rel = np.abs(br[nz] - b2[nz]) / np.maximum(np.abs(br[nz]), np.abs(b2[nz]))
+    assert rel.max() <= 2.0 ** -(52 - 28 - 8), rel.max()
+
+
 # ------------------------------------------------------------ limiter (P1, P8, P11)
 
 def test_fig1_worked_example(orc):
