@@ -263,6 +263,34 @@ def batched_comparison(ctx, args, eager_ms):
             "tuning": tun.as_dict()}
 
 
+def repro_rates(B, w, channels):
+    """Fraction of the deposited buffer's nonzero elements that are bit-identical
+    between two deposits of the same inputs: the same launch again, and tiles
+    of another shape (another summation order), for FP64 sums, the
+    reproducibility mode (App. A.1 error bound and truncation) and int64
+    fixed point."""
+    import numpy as np
+    import torch
+    out = {}
+    shapes = ({}, {}, {"tile_x": 32, "tile_yz": 4, "tile_block": 128})
+    for acc in ("f64", "f64r", "fix64"):
+        bufs = []
+        for tun in shapes:
+            ctx = B.Context(w, acc, channels=channels)
+            ctx.set_tuning(deposit_path=1, **tun)
+            ctx.deposit()
+            torch.cuda.synchronize()
+            bufs.append(ctx.buf.cpu().numpy().copy())
+            ctx.close()
+            del ctx
+            torch.cuda.empty_cache()
+        nz = bufs[0] != 0
+        out[acc] = {"elements": int(nz.sum()),
+                    "same_launch": float(np.mean(bufs[0][nz] == bufs[1][nz])),
+                    "other_tiles": float(np.mean(bufs[0][nz] == bufs[2][nz]))}
+    return out
+
+
 def cpu_baseline(w, n_particles, target_s=10.0):
     import oracle
     ncores = 1
@@ -423,7 +451,9 @@ def main():
         log(f"stream copy {gbps:.0f} GB/s")
     if not args.no_modes:
         modes = {}
-        for acc, dt in (("fix64", None), ("f64", np.float64)):
+        for acc, dt in (("fix64", None), ("f64r", None), ("f64", np.float64)):
+            if acc == "f64r" and (overrides or {}).get("deposit_path", 1) != 1:
+                continue  # the reproducibility mode runs on the binned path only
             wm = w.with_state(w.state.astype(dt)) if dt is not None else w
             c2 = B.Context(wm, acc, channels=args.channels)
             if overrides:
@@ -439,6 +469,8 @@ def main():
             log(f"mode {acc}: {mms:.4f} ms/step")
         out["modes"] = modes
         out["speedup_vs_plain_f64"] = modes["f64_plain"]["ms_per_step"] / ms
+        out["reproducibility"] = repro_rates(B, w, args.channels)
+        log(f"reproducibility: {out['reproducibility']}")
     if not args.no_cpu:
         log("cpu baseline (serial oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, nparts)

@@ -75,7 +75,13 @@ extern "C" {
 #define PMP_FLAG_FLOOR 0x10u    /* energy floor infeasible: E raised (counted in fall) */
 #define PMP_FLAG_CAPACITY 0x20u /* binned path: tile entry list full (entries skipped) */
 
-typedef enum { PMP_ACC_F32 = 0, PMP_ACC_F64 = 1, PMP_ACC_FIX64 = 2 } pmp_acc_t;
+/* PMP_ACC_F64R: the reproducibility mode of App. A.1.  The buffer is FP64;
+ * every addition to a buffer element also adds eps |sum after the addition|
+ * (eps = 2^-52) to that element's error bound, and once the element's
+ * deposits are complete its lowest 52 + M + ceil(log2(bound / |sum|))
+ * mantissa bits (clamped to [0, 52]) are cleared, M = margin_bits.  Binned
+ * path only (deposit_path 1), tiles never split. */
+typedef enum { PMP_ACC_F32 = 0, PMP_ACC_F64 = 1, PMP_ACC_FIX64 = 2, PMP_ACC_F64R = 3 } pmp_acc_t;
 typedef enum { PMP_STATE_F32 = 0, PMP_STATE_F64 = 1 } pmp_state_t;
 
 typedef struct pmp_ctx pmp_ctx;
@@ -97,6 +103,8 @@ typedef struct {
                           into is identically zero and need not be stored:
                           CIC needs RHO, supernovae RHO | E, sinks K; absent
                           channels read as zero in the apply. */
+  int32_t margin_bits; /* PMP_ACC_F64R: the safety margin M, 0 .. 52 (the
+                          paper's example: 28); ignored otherwise */
 } pmp_layout;
 
 #define PMP_CH_RHO 0x1

@@ -7,7 +7,8 @@
  * or constant with the HIP library.
  *
  * It computes, in plain double precision (or in exact int64 fixed point with
- * 40 fractional bits), one pass of the method of He et al. (2025), Sec. 2.2:
+ * 40 fractional bits, or with the error bound and mantissa truncation of the
+ * paper's App. A.1), one pass of the method of He et al. (2025), Sec. 2.2:
  *   Step 1  particle -> ghost-zoned buffer (CIC mass, uniform-sphere
  *           supernova injection, Gaussian-kernel sink removal),
  *   Step 2  ghost -> owner summation (here: periodic images / neighbouring

@@ -19,9 +19,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpmp.so")
 
-PMP_ACC_F32, PMP_ACC_F64, PMP_ACC_FIX64 = 0, 1, 2
+PMP_ACC_F32, PMP_ACC_F64, PMP_ACC_FIX64, PMP_ACC_F64R = 0, 1, 2, 3
+MARGIN_DEFAULT = 28  # PMP_ACC_F64R safety margin (bits) unless the workload sets margin_bits
 PMP_STATE_F32, PMP_STATE_F64 = 0, 1
-ACC = {"f32": PMP_ACC_F32, "f64": PMP_ACC_F64, "fix64": PMP_ACC_FIX64}
+ACC = {"f32": PMP_ACC_F32, "f64": PMP_ACC_F64, "fix64": PMP_ACC_FIX64, "f64r": PMP_ACC_F64R}
 FLAGS = {0x1: "OUTSIDE", 0x2: "REACH", 0x4: "OVERFLOW", 0x8: "NAN", 0x10: "FLOOR",
          0x20: "CAPACITY"}
 ERRORS = {-1: "EINVAL", -2: "ERANGE", -3: "EDEVICE", -4: "ENOMEM", -5: "EUNSUPPORTED"}
@@ -37,7 +38,7 @@ class pmp_layout(C.Structure):
     _fields_ = [("nbox", C.c_int32), ("lo", C.c_void_p), ("n", C.c_void_p),
                 ("ghost", C.c_int32), ("domain", C.c_int32 * 3), ("dx", C.c_double),
                 ("acc", C.c_int32), ("state", C.c_int32), ("with_sinks", C.c_int32),
-                ("channels", C.c_int32)]
+                ("channels", C.c_int32), ("margin_bits", C.c_int32)]
 
 
 # buffer channel bits (pmp_layout.channels): bit f is channel f of rho, px, py, pz, E, K
@@ -183,7 +184,8 @@ class Context:
         self.fields = [f for f in range(6) if full >> f & 1]
         self.layout = pmp_layout(w.nbox, self.lo.ctypes.data, self.n.ctypes.data, w.ghost,
                                  (C.c_int32 * 3)(*w.domain), float(w.dx), ACC[acc],
-                                 self.state_type, with_sinks, ch)
+                                 self.state_type, with_sinks, ch,
+                                 int(getattr(w, "margin_bits", MARGIN_DEFAULT)))
         h = C.c_void_p()
         _call("pmp_create", C.byref(h), C.byref(self.layout))
         self.h = h
@@ -192,7 +194,8 @@ class Context:
         self.state_elems, self.buffer_elems, self.owned_cells = se.value, be.value, oc.value
         assert self.state_elems == w.state.size, "state size does not match the layout"
         tdt = torch.float32 if self.state_type == PMP_STATE_F32 else torch.float64
-        bdt = {"f32": torch.float32, "f64": torch.float64, "fix64": torch.int64}[acc]
+        bdt = {"f32": torch.float32, "f64": torch.float64, "fix64": torch.int64,
+               "f64r": torch.float64}[acc]
         self.state = torch.from_numpy(np.ascontiguousarray(w.state)).to(device)
         assert self.state.dtype == tdt
         self.buf = torch.empty(self.buffer_elems, dtype=bdt, device=device)

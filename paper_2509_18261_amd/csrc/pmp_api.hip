@@ -124,6 +124,8 @@ struct pmp_ctx {
   DevStatus* d_status = nullptr;
   double* d_sink_scratch = nullptr;
   long long sink_cap = 0;
+  double* d_bound = nullptr;  // reproducibility mode with sinks: error bounds [buffer_elems]
+  int margin = 28;            // reproducibility mode: truncation margin M
   int num_cu = 256;
   int max_lds = 65536;  // LDS bytes one workgroup may use
   pmp_tuning tune{};
@@ -165,6 +167,7 @@ struct pmp_ctx {
     M.nfield = nfield;
     for (int f = 0; f < 6; ++f) M.slot[f] = slot[f];
     M.acc = acc;
+    M.margin = margin;
     M.state = state;
     M.buffer_elems = buffer_elems;
     M.owned_cells = owned_cells;
@@ -261,7 +264,10 @@ void release(pmp_ctx* c) {
   (void)hipFree(c->d_owned_prefix);
   (void)hipFree(c->d_shell_prefix);
   (void)hipFree(c->d_status);
-  if (!c->ws) (void)hipFree(c->d_sink_scratch);  // in a workspace: the caller's memory
+  if (!c->ws) {  // in a workspace: the caller's memory
+    (void)hipFree(c->d_sink_scratch);
+    (void)hipFree(c->d_bound);
+  }
   (void)hipFree(c->d_tile_prefix);
   (void)hipFree(c->d_tiles_axis);
   (void)hipFree(c->d_tile_geo);
@@ -481,15 +487,26 @@ bool capturing(hipStream_t s) {
 
 size_t sink_scratch_bytes(long long n);
 
+// Bytes of the error bounds the reproducibility mode keeps for the sinks'
+// global-atomic deposit (one per buffer element), 256-byte aligned.
+size_t bound_bytes(const pmp_ctx* c) {
+  return c->acc == PMP_ACC_F64R ? ((size_t)c->buffer_elems * 8 + 255) & ~(size_t)255 : 0;
+}
+
 int ensure_sink_scratch(pmp_ctx* c, long long n, hipStream_t s) {
   if (c->ws) {
-    const size_t need = sink_scratch_bytes(n);
+    const size_t sb = sink_scratch_bytes(n), need = sb + bound_bytes(c);
     if (need > c->ws_bytes)
       return fail(PMP_ERANGE, "workspace of %zu bytes is too small for %lld sinks", c->ws_bytes, n);
     c->d_sink_scratch = reinterpret_cast<double*>(c->ws);
+    c->d_bound = bound_bytes(c) ? reinterpret_cast<double*>(c->ws + sb) : nullptr;
     c->sink_cap = n;
     c->ws_sink_bytes = need;
     return PMP_OK;
+  }
+  if (bound_bytes(c) && !c->d_bound) {
+    if (capturing(s)) return fail(PMP_EINVAL, "sink scratch must be sized before graph capture");
+    PMP_HIP(dev_alloc(&c->d_bound, (size_t)c->buffer_elems));
   }
   if (n <= c->sink_cap) return PMP_OK;
   if (capturing(s))
@@ -839,7 +856,7 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
   if (has_sink) {
     PhaseTimer t(c, PMP_PHASE_SINK_DEPOSIT, s);
     PMP_HIP(launch_sink_deposit(M, from_sinks(sinks), state, buf, c->d_sink_scratch,
-                                sinks->r_k, sinks->r_gauss, to_limits(limits), s));
+                                sinks->r_k, sinks->r_gauss, to_limits(limits), c->d_bound, s));
   }
   return PMP_OK;
 }
@@ -916,7 +933,9 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   if (L->nbox < 1 || !L->lo || !L->n) return fail(PMP_EINVAL, "layout needs nbox >= 1 and boxes");
   if (L->ghost < 0 || L->ghost > 64) return fail(PMP_EINVAL, "ghost width must be 0..64");
   if (!(L->dx > 0.0)) return fail(PMP_EINVAL, "dx must be > 0");
-  if (L->acc < PMP_ACC_F32 || L->acc > PMP_ACC_FIX64) return fail(PMP_EINVAL, "bad acc type");
+  if (L->acc < PMP_ACC_F32 || L->acc > PMP_ACC_F64R) return fail(PMP_EINVAL, "bad acc type");
+  if (L->acc == PMP_ACC_F64R && (L->margin_bits < 0 || L->margin_bits > 52))
+    return fail(PMP_EINVAL, "margin_bits must be 0 .. 52");
   if (L->state != PMP_STATE_F32 && L->state != PMP_STATE_F64)
     return fail(PMP_EINVAL, "bad state type");
   for (int a = 0; a < 3; ++a)
@@ -941,6 +960,7 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   c->dx = L->dx;
   c->V = (L->dx * L->dx) * L->dx;
   c->acc = L->acc;
+  c->margin = L->margin_bits;
   c->state = L->state;
   {
     const int all = PMP_CH_RHO | PMP_CH_MOM | PMP_CH_E | PMP_CH_K;
@@ -1111,7 +1131,7 @@ int pmp_workspace_size(const pmp_ctx* c, int64_t max_cic, int64_t max_sn, double
   if (!c || !bytes) return fail(PMP_EINVAL, "NULL argument");
   if (max_cic < 0 || max_sn < 0 || max_sinks < 0 || !(max_sn_radius >= 0.0))
     return fail(PMP_EINVAL, "workspace_size: negative count or radius");
-  size_t total = max_sinks > 0 ? sink_scratch_bytes(max_sinks) : 0;
+  size_t total = max_sinks > 0 ? sink_scratch_bytes(max_sinks) + bound_bytes(c) : 0;
   if (max_cic > 0 || max_sn > 0) {
     BinSizes z;
     if (int rc = bin_sizes(c, max_cic, max_sn, max_sn_radius, z)) return rc;
@@ -1133,10 +1153,12 @@ int pmp_set_workspace(pmp_ctx* c, void* dev_ptr, size_t bytes) {
   if (!c->ws) {
     free_bin_work(c);
     (void)hipFree(c->d_sink_scratch);
+    (void)hipFree(c->d_bound);
   } else {
     c->bw = BinWork{};
   }
   c->d_sink_scratch = nullptr;
+  c->d_bound = nullptr;
   c->sink_cap = 0;
   c->ws = static_cast<char*>(dev_ptr);
   c->ws_bytes = dev_ptr ? bytes : 0;
@@ -1187,6 +1209,8 @@ int pmp_step_per_box(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, con
                      const pmp_limits* limits, const int64_t* cic_off, const int64_t* sn_off,
                      void* stream) {
   if (!c || !state || !buf) return fail(PMP_EINVAL, "per-box step: NULL argument");
+  if (c->acc == PMP_ACC_F64R)
+    return fail(PMP_EINVAL, "per-box step: the reproducibility mode runs on the binned path");
   hipStream_t s = (hipStream_t)stream;
   const bool has_cic = cic && cic->n > 0, has_sn = sn && sn->n > 0;
   if (has_cic && !cic_off) return fail(PMP_EINVAL, "per-box step: cic_off (host) is NULL");
@@ -1326,6 +1350,8 @@ int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
   if (!c || !t) return fail(PMP_EINVAL, "NULL argument");
   auto pow2_in = [](int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; };
   if (t->deposit_path < 0 || t->deposit_path > 1) return fail(PMP_EINVAL, "deposit_path 0 or 1");
+  if (c->acc == PMP_ACC_F64R && t->deposit_path != 1)
+    return fail(PMP_EINVAL, "the reproducibility mode runs on the binned path (deposit_path 1)");
   if (!pow2_in(t->tile_x, 16, 64)) return fail(PMP_EINVAL, "tile_x must be 16, 32 or 64");
   if (!pow2_in(t->tile_yz, 2, 8)) return fail(PMP_EINVAL, "tile_yz must be 2, 4 or 8");
   if (!pow2_in(t->tile_block, 64, 1024)) return fail(PMP_EINVAL, "tile_block 64..1024, power of 2");
@@ -1341,7 +1367,8 @@ int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
   if (t->count_lanes != 1 && t->count_lanes != 2 && t->count_lanes != 4 && t->count_lanes != 8)
     return fail(PMP_EINVAL, "count_lanes 1, 2, 4 or 8");
   {
-    const long long lds = tile_lds_bytes(t->tile_x, t->tile_yz, c->ghost);
+    const long long lds =
+        tile_lds_bytes(t->tile_x, t->tile_yz, c->ghost, c->acc == PMP_ACC_F64R);
     if (lds > c->max_lds)
       return fail(PMP_EINVAL, "tile %d x %d x %d needs %lld B of LDS, more than the %d B available",
                   t->tile_x, t->tile_yz, t->tile_yz, lds, c->max_lds);

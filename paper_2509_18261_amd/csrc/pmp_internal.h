@@ -65,6 +65,7 @@ struct Mesh {
   int nfield;   // buffer channels present
   int slot[6];  // buffer slot of rho, px, py, pz, E, K, or -1 when absent
   int acc;    // pmp_acc_t
+  int margin; // PMP_ACC_F64R: truncation margin M (bits)
   int state;  // pmp_state_t
   long long buffer_elems;
   long long owned_cells;
@@ -192,10 +193,11 @@ constexpr int kSlice = 4096;
 // Supernova entries per batch of the tile pass: one per lane of a wavefront.
 constexpr int kTileSnBatch = 64;
 // LDS of one tile workgroup: two accumulator channels of the widest tile
-// (tx + 2g cells along x) with rows padded by one cell, then one batch of
-// supernova entries.
-__host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz, int g) {
-  return 2ll * (tx + 2 * g + 1) * tyz * tyz * 8 + (long long)kTileSnBatch * (long long)sizeof(SnTile);
+// (tx + 2g cells along x) with rows padded by one cell (and their two error
+// bounds in the reproducibility mode), then one batch of supernova entries.
+__host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz, int g, bool bounds) {
+  return (bounds ? 4ll : 2ll) * (tx + 2 * g + 1) * tyz * tyz * 8 +
+         (long long)kTileSnBatch * (long long)sizeof(SnTile);
 }
 
 constexpr int kBinChunkCic = 1024;  // CIC particles per level-1 block
@@ -228,9 +230,10 @@ hipError_t launch_fold_apply(const Mesh& M, void* state, const void* buf, const 
                              hipStream_t s);
 hipError_t launch_sn_direct(const Mesh& M, const Particles& P, void* buf, int lanes,
                             hipStream_t s);
+// bound: the reproducibility mode's error bounds [buffer_elems] (else unused)
 hipError_t launch_sink_deposit(const Mesh& M, const Particles& P, const void* state,
                                void* buf, double* sink_scratch, double r_k, double r_gauss,
-                               const Limits& L, hipStream_t s);
+                               const Limits& L, double* bound, hipStream_t s);
 hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* state,
                               const void* buf, const double* sink_scratch, double r_k,
                               double r_gauss, const Limits& L, double* dm, double* dpx,

@@ -170,6 +170,25 @@ template <int ACC> struct AccT;
 template <> struct AccT<PMP_ACC_F32> { using T = float; };
 template <> struct AccT<PMP_ACC_F64> { using T = double; };
 template <> struct AccT<PMP_ACC_FIX64> { using T = long long; };
+template <> struct AccT<PMP_ACC_F64R> { using T = double; };
+
+// Reproducibility mode (App. A.1): machine epsilon of double, and a summed
+// buffer element v with error bound e truncated: its lowest
+// nb = 52 + M + ceil(log2(e / |v|)) mantissa bits cleared, nb clamped to
+// [0, 52].  ceil(log2 r) comes from frexp (r = m 2^k, m in [1/2, 1): k - 1
+// when m = 1/2, else k), so it is exact.  Zero and non-finite sums, and
+// elements nothing was added to, are left as they are.
+constexpr double kEps = 0x1p-52;
+__device__ __forceinline__ double truncate_bound(double v, double e, int margin) {
+  if (v == 0.0 || !isfinite(v) || !(e > 0.0)) return v;
+  int k;
+  const double m = frexp(e / fabs(v), &k);
+  int nb = 52 + margin + ((m == 0.5) ? k - 1 : k);
+  if (nb <= 0) return v;
+  nb = min(nb, 52);
+  const unsigned long long mask = ~((1ull << nb) - 1ull);
+  return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v) & mask));
+}
 
 template <class T> __device__ __forceinline__ double to_f64(T v);
 template <> __device__ __forceinline__ double to_f64<float>(float v) { return (double)v; }
@@ -556,7 +575,8 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
                                                      const S* __restrict__ state,
                                                      typename AccT<ACC>::T* __restrict__ buf,
                                                      double* __restrict__ scratch, double r_k,
-                                                     double r_gauss, double rho_tr) {
+                                                     double r_gauss, double rho_tr,
+                                                     double* __restrict__ bound) {
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
   const int lane = threadIdx.x;
   const DevBox B = M.boxes[0];
@@ -632,6 +652,11 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
         if (!quantise(kc, q1) || !quantise(kreq, q2)) { ok = false; continue; }
         gadd_fix(f5 + idx, q1);
         qreq += q2;
+      } else if constexpr (ACC == PMP_ACC_F64R) {
+        // the element's error bound (same index as the buffer) grows by
+        // eps |sum after the addition| (the atomic returns the sum before)
+        const double old = atomicAdd(f5 + idx, kc);
+        atomicAdd(bound + (f5 + idx - buf), kEps * fabs(old + kc));
       } else {
         gadd(f5 + idx, kc);
       }
@@ -669,6 +694,18 @@ __device__ __forceinline__ double limited_removal(double K, double rho, const Li
   double room = rho - L.rho_floor;
   if (room < 0.0) room = 0.0;
   return (lim < room) ? lim : room;
+}
+
+// Reproducibility mode: buffer elements with a nonzero error bound (those a
+// global-atomic deposit reached) truncated once their deposits are complete.
+__global__ __launch_bounds__(256) void k_truncate_bounds(double* __restrict__ buf,
+                                                        const double* __restrict__ bound,
+                                                        long long n, int margin) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double e = bound[i];
+    if (e > 0.0) buf[i] = truncate_bound(buf[i], e, margin);
+  }
 }
 
 // Step 4 (Sec. 2.2): each sink re-evaluates its removal over its kernel and
@@ -1754,6 +1791,13 @@ __device__ __forceinline__ void lds_add(unsigned long long* p, long long q) {
 __device__ __forceinline__ void lds_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
 template <class T> __device__ __forceinline__ T from_lds(unsigned long long v);
+// Reproducibility mode: the addition, then the bound of the element grows by
+// eps |sum after it| (the LDS atomic returns the sum before).
+__device__ __forceinline__ void lds_add_b(double* p, double* e, double v) {
+  const double old = unsafeAtomicAdd(p, v);
+  unsafeAtomicAdd(e, kEps * fabs(old + v));
+}
+
 template <> __device__ __forceinline__ long long from_lds<long long>(unsigned long long v) {
   return (long long)v;
 }
@@ -1788,6 +1832,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
                                                       void* __restrict__ state, Limits L) {
   using OutT = typename AccT<ACC>::T;
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
+  constexpr bool BOUNDS = (ACC == PMP_ACC_F64R);  // error bounds beside the sums
   using LT = typename LdsT<FIXED>::T;
   constexpr int TY = TYZ, TZ = TYZ, S = TYZ * TYZ;
   ApplyCounts cnt;
@@ -1806,10 +1851,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
   const int lcells = TXP * TY * TZ;
   LT* a0 = reinterpret_cast<LT*>(smem);
   LT* a4 = a0 + lcells;
+  // reproducibility mode: the error bounds of a0 and a4
+  double* eb0 = reinterpret_cast<double*>(a4 + lcells);
+  double* eb4 = eb0 + lcells;
   // the current batch of the tile's supernovae
   constexpr int NB = kTileSnBatch;
   static_assert(NB <= kWave && sizeof(SnTile) % 16 == 0, "one batch entry per lane of a wave");
-  SnTile* bent = reinterpret_cast<SnTile*>(a4 + lcells);
+  SnTile* bent = reinterpret_cast<SnTile*>(BOUNDS ? reinterpret_cast<LT*>(eb4 + lcells)
+                                                   : a4 + lcells);
   // work units: the chunks of split tiles first (the longest units), then
   // every other tile whole, in tile order
   const long long nheavy = min((long long)*heavy_count, slot_cap);
@@ -1836,6 +1885,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
     for (int c = threadIdx.x; c < lcells; c += blockDim.x) {
       a0[c] = (LT)0;
       a4[c] = (LT)0;
+      if constexpr (BOUNDS) {
+        eb0[c] = 0.0;
+        eb4[c] = 0.0;
+      }
     }
     int chunks = 1;
     if (base >= 0) {
@@ -1906,8 +1959,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
           auto add = [&](int i, int j, int k, auto v) {
             const int u = i - G.glo[0], vv = j - G.glo[1], w = k - G.glo[2];
             if ((unsigned)u < (unsigned)G.ext[0] && (unsigned)vv < (unsigned)G.ext[1] &&
-                (unsigned)w < (unsigned)G.ext[2])
-              lds_add(a0 + (w * TY + vv) * TXP + u, v);
+                (unsigned)w < (unsigned)G.ext[2]) {
+              const int lc = (w * TY + vv) * TXP + u;
+              if constexpr (BOUNDS) lds_add_b(a0 + lc, eb0 + lc, v);
+              else lds_add(a0 + lc, v);
+            }
           };
           if (!cic_one<FIXED>(CR.x, CR.y, CR.z, CR.w, M.V, h, add)) ovf = true;
         }
@@ -1941,6 +1997,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
           for (int u = ua; u <= ub; ++u) {
             lds_add(r0 + u, qr);
             lds_add(r4 + u, qe);
+          }
+        } else if constexpr (BOUNDS) {
+          const double cr = E.vr, ce = E.ve;
+          double* q0 = eb0 + (w * TY + v) * TXP;
+          double* q4 = eb4 + (w * TY + v) * TXP;
+          for (int u = ua; u <= ub; ++u) {
+            lds_add_b(r0 + u, q0 + u, cr);
+            lds_add_b(r4 + u, q4 + u, ce);
           }
         } else {
           const double cr = E.vr, ce = E.ve;
@@ -2005,7 +2069,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
       const int v = row & (TY - 1), w = row >> YSH;
       if (u < G.ext[0] && v < G.ext[1] && w < G.ext[2]) {
         const int lc = (w * TY + v) * TXP + u;
-        const LT r0 = a0[lc], r4 = a4[lc];
+        LT r0 = a0[lc], r4 = a4[lc];
+        if constexpr (BOUNDS) {
+          // the tile holds every contribution to its cells: the sums are complete
+          r0 = truncate_bound(r0, eb0[lc], M.margin);
+          r4 = truncate_bound(r4, eb4[lc], M.margin);
+        }
         const OutT vr = sr >= 0 ? from_lds<OutT>(r0) : (OutT)0;
         const OutT ve = se >= 0 ? from_lds<OutT>(r4) : (OutT)0;
         // owned-local coordinates: interior when g <= . < n - g on every axis
@@ -2083,6 +2152,7 @@ hipError_t launch_cic_direct(const Mesh& M, const Particles& P, void* buf, int b
       hipLaunchKernelGGL(k_cic_direct<PMP_ACC_F32>, dim3(grid), dim3(block), 0, s, M, P,
                          (float*)buf);
       break;
+    case PMP_ACC_F64R:
     case PMP_ACC_F64:
       hipLaunchKernelGGL(k_cic_direct<PMP_ACC_F64>, dim3(grid), dim3(block), 0, s, M, P,
                          (double*)buf);
@@ -2167,7 +2237,11 @@ hipError_t launch_tile_prep(const Mesh& M, const TileGrid& T, const Particles* c
   const int* coff = (cic && cic->n > 0) ? bw.cic_off : nullptr;
   const int* soff = (sn && sn->n > 0) ? bw.sn_off : nullptr;
   hipLaunchKernelGGL(k_units, dim3(grid_for(T.ntiles, 256, M.num_cu * 16)), dim3(256), 0, s, T,
-                     coff, bw.cic_cap, soff, bw.sn_cap, t.chunk_cic, t.chunk_sn, bw.heavy_base,
+                     coff, bw.cic_cap, soff, bw.sn_cap,
+                     // the reproducibility mode never splits a tile: each tile
+                     // sums all of its cells' contributions (and their bounds)
+                     M.acc == PMP_ACC_F64R ? 0x7fffffff : t.chunk_cic,
+                     M.acc == PMP_ACC_F64R ? 0x7fffffff : t.chunk_sn, bw.heavy_base,
                      bw.heavy_unit, bw.heavy_count, bw.arrive, bw.slot_cap);
   return hipGetLastError();
 }
@@ -2179,7 +2253,7 @@ hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles
   const int* coff = (cic && cic->n > 0) ? bw.cic_off : nullptr;
   const int* soff = (sn && sn->n > 0) ? bw.sn_off : nullptr;
   const int block = t.tile_block;
-  const size_t lds = (size_t)tile_lds_bytes(T.t[0], T.t[1], M.ghost);  // with the record batch
+  const size_t lds = (size_t)tile_lds_bytes(T.t[0], T.t[1], M.ghost, M.acc == PMP_ACC_F64R);
   long long grid = T.ntiles;
   if (t.tile_grid_per_cu > 0)
     grid = std::min<long long>(grid, (long long)M.num_cu * t.tile_grid_per_cu);
@@ -2197,6 +2271,7 @@ hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles
   switch (M.acc) {                                             \
     case PMP_ACC_F32: PMP_TILE(PMP_ACC_F32, float, TYZ); break; \
     case PMP_ACC_F64: PMP_TILE(PMP_ACC_F64, double, TYZ); break; \
+    case PMP_ACC_F64R: PMP_TILE(PMP_ACC_F64R, double, TYZ); break; \
     default: PMP_TILE(PMP_ACC_FIX64, long long, TYZ);          \
   }
   switch (T.t[1]) {
@@ -2231,6 +2306,7 @@ hipError_t launch_sn_direct(const Mesh& M, const Particles& P, void* buf, int la
   if (P.n <= 0) return hipSuccess;
   switch (M.acc) {
     case PMP_ACC_F32: sn_launch_lanes<PMP_ACC_F32>(M, P, buf, lanes, s); break;
+    case PMP_ACC_F64R:  // double buffer; its deposits are checked for the binned path
     case PMP_ACC_F64: sn_launch_lanes<PMP_ACC_F64>(M, P, buf, lanes, s); break;
     default: sn_launch_lanes<PMP_ACC_FIX64>(M, P, buf, lanes, s);
   }
@@ -2239,29 +2315,44 @@ hipError_t launch_sn_direct(const Mesh& M, const Particles& P, void* buf, int la
 
 template <int ACC, class S>
 static void sink_dep(const Mesh& M, const Particles& P, const void* state, void* buf,
-                     double* scratch, double r_k, double r_g, double rho_tr, hipStream_t s) {
+                     double* scratch, double r_k, double r_g, double rho_tr, double* bound,
+                     hipStream_t s) {
   const int grid = grid_for(P.n, 1, 65536);
   hipLaunchKernelGGL((k_sink_deposit<ACC, S>), dim3(grid), dim3(64), 0, s, M, P,
-                     (const S*)state, (typename AccT<ACC>::T*)buf, scratch, r_k, r_g, rho_tr);
+                     (const S*)state, (typename AccT<ACC>::T*)buf, scratch, r_k, r_g, rho_tr,
+                     bound);
 }
 
 hipError_t launch_sink_deposit(const Mesh& M, const Particles& P, const void* state,
                                void* buf, double* scratch, double r_k, double r_gauss,
-                               const Limits& L, hipStream_t s) {
+                               const Limits& L, double* bound, hipStream_t s) {
   if (P.n <= 0) return hipSuccess;
   const bool f32 = (M.state == PMP_STATE_F32);
+  const double tr = L.rho_tr;
   switch (M.acc) {
     case PMP_ACC_F32:
-      f32 ? sink_dep<PMP_ACC_F32, float>(M, P, state, buf, scratch, r_k, r_gauss, L.rho_tr, s)
-          : sink_dep<PMP_ACC_F32, double>(M, P, state, buf, scratch, r_k, r_gauss, L.rho_tr, s);
+      f32 ? sink_dep<PMP_ACC_F32, float>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr, s)
+          : sink_dep<PMP_ACC_F32, double>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr, s);
       break;
     case PMP_ACC_F64:
-      f32 ? sink_dep<PMP_ACC_F64, float>(M, P, state, buf, scratch, r_k, r_gauss, L.rho_tr, s)
-          : sink_dep<PMP_ACC_F64, double>(M, P, state, buf, scratch, r_k, r_gauss, L.rho_tr, s);
+      f32 ? sink_dep<PMP_ACC_F64, float>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr, s)
+          : sink_dep<PMP_ACC_F64, double>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr, s);
       break;
+    case PMP_ACC_F64R: {
+      // bounds of every buffer element zeroed, the removal channel summed with
+      // its bounds, then the elements it reached truncated
+      hipError_t e = launch_zero(bound, M.buffer_elems * 8, 256, s);
+      if (e != hipSuccess) return e;
+      f32 ? sink_dep<PMP_ACC_F64R, float>(M, P, state, buf, scratch, r_k, r_gauss, tr, bound, s)
+          : sink_dep<PMP_ACC_F64R, double>(M, P, state, buf, scratch, r_k, r_gauss, tr, bound, s);
+      const int grid = grid_for(M.buffer_elems, 256, M.num_cu * 16);
+      hipLaunchKernelGGL(k_truncate_bounds, dim3(grid), dim3(256), 0, s, (double*)buf,
+                         (const double*)bound, M.buffer_elems, M.margin);
+      break;
+    }
     default:
-      f32 ? sink_dep<PMP_ACC_FIX64, float>(M, P, state, buf, scratch, r_k, r_gauss, L.rho_tr, s)
-          : sink_dep<PMP_ACC_FIX64, double>(M, P, state, buf, scratch, r_k, r_gauss, L.rho_tr,
+      f32 ? sink_dep<PMP_ACC_FIX64, float>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr, s)
+          : sink_dep<PMP_ACC_FIX64, double>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr,
                                             s);
   }
   return hipGetLastError();
@@ -2290,6 +2381,7 @@ hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* sta
                                dpz, s))
   switch (M.acc) {
     case PMP_ACC_F32: PMP_SU(PMP_ACC_F32); break;
+    case PMP_ACC_F64R:  // double buffer; its deposits are checked for the binned path
     case PMP_ACC_F64: PMP_SU(PMP_ACC_F64); break;
     default: PMP_SU(PMP_ACC_FIX64);
   }
@@ -2338,6 +2430,7 @@ hipError_t launch_fold_apply(const Mesh& M, void* state, const void* buf, const 
                              hipStream_t s) {
   switch (M.acc) {
     case PMP_ACC_F32: fold_apply_launch<PMP_ACC_F32>(M, state, buf, L, s); break;
+    case PMP_ACC_F64R:  // double buffer; its deposits are checked for the binned path
     case PMP_ACC_F64: fold_apply_launch<PMP_ACC_F64>(M, state, buf, L, s); break;
     default: fold_apply_launch<PMP_ACC_FIX64>(M, state, buf, L, s);
   }
@@ -2348,6 +2441,7 @@ hipError_t launch_fold(const Mesh& M, void* buf, int block, hipStream_t s) {
   if (M.n_fold_chunks <= 0) return hipSuccess;
   switch (M.acc) {
     case PMP_ACC_F32: fold_launch<PMP_ACC_F32>(M, buf, block, s); break;
+    case PMP_ACC_F64R:  // double buffer; its deposits are checked for the binned path
     case PMP_ACC_F64: fold_launch<PMP_ACC_F64>(M, buf, block, s); break;
     default: fold_launch<PMP_ACC_FIX64>(M, buf, block, s);
   }
@@ -2372,6 +2466,7 @@ hipError_t launch_apply(const Mesh& M, void* state, const void* buf, const Limit
       f32 ? apply_launch<float, PMP_ACC_F32>(M, state, buf, L, eta, s)
           : apply_launch<double, PMP_ACC_F32>(M, state, buf, L, eta, s);
       break;
+    case PMP_ACC_F64R:
     case PMP_ACC_F64:
       f32 ? apply_launch<float, PMP_ACC_F64>(M, state, buf, L, eta, s)
           : apply_launch<double, PMP_ACC_F64>(M, state, buf, L, eta, s);

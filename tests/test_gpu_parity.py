@@ -562,3 +562,68 @@ def test_workspace_caller_owned(B, name):
     got, _ = run(ctx)
     assert np.array_equal(got, want)
     ctx.close()
+
+
+# ------------------------------------- reproducibility mode (App. A.1, error bound)
+
+def repro_bound(x, r, margin):
+    """Elementwise, the most two truncations (App. A.1) of sums of the same
+    contributions in different orders can differ by, relative to the larger
+    magnitude: one truncation interval for up to 2^8 contributions."""
+    return 2.0 ** -(52 - margin - 8)
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_reproducibility_mode_vs_oracle(B, orc, name):
+    """PMP_ACC_F64R against the oracle's mode: the deposited and the folded
+    buffers within one truncation interval of the oracle's in every element
+    and bit-identical in most (the GPU sums in another order, and the bound,
+    so the truncation width, follows the order from three contributions on);
+    the applied state within 1e-6 of the oracle's per field."""
+    w = SMALL[name]()
+    margin = 28
+    say(f"repro mode {w.name}")
+    got = run_gpu(B, w, "f64r")
+    assert got["status"]["flags"] in (0, 0x10), got["status"]
+    ref = orc.step(w, "f64r", want_eta=True)
+    for key in ("buf_deposit", "buf_fold"):
+        x, r = got[key], ref[key]
+        nz = (x != 0.0) | (r != 0.0)
+        assert np.array_equal(x[~nz], r[~nz])
+        if not nz.any():
+            continue
+        rel = np.abs(x[nz] - r[nz]) / np.maximum(np.abs(x[nz]), np.abs(r[nz]))
+        assert rel.max() <= repro_bound(x, r, margin), (key, rel.max())
+        same = float(np.mean(x[nz] == r[nz]))
+        say(f"  {key}: {nz.sum()} elements, {same:.4f} identical")
+        assert same >= 0.9, (key, same)
+    for f, (x, r) in enumerate(zip(field_views(w, got["state"], "state"),
+                                   field_views(w, ref["state"].astype(got["state"].dtype),
+                                               "state"))):
+        e = rel_err(x, r)
+        assert e <= max(1e-6, float(np.finfo(got["state"].dtype).eps)), (f, e)
+    if "sink_d" in ref:
+        for a, b in zip(got["sink_d"], ref["sink_d"]):
+            assert rel_err(a, b) <= 1e-6
+
+
+def test_reproducibility_mode_fused_step_and_errors(B, orc):
+    """The fused step in the reproducibility mode equals the separate calls'
+    result within the state tolerance, and the mode refuses the direct path
+    and the per-box launches."""
+    import torch
+    w = W.c2(nx=40)
+    ctx = B.Context(w, "f64r", channels="auto")
+    ctx.set_tuning(fuse_apply=1)
+    ctx.step()
+    torch.cuda.synchronize()
+    st = ctx.state.cpu().numpy()
+    ref = orc.step(w, "f64r")
+    for f, (x, r) in enumerate(zip(field_views(w, st, "state"),
+                                   field_views(w, ref["state"].astype(st.dtype), "state"))):
+        assert rel_err(x, r) <= 1e-6, f
+    with pytest.raises(B.PmpError):
+        ctx.set_tuning(deposit_path=0)
+    with pytest.raises(B.PmpError):
+        ctx.step_per_box()
+    ctx.close()
