@@ -112,3 +112,33 @@ def test_full_size_c4_fixed_point(B, orc):
     assert got["status"]["flags"] in (0, 0x10), got["status"]
     assert np.array_equal(got["buf_fold"], ref["buf_fold"])
     assert np.array_equal(got["state"], ref["state"].astype(np.float32))
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("acc", ["f32", "f64"])
+def test_full_size_c4_float_modes(B, orc, acc):
+    """512^3 mixed workload in FP32 (FP32 state) and FP64 (state promoted to
+    FP64) against the FP64 oracle: per-field max and RMS relative error of
+    the folded buffer and of the state, and the drift of the total mass and
+    energy (sum over owned cells) from the oracle's."""
+    w = W.c4()
+    if acc == "f64":
+        w = w.with_state(w.state.astype(np.float64))
+    say(f"full-size {w.name}: {acc} against the FP64 oracle")
+    got = run(B, w, acc)
+    assert got["status"]["flags"] in (0, 0x10), got["status"]
+    ref = orc.step(w, "f64")
+    sdt = got["state"].dtype
+    e_buf = per_field_rel(w, got["buf_fold"], ref["buf_fold"], w.nfield, w.ghost)
+    e_st = per_field_rel(w, got["state"], ref["state"].astype(sdt), 5, 0)
+    x = got["state"].astype(np.float64).reshape(5, -1)
+    r = ref["state"].astype(sdt).astype(np.float64).reshape(5, -1)
+    rms = [float(np.linalg.norm(x[f] - r[f]) / np.linalg.norm(r[f])) for f in range(5)]
+    drift = [abs(float(x[f].sum() - r[f].sum())) / abs(float(r[f].sum())) for f in (0, 4)]
+    say(f"  max rel: folded buffer {e_buf:.3e}, state {e_st:.3e}; state RMS rel "
+        f"{max(rms):.3e}; mass / energy drift {drift[0]:.3e} / {drift[1]:.3e}")
+    tol = 1e-6 if acc == "f32" else 1e-12
+    assert e_buf <= tol
+    assert e_st <= max(tol, float(np.finfo(sdt).eps))
+    assert max(rms) <= max(tol, float(np.finfo(sdt).eps))
+    assert max(drift) <= max(tol, 1e-9 if acc == "f32" else 1e-14)
