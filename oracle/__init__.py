@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: imported by the tests, by ``__graft_entry__.smoke``
 and by the benchmark's CPU-baseline leg; never by the library.  It does not
 import the HIP package either: workloads are passed in duck-typed (any object
 with ``lo, n, ghost, domain, dx, state, cic, sn, sinks, limits, r_k,
-r_gauss``), particle kinds as objects with ``fields`` and ``box_off``.
+r_gauss``; Bondi-Hoyle sinks as described in ``_sinks``), particle kinds as
+objects with ``fields`` and ``box_off``.
 
 Modes: ``"f64"`` (double buffer, sequential sums in array order),
 ``"fix64"`` (int64 buffer on the 2^-40 grid; exact and order-free) and
@@ -63,7 +64,30 @@ class _Sn(C.Structure):
 
 class _Sinks(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("a", C.c_void_p),
-                ("box_off", C.c_void_p), ("r_k", C.c_double), ("r_gauss", C.c_double)]
+                ("box_off", C.c_void_p), ("r_k", C.c_double), ("r_gauss", C.c_double),
+                ("m", C.c_void_p), ("vx", C.c_void_p), ("vy", C.c_void_p), ("vz", C.c_void_p),
+                ("rate", C.c_int32), ("G", C.c_double), ("dt", C.c_double),
+                ("gamma", C.c_double), ("lam", C.c_double)]
+
+
+RATE_FRACTION, RATE_BONDI = 0, 1
+
+
+def _sinks(w):
+    """ctypes sink description of a workload and the arrays it points at.
+    Bondi-Hoyle workloads (``sink_rate`` 1) carry the sink fields m, vx, vy,
+    vz and the scalars grav_G, dt, gamma, bhl_lambda."""
+    s4, keep = _kind(w.sinks, ["x", "y", "z", "a"], _Cic)
+    sk = _Sinks(s4.x, s4.y, s4.z, s4.m, s4.box_off, float(w.r_k), float(w.r_gauss))
+    rate = int(getattr(w, "sink_rate", RATE_FRACTION))
+    sk.rate = rate
+    if rate == RATE_BONDI:
+        arrs = [_f64(w.sinks.fields[k]) for k in ("m", "vx", "vy", "vz")]
+        keep += arrs
+        sk.m, sk.vx, sk.vy, sk.vz = (_ptr(a) for a in arrs)
+        sk.G, sk.dt = float(w.grav_G), float(w.dt)
+        sk.gamma, sk.lam = float(w.gamma), float(w.bhl_lambda)
+    return sk, keep
 
 
 class _Limits(C.Structure):
@@ -95,12 +119,12 @@ def lib():
         L.orc_buffer_elems.argtypes = [vp]
         L.orc_state_elems.restype = C.c_int64
         L.orc_state_elems.argtypes = [vp]
-        L.orc_deposit.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
-        L.orc_deposit_r.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]
+        L.orc_deposit.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_deposit_r.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp]
         L.orc_truncate_err.restype = C.c_double
         L.orc_truncate_err.argtypes = [C.c_double, C.c_double, i32]
         L.orc_fold.argtypes = [vp, i32, vp]
-        L.orc_sink_update.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_sink_update.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_apply.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
@@ -166,8 +190,9 @@ def _limits(L):
     return _Limits(float(L.rho_floor), float(L.rho_tr), float(L.cap), int(L.eint_mode))
 
 
-def deposit(w, mode, mesh=None, state64=None):
-    """Step 1. Returns (buffer, sink_w, sink_mreq)."""
+def deposit(w, mode, mesh=None, state64=None, want_racc=False):
+    """Step 1. Returns (buffer, sink_w, sink_mreq), and the sinks' Gaussian
+    widths r_acc as a fourth item with ``want_racc``."""
     m = MODES[mode]
     mesh = mesh or Mesh.of(w)
     keep = []
@@ -176,8 +201,7 @@ def deposit(w, mode, mesh=None, state64=None):
     sk = None
     nsink = 0
     if w.sinks is not None and w.sinks.n > 0:
-        s4, a = _kind(w.sinks, ["x", "y", "z", "a"], _Cic); keep += a
-        sk = _Sinks(s4.x, s4.y, s4.z, s4.m, s4.box_off, float(w.r_k), float(w.r_gauss))
+        sk, a = _sinks(w); keep += a
         nsink = w.sinks.n
     if state64 is None:
         state64 = _f64(w.state)
@@ -185,15 +209,18 @@ def deposit(w, mode, mesh=None, state64=None):
     buf = np.empty(mesh.buffer_elems, dtype=np.int64 if m == FIX64 else np.float64)
     sw = np.zeros(max(nsink, 1))
     sm = np.zeros(max(nsink, 1))
+    sr = np.zeros(max(nsink, 1))
     args = (C.byref(cic) if cic else None, C.byref(sn) if sn else None,
             C.byref(sk) if sk else None, C.byref(lim), _ptr(state64), _ptr(buf))
     if m == F64R:
         err = np.empty(mesh.buffer_elems)
         rc = lib().orc_deposit_r(C.byref(mesh.c), *args, _ptr(err), margin_of(w), _ptr(sw),
-                                 _ptr(sm))
+                                 _ptr(sm), _ptr(sr))
     else:
-        rc = lib().orc_deposit(C.byref(mesh.c), m, *args, _ptr(sw), _ptr(sm))
+        rc = lib().orc_deposit(C.byref(mesh.c), m, *args, _ptr(sw), _ptr(sm), _ptr(sr))
     _check(rc, "deposit")
+    if want_racc:
+        return buf, sw[:nsink], sm[:nsink], sr[:nsink]
     return buf, sw[:nsink], sm[:nsink]
 
 
@@ -214,19 +241,20 @@ def fold(w, mode, buf, mesh=None):
     return buf
 
 
-def sink_update(w, mode, buf, sink_w, sink_mreq, mesh=None, state64=None):
-    """Step 4. Returns (dm, dpx, dpy, dpz) per sink."""
+def sink_update(w, mode, buf, sink_w, sink_mreq, mesh=None, state64=None, sink_racc=None):
+    """Step 4. Returns (dm, dpx, dpy, dpz) per sink.  ``sink_racc`` (Step 1's
+    widths) defaults to the workload's fixed r_gauss."""
     mesh = mesh or Mesh.of(w)
     n = w.sinks.n
-    s4, keep = _kind(w.sinks, ["x", "y", "z", "a"], _Cic)
-    sk = _Sinks(s4.x, s4.y, s4.z, s4.m, s4.box_off, float(w.r_k), float(w.r_gauss))
+    sk, keep = _sinks(w)
     if state64 is None:
         state64 = _f64(w.state)
     lim = _limits(w.limits)
     outs = [np.zeros(n) for _ in range(4)]
     sw, sm = _f64(sink_w), _f64(sink_mreq)
+    sr = np.full(n, float(w.r_gauss)) if sink_racc is None else _f64(sink_racc)
     rc = lib().orc_sink_update(C.byref(mesh.c), MODES[mode], _ptr(state64), _ptr(buf),
-                               C.byref(sk), C.byref(lim), _ptr(sw), _ptr(sm),
+                               C.byref(sk), C.byref(lim), _ptr(sw), _ptr(sm), _ptr(sr),
                                *[_ptr(o) for o in outs])
     _check(rc, "sink_update")
     return tuple(outs)
@@ -250,12 +278,13 @@ def step(w, mode, want_eta=False):
     limit + apply.  Returns a dict of every intermediate."""
     mesh = Mesh.of(w)
     s64 = _f64(w.state)
-    buf, sw, sm = deposit(w, mode, mesh, s64)
+    buf, sw, sm, sr = deposit(w, mode, mesh, s64, want_racc=True)
     pre = buf.copy()
     fold(w, mode, buf, mesh)
-    out = {"buf_deposit": pre, "buf_fold": buf, "sink_w": sw, "sink_mreq": sm}
+    out = {"buf_deposit": pre, "buf_fold": buf, "sink_w": sw, "sink_mreq": sm,
+           "sink_racc": sr}
     if w.sinks is not None and w.sinks.n > 0:
-        out["sink_d"] = sink_update(w, mode, buf, sw, sm, mesh, s64)
+        out["sink_d"] = sink_update(w, mode, buf, sw, sm, mesh, s64, sr)
     st, eta, cnt = apply(w, mode, buf, mesh, s64, want_eta)
     out.update(state=st, eta=eta, counters=cnt)
     return out
@@ -267,10 +296,10 @@ def timed_step(w, mode="f64"):
     mesh = Mesh.of(w)
     s64 = _f64(w.state)
     t0 = time.perf_counter()
-    buf, sw, sm = deposit(w, mode, mesh, s64)
+    buf, sw, sm, sr = deposit(w, mode, mesh, s64, want_racc=True)
     fold(w, mode, buf, mesh)
     if w.sinks is not None and w.sinks.n > 0:
-        sink_update(w, mode, buf, sw, sm, mesh, s64)
+        sink_update(w, mode, buf, sw, sm, mesh, s64, sr)
     lim = _limits(w.limits)
     cnt = Counters()
     rc = lib().orc_apply(C.byref(mesh.c), MODES[mode], _ptr(s64), _ptr(buf), C.byref(lim),

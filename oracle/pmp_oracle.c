@@ -329,19 +329,98 @@ static int deposit_sn(const orc_mesh *M, const geom *G, int mode, const orc_sn *
   return ORC_OK;
 }
 
+#define ORC_FOUR_PI (4.0 * 3.141592653589793)
+
+/* Bondi-Hoyle request of one sink (Sec. 3.1.1, eqs. "rbh" and "mdot", and
+ * the clamp of r_acc).  Over the kernel cells (centres within r_K of the
+ * sink), each sum on the 2^-40 grid:
+ *   M     = sum rho V                      (kernel gas mass),
+ *   u     = sum p V / M - v_sink           (mass-weighted mean gas velocity
+ *                                           relative to the sink), v_inf = |u|,
+ *   c_inf = sum rho V c_s / M              (mass-weighted mean sound speed),
+ *           c_s^2 = gamma (gamma - 1) e_int / rho for an ideal gas, with
+ *           e_int = E - |p|^2 / (2 rho) taken as 0 where it is negative and
+ *           c_s = 0 where rho <= 0,
+ *   rho_inf = M / (N V)                    (mean density of the N cells).
+ * Then r_BH = G m / (v_inf^2 + c_inf^2) and the second form of eq. "mdot",
+ * mdot = 4 pi rho_inf r_BH^2 (lambda^2 c_inf^2 + v_inf^2)^(1/2).  The request
+ * mdot dt is capped at M (also when v_inf = c_inf = 0, where the rate has no
+ * finite value), and the Gaussian width is r_BH / dx clamped to
+ * [1/4, r_K / 2] cells (r_K / 2 when the rate has no finite value).  M <= 0
+ * requests nothing. */
+static int bondi_request(const orc_mesh *M, const geom *G, const orc_sinks *S, int64_t s,
+                         const int64_t lo[3], const int64_t hi[3], const double *state,
+                         double V, double *req_out, double *racc_out) {
+  const double x = S->x[s], y = S->y[s], z = S->z[s];
+  const double r2 = S->r_k * S->r_k;
+  int64_t ncell = 0, qm = 0, qx = 0, qy = 0, qz = 0, qc = 0;
+  for (int64_t k = lo[2]; k <= hi[2]; ++k)
+    for (int64_t j = lo[1]; j <= hi[1]; ++j)
+      for (int64_t i = lo[0]; i <= hi[0]; ++i) {
+        double d2 = dist2(x, y, z, i, j, k);
+        if (!(d2 <= r2)) continue;
+        int64_t iw, jw, kw;
+        int ob = owner_of(M, G, i, j, k, &iw, &jw, &kw);
+        if (ob < 0) return ORC_EINVAL;
+        double rho = state[state_index(M, G, ob, 0, iw, jw, kw)];
+        double px = state[state_index(M, G, ob, 1, iw, jw, kw)];
+        double py = state[state_index(M, G, ob, 2, iw, jw, kw)];
+        double pz = state[state_index(M, G, ob, 3, iw, jw, kw)];
+        double E = state[state_index(M, G, ob, 4, iw, jw, kw)];
+        double cs = 0.0;
+        if (rho > 0.0) {
+          double eint = E - ((px * px + py * py) + pz * pz) / (2.0 * rho);
+          if (!(eint > 0.0)) eint = 0.0;
+          cs = sqrt(((S->gamma * (S->gamma - 1.0)) * eint) / rho);
+        }
+        double m = rho * V;
+        int64_t a0, a1, a2, a3, a4;
+        if (q40(m, &a0) || q40(px * V, &a1) || q40(py * V, &a2) || q40(pz * V, &a3) ||
+            q40(m * cs, &a4))
+          return ORC_EOVERFLOW;
+        qm += a0; qx += a1; qy += a2; qz += a3; qc += a4;
+        ++ncell;
+      }
+  const double half = 0.5 * S->r_k;
+  const double Mk = (double)qm * FIX_INV;
+  *req_out = 0.0;
+  *racc_out = half;
+  if (!(Mk > 0.0)) return ORC_OK;
+  const double ux = ((double)qx * FIX_INV) / Mk - S->vx[s];
+  const double uy = ((double)qy * FIX_INV) / Mk - S->vy[s];
+  const double uz = ((double)qz * FIX_INV) / Mk - S->vz[s];
+  const double v2 = (ux * ux + uy * uy) + uz * uz;
+  const double cinf = ((double)qc * FIX_INV) / Mk;
+  const double c2 = cinf * cinf;
+  const double den = v2 + c2;
+  if (!(den > 0.0)) {
+    *req_out = Mk;
+    return ORC_OK;
+  }
+  const double rho_inf = Mk / ((double)ncell * V);
+  const double rbh = (S->G * S->m[s]) / den;
+  const double mdot =
+      ((ORC_FOUR_PI * rho_inf) * (rbh * rbh)) * sqrt((S->lambda * S->lambda) * c2 + v2);
+  const double req = mdot * S->dt;
+  *req_out = (req <= Mk) ? req : Mk;
+  const double rc = rbh / M->dx;
+  *racc_out = (rc < 0.25) ? 0.25 : ((rc > half) ? half : rc);
+  return ORC_OK;
+}
+
 /* Sink removal request (Sec. 3.1.1).  Per sink: Gaussian weights
  * w = exp(-d^2/r_acc^2) over the kernel (eq. "kernel"), normalised by their
- * sum (eq. "kernel_wgt"); the requested mass is a fixed fraction a of the gas
- * mass in the kernel (the Bondi-Hoyle rate of eq. "mdot" is replaced by this
- * request); each cell's removal is max(request * phi / V, rho - rho_Tr)
- * (eq. "accretion_function" with the Truelove term).  The kernel sums are
- * taken in 2^-40 fixed point so that they do not depend on summation order.
- * Field 5 holds the removed density K >= 0. */
+ * sum (eq. "kernel_wgt"); the requested mass is either a fixed fraction a of
+ * the gas mass in the kernel with a fixed width r_acc, or the Bondi-Hoyle
+ * request of bondi_request with its own width; each cell's removal is
+ * max(request * phi / V, rho - rho_Tr) (eq. "accretion_function" with the
+ * Truelove term).  The kernel sums are taken in 2^-40 fixed point so that
+ * they do not depend on summation order.  Field 5 holds the removed density
+ * K >= 0. */
 static int deposit_sinks(const orc_mesh *M, const geom *G, int mode, const orc_sinks *S,
                          const orc_limits *L, const double *state, void *buf, double *err,
-                         double V, double *sink_w, double *sink_mreq) {
+                         double V, double *sink_w, double *sink_mreq, double *sink_racc) {
   double r2 = S->r_k * S->r_k;
-  double g2 = S->r_gauss * S->r_gauss;
   for (int b = 0; b < M->nbox; ++b) {
     for (int64_t s = S->box_off[b]; s < S->box_off[b + 1]; ++s) {
       double x = S->x[s], y = S->y[s], z = S->z[s];
@@ -351,6 +430,13 @@ static int deposit_sinks(const orc_mesh *M, const geom *G, int mode, const orc_s
       sphere_range(x, S->r_k, &lo[0], &hi[0]);
       sphere_range(y, S->r_k, &lo[1], &hi[1]);
       sphere_range(z, S->r_k, &lo[2], &hi[2]);
+      double racc = S->r_gauss, Mbondi = 0.0;
+      if (S->rate == ORC_RATE_BONDI) {
+        int rc = bondi_request(M, G, S, s, lo, hi, state, V, &Mbondi, &racc);
+        if (rc) return rc;
+      }
+      const double g2 = racc * racc;
+      sink_racc[s] = racc;
       int64_t Wq = 0, Mq = 0;
       for (int64_t k = lo[2]; k <= hi[2]; ++k)
         for (int64_t j = lo[1]; j <= hi[1]; ++j)
@@ -371,7 +457,7 @@ static int deposit_sinks(const orc_mesh *M, const geom *G, int mode, const orc_s
       sink_mreq[s] = 0.0;
       if (Wq <= 0) continue;
       double W = (double)Wq * FIX_INV;
-      double Mreq = S->a[s] * ((double)Mq * FIX_INV);
+      double Mreq = (S->rate == ORC_RATE_BONDI) ? Mbondi : S->a[s] * ((double)Mq * FIX_INV);
       sink_w[s] = W;
       sink_mreq[s] = Mreq;
       int64_t qreq_sum = 0, first[3] = {0, 0, 0};
@@ -439,12 +525,30 @@ static double truncate_err(double v, double err, int margin) {
   return v;
 }
 
+/* Sink parameters: a kernel radius, and for the Bondi-Hoyle rate the sink
+ * masses and velocities and finite G, dt >= 0, gamma >= 1, lambda >= 0, with
+ * r_K >= 1/2 so that the clamp interval [1/4, r_K/2] is not empty. */
+static int check_sinks(const orc_sinks *S) {
+  if (!(S->r_k > 0.0)) return ORC_EINVAL;
+  if (S->rate == ORC_RATE_FRACTION) return (S->r_gauss > 0.0) ? ORC_OK : ORC_EINVAL;
+  if (S->rate != ORC_RATE_BONDI) return ORC_EINVAL;
+  if (!S->m || !S->vx || !S->vy || !S->vz) return ORC_EINVAL;
+  if (!(S->r_k >= 0.5) || !(S->G >= 0.0) || !isfinite(S->G) || !(S->dt >= 0.0) ||
+      !isfinite(S->dt) || !(S->gamma >= 1.0) || !isfinite(S->gamma) ||
+      !(S->lambda >= 0.0) || !isfinite(S->lambda))
+    return ORC_EINVAL;
+  return ORC_OK;
+}
+
 static int deposit_all(const orc_mesh *M, int mode, const orc_cic *cic, const orc_sn *sn,
                        const orc_sinks *sk, const orc_limits *L, const double *state,
-                       void *buf, double *err, double *sink_w, double *sink_mreq) {
+                       void *buf, double *err, double *sink_w, double *sink_mreq,
+                       double *sink_racc) {
   int rc = check_mesh(M);
   if (rc) return rc;
-  if (sk && (M->nfield != 6 || !state || !L || !sink_w || !sink_mreq)) return ORC_EINVAL;
+  if (sk && (M->nfield != 6 || !state || !L || !sink_w || !sink_mreq || !sink_racc))
+    return ORC_EINVAL;
+  if (sk && (rc = check_sinks(sk))) return rc;
   geom G;
   rc = geom_build(M, &G, sk != NULL);
   if (rc) return rc;
@@ -455,7 +559,7 @@ static int deposit_all(const orc_mesh *M, int mode, const orc_cic *cic, const or
   if (cic) rc = deposit_cic(M, &G, mode, cic, buf, err, V);
   if (!rc && sn) rc = deposit_sn(M, &G, mode, sn, buf, err, V);
   if (!rc && sk)
-    rc = deposit_sinks(M, &G, mode, sk, L, state, buf, err, V, sink_w, sink_mreq);
+    rc = deposit_sinks(M, &G, mode, sk, L, state, buf, err, V, sink_w, sink_mreq, sink_racc);
   if (!rc && mode == ORC_FIX64) rc = check_fix_range(buf, nb);
   geom_free(&G);
   return rc;
@@ -466,9 +570,9 @@ static int deposit_all(const orc_mesh *M, int mode, const orc_cic *cic, const or
  * each in array order. */
 int orc_deposit(const orc_mesh *M, int mode, const orc_cic *cic, const orc_sn *sn,
                 const orc_sinks *sk, const orc_limits *L, const double *state, void *buf,
-                double *sink_w, double *sink_mreq) {
+                double *sink_w, double *sink_mreq, double *sink_racc) {
   if (mode != ORC_F64 && mode != ORC_FIX64) return ORC_EINVAL;
-  return deposit_all(M, mode, cic, sn, sk, L, state, buf, NULL, sink_w, sink_mreq);
+  return deposit_all(M, mode, cic, sn, sk, L, state, buf, NULL, sink_w, sink_mreq, sink_racc);
 }
 
 /* Step 1 in the reproducibility mode of App. A.1: the double-precision sums
@@ -477,9 +581,11 @@ int orc_deposit(const orc_mesh *M, int mode, const orc_cic *cic, const orc_sn *s
  * the bounds. */
 int orc_deposit_r(const orc_mesh *M, const orc_cic *cic, const orc_sn *sn,
                   const orc_sinks *sk, const orc_limits *L, const double *state, double *buf,
-                  double *err, int margin, double *sink_w, double *sink_mreq) {
+                  double *err, int margin, double *sink_w, double *sink_mreq,
+                  double *sink_racc) {
   if (!err || margin < 0 || margin > 52) return ORC_EINVAL;
-  int rc = deposit_all(M, ORC_F64R, cic, sn, sk, L, state, buf, err, sink_w, sink_mreq);
+  int rc = deposit_all(M, ORC_F64R, cic, sn, sk, L, state, buf, err, sink_w, sink_mreq,
+                       sink_racc);
   if (rc) return rc;
   const int64_t nb = orc_buffer_elems(M);
   for (int64_t i = 0; i < nb; ++i) buf[i] = truncate_err(buf[i], err[i], margin);
@@ -553,11 +659,11 @@ static double buf_value(int mode, const void *buf, int64_t idx) {
 /* Sec. 2.2 Step 4: each sink re-evaluates its deposition function and gains
  * the limited amount, sum_c eta_c k_c V (mass) and the same times the cell
  * velocity p/rho (momentum).  eta_c = Kl_c / K_c from the folded buffer and
- * the state before Step 5. */
+ * the state before Step 5; W, the request and r_acc are Step 1's. */
 int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void *buf,
                     const orc_sinks *S, const orc_limits *L, const double *sink_w,
-                    const double *sink_mreq, double *dm, double *dpx, double *dpy,
-                    double *dpz) {
+                    const double *sink_mreq, const double *sink_racc, double *dm, double *dpx,
+                    double *dpy, double *dpz) {
   int rc = check_mesh(M);
   if (rc) return rc;
   if (M->nfield != 6) return ORC_EINVAL;
@@ -566,11 +672,12 @@ int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void
   if (rc) return rc;
   double V = (M->dx * M->dx) * M->dx;
   double r2 = S->r_k * S->r_k;
-  double g2 = S->r_gauss * S->r_gauss;
+  if (!sink_w || !sink_mreq || !sink_racc) rc = ORC_EINVAL;
   for (int b = 0; b < M->nbox && !rc; ++b) {
     for (int64_t s = S->box_off[b]; s < S->box_off[b + 1]; ++s) {
       double x = S->x[s], y = S->y[s], z = S->z[s];
       double W = sink_w[s], Mreq = sink_mreq[s];
+      double g2 = sink_racc[s] * sink_racc[s];
       double sm = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
       int64_t qm = 0, qx = 0, qy = 0, qz = 0;
       if (W > 0.0) {

@@ -69,11 +69,21 @@ typedef struct {
 
 typedef struct { const double *x, *y, *z, *m; const int64_t *box_off; } orc_cic;
 typedef struct { const double *x, *y, *z, *m, *e, *r; const int64_t *box_off; } orc_sn;
+/* Sink request rate: a fixed fraction a of the kernel gas mass with a fixed
+ * Gaussian width, or the Bondi-Hoyle-Lyttleton rate of Sec. 3.1.1 (eqs.
+ * "rbh", "mdot") with the width r_acc clamped to [dx/4, r_K/2]. */
+enum { ORC_RATE_FRACTION = 0, ORC_RATE_BONDI = 1 };
+
 typedef struct {
   const double *x, *y, *z, *a;   /* a: requested fraction of the kernel mass */
   const int64_t *box_off;
   double r_k;                    /* kernel radius (cells) */
-  double r_gauss;                /* Gaussian width r_acc (cells) */
+  double r_gauss;                /* Gaussian width r_acc (cells), fraction rate */
+  /* Bondi-Hoyle rate only */
+  const double *m, *vx, *vy, *vz;   /* sink mass and velocity */
+  int32_t rate;                     /* ORC_RATE_* */
+  double G, dt, gamma, lambda;      /* gravity constant, time step, adiabatic
+                                       index of the gas, the BHL lambda */
 } orc_sinks;
 typedef struct { double rho_floor, rho_tr, cap; int32_t eint_mode; } orc_limits;
 typedef struct {
@@ -87,17 +97,21 @@ int64_t orc_buffer_elems(const orc_mesh *M);
 int64_t orc_state_elems(const orc_mesh *M);
 double  orc_exp(double x);
 
+/* sink_w, sink_mreq, sink_racc [n sinks]: the kernel weight sum, the
+ * requested mass and the Gaussian width r_acc (cells) of each sink. */
 int orc_deposit(const orc_mesh *M, int mode, const orc_cic *cic, const orc_sn *sn,
                 const orc_sinks *sk, const orc_limits *L, const double *state, void *buf,
-                double *sink_w, double *sink_mreq);
+                double *sink_w, double *sink_mreq, double *sink_racc);
 int orc_deposit_r(const orc_mesh *M, const orc_cic *cic, const orc_sn *sn,
                   const orc_sinks *sk, const orc_limits *L, const double *state, double *buf,
-                  double *err, int margin, double *sink_w, double *sink_mreq);
+                  double *err, int margin, double *sink_w, double *sink_mreq,
+                  double *sink_racc);
 double orc_truncate_err(double v, double err, int margin);
 int orc_fold(const orc_mesh *M, int mode, void *buf);
 int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void *buf,
                     const orc_sinks *sk, const orc_limits *L, const double *sink_w,
-                    const double *sink_mreq, double *dm, double *dpx, double *dpy, double *dpz);
+                    const double *sink_mreq, const double *sink_racc, double *dm, double *dpx,
+                    double *dpy, double *dpz);
 int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
               const orc_limits *L, double *eta, orc_counters *cnt);
 

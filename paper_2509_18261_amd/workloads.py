@@ -63,8 +63,15 @@ class Workload:
     sn: Particles | None = None
     sinks: Particles | None = None
     r_k: float = 4.0         # sink kernel radius (cells)
-    r_gauss: float = 2.0     # sink Gaussian width (cells)
+    r_gauss: float = 2.0     # sink Gaussian width (cells), fraction rate
     limits: Limits = dataclasses.field(default_factory=Limits)
+    # sink request rate: 0 = fraction ``a`` of the kernel gas mass, 1 =
+    # Bondi-Hoyle (sink fields m, vx, vy, vz and the scalars below)
+    sink_rate: int = 0
+    grav_G: float = 1.0      # gravitational constant, code units
+    dt: float = 0.05         # time step
+    gamma: float = 5.0 / 3.0  # adiabatic index of the gas
+    bhl_lambda: float = math.exp(1.5) / 4.0  # isothermal value used throughout the paper
 
     @property
     def nbox(self) -> int:
@@ -269,6 +276,27 @@ def c3(seed: int = 3, nx: int = 256, n_cic: int | None = None, n_sink: int = 256
                     cic=cic, sinks=sk, r_k=4.0, r_gauss=2.0)
 
 
+def bondi_fields(rng, count, log10_m=(-1.5, 1.5), sigma_v=0.3):
+    """Sink masses log-uniform over ``log10_m`` and Gaussian velocities.
+    With the gas of ``gas_state`` (c_s about 1) and G = 1 the Bondi-Hoyle
+    radius G m / (v^2 + c^2) spans about 0.03 to 30 cells, so the three
+    branches of the r_acc clamp all occur."""
+    m = np.power(10.0, rng.uniform(log10_m[0], log10_m[1], count))
+    v = sigma_v * rng.standard_normal((3, count))
+    return {"a": np.zeros(count), "m": m, "vx": v[0], "vy": v[1], "vz": v[2]}
+
+
+def c3bh(seed: int = 3, nx: int = 256, n_cic: int | None = None, n_sink: int = 256,
+         dtype=np.float32) -> Workload:
+    """c3 with Bondi-Hoyle sinks (G = 1, dt = 0.05, gamma = 5/3)."""
+    w = c3(seed, nx, n_cic, n_sink, dtype)
+    rng = np.random.default_rng(seed + 1000)
+    pos = np.stack([w.sinks.fields[k] for k in ("x", "y", "z")], axis=1)
+    sk = _one_box(pos, bondi_fields(rng, n_sink))
+    return dataclasses.replace(w, name=f"c3bh_{nx}cube_plummer_bondi_sinks", sinks=sk,
+                               sink_rate=1)
+
+
 def c4(seed: int = 4, nx: int = 512, n_total: int | None = None,
        dtype=np.float32) -> Workload:
     """Half uniform, half in 32 Plummer clumps; CIC:SN = 10:1, SN r = 3, g = 4."""
@@ -329,4 +357,4 @@ def multibox(edges_x, edges_y, edges_z, ghost, positions_cic=None, masses=None,
     return Workload("multibox", domain, lo, n, ghost, 1.0, state, cic=cic, sn=sn)
 
 
-CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "c3bh": c3bh}

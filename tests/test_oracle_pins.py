@@ -1,6 +1,7 @@
 """Pins for the serial oracle: each check ties the oracle to something other
 than itself (the paper's worked example, closed forms, lattice counts,
 brute force over all cells and periodic images, invariants)."""
+import dataclasses
 import itertools
 import math
 import os
@@ -497,6 +498,227 @@ def test_sink_update_conservation_clustered(orc):
             p0 = w.state[(1 + ax) * 32 ** 3:(2 + ax) * 32 ** 3].astype(np.float64)
             p1 = out["state"][(1 + ax) * 32 ** 3:(2 + ax) * 32 ** 3]
             assert math.fsum(out["sink_d"][1 + ax]) == pytest.approx(math.fsum(p0 - p1), rel=1e-9, abs=1e-9)
+
+
+# ------------------------------------------------- Bondi-Hoyle sinks (S4, S5)
+
+LAMBDA_ISO = math.exp(1.5) / 4.0
+
+
+def kernel_offsets(x, r_k):
+    """Integer cells whose centres lie within r_k of x (brute force)."""
+    c = [range(int(math.floor(p - r_k)) - 1, int(math.ceil(p + r_k)) + 2) for p in x]
+    return [(i, j, k) for i in c[0] for j in c[1] for k in c[2]
+            if (i + 0.5 - x[0]) ** 2 + (j + 0.5 - x[1]) ** 2 + (k + 0.5 - x[2]) ** 2 <= r_k * r_k]
+
+
+def bondi_box(nx, state, pos, m, v, G=1.0, dt=0.05, gamma=5.0 / 3.0, r_k=4.0, ghost=4,
+              dx=1.0, limits=None):
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    v = np.asarray(v, dtype=np.float64).reshape(-1, 3)
+    fields = {"a": np.zeros(len(pos)), "m": np.asarray(m, dtype=np.float64),
+              "vx": v[:, 0], "vy": v[:, 1], "vz": v[:, 2]}
+    w = one_box(nx, ghost, state=state, sinks=(pos, fields), r_k=r_k, dx=dx, limits=limits)
+    return dataclasses.replace(w, sink_rate=1, grav_G=G, dt=dt, gamma=gamma)
+
+
+def moving_gas(nx, rho, u, e_sp):
+    """Uniform gas of density rho, velocity u and specific internal energy e_sp."""
+    n = nx ** 3
+    s = np.zeros((5, n))
+    s[0] = rho
+    for ax in range(3):
+        s[1 + ax] = rho * u[ax]
+    s[4] = rho * e_sp + 0.5 * rho * float(np.dot(u, u))
+    return s.reshape(-1)
+
+
+def test_bhl_lambda_is_the_isothermal_value():
+    # Sec. 3.1.1 quotes lambda = e^(3/2) / 4 ~ 1.120 for isothermal gas
+    lam = W.Workload("t", (1, 1, 1), None, None, 1, 1.0, None).bhl_lambda
+    assert lam == LAMBDA_ISO
+    assert abs(lam - 1.120) < 5e-4
+    assert lam * lam * 16.0 == pytest.approx(math.exp(3.0), rel=1e-15)
+
+
+@pytest.mark.parametrize("mode", ["f64", "fix64"])
+def test_bondi_limit_gas_at_rest(orc, mode):
+    """Sink at rest in uniform gas at rest: v_inf = 0, c_inf = c_s, rho_inf =
+    rho, so eq. "mdot" is the Bondi rate 4 pi lambda G^2 m^2 rho / c^3."""
+    gamma, e_sp, rho, G, dt = 5.0 / 3.0, 1.5, 2.0, 0.7, 0.05
+    c2 = gamma * (gamma - 1.0) * e_sp
+    c = math.sqrt(c2)
+    rbh = 1.5                                  # cells, inside [1/4, r_K/2]
+    m = rbh * c2 / G
+    x = (8.5, 8.5, 8.5)
+    w = bondi_box(16, moving_gas(16, rho, (0, 0, 0), e_sp), [x], [m], [(0, 0, 0)], G=G, dt=dt)
+    out = orc.step(w, mode)
+    bondi = 4.0 * math.pi * LAMBDA_ISO * G * G * m * m * rho / c ** 3 * dt
+    assert out["sink_mreq"][0] == pytest.approx(bondi, rel=1e-11)
+    assert out["sink_racc"][0] == pytest.approx(rbh, rel=1e-13)
+    offs = kernel_offsets(x, 4.0)
+    assert len(offs) == 257
+    wts = [math.exp(-((i + 0.5 - x[0]) ** 2 + (j + 0.5 - x[1]) ** 2 + (k + 0.5 - x[2]) ** 2)
+                    / rbh ** 2) for i, j, k in offs]
+    assert out["sink_w"][0] == pytest.approx(math.fsum(wts), rel=1e-11)
+    # what the buffer receives sums to the request; a cell next to the host
+    # holds its Gaussian share (no Truelove term; in fixed point the host
+    # cell also takes the rounding remainder of the request)
+    K = owned(orc, w, out["buf_deposit"], 5)
+    K = K * Q ** -1 if mode == "fix64" else K
+    assert math.fsum(K.ravel()) == pytest.approx(bondi, rel=1e-11)
+    share = bondi * math.exp(-1.0 / rbh ** 2) / math.fsum(wts)
+    assert K[9, 8, 8] == pytest.approx(share, rel=1e-11)
+
+
+@pytest.mark.parametrize("mode", ["f64", "fix64"])
+def test_bondi_moving_gas_first_form_and_clamp(orc, mode):
+    """Moving gas, moving sinks: eq. "mdot" in its first form
+    4 pi rho G^2 m^2 [(lambda^2 c^2 + v^2) / (c^2 + v^2)^4]^(1/2), and r_acc
+    on all three branches of its clamp (dx = 0.5, so cells and lengths differ)."""
+    gamma, e_sp, rho, G, dt, dx = 1.4, 0.9, 0.8, 2.0, 0.01, 0.5
+    u = np.array([0.8, -0.3, 0.5])
+    vs = np.array([0.1, 0.2, -0.1])
+    c2 = gamma * (gamma - 1.0) * e_sp
+    v2 = float(np.dot(u - vs, u - vs))
+    V = dx ** 3
+    pos = [(8.5, 8.5, 8.5), (24.5, 8.5, 8.5), (8.5, 24.5, 8.5)]
+    rbh_len = np.array([0.05, 0.7, 3.0])          # lengths: 0.1, 1.4, 6 cells
+    m = rbh_len * (c2 + v2) / G
+    w = bondi_box(32, moving_gas(32, rho, u, e_sp), pos, m, [vs] * 3, G=G, dt=dt, gamma=gamma,
+                  dx=dx)
+    out = orc.step(w, mode)
+    first = [4.0 * math.pi * rho * G * G * mm * mm *
+             math.sqrt((LAMBDA_ISO ** 2 * c2 + v2) / (c2 + v2) ** 4) * dt for mm in m]
+    # the kernel sums sit on the 2^-40 grid: terms of about 0.1 carry a
+    # relative rounding of up to 5e-12 each, and the rate goes as 1/(c^2+v^2)^2
+    np.testing.assert_allclose(out["sink_mreq"], first, rtol=1e-10)
+    np.testing.assert_allclose(out["sink_racc"], [0.25, 1.4, 2.0], rtol=1e-10)
+    # the gas loses what the sinks gain, in mass and momentum
+    n = 32 ** 3
+    lost = rho * n - math.fsum(out["state"][:n])
+    assert math.fsum(out["sink_d"][0]) == pytest.approx(lost * V, rel=1e-10)
+    # the two lighter sinks get their whole request; the heaviest one's
+    # central cells hit the removal limiter (a quarter of the cell's mass)
+    x = pos[2]
+    d2 = [(i + 0.5 - x[0]) ** 2 + (j + 0.5 - x[1]) ** 2 + (k + 0.5 - x[2]) ** 2
+          for i, j, k in kernel_offsets(x, 4.0)]
+    wts = [math.exp(-d / 4.0) for d in d2]
+    got2 = math.fsum(min(first[2] * wk / (math.fsum(wts) * V), 0.25 * rho) * V for wk in wts)
+    assert got2 < first[2]
+    gain = np.array([first[0], first[1], got2])
+    # fixed point sums 257 terms on the 2^-40 grid: at most 257 * 2^-41 apart
+    tol = dict(rtol=1e-10, atol=257 * 2.0 ** -41)
+    np.testing.assert_allclose(out["sink_d"][0], gain, **tol)
+    for ax in range(3):
+        np.testing.assert_allclose(out["sink_d"][1 + ax], gain * u[ax], **tol)
+
+
+def test_bondi_hoyle_lyttleton_limit_cold_gas(orc):
+    """Cold gas (c_s = 0) streaming past the sink: the Hoyle-Lyttleton rate
+    4 pi G^2 m^2 rho / v^3."""
+    rho, G, dt = 3.0, 1.0, 0.02
+    u = np.array([0.0, 0.6, 0.0])
+    m = 0.5 * 0.36                                   # r_BH = 0.5 cells
+    w = bondi_box(16, moving_gas(16, rho, u, 0.0), [(8.2, 7.9, 8.6)], [m], [(0, 0, 0)], G=G,
+                  dt=dt)
+    out = orc.step(w, "f64")
+    assert out["sink_mreq"][0] == pytest.approx(4 * math.pi * G * G * m * m * rho / 0.6 ** 3 * dt,
+                                               rel=1e-12)
+    assert out["sink_racc"][0] == pytest.approx(0.5, rel=1e-13)
+
+
+def test_bondi_mass_weighted_means_brute_force(orc):
+    """Log-normal gas: v_inf, c_inf mass-weighted over the kernel, rho_inf
+    the kernel's mean density, all by brute force over the kernel cells
+    (periodic images included: the sink sits next to the domain corner)."""
+    nx, gamma, G, dt = 16, 5.0 / 3.0, 1.0, 0.05
+    rng = np.random.default_rng(11)
+    st = W.gas_state(rng, nx ** 3, np.float64)
+    # a spread of temperatures, so that the mass-weighted mean sound speed
+    # differs from the root-mean-square and from the volume mean
+    e_sp = np.exp(0.7 * rng.standard_normal(nx ** 3))
+    st[4] = st[0] * e_sp + 0.5 * (st[1] ** 2 + st[2] ** 2 + st[3] ** 2) / st[0]
+    pos = [(1.3, 14.8, 0.6), (8.1, 8.9, 7.7)]
+    vs = [(0.2, -0.1, 0.05), (-0.3, 0.0, 0.1)]
+    m = [0.4, 1.7]
+    w = bondi_box(nx, st.reshape(-1), pos, m, vs, G=G, dt=dt, gamma=gamma)
+    out = orc.step(w, "f64")
+    F = st.reshape(5, nx, nx, nx)                       # [f][z][y][x]
+    for s in range(2):
+        cells = kernel_offsets(pos[s], 4.0)
+        Ms = Px = Py = Pz = Cs = 0.0
+        for i, j, k in cells:
+            r, px, py, pz, E = (F[f, k % nx, j % nx, i % nx] for f in range(5))
+            eint = max(E - (px * px + py * py + pz * pz) / (2 * r), 0.0)
+            cs = math.sqrt(gamma * (gamma - 1) * eint / r)
+            Ms += r
+            Px += px
+            Py += py
+            Pz += pz
+            Cs += r * cs
+        uinf = np.array([Px, Py, Pz]) / Ms - np.asarray(vs[s])
+        v2 = float(np.dot(uinf, uinf))
+        cinf = Cs / Ms
+        rho_inf = Ms / len(cells)
+        rbh = G * m[s] / (v2 + cinf ** 2)
+        mdot = 4 * math.pi * rho_inf * rbh ** 2 * math.sqrt(LAMBDA_ISO ** 2 * cinf ** 2 + v2)
+        assert out["sink_mreq"][s] == pytest.approx(min(mdot * dt, Ms), rel=1e-10)
+        assert out["sink_racc"][s] == pytest.approx(min(max(rbh, 0.25), 2.0), rel=1e-12)
+        racc = out["sink_racc"][s]
+        Wb = math.fsum(math.exp(-((i + 0.5 - pos[s][0]) ** 2 + (j + 0.5 - pos[s][1]) ** 2 +
+                                  (k + 0.5 - pos[s][2]) ** 2) / racc ** 2) for i, j, k in cells)
+        assert out["sink_w"][s] == pytest.approx(Wb, rel=1e-11)
+
+
+def test_bondi_request_capped_at_kernel_mass(orc):
+    rho, e_sp = 1.25, 1.0
+    x = (8.5, 8.5, 8.5)
+    # a heavy sink asks for more than its kernel holds
+    w = bondi_box(16, moving_gas(16, rho, (0, 0, 0), e_sp), [x], [1e4], [(0, 0, 0)])
+    out = orc.step(w, "f64", want_eta=True)
+    assert out["sink_mreq"][0] == pytest.approx(257 * rho, rel=1e-14)
+    assert out["sink_racc"][0] == 2.0
+    # the removal limiter (a quarter of a cell's mass) binds wherever the
+    # Gaussian share of 257 rho exceeds rho / 4
+    wts = np.array([math.exp(-((i + 0.5 - x[0]) ** 2 + (j + 0.5 - x[1]) ** 2 +
+                               (k + 0.5 - x[2]) ** 2) / 4.0) for i, j, k in kernel_offsets(x, 4.0)])
+    assert out["counters"]["bind"] == int((257 * wts / wts.sum() > 0.25).sum()) == 179
+    # cold gas at rest with the sink: v_inf = c_inf = 0 requests the kernel mass
+    w = bondi_box(16, moving_gas(16, rho, (0, 0, 0), 0.0), [x], [0.1], [(0, 0, 0)])
+    out = orc.step(w, "fix64")
+    assert out["sink_mreq"][0] == pytest.approx(257 * rho, rel=1e-14)
+    assert out["sink_racc"][0] == 2.0
+    # a massless sink asks for nothing
+    w = bondi_box(16, moving_gas(16, rho, (0, 0, 0), e_sp), [x], [0.0], [(0, 0, 0)])
+    out = orc.step(w, "f64")
+    assert out["sink_mreq"][0] == 0.0 and out["sink_racc"][0] == 0.25
+    assert not out["buf_deposit"].any()
+
+
+def test_bondi_clustered_conservation_and_modes(orc):
+    w = W.c3bh(nx=32, n_cic=200, n_sink=40, dtype=np.float64)
+    a = orc.step(w, "f64")
+    b = orc.step(w, "fix64")
+    np.testing.assert_allclose(a["sink_mreq"], b["sink_mreq"], rtol=1e-15)
+    np.testing.assert_array_equal(a["sink_racc"], b["sink_racc"])
+    np.testing.assert_allclose(a["state"], b["state"], rtol=1e-10, atol=1e-10)
+    racc = a["sink_racc"]
+    # the drawn masses put sinks on all three branches of the clamp
+    assert (racc == 0.25).any() and (racc == 2.0).any() and ((racc > 0.25) & (racc < 2)).any()
+    n = 32 ** 3
+    cic = math.fsum(w.cic.fields["m"])
+    lost = math.fsum(w.state[:n]) + cic - math.fsum(b["state"][:n])
+    assert math.fsum(b["sink_d"][0]) == pytest.approx(lost, rel=1e-10)
+
+
+def test_bondi_parameter_errors(orc):
+    x = (8.5, 8.5, 8.5)
+    st = moving_gas(16, 1.0, (0, 0, 0), 1.0)
+    for kw in ({"gamma": 0.9}, {"dt": -1.0}, {"G": float("nan")}, {"r_k": 0.4}):
+        w = bondi_box(16, st, [x], [1.0], [(0, 0, 0)], **kw)
+        with pytest.raises(RuntimeError, match="EINVAL"):
+            orc.deposit(w, "f64")
 
 
 # ------------------------------------------------------------ C1 totals (P10)
