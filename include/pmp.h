@@ -129,14 +129,39 @@ typedef struct {
   double r_max;                         /* host: largest r, for the ghost check */
 } pmp_sn;
 
-/* Sink particles (Sec. 3.1.1): each requests the fraction a of the gas mass
- * within r_k, spread with Gaussian weights exp(-d^2/r_gauss^2) (eqs. "kernel",
- * "kernel_wgt", "accretion_function").  Single-box layouts only. */
+/* Sink request rates (pmp_sinks.rate). */
+typedef enum {
+  PMP_SINK_FRACTION = 0,  /* the fraction a of the kernel gas mass, Gaussian width r_gauss */
+  PMP_SINK_BONDI = 1      /* the Bondi-Hoyle-Lyttleton rate, width r_acc per sink */
+} pmp_sink_rate_t;
+
+/* Sink particles (Sec. 3.1.1).  Each removes gas from the cells whose centres
+ * lie within r_k, spread with Gaussian weights exp(-d^2/r_acc^2) normalised
+ * over those cells (eqs. "kernel", "kernel_wgt"); a cell's removal is at least
+ * rho - rho_Tr (eq. "accretion_function").  The requested mass is
+ *   PMP_SINK_FRACTION: a times the kernel gas mass sum rho V, r_acc = r_gauss;
+ *   PMP_SINK_BONDI: mdot dt with mdot = 4 pi rho_inf r_BH^2
+ *     (lambda^2 c_inf^2 + v_inf^2)^(1/2) and r_BH = G m / (v_inf^2 + c_inf^2)
+ *     (eqs. "rbh", "mdot"), where over the kernel cells v_inf is the length of
+ *     the mass-weighted mean gas velocity minus the sink velocity, c_inf the
+ *     mass-weighted mean of c_s = (gamma (gamma-1) e_int / rho)^(1/2) (e_int =
+ *     E - |p|^2/(2 rho), negative values taken as 0) and rho_inf the mean
+ *     density (kernel mass over kernel volume); the request is capped at the
+ *     kernel gas mass (also when v_inf = c_inf = 0), and r_acc = r_BH / dx
+ *     clamped to [1/4, r_k/2] cells (r_k/2 when the rate is not finite).
+ * The kernel sums are taken on the 2^-40 grid, so they do not depend on the
+ * order of summation (PMP_FLAG_OVERFLOW past 2^22 per term).  Single-box
+ * layouts only. */
 typedef struct {
-  const double *x, *y, *z, *a;  /* device [n] */
+  const double *x, *y, *z, *a;  /* device [n]; a is read by PMP_SINK_FRACTION only */
   int64_t n;
   const int64_t *box_off;       /* device [nbox+1] */
-  double r_k, r_gauss;          /* host scalars, cells */
+  double r_k, r_gauss;          /* host scalars, cells; r_gauss: PMP_SINK_FRACTION only */
+  int32_t rate;                 /* pmp_sink_rate_t */
+  const double *m, *vx, *vy, *vz;  /* device [n], PMP_SINK_BONDI: sink mass and velocity */
+  double G, dt, gamma, lambda;  /* host, PMP_SINK_BONDI: gravitational constant, time step,
+                                   adiabatic index (>= 1), BHL lambda (e^(3/2)/4 in the
+                                   paper); G, dt, lambda >= 0 and finite, r_k >= 1/2 */
 } pmp_sinks;
 
 /* Limiter parameters (Sec. 3.1.1 removal limiter, Sec. 3.2.1 eq. "lambda"). */

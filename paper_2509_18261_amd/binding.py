@@ -56,10 +56,16 @@ class pmp_sn(C.Structure):
                 ("r_max", C.c_double)]
 
 
+PMP_SINK_FRACTION, PMP_SINK_BONDI = 0, 1
+
+
 class pmp_sinks(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("a", C.c_void_p),
                 ("n", C.c_int64), ("box_off", C.c_void_p), ("r_k", C.c_double),
-                ("r_gauss", C.c_double)]
+                ("r_gauss", C.c_double), ("rate", C.c_int32),
+                ("m", C.c_void_p), ("vx", C.c_void_p), ("vy", C.c_void_p), ("vz", C.c_void_p),
+                ("G", C.c_double), ("dt", C.c_double), ("gamma", C.c_double),
+                ("lambda_", C.c_double)]
 
 
 class pmp_limits(C.Structure):
@@ -206,11 +212,17 @@ class Context:
         self.sn = self._kind(w.sn, ["x", "y", "z", "m", "e", "r"], pmp_sn)
         if self.sn is not None:
             self.sn.r_max = float(np.max(w.sn.fields["r"]))
-        self.sinks = self._kind(w.sinks, ["x", "y", "z", "a"], pmp_sinks)
+        rate = int(getattr(w, "sink_rate", PMP_SINK_FRACTION))
+        names = ["x", "y", "z", "a"] + (["m", "vx", "vy", "vz"] if rate == PMP_SINK_BONDI else [])
+        self.sinks = self._kind(w.sinks, names, pmp_sinks)
         self.sink_out = None
         if self.sinks is not None:
             self.sinks.r_k = float(w.r_k)
             self.sinks.r_gauss = float(w.r_gauss)
+            self.sinks.rate = rate
+            if rate == PMP_SINK_BONDI:
+                self.sinks.G, self.sinks.dt = float(w.grav_G), float(w.dt)
+                self.sinks.gamma, self.sinks.lambda_ = float(w.gamma), float(w.bhl_lambda)
             self.sink_out = torch.zeros(4 * w.sinks.n, dtype=torch.float64, device=device)
 
     def _kind(self, P, names, struct):

@@ -514,7 +514,7 @@ int ensure_sink_scratch(pmp_ctx* c, long long n, hipStream_t s) {
   (void)hipFree(c->d_sink_scratch);
   c->d_sink_scratch = nullptr;
   c->sink_cap = 0;
-  PMP_HIP(dev_alloc(&c->d_sink_scratch, (size_t)(2 * n)));
+  PMP_HIP(dev_alloc(&c->d_sink_scratch, (size_t)(kSinkScratch * n)));
   c->sink_cap = n;
   return PMP_OK;
 }
@@ -634,7 +634,8 @@ size_t carve_bin(const BinSizes& z, char* base, BinWork* w) {
 }
 
 size_t sink_scratch_bytes(long long n) {
-  return ((size_t)std::max<long long>(2 * n, 1) * sizeof(double) + 255) & ~(size_t)255;
+  return ((size_t)std::max<long long>(kSinkScratch * n, 1) * sizeof(double) + 255) &
+         ~(size_t)255;
 }
 
 int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, hipStream_t s) {
@@ -741,8 +742,20 @@ int check_limits(const pmp_limits* L) {
 }
 
 int check_sinks(const pmp_ctx* c, const pmp_sinks* k) {
-  if (!k->x || !k->y || !k->z || !k->a || !k->box_off)
+  if (k->rate != PMP_SINK_FRACTION && k->rate != PMP_SINK_BONDI)
+    return fail(PMP_EINVAL, "sink rate %d is not a pmp_sink_rate_t", (int)k->rate);
+  if (!k->x || !k->y || !k->z || !k->box_off || (k->rate == PMP_SINK_FRACTION && !k->a))
     return fail(PMP_EINVAL, "sink arrays must be non-NULL");
+  if (k->rate == PMP_SINK_BONDI) {
+    if (!k->m || !k->vx || !k->vy || !k->vz)
+      return fail(PMP_EINVAL, "Bondi-Hoyle sinks need the mass and velocity arrays");
+    if (!(k->r_k >= 0.5))
+      return fail(PMP_EINVAL, "Bondi-Hoyle sinks need r_k >= 1/2 (r_acc in [1/4, r_k/2])");
+    if (!(k->G >= 0.0) || !std::isfinite(k->G) || !(k->dt >= 0.0) || !std::isfinite(k->dt) ||
+        !(k->gamma >= 1.0) || !std::isfinite(k->gamma) || !(k->lambda >= 0.0) ||
+        !std::isfinite(k->lambda))
+      return fail(PMP_EINVAL, "Bondi-Hoyle sinks need finite G, dt, lambda >= 0, gamma >= 1");
+  }
   if (c->slot[5] < 0)
     return fail(PMP_EINVAL, "sinks need a layout with the removal channel K (with_sinks = 1)");
   if (c->nbox != 1)
@@ -750,7 +763,7 @@ int check_sinks(const pmp_ctx* c, const pmp_sinks* k) {
   for (int a = 0; a < 3; ++a)
     if (c->hboxes[0].lo[a] != 0 || c->hboxes[0].n[a] != c->domain[a])
       return fail(PMP_EUNSUPPORTED, "sinks need the single box to cover the domain");
-  if (!(k->r_k >= 0.0) || !(k->r_gauss > 0.0))
+  if (!(k->r_k >= 0.0) || (k->rate == PMP_SINK_FRACTION && !(k->r_gauss > 0.0)))
     return fail(PMP_EINVAL, "sink radii must satisfy r_k >= 0, r_gauss > 0");
   if (std::floor(k->r_k + 0.5) > c->ghost)
     return fail(PMP_ERANGE, "sink kernel reach floor(r_k + 1/2) = %g exceeds ghost width %d",
@@ -775,6 +788,15 @@ Particles from_sinks(const pmp_sinks* p) {
   P.x = p->x; P.y = p->y; P.z = p->z; P.a = p->a;
   P.n = p->n; P.box_off = (const long long*)p->box_off;
   return P;
+}
+
+SinkParams sink_params(const pmp_ctx* c, const pmp_sinks* p) {
+  SinkParams K{};
+  K.m = p->m; K.vx = p->vx; K.vy = p->vy; K.vz = p->vz;
+  K.r_k = p->r_k; K.r_gauss = p->r_gauss; K.dx = c->dx;
+  K.G = p->G; K.dt = p->dt; K.gamma = p->gamma; K.lambda = p->lambda;
+  K.rate = p->rate;
+  return K;
 }
 
 // fuse_state non-null (a step without sinks): the binned path also applies
@@ -856,7 +878,7 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
   if (has_sink) {
     PhaseTimer t(c, PMP_PHASE_SINK_DEPOSIT, s);
     PMP_HIP(launch_sink_deposit(M, from_sinks(sinks), state, buf, c->d_sink_scratch,
-                                sinks->r_k, sinks->r_gauss, to_limits(limits), c->d_bound, s));
+                                sink_params(c, sinks), to_limits(limits), c->d_bound, s));
   }
   return PMP_OK;
 }
@@ -875,7 +897,7 @@ int do_sink_update(pmp_ctx* c, const void* state, const void* buf, const pmp_sin
     return fail(PMP_EINVAL, "sink update before a deposit with these sinks");
   PhaseTimer t(c, PMP_PHASE_SINK_UPDATE, s);
   PMP_HIP(launch_sink_update(c->mesh(), from_sinks(sinks), state, buf, c->d_sink_scratch,
-                             sinks->r_k, sinks->r_gauss, to_limits(limits), dm, dpx, dpy, dpz,
+                             sink_params(c, sinks), to_limits(limits), dm, dpx, dpy, dpz,
                              s));
   return PMP_OK;
 }

@@ -231,13 +231,26 @@ hipError_t launch_fold_apply(const Mesh& M, void* state, const void* buf, const 
 hipError_t launch_sn_direct(const Mesh& M, const Particles& P, void* buf, int lanes,
                             hipStream_t s);
 // bound: the reproducibility mode's error bounds [buffer_elems] (else unused)
+// Sink request parameters (pmp_sinks and the cell edge).  rate 1 is the
+// Bondi-Hoyle rate and reads the sink mass and velocity arrays.
+struct SinkParams {
+  const double *m, *vx, *vy, *vz;
+  double r_k, r_gauss, dx;
+  double G, dt, gamma, lambda;
+  int rate;
+};
+
+// The sink scratch holds kSinkScratch doubles per sink: the kernel weight
+// sum W, the requested mass and r_acc^2.
+constexpr int kSinkScratch = 3;
+
 hipError_t launch_sink_deposit(const Mesh& M, const Particles& P, const void* state,
-                               void* buf, double* sink_scratch, double r_k, double r_gauss,
+                               void* buf, double* sink_scratch, const SinkParams& K,
                                const Limits& L, double* bound, hipStream_t s);
 hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* state,
-                              const void* buf, const double* sink_scratch, double r_k,
-                              double r_gauss, const Limits& L, double* dm, double* dpx,
-                              double* dpy, double* dpz, hipStream_t s);
+                              const void* buf, const double* sink_scratch, const SinkParams& K,
+                              const Limits& L, double* dm, double* dpx, double* dpy,
+                              double* dpz, hipStream_t s);
 hipError_t launch_fold(const Mesh& M, void* buf, int block, hipStream_t s);
 hipError_t launch_apply(const Mesh& M, void* state, const void* buf, const Limits& L,
                         double* eta, int block, hipStream_t s);

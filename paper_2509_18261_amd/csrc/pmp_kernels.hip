@@ -20,6 +20,7 @@ namespace {
 constexpr double kFix = 0x1p40;         // fixed-point scale (40 fractional bits)
 constexpr double kFixInv = 0x1p-40;
 constexpr double kFixLimit = 0x1p62;    // largest accepted magnitude of a scaled value
+constexpr double kFourPi = 0x1.921fb54442d18p+3;  // 4 pi, rounded to double
 constexpr int kWave = 64;
 
 // ----------------------------------------------------------------- helpers
@@ -563,45 +564,127 @@ __device__ __forceinline__ long long state_cell(const DevBox& B, int iw, int jw,
   return ((long long)(kw - B.lo[2]) * B.n[1] + (jw - B.lo[1])) * B.n[0] + (iw - B.lo[0]);
 }
 
-// Sink removal request (Sec. 3.1.1).  One wavefront per sink.  Pass 1 sums
-// the Gaussian weights w = exp(-d^2/r_g^2) (eq. "kernel") and the kernel gas
-// mass sum rho V on the 2^-40 grid (exact, order-free); the request is the
-// fraction a of that mass.  Pass 2 adds each cell's removal
-// k = max(M_req w / (W V), rho - rho_Tr) (eqs. "kernel_wgt",
+// Bondi-Hoyle request of one sink (Sec. 3.1.1, eqs. "rbh" and "mdot", and the
+// clamp of r_acc), computed by every lane of the sink's wavefront.  Over the
+// kernel cells, on the 2^-40 grid: gas mass sum rho V, momentum sum p V and
+// sum rho V c_s with c_s^2 = gamma (gamma - 1) e_int / rho (e_int = E -
+// |p|^2/(2 rho), negative values as 0; c_s = 0 where rho <= 0), and the cell
+// count.  v_inf = |sum p V / M - v_sink|, c_inf = sum rho V c_s / M, rho_inf =
+// M / (N V); r_BH = G m / (v_inf^2 + c_inf^2), mdot = 4 pi rho_inf r_BH^2
+// (lambda^2 c_inf^2 + v_inf^2)^(1/2).  The request mdot dt is capped at M (M
+// also when v_inf = c_inf = 0), r_acc = r_BH / dx clamped to [1/4, r_k/2].
+template <class S>
+__device__ void bondi_request(const Mesh& M, const DevBox& B, const S* __restrict__ state,
+                              const SinkParams& K, long long s, double x, double y, double z,
+                              const int lo[3], int cx, int cxy, int total, bool& ok,
+                              double& req, double& racc) {
+  const double r2 = K.r_k * K.r_k;
+  long long qn = 0, qm = 0, qx = 0, qy = 0, qz = 0, qc = 0;
+  for (int t = threadIdx.x; t < total; t += kWave) {
+    const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
+    const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
+    const double d2 = dist2(x, y, z, i, j, k);
+    if (!(d2 <= r2)) continue;
+    const long long c = B.soff + state_cell<S>(B, imod(i, M.domain[0]), imod(j, M.domain[1]),
+                                               imod(k, M.domain[2]));
+    const double rho = (double)state[c];
+    const double px = (double)state[c + B.ncell];
+    const double py = (double)state[c + 2 * B.ncell];
+    const double pz = (double)state[c + 3 * B.ncell];
+    const double E = (double)state[c + 4 * B.ncell];
+    double cs = 0.0;
+    if (rho > 0.0) {
+      double eint = E - ((px * px + py * py) + pz * pz) / (2.0 * rho);
+      if (!(eint > 0.0)) eint = 0.0;
+      cs = sqrt(((K.gamma * (K.gamma - 1.0)) * eint) / rho);
+    }
+    const double m = rho * M.V;
+    long long a0, a1, a2, a3, a4;
+    if (!quantise(m, a0) || !quantise(px * M.V, a1) || !quantise(py * M.V, a2) ||
+        !quantise(pz * M.V, a3) || !quantise(m * cs, a4)) {
+      ok = false;
+      continue;
+    }
+    qm += a0; qx += a1; qy += a2; qz += a3; qc += a4;
+    ++qn;
+  }
+  qn = group_sum<kWave>(qn);
+  qm = group_sum<kWave>(qm);
+  qx = group_sum<kWave>(qx);
+  qy = group_sum<kWave>(qy);
+  qz = group_sum<kWave>(qz);
+  qc = group_sum<kWave>(qc);
+  const double half = 0.5 * K.r_k;
+  const double Mk = (double)qm * kFixInv;
+  req = 0.0;
+  racc = half;
+  if (!(Mk > 0.0)) return;
+  const double ux = ((double)qx * kFixInv) / Mk - K.vx[s];
+  const double uy = ((double)qy * kFixInv) / Mk - K.vy[s];
+  const double uz = ((double)qz * kFixInv) / Mk - K.vz[s];
+  const double v2 = (ux * ux + uy * uy) + uz * uz;
+  const double cinf = ((double)qc * kFixInv) / Mk;
+  const double c2 = cinf * cinf;
+  const double den = v2 + c2;
+  if (!(den > 0.0)) {
+    req = Mk;
+    return;
+  }
+  const double rho_inf = Mk / ((double)qn * M.V);
+  const double rbh = (K.G * K.m[s]) / den;
+  const double mdot = ((kFourPi * rho_inf) * (rbh * rbh)) * sqrt((K.lambda * K.lambda) * c2 + v2);
+  const double want = mdot * K.dt;
+  req = (want <= Mk) ? want : Mk;
+  const double rc = rbh / K.dx;
+  racc = (rc < 0.25) ? 0.25 : ((rc > half) ? half : rc);
+}
+
+// Sink removal request (Sec. 3.1.1).  One wavefront per sink.  The request is
+// the fraction a of the kernel gas mass with the fixed width r_gauss, or the
+// Bondi-Hoyle request of bondi_request with its own width r_acc.  Pass 1 sums
+// the Gaussian weights w = exp(-d^2/r_acc^2) (eq. "kernel") and the kernel gas
+// mass sum rho V on the 2^-40 grid (exact, order-free).  Pass 2 adds each
+// cell's removal k = max(M_req w / (W V), rho - rho_Tr) (eqs. "kernel_wgt",
 // "accretion_function") to field 5.  Single box covering the domain: state
 // reads wrap periodically, deposits go to the ghost-zoned buffer unwrapped.
+// scratch receives W, M_req and r_acc^2 per sink.
 template <int ACC, class S>
 __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
                                                      const S* __restrict__ state,
                                                      typename AccT<ACC>::T* __restrict__ buf,
-                                                     double* __restrict__ scratch, double r_k,
-                                                     double r_gauss, double rho_tr,
-                                                     double* __restrict__ bound) {
+                                                     double* __restrict__ scratch, SinkParams K,
+                                                     double rho_tr, double* __restrict__ bound) {
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
   const int lane = threadIdx.x;
   const DevBox B = M.boxes[0];
   const int g = M.ghost;
-  const double r2 = r_k * r_k, g2 = r_gauss * r_gauss;
+  const double r2 = K.r_k * K.r_k;
   for (long long s = blockIdx.x; s < P.n; s += gridDim.x) {
-    const double x = P.x[s], y = P.y[s], z = P.z[s], a = P.a[s];
+    const double x = P.x[s], y = P.y[s], z = P.z[s];
+    double* out = scratch + kSinkScratch * s;
     int h[3];
     if (!host_cell(B, x, y, z, h)) {
       if (lane == 0) {
         raise_flag(M.status, PMP_FLAG_OUTSIDE);
-        scratch[2 * s] = 0.0;
-        scratch[2 * s + 1] = 0.0;
+        out[0] = 0.0;
+        out[1] = 0.0;
+        out[2] = 0.0;
       }
       continue;
     }
     int lo[3], hi[3];
-    sphere_range(x, r_k, lo[0], hi[0]);
-    sphere_range(y, r_k, lo[1], hi[1]);
-    sphere_range(z, r_k, lo[2], hi[2]);
+    sphere_range(x, K.r_k, lo[0], hi[0]);
+    sphere_range(y, K.r_k, lo[1], hi[1]);
+    sphere_range(z, K.r_k, lo[2], hi[2]);
     const int cx = hi[0] - lo[0] + 1, cy = hi[1] - lo[1] + 1;
     const int cxy = cx * cy;
     const int total = cxy * (hi[2] - lo[2] + 1);
-    long long wq = 0, mq = 0;
     bool ok = true;
+    double racc = K.r_gauss, Mbondi = 0.0;
+    if (K.rate == PMP_SINK_BONDI)
+      bondi_request<S>(M, B, state, K, s, x, y, z, lo, cx, cxy, total, ok, Mbondi, racc);
+    const double g2 = racc * racc;
+    long long wq = 0, mq = 0;
     for (int t = lane; t < total; t += kWave) {
       const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
       const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
@@ -620,12 +703,13 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
     mq = group_sum<kWave>(mq);
     if (!ok) raise_flag(M.status, PMP_FLAG_OVERFLOW);
     if (wq <= 0) {
-      if (lane == 0) { scratch[2 * s] = 0.0; scratch[2 * s + 1] = 0.0; }
+      if (lane == 0) { out[0] = 0.0; out[1] = 0.0; out[2] = g2; }
       continue;
     }
     const double W = (double)wq * kFixInv;
-    const double Mreq = a * ((double)mq * kFixInv);
-    if (lane == 0) { scratch[2 * s] = W; scratch[2 * s + 1] = Mreq; }
+    const double Mreq =
+        (K.rate == PMP_SINK_BONDI) ? Mbondi : P.a[s] * ((double)mq * kFixInv);
+    if (lane == 0) { out[0] = W; out[1] = Mreq; out[2] = g2; }
     using T = typename AccT<ACC>::T;
     T* f5 = buf + B.boff + M.slot[5] * B.npad;
     long long qreq = 0;
@@ -710,24 +794,25 @@ __global__ __launch_bounds__(256) void k_truncate_bounds(double* __restrict__ bu
 
 // Step 4 (Sec. 2.2): each sink re-evaluates its removal over its kernel and
 // gains sum eta k V (mass) and sum eta k V p/rho (momentum), eta = Kl/K from
-// the folded buffer and the state before Step 5.  One wavefront per sink;
-// fixed point sums each term on the 2^-40 grid.
+// the folded buffer and the state before Step 5; W, the request and r_acc^2
+// come from Step 1's scratch.  One wavefront per sink; fixed point sums each
+// term on the 2^-40 grid.
 template <int ACC, class S>
 __global__ __launch_bounds__(64) void k_sink_update(Mesh M, Particles P,
                                                     const S* __restrict__ state,
                                                     const typename AccT<ACC>::T* __restrict__ buf,
                                                     const double* __restrict__ scratch,
-                                                    double r_k, double r_gauss, Limits L,
-                                                    double* dm, double* dpx, double* dpy,
-                                                    double* dpz) {
+                                                    double r_k, Limits L, double* dm,
+                                                    double* dpx, double* dpy, double* dpz) {
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
   const int lane = threadIdx.x;
   const DevBox B = M.boxes[0];
   const int g = M.ghost;
-  const double r2 = r_k * r_k, g2 = r_gauss * r_gauss;
+  const double r2 = r_k * r_k;
   for (long long s = blockIdx.x; s < P.n; s += gridDim.x) {
     const double x = P.x[s], y = P.y[s], z = P.z[s];
-    const double W = scratch[2 * s], Mreq = scratch[2 * s + 1];
+    const double* in = scratch + kSinkScratch * s;
+    const double W = in[0], Mreq = in[1], g2 = in[2];
     double sm = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     long long qm = 0, qx = 0, qy = 0, qz = 0;
     bool ok = true;
@@ -2315,70 +2400,67 @@ hipError_t launch_sn_direct(const Mesh& M, const Particles& P, void* buf, int la
 
 template <int ACC, class S>
 static void sink_dep(const Mesh& M, const Particles& P, const void* state, void* buf,
-                     double* scratch, double r_k, double r_g, double rho_tr, double* bound,
+                     double* scratch, const SinkParams& K, double rho_tr, double* bound,
                      hipStream_t s) {
   const int grid = grid_for(P.n, 1, 65536);
   hipLaunchKernelGGL((k_sink_deposit<ACC, S>), dim3(grid), dim3(64), 0, s, M, P,
-                     (const S*)state, (typename AccT<ACC>::T*)buf, scratch, r_k, r_g, rho_tr,
-                     bound);
+                     (const S*)state, (typename AccT<ACC>::T*)buf, scratch, K, rho_tr, bound);
 }
 
 hipError_t launch_sink_deposit(const Mesh& M, const Particles& P, const void* state,
-                               void* buf, double* scratch, double r_k, double r_gauss,
+                               void* buf, double* scratch, const SinkParams& K,
                                const Limits& L, double* bound, hipStream_t s) {
   if (P.n <= 0) return hipSuccess;
   const bool f32 = (M.state == PMP_STATE_F32);
   const double tr = L.rho_tr;
   switch (M.acc) {
     case PMP_ACC_F32:
-      f32 ? sink_dep<PMP_ACC_F32, float>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr, s)
-          : sink_dep<PMP_ACC_F32, double>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr, s);
+      f32 ? sink_dep<PMP_ACC_F32, float>(M, P, state, buf, scratch, K, tr, nullptr, s)
+          : sink_dep<PMP_ACC_F32, double>(M, P, state, buf, scratch, K, tr, nullptr, s);
       break;
     case PMP_ACC_F64:
-      f32 ? sink_dep<PMP_ACC_F64, float>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr, s)
-          : sink_dep<PMP_ACC_F64, double>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr, s);
+      f32 ? sink_dep<PMP_ACC_F64, float>(M, P, state, buf, scratch, K, tr, nullptr, s)
+          : sink_dep<PMP_ACC_F64, double>(M, P, state, buf, scratch, K, tr, nullptr, s);
       break;
     case PMP_ACC_F64R: {
       // bounds of every buffer element zeroed, the removal channel summed with
       // its bounds, then the elements it reached truncated
       hipError_t e = launch_zero(bound, M.buffer_elems * 8, 256, s);
       if (e != hipSuccess) return e;
-      f32 ? sink_dep<PMP_ACC_F64R, float>(M, P, state, buf, scratch, r_k, r_gauss, tr, bound, s)
-          : sink_dep<PMP_ACC_F64R, double>(M, P, state, buf, scratch, r_k, r_gauss, tr, bound, s);
+      f32 ? sink_dep<PMP_ACC_F64R, float>(M, P, state, buf, scratch, K, tr, bound, s)
+          : sink_dep<PMP_ACC_F64R, double>(M, P, state, buf, scratch, K, tr, bound, s);
       const int grid = grid_for(M.buffer_elems, 256, M.num_cu * 16);
       hipLaunchKernelGGL(k_truncate_bounds, dim3(grid), dim3(256), 0, s, (double*)buf,
                          (const double*)bound, M.buffer_elems, M.margin);
       break;
     }
     default:
-      f32 ? sink_dep<PMP_ACC_FIX64, float>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr, s)
-          : sink_dep<PMP_ACC_FIX64, double>(M, P, state, buf, scratch, r_k, r_gauss, tr, nullptr,
-                                            s);
+      f32 ? sink_dep<PMP_ACC_FIX64, float>(M, P, state, buf, scratch, K, tr, nullptr, s)
+          : sink_dep<PMP_ACC_FIX64, double>(M, P, state, buf, scratch, K, tr, nullptr, s);
   }
   return hipGetLastError();
 }
 
 template <int ACC, class S>
 static void sink_upd(const Mesh& M, const Particles& P, const void* state, const void* buf,
-                     const double* scratch, double r_k, double r_g, const Limits& L,
-                     double* dm, double* dpx, double* dpy, double* dpz, hipStream_t s) {
+                     const double* scratch, double r_k, const Limits& L, double* dm,
+                     double* dpx, double* dpy, double* dpz, hipStream_t s) {
   const int grid = grid_for(P.n, 1, 65536);
   hipLaunchKernelGGL((k_sink_update<ACC, S>), dim3(grid), dim3(64), 0, s, M, P,
-                     (const S*)state, (const typename AccT<ACC>::T*)buf, scratch, r_k, r_g, L,
-                     dm, dpx, dpy, dpz);
+                     (const S*)state, (const typename AccT<ACC>::T*)buf, scratch, r_k, L, dm,
+                     dpx, dpy, dpz);
 }
 
 hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* state,
-                              const void* buf, const double* scratch, double r_k,
-                              double r_gauss, const Limits& L, double* dm, double* dpx,
-                              double* dpy, double* dpz, hipStream_t s) {
+                              const void* buf, const double* scratch, const SinkParams& K,
+                              const Limits& L, double* dm, double* dpx, double* dpy,
+                              double* dpz, hipStream_t s) {
   if (P.n <= 0) return hipSuccess;
   const bool f32 = (M.state == PMP_STATE_F32);
-#define PMP_SU(ACC)                                                                         \
-  (f32 ? sink_upd<ACC, float>(M, P, state, buf, scratch, r_k, r_gauss, L, dm, dpx, dpy, dpz, \
-                              s)                                                            \
-       : sink_upd<ACC, double>(M, P, state, buf, scratch, r_k, r_gauss, L, dm, dpx, dpy,     \
-                               dpz, s))
+  const double r_k = K.r_k;
+#define PMP_SU(ACC)                                                                            \
+  (f32 ? sink_upd<ACC, float>(M, P, state, buf, scratch, r_k, L, dm, dpx, dpy, dpz, s)         \
+       : sink_upd<ACC, double>(M, P, state, buf, scratch, r_k, L, dm, dpx, dpy, dpz, s))
   switch (M.acc) {
     case PMP_ACC_F32: PMP_SU(PMP_ACC_F32); break;
     case PMP_ACC_F64R:  // double buffer; its deposits are checked for the binned path

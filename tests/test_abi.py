@@ -40,7 +40,8 @@ STRUCTS = {
                    "channels"],
     "pmp_cic": ["x", "y", "z", "m", "n", "box_off"],
     "pmp_sn": ["x", "y", "z", "m", "e", "r", "n", "box_off", "r_max"],
-    "pmp_sinks": ["x", "y", "z", "a", "n", "box_off", "r_k", "r_gauss"],
+    "pmp_sinks": ["x", "y", "z", "a", "n", "box_off", "r_k", "r_gauss", "rate", "m", "vx",
+                  "vy", "vz", "G", "dt", "gamma", "lambda"],
     "pmp_limits": ["rho_floor", "rho_tr", "cap", "eint_mode"],
     "pmp_status": ["flags", "reserved", "touched", "bind", "lam", "fall"],
     "pmp_tuning": ["deposit_path", "tile_x", "tile_yz", "tile_block", "block", "grid_per_cu",
@@ -69,7 +70,8 @@ def test_struct_layout_matches_header(tmp_path):
         if f == "size":
             assert C_sizeof(cls) == int(v), line
         else:
-            assert getattr(cls, f).offset == int(v), line
+            # "lambda" is a Python keyword: the binding names that field "lambda_"
+            assert getattr(cls, "lambda_" if f == "lambda" else f).offset == int(v), line
 
 
 def C_sizeof(cls):

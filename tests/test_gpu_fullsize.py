@@ -67,7 +67,7 @@ def per_field_rel(w, x, r, nf, g):
     return worst
 
 
-CASES = {"c2": W.c2, "c3": W.c3, "c5": W.c5}
+CASES = {"c2": W.c2, "c3": W.c3, "c3bh": W.c3bh, "c5": W.c5}
 
 
 @pytest.mark.timeout(600)

@@ -132,6 +132,7 @@ SMALL = {
     "c1": lambda: W.c1(),
     "c2_40": lambda: W.c2(nx=40),
     "c3_40": lambda: W.c3(nx=40, n_sink=48),
+    "c3bh_40": lambda: W.c3bh(nx=40, n_sink=48),
     "c4_48": lambda: W.c4(nx=48),
     "c5_4": lambda: W.c5(nb=4),
 }
@@ -255,6 +256,24 @@ def test_limiter_binds_on_clustered_sinks(B, orc):
     st = got["status"]
     assert st["touched"] > 0
     assert st["bind"] / st["touched"] >= 0.10, st
+
+
+def test_bondi_sink_parameter_errors(B):
+    """Bondi-Hoyle sink parameters are checked on the host before any launch."""
+    w = W.c3bh(nx=16, n_cic=10, n_sink=4, dtype=np.float64)
+    for kw, msg in (({"gamma": 0.5}, "gamma"), ({"dt": float("inf")}, "dt"),
+                    ({"r_k": 0.4}, "r_k")):
+        bad = dataclasses.replace(w, **kw)
+        say(f"case bondi error {kw}")
+        ctx = B.Context(bad, "f64")
+        with pytest.raises(B.PmpError):
+            ctx.deposit()
+        ctx.close()
+    ctx = B.Context(w, "f64")
+    ctx.sinks.rate = 7
+    with pytest.raises(B.PmpError):
+        ctx.deposit()
+    ctx.close()
 
 
 def test_outside_particle_flagged(B):
