@@ -126,6 +126,7 @@ def lib():
         L.orc_fold.argtypes = [vp, i32, vp]
         L.orc_sink_update.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_apply.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.orc_sink_create.argtypes = [vp, i32, vp, vp, C.c_double, C.c_double, C.c_int64, vp, vp]
         _lib = L
     return _lib
 
@@ -271,6 +272,21 @@ def apply(w, mode, buf, mesh=None, state64=None, want_eta=False):
                          _ptr(eta), C.byref(cnt))
     _check(rc, "apply")
     return st, eta, cnt.as_dict()
+
+
+def sink_create(w, mode, state64, buf, r_k, rho_tr, max_new, mesh=None):
+    """Sink creation (Sec. 3.1.2) on a single periodic box, after a step.
+    ``state64`` (float64, packed) is updated in place; ``buf`` is the folded
+    buffer in the mode's type, or None.  Returns (count, out[7][max_new])."""
+    mesh = mesh or Mesh.of(w)
+    out = np.zeros((7, max(int(max_new), 1)))
+    cnt = C.c_int64(0)
+    b = None if buf is None else np.ascontiguousarray(buf)
+    rc = lib().orc_sink_create(C.byref(mesh.c), MODES[mode], _ptr(state64), _ptr(b),
+                               float(r_k), float(rho_tr), int(max_new), _ptr(out),
+                               C.byref(cnt))
+    _check(rc, "sink_create")
+    return int(cnt.value), out[:, :int(max_new)]
 
 
 def step(w, mode, want_eta=False):

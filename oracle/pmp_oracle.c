@@ -829,3 +829,93 @@ int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
   geom_free(&G);
   return rc;
 }
+
+/* ------------------------------------------------------ sink creation */
+
+/* Sink creation (Sec. 3.1.2).  A cell c of the single periodic box becomes a
+ * sink when
+ *   (1) rho_c > rho_Tr (the Truelove density of eq. "truelove"),
+ *   (2) c is the densest cell among those whose centres lie within r_K of
+ *       its centre (the cell itself included; equal densities are ranked by
+ *       the linear cell index, the lower index counting as denser), and
+ *   (3) the folded removal channel K is zero at c, that is no sink kernel
+ *       reaches c (the paper's test for another sink within r_K).
+ * Every test reads the state as it was before any creation, so the result
+ * does not depend on the order of the cells.  A new sink sits at the cell
+ * centre with mass (rho_c - rho_Tr) V and momentum (mass) p_c / rho_c; the
+ * cell keeps its velocity and specific energy: rho -> rho_Tr,
+ * p -> (p / rho) rho_Tr, E -> (E / rho) rho_Tr.  The sinks are listed in
+ * increasing linear cell index (x fastest) in out [7][max_new] (x, y, z, m,
+ * px, py, pz); *count receives the number of qualifying cells, and when it
+ * exceeds max_new nothing is created.  buf may be NULL, or a buffer without
+ * the K channel (nfield 5): then no cell is excluded by (3). */
+int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf, double r_k,
+                    double rho_tr, int64_t max_new, double *out, int64_t *count) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (M->nbox != 1 || !state || !count || max_new < 0 || (max_new > 0 && !out)) return ORC_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (M->lo[a] != 0 || M->n[a] != M->domain[a]) return ORC_EINVAL;
+  if (!(r_k >= 0.0) || !(r_k <= 16.0) || rho_tr != rho_tr) return ORC_EINVAL;
+  if (mode != ORC_F64 && mode != ORC_FIX64) return ORC_EINVAL;
+  geom G;
+  rc = geom_build(M, &G, 0);
+  if (rc) return rc;
+  const int64_t nx = M->n[0], ny = M->n[1], nz = M->n[2];
+  const int64_t ncell = nx * ny * nz;
+  const double V = (M->dx * M->dx) * M->dx;
+  const int64_t R = (int64_t)floor(r_k);
+  const double r2 = r_k * r_k;
+  int64_t *made = (int64_t *)malloc((size_t)(ncell > 0 ? ncell : 1) * sizeof(int64_t));
+  if (!made) {
+    geom_free(&G);
+    return ORC_ENOMEM;
+  }
+  int64_t n_new = 0;
+  for (int64_t k = 0; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        const int64_t c = (k * ny + j) * nx + i;
+        const double rho = state[state_index(M, &G, 0, 0, i, j, k)];
+        if (!(rho > rho_tr)) continue;
+        if (buf && M->nfield == 6 && buf_value(mode, buf, buf_index(M, &G, 0, 5, i, j, k)) != 0.0)
+          continue;
+        int densest = 1;
+        for (int64_t dk = -R; dk <= R && densest; ++dk)
+          for (int64_t dj = -R; dj <= R && densest; ++dj)
+            for (int64_t di = -R; di <= R && densest; ++di) {
+              if (!((double)(di * di + dj * dj + dk * dk) <= r2)) continue;
+              const int64_t ii = imod(i + di, nx), jj = imod(j + dj, ny), kk = imod(k + dk, nz);
+              const int64_t o = (kk * ny + jj) * nx + ii;
+              if (o == c) continue;
+              const double ro = state[state_index(M, &G, 0, 0, ii, jj, kk)];
+              if (ro > rho || (ro == rho && o < c)) densest = 0;
+            }
+        if (densest) made[n_new++] = c;
+      }
+  *count = n_new;
+  if (n_new <= max_new) {
+    for (int64_t s = 0; s < n_new; ++s) {
+      const int64_t c = made[s];
+      const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+      const int64_t i0 = state_index(M, &G, 0, 0, i, j, k);
+      const int64_t step = box_cells(M, 0);
+      const double rho = state[i0];
+      const double m = (rho - rho_tr) * V;
+      out[0 * max_new + s] = (double)i + 0.5;
+      out[1 * max_new + s] = (double)j + 0.5;
+      out[2 * max_new + s] = (double)k + 0.5;
+      out[3 * max_new + s] = m;
+      for (int a = 0; a < 3; ++a) {
+        const double v = state[i0 + (1 + a) * step] / rho;
+        out[(4 + a) * max_new + s] = m * v;
+        state[i0 + (1 + a) * step] = v * rho_tr;
+      }
+      state[i0 + 4 * step] = (state[i0 + 4 * step] / rho) * rho_tr;
+      state[i0] = rho_tr;
+    }
+  }
+  free(made);
+  geom_free(&G);
+  return ORC_OK;
+}

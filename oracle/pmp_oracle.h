@@ -16,7 +16,8 @@
  *   Step 3  cell-wise limiter (sink removal limiter of Sec. 3.1.1 and the
  *           momentum/energy limiter of Sec. 3.2.1, eq. "lambda"),
  *   Step 4  sink update with the limited changes,
- *   Step 5  mesh update.
+ *   Step 5  mesh update,
+ * and, after the step, sink creation (Sec. 3.1.2).
  * Every loop runs in the order of the definitions; no blocking, fusion or
  * reordering.  Floating-point expressions are written in one fixed order and
  * the file is compiled without contraction (-ffp-contract=off).
@@ -114,6 +115,10 @@ int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void
                     double *dpy, double *dpz);
 int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
               const orc_limits *L, double *eta, orc_counters *cnt);
+/* Sink creation of Sec. 3.1.2 on a single periodic box (state updated in
+ * place; out [7][max_new]: x, y, z, m, px, py, pz in cell index order). */
+int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf, double r_k,
+                    double rho_tr, int64_t max_new, double *out, int64_t *count);
 
 #ifdef __cplusplus
 }

@@ -721,6 +721,129 @@ def test_bondi_parameter_errors(orc):
             orc.deposit(w, "f64")
 
 
+# ------------------------------------------------------ sink creation (S11)
+
+def peaks_state(nx, peaks, u=(0.2, -0.1, 0.3), e_sp=1.3, rho0=1.0):
+    """Uniform moving gas with single-cell density peaks {(i, j, k): rho}."""
+    rho = np.full((nx, nx, nx), rho0)
+    for (i, j, k), r in peaks.items():
+        rho[k, j, i] = r
+    st = np.zeros((5, nx, nx, nx))
+    st[0] = rho
+    for a in range(3):
+        st[1 + a] = rho * u[a]
+    st[4] = rho * (e_sp + 0.5 * float(np.dot(u, u)))
+    return st.reshape(-1)
+
+
+def created_cells(out, count):
+    return [tuple(int(v) for v in np.floor(out[:3, s])) for s in range(count)]
+
+
+def test_sink_create_single_peak(orc):
+    u, e_sp, dx = np.array([0.2, -0.1, 0.3]), 1.3, 0.5
+    V = dx ** 3
+    st = peaks_state(16, {(5, 6, 7): 10.0}, u, e_sp)
+    w = one_box(16, 3, state=st, dx=dx)
+    s64 = st.copy()
+    n, out = orc.sink_create(w, "f64", s64, None, 3.0, 4.0, 8)
+    assert n == 1
+    assert tuple(out[:3, 0]) == (5.5, 6.5, 7.5)
+    assert out[3, 0] == pytest.approx(6.0 * V, rel=1e-15)
+    np.testing.assert_allclose(out[4:, 0], 6.0 * V * u, rtol=1e-15)
+    after = s64.reshape(5, 16, 16, 16)[:, 7, 6, 5]
+    assert after[0] == 4.0
+    np.testing.assert_allclose(after[1:4] / after[0], u, rtol=1e-15)
+    assert after[4] / after[0] == pytest.approx(e_sp + 0.5 * float(np.dot(u, u)), rel=1e-15)
+    # mass and momentum move from the cell to the sink
+    assert math.fsum(s64[:16 ** 3]) * V + out[3, 0] == pytest.approx(math.fsum(st[:16 ** 3]) * V,
+                                                                     rel=1e-15)
+    # every other cell is untouched
+    changed = np.flatnonzero(s64 != st)
+    assert set(changed % 16 ** 3) == {(7 * 16 + 6) * 16 + 5}
+
+
+@pytest.mark.parametrize("mode", ["f64", "fix64"])
+def test_sink_create_excluded_where_sinks_remove(orc, mode):
+    st = peaks_state(16, {(5, 6, 7): 10.0})
+    w = one_box(16, 3, state=st, sinks=([[1.5, 1.5, 1.5]], {"a": [0.1]}), r_k=3.0)
+    mesh = orc.Mesh.of(w)
+    buf = np.zeros(mesh.buffer_elems, dtype=np.int64 if mode == "fix64" else np.float64)
+    view = mesh.box_buffer(buf, 0)
+    view[5, 7 + 3, 6 + 3, 5 + 3] = 1            # removal reaches the peak cell
+    s64 = st.copy()
+    n, _ = orc.sink_create(w, mode, s64, buf, 3.0, 4.0, 8)
+    assert n == 0 and np.array_equal(s64, st)
+    view[5, 7 + 3, 6 + 3, 5 + 3] = 0
+    view[5, 7 + 3, 6 + 3, 6 + 3] = 1            # a neighbour only: creation goes ahead
+    n, _ = orc.sink_create(w, mode, s64, buf, 3.0, 4.0, 8)
+    assert n == 1
+
+
+def test_sink_create_local_maximum_in_a_sphere(orc):
+    # two peaks 2 cells apart (inside r_K = 3): only the denser
+    n, out = orc.sink_create(one_box(16, 3), "f64",
+                             peaks_state(16, {(5, 6, 7): 10.0, (7, 6, 7): 12.0}), None, 3.0, 4.0, 8)
+    assert n == 1 and created_cells(out, n) == [(7, 6, 7)]
+    # offset (2, 2, 2): inside the cube [-3, 3]^3 but |d| = sqrt(12) > 3, so both
+    n, out = orc.sink_create(one_box(16, 3), "f64",
+                             peaks_state(16, {(5, 6, 7): 10.0, (7, 8, 9): 12.0}), None, 3.0, 4.0, 8)
+    assert n == 2 and created_cells(out, n) == [(5, 6, 7), (7, 8, 9)]
+    # offset (3, 0, 0): on the sphere, |d| = r_K, so only the denser
+    n, out = orc.sink_create(one_box(16, 3), "f64",
+                             peaks_state(16, {(5, 6, 7): 10.0, (8, 6, 7): 12.0}), None, 3.0, 4.0, 8)
+    assert n == 1
+    # through the periodic boundary: (0, 0, 0) and (15, 0, 0) are neighbours
+    n, out = orc.sink_create(one_box(16, 3), "f64",
+                             peaks_state(16, {(0, 0, 0): 10.0, (15, 0, 0): 9.0}), None, 3.0, 4.0, 8)
+    assert n == 1 and created_cells(out, n) == [(0, 0, 0)]
+    # a plateau of two equal cells: one sink, in the cell of lower index
+    n, out = orc.sink_create(one_box(16, 3), "f64",
+                             peaks_state(16, {(5, 6, 7): 10.0, (6, 6, 7): 10.0}), None, 3.0, 4.0, 8)
+    assert n == 1 and created_cells(out, n) == [(5, 6, 7)]
+    # below the Truelove density: nothing
+    n, _ = orc.sink_create(one_box(16, 3), "f64", peaks_state(16, {(5, 6, 7): 3.9}), None, 3.0,
+                           4.0, 8)
+    assert n == 0
+    # r_K = 0: every cell above rho_Tr
+    st = peaks_state(16, {(5, 6, 7): 10.0, (6, 6, 7): 10.0, (1, 1, 1): 5.0})
+    n, out = orc.sink_create(one_box(16, 3), "f64", st, None, 0.0, 4.0, 8)
+    assert n == 3 and created_cells(out, n) == [(1, 1, 1), (5, 6, 7), (6, 6, 7)]
+
+
+def test_sink_create_brute_force_lognormal(orc):
+    """A log-normal density field: the qualifying cells found by shifting the
+    whole field over every offset of the r_K sphere."""
+    nx, r_k, rho_tr = 12, 2.5, math.exp(1.2)
+    rng = np.random.default_rng(21)
+    st = W.gas_state(rng, nx ** 3, np.float64)
+    rho = st[0].reshape(nx, nx, nx)
+    idx = np.arange(nx ** 3).reshape(nx, nx, nx)
+    best = rho > rho_tr
+    R = int(r_k)
+    for dk, dj, di in itertools.product(range(-R, R + 1), repeat=3):
+        if (di, dj, dk) == (0, 0, 0) or di * di + dj * dj + dk * dk > r_k * r_k:
+            continue
+        ro = np.roll(rho, (-dk, -dj, -di), axis=(0, 1, 2))
+        io = np.roll(idx, (-dk, -dj, -di), axis=(0, 1, 2))
+        best &= (ro < rho) | ((ro == rho) & (io > idx))
+    expect = np.flatnonzero(best.ravel())
+    assert 5 < expect.size < 60
+    w = one_box(nx, 2, state=st.reshape(-1))
+    s64 = st.reshape(-1).copy()
+    n, out = orc.sink_create(w, "f64", s64, None, r_k, rho_tr, 100)
+    assert n == expect.size
+    k, j, i = np.unravel_index(expect, (nx, nx, nx))
+    np.testing.assert_array_equal(out[0, :n], i + 0.5)
+    np.testing.assert_array_equal(out[1, :n], j + 0.5)
+    np.testing.assert_array_equal(out[2, :n], k + 0.5)
+    np.testing.assert_allclose(out[3, :n], rho.ravel()[expect] - rho_tr, rtol=1e-14)
+    # too small an output list: the count is reported, nothing is created
+    s2 = st.reshape(-1).copy()
+    n2, _ = orc.sink_create(w, "f64", s2, None, r_k, rho_tr, expect.size - 1)
+    assert n2 == expect.size and np.array_equal(s2, st.reshape(-1))
+
+
 # ------------------------------------------------------------ C1 totals (P10)
 
 @pytest.mark.parametrize("mode", ["f64", "fix64"])
