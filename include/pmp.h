@@ -288,6 +288,30 @@ int pmp_sink_update(pmp_ctx *ctx, const void *state, const void *buf, const pmp_
 int pmp_apply(pmp_ctx *ctx, void *state, const void *buf, const pmp_limits *limits,
               double *eta, void *stream);
 
+/* Sink creation (Sec. 3.1.2), after a step: on a single box covering the
+ * periodic domain, a cell becomes a sink when rho > rho_tr (the Truelove
+ * density of eq. "truelove"), it is the densest cell among those whose
+ * centres lie within r_k (cells) of its centre (equal densities ranked by
+ * the linear cell index, the lower index counting as denser), and the folded
+ * removal channel K of buf is zero there (no existing sink's kernel reaches
+ * it; buf may be NULL, or have no K channel: no cell is excluded).  All tests
+ * read the state before any creation, so the result does not depend on the
+ * order of the cells.  Each new sink sits at its cell centre (cell units)
+ * with mass (rho - rho_tr) V and momentum mass * p / rho; the cell keeps its
+ * velocity and specific energy (rho -> rho_tr, p -> (p / rho) rho_tr,
+ * E -> (E / rho) rho_tr), updated in place in the device state.
+ *   out   device float64 [7][max_new]: x, y, z, m, px, py, pz of the new
+ *         sinks in increasing linear cell index (x fastest);
+ *   work  device int64 [2 max_new + 1], caller-owned scratch; work[0]
+ *         receives the number of qualifying cells.  When it exceeds max_new,
+ *         nothing is created and state and out are left alone (call again
+ *         with a larger list).
+ * max_new in [0, 65536], r_k in [0, 16].  Allocates nothing.  Errors:
+ * PMP_EINVAL (arguments), PMP_EUNSUPPORTED (not one box covering the
+ * domain). */
+int pmp_sink_create(pmp_ctx *ctx, void *state, const void *buf, double r_k, double rho_tr,
+                    int64_t max_new, double *out, int64_t *work, void *stream);
+
 /* One whole step: deposit, fold, sink update (if sinks), apply.  sink_out
  * (device) is four float64 arrays [4][sinks->n] (dm, dpx, dpy, dpz) or NULL
  * without sinks. */

@@ -112,6 +112,7 @@ SIGNATURES = [
     ("pmp_sink_update", _I, [_VP, _VP, _VP, C.POINTER(pmp_sinks), C.POINTER(pmp_limits),
                              _VP, _VP, _VP, _VP, _VP]),
     ("pmp_apply", _I, [_VP, _VP, _VP, C.POINTER(pmp_limits), _VP, _VP]),
+    ("pmp_sink_create", _I, [_VP, _VP, _VP, C.c_double, C.c_double, C.c_int64, _VP, _VP, _VP]),
     ("pmp_step", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
                       C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP, _VP]),
     ("pmp_step_per_box", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
@@ -289,6 +290,17 @@ class Context:
     def apply(self, eta=None, stream=None):
         _call("pmp_apply", self.h, _ptr(self.state), _ptr(self.buf), C.byref(self.lim),
               _ptr(eta), _stream(stream))
+
+    def sink_create(self, r_k, rho_tr, max_new, buf=True, stream=None):
+        """Sink creation after a step (state updated in place).  Returns the
+        device arrays (out [7][max_new], work [2 max_new + 1]); work[0] is the
+        number of qualifying cells.  ``buf=False`` passes no buffer."""
+        import torch
+        out = torch.zeros(7 * max(int(max_new), 1), dtype=torch.float64, device=self.device)
+        work = torch.zeros(2 * int(max_new) + 1, dtype=torch.int64, device=self.device)
+        _call("pmp_sink_create", self.h, _ptr(self.state), _ptr(self.buf) if buf else None,
+              float(r_k), float(rho_tr), int(max_new), _ptr(out), _ptr(work), _stream(stream))
+        return out, work
 
     def step(self, stream=None):
         _call("pmp_step", self.h, _ptr(self.state), _ptr(self.buf), self._r(self.cic),

@@ -1221,6 +1221,27 @@ int pmp_apply(pmp_ctx* c, void* state, const void* buf, const pmp_limits* limits
   return do_apply(c, state, buf, limits, eta, (hipStream_t)stream);
 }
 
+int pmp_sink_create(pmp_ctx* c, void* state, const void* buf, double r_k, double rho_tr,
+                    int64_t max_new, double* out, int64_t* work, void* stream) {
+  if (!c) return fail(PMP_EINVAL, "NULL context");
+  if (!state || !work) return fail(PMP_EINVAL, "state and work must be non-NULL");
+  if (max_new < 0 || max_new > kCreateMax)
+    return fail(PMP_EINVAL, "max_new must lie in [0, %lld]", (long long)kCreateMax);
+  if (max_new > 0 && !out) return fail(PMP_EINVAL, "out is NULL");
+  if (!(r_k >= 0.0) || !(r_k <= 16.0)) return fail(PMP_EINVAL, "r_k must lie in [0, 16]");
+  if (std::isnan(rho_tr)) return fail(PMP_EINVAL, "rho_tr is NaN");
+  if (c->nbox != 1) return fail(PMP_EUNSUPPORTED, "sink creation needs a single-box layout");
+  for (int a = 0; a < 3; ++a)
+    if (c->hboxes[0].lo[a] != 0 || c->hboxes[0].n[a] != c->domain[a])
+      return fail(PMP_EUNSUPPORTED, "sink creation needs the single box to cover the domain");
+  const Mesh M = c->mesh();
+  PMP_HIP(launch_sink_create(M, state, buf, r_k, rho_tr, (long long)max_new, out,
+                             (long long*)work,
+                             (long long)c->domain[0] * c->domain[1] * c->domain[2],
+                             (hipStream_t)stream));
+  return PMP_OK;
+}
+
 int pmp_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn* sn,
              const pmp_sinks* sinks, const pmp_limits* limits, double* sink_out, void* stream) {
   if (!c) return fail(PMP_EINVAL, "NULL context");

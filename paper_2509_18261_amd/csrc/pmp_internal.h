@@ -251,6 +251,13 @@ hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* sta
                               const void* buf, const double* sink_scratch, const SinkParams& K,
                               const Limits& L, double* dm, double* dpx, double* dpy,
                               double* dpz, hipStream_t s);
+// Largest output list of one sink creation call (the index sort is
+// quadratic in the number of new sinks).
+constexpr long long kCreateMax = 65536;
+
+hipError_t launch_sink_create(const Mesh& M, void* state, const void* buf, double r_k,
+                              double rho_tr, long long max_new, double* out, long long* work,
+                              long long ncell, hipStream_t s);
 hipError_t launch_fold(const Mesh& M, void* buf, int block, hipStream_t s);
 hipError_t launch_apply(const Mesh& M, void* state, const void* buf, const Limits& L,
                         double* eta, int block, hipStream_t s);

@@ -2471,6 +2471,135 @@ hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* sta
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ sink creation
+
+// Sink creation (Sec. 3.1.2), pass 1, one thread per owned cell of the single
+// periodic box.  A cell qualifies when rho > rho_Tr, the folded removal
+// channel K is zero there (no sink kernel reaches it), and it is the densest
+// cell within r_K of its centre (equal densities ranked by the linear cell
+// index, the lower index counting as denser).  Only the state before any
+// creation is read.  Qualifying cells are counted in work[0] and, up to
+// max_new of them, appended in arrival order to work[1 ..].
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_create_find(Mesh M, const S* __restrict__ state,
+                                                     const T* __restrict__ buf, double r_k,
+                                                     double rho_tr, long long max_new,
+                                                     long long* __restrict__ work) {
+  const DevBox B = M.boxes[0];
+  const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
+  const int g = M.ghost;
+  const int R = (int)floor(r_k);
+  const double r2 = r_k * r_k;
+  const T* K = (buf != nullptr && M.slot[5] >= 0) ? buf + B.boff + M.slot[5] * B.npad : nullptr;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < B.ncell;
+       c += (long long)gridDim.x * blockDim.x) {
+    const double rho = (double)state[B.soff + c];
+    if (!(rho > rho_tr)) continue;
+    const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((long long)nx * ny));
+    if (K != nullptr &&
+        to_f64(K[((long long)(k + g) * B.p[1] + (j + g)) * B.p[0] + (i + g)]) != 0.0)
+      continue;
+    bool densest = true;
+    for (int dk = -R; dk <= R && densest; ++dk)
+      for (int dj = -R; dj <= R && densest; ++dj)
+        for (int di = -R; di <= R && densest; ++di) {
+          if (!((double)(di * di + dj * dj + dk * dk) <= r2)) continue;
+          const long long o = ((long long)imod(k + dk, nz) * ny + imod(j + dj, ny)) * nx +
+                              imod(i + di, nx);
+          if (o == c) continue;
+          const double ro = (double)state[B.soff + o];
+          if (ro > rho || (ro == rho && o < c)) densest = false;
+        }
+    if (!densest) continue;
+    const long long slot = (long long)atomicAdd((unsigned long long*)work, 1ull);
+    if (slot < max_new) work[1 + slot] = c;
+  }
+}
+
+// Pass 2: the appended cell indices (distinct) put in increasing order by
+// rank, rank = how many others are smaller, into work[1 + max_new ..].  Does
+// nothing when more cells qualified than max_new.
+__global__ __launch_bounds__(256) void k_create_rank(long long max_new,
+                                                     long long* __restrict__ work) {
+  const long long n = work[0];
+  if (n > max_new) return;
+  const long long* keys = work + 1;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long key = keys[t];
+    long long rank = 0;
+    for (long long u = 0; u < n; ++u) rank += (keys[u] < key);
+    work[1 + max_new + rank] = key;
+  }
+}
+
+// Pass 3: one thread per new sink, in cell index order.  The sink sits at
+// the cell centre with mass (rho - rho_Tr) V and momentum mass * p / rho; the
+// cell keeps its velocity and specific energy (rho -> rho_Tr, p ->
+// (p / rho) rho_Tr, E -> (E / rho) rho_Tr).  out is [7][max_new]: x, y, z,
+// m, px, py, pz.
+template <class S>
+__global__ __launch_bounds__(256) void k_create_apply(Mesh M, S* __restrict__ state,
+                                                      double rho_tr, long long max_new,
+                                                      const long long* __restrict__ work,
+                                                      double* __restrict__ out) {
+  const long long n = work[0];
+  if (n > max_new) return;
+  const DevBox B = M.boxes[0];
+  const int nx = B.n[0], ny = B.n[1];
+  const long long* sorted = work + 1 + max_new;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long c = sorted[t];
+    S* cell = state + B.soff + c;
+    const double rho = (double)cell[0];
+    const double m = (rho - rho_tr) * M.V;
+    out[t] = (double)(c % nx) + 0.5;
+    out[max_new + t] = (double)((c / nx) % ny) + 0.5;
+    out[2 * max_new + t] = (double)(c / ((long long)nx * ny)) + 0.5;
+    out[3 * max_new + t] = m;
+    for (int a = 1; a <= 3; ++a) {
+      const double v = (double)cell[a * B.ncell] / rho;
+      out[(3 + a) * max_new + t] = m * v;
+      cell[a * B.ncell] = (S)(v * rho_tr);
+    }
+    cell[4 * B.ncell] = (S)(((double)cell[4 * B.ncell] / rho) * rho_tr);
+    cell[0] = (S)rho_tr;
+  }
+}
+
+template <class T, class S>
+static void create_launch(const Mesh& M, void* state, const void* buf, double r_k,
+                          double rho_tr, long long max_new, double* out, long long* work,
+                          long long ncell, hipStream_t s) {
+  const int grid = grid_for(ncell, 256, M.num_cu * 32);
+  hipLaunchKernelGGL((k_create_find<T, S>), dim3(grid), dim3(256), 0, s, M, (const S*)state,
+                     (const T*)buf, r_k, rho_tr, max_new, work);
+  const int g2 = grid_for(max_new, 256, 1024);
+  hipLaunchKernelGGL(k_create_rank, dim3(g2), dim3(256), 0, s, max_new, work);
+  hipLaunchKernelGGL((k_create_apply<S>), dim3(g2), dim3(256), 0, s, M, (S*)state, rho_tr,
+                     max_new, (const long long*)work, out);
+}
+
+hipError_t launch_sink_create(const Mesh& M, void* state, const void* buf, double r_k,
+                              double rho_tr, long long max_new, double* out, long long* work,
+                              long long ncell, hipStream_t s) {
+  hipError_t e = launch_zero(work, 8, 256, s);
+  if (e != hipSuccess) return e;
+  const bool f32 = (M.state == PMP_STATE_F32);
+#define PMP_CR(T)                                                                              \
+  (f32 ? create_launch<T, float>(M, state, buf, r_k, rho_tr, max_new, out, work, ncell, s)     \
+       : create_launch<T, double>(M, state, buf, r_k, rho_tr, max_new, out, work, ncell, s))
+  switch (M.acc) {
+    case PMP_ACC_F32: PMP_CR(float); break;
+    case PMP_ACC_F64R:
+    case PMP_ACC_F64: PMP_CR(double); break;
+    default: PMP_CR(long long);
+  }
+#undef PMP_CR
+  return hipGetLastError();
+}
+
 template <int ACC>
 static void fold_launch(const Mesh& M, void* buf, int block, hipStream_t s) {
   using T = typename AccT<ACC>::T;

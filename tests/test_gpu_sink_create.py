@@ -1,0 +1,128 @@
+"""Sink creation (Sec. 3.1.2) on the GPU against the serial oracle, through
+the C-ABI.  The test outcome of every cell is a comparison of values read
+from the state, and the new sinks' values are computed in double from the
+same inputs on both sides, so the created list (in cell index order), the
+count and the updated state are compared bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_18261_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_18261_amd import binding
+    return binding
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_create(B, w, acc, buf_np, r_k, rho_tr, max_new, state=None):
+    import torch
+    ctx = B.Context(w, acc, channels="all")
+    if state is not None:
+        ctx.state.copy_(torch.from_numpy(np.ascontiguousarray(state)))
+    if buf_np is not None:
+        ctx.buf.copy_(torch.from_numpy(np.ascontiguousarray(buf_np).astype(
+            {"f32": np.float32, "f64": np.float64, "fix64": np.int64}[acc])))
+    out, work = ctx.sink_create(r_k, rho_tr, max_new, buf=buf_np is not None)
+    torch.cuda.synchronize()
+    res = (int(work[0].item()), out.cpu().numpy().reshape(7, -1)[:, :max_new],
+           ctx.state.cpu().numpy())
+    ctx.close()
+    return res
+
+
+def oracle_create(orc, w, mode, state, buf, r_k, rho_tr, max_new):
+    s64 = np.asarray(state, dtype=np.float64).copy()
+    n, out = orc.sink_create(w, mode, s64, buf, r_k, rho_tr, max_new)
+    return n, out, s64
+
+
+def compare(got, ref, max_new, dtype):
+    n, out, st = got
+    rn, rout, rst = ref
+    assert n == rn, (n, rn)
+    if n <= max_new:
+        assert np.array_equal(out[:, :n], rout[:, :n]), "sink records differ"
+    assert np.array_equal(st, rst.astype(dtype)), "state differs"
+
+
+@pytest.mark.parametrize("state_dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
+def test_create_standalone_vs_oracle(B, orc, acc, state_dtype):
+    """Log-normal gas and the removal channel of 48 clustered sinks (the
+    oracle's deposit), handed to both sides."""
+    w = W.c3(nx=40, n_cic=0, n_sink=48, dtype=state_dtype)
+    w = W.Workload(w.name, w.domain, w.lo, w.n, w.ghost, w.dx, w.state, sinks=w.sinks,
+                   r_k=w.r_k, r_gauss=w.r_gauss)
+    mode = "fix64" if acc == "fix64" else "f64"
+    buf, _, _ = orc.deposit(w, mode)
+    orc.fold(w, mode, buf)
+    rho_tr, r_k, max_new = float(np.exp(2.0)), 2.0, 4096
+    say(f"case create standalone acc={acc} state={np.dtype(state_dtype).name}")
+    ref_buf = buf.astype(np.float32).astype(np.float64) if acc == "f32" else buf
+    ref = oracle_create(orc, w, mode, w.state, ref_buf, r_k, rho_tr, max_new)
+    assert 20 < ref[0] < max_new
+    got = gpu_create(B, w, acc, buf, r_k, rho_tr, max_new)
+    compare(got, ref, max_new, state_dtype)
+    # without the buffer no cell is excluded: at least as many sinks
+    ref2 = oracle_create(orc, w, mode, w.state, None, r_k, rho_tr, max_new)
+    got2 = gpu_create(B, w, acc, None, r_k, rho_tr, max_new)
+    compare(got2, ref2, max_new, state_dtype)
+    assert ref2[0] > ref[0]
+
+
+def test_create_after_fixed_point_step(B, orc):
+    """A whole fixed-point step (the GPU state equals the oracle's rounded to
+    FP32 bit for bit), then creation on each side's own result."""
+    import torch
+    w = W.c3(nx=40, n_sink=48)
+    ref = orc.step(w, "fix64")
+    rho_tr, r_k, max_new = 6.0, 3.0, 2048
+    ref_c = oracle_create(orc, w, "fix64", ref["state"].astype(np.float32), ref["buf_fold"],
+                          r_k, rho_tr, max_new)
+    say("case create after fix64 step c3_40")
+    ctx = B.Context(w, "fix64", channels="all")
+    ctx.deposit()
+    ctx.ghost_fold()
+    ctx.sink_update()
+    ctx.apply()
+    out, work = ctx.sink_create(r_k, rho_tr, max_new)
+    torch.cuda.synchronize()
+    got = (int(work[0].item()), out.cpu().numpy().reshape(7, -1), ctx.state.cpu().numpy())
+    ctx.close()
+    assert ref_c[0] > 5
+    compare(got, ref_c, max_new, np.float32)
+
+
+def test_create_capacity_and_errors(B, orc):
+    w = W.c3(nx=24, n_cic=0, n_sink=8, dtype=np.float64)
+    w = W.Workload(w.name, w.domain, w.lo, w.n, w.ghost, w.dx, w.state, sinks=w.sinks)
+    rho_tr, r_k = float(np.exp(1.5)), 1.5
+    n_all, _, _ = oracle_create(orc, w, "f64", w.state, None, r_k, rho_tr, 4096)
+    assert n_all > 3
+    say("case create capacity")
+    n, out, st = gpu_create(B, w, "f64", None, r_k, rho_tr, n_all - 1)
+    assert n == n_all and not out.any() and np.array_equal(st, w.state)
+    ctx = B.Context(w, "f64")
+    for args in ((17.0, rho_tr, 8), (r_k, float("nan"), 8), (r_k, rho_tr, 65537),
+                 (-1.0, rho_tr, 8)):
+        with pytest.raises(B.PmpError):
+            ctx.sink_create(*args)
+    ctx.close()
+    mb = W.multibox([8, 8], [8], [8], ghost=1, positions_cic=[[1.5, 1.5, 1.5]], seed=1)
+    ctx = B.Context(mb, "f64")
+    with pytest.raises(B.PmpError):
+        ctx.sink_create(1.0, 2.0, 8)
+    ctx.close()
