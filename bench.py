@@ -9,7 +9,7 @@ width 4.  Inputs are resident in HBM before timing starts.  Prints one JSON
 line.
 
   python bench.py [--steps K] [--warmup W] [--acc f32|f64|fix64]
-                  [--workload c2|c3|c4|c5] [--no-cpu] [--no-modes]
+                  [--workload c2|c3|c3bh|c4|c5] [--no-cpu] [--no-modes]
 """
 from __future__ import annotations
 
@@ -187,6 +187,43 @@ def run_graph(ctx, steps, warmup, spread=None):
         per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
         spread.update({"median": statistics.median(per), "min": min(per), "max": max(per)})
     return ms
+
+
+def sink_create_rate(B, w, acc, channels, reps=10):
+    """Sink creation (Sec. 3.1.2) after one step: rho_Tr = e^3 (about one cell
+    in 700 of the log-normal gas lies above it), r_K the workload's.  Each
+    timed call starts from the same post-step state (restored outside the
+    timed region).  Algorithmic bytes: rho and K of every cell."""
+    import math
+
+    import numpy as np
+    import torch
+    ctx = B.Context(w, acc, channels=channels)
+    ctx.step()
+    torch.cuda.synchronize()
+    base = ctx.state.clone()
+    rho_tr, max_new = math.exp(3.0), 65536
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    total, n = 0.0, 0
+    for r in range(reps + 1):
+        ctx.state.copy_(base)
+        torch.cuda.synchronize()
+        t0.record()
+        out, work = ctx.sink_create(w.r_k, rho_tr, max_new)
+        t1.record()
+        torch.cuda.synchronize()
+        if r:  # the first call warms up
+            total += t0.elapsed_time(t1)
+        n = int(work[0].item())
+    ctx.close()
+    ms = total / reps
+    bs = np.dtype(w.state.dtype).itemsize
+    ba = {"f32": 4, "f64": 8, "fix64": 8}[acc]
+    nbytes = w.owned_cells * (bs + ba)
+    return {"ms_per_call": round(ms, 4), "new_sinks": n, "rho_tr": rho_tr, "r_k": w.r_k,
+            "algo_GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "kernels": "k_create_find+k_create_rank+k_create_apply"}
 
 
 def stream_copy_gbps(B, nbytes=1 << 30, reps=10):
@@ -445,6 +482,9 @@ def main():
     }
     if batched is not None:
         out["batched"] = batched
+    if w.sinks is not None and w.sinks.n:
+        out["sink_create"] = sink_create_rate(B, w, args.acc, args.channels)
+        log(f"sink creation: {out['sink_create']}")
     if not args.no_calib:
         gbps, cms = stream_copy_gbps(B)
         out["stream_copy_GBps"] = round(gbps, 1)

@@ -142,3 +142,32 @@ def test_full_size_c4_float_modes(B, orc, acc):
     assert e_st <= max(tol, float(np.finfo(sdt).eps))
     assert max(rms) <= max(tol, float(np.finfo(sdt).eps))
     assert max(drift) <= max(tol, 1e-9 if acc == "f32" else 1e-14)
+
+
+@pytest.mark.timeout(600)
+def test_full_size_sink_create_after_step(B, orc):
+    """256^3 with 256 sinks: a fixed-point step, then sink creation (r_K = 4,
+    rho_Tr = e^3) on each side's own result, compared bit for bit."""
+    import torch
+    w = W.c3()
+    say(f"full-size {w.name}: sink creation after a fixed-point step")
+    ref = orc.step(w, "fix64")
+    rho_tr, max_new = float(np.exp(3.0)), 65536
+    s64 = ref["state"].astype(np.float32).astype(np.float64)
+    n_ref, out_ref = orc.sink_create(w, "fix64", s64, ref["buf_fold"], w.r_k, rho_tr, max_new)
+    assert 100 < n_ref < max_new
+    ctx = B.Context(w, "fix64", channels="all")
+    ctx.deposit()
+    ctx.ghost_fold()
+    ctx.sink_update()
+    ctx.apply()
+    out, work = ctx.sink_create(w.r_k, rho_tr, max_new)
+    torch.cuda.synchronize()
+    n = int(work[0].item())
+    got = out.cpu().numpy().reshape(7, -1)
+    st = ctx.state.cpu().numpy()
+    ctx.close()
+    say(f"  {n} new sinks")
+    assert n == n_ref
+    assert np.array_equal(got[:, :n], out_ref[:, :n])
+    assert np.array_equal(st, s64.astype(np.float32))
