@@ -306,7 +306,8 @@ int pmp_apply(pmp_ctx *ctx, void *state, const void *buf, const pmp_limits *limi
  *         receives the number of qualifying cells.  When it exceeds max_new,
  *         nothing is created and state and out are left alone (call again
  *         with a larger list).
- * max_new in [0, 65536], r_k in [0, 16].  Allocates nothing.  Errors:
+ * max_new in [0, 65536], r_k in [0, 16] and floor(r_k) at most every axis
+ * length of the domain.  Allocates nothing.  Errors:
  * PMP_EINVAL (arguments), PMP_EUNSUPPORTED (not one box covering the
  * domain). */
 int pmp_sink_create(pmp_ctx *ctx, void *state, const void *buf, double r_k, double rho_tr,

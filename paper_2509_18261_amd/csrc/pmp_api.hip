@@ -1234,6 +1234,10 @@ int pmp_sink_create(pmp_ctx* c, void* state, const void* buf, double r_k, double
   for (int a = 0; a < 3; ++a)
     if (c->hboxes[0].lo[a] != 0 || c->hboxes[0].n[a] != c->domain[a])
       return fail(PMP_EUNSUPPORTED, "sink creation needs the single box to cover the domain");
+  for (int a = 0; a < 3; ++a)
+    if (std::floor(r_k) > c->domain[a])
+      return fail(PMP_EINVAL, "r_k = %g reaches past the domain (%d cells along axis %d)", r_k,
+                  c->domain[a], a);
   const Mesh M = c->mesh();
   PMP_HIP(launch_sink_create(M, state, buf, r_k, rho_tr, (long long)max_new, out,
                              (long long*)work,

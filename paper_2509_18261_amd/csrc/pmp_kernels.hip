@@ -2473,13 +2473,18 @@ hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* sta
 
 // ------------------------------------------------------------ sink creation
 
-// Sink creation (Sec. 3.1.2), pass 1, one thread per owned cell of the single
-// periodic box.  A cell qualifies when rho > rho_Tr, the folded removal
-// channel K is zero there (no sink kernel reaches it), and it is the densest
-// cell within r_K of its centre (equal densities ranked by the linear cell
-// index, the lower index counting as denser).  Only the state before any
-// creation is read.  Qualifying cells are counted in work[0] and, up to
-// max_new of them, appended in arrival order to work[1 ..].
+// Sink creation (Sec. 3.1.2), pass 1.  Each wavefront takes 64 consecutive
+// cells of the single periodic box; a cell is a candidate when rho > rho_Tr
+// and the folded removal channel K is zero there (no sink kernel reaches it).
+// The whole wavefront then tests each candidate in turn: the lanes cover the
+// (dy, dx) offsets of the r_K cube (their sphere test needs dz as well), the
+// loop runs over dz, and any cell within r_K that is denser (equal densities
+// ranked by the linear cell index, the lower index counting as denser)
+// disqualifies the candidate.  Only the state before any creation is read.
+// Qualifying cells are counted in work[0] and, up to max_new of them,
+// appended in arrival order to work[1 ..]; work[1 + max_new ..] (pass 2's
+// rank accumulators) is zeroed.  R = floor(r_K) must not exceed
+// any axis length, so one wrap per axis suffices.
 template <class T, class S>
 __global__ __launch_bounds__(256) void k_create_find(Mesh M, const S* __restrict__ state,
                                                      const T* __restrict__ buf, double r_k,
@@ -2488,56 +2493,100 @@ __global__ __launch_bounds__(256) void k_create_find(Mesh M, const S* __restrict
   const DevBox B = M.boxes[0];
   const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
   const int g = M.ghost;
-  const int R = (int)floor(r_k);
+  const int R = (int)floor(r_k), side = 2 * R + 1, plane = side * side;
   const double r2 = r_k * r_k;
+  const int lane = threadIdx.x & (kWave - 1);
   const T* K = (buf != nullptr && M.slot[5] >= 0) ? buf + B.boff + M.slot[5] * B.npad : nullptr;
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < B.ncell;
-       c += (long long)gridDim.x * blockDim.x) {
-    const double rho = (double)state[B.soff + c];
-    if (!(rho > rho_tr)) continue;
-    const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((long long)nx * ny));
-    if (K != nullptr &&
-        to_f64(K[((long long)(k + g) * B.p[1] + (j + g)) * B.p[0] + (i + g)]) != 0.0)
-      continue;
-    bool densest = true;
-    for (int dk = -R; dk <= R && densest; ++dk)
-      for (int dj = -R; dj <= R && densest; ++dj)
-        for (int di = -R; di <= R && densest; ++di) {
-          if (!((double)(di * di + dj * dj + dk * dk) <= r2)) continue;
-          const long long o = ((long long)imod(k + dk, nz) * ny + imod(j + dj, ny)) * nx +
-                              imod(i + di, nx);
-          if (o == c) continue;
-          const double ro = (double)state[B.soff + o];
-          if (ro > rho || (ro == rho && o < c)) densest = false;
+  const S* rho_f = state + B.soff;
+  // the rank accumulators of pass 2 start at zero
+  for (long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x; z < max_new;
+       z += (long long)gridDim.x * blockDim.x)
+    work[1 + max_new + z] = 0;
+  const long long nwave = (long long)gridDim.x * (blockDim.x / kWave);
+  for (long long base = ((long long)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave)) *
+                        kWave;
+       base < B.ncell; base += nwave * kWave) {
+    const long long c = base + lane;
+    bool cand = false;
+    double rho = 0.0;
+    int i = 0, j = 0, k = 0;
+    if (c < B.ncell) {
+      rho = (double)rho_f[c];
+      if (rho > rho_tr) {
+        i = (int)(c % nx);
+        j = (int)((c / nx) % ny);
+        k = (int)(c / ((long long)nx * ny));
+        cand = (K == nullptr) ||
+               to_f64(K[((long long)(k + g) * B.p[1] + (j + g)) * B.p[0] + (i + g)]) == 0.0;
+      }
+    }
+    unsigned long long mask = __ballot(cand);
+    while (mask) {
+      const int src = __ffsll((long long)mask) - 1;
+      mask &= mask - 1;
+      const long long cc = __shfl(c, src, kWave);
+      const double rc = __shfl(rho, src, kWave);
+      const int ci = __shfl(i, src, kWave), cj = __shfl(j, src, kWave),
+                ck = __shfl(k, src, kWave);
+      bool beaten = false;
+      for (int q = lane; q < plane; q += kWave) {
+        const int dj = q / side - R, di = q - (dj + R) * side - R;
+        const int dyx = di * di + dj * dj;
+        // members of this (dy, dx) column: dz^2 <= r_K^2 - dy^2 - dx^2, the
+        // same test as (double)(dy^2 + dx^2 + dz^2) <= r_K^2 on integers
+        int kmax = -1;
+        while (kmax < R && (double)(dyx + (kmax + 1) * (kmax + 1)) <= r2) ++kmax;
+        int ii = ci + di, jj = cj + dj;
+        ii += (ii < 0) ? nx : ((ii >= nx) ? -nx : 0);
+        jj += (jj < 0) ? ny : ((jj >= ny) ? -ny : 0);
+        const long long col = (long long)jj * nx + ii;
+#pragma unroll 4
+        for (int dk = -kmax; dk <= kmax; ++dk) {
+          int kk = ck + dk;
+          kk += (kk < 0) ? nz : ((kk >= nz) ? -nz : 0);
+          const long long o = (long long)kk * ny * nx + col;
+          const double ro = (double)rho_f[o];
+          beaten |= (o != cc) && ((ro > rc) || (ro == rc && o < cc));
         }
-    if (!densest) continue;
-    const long long slot = (long long)atomicAdd((unsigned long long*)work, 1ull);
-    if (slot < max_new) work[1 + slot] = c;
+      }
+      if (__ballot(beaten) == 0 && lane == src) {
+        const long long slot = (long long)atomicAdd((unsigned long long*)work, 1ull);
+        if (slot < max_new) work[1 + slot] = cc;
+      }
+    }
   }
 }
 
-// Pass 2: the appended cell indices (distinct) put in increasing order by
-// rank, rank = how many others are smaller, into work[1 + max_new ..].  Does
-// nothing when more cells qualified than max_new.
+// Pass 2: the rank of each appended cell index (distinct keys), rank = how
+// many others are smaller, accumulated into work[1 + max_new ..] (zeroed
+// before).  Block (x, y) compares 256 keys against one LDS chunk of
+// kRankChunk keys.  Does nothing when more cells qualified than max_new.
+constexpr int kRankChunk = 2048;
 __global__ __launch_bounds__(256) void k_create_rank(long long max_new,
                                                      long long* __restrict__ work) {
+  __shared__ long long chunk[kRankChunk];
   const long long n = work[0];
-  if (n > max_new) return;
+  const long long t0 = (long long)blockIdx.x * blockDim.x;
+  const long long u0 = (long long)blockIdx.y * kRankChunk;
+  if (n > max_new || t0 >= n || u0 >= n) return;
   const long long* keys = work + 1;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-       t += (long long)gridDim.x * blockDim.x) {
-    const long long key = keys[t];
-    long long rank = 0;
-    for (long long u = 0; u < n; ++u) rank += (keys[u] < key);
-    work[1 + max_new + rank] = key;
-  }
+  const int m = (int)((n - u0 < kRankChunk) ? n - u0 : kRankChunk);
+  for (int u = threadIdx.x; u < m; u += blockDim.x) chunk[u] = keys[u0 + u];
+  __syncthreads();
+  const long long t = t0 + threadIdx.x;
+  if (t >= n) return;
+  const long long key = keys[t];
+  long long rank = 0;
+#pragma unroll 8
+  for (int u = 0; u < m; ++u) rank += (chunk[u] < key);
+  if (rank) atomicAdd((unsigned long long*)(work + 1 + max_new + t), (unsigned long long)rank);
 }
 
-// Pass 3: one thread per new sink, in cell index order.  The sink sits at
-// the cell centre with mass (rho - rho_Tr) V and momentum mass * p / rho; the
-// cell keeps its velocity and specific energy (rho -> rho_Tr, p ->
-// (p / rho) rho_Tr, E -> (E / rho) rho_Tr).  out is [7][max_new]: x, y, z,
-// m, px, py, pz.
+// Pass 3: one thread per new sink, written at its rank (cell index order).
+// The sink sits at the cell centre with mass (rho - rho_Tr) V and momentum
+// mass * p / rho; the cell keeps its velocity and specific energy (rho ->
+// rho_Tr, p -> (p / rho) rho_Tr, E -> (E / rho) rho_Tr).  out is
+// [7][max_new]: x, y, z, m, px, py, pz.
 template <class S>
 __global__ __launch_bounds__(256) void k_create_apply(Mesh M, S* __restrict__ state,
                                                       double rho_tr, long long max_new,
@@ -2547,20 +2596,21 @@ __global__ __launch_bounds__(256) void k_create_apply(Mesh M, S* __restrict__ st
   if (n > max_new) return;
   const DevBox B = M.boxes[0];
   const int nx = B.n[0], ny = B.n[1];
-  const long long* sorted = work + 1 + max_new;
+  const long long* keys = work + 1;
+  const long long* ranks = work + 1 + max_new;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (long long)gridDim.x * blockDim.x) {
-    const long long c = sorted[t];
+    const long long c = keys[t], r = ranks[t];
     S* cell = state + B.soff + c;
     const double rho = (double)cell[0];
     const double m = (rho - rho_tr) * M.V;
-    out[t] = (double)(c % nx) + 0.5;
-    out[max_new + t] = (double)((c / nx) % ny) + 0.5;
-    out[2 * max_new + t] = (double)(c / ((long long)nx * ny)) + 0.5;
-    out[3 * max_new + t] = m;
+    out[r] = (double)(c % nx) + 0.5;
+    out[max_new + r] = (double)((c / nx) % ny) + 0.5;
+    out[2 * max_new + r] = (double)(c / ((long long)nx * ny)) + 0.5;
+    out[3 * max_new + r] = m;
     for (int a = 1; a <= 3; ++a) {
       const double v = (double)cell[a * B.ncell] / rho;
-      out[(3 + a) * max_new + t] = m * v;
+      out[(3 + a) * max_new + r] = m * v;
       cell[a * B.ncell] = (S)(v * rho_tr);
     }
     cell[4 * B.ncell] = (S)(((double)cell[4 * B.ncell] / rho) * rho_tr);
@@ -2575,16 +2625,18 @@ static void create_launch(const Mesh& M, void* state, const void* buf, double r_
   const int grid = grid_for(ncell, 256, M.num_cu * 32);
   hipLaunchKernelGGL((k_create_find<T, S>), dim3(grid), dim3(256), 0, s, M, (const S*)state,
                      (const T*)buf, r_k, rho_tr, max_new, work);
-  const int g2 = grid_for(max_new, 256, 1024);
-  hipLaunchKernelGGL(k_create_rank, dim3(g2), dim3(256), 0, s, max_new, work);
-  hipLaunchKernelGGL((k_create_apply<S>), dim3(g2), dim3(256), 0, s, M, (S*)state, rho_tr,
-                     max_new, (const long long*)work, out);
+  if (max_new <= 0) return;
+  const int gx = grid_for(max_new, 256, 1 << 30);
+  const int gy = grid_for(max_new, kRankChunk, 1 << 30);
+  hipLaunchKernelGGL(k_create_rank, dim3(gx, gy), dim3(256), 0, s, max_new, work);
+  hipLaunchKernelGGL((k_create_apply<S>), dim3(grid_for(max_new, 256, 1024)), dim3(256), 0, s,
+                     M, (S*)state, rho_tr, max_new, (const long long*)work, out);
 }
 
 hipError_t launch_sink_create(const Mesh& M, void* state, const void* buf, double r_k,
                               double rho_tr, long long max_new, double* out, long long* work,
                               long long ncell, hipStream_t s) {
-  hipError_t e = launch_zero(work, 8, 256, s);
+  hipError_t e = launch_zero(work, 8, 256, s);  // the count (the find pass zeroes the ranks)
   if (e != hipSuccess) return e;
   const bool f32 = (M.state == PMP_STATE_F32);
 #define PMP_CR(T)                                                                              \
