@@ -9,7 +9,7 @@ width 4.  Inputs are resident in HBM before timing starts.  Prints one JSON
 line.
 
   python bench.py [--steps K] [--warmup W] [--acc f32|f64|fix64]
-                  [--workload c2|c3|c3bh|c4|c5] [--no-cpu] [--no-modes]
+                  [--workload c2|c3|c3bh|c4|c5|c5s] [--no-cpu] [--no-modes]
 """
 from __future__ import annotations
 
@@ -411,7 +411,8 @@ def main():
     log(f"step {ms:.4f} ms (graph), {eager_ms:.4f} ms (eager); status {st}")
     tun = ctx.tuning().as_dict()
     batched = None
-    if w.nbox > 1:
+    if w.nbox > 1 and (w.sinks is None or w.sinks.n == 0):
+        # the per-box launch form has no sinks, so it is compared only without them
         batched = batched_comparison(ctx, args, eager_ms)
     ctx.close()
     del ctx
@@ -482,7 +483,7 @@ def main():
     }
     if batched is not None:
         out["batched"] = batched
-    if w.sinks is not None and w.sinks.n:
+    if w.sinks is not None and w.sinks.n and w.nbox == 1:
         out["sink_create"] = sink_create_rate(B, w, args.acc, args.channels)
         log(f"sink creation: {out['sink_create']}")
     if not args.no_calib:

@@ -150,8 +150,13 @@ typedef enum {
  *     kernel gas mass (also when v_inf = c_inf = 0), and r_acc = r_BH / dx
  *     clamped to [1/4, r_k/2] cells (r_k/2 when the rate is not finite).
  * The kernel sums are taken on the 2^-40 grid, so they do not depend on the
- * order of summation (PMP_FLAG_OVERFLOW past 2^22 per term).  Single-box
- * layouts only. */
+ * order of summation (PMP_FLAG_OVERFLOW past 2^22 per term).  Any box
+ * layout: sinks are grouped by box like the other kinds (box_off), the
+ * kernel reads the state of whichever box owns each (periodically wrapped)
+ * cell, the removal goes to the sink's own box (its ghost zone where the
+ * kernel leaves the box; the fold moves it to the owners), and Step 4 reads
+ * eta from the owners.  A kernel cell that no box owns is skipped and raises
+ * PMP_FLAG_REACH. */
 typedef struct {
   const double *x, *y, *z, *a;  /* device [n]; a is read by PMP_SINK_FRACTION only */
   int64_t n;

@@ -153,6 +153,9 @@ struct pmp_ctx {
 
   int* d_zone_off = nullptr;   // [28 nbox]
   ZoneSeg* d_zone_seg = nullptr;
+  int* d_own_start = nullptr;  // owner index (multi-box layouts), see Mesh
+  int* d_own_box = nullptr;
+  int own_bin[3] = {1, 1, 1}, own_dims[3] = {1, 1, 1};
   int2* d_apply_chunks = nullptr;
   int2* d_fold_chunks = nullptr;
   std::vector<long long> apply_chunk_off, fold_chunk_off;  // [nbox+1] host
@@ -182,6 +185,12 @@ struct pmp_ctx {
     M.shell_cells = shell_cells;
     M.status = d_status;
     M.num_cu = num_cu;
+    M.own_start = d_own_start;
+    M.own_box = d_own_box;
+    for (int a = 0; a < 3; ++a) {
+      M.own_bin[a] = own_bin[a];
+      M.own_dims[a] = own_dims[a];
+    }
     return M;
   }
   size_t acc_bytes() const { return acc == PMP_ACC_F32 ? 4 : 8; }
@@ -273,6 +282,8 @@ void release(pmp_ctx* c) {
   (void)hipFree(c->d_tile_geo);
   (void)hipFree(c->d_zone_off);
   (void)hipFree(c->d_zone_seg);
+  (void)hipFree(c->d_own_start);
+  (void)hipFree(c->d_own_box);
   (void)hipFree(c->d_apply_chunks);
   (void)hipFree(c->d_fold_chunks);
   if (!c->ws) free_bin_work(c);
@@ -741,6 +752,46 @@ int check_limits(const pmp_limits* L) {
   return PMP_OK;
 }
 
+bool covers_domain(const pmp_ctx* c) {
+  if (c->nbox != 1) return false;
+  for (int a = 0; a < 3; ++a)
+    if (c->hboxes[0].lo[a] != 0 || c->hboxes[0].n[a] != c->domain[a]) return false;
+  return true;
+}
+
+// Owner index for kernels that read cells of other boxes (the sinks): bins
+// of the smallest box extent per axis (at least domain / 128, so the index
+// stays small), each listing the boxes that overlap it.  With bins no larger
+// than any box, a bin meets at most two boxes per axis.
+void build_owner_index(pmp_ctx* c, std::vector<int>& start, std::vector<int>& boxes) {
+  for (int a = 0; a < 3; ++a) {
+    int m = c->domain[a];
+    for (const auto& b : c->hboxes) m = std::min(m, b.n[a]);
+    m = std::max(m, (c->domain[a] + 127) / 128);
+    c->own_bin[a] = std::max(m, 1);
+    c->own_dims[a] = (c->domain[a] + c->own_bin[a] - 1) / c->own_bin[a];
+  }
+  const size_t nbin = (size_t)c->own_dims[0] * c->own_dims[1] * c->own_dims[2];
+  std::vector<std::vector<int>> bins(nbin);
+  for (int i = 0; i < c->nbox; ++i) {
+    const HostBox& b = c->hboxes[i];
+    int b0[3], b1[3];
+    for (int a = 0; a < 3; ++a) {
+      b0[a] = b.lo[a] / c->own_bin[a];
+      b1[a] = (b.lo[a] + b.n[a] - 1) / c->own_bin[a];
+    }
+    for (int z = b0[2]; z <= b1[2]; ++z)
+      for (int y = b0[1]; y <= b1[1]; ++y)
+        for (int x = b0[0]; x <= b1[0]; ++x)
+          bins[((size_t)z * c->own_dims[1] + y) * c->own_dims[0] + x].push_back(i);
+  }
+  start.assign(nbin + 1, 0);
+  for (size_t q = 0; q < nbin; ++q) start[q + 1] = start[q] + (int)bins[q].size();
+  boxes.clear();
+  boxes.reserve(start[nbin]);
+  for (const auto& v : bins) boxes.insert(boxes.end(), v.begin(), v.end());
+}
+
 int check_sinks(const pmp_ctx* c, const pmp_sinks* k) {
   if (k->rate != PMP_SINK_FRACTION && k->rate != PMP_SINK_BONDI)
     return fail(PMP_EINVAL, "sink rate %d is not a pmp_sink_rate_t", (int)k->rate);
@@ -758,11 +809,6 @@ int check_sinks(const pmp_ctx* c, const pmp_sinks* k) {
   }
   if (c->slot[5] < 0)
     return fail(PMP_EINVAL, "sinks need a layout with the removal channel K (with_sinks = 1)");
-  if (c->nbox != 1)
-    return fail(PMP_EUNSUPPORTED, "sinks are supported on single-box layouts only");
-  for (int a = 0; a < 3; ++a)
-    if (c->hboxes[0].lo[a] != 0 || c->hboxes[0].n[a] != c->domain[a])
-      return fail(PMP_EUNSUPPORTED, "sinks need the single box to cover the domain");
   if (!(k->r_k >= 0.0) || (k->rate == PMP_SINK_FRACTION && !(k->r_gauss > 0.0)))
     return fail(PMP_EINVAL, "sink radii must satisfy r_k >= 0, r_gauss > 0");
   if (std::floor(k->r_k + 0.5) > c->ghost)
@@ -1108,6 +1154,12 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   };
   upload(&c->d_zone_off, zone_off);
   upload(&c->d_zone_seg, zone_seg);
+  if (!covers_domain(c)) {
+    std::vector<int> own_start, own_box;
+    build_owner_index(c, own_start, own_box);
+    upload(&c->d_own_start, own_start);
+    upload(&c->d_own_box, own_box);
+  }
   upload(&c->d_apply_chunks, apply_chunks);
   upload(&c->d_fold_chunks, fold_chunks);
   if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(DevStatus));

@@ -86,6 +86,12 @@ struct Mesh {
   long long shell_cells;
   DevStatus* status;
   int num_cu;
+  // Owner index of the periodic domain (null when one box covers it): the
+  // domain cut into bins of own_bin cells per axis, bin b listing the boxes
+  // own_box[own_start[b] .. own_start[b + 1]) that overlap it.
+  const int* own_start;
+  const int* own_box;
+  int own_bin[3], own_dims[3];
 };
 
 struct Particles {

@@ -559,9 +559,47 @@ __global__ __launch_bounds__(256) void k_sn_direct(Mesh M, Particles P,
 
 // ------------------------------------------------------------------ sinks
 
-template <class S>
-__device__ __forceinline__ long long state_cell(const DevBox& B, int iw, int jw, int kw) {
-  return ((long long)(kw - B.lo[2]) * B.n[1] + (jw - B.lo[1])) * B.n[0] + (iw - B.lo[0]);
+// Where global cell (i, j, k) lives: wrapped into the periodic domain, the
+// box that owns it (through the owner index when one box does not cover the
+// domain), its local owned coordinates and the state element of its field 0.
+// False when no box owns the cell.
+struct CellLoc {
+  const DevBox* B;
+  int l[3];
+  long long s;
+};
+
+__device__ __forceinline__ bool locate(const Mesh& M, int i, int j, int k, CellLoc& L) {
+  const int w[3] = {imod(i, M.domain[0]), imod(j, M.domain[1]), imod(k, M.domain[2])};
+  if (M.own_start == nullptr) {
+    L.B = M.all_boxes;
+  } else {
+    const int bin = ((w[2] / M.own_bin[2]) * M.own_dims[1] + w[1] / M.own_bin[1]) *
+                        M.own_dims[0] + w[0] / M.own_bin[0];
+    const DevBox* hit = nullptr;
+    for (int q = M.own_start[bin]; q < M.own_start[bin + 1] && hit == nullptr; ++q) {
+      const DevBox* B = M.all_boxes + M.own_box[q];
+      if ((unsigned)(w[0] - B->lo[0]) < (unsigned)B->n[0] &&
+          (unsigned)(w[1] - B->lo[1]) < (unsigned)B->n[1] &&
+          (unsigned)(w[2] - B->lo[2]) < (unsigned)B->n[2])
+        hit = B;
+    }
+    if (hit == nullptr) return false;
+    L.B = hit;
+  }
+  for (int a = 0; a < 3; ++a) L.l[a] = w[a] - L.B->lo[a];
+  L.s = L.B->soff + ((long long)L.l[2] * L.B->n[1] + L.l[1]) * L.B->n[0] + L.l[0];
+  return true;
+}
+
+// Box of sink s: the b with off[b] <= s < off[b + 1] (empty boxes skipped).
+__device__ __forceinline__ int particle_box(const long long* off, int nbox, long long s) {
+  int lo = 0, hi = nbox - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= s) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 // Bondi-Hoyle request of one sink (Sec. 3.1.1, eqs. "rbh" and "mdot", and the
@@ -574,10 +612,10 @@ __device__ __forceinline__ long long state_cell(const DevBox& B, int iw, int jw,
 // (lambda^2 c_inf^2 + v_inf^2)^(1/2).  The request mdot dt is capped at M (M
 // also when v_inf = c_inf = 0), r_acc = r_BH / dx clamped to [1/4, r_k/2].
 template <class S>
-__device__ void bondi_request(const Mesh& M, const DevBox& B, const S* __restrict__ state,
-                              const SinkParams& K, long long s, double x, double y, double z,
-                              const int lo[3], int cx, int cxy, int total, bool& ok,
-                              double& req, double& racc) {
+__device__ void bondi_request(const Mesh& M, const S* __restrict__ state, const SinkParams& K,
+                              long long s, double x, double y, double z, const int lo[3], int cx,
+                              int cxy, int total, bool& ok, bool& reach, double& req,
+                              double& racc) {
   const double r2 = K.r_k * K.r_k;
   long long qn = 0, qm = 0, qx = 0, qy = 0, qz = 0, qc = 0;
   for (int t = threadIdx.x; t < total; t += kWave) {
@@ -585,13 +623,17 @@ __device__ void bondi_request(const Mesh& M, const DevBox& B, const S* __restric
     const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
     const double d2 = dist2(x, y, z, i, j, k);
     if (!(d2 <= r2)) continue;
-    const long long c = B.soff + state_cell<S>(B, imod(i, M.domain[0]), imod(j, M.domain[1]),
-                                               imod(k, M.domain[2]));
+    CellLoc Lc;
+    if (!locate(M, i, j, k, Lc)) {
+      reach = true;
+      continue;
+    }
+    const long long c = Lc.s, nc = Lc.B->ncell;
     const double rho = (double)state[c];
-    const double px = (double)state[c + B.ncell];
-    const double py = (double)state[c + 2 * B.ncell];
-    const double pz = (double)state[c + 3 * B.ncell];
-    const double E = (double)state[c + 4 * B.ncell];
+    const double px = (double)state[c + nc];
+    const double py = (double)state[c + 2 * nc];
+    const double pz = (double)state[c + 3 * nc];
+    const double E = (double)state[c + 4 * nc];
     double cs = 0.0;
     if (rho > 0.0) {
       double eint = E - ((px * px + py * py) + pz * pz) / (2.0 * rho);
@@ -645,9 +687,10 @@ __device__ void bondi_request(const Mesh& M, const DevBox& B, const S* __restric
 // the Gaussian weights w = exp(-d^2/r_acc^2) (eq. "kernel") and the kernel gas
 // mass sum rho V on the 2^-40 grid (exact, order-free).  Pass 2 adds each
 // cell's removal k = max(M_req w / (W V), rho - rho_Tr) (eqs. "kernel_wgt",
-// "accretion_function") to field 5.  Single box covering the domain: state
-// reads wrap periodically, deposits go to the ghost-zoned buffer unwrapped.
-// scratch receives W, M_req and r_acc^2 per sink.
+// "accretion_function") to field 5 of the sink's own box, in its ghost zone
+// where the kernel leaves the box (the fold moves it to the owners).  State
+// reads go to the box that owns each (periodically wrapped) cell.  scratch
+// receives W, M_req and r_acc^2 per sink.
 template <int ACC, class S>
 __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
                                                      const S* __restrict__ state,
@@ -656,10 +699,10 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
                                                      double rho_tr, double* __restrict__ bound) {
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
   const int lane = threadIdx.x;
-  const DevBox B = M.boxes[0];
   const int g = M.ghost;
   const double r2 = K.r_k * K.r_k;
   for (long long s = blockIdx.x; s < P.n; s += gridDim.x) {
+    const DevBox B = M.all_boxes[particle_box(P.box_off, M.nbox, s)];
     const double x = P.x[s], y = P.y[s], z = P.z[s];
     double* out = scratch + kSinkScratch * s;
     int h[3];
@@ -679,10 +722,10 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
     const int cx = hi[0] - lo[0] + 1, cy = hi[1] - lo[1] + 1;
     const int cxy = cx * cy;
     const int total = cxy * (hi[2] - lo[2] + 1);
-    bool ok = true;
+    bool ok = true, reach_bad = false;
     double racc = K.r_gauss, Mbondi = 0.0;
     if (K.rate == PMP_SINK_BONDI)
-      bondi_request<S>(M, B, state, K, s, x, y, z, lo, cx, cxy, total, ok, Mbondi, racc);
+      bondi_request<S>(M, state, K, s, x, y, z, lo, cx, cxy, total, ok, reach_bad, Mbondi, racc);
     const double g2 = racc * racc;
     long long wq = 0, mq = 0;
     for (int t = lane; t < total; t += kWave) {
@@ -690,9 +733,12 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
       const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
       const double d2 = dist2(x, y, z, i, j, k);
       if (!(d2 <= r2)) continue;
-      const long long c = state_cell<S>(B, imod(i, M.domain[0]), imod(j, M.domain[1]),
-                                        imod(k, M.domain[2]));
-      const double rho = (double)state[B.soff + c];
+      CellLoc Lc;
+      if (!locate(M, i, j, k, Lc)) {
+        reach_bad = true;
+        continue;
+      }
+      const double rho = (double)state[Lc.s];
       const double w = kernel_exp(-(d2 / g2));
       long long q1, q2;
       if (!quantise(w, q1) || !quantise(rho * M.V, q2)) { ok = false; continue; }
@@ -702,6 +748,7 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
     wq = group_sum<kWave>(wq);
     mq = group_sum<kWave>(mq);
     if (!ok) raise_flag(M.status, PMP_FLAG_OVERFLOW);
+    if (reach_bad) raise_flag(M.status, PMP_FLAG_REACH);
     if (wq <= 0) {
       if (lane == 0) { out[0] = 0.0; out[1] = 0.0; out[2] = g2; }
       continue;
@@ -714,7 +761,6 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
     T* f5 = buf + B.boff + M.slot[5] * B.npad;
     long long qreq = 0;
     int first = 0x7fffffff, hostm = 0;
-    bool reach_bad = false;
     for (int t = lane; t < total; t += kWave) {
       const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
       const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
@@ -722,9 +768,12 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
       if (!(d2 <= r2)) continue;
       first = min(first, t);
       hostm |= (i == h[0] && j == h[1] && k == h[2]);
-      const long long c = state_cell<S>(B, imod(i, M.domain[0]), imod(j, M.domain[1]),
-                                        imod(k, M.domain[2]));
-      const double rho = (double)state[B.soff + c];
+      CellLoc Lc;
+      if (!locate(M, i, j, k, Lc)) {
+        reach_bad = true;
+        continue;
+      }
+      const double rho = (double)state[Lc.s];
       const double w = kernel_exp(-(d2 / g2));
       const double kreq = (Mreq * w) / (W * M.V);
       const double tr = rho - rho_tr;
@@ -806,16 +855,16 @@ __global__ __launch_bounds__(64) void k_sink_update(Mesh M, Particles P,
                                                     double* dpx, double* dpy, double* dpz) {
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
   const int lane = threadIdx.x;
-  const DevBox B = M.boxes[0];
   const int g = M.ghost;
   const double r2 = r_k * r_k;
   for (long long s = blockIdx.x; s < P.n; s += gridDim.x) {
+    const DevBox B = M.all_boxes[particle_box(P.box_off, M.nbox, s)];
     const double x = P.x[s], y = P.y[s], z = P.z[s];
     const double* in = scratch + kSinkScratch * s;
     const double W = in[0], Mreq = in[1], g2 = in[2];
     double sm = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     long long qm = 0, qx = 0, qy = 0, qz = 0;
-    bool ok = true;
+    bool ok = true, reach_bad = false;
     int h[3];
     if (W > 0.0 && host_cell(B, x, y, z, h)) {
       int lo[3], hi[3];
@@ -830,22 +879,26 @@ __global__ __launch_bounds__(64) void k_sink_update(Mesh M, Particles P,
         const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
         const double d2 = dist2(x, y, z, i, j, k);
         if (!(d2 <= r2)) continue;
-        const int iw = imod(i, M.domain[0]), jw = imod(j, M.domain[1]), kw = imod(k, M.domain[2]);
-        const long long c = state_cell<S>(B, iw, jw, kw);
-        const double rho = (double)state[B.soff + c];
+        CellLoc Lc;
+        if (!locate(M, i, j, k, Lc)) {
+          reach_bad = true;
+          continue;
+        }
+        const DevBox& Bo = *Lc.B;  // owner: its state and its folded buffer
+        const double rho = (double)state[Lc.s];
         const double w = kernel_exp(-(d2 / g2));
         const double kreq = (Mreq * w) / (W * M.V);
         const double tr = rho - L.rho_tr;
         const double kc = (tr > kreq) ? tr : kreq;
-        const long long bidx = ((long long)(kw - B.lo[2] + g) * B.p[1] + (jw - B.lo[1] + g)) *
-                                   B.p[0] + (iw - B.lo[0] + g);
-        const double K = to_f64(buf[B.boff + M.slot[5] * B.npad + bidx]);
+        const long long bidx =
+            ((long long)(Lc.l[2] + g) * Bo.p[1] + (Lc.l[1] + g)) * Bo.p[0] + (Lc.l[0] + g);
+        const double K = to_f64(buf[Bo.boff + M.slot[5] * Bo.npad + bidx]);
         const double Kl = limited_removal(K, rho, L);
         const double eta = (K > 0.0) ? Kl / K : 1.0;
         const double term = (eta * kc) * M.V;
-        const double vx = (double)state[B.soff + B.ncell + c] / rho;
-        const double vy = (double)state[B.soff + 2 * B.ncell + c] / rho;
-        const double vz = (double)state[B.soff + 3 * B.ncell + c] / rho;
+        const double vx = (double)state[Lc.s + Bo.ncell] / rho;
+        const double vy = (double)state[Lc.s + 2 * Bo.ncell] / rho;
+        const double vz = (double)state[Lc.s + 3 * Bo.ncell] / rho;
         if constexpr (FIXED) {
           long long a0, a1, a2, a3;
           if (!quantise(term, a0) || !quantise(term * vx, a1) || !quantise(term * vy, a2) ||
@@ -875,6 +928,7 @@ __global__ __launch_bounds__(64) void k_sink_update(Mesh M, Particles P,
       sz = group_sum<kWave>(sz);
     }
     if (!ok) raise_flag(M.status, PMP_FLAG_OVERFLOW);
+    if (reach_bad) raise_flag(M.status, PMP_FLAG_REACH);
     if (lane == 0) {
       dm[s] = sm;
       dpx[s] = sx;

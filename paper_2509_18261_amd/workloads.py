@@ -338,9 +338,13 @@ def c5(seed: int = 5, nb: int = 16, n_total: int | None = None, emin=8, emax=64,
 
 
 def multibox(edges_x, edges_y, edges_z, ghost, positions_cic=None, masses=None,
-             positions_sn=None, sn_radius=1.0, seed=0, dtype=np.float64) -> Workload:
+             positions_sn=None, sn_radius=1.0, seed=0, dtype=np.float64,
+             positions_sink=None, sink_rate=0, r_k=None) -> Workload:
     """Hand-built rectilinear layout with given particle positions, for edge
-    and corner tests (particles placed on box faces, edges and corners)."""
+    and corner tests (particles placed on box faces, edges and corners).
+    Sinks (``positions_sink``) request a quarter of their kernel mass, or the
+    Bondi-Hoyle rate with ``sink_rate`` 1; r_K defaults to the ghost width
+    and the Gaussian width to r_K / 2."""
     rng = np.random.default_rng(seed)
     domain, lo, n, cuts = rectilinear(edges_x, edges_y, edges_z)
     nbx, nby, nbz = len(edges_x), len(edges_y), len(edges_z)
@@ -354,7 +358,42 @@ def multibox(edges_x, edges_y, edges_z, ghost, positions_cic=None, masses=None,
     if positions_sn is not None:
         ps = np.asarray(positions_sn, dtype=np.float64).reshape(-1, 3)
         sn = _group_by_box(ps, sn_fields(ps.shape[0], sn_radius), cuts, (nbx, nby, nbz))
-    return Workload("multibox", domain, lo, n, ghost, 1.0, state, cic=cic, sn=sn)
+    sk = None
+    r_k = float(ghost) if r_k is None else float(r_k)
+    if positions_sink is not None:
+        pk = np.asarray(positions_sink, dtype=np.float64).reshape(-1, 3)
+        fields = (bondi_fields(rng, pk.shape[0]) if sink_rate == 1
+                  else {"a": np.full(pk.shape[0], 0.25)})
+        sk = _group_by_box(pk, fields, cuts, (nbx, nby, nbz))
+    return Workload("multibox", domain, lo, n, ghost, 1.0, state, cic=cic, sn=sn, sinks=sk,
+                    r_k=r_k, r_gauss=r_k / 2.0, sink_rate=sink_rate)
 
 
-CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "c3bh": c3bh}
+def c5s(seed: int = 5, nb: int = 16, n_sink: int | None = None, bondi: bool = False,
+        dtype=np.float32) -> Workload:
+    """The batched AMR level of c5 with sinks drawn from the same clumps,
+    grouped by box: r_K = g = 2, Gaussian width 1 (fraction a = 1/4), or the
+    Bondi-Hoyle rate with r_acc clamped to [1/4, 1]."""
+    w = c5(seed, nb, dtype=dtype)
+    rng = np.random.default_rng(seed + 2000)
+    n_sink = int(round(1024 * (nb / 16.0) ** 3)) if n_sink is None else n_sink
+    cx, cy, cz = (np.concatenate([[0], np.cumsum(e)]) for e in _edges_of(w))
+    pos = clumped_positions(rng, n_sink, w.domain)
+    fields = bondi_fields(rng, n_sink) if bondi else {"a": np.full(n_sink, 0.25)}
+    sk = _group_by_box(pos, fields, (cx, cy, cz), (nb, nb, nb))
+    return dataclasses.replace(w, name=w.name + ("_bondi_sinks" if bondi else "_sinks"),
+                               sinks=sk, r_k=2.0, r_gauss=1.0, sink_rate=1 if bondi else 0)
+
+
+def _edges_of(w):
+    """Per-axis box edges of a rectilinear layout (boxes in x-fastest order)."""
+    lo = np.asarray(w.lo)
+    n = np.asarray(w.n)
+    out = []
+    for a in range(3):
+        firsts = np.unique(lo[:, a])
+        out.append(np.array([n[np.flatnonzero(lo[:, a] == f)[0], a] for f in firsts]))
+    return out
+
+
+CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "c3bh": c3bh, "c5s": c5s}

@@ -135,6 +135,8 @@ SMALL = {
     "c3bh_40": lambda: W.c3bh(nx=40, n_sink=48),
     "c4_48": lambda: W.c4(nx=48),
     "c5_4": lambda: W.c5(nb=4),
+    "c5s_4": lambda: W.c5s(nb=4),
+    "c5sbh_4": lambda: W.c5s(nb=4, bondi=True),
 }
 
 
@@ -191,6 +193,21 @@ def test_edge_layouts(B, orc, idx, acc, path):
     got, _ = check(B, orc, w, acc, tuning={"deposit_path": path})
     if w.name == "empty":
         assert np.array_equal(got["state"], w.state)
+
+
+SINK_EDGE_PTS = [(6.0, 5.0, 3.5), (5.9, 4.9, 0.2), (12.6, 13.4, 7.9), (3.5, 10.2, 4.4),
+                 (0.3, 0.4, 0.5), (6.5, 5.5, 4.0), (6.99, 13.99, 7.99)]
+
+
+@pytest.mark.parametrize("rate", [0, 1])
+@pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
+def test_multibox_sinks_on_faces_and_corners(B, orc, acc, rate):
+    """Sinks on box faces, edges and corners of a 2 x 2 x 1 tiling, with
+    kernels reaching into three other boxes and across the periodic boundary."""
+    w = W.multibox([6, 7], [5, 9], [8], ghost=2, positions_cic=[(6.2, 5.1, 3.3)],
+                   masses=[0.5], positions_sink=SINK_EDGE_PTS, sink_rate=rate, seed=3,
+                   dtype=np.float32 if acc == "f32" else np.float64)
+    check(B, orc, w, acc)
 
 
 SHAPES = [
