@@ -832,12 +832,13 @@ int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
 
 /* ------------------------------------------------------ sink creation */
 
-/* Sink creation (Sec. 3.1.2).  A cell c of the single periodic box becomes a
- * sink when
+/* Sink creation (Sec. 3.1.2).  A cell c of the periodic domain, owned by
+ * some box, becomes a sink when
  *   (1) rho_c > rho_Tr (the Truelove density of eq. "truelove"),
  *   (2) c is the densest cell among those whose centres lie within r_K of
- *       its centre (the cell itself included; equal densities are ranked by
- *       the linear cell index, the lower index counting as denser), and
+ *       its centre (the cell itself included; cells no box owns are left
+ *       out; equal densities are ranked by the global linear cell index, the
+ *       lower index counting as denser), and
  *   (3) the folded removal channel K is zero at c, that is no sink kernel
  *       reaches c (the paper's test for another sink within r_K).
  * Every test reads the state as it was before any creation, so the result
@@ -845,23 +846,21 @@ int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
  * centre with mass (rho_c - rho_Tr) V and momentum (mass) p_c / rho_c; the
  * cell keeps its velocity and specific energy: rho -> rho_Tr,
  * p -> (p / rho) rho_Tr, E -> (E / rho) rho_Tr.  The sinks are listed in
- * increasing linear cell index (x fastest) in out [7][max_new] (x, y, z, m,
- * px, py, pz); *count receives the number of qualifying cells, and when it
- * exceeds max_new nothing is created.  buf may be NULL, or a buffer without
- * the K channel (nfield 5): then no cell is excluded by (3). */
+ * increasing global linear cell index (x fastest) in out [7][max_new] (x, y,
+ * z, m, px, py, pz); *count receives the number of qualifying cells, and
+ * when it exceeds max_new nothing is created.  buf may be NULL, or a buffer
+ * without the K channel (nfield 5): then no cell is excluded by (3). */
 int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf, double r_k,
                     double rho_tr, int64_t max_new, double *out, int64_t *count) {
   int rc = check_mesh(M);
   if (rc) return rc;
-  if (M->nbox != 1 || !state || !count || max_new < 0 || (max_new > 0 && !out)) return ORC_EINVAL;
-  for (int a = 0; a < 3; ++a)
-    if (M->lo[a] != 0 || M->n[a] != M->domain[a]) return ORC_EINVAL;
+  if (!state || !count || max_new < 0 || (max_new > 0 && !out)) return ORC_EINVAL;
   if (!(r_k >= 0.0) || !(r_k <= 16.0) || rho_tr != rho_tr) return ORC_EINVAL;
   if (mode != ORC_F64 && mode != ORC_FIX64) return ORC_EINVAL;
   geom G;
-  rc = geom_build(M, &G, 0);
+  rc = geom_build(M, &G, 1);
   if (rc) return rc;
-  const int64_t nx = M->n[0], ny = M->n[1], nz = M->n[2];
+  const int64_t nx = M->domain[0], ny = M->domain[1], nz = M->domain[2];
   const int64_t ncell = nx * ny * nz;
   const double V = (M->dx * M->dx) * M->dx;
   const int64_t R = (int64_t)floor(r_k);
@@ -876,19 +875,25 @@ int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf,
     for (int64_t j = 0; j < ny; ++j)
       for (int64_t i = 0; i < nx; ++i) {
         const int64_t c = (k * ny + j) * nx + i;
-        const double rho = state[state_index(M, &G, 0, 0, i, j, k)];
+        int64_t iw, jw, kw;
+        const int ob = owner_of(M, &G, i, j, k, &iw, &jw, &kw);
+        if (ob < 0) continue;
+        const double rho = state[state_index(M, &G, ob, 0, iw, jw, kw)];
         if (!(rho > rho_tr)) continue;
-        if (buf && M->nfield == 6 && buf_value(mode, buf, buf_index(M, &G, 0, 5, i, j, k)) != 0.0)
+        if (buf && M->nfield == 6 &&
+            buf_value(mode, buf, buf_index(M, &G, ob, 5, iw, jw, kw)) != 0.0)
           continue;
         int densest = 1;
         for (int64_t dk = -R; dk <= R && densest; ++dk)
           for (int64_t dj = -R; dj <= R && densest; ++dj)
             for (int64_t di = -R; di <= R && densest; ++di) {
               if (!((double)(di * di + dj * dj + dk * dk) <= r2)) continue;
-              const int64_t ii = imod(i + di, nx), jj = imod(j + dj, ny), kk = imod(k + dk, nz);
+              int64_t ii, jj, kk;
+              const int on = owner_of(M, &G, i + di, j + dj, k + dk, &ii, &jj, &kk);
+              if (on < 0) continue;
               const int64_t o = (kk * ny + jj) * nx + ii;
               if (o == c) continue;
-              const double ro = state[state_index(M, &G, 0, 0, ii, jj, kk)];
+              const double ro = state[state_index(M, &G, on, 0, ii, jj, kk)];
               if (ro > rho || (ro == rho && o < c)) densest = 0;
             }
         if (densest) made[n_new++] = c;
@@ -898,8 +903,10 @@ int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf,
     for (int64_t s = 0; s < n_new; ++s) {
       const int64_t c = made[s];
       const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
-      const int64_t i0 = state_index(M, &G, 0, 0, i, j, k);
-      const int64_t step = box_cells(M, 0);
+      int64_t iw, jw, kw;
+      const int ob = owner_of(M, &G, i, j, k, &iw, &jw, &kw);
+      const int64_t i0 = state_index(M, &G, ob, 0, iw, jw, kw);
+      const int64_t step = box_cells(M, ob);
       const double rho = state[i0];
       const double m = (rho - rho_tr) * V;
       out[0 * max_new + s] = (double)i + 0.5;

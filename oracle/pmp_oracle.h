@@ -115,8 +115,8 @@ int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void
                     double *dpy, double *dpz);
 int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
               const orc_limits *L, double *eta, orc_counters *cnt);
-/* Sink creation of Sec. 3.1.2 on a single periodic box (state updated in
- * place; out [7][max_new]: x, y, z, m, px, py, pz in cell index order). */
+/* Sink creation of Sec. 3.1.2 on any box layout (state updated in place;
+ * out [7][max_new]: x, y, z, m, px, py, pz in global cell index order). */
 int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf, double r_k,
                     double rho_tr, int64_t max_new, double *out, int64_t *count);
 

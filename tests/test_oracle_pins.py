@@ -888,6 +888,34 @@ def test_sink_create_brute_force_lognormal(orc):
     assert n2 == expect.size and np.array_equal(s2, st.reshape(-1))
 
 
+def test_sink_create_multibox_equals_single_box(orc):
+    """Creation after a fixed-point step with sinks, on a 2 x 2 x 1 tiling and
+    on one box covering the same domain: the same new sinks (global cell
+    order) and the same state."""
+    pts = [(6.0, 5.0, 3.5), (12.6, 13.4, 7.9), (0.3, 0.4, 0.5)]
+    mb = W.multibox([6, 7], [5, 9], [8], ghost=2, positions_sink=pts, seed=8)
+    g = to_global(mb, mb.state)
+    domain, lo, n = W.single_box(13, 14, 8)
+    order = np.lexsort((mb.sinks.fields["z"], mb.sinks.fields["y"], mb.sinks.fields["x"]))
+    f = {k: np.ascontiguousarray(v[order]) for k, v in mb.sinks.fields.items()}
+    sb = dataclasses.replace(mb, lo=lo, n=n, state=g.reshape(-1),
+                             sinks=W.Particles(f, np.array([0, len(order)], dtype=np.int64)))
+    rho_tr, r_k = float(np.exp(1.0)), 1.5
+    res = []
+    for w in (mb, sb):
+        out = orc.step(w, "fix64")
+        st = out["state"].copy()
+        nn, rec = orc.sink_create(w, "fix64", st, out["buf_fold"], r_k, rho_tr, 256)
+        # without the removal channel no cell is excluded
+        nfree, _ = orc.sink_create(w, "fix64", out["state"].copy(), None, r_k, rho_tr, 256)
+        res.append((nn, rec, st, nfree))
+    (n1, o1, s1, f1), (n2, o2, s2, f2) = res
+    assert n1 == n2 and n1 > 5
+    assert np.array_equal(o1[:, :n1], o2[:, :n2])
+    assert np.array_equal(to_global(mb, s1), s2.reshape(5, 8, 14, 13))
+    assert f1 == f2 > n1
+
+
 # ------------------------------------------------------------ C1 totals (P10)
 
 @pytest.mark.parametrize("mode", ["f64", "fix64"])
