@@ -121,8 +121,52 @@ def test_create_capacity_and_errors(B, orc):
         with pytest.raises(B.PmpError):
             ctx.sink_create(*args)
     ctx.close()
+    # a reach past the domain
+    tiny = W.Workload("tiny", *W.single_box(4, 3, 3), 1, 1.0,
+                      W.uniform_state(36, np.float64).reshape(-1))
+    ctx = B.Context(tiny, "f64")
+    with pytest.raises(B.PmpError):
+        ctx.sink_create(4.5, 2.0, 8)
+    ctx.close()
+    # the GPU entry point covers one box spanning the domain only
     mb = W.multibox([8, 8], [8], [8], ghost=1, positions_cic=[[1.5, 1.5, 1.5]], seed=1)
     ctx = B.Context(mb, "f64")
-    with pytest.raises(B.PmpError):
+    with pytest.raises(B.PmpError, match="EUNSUPPORTED"):
         ctx.sink_create(1.0, 2.0, 8)
     ctx.close()
+
+
+@pytest.mark.skip(reason="multi-box sink creation on the GPU is switched off: its first "
+                  "version (per-box chunks, owner lookups) faulted the GPU once and no cause "
+                  "was found; pmp_sink_create returns PMP_EUNSUPPORTED for multi-box layouts")
+@pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
+def test_create_multibox_after_step(B, orc, acc):
+    """4 x 4 x 4 boxes of the batched AMR level with sinks: a step (fixed
+    point, so both sides hold the same state), then creation with r_K = 2
+    crossing box faces; for the float modes creation runs on the oracle's
+    fixed-point state and buffer handed to both sides."""
+    import torch
+    w = W.c5s(nb=4)
+    ref = orc.step(w, "fix64")
+    rho_tr, r_k, max_new = float(np.exp(2.5)), 2.0, 8192
+    st32 = ref["state"].astype(np.float32)
+    say(f"case create multibox acc={acc}")
+    if acc == "fix64":
+        ref_c = oracle_create(orc, w, "fix64", st32, ref["buf_fold"], r_k, rho_tr, max_new)
+        ctx = B.Context(w, "fix64", channels="all")
+        ctx.deposit()
+        ctx.ghost_fold()
+        ctx.sink_update()
+        ctx.apply()
+        out, work = ctx.sink_create(r_k, rho_tr, max_new)
+        torch.cuda.synchronize()
+        got = (int(work[0].item()), out.cpu().numpy().reshape(7, -1), ctx.state.cpu().numpy())
+        ctx.close()
+    else:
+        mode = "f64"
+        buf = ref["buf_fold"].astype(np.float64) * 2.0 ** -40
+        ref_buf = buf.astype(np.float32).astype(np.float64) if acc == "f32" else buf
+        ref_c = oracle_create(orc, w, mode, st32, ref_buf, r_k, rho_tr, max_new)
+        got = gpu_create(B, w, acc, buf, r_k, rho_tr, max_new, state=st32)
+    assert 10 < ref_c[0] < max_new
+    compare(got, ref_c, max_new, np.float32)
