@@ -215,7 +215,7 @@ typedef struct {
                             The buffer's interior cells are left unwritten. */
   int32_t count_lanes;   /* binned path: lanes counting one supernova's sphere
                             members (its candidate rows dealt round them):
-                            1, 2, 4 or 8 */
+                            1, 2, 4, 8 or 16 */
 } pmp_tuning;
 
 /* Create a context on the current HIP device.  Copies the layout, checks the

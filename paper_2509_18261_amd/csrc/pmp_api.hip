@@ -1463,8 +1463,9 @@ int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
   if (t->chunk_cic < 64 || t->chunk_cic > (1 << 24)) return fail(PMP_EINVAL, "chunk_cic 64..2^24");
   if (t->chunk_sn < 16 || t->chunk_sn > (1 << 24)) return fail(PMP_EINVAL, "chunk_sn 16..2^24");
   if (t->fuse_apply != 0 && t->fuse_apply != 1) return fail(PMP_EINVAL, "fuse_apply 0 or 1");
-  if (t->count_lanes != 1 && t->count_lanes != 2 && t->count_lanes != 4 && t->count_lanes != 8)
-    return fail(PMP_EINVAL, "count_lanes 1, 2, 4 or 8");
+  if (t->count_lanes != 1 && t->count_lanes != 2 && t->count_lanes != 4 && t->count_lanes != 8 &&
+      t->count_lanes != 16)
+    return fail(PMP_EINVAL, "count_lanes 1, 2, 4, 8 or 16");
   {
     const long long lds =
         tile_lds_bytes(t->tile_x, t->tile_yz, c->ghost, c->acc == PMP_ACC_F64R);
@@ -1585,7 +1586,7 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
     if (has_sn) {
       // lanes per supernova in the member count (large spheres want more)
       const pmp_tuning w3 = best_t;
-      for (int lanes : {1, 2, 8}) {
+      for (int lanes : {1, 2, 4, 8, 16}) {
         if (lanes == w3.count_lanes) continue;
         pmp_tuning t = w3;
         t.count_lanes = lanes;

@@ -2320,6 +2320,7 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
       case 1: hipLaunchKernelGGL(k_sn_count<1>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk); break;
       case 2: hipLaunchKernelGGL(k_sn_count<2>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk); break;
       case 8: hipLaunchKernelGGL(k_sn_count<8>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk); break;
+      case 16: hipLaunchKernelGGL(k_sn_count<16>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk); break;
       default: hipLaunchKernelGGL(k_sn_count<4>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk);
     }
   }

@@ -221,6 +221,9 @@ SHAPES = [
     {"deposit_path": 1, "chunk_cic": 64, "chunk_sn": 16},
     {"deposit_path": 1, "tile_x": 16, "tile_yz": 2, "chunk_cic": 64, "chunk_sn": 16,
      "tile_grid_per_cu": 1},
+    # lanes per supernova in the member count
+    {"deposit_path": 1, "count_lanes": 1},
+    {"deposit_path": 1, "count_lanes": 16},
 ]
 
 
