@@ -602,8 +602,51 @@ __device__ __forceinline__ int particle_box(const long long* off, int nbox, long
   return lo;
 }
 
+// One workgroup of kSinkBlock threads per sink.  Reductions over the
+// workgroup: each wavefront reduces its lanes, then the wavefront results are
+// combined in wavefront order (a fixed order, also for floats).  Every thread
+// of the workgroup must call them (they synchronise).
+constexpr int kSinkBlock = 256;
+
+template <class T>
+__device__ __forceinline__ T block_sum(T v) {
+  __shared__ T red[kSinkBlock / kWave];
+  v = group_sum<kWave>(v);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  T t = red[0];
+#pragma unroll
+  for (int w = 1; w < kSinkBlock / kWave; ++w) t += red[w];
+  return t;
+}
+
+__device__ __forceinline__ int block_min(int v) {
+  __shared__ int red[kSinkBlock / kWave];
+  v = group_min<kWave>(v);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  int t = red[0];
+#pragma unroll
+  for (int w = 1; w < kSinkBlock / kWave; ++w) t = min(t, red[w]);
+  return t;
+}
+
+__device__ __forceinline__ int block_max(int v) {
+  __shared__ int red[kSinkBlock / kWave];
+  v = group_max<kWave>(v);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  int t = red[0];
+#pragma unroll
+  for (int w = 1; w < kSinkBlock / kWave; ++w) t = max(t, red[w]);
+  return t;
+}
+
 // Bondi-Hoyle request of one sink (Sec. 3.1.1, eqs. "rbh" and "mdot", and the
-// clamp of r_acc), computed by every lane of the sink's wavefront.  Over the
+// clamp of r_acc), computed by every thread of the sink's workgroup.  Over the
 // kernel cells, on the 2^-40 grid: gas mass sum rho V, momentum sum p V and
 // sum rho V c_s with c_s^2 = gamma (gamma - 1) e_int / rho (e_int = E -
 // |p|^2/(2 rho), negative values as 0; c_s = 0 where rho <= 0), and the cell
@@ -618,7 +661,7 @@ __device__ void bondi_request(const Mesh& M, const S* __restrict__ state, const 
                               double& racc) {
   const double r2 = K.r_k * K.r_k;
   long long qn = 0, qm = 0, qx = 0, qy = 0, qz = 0, qc = 0;
-  for (int t = threadIdx.x; t < total; t += kWave) {
+  for (int t = threadIdx.x; t < total; t += kSinkBlock) {
     const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
     const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
     const double d2 = dist2(x, y, z, i, j, k);
@@ -650,12 +693,12 @@ __device__ void bondi_request(const Mesh& M, const S* __restrict__ state, const 
     qm += a0; qx += a1; qy += a2; qz += a3; qc += a4;
     ++qn;
   }
-  qn = group_sum<kWave>(qn);
-  qm = group_sum<kWave>(qm);
-  qx = group_sum<kWave>(qx);
-  qy = group_sum<kWave>(qy);
-  qz = group_sum<kWave>(qz);
-  qc = group_sum<kWave>(qc);
+  qn = block_sum(qn);
+  qm = block_sum(qm);
+  qx = block_sum(qx);
+  qy = block_sum(qy);
+  qz = block_sum(qz);
+  qc = block_sum(qc);
   const double half = 0.5 * K.r_k;
   const double Mk = (double)qm * kFixInv;
   req = 0.0;
@@ -681,7 +724,7 @@ __device__ void bondi_request(const Mesh& M, const S* __restrict__ state, const 
   racc = (rc < 0.25) ? 0.25 : ((rc > half) ? half : rc);
 }
 
-// Sink removal request (Sec. 3.1.1).  One wavefront per sink.  The request is
+// Sink removal request (Sec. 3.1.1).  One workgroup per sink.  The request is
 // the fraction a of the kernel gas mass with the fixed width r_gauss, or the
 // Bondi-Hoyle request of bondi_request with its own width r_acc.  Pass 1 sums
 // the Gaussian weights w = exp(-d^2/r_acc^2) (eq. "kernel") and the kernel gas
@@ -692,7 +735,7 @@ __device__ void bondi_request(const Mesh& M, const S* __restrict__ state, const 
 // reads go to the box that owns each (periodically wrapped) cell.  scratch
 // receives W, M_req and r_acc^2 per sink.
 template <int ACC, class S>
-__global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
+__global__ __launch_bounds__(kSinkBlock) void k_sink_deposit(Mesh M, Particles P,
                                                      const S* __restrict__ state,
                                                      typename AccT<ACC>::T* __restrict__ buf,
                                                      double* __restrict__ scratch, SinkParams K,
@@ -728,7 +771,7 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
       bondi_request<S>(M, state, K, s, x, y, z, lo, cx, cxy, total, ok, reach_bad, Mbondi, racc);
     const double g2 = racc * racc;
     long long wq = 0, mq = 0;
-    for (int t = lane; t < total; t += kWave) {
+    for (int t = lane; t < total; t += kSinkBlock) {
       const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
       const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
       const double d2 = dist2(x, y, z, i, j, k);
@@ -745,8 +788,8 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
       wq += q1;
       mq += q2;
     }
-    wq = group_sum<kWave>(wq);
-    mq = group_sum<kWave>(mq);
+    wq = block_sum(wq);
+    mq = block_sum(mq);
     if (!ok) raise_flag(M.status, PMP_FLAG_OVERFLOW);
     if (reach_bad) raise_flag(M.status, PMP_FLAG_REACH);
     if (wq <= 0) {
@@ -761,7 +804,7 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
     T* f5 = buf + B.boff + M.slot[5] * B.npad;
     long long qreq = 0;
     int first = 0x7fffffff, hostm = 0;
-    for (int t = lane; t < total; t += kWave) {
+    for (int t = lane; t < total; t += kSinkBlock) {
       const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
       const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
       const double d2 = dist2(x, y, z, i, j, k);
@@ -796,9 +839,9 @@ __global__ __launch_bounds__(64) void k_sink_deposit(Mesh M, Particles P,
     }
     if (reach_bad) raise_flag(M.status, PMP_FLAG_REACH);
     if constexpr (FIXED) {
-      qreq = group_sum<kWave>(qreq);
-      first = group_min<kWave>(first);
-      hostm = group_max<kWave>(hostm);
+      qreq = block_sum(qreq);
+      first = block_min(first);
+      hostm = block_max(hostm);
       if (lane == 0) {
         long long Q;
         if (ok && quantise(Mreq / M.V, Q)) {
@@ -844,10 +887,10 @@ __global__ __launch_bounds__(256) void k_truncate_bounds(double* __restrict__ bu
 // Step 4 (Sec. 2.2): each sink re-evaluates its removal over its kernel and
 // gains sum eta k V (mass) and sum eta k V p/rho (momentum), eta = Kl/K from
 // the folded buffer and the state before Step 5; W, the request and r_acc^2
-// come from Step 1's scratch.  One wavefront per sink; fixed point sums each
+// come from Step 1's scratch.  One workgroup per sink; fixed point sums each
 // term on the 2^-40 grid.
 template <int ACC, class S>
-__global__ __launch_bounds__(64) void k_sink_update(Mesh M, Particles P,
+__global__ __launch_bounds__(kSinkBlock) void k_sink_update(Mesh M, Particles P,
                                                     const S* __restrict__ state,
                                                     const typename AccT<ACC>::T* __restrict__ buf,
                                                     const double* __restrict__ scratch,
@@ -874,7 +917,7 @@ __global__ __launch_bounds__(64) void k_sink_update(Mesh M, Particles P,
       const int cx = hi[0] - lo[0] + 1, cy = hi[1] - lo[1] + 1;
       const int cxy = cx * cy;
       const int total = cxy * (hi[2] - lo[2] + 1);
-      for (int t = lane; t < total; t += kWave) {
+      for (int t = lane; t < total; t += kSinkBlock) {
         const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
         const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
         const double d2 = dist2(x, y, z, i, j, k);
@@ -913,19 +956,19 @@ __global__ __launch_bounds__(64) void k_sink_update(Mesh M, Particles P,
       }
     }
     if constexpr (FIXED) {
-      qm = group_sum<kWave>(qm);
-      qx = group_sum<kWave>(qx);
-      qy = group_sum<kWave>(qy);
-      qz = group_sum<kWave>(qz);
+      qm = block_sum(qm);
+      qx = block_sum(qx);
+      qy = block_sum(qy);
+      qz = block_sum(qz);
       sm = (double)qm * kFixInv;
       sx = (double)qx * kFixInv;
       sy = (double)qy * kFixInv;
       sz = (double)qz * kFixInv;
     } else {
-      sm = group_sum<kWave>(sm);
-      sx = group_sum<kWave>(sx);
-      sy = group_sum<kWave>(sy);
-      sz = group_sum<kWave>(sz);
+      sm = block_sum(sm);
+      sx = block_sum(sx);
+      sy = block_sum(sy);
+      sz = block_sum(sz);
     }
     if (!ok) raise_flag(M.status, PMP_FLAG_OVERFLOW);
     if (reach_bad) raise_flag(M.status, PMP_FLAG_REACH);
@@ -2458,7 +2501,7 @@ static void sink_dep(const Mesh& M, const Particles& P, const void* state, void*
                      double* scratch, const SinkParams& K, double rho_tr, double* bound,
                      hipStream_t s) {
   const int grid = grid_for(P.n, 1, 65536);
-  hipLaunchKernelGGL((k_sink_deposit<ACC, S>), dim3(grid), dim3(64), 0, s, M, P,
+  hipLaunchKernelGGL((k_sink_deposit<ACC, S>), dim3(grid), dim3(kSinkBlock), 0, s, M, P,
                      (const S*)state, (typename AccT<ACC>::T*)buf, scratch, K, rho_tr, bound);
 }
 
@@ -2501,7 +2544,7 @@ static void sink_upd(const Mesh& M, const Particles& P, const void* state, const
                      const double* scratch, double r_k, const Limits& L, double* dm,
                      double* dpx, double* dpy, double* dpz, hipStream_t s) {
   const int grid = grid_for(P.n, 1, 65536);
-  hipLaunchKernelGGL((k_sink_update<ACC, S>), dim3(grid), dim3(64), 0, s, M, P,
+  hipLaunchKernelGGL((k_sink_update<ACC, S>), dim3(grid), dim3(kSinkBlock), 0, s, M, P,
                      (const S*)state, (const typename AccT<ACC>::T*)buf, scratch, r_k, L, dm,
                      dpx, dpy, dpz);
 }
