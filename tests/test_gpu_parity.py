@@ -325,16 +325,27 @@ def test_geometry_errors(B):
     ctx.close()
 
 
-def test_graph_replays_match_eager(B):
-    """A captured 3-step graph equals 3 eager steps, on every replay, with
-    eager work and synchronisation between replays."""
+GRAPH_CASES = {
+    "c2_32": lambda: W.c2(nx=32),
+    "c3bh_32": lambda: W.c3bh(nx=32, n_cic=2000, n_sink=24),
+    "c5s_4": lambda: W.c5s(nb=4),
+}
+
+
+@pytest.mark.parametrize("name", list(GRAPH_CASES))
+def test_graph_replays_match_eager(B, name):
+    """A captured 3-step graph equals 3 eager steps (state and, with sinks,
+    the last step's sink gains), on every replay, with eager work and
+    synchronisation between replays."""
     import torch
-    w = W.c2(nx=32)
+    w = GRAPH_CASES[name]()
+    say(f"case graph {name}")
     eager = B.Context(w, "fix64")
     for _ in range(3):
         eager.step()
     torch.cuda.synchronize()
     ref = eager.state.cpu().numpy()
+    ref_sink = None if eager.sink_out is None else eager.sink_out.cpu().numpy()
     g = B.Context(w, "fix64")
     g.graph_build(3)
     for rep in range(3):
@@ -343,6 +354,8 @@ def test_graph_replays_match_eager(B):
         g.graph_launch()
         torch.cuda.synchronize()
         assert np.array_equal(g.state.cpu().numpy(), ref), f"replay {rep}"
+        if ref_sink is not None:
+            assert np.array_equal(g.sink_out.cpu().numpy(), ref_sink), f"replay {rep} sinks"
         eager.reset_state()
         eager.step()
         torch.cuda.synchronize()
