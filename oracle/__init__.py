@@ -92,7 +92,8 @@ def _sinks(w):
 
 class _Limits(C.Structure):
     _fields_ = [("rho_floor", C.c_double), ("rho_tr", C.c_double), ("cap", C.c_double),
-                ("eint_mode", C.c_int32)]
+                ("eint_mode", C.c_int32), ("truelove_J", C.c_double), ("G", C.c_double),
+                ("gamma", C.c_double)]
 
 
 class Counters(C.Structure):
@@ -126,7 +127,7 @@ def lib():
         L.orc_fold.argtypes = [vp, i32, vp]
         L.orc_sink_update.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_apply.argtypes = [vp, i32, vp, vp, vp, vp, vp]
-        L.orc_sink_create.argtypes = [vp, i32, vp, vp, C.c_double, C.c_double, C.c_int64, vp, vp]
+        L.orc_sink_create.argtypes = [vp, i32, vp, vp, vp, C.c_double, vp, C.c_int64, vp, vp]
         _lib = L
     return _lib
 
@@ -188,7 +189,9 @@ def _kind(P, names, struct):
 
 
 def _limits(L):
-    return _Limits(float(L.rho_floor), float(L.rho_tr), float(L.cap), int(L.eint_mode))
+    return _Limits(float(L.rho_floor), float(L.rho_tr), float(L.cap), int(L.eint_mode),
+                   float(getattr(L, "truelove_J", 0.0)), float(getattr(L, "G", 1.0)),
+                   float(getattr(L, "gamma", 5.0 / 3.0)))
 
 
 def deposit(w, mode, mesh=None, state64=None, want_racc=False):
@@ -274,17 +277,33 @@ def apply(w, mode, buf, mesh=None, state64=None, want_eta=False):
     return st, eta, cnt.as_dict()
 
 
-def sink_create(w, mode, state64, buf, r_k, rho_tr, max_new, mesh=None):
-    """Sink creation (Sec. 3.1.2) on a single periodic box, after a step.
+def sink_create(w, mode, state64, buf, r_k, rho_tr, max_new, mesh=None, limits=None,
+                existing=None):
+    """Sink creation (Sec. 3.1.2) on any box layout, after a step.
     ``state64`` (float64, packed) is updated in place; ``buf`` is the folded
-    buffer in the mode's type, or None.  Returns (count, out[7][max_new])."""
+    buffer in the mode's type, or None.  The Truelove density is the
+    constant ``rho_tr``, or per cell from ``limits`` (a Limits with
+    truelove_J > 0; its rho_tr is then unused).  ``existing``: a particle kind
+    (fields x, y, z and box_off) of the sinks already present, or None.
+    Returns (count, out[7][max_new])."""
     mesh = mesh or Mesh.of(w)
     out = np.zeros((7, max(int(max_new), 1)))
     cnt = C.c_int64(0)
     b = None if buf is None else np.ascontiguousarray(buf)
+    if limits is None:
+        lim = _Limits(float(w.limits.rho_floor), float(rho_tr), float(w.limits.cap),
+                      int(w.limits.eint_mode), 0.0, 1.0, 5.0 / 3.0)
+    else:
+        lim = _limits(limits)
+    ex, keep = (None, [])
+    if existing is not None and existing.n > 0:
+        ex, keep = _kind(existing, ["x", "y", "z", "x"], _Cic)
+        sk = _Sinks(ex.x, ex.y, ex.z, ex.m, ex.box_off, float(r_k), 1.0, None, None, None,
+                    None, RATE_FRACTION, 0.0, 0.0, 1.0, 0.0)
+        ex = sk
     rc = lib().orc_sink_create(C.byref(mesh.c), MODES[mode], _ptr(state64), _ptr(b),
-                               float(r_k), float(rho_tr), int(max_new), _ptr(out),
-                               C.byref(cnt))
+                               C.byref(ex) if ex is not None else None, float(r_k),
+                               C.byref(lim), int(max_new), _ptr(out), C.byref(cnt))
     _check(rc, "sink_create")
     return int(cnt.value), out[:, :int(max_new)]
 

@@ -408,6 +408,45 @@ static int bondi_request(const orc_mesh *M, const geom *G, const orc_sinks *S, i
   return ORC_OK;
 }
 
+#define ORC_PI 3.141592653589793
+
+/* Truelove density of one cell (Sec. 3.1.1, eq. "truelove"): the caller's
+ * constant rho_tr, or with truelove_J > 0 the cell's own
+ * rho_Tr = J^2 pi c_s^2 / (G dx^2), the sound speed from the cell's state as
+ * in the Bondi-Hoyle rate, c_s^2 = gamma (gamma - 1) e_int / rho with
+ * e_int = E - |p|^2 / (2 rho) taken as 0 where negative, and c_s = 0 where
+ * rho <= 0. */
+static double truelove_rho(const orc_limits *L, double dx, double rho, double px, double py,
+                           double pz, double E) {
+  if (!(L->truelove_J > 0.0)) return L->rho_tr;
+  double c2 = 0.0;
+  if (rho > 0.0) {
+    double eint = E - ((px * px + py * py) + pz * pz) / (2.0 * rho);
+    if (!(eint > 0.0)) eint = 0.0;
+    c2 = ((L->gamma * (L->gamma - 1.0)) * eint) / rho;
+  }
+  return (((L->truelove_J * L->truelove_J) * ORC_PI) * c2) / ((L->G * dx) * dx);
+}
+
+/* The Truelove density of the cell whose field-0 state element is i0 in a
+ * box of `step` cells per field. */
+static double truelove_at(const orc_limits *L, double dx, const double *state, int64_t i0,
+                          int64_t step) {
+  return truelove_rho(L, dx, state[i0], state[i0 + step], state[i0 + 2 * step],
+                      state[i0 + 3 * step], state[i0 + 4 * step]);
+}
+
+/* Limiter parameters: a per-cell Truelove density needs G > 0 and a finite
+ * gamma >= 1. */
+static int check_limits(const orc_limits *L) {
+  if (L->rho_tr != L->rho_tr) return ORC_EINVAL;
+  if (L->truelove_J > 0.0 &&
+      (!(L->G > 0.0) || !isfinite(L->G) || !(L->gamma >= 1.0) || !isfinite(L->gamma) ||
+       !isfinite(L->truelove_J)))
+    return ORC_EINVAL;
+  return ORC_OK;
+}
+
 /* Sink removal request (Sec. 3.1.1).  Per sink: Gaussian weights
  * w = exp(-d^2/r_acc^2) over the kernel (eq. "kernel"), normalised by their
  * sum (eq. "kernel_wgt"); the requested mass is either a fixed fraction a of
@@ -471,10 +510,11 @@ static int deposit_sinks(const orc_mesh *M, const geom *G, int mode, const orc_s
             if (i == h[0] && j == h[1] && k == h[2]) host_member = 1;
             int64_t iw, jw, kw;
             int ob = owner_of(M, G, i, j, k, &iw, &jw, &kw);
-            double rho = state[state_index(M, G, ob, 0, iw, jw, kw)];
+            int64_t i0 = state_index(M, G, ob, 0, iw, jw, kw);
+            double rho = state[i0];
             double w = orc_exp(-(d2 / g2));
             double kreq = (Mreq * w) / (W * V);
-            double tr = rho - L->rho_tr;
+            double tr = rho - truelove_at(L, M->dx, state, i0, box_cells(M, ob));
             double kc = (tr > kreq) ? tr : kreq;
             int64_t idx = buf_index(M, G, b, 5, i, j, k);
             if (idx < 0) return ORC_EREACH;
@@ -549,6 +589,7 @@ static int deposit_all(const orc_mesh *M, int mode, const orc_cic *cic, const or
   if (sk && (M->nfield != 6 || !state || !L || !sink_w || !sink_mreq || !sink_racc))
     return ORC_EINVAL;
   if (sk && (rc = check_sinks(sk))) return rc;
+  if (sk && (rc = check_limits(L))) return rc;
   geom G;
   rc = geom_build(M, &G, sk != NULL);
   if (rc) return rc;
@@ -637,12 +678,13 @@ int orc_fold(const orc_mesh *M, int mode, void *buf) {
 /* ------------------------------------------------------- Step 3: limiters */
 
 /* Removal limiter of Sec. 3.1.1: a cell loses at most cap*rho unless the
- * Truelove condition asks for more, and never falls below rho_floor.
+ * Truelove condition (the cell's Truelove density rho_tr) asks for more, and
+ * never falls below rho_floor.
  * Returns the limited removal Kl for a requested removal K >= 0. */
-static double limited_removal(double K, double rho, const orc_limits *L) {
+static double limited_removal(double K, double rho, double rho_tr, const orc_limits *L) {
   if (!(K > 0.0)) return 0.0;
   double capped = (K < L->cap * rho) ? K : L->cap * rho;
-  double tr = rho - L->rho_tr;
+  double tr = rho - rho_tr;
   double lim = (capped > tr) ? capped : tr;
   double room = rho - L->rho_floor;
   if (room < 0.0) room = 0.0;
@@ -666,7 +708,7 @@ int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void
                     double *dpy, double *dpz) {
   int rc = check_mesh(M);
   if (rc) return rc;
-  if (M->nfield != 6) return ORC_EINVAL;
+  if (M->nfield != 6 || !L || check_limits(L)) return ORC_EINVAL;
   geom G;
   rc = geom_build(M, &G, 1);
   if (rc) return rc;
@@ -692,13 +734,15 @@ int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void
               if (!(d2 <= r2)) continue;
               int64_t iw, jw, kw;
               int ob = owner_of(M, &G, i, j, k, &iw, &jw, &kw);
-              double rho = state[state_index(M, &G, ob, 0, iw, jw, kw)];
+              int64_t i0 = state_index(M, &G, ob, 0, iw, jw, kw);
+              double rho = state[i0];
               double w = orc_exp(-(d2 / g2));
               double kreq = (Mreq * w) / (W * V);
-              double tr = rho - L->rho_tr;
+              double rtr = truelove_at(L, M->dx, state, i0, box_cells(M, ob));
+              double tr = rho - rtr;
               double kc = (tr > kreq) ? tr : kreq;
               double K = buf_value(mode, buf, buf_index(M, &G, ob, 5, iw, jw, kw));
-              double Kl = limited_removal(K, rho, L);
+              double Kl = limited_removal(K, rho, rtr, L);
               double eta = (K > 0.0) ? Kl / K : 1.0;
               double term = (eta * kc) * V;
               double vx = state[state_index(M, &G, ob, 1, iw, jw, kw)] / rho;
@@ -754,6 +798,7 @@ int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
               const orc_limits *L, double *eta, orc_counters *cnt) {
   int rc = check_mesh(M);
   if (rc) return rc;
+  if (!L || check_limits(L)) return ORC_EINVAL;
   geom G;
   rc = geom_build(M, &G, 0);
   if (rc) return rc;
@@ -777,7 +822,9 @@ int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
           double DE = buf_value(mode, buf, buf_index(M, &G, b, 4, gi, gj, gk));
           double K = 0.0;
           if (M->nfield == 6) K = buf_value(mode, buf, buf_index(M, &G, b, 5, gi, gj, gk));
-          double Kl = limited_removal(K, rho, L);
+          double Kl = 0.0;
+          if (K > 0.0)
+            Kl = limited_removal(K, rho, truelove_rho(L, M->dx, rho, px, py, pz, E), L);
           double et = (K > 0.0) ? Kl / K : 1.0;
           if (K > 0.0) {
             C.touched++;
@@ -832,31 +879,53 @@ int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
 
 /* ------------------------------------------------------ sink creation */
 
+/* Whether cell (i, j, k) lies within r of the sink at (x, y, z): the kernel
+ * membership test (squared distance between the cell centre and the sink,
+ * summed in x, y, z order, <= r^2) on the cell's periodic images one domain
+ * length away along each axis, so that it matches the stencil a kernel
+ * near a domain face enumerates. */
+static int within_kernel(const orc_mesh *M, double x, double y, double z, int64_t i, int64_t j,
+                         int64_t k, double r2) {
+  for (int c = -1; c <= 1; ++c)
+    for (int b = -1; b <= 1; ++b)
+      for (int a = -1; a <= 1; ++a)
+        if (dist2(x, y, z, i + a * (int64_t)M->domain[0], j + b * (int64_t)M->domain[1],
+                  k + c * (int64_t)M->domain[2]) <= r2)
+          return 1;
+  return 0;
+}
+
 /* Sink creation (Sec. 3.1.2).  A cell c of the periodic domain, owned by
  * some box, becomes a sink when
- *   (1) rho_c > rho_Tr (the Truelove density of eq. "truelove"),
+ *   (1) rho_c > rho_Tr,c (its Truelove density, eq. "truelove": the
+ *       limiter's constant, or the cell's own with truelove_J > 0),
  *   (2) c is the densest cell among those whose centres lie within r_K of
  *       its centre (the cell itself included; cells no box owns are left
  *       out; equal densities are ranked by the global linear cell index, the
  *       lower index counting as denser), and
- *   (3) the folded removal channel K is zero at c, that is no sink kernel
- *       reaches c (the paper's test for another sink within r_K).
+ *   (3) no existing sink lies within r_K of c's centre (the kernel
+ *       membership test, periodic), and, where a buffer with the removal
+ *       channel K is given, K is zero at c (the paper's form of the same
+ *       test: a cell in no sink's kernel receives no removal).
  * Every test reads the state as it was before any creation, so the result
  * does not depend on the order of the cells.  A new sink sits at the cell
- * centre with mass (rho_c - rho_Tr) V and momentum (mass) p_c / rho_c; the
- * cell keeps its velocity and specific energy: rho -> rho_Tr,
- * p -> (p / rho) rho_Tr, E -> (E / rho) rho_Tr.  The sinks are listed in
- * increasing global linear cell index (x fastest) in out [7][max_new] (x, y,
- * z, m, px, py, pz); *count receives the number of qualifying cells, and
- * when it exceeds max_new nothing is created.  buf may be NULL, or a buffer
- * without the K channel (nfield 5): then no cell is excluded by (3). */
-int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf, double r_k,
-                    double rho_tr, int64_t max_new, double *out, int64_t *count) {
+ * centre with mass (rho_c - rho_Tr,c) V and momentum (mass) p_c / rho_c; the
+ * cell keeps its velocity and specific energy: rho -> rho_Tr,c,
+ * p -> (p / rho) rho_Tr,c, E -> (E / rho) rho_Tr,c (specific energies, and so
+ * the per-cell rho_Tr, do not change).  The sinks are listed in increasing
+ * global linear cell index (x fastest) in out [7][max_new] (x, y, z, m, px,
+ * py, pz); *count receives the number of qualifying cells, and when it
+ * exceeds max_new nothing is created.  buf may be NULL, or a buffer without
+ * the K channel (nfield 5); existing may be NULL (no sinks). */
+int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf,
+                    const orc_sinks *existing, double r_k, const orc_limits *L,
+                    int64_t max_new, double *out, int64_t *count) {
   int rc = check_mesh(M);
   if (rc) return rc;
-  if (!state || !count || max_new < 0 || (max_new > 0 && !out)) return ORC_EINVAL;
-  if (!(r_k >= 0.0) || !(r_k <= 16.0) || rho_tr != rho_tr) return ORC_EINVAL;
+  if (!state || !count || !L || max_new < 0 || (max_new > 0 && !out)) return ORC_EINVAL;
+  if (!(r_k >= 0.0) || !(r_k <= 16.0) || check_limits(L)) return ORC_EINVAL;
   if (mode != ORC_F64 && mode != ORC_FIX64) return ORC_EINVAL;
+  const int64_t nsink = existing ? existing->box_off[M->nbox] : 0;
   geom G;
   rc = geom_build(M, &G, 1);
   if (rc) return rc;
@@ -878,11 +947,16 @@ int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf,
         int64_t iw, jw, kw;
         const int ob = owner_of(M, &G, i, j, k, &iw, &jw, &kw);
         if (ob < 0) continue;
-        const double rho = state[state_index(M, &G, ob, 0, iw, jw, kw)];
-        if (!(rho > rho_tr)) continue;
+        const int64_t i0 = state_index(M, &G, ob, 0, iw, jw, kw);
+        const double rho = state[i0];
+        if (!(rho > truelove_at(L, M->dx, state, i0, box_cells(M, ob)))) continue;
         if (buf && M->nfield == 6 &&
             buf_value(mode, buf, buf_index(M, &G, ob, 5, iw, jw, kw)) != 0.0)
           continue;
+        int near = 0;
+        for (int64_t s = 0; s < nsink && !near; ++s)
+          near = within_kernel(M, existing->x[s], existing->y[s], existing->z[s], i, j, k, r2);
+        if (near) continue;
         int densest = 1;
         for (int64_t dk = -R; dk <= R && densest; ++dk)
           for (int64_t dj = -R; dj <= R && densest; ++dj)
@@ -908,7 +982,8 @@ int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf,
       const int64_t i0 = state_index(M, &G, ob, 0, iw, jw, kw);
       const int64_t step = box_cells(M, ob);
       const double rho = state[i0];
-      const double m = (rho - rho_tr) * V;
+      const double rtr = truelove_at(L, M->dx, state, i0, step);
+      const double m = (rho - rtr) * V;
       out[0 * max_new + s] = (double)i + 0.5;
       out[1 * max_new + s] = (double)j + 0.5;
       out[2 * max_new + s] = (double)k + 0.5;
@@ -916,10 +991,10 @@ int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf,
       for (int a = 0; a < 3; ++a) {
         const double v = state[i0 + (1 + a) * step] / rho;
         out[(4 + a) * max_new + s] = m * v;
-        state[i0 + (1 + a) * step] = v * rho_tr;
+        state[i0 + (1 + a) * step] = v * rtr;
       }
-      state[i0 + 4 * step] = (state[i0 + 4 * step] / rho) * rho_tr;
-      state[i0] = rho_tr;
+      state[i0 + 4 * step] = (state[i0 + 4 * step] / rho) * rtr;
+      state[i0] = rtr;
     }
   }
   free(made);

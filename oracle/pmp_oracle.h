@@ -86,7 +86,14 @@ typedef struct {
   double G, dt, gamma, lambda;      /* gravity constant, time step, adiabatic
                                        index of the gas, the BHL lambda */
 } orc_sinks;
-typedef struct { double rho_floor, rho_tr, cap; int32_t eint_mode; } orc_limits;
+/* Limiter parameters.  rho_tr is the Truelove density as a constant; with
+ * truelove_J > 0 each cell has its own, J^2 pi c_s^2 / (G dx^2) (Sec. 3.1.1,
+ * eq. "truelove"), c_s from the cell's state as in the Bondi-Hoyle rate. */
+typedef struct {
+  double rho_floor, rho_tr, cap;
+  int32_t eint_mode;
+  double truelove_J, G, gamma;
+} orc_limits;
 typedef struct {
   int64_t touched;   /* cells with K > 0 */
   int64_t bind;      /* cells where the removal limiter binds (Kl < K) */
@@ -116,9 +123,12 @@ int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void
 int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
               const orc_limits *L, double *eta, orc_counters *cnt);
 /* Sink creation of Sec. 3.1.2 on any box layout (state updated in place;
- * out [7][max_new]: x, y, z, m, px, py, pz in global cell index order). */
-int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf, double r_k,
-                    double rho_tr, int64_t max_new, double *out, int64_t *count);
+ * out [7][max_new]: x, y, z, m, px, py, pz in global cell index order).
+ * existing: the sinks already present (positions and box_off only; may be
+ * NULL); L: the Truelove density (constant or per cell). */
+int orc_sink_create(const orc_mesh *M, int mode, double *state, const void *buf,
+                    const orc_sinks *existing, double r_k, const orc_limits *L,
+                    int64_t max_new, double *out, int64_t *count);
 
 #ifdef __cplusplus
 }

@@ -37,6 +37,12 @@ class Limits:
     rho_tr: float = math.inf   # Truelove density; +inf disables it
     cap: float = 0.25          # largest removed fraction of a cell's mass per step
     eint_mode: int = 0         # 0: e_int >= 0, 1: specific e_int may not drop
+    # truelove_J > 0: each cell's Truelove density from its own sound speed
+    # (Jeans number J, gravitational constant G, adiabatic index gamma);
+    # rho_tr is then unused
+    truelove_J: float = 0.0
+    G: float = 1.0
+    gamma: float = 5.0 / 3.0
 
 
 @dataclasses.dataclass
