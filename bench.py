@@ -1,15 +1,19 @@
 #!/usr/bin/env python3
 """Throughput of the particle-mesh-particle hot path on one MI355X.
 
-One step = Step 1 (zero the buffer, CIC and supernova deposits with atomic
-adds), Step 2 (ghost fold), Steps 3 + 5 (limiter + apply), run through the
-C-ABI of libpmp.so on the 256^3 periodic workload: log-normal gas in FP32,
-1e6 uniform CIC particles, 1e5 uniform supernovae of radius 4 cells, ghost
-width 4.  Inputs are resident in HBM before timing starts.  Prints one JSON
-line.
+One step = Step 1 (CIC and supernova deposits into a zeroed, ghost-zoned
+buffer), Step 2 (ghost fold), Steps 3 + 5 (limiter + apply), run through the
+C-ABI of libpmp.so.  Default workload: the 512^3 periodic box (log-normal
+gas, 4e6 particles, half uniform and half in 32 Plummer clumps, CIC:SN 10:1,
+supernova radius 3, ghost width 4) with FP64 state and FP64 buffer; inputs
+are resident in HBM before timing starts.  Also reported: the FP32 and
+fixed-point modes, the plain FP64 path (direct atomics, nothing fused), the
+atomic and copy peaks, the 4096-box batched level against per-box launches,
+and the serial oracle on the host.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--acc f32|f64|fix64]
+  python bench.py [--steps K] [--warmup W] [--acc f32|f64|fix64] [--state f32|f64]
                   [--workload c2|c3|c3bh|c4|c5|c5s] [--no-cpu] [--no-modes]
+                  [--no-calib] [--no-c5]
 """
 from __future__ import annotations
 
@@ -37,79 +41,92 @@ def acc_bytes(acc):
     return 4 if acc == "f32" else 8
 
 
-def algorithmic_bytes(w, acc, counts, F, fused=False):
-    """Bytes per launch each phase must move at minimum (no scratch, no
-    re-reads): buffer writes for the zero fill, particle records plus a
-    read-modify-write of every touched (cell, field) for deposits, the owned
-    shell and its ghost images for the fold, and for apply the buffer in, the
-    five state fields in and rho and E out (the momentum is written back only
-    where a sink removes mass: no kind deposits momentum).  F = buffer
-    channels of the timed layout.  fused: the step applies the interior cells
-    (owned, at least g from every face) in the tile pass, which stores the
-    buffer only for the other cells, and the shell cells are folded and
-    applied in one pass."""
+def _shape(w):
     import numpy as np
-    ba = acc_bytes(acc)
-    bs = np.dtype(w.state.dtype).itemsize
     n = w.n.astype(np.int64)
     g = w.ghost
     owned = int(np.prod(n, axis=1).sum())
     padded = int(np.prod(n + 2 * g, axis=1).sum())
-    ghost_cells = padded - owned
-    inner = np.maximum(n - 2 * g, 0)
-    shell = owned - int(np.prod(inner, axis=1).sum())
-    parts = 0
-    if w.cic is not None:
-        parts += w.cic.n * 32
-    if w.sn is not None:
-        parts += w.sn.n * 48
     interior = int(np.prod(np.maximum(n - 2 * g, 0), axis=1).sum())
-    st = 7 * bs  # per applied cell: 5 fields in, rho and E out
-    removed = counts.get("sink", 0) if w.sinks is not None else 0  # cells with a removal
+    return owned, padded, interior
+
+
+def record_bytes(w):
+    """Particle records read: CIC x, y, z, m (32 B); supernova x, y, z, m, e,
+    r (48 B); sink x, y, z, a (32 B)."""
+    return sum(P.n * nb for P, nb in ((w.cic, 32), (w.sn, 48), (w.sinks, 32)) if P is not None)
+
+
+def method_bytes(w, acc, counts, F):
+    """The method's own HBM bytes per step (Sec. 2.2 Steps 1-5 as written,
+    every phase separate, only the F buffer channels the particle kinds
+    deposit into; no binning or scratch traffic, nothing fused):
+      zero      F b_acc per padded cell;
+      records   per particle (record_bytes);
+      deposit   2 b_acc per unique touched (cell, channel) (read-modify-write);
+      sinks     5 b_state per sink-kernel cell (the state the request reads);
+      fold      3 b_acc per ghost cell and channel (ghost in, owner in/out);
+      apply     per owned cell 5 b_state in (the energy limiter needs |p|^2),
+                rho and E out (2 b_state) and the F channels in; the momentum
+                out (3 b_state) only in cells a sink removes from (no kind
+                deposits momentum, so elsewhere it does not change);
+      sink update: 64 B per sink (record, gains out) and per kernel cell
+                4 b_state (rho, p) + b_acc (K).
+    """
+    import numpy as np
+    ba = acc_bytes(acc)
+    bs = np.dtype(w.state.dtype).itemsize
+    owned, padded, _ = _shape(w)
+    ks = counts.get("sink", 0)
+    touched = counts.get("cic", 0) + counts.get("sn", 0) + ks
     out = {
         "zero": padded * F * ba,
-        # binned path: every buffer cell stored once plus the particle records
-        "tile": padded * F * ba + parts,
+        "records": record_bytes(w),
+        "deposit": 2 * ba * touched + 5 * bs * ks,
+        "fold": 3 * ba * F * (padded - owned),
+        "apply": owned * (7 * bs + F * ba) + 3 * bs * ks,
+        "sink_update": (w.sinks.n * 64 + ks * (4 * bs + ba)) if w.sinks is not None else 0,
+    }
+    out["total"] = sum(out.values())
+    return out
+
+
+def kernel_method_bytes(w, acc, counts, F, fused):
+    """The method's bytes that each kernel of the timed step carries (the
+    terms of method_bytes assigned to the kernel that does that work).
+    Binned path: the tile pass does the zero fill, reads the records and
+    performs every deposit read-modify-write (in LDS; counted as the method's
+    HBM bytes all the same); fused (no sinks), it also applies the interior
+    cells (owned, at least g from every face), and the shell kernel folds and
+    applies the rest.  Direct path: zero fill, CIC and supernova atomics,
+    fold, apply, one kernel each."""
+    import numpy as np
+    ba = acc_bytes(acc)
+    bs = np.dtype(w.state.dtype).itemsize
+    owned, padded, interior = _shape(w)
+    cell_apply = 7 * bs + F * ba
+    dep = 2 * ba * (counts.get("cic", 0) + counts.get("sn", 0))
+    out = {
+        "tile": padded * F * ba + record_bytes(w) - (w.sinks.n * 32 if w.sinks else 0) + dep,
+        "zero": padded * F * ba,
+        "fold": 3 * ba * F * (padded - owned),
+        "apply": owned * cell_apply + 3 * bs * counts.get("sink", 0),
         "bin": 0,
-        "fold": F * ba * (2 * shell + ghost_cells),
-        "apply": owned * (st + F * ba) + 3 * bs * removed,
     }
     if fused:
-        # tile: buffer for the non-interior cells, records, interior state in/out
-        out["tile"] = (padded - interior) * F * ba + parts + interior * st
-        # fold: shell values and their ghost images in, shell state in/out
-        out["fold"] = F * ba * (shell + ghost_cells) + shell * st
+        out["tile"] = (padded - interior) * F * ba + record_bytes(w) + dep + \
+            interior * cell_apply
+        out["fold"] = 3 * ba * F * (padded - owned) + (owned - interior) * cell_apply
         out["apply"] = 0
     if w.cic is not None and w.cic.n:
         out["cic"] = w.cic.n * 32 + 2 * ba * counts["cic"]
     if w.sn is not None and w.sn.n:
         out["sn"] = w.sn.n * 48 + 2 * ba * counts["sn"]
     if w.sinks is not None and w.sinks.n:
-        out["sink_deposit"] = w.sinks.n * 32 + 2 * ba * counts["sink"] + bs * counts["sink"]
-        out["sink_update"] = w.sinks.n * 64 + counts["sink"] * (4 * bs + ba)
+        ks = counts["sink"]
+        out["sink_deposit"] = w.sinks.n * 32 + 2 * ba * ks + 5 * bs * ks
+        out["sink_update"] = w.sinks.n * 64 + ks * (4 * bs + ba)
     return out
-
-
-def nominal_step_bytes(w, acc, counts):
-    """The method's nominal bytes per step, counted as if every phase ran
-    separately with the full channel set (5 fields, 6 with sinks): zero fill,
-    particle records, a read-modify-write of every touched (cell, field), the
-    sinks' state reads, three accesses per ghost cell and field for the fold,
-    and state in/out plus buffer in for the apply.  A yardstick for the whole
-    step; the fused path moves far fewer bytes than this."""
-    import numpy as np
-    ba = acc_bytes(acc)
-    bs = np.dtype(w.state.dtype).itemsize
-    n = w.n.astype(np.int64)
-    g = w.ghost
-    owned = int(np.prod(n, axis=1).sum())
-    padded = int(np.prod(n + 2 * g, axis=1).sum())
-    F = 6 if (w.sinks is not None and w.sinks.n) else 5
-    parts = (w.cic.n * 32 if w.cic is not None else 0) + (w.sn.n * 48 if w.sn is not None else 0) + \
-        (w.sinks.n * 32 if w.sinks is not None else 0)
-    touched = counts.get("cic", 0) + counts.get("sn", 0) + counts.get("sink", 0)
-    return (padded * F * ba + parts + 2 * ba * touched + 5 * bs * counts.get("sink", 0)
-            + 3 * ba * F * (padded - owned) + owned * F * (2 * bs + ba))
 
 
 def touched_counts(B, w, acc):
@@ -226,23 +243,56 @@ def sink_create_rate(B, w, acc, channels, reps=10):
             "kernels": "k_create_find+k_create_rank+k_create_apply"}
 
 
-def stream_copy_gbps(B, nbytes=1 << 30, reps=10):
+def copy_gbps(B, nbytes=1 << 30, reps=10):
+    """Device copy bandwidth (bytes read + written per second) of the
+    library's two copy kernels and the runtime's hipMemcpyAsync."""
     import torch
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    B.stream_copy(b, a)
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(reps):
-        B.stream_copy(b, a)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / reps
+    out = {}
+    for variant, name in ((0, "k_copy"), (1, "k_copy4"), (2, "hipMemcpyAsync")):
+        B.copy_bench(b, a, variant)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            B.copy_bench(b, a, variant)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        out[name] = round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
     del a, b
     torch.cuda.empty_cache()
-    return 2 * nbytes / (ms * 1e-3) / 1e9, ms
+    return out
+
+
+def atomic_rates(B, slots_log2=26, reps=3):
+    """Global-atomic throughput (adds per second) measured by the library's
+    microbenchmark: int64, f32 and f64 adds on coalesced and scattered
+    distinct addresses (2^26 elements) and on one contended address."""
+    import torch
+    out = {}
+    dt = {"int64": torch.int64, "f32": torch.float32, "f64": torch.float64}
+    for tname, tdt in dt.items():
+        buf = torch.zeros(1 << slots_log2, dtype=tdt, device="cuda")
+        out[tname] = {}
+        for pat, n_ops in (("coalesced", 1 << 28), ("scattered", 1 << 28),
+                           ("same_address", 1 << 22)):
+            B.atomic_bench(buf, tname, pat, n_ops)
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(reps):
+                B.atomic_bench(buf, tname, pat, n_ops)
+            t1.record()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / reps
+            out[tname][pat] = n_ops / (ms * 1e-3)
+        del buf
+        torch.cuda.empty_cache()
+    return out
 
 
 def traffic_for(workload, kernel):
@@ -328,27 +378,138 @@ def repro_rates(B, w, channels):
     return out
 
 
-def cpu_baseline(w, n_particles, target_s=10.0):
+def cpu_baseline(w, n_particles):
+    """One full serial FP64 step of the oracle on the headline workload (the
+    oracle as it stands, single-threaded: deposit, fold, limiter + apply)."""
     import oracle
-    ncores = 1
-    times = []
-    t_start = time.perf_counter()
-    while True:
-        times.append(oracle.timed_step(w, "f64"))
-        if time.perf_counter() - t_start >= target_s or len(times) >= 5:
-            break
-    t = min(times)
+    t = oracle.timed_step(w, "f64")
     cpu = platform.processor() or "unknown"
     try:
         with open("/proc/cpuinfo") as f:
             cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
-    return {"value": n_particles / t, "unit": "particles/s", "cores": ncores, "kind": "oracle",
+    return {"value": n_particles / t, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "host_cpu": cpu, "host_cpus_visible": os.cpu_count(),
-            "sample": f"{len(times)} full serial FP64 oracle steps of the same workload "
-                      f"(deposit, fold, apply; {t:.2f} s each, best taken)",
+            "sample": f"one full serial FP64 oracle step of the same workload ({w.name}: "
+                      f"deposit, fold, limiter + apply; {t:.2f} s)",
             "cells_per_s": w.owned_cells / t, "s_per_step": t}
+
+
+def sn_contributions(w):
+    """Supernova (cell, channel) contributions of one step, counted on the
+    host from the sphere membership test (cell centre within r, inclusive):
+    two channels (rho, E) per member cell."""
+    import numpy as np
+    if w.sn is None or w.sn.n == 0:
+        return 0
+    total = 0
+    f = w.sn.fields
+    for s0 in range(0, w.sn.n, 1 << 16):
+        x, y, z, r = (f[k][s0:s0 + (1 << 16)] for k in ("x", "y", "z", "r"))
+        r2 = r * r
+        span = int(np.ceil(r.max())) * 2 + 2
+        cnt = np.zeros(x.size, dtype=np.int64)
+        lo = [np.ceil(p - r - 0.5 - 1e-6).astype(np.int64) for p in (x, y, z)]
+        for dk in range(span):
+            ddz = (lo[2] + dk + 0.5) - z
+            for dj in range(span):
+                ddy = (lo[1] + dj + 0.5) - y
+                for di in range(span):
+                    ddx = (lo[0] + di + 0.5) - x
+                    cnt += ((ddx * ddx + ddy * ddy) + ddz * ddz) <= r2
+        total += int(cnt.sum())
+    return 2 * total
+
+
+def tuned_context(B, w, acc, channels, overrides=None, autotune_on=True):
+    ctx = B.Context(w, acc, channels=channels)
+    tuned = None
+    if autotune_on and not overrides:
+        from paper_2509_18261_amd import autotune
+        cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+        tuned = autotune.tune(ctx, cache_path=cache)
+    if overrides:
+        ctx.set_tuning(**overrides)
+    return ctx, tuned
+
+
+def measure(ctx, steps, warmup):
+    """Headline timing: the step replayed from a captured one-step HIP graph;
+    eager launches and the per-kernel profile (HIP events around every
+    kernel, on the stream it runs on) in passes of their own."""
+    eager_ms, _ = run_steps(ctx, steps, warmup, profile=False)
+    spread = {}
+    ms = run_graph(ctx, steps, warmup, spread)
+    _, phases = run_steps(ctx, steps, 2, profile=True)
+    return ms, eager_ms, spread, phases, ctx.status()
+
+
+KERNELS = {"bin": "k_sn_count+k_l1_*+k_scan_*+k_l2_*+k_units", "tile": "k_tile_deposit",
+           "zero": "k_zero", "cic": "k_cic_direct", "sn": "k_sn_direct",
+           "sink_deposit": "k_sink_deposit", "fold": "k_fold", "sink_update": "k_sink_update",
+           "apply": "k_apply"}
+
+
+def phase_table(phases, kbytes):
+    out = {}
+    for name in PHASE_ORDER:
+        if name not in phases:
+            continue
+        tot_ms, nl = phases[name]
+        avg = tot_ms / nl
+        b = kbytes.get(name, 0)
+        out[name] = {"avg_ms": round(avg, 5), "launches": nl, "method_bytes": int(b),
+                     "GBps": round(b / (avg * 1e-3) / 1e9, 1) if avg > 0 else None}
+    return out
+
+
+def is_fused(tun, w, nparts):
+    return bool(tun.get("fuse_apply", 0)) and tun.get("deposit_path", 0) == 1 and \
+        (w.sinks is None or w.sinks.n == 0) and nparts > 0
+
+
+def run_mode(B, w, acc, counts_acc, args, overrides=None, autotune_on=True, steps=None):
+    """A timed run of one (state, accumulator) mode: ms per step (graph),
+    the per-kernel table and the step's method bytes."""
+    import torch
+    nparts = sum(P.n for P in (w.cic, w.sn, w.sinks) if P is not None)
+    ctx, tuned = tuned_context(B, w, acc, args.channels, overrides, autotune_on)
+    nchan = len(ctx.fields)
+    ms, eager_ms, spread, phases, st = measure(ctx, steps or args.steps, args.warmup)
+    tun = ctx.tuning().as_dict()
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    fused = is_fused(tun, w, nparts)
+    mb = method_bytes(w, acc, counts_acc, nchan)
+    table = phase_table(phases, kernel_method_bytes(w, acc, counts_acc, nchan, fused))
+    return {"ms_per_step": ms, "eager_ms_per_step": eager_ms, "spread": spread,
+            "particles_per_s": nparts / (ms * 1e-3), "cells_per_s": w.owned_cells / (ms * 1e-3),
+            "state": str(w.state.dtype), "acc": acc, "tuning": tun, "autotune": tuned,
+            "fused_apply": fused, "buffer_channels": nchan, "phases": table,
+            "step_method_bytes": mb["total"],
+            "step_method_frac": mb["total"] / (ms * 1e-3) / (HBM_PEAK_GBPS * 1e9),
+            "status_flags": st["flag_names"]}
+
+
+def c5_batched(B, args):
+    """The batched AMR level (4096 uneven boxes, FP32): the step replayed
+    from a graph of 10 steps, autotuned, against the per-box launch form."""
+    import torch
+    from paper_2509_18261_amd import workloads as W
+    w = W.c5()
+    ctx, tuned = tuned_context(B, w, "f32", args.channels)
+    eager_ms, _ = run_steps(ctx, 5, 2, profile=False)
+    res = batched_comparison(ctx, args, eager_ms)
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    nparts = w.cic.n + w.sn.n
+    res.update({"workload": w.name, "acc": "f32", "state": "float32", "particles": nparts,
+                "particles_per_s_graph": nparts / (res["graph_ms_per_step"] * 1e-3),
+                "autotune": tuned})
+    return res
 
 
 def main():
@@ -356,11 +517,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2")
-    ap.add_argument("--acc", default="f32", choices=["f32", "f64", "fix64"])
+    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--acc", default="f64", choices=["f32", "f64", "fix64"])
+    ap.add_argument("--state", default="f64", choices=["f32", "f64"],
+                    help="gas state type (the workload's FP32 draw, promoted for f64)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--no-calib", action="store_true")
+    ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--set", default="", help="tuning overrides, e.g. deposit_path=0,tile_x=32")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the library's autotuner (default: tune, cached per shape)")
@@ -381,67 +545,42 @@ def main():
     from paper_2509_18261_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    log(f"bench: workload {args.workload}, acc {args.acc}, steps {args.steps}")
-    w = W.CONFIGS[args.workload]()
+    log(f"bench: workload {args.workload}, state {args.state}, acc {args.acc}, "
+        f"steps {args.steps}")
+    w32 = W.CONFIGS[args.workload]()
+    w = w32.with_state(w32.state.astype(np.float64)) if args.state == "f64" else w32
     nparts = sum(P.n for P in (w.cic, w.sn, w.sinks) if P is not None)
     counts = touched_counts(B, w, args.acc)
-    log("touched (cell, field) pairs:", counts)
+    log("touched (cell, channel) pairs:", counts)
     overrides = {}
     for kv in filter(None, args.set.split(",")):
         k, v = kv.split("=")
         overrides[k.strip()] = int(v)
-    ctx = B.Context(w, args.acc, channels=args.channels)
-    nchan = len(ctx.fields)
-    log(f"buffer channels {ctx.fields}")
-    tuned = None
-    if not args.no_autotune and not overrides:
-        from paper_2509_18261_amd import autotune
-        cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
-        tuned = autotune.tune(ctx, cache_path=cache)
-        log(f"autotune: {tuned}")
-    if overrides:
-        ctx.set_tuning(**overrides)
-    # headline: the step replayed from a captured HIP graph; eager launches
-    # and the per-phase profile (events between phases) in runs of their own
-    eager_ms, _ = run_steps(ctx, args.steps, args.warmup, profile=False)
-    spread = {}
-    ms = run_graph(ctx, args.steps, args.warmup, spread)
-    _, phases = run_steps(ctx, args.steps, 2, profile=True)
-    st = ctx.status()
-    log(f"step {ms:.4f} ms (graph), {eager_ms:.4f} ms (eager); status {st}")
-    tun = ctx.tuning().as_dict()
+
+    head = run_mode(B, w, args.acc, counts, args, overrides, not args.no_autotune)
+    ms = head["ms_per_step"]
+    log(f"step {ms:.4f} ms (graph), {head['eager_ms_per_step']:.4f} ms (eager); "
+        f"flags {head['status_flags']}")
     batched = None
     if w.nbox > 1 and (w.sinks is None or w.sinks.n == 0):
-        # the per-box launch form has no sinks, so it is compared only without them
-        batched = batched_comparison(ctx, args, eager_ms)
-    ctx.close()
-    del ctx
-    torch.cuda.empty_cache()
+        ctx, _ = tuned_context(B, w, args.acc, args.channels, overrides, not args.no_autotune)
+        batched = batched_comparison(ctx, args, head["eager_ms_per_step"])
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
 
-    fused = bool(tun.get("fuse_apply", 0)) and tun.get("deposit_path", 0) == 1 and \
-        (w.sinks is None or w.sinks.n == 0) and nparts > 0
-    algo = algorithmic_bytes(w, args.acc, counts, nchan, fused)
-    per_phase = {}
-    for name in PHASE_ORDER:
-        if name not in phases:
-            continue
-        tot_ms, nl = phases[name]
-        avg = tot_ms / nl
-        b = algo.get(name, 0)
-        per_phase[name] = {"avg_ms": round(avg, 5), "launches": nl,
-                           "algo_bytes": int(b),
-                           "GBps": round(b / (avg * 1e-3) / 1e9, 1) if avg > 0 else None}
-    # dominant kernel: the longest single kernel that moves algorithmic bytes
-    # (the binning phase is several small launches of scratch traffic)
-    dom = max((k for k in per_phase if per_phase[k]["algo_bytes"] > 0),
+    per_phase = head["phases"]
+    # dominant kernel: the longest single kernel that carries method bytes
+    # (binning is several small launches of scratch traffic)
+    dom = max((k for k in per_phase if per_phase[k]["method_bytes"] > 0),
               key=lambda k: per_phase[k]["avg_ms"])
-    kernel_names = {"bin": "k_sn_count+k_l1_*+k_scan_*+k_l2_*+k_units", "tile": "k_tile_deposit",
-                    "zero": "k_zero", "cic": "k_cic_direct", "sn": "k_sn_direct",
-                    "sink_deposit": "k_sink_deposit", "fold": "k_fold_apply" if fused else "k_fold",
-                    "sink_update": "k_sink_update", "apply": "k_apply"}
     d = per_phase[dom]
-    achieved = d["algo_bytes"] / (d["avg_ms"] * 1e-3) / 1e9
-    step_bytes = sum(algo.get(k, 0) for k in per_phase)
+    achieved = d["method_bytes"] / (d["avg_ms"] * 1e-3) / 1e9
+    kname = KERNELS[dom]
+    if dom == "fold" and head["fused_apply"]:
+        kname = "k_fold_apply"
+    mb = method_bytes(w, args.acc, counts, head["buffer_channels"])
+    step_gbps = mb["total"] / (ms * 1e-3) / 1e9
     out = {
         "metric": "particle-deposits/s and mesh cells applied/s; % HBM roofline vs plain FP64",
         "value": nparts / (ms * 1e-3),
@@ -450,8 +589,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
-        "ms_per_step_spread": {k: round(v, 5) for k, v in spread.items()},
-        "eager_ms_per_step": eager_ms,
+        "ms_per_step_spread": {k: round(v, 5) for k, v in head["spread"].items()},
+        "eager_ms_per_step": head["eager_ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -461,57 +600,85 @@ def main():
                    "cic": w.cic.n if w.cic else 0, "sn": w.sn.n if w.sn else 0,
                    "sinks": w.sinks.n if w.sinks else 0, "ghost": w.ghost,
                    "state": str(np.dtype(w.state.dtype)), "acc": args.acc,
-                   "limiter": "f64", "boxes": w.nbox, "buffer_channels": nchan,
-                   "fused_apply": fused},
+                   "limiter": "f64", "boxes": w.nbox,
+                   "buffer_channels": head["buffer_channels"],
+                   "fused_apply": head["fused_apply"]},
         "cells_per_s": w.owned_cells / (ms * 1e-3),
-        "step_algo_bytes": int(step_bytes),
-        "step_hbm_frac": step_bytes / (ms * 1e-3) / (HBM_PEAK_GBPS * 1e9),
-        # the unfused, full-channel count of the same step (a yardstick, not traffic)
-        "step_nominal_bytes": int(nominal_step_bytes(w, args.acc, counts)),
-        "step_nominal_frac": nominal_step_bytes(w, args.acc, counts) / (ms * 1e-3) /
-                             (HBM_PEAK_GBPS * 1e9),
-        "roofline": {"bound": "hbm", "kernel": kernel_names[dom], "phase": dom,
+        "roofline": {"bound": "hbm", "kernel": kname, "phase": dom,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic_for(args.workload, kernel_names[dom]),
-                     "algo_bytes_per_launch": d["algo_bytes"],
+                     "traffic": traffic_for(args.workload, kname),
+                     "method_bytes_per_launch": d["method_bytes"],
                      "avg_launch_ms": d["avg_ms"]},
+        # the whole step: the method's own bytes (every phase separate, the
+        # deposited channels only) over the step time
+        "step_roofline": {"bound": "hbm", "achieved": round(step_gbps, 1),
+                          "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                          "frac": round(step_gbps / HBM_PEAK_GBPS, 4),
+                          "method_bytes": mb},
         "phases": per_phase,
-        "tuning": tun,
-        "autotune": tuned,
-        "status_flags": st["flag_names"],
+        "tuning": head["tuning"],
+        "autotune": head["autotune"],
+        "status_flags": head["status_flags"],
     }
     if batched is not None:
         out["batched"] = batched
     if w.sinks is not None and w.sinks.n and w.nbox == 1:
         out["sink_create"] = sink_create_rate(B, w, args.acc, args.channels)
         log(f"sink creation: {out['sink_create']}")
-    if not args.no_calib:
-        gbps, cms = stream_copy_gbps(B)
-        out["stream_copy_GBps"] = round(gbps, 1)
-        log(f"stream copy {gbps:.0f} GB/s")
     if not args.no_modes:
         modes = {}
-        for acc, dt in (("fix64", None), ("f64r", None), ("f64", np.float64)):
-            if acc == "f64r" and (overrides or {}).get("deposit_path", 1) != 1:
-                continue  # the reproducibility mode runs on the binned path only
-            wm = w.with_state(w.state.astype(dt)) if dt is not None else w
-            c2 = B.Context(wm, acc, channels=args.channels)
-            if overrides:
-                c2.set_tuning(**overrides)
-            mms = run_graph(c2, max(5, args.steps // 2), 2)
-            c2.close()
-            del c2
-            torch.cuda.empty_cache()
-            modes[acc if dt is None else "f64_plain"] = {
-                "ms_per_step": mms, "particles_per_s": nparts / (mms * 1e-3),
-                "cells_per_s": w.owned_cells / (mms * 1e-3),
-                "state": "f64" if dt is not None else str(np.dtype(w.state.dtype))}
-            log(f"mode {acc}: {mms:.4f} ms/step")
+        for acc, wm in (("f32", w32), ("fix64", w32)):
+            if acc == args.acc and wm is w:
+                continue
+            # the same particles touch the same (cell, channel) pairs in every mode
+            modes[f"{acc}_state_{wm.state.dtype}"] = run_mode(B, wm, acc, counts, args, None,
+                                                              True, max(5, args.steps // 2))
+            log(f"mode {acc}: {modes[f'{acc}_state_{wm.state.dtype}']['ms_per_step']:.4f} ms")
+        if w.sinks is None or w.sinks.n == 0:
+            modes["f64r_state_" + str(w.state.dtype)] = run_mode(
+                B, w, "f64r", counts, args, {"deposit_path": 1}, False, max(5, args.steps // 2))
         out["modes"] = modes
-        out["speedup_vs_plain_f64"] = modes["f64_plain"]["ms_per_step"] / ms
+        # the plain FP64 path: zero fill, direct global atomics, separate
+        # fold and apply, no binning or fusion
+        plain = run_mode(B, w, "f64", counts, args, {"deposit_path": 0, "fuse_apply": 0},
+                         False, max(5, args.steps // 2))
+        out["plain_f64"] = plain
+        out["speedup_vs_plain_f64"] = plain["ms_per_step"] / ms
+        log(f"plain f64: {plain['ms_per_step']:.4f} ms")
         out["reproducibility"] = repro_rates(B, w, args.channels)
         log(f"reproducibility: {out['reproducibility']}")
+    if not args.no_calib:
+        out["copy_GBps"] = copy_gbps(B)
+        log(f"copy: {out['copy_GBps']}")
+        rates = atomic_rates(B)
+        out["atomics_per_s"] = rates
+        log(f"atomics: {rates}")
+        if "plain_f64" in out:
+            ph = out["plain_f64"]["phases"]
+            ach = {}
+            if "cic" in ph and w.cic is not None:
+                n_at = 8 * w.cic.n
+                ach["k_cic_direct"] = {"atomics": n_at,
+                                       "per_s": n_at / (ph["cic"]["avg_ms"] * 1e-3)}
+            if "sn" in ph and w.sn is not None:
+                n_at = sn_contributions(w)
+                ach["k_sn_direct"] = {"atomics": n_at,
+                                      "per_s": n_at / (ph["sn"]["avg_ms"] * 1e-3)}
+            # CIC atomics hit 8 cells in pairs along x (nearly scattered);
+            # supernova atomics run along x rows of the sphere (coalesced runs)
+            for v in ach.values():
+                v["frac_of_scattered_f64_peak"] = v["per_s"] / rates["f64"]["scattered"]
+                v["frac_of_coalesced_f64_peak"] = v["per_s"] / rates["f64"]["coalesced"]
+            out["atomic_roofline"] = {
+                "peaks": "f64 adds measured by pmp_atomic_bench: scattered distinct addresses "
+                         "and wavefront-coalesced consecutive addresses",
+                "scattered_per_s": rates["f64"]["scattered"],
+                "coalesced_per_s": rates["f64"]["coalesced"], "kernels": ach}
+    if not args.no_c5 and args.workload != "c5":
+        out["c5_batched"] = c5_batched(B, args)
+        log(f"c5 batched: graph {out['c5_batched']['graph_ms_per_step']:.3f} ms, per-box "
+            f"{out['c5_batched']['per_box_launch_ms_per_step']:.3f} ms")
     if not args.no_cpu:
         log("cpu baseline (serial oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, nparts)

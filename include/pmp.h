@@ -169,12 +169,22 @@ typedef struct {
                                    paper); G, dt, lambda >= 0 and finite, r_k >= 1/2 */
 } pmp_sinks;
 
-/* Limiter parameters (Sec. 3.1.1 removal limiter, Sec. 3.2.1 eq. "lambda"). */
+/* Limiter parameters (Sec. 3.1.1 removal limiter, Sec. 3.2.1 eq. "lambda").
+ * The Truelove density rho_Tr (Sec. 3.1.1, eq. "truelove") enters the sink
+ * removal k = max(M_req w / (W V), rho - rho_Tr), the removal limiter and
+ * sink creation.  With truelove_J = 0 it is the constant rho_tr; with
+ * truelove_J > 0 every cell has its own,
+ *   rho_Tr = J^2 pi c_s^2 / (G dx^2),  c_s^2 = gamma (gamma - 1) e_int / rho,
+ * e_int = E - |p|^2 / (2 rho) from the cell's state (negative values as 0,
+ * c_s = 0 where rho <= 0), and rho_tr is ignored (J = 1/4 in the paper). */
 typedef struct {
   double rho_floor;   /* density never drops below this by removal */
-  double rho_tr;      /* Truelove density (+inf disables the term) */
+  double rho_tr;      /* constant Truelove density (+inf disables the term) */
   double cap;         /* largest removed fraction per step (0.25 in the paper) */
   int32_t eint_mode;  /* 0: e_int >= 0; 1: specific e_int may not drop */
+  double truelove_J;  /* 0: constant rho_tr; > 0 (finite): per-cell rho_Tr with this J */
+  double G;           /* gravitational constant of the per-cell rho_Tr (> 0, finite) */
+  double gamma;       /* adiabatic index of the per-cell rho_Tr (>= 1, finite) */
 } pmp_limits;
 
 /* Device-side diagnostics accumulated since the last reset. */
@@ -293,30 +303,37 @@ int pmp_sink_update(pmp_ctx *ctx, const void *state, const void *buf, const pmp_
 int pmp_apply(pmp_ctx *ctx, void *state, const void *buf, const pmp_limits *limits,
               double *eta, void *stream);
 
-/* Sink creation (Sec. 3.1.2), after a step: on a single box covering the
- * periodic domain, a cell becomes a sink when rho > rho_tr (the Truelove
- * density of eq. "truelove"), it is the densest cell among those whose
- * centres lie within r_k (cells) of its centre (equal densities ranked by
- * the linear cell index, the lower index counting as denser), and the folded
- * removal channel K of buf is zero there (no existing sink's kernel reaches
- * it; buf may be NULL, or have no K channel: no cell is excluded).  All tests
- * read the state before any creation, so the result does not depend on the
- * order of the cells.  Each new sink sits at its cell centre (cell units)
- * with mass (rho - rho_tr) V and momentum mass * p / rho; the cell keeps its
- * velocity and specific energy (rho -> rho_tr, p -> (p / rho) rho_tr,
- * E -> (E / rho) rho_tr), updated in place in the device state.
+/* Sink creation (Sec. 3.1.2), after a step, on any box layout that tiles the
+ * periodic domain.  A cell becomes a sink when
+ *   (1) rho > rho_Tr, the cell's Truelove density (limits: the constant, or
+ *       the cell's own with truelove_J > 0);
+ *   (2) it is the densest cell among those whose centres lie within r_k
+ *       (cells) of its centre, periodic (equal densities ranked by the
+ *       global linear cell index, x fastest, the lower index counting as
+ *       denser);
+ *   (3) no sink lies within r_k of its centre: none of the existing sinks
+ *       (existing: positions x, y, z and n are read, may be NULL) is at
+ *       squared distance <= r_k^2 from the cell centre or one of its
+ *       periodic images, and, where buf is given with the removal channel,
+ *       the folded removal K is zero there (no kernel reached it).
+ * All tests read the state before any creation, so the result does not
+ * depend on the order of the cells.  Each new sink sits at its cell centre
+ * (global cell units) with mass (rho - rho_Tr) V and momentum mass p / rho;
+ * the cell keeps its velocity and specific energy (rho -> rho_Tr,
+ * p -> (p / rho) rho_Tr, E -> (E / rho) rho_Tr), updated in place in the
+ * device state of the box that owns it.
  *   out   device float64 [7][max_new]: x, y, z, m, px, py, pz of the new
- *         sinks in increasing linear cell index (x fastest);
+ *         sinks in increasing global linear cell index;
  *   work  device int64 [2 max_new + 1], caller-owned scratch; work[0]
  *         receives the number of qualifying cells.  When it exceeds max_new,
  *         nothing is created and state and out are left alone (call again
  *         with a larger list).
  * max_new in [0, 65536], r_k in [0, 16] and floor(r_k) at most every axis
- * length of the domain.  Allocates nothing.  Errors:
- * PMP_EINVAL (arguments), PMP_EUNSUPPORTED (not one box covering the
- * domain). */
-int pmp_sink_create(pmp_ctx *ctx, void *state, const void *buf, double r_k, double rho_tr,
-                    int64_t max_new, double *out, int64_t *work, void *stream);
+ * length of the domain.  Allocates nothing.  Errors: PMP_EINVAL (arguments,
+ * limits), PMP_ERANGE (boxes that leave cells of the domain unowned). */
+int pmp_sink_create(pmp_ctx *ctx, void *state, const void *buf, const pmp_sinks *existing,
+                    double r_k, const pmp_limits *limits, int64_t max_new, double *out,
+                    int64_t *work, void *stream);
 
 /* One whole step: deposit, fold, sink update (if sinks), apply.  sink_out
  * (device) is four float64 arrays [4][sinks->n] (dm, dpx, dpy, dpz) or NULL
@@ -393,6 +410,24 @@ int pmp_profile_end(pmp_ctx *ctx, double *ms, int64_t *launches);
 /* Bandwidth calibration: copy bytes from device src to device dst with a
  * plain streaming kernel (16-byte loads and stores). */
 int pmp_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* Bandwidth calibration variants (measurement support): variant 0 is
+ * pmp_stream_copy; 1 moves groups of 1024 16-byte vectors per 256-thread
+ * workgroup, four coalesced loads per thread before nontemporal stores
+ * (bytes a multiple of 16384, 16-byte aligned pointers); 2 is the runtime's
+ * device-to-device hipMemcpyAsync. */
+int pmp_copy_bench(void *dst, const void *src, size_t bytes, int variant, void *stream);
+
+/* Global-atomic throughput microbenchmark (measurement support: the peak the
+ * atomic deposits are measured against; no part of the method).  Enqueues
+ * one kernel that performs n_ops atomic adds of 1 into the device array dst
+ * of `slots` elements (a power of two): type 0 int64, 1 float, 2 double;
+ * pattern 0 op i -> element i mod slots (each wavefront's 64 ops on
+ * consecutive elements), 1 a multiplicative hash of i mod slots (scattered
+ * addresses), 2 element 0 for every op (all contend for one address).  The
+ * caller times it (events on stream).  PMP_EINVAL on bad arguments. */
+int pmp_atomic_bench(void *dst, int64_t slots, int type, int pattern, int64_t n_ops,
+                     void *stream);
 
 const char *pmp_last_error(void);
 

@@ -70,7 +70,15 @@ class pmp_sinks(C.Structure):
 
 class pmp_limits(C.Structure):
     _fields_ = [("rho_floor", C.c_double), ("rho_tr", C.c_double), ("cap", C.c_double),
-                ("eint_mode", C.c_int32)]
+                ("eint_mode", C.c_int32), ("truelove_J", C.c_double), ("G", C.c_double),
+                ("gamma", C.c_double)]
+
+
+def limits_of(L, rho_tr=None):
+    """pmp_limits from a workloads.Limits (rho_tr overrides its constant)."""
+    return pmp_limits(float(L.rho_floor), float(L.rho_tr if rho_tr is None else rho_tr),
+                      float(L.cap), int(L.eint_mode), float(getattr(L, "truelove_J", 0.0)),
+                      float(getattr(L, "G", 1.0)), float(getattr(L, "gamma", 5.0 / 3.0)))
 
 
 class pmp_status(C.Structure):
@@ -112,7 +120,8 @@ SIGNATURES = [
     ("pmp_sink_update", _I, [_VP, _VP, _VP, C.POINTER(pmp_sinks), C.POINTER(pmp_limits),
                              _VP, _VP, _VP, _VP, _VP]),
     ("pmp_apply", _I, [_VP, _VP, _VP, C.POINTER(pmp_limits), _VP, _VP]),
-    ("pmp_sink_create", _I, [_VP, _VP, _VP, C.c_double, C.c_double, C.c_int64, _VP, _VP, _VP]),
+    ("pmp_sink_create", _I, [_VP, _VP, _VP, C.POINTER(pmp_sinks), C.c_double,
+                             C.POINTER(pmp_limits), C.c_int64, _VP, _VP, _VP]),
     ("pmp_step", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
                       C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP, _VP]),
     ("pmp_step_per_box", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
@@ -129,6 +138,8 @@ SIGNATURES = [
     ("pmp_profile_begin", _I, [_VP, _I]),
     ("pmp_profile_end", _I, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("pmp_stream_copy", _I, [_VP, _VP, C.c_size_t, _VP]),
+    ("pmp_copy_bench", _I, [_VP, _VP, C.c_size_t, _I, _VP]),
+    ("pmp_atomic_bench", _I, [_VP, C.c_int64, _I, _I, C.c_int64, _VP]),
     ("pmp_last_error", C.c_char_p, []),
 ]
 
@@ -206,8 +217,7 @@ class Context:
         self.state = torch.from_numpy(np.ascontiguousarray(w.state)).to(device)
         assert self.state.dtype == tdt
         self.buf = torch.empty(self.buffer_elems, dtype=bdt, device=device)
-        self.lim = pmp_limits(float(w.limits.rho_floor), float(w.limits.rho_tr),
-                              float(w.limits.cap), int(w.limits.eint_mode))
+        self.lim = limits_of(w.limits)
         self._keep = []
         self.cic = self._kind(w.cic, ["x", "y", "z", "m"], pmp_cic)
         self.sn = self._kind(w.sn, ["x", "y", "z", "m", "e", "r"], pmp_sn)
@@ -291,16 +301,42 @@ class Context:
         _call("pmp_apply", self.h, _ptr(self.state), _ptr(self.buf), C.byref(self.lim),
               _ptr(eta), _stream(stream))
 
-    def sink_create(self, r_k, rho_tr, max_new, buf=True, stream=None):
+    def sink_create(self, r_k, rho_tr, max_new, buf=True, limits=None, existing=None,
+                    stream=None):
         """Sink creation after a step (state updated in place).  Returns the
         device arrays (out [7][max_new], work [2 max_new + 1]); work[0] is the
-        number of qualifying cells.  ``buf=False`` passes no buffer."""
+        number of qualifying cells.  ``buf=False`` passes no buffer.  The
+        Truelove density is the constant ``rho_tr``, or comes from ``limits``
+        (a workloads.Limits, per cell when its truelove_J > 0).  ``existing``:
+        "workload" (this workload's sinks), a particle kind with x, y, z, or
+        None."""
         import torch
         out = torch.zeros(7 * max(int(max_new), 1), dtype=torch.float64, device=self.device)
         work = torch.zeros(2 * int(max_new) + 1, dtype=torch.int64, device=self.device)
+        lim = limits_of(self.w.limits, rho_tr) if limits is None else limits_of(limits)
+        ex = self._positions(existing)
         _call("pmp_sink_create", self.h, _ptr(self.state), _ptr(self.buf) if buf else None,
-              float(r_k), float(rho_tr), int(max_new), _ptr(out), _ptr(work), _stream(stream))
+              None if ex is None else C.byref(ex), float(r_k), C.byref(lim), int(max_new),
+              _ptr(out), _ptr(work), _stream(stream))
         return out, work
+
+    def _positions(self, existing):
+        """pmp_sinks holding only the positions of ``existing`` (see sink_create)."""
+        import torch
+        if existing is None:
+            return None
+        if isinstance(existing, str):
+            assert existing == "workload"
+            return self.sinks
+        if existing.n == 0:
+            return None
+        ts = [torch.from_numpy(np.ascontiguousarray(existing.fields[k], dtype=np.float64))
+              .to(self.device) for k in ("x", "y", "z")]
+        self._keep += ts
+        s = pmp_sinks()
+        s.x, s.y, s.z = (C.c_void_p(t.data_ptr()) for t in ts)
+        s.n = existing.n
+        return s
 
     def step(self, stream=None):
         _call("pmp_step", self.h, _ptr(self.state), _ptr(self.buf), self._r(self.cic),
@@ -393,6 +429,21 @@ def channel_bits(w, channels):
 def stream_copy(dst, src, stream=None):
     _call("pmp_stream_copy", _ptr(dst), _ptr(src), dst.numel() * dst.element_size(),
           _stream(stream))
+
+
+def copy_bench(dst, src, variant, stream=None):
+    _call("pmp_copy_bench", _ptr(dst), _ptr(src), dst.numel() * dst.element_size(),
+          int(variant), _stream(stream))
+
+
+ATOMIC_TYPES = {"int64": 0, "f32": 1, "f64": 2}
+ATOMIC_PATTERNS = {"coalesced": 0, "scattered": 1, "same_address": 2}
+
+
+def atomic_bench(dst, type_name, pattern, n_ops, stream=None):
+    """n_ops atomic adds into the tensor dst (its element count a power of two)."""
+    _call("pmp_atomic_bench", _ptr(dst), dst.numel(), ATOMIC_TYPES[type_name],
+          ATOMIC_PATTERNS[pattern], int(n_ops), _stream(stream))
 
 
 def buffer_to_numpy(ctx, t=None):

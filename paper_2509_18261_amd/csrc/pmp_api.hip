@@ -116,6 +116,7 @@ struct pmp_ctx {
   std::vector<HostBox> hboxes;
   std::vector<DevBox> dboxes;
   long long state_elems = 0, buffer_elems = 0, owned_cells = 0, shell_cells = 0;
+  bool tiles_domain = false;  // the boxes (disjoint, inside the domain) own every cell
   int nseg = 0;
   // device allocations
   DevBox* d_boxes = nullptr;
@@ -733,12 +734,16 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
   return rc;
 }
 
-Limits to_limits(const pmp_limits* L) {
+Limits to_limits(const pmp_ctx* c, const pmp_limits* L) {
   Limits l;
   l.rho_floor = L->rho_floor;
   l.rho_tr = L->rho_tr;
   l.cap = L->cap;
   l.eint_mode = L->eint_mode;
+  l.truelove_J = L->truelove_J;
+  l.G = L->G;
+  l.gamma = L->gamma;
+  l.dx = c->dx;
   return l;
 }
 
@@ -749,6 +754,11 @@ int check_limits(const pmp_limits* L) {
                 L->rho_floor, L->rho_tr);
   if (L->eint_mode != 0 && L->eint_mode != 1)
     return fail(PMP_EINVAL, "eint_mode must be 0 or 1");
+  if (std::isnan(L->truelove_J) || !std::isfinite(L->truelove_J))
+    return fail(PMP_EINVAL, "truelove_J must be finite");
+  if (L->truelove_J > 0.0 && (!(L->G > 0.0) || !std::isfinite(L->G) || !(L->gamma >= 1.0) ||
+                              !std::isfinite(L->gamma)))
+    return fail(PMP_EINVAL, "a per-cell Truelove density needs finite G > 0 and gamma >= 1");
   return PMP_OK;
 }
 
@@ -901,7 +911,7 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
       if (fuse_state) {
         const int rc2 = check_limits(limits);
         if (rc2) return rc2;
-        L = to_limits(limits);
+        L = to_limits(c, limits);
       }
       PMP_HIP(launch_tile_deposit(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
                                   buf, c->tune, fuse_state, L, s));
@@ -924,7 +934,7 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
   if (has_sink) {
     PhaseTimer t(c, PMP_PHASE_SINK_DEPOSIT, s);
     PMP_HIP(launch_sink_deposit(M, from_sinks(sinks), state, buf, c->d_sink_scratch,
-                                sink_params(c, sinks), to_limits(limits), c->d_bound, s));
+                                sink_params(c, sinks), to_limits(c, limits), c->d_bound, s));
   }
   return PMP_OK;
 }
@@ -943,7 +953,7 @@ int do_sink_update(pmp_ctx* c, const void* state, const void* buf, const pmp_sin
     return fail(PMP_EINVAL, "sink update before a deposit with these sinks");
   PhaseTimer t(c, PMP_PHASE_SINK_UPDATE, s);
   PMP_HIP(launch_sink_update(c->mesh(), from_sinks(sinks), state, buf, c->d_sink_scratch,
-                             sink_params(c, sinks), to_limits(limits), dm, dpx, dpy, dpz,
+                             sink_params(c, sinks), to_limits(c, limits), dm, dpx, dpy, dpz,
                              s));
   return PMP_OK;
 }
@@ -954,7 +964,7 @@ int do_apply(pmp_ctx* c, void* state, const void* buf, const pmp_limits* limits,
   int rc = check_limits(limits);
   if (rc) return rc;
   PhaseTimer t(c, PMP_PHASE_APPLY, s);
-  PMP_HIP(launch_apply(c->mesh(), state, buf, to_limits(limits), eta, c->tune.block, s));
+  PMP_HIP(launch_apply(c->mesh(), state, buf, to_limits(c, limits), eta, c->tune.block, s));
   return PMP_OK;
 }
 
@@ -974,7 +984,7 @@ int do_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn
   if (fused) {
     // interior cells are done; fold and apply the shell
     PhaseTimer t(c, PMP_PHASE_FOLD, s);
-    PMP_HIP(launch_fold_apply(c->mesh(), state, buf, to_limits(limits), s));
+    PMP_HIP(launch_fold_apply(c->mesh(), state, buf, to_limits(c, limits), s));
     return PMP_OK;
   }
   rc = do_fold(c, buf, s);
@@ -1093,6 +1103,8 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   c->buffer_elems = boff;
   c->owned_cells = owned_prefix[c->nbox];
   c->shell_cells = shell_prefix[c->nbox];
+  c->tiles_domain =
+      c->owned_cells == (long long)c->domain[0] * c->domain[1] * (long long)c->domain[2];
   // overlap check: every box against the boxes its region touches
   {
     BoxIndex idx;
@@ -1273,28 +1285,54 @@ int pmp_apply(pmp_ctx* c, void* state, const void* buf, const pmp_limits* limits
   return do_apply(c, state, buf, limits, eta, (hipStream_t)stream);
 }
 
-int pmp_sink_create(pmp_ctx* c, void* state, const void* buf, double r_k, double rho_tr,
-                    int64_t max_new, double* out, int64_t* work, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks of the sink creation entry point; E receives
+// the existing sinks' positions.
+int create_checks(const pmp_ctx* c, const void* state, const pmp_sinks* existing, double r_k,
+                  const pmp_limits* limits, int64_t max_new, const double* out, SinkPos& E) {
   if (!c) return fail(PMP_EINVAL, "NULL context");
-  if (!state || !work) return fail(PMP_EINVAL, "state and work must be non-NULL");
+  if (!state) return fail(PMP_EINVAL, "state is NULL");
   if (max_new < 0 || max_new > kCreateMax)
     return fail(PMP_EINVAL, "max_new must lie in [0, %lld]", (long long)kCreateMax);
   if (max_new > 0 && !out) return fail(PMP_EINVAL, "out is NULL");
   if (!(r_k >= 0.0) || !(r_k <= 16.0)) return fail(PMP_EINVAL, "r_k must lie in [0, 16]");
-  if (std::isnan(rho_tr)) return fail(PMP_EINVAL, "rho_tr is NaN");
-  if (c->nbox != 1) return fail(PMP_EUNSUPPORTED, "sink creation needs a single-box layout");
-  for (int a = 0; a < 3; ++a)
-    if (c->hboxes[0].lo[a] != 0 || c->hboxes[0].n[a] != c->domain[a])
-      return fail(PMP_EUNSUPPORTED, "sink creation needs the single box to cover the domain");
+  int rc = check_limits(limits);
+  if (rc) return rc;
+  E = SinkPos{};
+  if (existing && existing->n != 0) {
+    if (existing->n < 0) return fail(PMP_EINVAL, "existing sinks: negative count");
+    if (!existing->x || !existing->y || !existing->z)
+      return fail(PMP_EINVAL, "existing sinks: position arrays must be non-NULL");
+    E.x = existing->x;
+    E.y = existing->y;
+    E.z = existing->z;
+    E.n = existing->n;
+  }
+  if (!c->tiles_domain)
+    return fail(PMP_ERANGE, "sink creation needs boxes that tile the periodic domain");
   for (int a = 0; a < 3; ++a)
     if (std::floor(r_k) > c->domain[a])
       return fail(PMP_EINVAL, "r_k = %g reaches past the domain (%d cells along axis %d)", r_k,
                   c->domain[a], a);
-  const Mesh M = c->mesh();
-  PMP_HIP(launch_sink_create(M, state, buf, r_k, rho_tr, (long long)max_new, out,
-                             (long long*)work,
-                             (long long)c->domain[0] * c->domain[1] * c->domain[2],
-                             (hipStream_t)stream));
+  return PMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmp_sink_create(pmp_ctx* c, void* state, const void* buf, const pmp_sinks* existing,
+                    double r_k, const pmp_limits* limits, int64_t max_new, double* out,
+                    int64_t* work, void* stream) {
+  SinkPos E;
+  int rc = create_checks(c, state, existing, r_k, limits, max_new, out, E);
+  if (rc) return rc;
+  if (!work) return fail(PMP_EINVAL, "work is NULL");
+  PMP_HIP(launch_sink_create(c->mesh(), state, buf, E, r_k, to_limits(c, limits),
+                             (long long)max_new, out, (long long*)work, (hipStream_t)stream));
   return PMP_OK;
 }
 
@@ -1320,7 +1358,7 @@ int pmp_step_per_box(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, con
   int rc = check_limits(limits);
   if (rc) return rc;
   const Mesh all = c->mesh();
-  const Limits L = to_limits(limits);
+  const Limits L = to_limits(c, limits);
   const size_t ab = c->acc_bytes();
   // Step 1 for every box, then Step 2 for every box (the fold reads other
   // boxes' ghosts), then Steps 3 + 5 for every box.
@@ -1646,6 +1684,37 @@ int pmp_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
   if (!dst || !src) return fail(PMP_EINVAL, "NULL argument");
   if (bytes % 4) return fail(PMP_EINVAL, "bytes must be a multiple of 4");
   PMP_HIP(launch_copy(dst, src, (long long)bytes, (hipStream_t)stream));
+  return PMP_OK;
+}
+
+int pmp_copy_bench(void* dst, const void* src, size_t bytes, int variant, void* stream) {
+  if (!dst || !src) return fail(PMP_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (variant == 0) {
+    if (bytes % 4) return fail(PMP_EINVAL, "bytes must be a multiple of 4");
+    PMP_HIP(launch_copy(dst, src, (long long)bytes, s));
+  } else if (variant == 1) {
+    if (bytes % 16384 || ((uintptr_t)dst | (uintptr_t)src) % 16)
+      return fail(PMP_EINVAL, "variant 1: bytes a multiple of 16384, 16-byte aligned pointers");
+    PMP_HIP(launch_copy4(dst, src, (long long)bytes, s));
+  } else if (variant == 2) {
+    PMP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+  } else {
+    return fail(PMP_EINVAL, "copy variant must be 0, 1 or 2");
+  }
+  return PMP_OK;
+}
+
+int pmp_atomic_bench(void* dst, int64_t slots, int type, int pattern, int64_t n_ops,
+                     void* stream) {
+  if (!dst) return fail(PMP_EINVAL, "dst is NULL");
+  if (slots < 1 || (slots & (slots - 1)) != 0)
+    return fail(PMP_EINVAL, "slots must be a power of two");
+  if (type < 0 || type > 2 || pattern < 0 || pattern > 2 || n_ops < 0)
+    return fail(PMP_EINVAL, "type and pattern must lie in [0, 2], n_ops >= 0");
+  if (n_ops == 0) return PMP_OK;
+  PMP_HIP(launch_atomic_bench(dst, (long long)slots, type, pattern, (long long)n_ops,
+                              (hipStream_t)stream));
   return PMP_OK;
 }
 

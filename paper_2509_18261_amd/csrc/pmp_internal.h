@@ -49,9 +49,12 @@ struct DevStatus {
   unsigned long long touched, bind, lam, fall;
 };
 
+// Limiter parameters (pmp_limits) and the cell edge.  truelove_J > 0: each
+// cell's Truelove density from its own sound speed (truelove_rho).
 struct Limits {
   double rho_floor, rho_tr, cap;
   int eint_mode;
+  double truelove_J, G, gamma, dx;
 };
 
 // Everything a launch needs about the mesh.
@@ -261,13 +264,22 @@ hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* sta
 // quadratic in the number of new sinks).
 constexpr long long kCreateMax = 65536;
 
-hipError_t launch_sink_create(const Mesh& M, void* state, const void* buf, double r_k,
-                              double rho_tr, long long max_new, double* out, long long* work,
-                              long long ncell, hipStream_t s);
+// Existing sinks of a creation call: positions only (x, y, z device [n]).
+struct SinkPos {
+  const double *x, *y, *z;
+  long long n;
+};
+hipError_t launch_sink_create(const Mesh& M, void* state, const void* buf, const SinkPos& E,
+                              double r_k, const Limits& L, long long max_new, double* out,
+                              long long* work, hipStream_t s);
 hipError_t launch_fold(const Mesh& M, void* buf, int block, hipStream_t s);
 hipError_t launch_apply(const Mesh& M, void* state, const void* buf, const Limits& L,
                         double* eta, int block, hipStream_t s);
 hipError_t launch_clear_status(DevStatus* st, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, long long bytes, hipStream_t s);
+// bytes a multiple of 64, 16-byte aligned
+hipError_t launch_copy4(void* dst, const void* src, long long bytes, hipStream_t s);
+hipError_t launch_atomic_bench(void* dst, long long slots, int type, int pattern,
+                               long long n_ops, hipStream_t s);
 
 }  // namespace pmp

@@ -21,6 +21,7 @@ constexpr double kFix = 0x1p40;         // fixed-point scale (40 fractional bits
 constexpr double kFixInv = 0x1p-40;
 constexpr double kFixLimit = 0x1p62;    // largest accepted magnitude of a scaled value
 constexpr double kFourPi = 0x1.921fb54442d18p+3;  // 4 pi, rounded to double
+constexpr double kPi = 0x1.921fb54442d18p+1;      // pi, rounded to double
 constexpr int kWave = 64;
 
 // ----------------------------------------------------------------- helpers
@@ -378,6 +379,56 @@ __global__ void k_copy(uint4* __restrict__ d, const uint4* __restrict__ s, long 
   if (blockIdx.x == 0 && (int)threadIdx.x < ntail) dt[threadIdx.x] = st[threadIdx.x];
 }
 
+// A second copy variant for the bandwidth calibration: a workgroup of 256
+// threads moves groups of 1024 16-byte vectors, each thread four of them at
+// a stride of 256 vectors (every load instruction coalesced over the
+// wavefront, all four loads issued before the stores), nontemporal stores,
+// grid-stride over the groups.
+__global__ __launch_bounds__(256) void k_copy4(u32x4* __restrict__ d, const u32x4* __restrict__ s,
+                                               long long ngroups) {
+  for (long long gq = blockIdx.x; gq < ngroups; gq += gridDim.x) {
+    const u32x4* src = s + gq * 1024 + threadIdx.x;
+    u32x4 v0 = src[0], v1 = src[256], v2 = src[512], v3 = src[768];
+    u32x4* dst = d + gq * 1024 + threadIdx.x;
+    __builtin_nontemporal_store(v0, dst);
+    __builtin_nontemporal_store(v1, dst + 256);
+    __builtin_nontemporal_store(v2, dst + 512);
+    __builtin_nontemporal_store(v3, dst + 768);
+  }
+}
+
+// Global-atomic throughput microbenchmark: n_ops adds of 1 into dst[slots]
+// (slots a power of two, mask = slots - 1).  pattern 0: op i -> element
+// i & mask (a wavefront's 64 ops on consecutive elements); 1: a
+// multiplicative hash of i, masked (scattered, distinct until the slots
+// wrap); 2: element (i >> 62) & mask, i.e. element 0 for every op (all
+// contend), computed from the lane's own index so that the address is a
+// per-lane vector value like the other patterns'.
+template <class T>
+__device__ __forceinline__ void bench_add(T* p);
+template <>
+__device__ __forceinline__ void bench_add<unsigned long long>(unsigned long long* p) {
+  atomicAdd(p, 1ull);
+}
+template <>
+__device__ __forceinline__ void bench_add<float>(float* p) { unsafeAtomicAdd(p, 1.0f); }
+template <>
+__device__ __forceinline__ void bench_add<double>(double* p) { unsafeAtomicAdd(p, 1.0); }
+
+template <class T>
+__global__ __launch_bounds__(256) void k_atomic_bench(T* __restrict__ dst, unsigned long long mask,
+                                                      int pattern, long long n_ops) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_ops; i += stride) {
+    const unsigned long long u = (unsigned long long)i;
+    unsigned long long e;
+    if (pattern == 0) e = u & mask;
+    else if (pattern == 1) e = ((u * 0x9E3779B97F4A7C15ull) >> 20) & mask;
+    else e = (u >> 62) & mask;
+    bench_add(dst + e);
+  }
+}
+
 __global__ void k_clear_status(DevStatus* st) {
   if (threadIdx.x == 0) {
     st->flags = 0u;
@@ -569,8 +620,8 @@ struct CellLoc {
   long long s;
 };
 
-__device__ __forceinline__ bool locate(const Mesh& M, int i, int j, int k, CellLoc& L) {
-  const int w[3] = {imod(i, M.domain[0]), imod(j, M.domain[1]), imod(k, M.domain[2])};
+// locate for a cell already wrapped into the domain (0 <= w[a] < domain[a]).
+__device__ __forceinline__ bool locate_wrapped(const Mesh& M, const int w[3], CellLoc& L) {
   if (M.own_start == nullptr) {
     L.B = M.all_boxes;
   } else {
@@ -590,6 +641,11 @@ __device__ __forceinline__ bool locate(const Mesh& M, int i, int j, int k, CellL
   for (int a = 0; a < 3; ++a) L.l[a] = w[a] - L.B->lo[a];
   L.s = L.B->soff + ((long long)L.l[2] * L.B->n[1] + L.l[1]) * L.B->n[0] + L.l[0];
   return true;
+}
+
+__device__ __forceinline__ bool locate(const Mesh& M, int i, int j, int k, CellLoc& L) {
+  const int w[3] = {imod(i, M.domain[0]), imod(j, M.domain[1]), imod(k, M.domain[2])};
+  return locate_wrapped(M, w, L);
 }
 
 // Box of sink s: the b with off[b] <= s < off[b + 1] (empty boxes skipped).
@@ -643,6 +699,31 @@ __device__ __forceinline__ int block_max(int v) {
 #pragma unroll
   for (int w = 1; w < kSinkBlock / kWave; ++w) t = max(t, red[w]);
   return t;
+}
+
+// Truelove density of one cell (Sec. 3.1.1, eq. "truelove"): the constant
+// rho_tr, or with truelove_J > 0 the cell's own J^2 pi c_s^2 / (G dx^2), with
+// c_s^2 = gamma (gamma - 1) e_int / rho, e_int = E - |p|^2 / (2 rho) taken as
+// 0 where negative, and c_s = 0 where rho <= 0.
+__device__ __forceinline__ double truelove_rho(const Limits& L, double rho, double px,
+                                               double py, double pz, double E) {
+  if (!(L.truelove_J > 0.0)) return L.rho_tr;
+  double c2 = 0.0;
+  if (rho > 0.0) {
+    double eint = E - ((px * px + py * py) + pz * pz) / (2.0 * rho);
+    if (!(eint > 0.0)) eint = 0.0;
+    c2 = ((L.gamma * (L.gamma - 1.0)) * eint) / rho;
+  }
+  return (((L.truelove_J * L.truelove_J) * kPi) * c2) / ((L.G * L.dx) * L.dx);
+}
+
+// The Truelove density of the cell whose rho is st[0] (the other state
+// fields at multiples of stride); reads only rho's field for a constant.
+template <class S>
+__device__ __forceinline__ double truelove_at(const Limits& L, const S* st, long long stride) {
+  if (!(L.truelove_J > 0.0)) return L.rho_tr;
+  return truelove_rho(L, (double)st[0], (double)st[stride], (double)st[2 * stride],
+                      (double)st[3 * stride], (double)st[4 * stride]);
 }
 
 // Bondi-Hoyle request of one sink (Sec. 3.1.1, eqs. "rbh" and "mdot", and the
@@ -739,7 +820,7 @@ __global__ __launch_bounds__(kSinkBlock) void k_sink_deposit(Mesh M, Particles P
                                                      const S* __restrict__ state,
                                                      typename AccT<ACC>::T* __restrict__ buf,
                                                      double* __restrict__ scratch, SinkParams K,
-                                                     double rho_tr, double* __restrict__ bound) {
+                                                     Limits L, double* __restrict__ bound) {
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
   const int lane = threadIdx.x;
   const int g = M.ghost;
@@ -819,7 +900,7 @@ __global__ __launch_bounds__(kSinkBlock) void k_sink_deposit(Mesh M, Particles P
       const double rho = (double)state[Lc.s];
       const double w = kernel_exp(-(d2 / g2));
       const double kreq = (Mreq * w) / (W * M.V);
-      const double tr = rho - rho_tr;
+      const double tr = rho - truelove_at(L, state + Lc.s, Lc.B->ncell);
       const double kc = (tr > kreq) ? tr : kreq;
       long long idx;
       if (!pad_index(B, g, i, j, k, idx)) { reach_bad = true; continue; }
@@ -861,11 +942,13 @@ __global__ __launch_bounds__(kSinkBlock) void k_sink_deposit(Mesh M, Particles P
 }
 
 // Removal limiter of Sec. 3.1.1: at most cap * rho unless the Truelove
-// condition asks for more, and never below rho_floor.
-__device__ __forceinline__ double limited_removal(double K, double rho, const Limits& L) {
+// condition (the cell's Truelove density rho_tr) asks for more, and never
+// below rho_floor.
+__device__ __forceinline__ double limited_removal(double K, double rho, double rho_tr,
+                                                  const Limits& L) {
   if (!(K > 0.0)) return 0.0;
   const double capped = (K < L.cap * rho) ? K : L.cap * rho;
-  const double tr = rho - L.rho_tr;
+  const double tr = rho - rho_tr;
   const double lim = (capped > tr) ? capped : tr;
   double room = rho - L.rho_floor;
   if (room < 0.0) room = 0.0;
@@ -931,12 +1014,13 @@ __global__ __launch_bounds__(kSinkBlock) void k_sink_update(Mesh M, Particles P,
         const double rho = (double)state[Lc.s];
         const double w = kernel_exp(-(d2 / g2));
         const double kreq = (Mreq * w) / (W * M.V);
-        const double tr = rho - L.rho_tr;
+        const double rtr = truelove_at(L, state + Lc.s, Bo.ncell);
+        const double tr = rho - rtr;
         const double kc = (tr > kreq) ? tr : kreq;
         const long long bidx =
             ((long long)(Lc.l[2] + g) * Bo.p[1] + (Lc.l[1] + g)) * Bo.p[0] + (Lc.l[0] + g);
         const double K = to_f64(buf[Bo.boff + M.slot[5] * Bo.npad + bidx]);
-        const double Kl = limited_removal(K, rho, L);
+        const double Kl = limited_removal(K, rho, rtr, L);
         const double eta = (K > 0.0) ? Kl / K : 1.0;
         const double term = (eta * kc) * M.V;
         const double vx = (double)state[Lc.s + Bo.ncell] / rho;
@@ -1106,7 +1190,8 @@ __device__ __forceinline__ double apply_cell(S* st, long long stride, double Dr,
   const double py = (double)st[2 * stride];
   const double pz = (double)st[3 * stride];
   const double E = (double)st[4 * stride];
-  const double Kl = limited_removal(K, rho, L);
+  const double Kl =
+      (K > 0.0) ? limited_removal(K, rho, truelove_rho(L, rho, px, py, pz, E), L) : 0.0;
   if (K > 0.0) {
     ++cnt.touched;
     if (Kl < K) ++cnt.bind;
@@ -2320,6 +2405,30 @@ hipError_t launch_copy(void* dst, const void* src, long long bytes, hipStream_t 
   return hipGetLastError();
 }
 
+hipError_t launch_copy4(void* dst, const void* src, long long bytes, hipStream_t s) {
+  const long long ngroups = bytes / 16384;
+  const int grid = grid_for(ngroups, 1, 256 * 16);
+  hipLaunchKernelGGL(k_copy4, dim3(grid), dim3(256), 0, s, (u32x4*)dst, (const u32x4*)src,
+                     ngroups);
+  return hipGetLastError();
+}
+
+hipError_t launch_atomic_bench(void* dst, long long slots, int type, int pattern,
+                               long long n_ops, hipStream_t s) {
+  const int grid = grid_for(n_ops, 256, 256 * 64);
+  const unsigned long long mask = (unsigned long long)slots - 1ull;
+  if (type == 0)
+    hipLaunchKernelGGL(k_atomic_bench<unsigned long long>, dim3(grid), dim3(256), 0, s,
+                       (unsigned long long*)dst, mask, pattern, n_ops);
+  else if (type == 1)
+    hipLaunchKernelGGL(k_atomic_bench<float>, dim3(grid), dim3(256), 0, s, (float*)dst, mask,
+                       pattern, n_ops);
+  else
+    hipLaunchKernelGGL(k_atomic_bench<double>, dim3(grid), dim3(256), 0, s, (double*)dst, mask,
+                       pattern, n_ops);
+  return hipGetLastError();
+}
+
 hipError_t launch_clear_status(DevStatus* st, hipStream_t s) {
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
@@ -2498,11 +2607,11 @@ hipError_t launch_sn_direct(const Mesh& M, const Particles& P, void* buf, int la
 
 template <int ACC, class S>
 static void sink_dep(const Mesh& M, const Particles& P, const void* state, void* buf,
-                     double* scratch, const SinkParams& K, double rho_tr, double* bound,
+                     double* scratch, const SinkParams& K, const Limits& L, double* bound,
                      hipStream_t s) {
   const int grid = grid_for(P.n, 1, 65536);
   hipLaunchKernelGGL((k_sink_deposit<ACC, S>), dim3(grid), dim3(kSinkBlock), 0, s, M, P,
-                     (const S*)state, (typename AccT<ACC>::T*)buf, scratch, K, rho_tr, bound);
+                     (const S*)state, (typename AccT<ACC>::T*)buf, scratch, K, L, bound);
 }
 
 hipError_t launch_sink_deposit(const Mesh& M, const Particles& P, const void* state,
@@ -2510,7 +2619,7 @@ hipError_t launch_sink_deposit(const Mesh& M, const Particles& P, const void* st
                                const Limits& L, double* bound, hipStream_t s) {
   if (P.n <= 0) return hipSuccess;
   const bool f32 = (M.state == PMP_STATE_F32);
-  const double tr = L.rho_tr;
+  const Limits& tr = L;
   switch (M.acc) {
     case PMP_ACC_F32:
       f32 ? sink_dep<PMP_ACC_F32, float>(M, P, state, buf, scratch, K, tr, nullptr, s)
@@ -2571,85 +2680,119 @@ hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* sta
 
 // ------------------------------------------------------------ sink creation
 
-// Sink creation (Sec. 3.1.2), pass 1.  Each wavefront takes 64 consecutive
-// cells of the single periodic box; a cell is a candidate when rho > rho_Tr
-// and the folded removal channel K is zero there (no sink kernel reaches it).
-// The whole wavefront then tests each candidate in turn: the lanes cover the
-// (dy, dx) offsets of the r_K cube (their sphere test needs dz as well), the
-// loop runs over dz, and any cell within r_K that is denser (equal densities
-// ranked by the linear cell index, the lower index counting as denser)
-// disqualifies the candidate.  Only the state before any creation is read.
-// Qualifying cells are counted in work[0] and, up to max_new of them,
-// appended in arrival order to work[1 ..]; work[1 + max_new ..] (pass 2's
-// rank accumulators) is zeroed.  R = floor(r_K) must not exceed
-// any axis length, so one wrap per axis suffices.
+// Squared distance along one axis from p to the centre of cell i or of its
+// periodic images one domain length n away, the smallest of the three (each
+// as the distance test of dist2 computes it).  The sum of the three axes'
+// smallest terms is the smallest dist2 over the 27 images, since rounded
+// sums and squares are monotone.
+__device__ __forceinline__ double image_term(int i, int n, double p) {
+  const double a = ((double)i + 0.5) - p;
+  const double b = ((double)(i - n) + 0.5) - p;
+  const double c = ((double)(i + n) + 0.5) - p;
+  double m = a * a;
+  if (b * b < m) m = b * b;
+  if (c * c < m) m = c * c;
+  return m;
+}
+
+// Sink creation (Sec. 3.1.2), pass 1.  The blocks walk the apply chunks
+// (256 owned cells of one box); each wavefront takes 64 of them.  A cell is a
+// candidate when rho > rho_Tr (its Truelove density) and the folded removal
+// channel K of its box is zero there.  The whole wavefront then tests each
+// candidate in turn: first the existing sinks (lanes over the sinks, any one
+// within r_K of the cell centre or of a periodic image disqualifies), then
+// the cells within r_K (lanes over the (dy, dx) columns of the r_K cube, a
+// loop over dz; each neighbour wrapped into the domain and found in the box
+// that owns it, cells no box owns left out): a denser one (equal densities
+// ranked by the global linear cell index, the lower index counting as
+// denser) disqualifies.  Only the state before any creation is read.
+// Qualifying cells are counted in work[0] and, up to max_new of them, their
+// global linear index appended in arrival order to work[1 ..];
+// work[1 + max_new ..] (pass 2's rank accumulators) is zeroed.  R = floor(r_K)
+// must not exceed any axis length of the domain (one wrap per axis).
 template <class T, class S>
 __global__ __launch_bounds__(256) void k_create_find(Mesh M, const S* __restrict__ state,
-                                                     const T* __restrict__ buf, double r_k,
-                                                     double rho_tr, long long max_new,
+                                                     const T* __restrict__ buf, SinkPos E,
+                                                     double r_k, Limits L, long long max_new,
                                                      long long* __restrict__ work) {
-  const DevBox B = M.boxes[0];
-  const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
   const int g = M.ghost;
+  const int nx = M.domain[0], ny = M.domain[1], nz = M.domain[2];
   const int R = (int)floor(r_k), side = 2 * R + 1, plane = side * side;
   const double r2 = r_k * r_k;
   const int lane = threadIdx.x & (kWave - 1);
-  const T* K = (buf != nullptr && M.slot[5] >= 0) ? buf + B.boff + M.slot[5] * B.npad : nullptr;
-  const S* rho_f = state + B.soff;
+  const bool has_k = buf != nullptr && M.slot[5] >= 0;
   // the rank accumulators of pass 2 start at zero
   for (long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x; z < max_new;
        z += (long long)gridDim.x * blockDim.x)
     work[1 + max_new + z] = 0;
-  const long long nwave = (long long)gridDim.x * (blockDim.x / kWave);
-  for (long long base = ((long long)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave)) *
-                        kWave;
-       base < B.ncell; base += nwave * kWave) {
-    const long long c = base + lane;
+  // the chunk loop is uniform over the block, so every wavefront runs the
+  // ballots below with all its lanes
+  for (long long ch = blockIdx.x; ch < M.n_apply_chunks; ch += gridDim.x) {
+    const int2 C = M.apply_chunks[ch];
+    const DevBox B = M.all_boxes[C.x];
+    const long long c = (long long)C.y + threadIdx.x;  // owned cell of box C.x
     bool cand = false;
     double rho = 0.0;
-    int i = 0, j = 0, k = 0;
+    int gi = 0, gj = 0, gk = 0;
+    long long key = 0;
     if (c < B.ncell) {
-      rho = (double)rho_f[c];
-      if (rho > rho_tr) {
-        i = (int)(c % nx);
-        j = (int)((c / nx) % ny);
-        k = (int)(c / ((long long)nx * ny));
-        cand = (K == nullptr) ||
-               to_f64(K[((long long)(k + g) * B.p[1] + (j + g)) * B.p[0] + (i + g)]) == 0.0;
+      const S* st = state + B.soff + c;
+      rho = (double)st[0];
+      if (rho > truelove_at(L, st, B.ncell)) {
+        const long long row = c / B.n[0];
+        const int li = (int)(c - row * B.n[0]);
+        const int lk = (int)(row / B.n[1]);
+        const int lj = (int)(row - (long long)lk * B.n[1]);
+        gi = B.lo[0] + li;
+        gj = B.lo[1] + lj;
+        gk = B.lo[2] + lk;
+        key = ((long long)gk * ny + gj) * nx + gi;
+        cand = true;
+        if (has_k) {
+          const T* K = buf + B.boff + M.slot[5] * B.npad;
+          cand = to_f64(K[((long long)(lk + g) * B.p[1] + (lj + g)) * B.p[0] + (li + g)]) == 0.0;
+        }
       }
     }
     unsigned long long mask = __ballot(cand);
     while (mask) {
       const int src = __ffsll((long long)mask) - 1;
       mask &= mask - 1;
-      const long long cc = __shfl(c, src, kWave);
+      const long long ck = __shfl(key, src, kWave);
       const double rc = __shfl(rho, src, kWave);
-      const int ci = __shfl(i, src, kWave), cj = __shfl(j, src, kWave),
-                ck = __shfl(k, src, kWave);
+      const int ci = __shfl(gi, src, kWave), cj = __shfl(gj, src, kWave),
+                cz = __shfl(gk, src, kWave);
       bool beaten = false;
-      for (int q = lane; q < plane; q += kWave) {
-        const int dj = q / side - R, di = q - (dj + R) * side - R;
-        const int dyx = di * di + dj * dj;
-        // members of this (dy, dx) column: dz^2 <= r_K^2 - dy^2 - dx^2, the
-        // same test as (double)(dy^2 + dx^2 + dz^2) <= r_K^2 on integers
-        int kmax = -1;
-        while (kmax < R && (double)(dyx + (kmax + 1) * (kmax + 1)) <= r2) ++kmax;
-        int ii = ci + di, jj = cj + dj;
-        ii += (ii < 0) ? nx : ((ii >= nx) ? -nx : 0);
-        jj += (jj < 0) ? ny : ((jj >= ny) ? -ny : 0);
-        const long long col = (long long)jj * nx + ii;
-#pragma unroll 4
-        for (int dk = -kmax; dk <= kmax; ++dk) {
-          int kk = ck + dk;
-          kk += (kk < 0) ? nz : ((kk >= nz) ? -nz : 0);
-          const long long o = (long long)kk * ny * nx + col;
-          const double ro = (double)rho_f[o];
-          beaten |= (o != cc) && ((ro > rc) || (ro == rc && o < cc));
+      for (long long q = lane; q < E.n; q += kWave) {
+        const double d2 = (image_term(ci, nx, E.x[q]) + image_term(cj, ny, E.y[q])) +
+                          image_term(cz, nz, E.z[q]);
+        beaten |= (d2 <= r2);
+      }
+      if (__ballot(beaten) == 0) {
+        for (int q = lane; q < plane; q += kWave) {
+          const int dj = q / side - R, di = q - (dj + R) * side - R;
+          const int dyx = di * di + dj * dj;
+          // members of this (dy, dx) column: dz^2 <= r_K^2 - dy^2 - dx^2, the
+          // same test as (double)(dy^2 + dx^2 + dz^2) <= r_K^2 on integers
+          int kmax = -1;
+          while (kmax < R && (double)(dyx + (kmax + 1) * (kmax + 1)) <= r2) ++kmax;
+          int w[3] = {ci + di, cj + dj, 0};
+          w[0] += (w[0] < 0) ? nx : ((w[0] >= nx) ? -nx : 0);
+          w[1] += (w[1] < 0) ? ny : ((w[1] >= ny) ? -ny : 0);
+          for (int dk = -kmax; dk <= kmax; ++dk) {
+            w[2] = cz + dk;
+            w[2] += (w[2] < 0) ? nz : ((w[2] >= nz) ? -nz : 0);
+            CellLoc Lc;
+            if (!locate_wrapped(M, w, Lc)) continue;
+            const long long o = ((long long)w[2] * ny + w[1]) * nx + w[0];
+            const double ro = (double)state[Lc.s];
+            beaten |= (o != ck) && ((ro > rc) || (ro == rc && o < ck));
+          }
         }
       }
       if (__ballot(beaten) == 0 && lane == src) {
         const long long slot = (long long)atomicAdd((unsigned long long*)work, 1ull);
-        if (slot < max_new) work[1 + slot] = cc;
+        if (slot < max_new) work[1 + slot] = ck;
       }
     }
   }
@@ -2680,66 +2823,72 @@ __global__ __launch_bounds__(256) void k_create_rank(long long max_new,
   if (rank) atomicAdd((unsigned long long*)(work + 1 + max_new + t), (unsigned long long)rank);
 }
 
-// Pass 3: one thread per new sink, written at its rank (cell index order).
-// The sink sits at the cell centre with mass (rho - rho_Tr) V and momentum
-// mass * p / rho; the cell keeps its velocity and specific energy (rho ->
-// rho_Tr, p -> (p / rho) rho_Tr, E -> (E / rho) rho_Tr).  out is
-// [7][max_new]: x, y, z, m, px, py, pz.
+// Pass 3: one thread per new sink, written at its rank (global cell index
+// order).  The cell is found in the box that owns it.  The sink sits at the
+// cell centre with mass (rho - rho_Tr) V and momentum mass * p / rho; the cell
+// keeps its velocity and specific energy (rho -> rho_Tr, p -> (p / rho)
+// rho_Tr, E -> (E / rho) rho_Tr), rho_Tr the cell's Truelove density before
+// the update.  out is [7][max_new]: x, y, z, m, px, py, pz.
 template <class S>
-__global__ __launch_bounds__(256) void k_create_apply(Mesh M, S* __restrict__ state,
-                                                      double rho_tr, long long max_new,
+__global__ __launch_bounds__(256) void k_create_apply(Mesh M, S* __restrict__ state, Limits L,
+                                                      long long max_new,
                                                       const long long* __restrict__ work,
                                                       double* __restrict__ out) {
   const long long n = work[0];
   if (n > max_new) return;
-  const DevBox B = M.boxes[0];
-  const int nx = B.n[0], ny = B.n[1];
+  const long long nx = M.domain[0], ny = M.domain[1];
   const long long* keys = work + 1;
   const long long* ranks = work + 1 + max_new;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (long long)gridDim.x * blockDim.x) {
     const long long c = keys[t], r = ranks[t];
-    S* cell = state + B.soff + c;
+    const long long row = c / nx;
+    const int w[3] = {(int)(c - row * nx), (int)(row % ny), (int)(row / ny)};
+    CellLoc Lc;
+    if (!locate_wrapped(M, w, Lc)) continue;  // every key came from an owned cell
+    S* cell = state + Lc.s;
+    const long long nc = Lc.B->ncell;
     const double rho = (double)cell[0];
-    const double m = (rho - rho_tr) * M.V;
-    out[r] = (double)(c % nx) + 0.5;
-    out[max_new + r] = (double)((c / nx) % ny) + 0.5;
-    out[2 * max_new + r] = (double)(c / ((long long)nx * ny)) + 0.5;
+    const double rtr = truelove_at(L, (const S*)cell, nc);
+    const double m = (rho - rtr) * M.V;
+    out[r] = (double)w[0] + 0.5;
+    out[max_new + r] = (double)w[1] + 0.5;
+    out[2 * max_new + r] = (double)w[2] + 0.5;
     out[3 * max_new + r] = m;
     for (int a = 1; a <= 3; ++a) {
-      const double v = (double)cell[a * B.ncell] / rho;
+      const double v = (double)cell[a * nc] / rho;
       out[(3 + a) * max_new + r] = m * v;
-      cell[a * B.ncell] = (S)(v * rho_tr);
+      cell[a * nc] = (S)(v * rtr);
     }
-    cell[4 * B.ncell] = (S)(((double)cell[4 * B.ncell] / rho) * rho_tr);
-    cell[0] = (S)rho_tr;
+    cell[4 * nc] = (S)(((double)cell[4 * nc] / rho) * rtr);
+    cell[0] = (S)rtr;
   }
 }
 
 template <class T, class S>
-static void create_launch(const Mesh& M, void* state, const void* buf, double r_k,
-                          double rho_tr, long long max_new, double* out, long long* work,
-                          long long ncell, hipStream_t s) {
-  const int grid = grid_for(ncell, 256, M.num_cu * 32);
+static void create_launch(const Mesh& M, void* state, const void* buf, const SinkPos& E,
+                          double r_k, const Limits& L, long long max_new, double* out,
+                          long long* work, hipStream_t s) {
+  const int grid = grid_for(M.n_apply_chunks, 1, M.num_cu * 32);
   hipLaunchKernelGGL((k_create_find<T, S>), dim3(grid), dim3(256), 0, s, M, (const S*)state,
-                     (const T*)buf, r_k, rho_tr, max_new, work);
+                     (const T*)buf, E, r_k, L, max_new, work);
   if (max_new <= 0) return;
   const int gx = grid_for(max_new, 256, 1 << 30);
   const int gy = grid_for(max_new, kRankChunk, 1 << 30);
   hipLaunchKernelGGL(k_create_rank, dim3(gx, gy), dim3(256), 0, s, max_new, work);
   hipLaunchKernelGGL((k_create_apply<S>), dim3(grid_for(max_new, 256, 1024)), dim3(256), 0, s,
-                     M, (S*)state, rho_tr, max_new, (const long long*)work, out);
+                     M, (S*)state, L, max_new, (const long long*)work, out);
 }
 
-hipError_t launch_sink_create(const Mesh& M, void* state, const void* buf, double r_k,
-                              double rho_tr, long long max_new, double* out, long long* work,
-                              long long ncell, hipStream_t s) {
+hipError_t launch_sink_create(const Mesh& M, void* state, const void* buf, const SinkPos& E,
+                              double r_k, const Limits& L, long long max_new, double* out,
+                              long long* work, hipStream_t s) {
   hipError_t e = launch_zero(work, 8, 256, s);  // the count (the find pass zeroes the ranks)
   if (e != hipSuccess) return e;
   const bool f32 = (M.state == PMP_STATE_F32);
-#define PMP_CR(T)                                                                              \
-  (f32 ? create_launch<T, float>(M, state, buf, r_k, rho_tr, max_new, out, work, ncell, s)     \
-       : create_launch<T, double>(M, state, buf, r_k, rho_tr, max_new, out, work, ncell, s))
+#define PMP_CR(T)                                                                     \
+  (f32 ? create_launch<T, float>(M, state, buf, E, r_k, L, max_new, out, work, s)     \
+       : create_launch<T, double>(M, state, buf, E, r_k, L, max_new, out, work, s))
   switch (M.acc) {
     case PMP_ACC_F32: PMP_CR(float); break;
     case PMP_ACC_F64R:

@@ -137,7 +137,18 @@ SMALL = {
     "c5_4": lambda: W.c5(nb=4),
     "c5s_4": lambda: W.c5s(nb=4),
     "c5sbh_4": lambda: W.c5s(nb=4, bondi=True),
+    "c3tl_40": lambda: truelove(W.c3(nx=40, n_sink=48)),
+    "c5sbhtl_4": lambda: truelove(W.c5s(nb=4, bondi=True), G=0.04),
 }
+
+
+def truelove(w, J=0.25, G=0.05):
+    """The workload with the per-cell Truelove density (eq. "truelove"): its gas
+    has specific e_int = 1, so with gamma 5/3 each cell's rho_Tr is about
+    J^2 pi (10/9) / G (4.4 for G = 0.05), which the densest few percent of the
+    log-normal cells exceed."""
+    return dataclasses.replace(w, name=w.name + "_truelove",
+                               limits=dataclasses.replace(w.limits, truelove_J=J, G=G))
 
 
 @pytest.mark.parametrize("path", [1, 0])
@@ -679,3 +690,13 @@ def test_reproducibility_mode_fused_step_and_errors(B, orc):
     with pytest.raises(B.PmpError):
         ctx.step_per_box()
     ctx.close()
+
+
+def test_truelove_per_cell_changes_the_limiter(B, orc):
+    """The per-cell Truelove density raises removals in dense cells: the
+    limiter's counters differ from the constant (disabled) density's, and the
+    GPU step still matches the oracle bit for bit."""
+    w = W.c3(nx=40, n_sink=48)
+    base = orc.step(w, "fix64")["counters"]
+    got, ref = check(B, orc, truelove(w), "fix64")
+    assert ref["counters"]["touched"] > base["touched"] or ref["counters"]["bind"] != base["bind"]

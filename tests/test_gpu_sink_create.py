@@ -3,6 +3,7 @@ the C-ABI.  The test outcome of every cell is a comparison of values read
 from the state, and the new sinks' values are computed in double from the
 same inputs on both sides, so the created list (in cell index order), the
 count and the updated state are compared bit for bit."""
+import dataclasses
 import sys
 
 import numpy as np
@@ -27,7 +28,8 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_create(B, w, acc, buf_np, r_k, rho_tr, max_new, state=None):
+def gpu_create(B, w, acc, buf_np, r_k, rho_tr, max_new, state=None, limits=None,
+               existing=None):
     import torch
     ctx = B.Context(w, acc, channels="all")
     if state is not None:
@@ -35,7 +37,8 @@ def gpu_create(B, w, acc, buf_np, r_k, rho_tr, max_new, state=None):
     if buf_np is not None:
         ctx.buf.copy_(torch.from_numpy(np.ascontiguousarray(buf_np).astype(
             {"f32": np.float32, "f64": np.float64, "fix64": np.int64}[acc])))
-    out, work = ctx.sink_create(r_k, rho_tr, max_new, buf=buf_np is not None)
+    out, work = ctx.sink_create(r_k, rho_tr, max_new, buf=buf_np is not None, limits=limits,
+                                existing=existing)
     torch.cuda.synchronize()
     res = (int(work[0].item()), out.cpu().numpy().reshape(7, -1)[:, :max_new],
            ctx.state.cpu().numpy())
@@ -43,10 +46,18 @@ def gpu_create(B, w, acc, buf_np, r_k, rho_tr, max_new, state=None):
     return res
 
 
-def oracle_create(orc, w, mode, state, buf, r_k, rho_tr, max_new):
+def oracle_create(orc, w, mode, state, buf, r_k, rho_tr, max_new, limits=None, existing=None):
     s64 = np.asarray(state, dtype=np.float64).copy()
-    n, out = orc.sink_create(w, mode, s64, buf, r_k, rho_tr, max_new)
+    n, out = orc.sink_create(w, mode, s64, buf, r_k, rho_tr, max_new, limits=limits,
+                             existing=existing)
     return n, out, s64
+
+
+def truelove_limits(w, J=0.25, G=0.05):
+    """Per-cell Truelove density (eq. "truelove"): the workloads' gas has
+    specific e_int = 1, so with gamma 5/3 every cell has rho_Tr =
+    J^2 pi (10/9) / G, about 4.4 here, in its own floating-point rounding."""
+    return dataclasses.replace(w.limits, truelove_J=J, G=G)
 
 
 def compare(got, ref, max_new, dtype):
@@ -128,17 +139,51 @@ def test_create_capacity_and_errors(B, orc):
     with pytest.raises(B.PmpError):
         ctx.sink_create(4.5, 2.0, 8)
     ctx.close()
-    # the GPU entry point covers one box spanning the domain only
-    mb = W.multibox([8, 8], [8], [8], ghost=1, positions_cic=[[1.5, 1.5, 1.5]], seed=1)
-    ctx = B.Context(mb, "f64")
-    with pytest.raises(B.PmpError, match="EUNSUPPORTED"):
+    # boxes that leave cells of the domain unowned
+    rng = np.random.default_rng(1)
+    gap = W.Workload("gap", (8, 8, 8), np.array([[0, 0, 0]]), np.array([[4, 8, 8]]), 1, 1.0,
+                     W.gas_state(rng, 256, np.float64).reshape(-1))
+    ctx = B.Context(gap, "f64")
+    with pytest.raises(B.PmpError, match="ERANGE"):
         ctx.sink_create(1.0, 2.0, 8)
+    ctx.close()
+    # a per-cell Truelove density needs G > 0
+    ctx = B.Context(w, "f64")
+    with pytest.raises(B.PmpError, match="EINVAL"):
+        ctx.sink_create(r_k, rho_tr, 8, limits=truelove_limits(w, G=0.0))
     ctx.close()
 
 
-@pytest.mark.skip(reason="multi-box sink creation on the GPU is switched off: its first "
-                  "version (per-box chunks, owner lookups) faulted the GPU once and no cause "
-                  "was found; pmp_sink_create returns PMP_EUNSUPPORTED for multi-box layouts")
+@pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
+def test_create_truelove_and_existing_sinks(B, orc, acc):
+    """Per-cell Truelove density (eq. "truelove") and the existing sinks'
+    exclusion zone (Sec. 3.1.2, no sink within r_K), with and without the
+    removal channel, on the log-normal gas of c3."""
+    w = W.c3(nx=40, n_cic=0, n_sink=48)
+    w = W.Workload(w.name, w.domain, w.lo, w.n, w.ghost, w.dx, w.state, sinks=w.sinks,
+                   r_k=w.r_k, r_gauss=w.r_gauss)
+    mode = "fix64" if acc == "fix64" else "f64"
+    buf, _, _ = orc.deposit(w, mode)
+    orc.fold(w, mode, buf)
+    ref_buf = buf.astype(np.float32).astype(np.float64) if acc == "f32" else buf
+    lim = truelove_limits(w)
+    r_k, max_new = 2.0, 4096
+    counts = []
+    for use_buf in (True, False):
+        for existing in (None, "workload"):
+            say(f"case create truelove acc={acc} buf={use_buf} existing={existing}")
+            ex = w.sinks if existing else None
+            ref = oracle_create(orc, w, mode, w.state, ref_buf if use_buf else None, r_k,
+                                float("nan"), max_new, limits=lim, existing=ex)
+            got = gpu_create(B, w, acc, buf if use_buf else None, r_k, float("nan"), max_new,
+                             limits=lim, existing=existing)
+            compare(got, ref, max_new, np.float32)
+            counts.append(ref[0])
+    # the exclusion zone removes candidates the removal channel alone keeps
+    # (and the other way round for sinks whose kernels do not deposit here)
+    assert counts[2] > counts[3] and counts[0] >= counts[1] and counts[3] > 20
+
+
 @pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
 def test_create_multibox_after_step(B, orc, acc):
     """4 x 4 x 4 boxes of the batched AMR level with sinks: a step (fixed
@@ -168,5 +213,25 @@ def test_create_multibox_after_step(B, orc, acc):
         ref_buf = buf.astype(np.float32).astype(np.float64) if acc == "f32" else buf
         ref_c = oracle_create(orc, w, mode, st32, ref_buf, r_k, rho_tr, max_new)
         got = gpu_create(B, w, acc, buf, r_k, rho_tr, max_new, state=st32)
+    assert 10 < ref_c[0] < max_new
+    compare(got, ref_c, max_new, np.float32)
+
+
+@pytest.mark.parametrize("acc", ["fix64", "f32"])
+def test_create_multibox_truelove_existing(B, orc, acc):
+    """Multi-box creation with the per-cell Truelove density and the
+    existing sinks' exclusion zone, on the oracle's fixed-point step result
+    (no removal channel handed over: the exclusion zone alone applies)."""
+    w = W.c5s(nb=4)
+    ref = orc.step(w, "fix64")
+    st32 = ref["state"].astype(np.float32)
+    lim = truelove_limits(w, G=0.03)
+    r_k, max_new = 2.0, 65536
+    say(f"case create multibox truelove acc={acc}")
+    mode = "fix64" if acc == "fix64" else "f64"
+    ref_c = oracle_create(orc, w, mode, st32, None, r_k, float("nan"), max_new, limits=lim,
+                          existing=w.sinks)
+    got = gpu_create(B, w, acc, None, r_k, float("nan"), max_new, state=st32, limits=lim,
+                     existing="workload")
     assert 10 < ref_c[0] < max_new
     compare(got, ref_c, max_new, np.float32)
