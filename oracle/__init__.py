@@ -73,6 +73,26 @@ class _Sinks(C.Structure):
 RATE_FRACTION, RATE_BONDI = 0, 1
 
 
+class _Snr(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("m", C.c_void_p),
+                ("e", C.c_void_p), ("vx", C.c_void_p), ("vy", C.c_void_p), ("vz", C.c_void_p),
+                ("box_off", C.c_void_p), ("r_k", C.c_double), ("sub", C.c_int32),
+                ("nh_per_rho", C.c_double), ("msf_coef", C.c_double),
+                ("psnr_coef", C.c_double), ("eps_k", C.c_double)]
+
+
+def _snr(w):
+    """ctypes description of a workload's supernova remnants (kind ``snr``:
+    fields x, y, z, m (ejecta mass), e (energy), vx, vy, vz; parameters in
+    ``snr_params``)."""
+    s, keep = _kind(w.snr, ["x", "y", "z", "m", "e", "vx", "vy", "vz"], _Snr)
+    P = w.snr_params
+    s.r_k, s.sub = float(P.r_k), int(P.sub)
+    s.nh_per_rho, s.msf_coef = float(P.nh_per_rho), float(P.msf_coef)
+    s.psnr_coef, s.eps_k = float(P.psnr_coef), float(P.eps_k)
+    return s, keep
+
+
 def _sinks(w):
     """ctypes sink description of a workload and the arrays it points at.
     Bondi-Hoyle workloads (``sink_rate`` 1) carry the sink fields m, vx, vy,
@@ -116,6 +136,11 @@ def lib():
         vp, i32 = C.c_void_p, C.c_int
         L.orc_exp.restype = C.c_double
         L.orc_exp.argtypes = [C.c_double]
+        L.orc_log.restype = C.c_double
+        L.orc_log.argtypes = [C.c_double]
+        L.orc_pow.restype = C.c_double
+        L.orc_pow.argtypes = [C.c_double, C.c_double]
+        L.orc_deposit_snr.argtypes = [vp, i32, vp, vp, vp, vp]
         L.orc_buffer_elems.restype = C.c_int64
         L.orc_buffer_elems.argtypes = [vp]
         L.orc_state_elems.restype = C.c_int64
@@ -228,6 +253,26 @@ def deposit(w, mode, mesh=None, state64=None, want_racc=False):
     return buf, sw[:nsink], sm[:nsink]
 
 
+def deposit_snr(w, mode, buf, mesh=None, state64=None):
+    """Supernova remnants (TIGRESS variant, Sec. 3.2.1) added to the
+    deposited buffer ``buf`` in place.  Returns info [4][n]: V_snr, M_snr,
+    n_H and |p_rad| per supernova."""
+    mesh = mesh or Mesh.of(w)
+    s, keep = _snr(w)
+    if state64 is None:
+        state64 = _f64(w.state)
+    n = w.snr.n
+    info = np.zeros((4, max(n, 1)))
+    rc = lib().orc_deposit_snr(C.byref(mesh.c), MODES[mode], C.byref(s), _ptr(state64),
+                               _ptr(buf), _ptr(info))
+    _check(rc, "deposit_snr")
+    return info[:, :n]
+
+
+def has_snr(w):
+    return getattr(w, "snr", None) is not None and w.snr.n > 0
+
+
 def margin_of(w):
     """The reproducibility mode's safety margin M (bits) of a workload."""
     return int(getattr(w, "margin_bits", MARGIN_DEFAULT))
@@ -314,10 +359,13 @@ def step(w, mode, want_eta=False):
     mesh = Mesh.of(w)
     s64 = _f64(w.state)
     buf, sw, sm, sr = deposit(w, mode, mesh, s64, want_racc=True)
+    out = {}
+    if has_snr(w):
+        out["snr_info"] = deposit_snr(w, mode, buf, mesh, s64)
     pre = buf.copy()
     fold(w, mode, buf, mesh)
-    out = {"buf_deposit": pre, "buf_fold": buf, "sink_w": sw, "sink_mreq": sm,
-           "sink_racc": sr}
+    out.update({"buf_deposit": pre, "buf_fold": buf, "sink_w": sw, "sink_mreq": sm,
+                "sink_racc": sr})
     if w.sinks is not None and w.sinks.n > 0:
         out["sink_d"] = sink_update(w, mode, buf, sw, sm, mesh, s64, sr)
     st, eta, cnt = apply(w, mode, buf, mesh, s64, want_eta)

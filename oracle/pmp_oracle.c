@@ -877,6 +877,263 @@ int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
   return rc;
 }
 
+/* ------------------------------------------- supernova remnants (TIGRESS) */
+
+/* Natural logarithm for the power laws of Sec. 3.2.1 (M_sf, P_snr).
+ * Method: x = m 2^e with m in [sqrt(1/2), sqrt(2)), then
+ * ln m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^23/23) with s = (m-1)/(m+1)
+ * (|s| <= 0.172, so the omitted terms are below 2^-60 relative) in Horner
+ * form, plus e ln 2 with ln 2 split as in orc_exp.  Written from the series,
+ * not from any library; checked against libm. */
+double orc_log(double x) {
+  if (x != x || x < 0.0) return NAN;
+  if (x == 0.0) return -HUGE_VAL;
+  if (isinf(x)) return x;
+  int e;
+  double m = frexp(x, &e);
+  if (m < 0x1.6a09e667f3bcdp-1) {  /* sqrt(1/2) rounded to double */
+    m = m * 2.0;
+    e = e - 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double s2 = s * s;
+  double t = 1.0 / 23.0;
+  t = t * s2 + 1.0 / 21.0;
+  t = t * s2 + 1.0 / 19.0;
+  t = t * s2 + 1.0 / 17.0;
+  t = t * s2 + 1.0 / 15.0;
+  t = t * s2 + 1.0 / 13.0;
+  t = t * s2 + 1.0 / 11.0;
+  t = t * s2 + 1.0 / 9.0;
+  t = t * s2 + 1.0 / 7.0;
+  t = t * s2 + 1.0 / 5.0;
+  t = t * s2 + 1.0 / 3.0;
+  t = t * s2 + 1.0;
+  const double lnm = (2.0 * s) * t;
+  const double ln2_hi = 0x1.62e42ffp-1;
+  const double ln2_lo = -0x1.718432a1b0e26p-35;
+  const double k = (double)e;
+  return k * ln2_hi + (k * ln2_lo + lnm);
+}
+
+/* x^a = exp(a ln x) for x > 0, from orc_log and orc_exp. */
+double orc_pow(double x, double a) { return orc_exp(a * orc_log(x)); }
+
+/* Covered fraction of cell (i, j, k) by the sphere of squared radius r2
+ * around (x, y, z): the number of its ns^3 sample points, the centres of
+ * the sub-cells of edge 1/ns (ns a power of two, so every coordinate is
+ * exact), whose squared distance to the centre, summed in x, y, z order,
+ * is at most r2. */
+static int64_t covered_samples(double x, double y, double z, double r2, int64_t i, int64_t j,
+                               int64_t k, int ns) {
+  int64_t c = 0;
+  for (int c3 = 0; c3 < ns; ++c3) {
+    const double dz = ((double)k + ((double)c3 + 0.5) / (double)ns) - z;
+    for (int c2 = 0; c2 < ns; ++c2) {
+      const double dy = ((double)j + ((double)c2 + 0.5) / (double)ns) - y;
+      for (int c1 = 0; c1 < ns; ++c1) {
+        const double ddx = ((double)i + ((double)c1 + 0.5) / (double)ns) - x;
+        if ((ddx * ddx + dy * dy) + dz * dz <= r2) ++c;
+      }
+    }
+  }
+  return c;
+}
+
+/* Covered fraction w of cell (i, j, k) (the host cell h alone, with w = 1,
+ * when no sample point of any cell lies within r). */
+static double snr_weight(double x, double y, double z, double r2, int64_t i, int64_t j,
+                         int64_t k, int ns, double nsamp, int alone, const int64_t h[3]) {
+  if (alone) return (i == h[0] && j == h[1] && k == h[2]) ? 1.0 : 0.0;
+  const int64_t c = covered_samples(x, y, z, r2, i, j, k, ns);
+  return c ? (double)c / nsamp : 0.0;
+}
+
+static int snr_params_ok(const orc_snr *S) {
+  if (!S || !S->x || !S->y || !S->z || !S->m || !S->e || !S->vx || !S->vy || !S->vz ||
+      !S->box_off)
+    return 0;
+  if (!(S->r_k >= 0.0) || !(S->r_k <= 16.0)) return 0;
+  if (S->sub < 1 || S->sub > 16 || (S->sub & (S->sub - 1)) != 0) return 0;
+  if (!(S->nh_per_rho > 0.0) || !(S->msf_coef > 0.0) || !(S->psnr_coef >= 0.0) ||
+      !(S->eps_k >= 0.0))
+    return 0;
+  if (!isfinite(S->nh_per_rho) || !isfinite(S->msf_coef) || !isfinite(S->psnr_coef) ||
+      !isfinite(S->eps_k))
+    return 0;
+  return 1;
+}
+
+/* Supernova remnants with the variant of the TIGRESS prescription of
+ * Sec. 3.2.1 (eqs. "du", "dp", "psnr"), added to the buffer (after
+ * orc_deposit).  Per supernova s at x_s with ejecta mass M_ej, energy E_sn
+ * and velocity v_s:
+ *   kernel    every cell with a covered fraction w > 0 (covered_samples /
+ *             sub^3; r_K = S->r_k); if no sample point lies within r_K, the
+ *             host cell alone with w = 1;
+ *   sums      on the 2^-40 grid: V_snr = sum w V, M_gas = sum w rho V,
+ *             P_gas = sum w p V (the state read in place, periodic);
+ *   scalars   M_snr = M_gas + M_ej, n_H = nh_per_rho M_snr / V_snr,
+ *             M_sf = msf_coef n_H^-0.26, R_M = M_snr / M_sf,
+ *             |p_rad| = psnr_coef n_H^-0.17 (R_M > 1, MC),
+ *                       sqrt(2 M_ej eps_k E_sn) (0.027 < R_M <= 1, ST),
+ *                       0 (EJ),
+ *             v_COM = (P_gas + M_ej v_s) / M_snr, E_kin = M_ej |v_s|^2 / 2;
+ *   per cell  a = w / V_snr, rhat the unit vector from x_s to the cell
+ *             centre (0 at x_s), p_rad = a |p_rad| rhat,
+ *             d rho = a M_ej,
+ *             d p   = w ((rho + M_ej / V_snr) v_COM - p) + p_rad,
+ *             d E   = a (E_sn + E_kin) + v_COM . p_rad.
+ * Fixed point: every term rounded on the 2^-40 grid; the mass and the
+ * injected energy a (E_sn + E_kin) keep the remainder rule (residue of
+ * rint(M_ej / V 2^40), rint((E_sn + E_kin) / V 2^40) to the host cell if it
+ * is a kernel cell, else the first in (k, j, i) order); momentum and v_COM .
+ * p_rad are rounded per cell.  info (may be NULL) receives per supernova
+ * [4][n]: V_snr, M_snr, n_H, |p_rad|.  Fields 0 (rho), 1-3 (p), 4 (E). */
+int orc_deposit_snr(const orc_mesh *M, int mode, const orc_snr *S, const double *state,
+                    void *buf, double *info) {
+  int rc = check_mesh(M);
+  if (rc) return rc;
+  if (!snr_params_ok(S) || !state || !buf) return ORC_EINVAL;
+  if (mode != ORC_F64 && mode != ORC_FIX64) return ORC_EINVAL;
+  geom G;
+  rc = geom_build(M, &G, 1);
+  if (rc) return rc;
+  const double V = (M->dx * M->dx) * M->dx;
+  const double r2 = S->r_k * S->r_k;
+  const int ns = S->sub;
+  const double nsamp = (double)ns * (double)ns * (double)ns;
+  const int64_t ntot = S->box_off[M->nbox];
+  for (int b = 0; b < M->nbox && !rc; ++b) {
+    for (int64_t p = S->box_off[b]; p < S->box_off[b + 1] && !rc; ++p) {
+      const double x = S->x[p], y = S->y[p], z = S->z[p];
+      const double Mej = S->m[p], Esn = S->e[p];
+      const double vs[3] = {S->vx[p], S->vy[p], S->vz[p]};
+      const int64_t h[3] = {(int64_t)floor(x), (int64_t)floor(y), (int64_t)floor(z)};
+      if (!host_in_box(M, b, h)) { rc = ORC_EOUTSIDE; break; }
+      int64_t lo[3], hi[3];
+      const double pos[3] = {x, y, z};
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = (int64_t)floor(pos[a] - S->r_k) - 1;
+        hi[a] = (int64_t)floor(pos[a] + S->r_k) + 1;
+      }
+      /* the kernel: cells with a covered sample point, or the host cell alone */
+      int any = 0;
+      for (int64_t k = lo[2]; k <= hi[2] && !any; ++k)
+        for (int64_t j = lo[1]; j <= hi[1] && !any; ++j)
+          for (int64_t i = lo[0]; i <= hi[0] && !any; ++i)
+            any = covered_samples(x, y, z, r2, i, j, k, ns) > 0;
+      const int alone = !any;
+      /* kernel sums on the 2^-40 grid */
+      int64_t qV = 0, qM = 0, qP[3] = {0, 0, 0}, first[3] = {0, 0, 0};
+      int nmem = 0, host_member = 0;
+      for (int64_t k = lo[2]; k <= hi[2] && !rc; ++k)
+        for (int64_t j = lo[1]; j <= hi[1] && !rc; ++j)
+          for (int64_t i = lo[0]; i <= hi[0] && !rc; ++i) {
+            const double w = snr_weight(x, y, z, r2, i, j, k, ns, nsamp, alone, h);
+            if (w == 0.0) continue;
+            if (nmem++ == 0) { first[0] = i; first[1] = j; first[2] = k; }
+            if (i == h[0] && j == h[1] && k == h[2]) host_member = 1;
+            int64_t iw, jw, kw;
+            const int ob = owner_of(M, &G, i, j, k, &iw, &jw, &kw);
+            if (ob < 0) { rc = ORC_EINVAL; break; }
+            const int64_t i0 = state_index(M, &G, ob, 0, iw, jw, kw);
+            const int64_t st = box_cells(M, ob);
+            int64_t a0, a1, a2, a3, a4;
+            if (q40(w * V, &a0) || q40((w * state[i0]) * V, &a1) ||
+                q40((w * state[i0 + st]) * V, &a2) || q40((w * state[i0 + 2 * st]) * V, &a3) ||
+                q40((w * state[i0 + 3 * st]) * V, &a4)) {
+              rc = ORC_EOVERFLOW;
+              break;
+            }
+            qV += a0; qM += a1; qP[0] += a2; qP[1] += a3; qP[2] += a4;
+          }
+      if (rc) break;
+      /* the remnant's scalars (eqs. "dp", "psnr") */
+      const double Vsnr = (double)qV * FIX_INV;
+      if (!(Vsnr > 0.0)) { rc = ORC_EINVAL; break; }
+      const double Msnr = (double)qM * FIX_INV + Mej;
+      const double nH = (Msnr / Vsnr) * S->nh_per_rho;
+      const double Msf = S->msf_coef * orc_pow(nH, -0.26);
+      const double RM = Msnr / Msf;
+      double P = 0.0;
+      if (RM > 1.0) P = S->psnr_coef * orc_pow(nH, -0.17);
+      else if (RM > 0.027) P = sqrt(((2.0 * Mej) * S->eps_k) * Esn);
+      double vc[3];
+      for (int a = 0; a < 3; ++a) vc[a] = ((double)qP[a] * FIX_INV + Mej * vs[a]) / Msnr;
+      const double Ekin = (0.5 * Mej) * ((vs[0] * vs[0] + vs[1] * vs[1]) + vs[2] * vs[2]);
+      const double Eall = Esn + Ekin;
+      const double dens_ej = Mej / Vsnr;
+      if (info) {
+        info[p] = Vsnr;
+        info[ntot + p] = Msnr;
+        info[2 * ntot + p] = nH;
+        info[3 * ntot + p] = P;
+      }
+      /* the deposition function (eq. "du") */
+      int64_t qr_sum = 0, qe_sum = 0;
+      for (int64_t k = lo[2]; k <= hi[2] && !rc; ++k)
+        for (int64_t j = lo[1]; j <= hi[1] && !rc; ++j)
+          for (int64_t i = lo[0]; i <= hi[0] && !rc; ++i) {
+            const double w = snr_weight(x, y, z, r2, i, j, k, ns, nsamp, alone, h);
+            if (w == 0.0) continue;
+            int64_t iw, jw, kw;
+            const int ob = owner_of(M, &G, i, j, k, &iw, &jw, &kw);
+            const int64_t i0 = state_index(M, &G, ob, 0, iw, jw, kw);
+            const int64_t st = box_cells(M, ob);
+            const double rho = state[i0];
+            const double pc[3] = {state[i0 + st], state[i0 + 2 * st], state[i0 + 3 * st]};
+            const double aw = w / Vsnr;
+            const double dr = aw * Mej;
+            const double d[3] = {((double)i + 0.5) - x, ((double)j + 0.5) - y,
+                                 ((double)k + 0.5) - z};
+            const double len = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+            const double pr = aw * P;
+            double prad[3], dp[3];
+            for (int a = 0; a < 3; ++a) {
+              prad[a] = (len > 0.0) ? pr * (d[a] / len) : 0.0;
+              dp[a] = w * ((rho + dens_ej) * vc[a] - pc[a]) + prad[a];
+            }
+            const double einj = aw * Eall;
+            const double ecross = (vc[0] * prad[0] + vc[1] * prad[1]) + vc[2] * prad[2];
+            int64_t idx[5];
+            for (int f = 0; f < 5; ++f) {
+              idx[f] = buf_index(M, &G, b, f, i, j, k);
+              if (idx[f] < 0) rc = ORC_EREACH;
+            }
+            if (rc) break;
+            if (mode == ORC_F64) {
+              add_f64(buf, NULL, idx[0], dr);
+              for (int a = 0; a < 3; ++a) add_f64(buf, NULL, idx[1 + a], dp[a]);
+              add_f64(buf, NULL, idx[4], einj + ecross);
+            } else {
+              int64_t q[6];
+              if (q40(dr, &q[0]) || q40(dp[0], &q[1]) || q40(dp[1], &q[2]) ||
+                  q40(dp[2], &q[3]) || q40(einj, &q[4]) || q40(ecross, &q[5])) {
+                rc = ORC_EOVERFLOW;
+                break;
+              }
+              for (int f = 0; f < 4; ++f) add_fix(buf, idx[f], q[f]);
+              add_fix(buf, idx[4], iadd(q[4], q[5]));
+              qr_sum = iadd(qr_sum, q[0]);
+              qe_sum = iadd(qe_sum, q[4]);
+            }
+          }
+      if (rc) break;
+      if (mode == ORC_FIX64) {
+        /* remainder rule: mass and injected energy land exactly */
+        int64_t Qr, Qe;
+        if (q40(Mej / V, &Qr) || q40(Eall / V, &Qe)) { rc = ORC_EOVERFLOW; break; }
+        const int64_t *t = host_member ? h : first;
+        add_fix(buf, buf_index(M, &G, b, 0, t[0], t[1], t[2]), iadd(Qr, -qr_sum));
+        add_fix(buf, buf_index(M, &G, b, 4, t[0], t[1], t[2]), iadd(Qe, -qe_sum));
+      }
+    }
+  }
+  geom_free(&G);
+  return rc;
+}
+
 /* ------------------------------------------------------ sink creation */
 
 /* Whether cell (i, j, k) lies within r of the sink at (x, y, z): the kernel

@@ -86,6 +86,23 @@ typedef struct {
   double G, dt, gamma, lambda;      /* gravity constant, time step, adiabatic
                                        index of the gas, the BHL lambda */
 } orc_sinks;
+/* Supernova remnants, the variant of the TIGRESS prescription of Sec. 3.2.1
+ * (orc_deposit_snr).  Code units throughout: nh_per_rho converts a mass
+ * density to the number density of H nuclei n_H in cm^-3 (1/(mu_H m_H)),
+ * msf_coef and psnr_coef are the shell-formation mass and the terminal
+ * momentum at n_H = 1 cm^-3 (1679 Msun and 2.8e5 Msun km/s in the paper). */
+typedef struct {
+  const double *x, *y, *z;       /* position (cells) */
+  const double *m, *e;           /* ejecta mass M_ej, supernova energy E_sn */
+  const double *vx, *vy, *vz;    /* velocity of the exploding particle */
+  const int64_t *box_off;
+  double r_k;                    /* kernel radius (cells) */
+  int32_t sub;                   /* sample points per axis of the covered
+                                    fraction: 1, 2, 4, 8 or 16 */
+  double nh_per_rho, msf_coef, psnr_coef;
+  double eps_k;                  /* kinetic fraction in the Sedov-Taylor phase */
+} orc_snr;
+
 /* Limiter parameters.  rho_tr is the Truelove density as a constant; with
  * truelove_J > 0 each cell has its own, J^2 pi c_s^2 / (G dx^2) (Sec. 3.1.1,
  * eq. "truelove"), c_s from the cell's state as in the Bondi-Hoyle rate. */
@@ -104,6 +121,8 @@ typedef struct {
 int64_t orc_buffer_elems(const orc_mesh *M);
 int64_t orc_state_elems(const orc_mesh *M);
 double  orc_exp(double x);
+double  orc_log(double x);
+double  orc_pow(double x, double a);   /* orc_exp(a orc_log(x)), x > 0 */
 
 /* sink_w, sink_mreq, sink_racc [n sinks]: the kernel weight sum, the
  * requested mass and the Gaussian width r_acc (cells) of each sink. */
@@ -115,6 +134,10 @@ int orc_deposit_r(const orc_mesh *M, const orc_cic *cic, const orc_sn *sn,
                   double *err, int margin, double *sink_w, double *sink_mreq,
                   double *sink_racc);
 double orc_truncate_err(double v, double err, int margin);
+/* Supernova remnants (TIGRESS variant), added to a deposited buffer;
+ * info [4][n] (may be NULL): V_snr, M_snr, n_H, |p_rad| per supernova. */
+int orc_deposit_snr(const orc_mesh *M, int mode, const orc_snr *S, const double *state,
+                    void *buf, double *info);
 int orc_fold(const orc_mesh *M, int mode, void *buf);
 int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void *buf,
                     const orc_sinks *sk, const orc_limits *L, const double *sink_w,

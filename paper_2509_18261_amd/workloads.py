@@ -45,6 +45,28 @@ class Limits:
     gamma: float = 5.0 / 3.0
 
 
+# Code units of the supernova-remnant workloads: mass 1 Msun, length one
+# cell of 4 pc, velocity 10 km/s.  Then a code density of 1 is
+# 1 Msun / (4 pc)^3 = 1.058e-24 g cm^-3, i.e. n_H = 0.4518 cm^-3 with
+# mu_H = 1.4 m_H; 1e51 erg is 5.028e5 code energy units; the paper's
+# shell-formation mass at n_H = 1 is 1679 Msun and its terminal momentum
+# 2.8e5 Msun km/s = 2.8e4 code units; the ejecta mass is 10 Msun.
+SNR_NH_PER_RHO = 0.4518
+SNR_E_SN = 5.028e5
+SNR_M_EJ = 10.0
+
+
+@dataclasses.dataclass
+class SnrParams:
+    """Parameters of the TIGRESS-variant supernova deposit (code units)."""
+    r_k: float = 3.0              # kernel radius (cells); 3 dx in the paper
+    sub: int = 4                  # sample points per axis for the covered fraction
+    nh_per_rho: float = SNR_NH_PER_RHO   # n_H (cm^-3) per unit code density
+    msf_coef: float = 1679.0      # shell-formation mass at n_H = 1 cm^-3
+    psnr_coef: float = 2.8e4      # terminal momentum at n_H = 1 cm^-3
+    eps_k: float = 0.28           # kinetic fraction of the Sedov-Taylor phase
+
+
 @dataclasses.dataclass
 class Particles:
     """One particle kind, grouped by box.  Fields are float64 arrays."""
@@ -78,6 +100,10 @@ class Workload:
     dt: float = 0.05         # time step
     gamma: float = 5.0 / 3.0  # adiabatic index of the gas
     bhl_lambda: float = math.exp(1.5) / 4.0  # isothermal value used throughout the paper
+    # supernova remnants with the TIGRESS-variant deposit (fields x, y, z,
+    # m (ejecta mass), e (energy), vx, vy, vz)
+    snr: Particles | None = None
+    snr_params: SnrParams = dataclasses.field(default_factory=SnrParams)
 
     @property
     def nbox(self) -> int:
@@ -400,6 +426,57 @@ def _edges_of(w):
         firsts = np.unique(lo[:, a])
         out.append(np.array([n[np.flatnonzero(lo[:, a] == f)[0], a] for f in firsts]))
     return out
+
+
+def snr_box(seed: int = 7, nx: int = 32, n_snr: int = 24, dtype=np.float64, sub: int = 4,
+            r_k: float = 3.0, nb: int = 1) -> Workload:
+    """Supernova remnants over gas whose mean density steps between three
+    slabs along x (0.05, 1 and 30 code units, each with log-normal scatter of
+    0.5 dex in e), so that the kernels fall in all three regimes (ejecta,
+    Sedov-Taylor, momentum-conserving) and some straddle a density step;
+    gas velocities N(0, 1), specific e_int = 1; remnant velocities N(0, 2).
+    nb > 1: an nb^3 rectilinear tiling with uneven edges; g = 4."""
+    rng = np.random.default_rng(seed)
+    if nb == 1:
+        domain, lo, n = single_box(nx)
+        cuts, axes = None, None
+    else:
+        edges = [np.full(nb, nx // nb, dtype=np.int64) for _ in range(3)]
+        for e in edges:
+            e[0] += nx - e.sum() + 2
+            e[-1] -= 2
+        domain, lo, n, cuts = rectilinear(*edges)
+        axes = (nb, nb, nb)
+    ncell = int(np.prod(np.asarray(domain, dtype=np.int64)))
+    X, _Y, _Z = domain
+    ix = np.arange(ncell) % X
+    level = np.where(ix < X // 3, 0.05, np.where(ix < 2 * X // 3, 1.0, 30.0))
+    rho = (level * np.exp(0.5 * rng.standard_normal(ncell))).astype(dtype)
+    v = rng.standard_normal((3, ncell))
+    r64 = rho.astype(np.float64)
+    p = (r64[None, :] * v).astype(dtype)
+    p64 = p.astype(np.float64)
+    E = (r64 + 0.5 * (p64 * p64).sum(axis=0) / r64).astype(dtype)
+    fields = np.concatenate([rho[None], p, E[None]], axis=0)
+    # the gas draw is in global x-fastest order; lay it out per box
+    if nb == 1:
+        state = fields.reshape(-1)
+    else:
+        gz, gy, gx = np.unravel_index(np.arange(ncell), (domain[2], domain[1], domain[0]))
+        parts = []
+        for b in range(lo.shape[0]):
+            sel = ((gx >= lo[b, 0]) & (gx < lo[b, 0] + n[b, 0]) & (gy >= lo[b, 1]) &
+                   (gy < lo[b, 1] + n[b, 1]) & (gz >= lo[b, 2]) & (gz < lo[b, 2] + n[b, 2]))
+            parts.append(fields[:, np.flatnonzero(sel)].reshape(-1))
+        state = np.concatenate(parts)
+    pos = uniform_positions(rng, n_snr, domain)
+    f = {"m": np.full(n_snr, SNR_M_EJ), "e": np.full(n_snr, SNR_E_SN)}
+    vel = 2.0 * rng.standard_normal((3, n_snr))
+    f.update({"vx": vel[0], "vy": vel[1], "vz": vel[2]})
+    snr = _one_box(pos, f) if nb == 1 else _group_by_box(pos, f, cuts, axes)
+    return Workload(f"snr_{nx}cube_{n_snr}_remnants" + ("" if nb == 1 else f"_{nb}boxes"),
+                    domain, lo, n, 4, 1.0, state, snr=snr,
+                    snr_params=SnrParams(r_k=r_k, sub=sub))
 
 
 CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "c3bh": c3bh, "c5s": c5s}

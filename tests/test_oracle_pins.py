@@ -1145,3 +1145,288 @@ def test_sink_create_excluded_near_existing_sinks_by_distance(orc):
                            existing=sinks_at((12.2, 6.5, 7.5)))
     assert n == 1
     assert isinstance(sinks_at((1.0, 1.0, 1.0)), Particles)
+
+
+# -------------------------------------- supernova remnants, TIGRESS variant
+
+def test_log_and_pow_against_libm(orc):
+    """The power laws of Sec. 3.2.1 (M_sf, P_snr) go through the oracle's own
+    log and exp: log within 4 ulp of libm, x^a within 1e-15 relative."""
+    L = orc.lib()
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([np.exp(rng.uniform(-690, 690, 4000)),
+                         1.0 + rng.uniform(-1e-3, 1e-3, 1000), rng.uniform(0.5, 2.0, 1000),
+                         [1.0, 2.0, 0.5, 10.0, 1e-300, 1e300]])
+    for x in xs:
+        a, b = L.orc_log(float(x)), math.log(x)
+        assert a == b or abs(a - b) <= 4 * math.ulp(b), (x, a, b)
+    for x in np.exp(rng.uniform(-20, 20, 1000)):
+        for e in (-0.26, -0.17, 0.5, 2.0):
+            assert abs(L.orc_pow(float(x), e) - x ** e) <= 1e-15 * x ** e
+
+
+def snr_uniform(nx, rho, pos, v_s=(0.0, 0.0, 0.0), sub=1, r_k=3.0, u_gas=(0.0, 0.0, 0.0),
+                e_sp=1.0, m_ej=W.SNR_M_EJ, e_sn=W.SNR_E_SN):
+    """Uniform gas of density rho moving at u_gas with specific e_int e_sp,
+    and supernova remnants at pos, all with velocity v_s."""
+    domain, lo, n = W.single_box(nx)
+    ncell = nx ** 3
+    st = np.zeros((5, ncell))
+    st[0] = rho
+    for a in range(3):
+        st[1 + a] = rho * u_gas[a]
+    st[4] = rho * e_sp + 0.5 * rho * float(np.dot(u_gas, u_gas))
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    k = pos.shape[0]
+    f = {"m": np.full(k, m_ej), "e": np.full(k, e_sn), "vx": np.full(k, v_s[0]),
+         "vy": np.full(k, v_s[1]), "vz": np.full(k, v_s[2])}
+    return W.Workload("snr_t", domain, lo, n, 4, 1.0, st.reshape(-1), snr=W._one_box(pos, f),
+                      snr_params=W.SnrParams(r_k=r_k, sub=sub))
+
+
+def snr_fields(orc, w, mode="f64"):
+    """Deposited buffer (owned + ghost, 5 fields, float64 values) and info."""
+    mesh = orc.Mesh.of(w)
+    buf, _, _ = orc.deposit(w, mode, mesh)
+    info = orc.deposit_snr(w, mode, buf, mesh)
+    B = mesh.box_buffer(buf, 0).astype(np.float64)
+    if mode == "fix64":
+        B = B / Q
+    return B, info
+
+
+def kernel_cells(x, r_k, nx, g):
+    """Centre members of the r_K sphere (sub = 1): padded-local indices and
+    the offset of each centre from x (lattice enumeration)."""
+    out = []
+    R = int(math.ceil(r_k)) + 1
+    h = [int(math.floor(c)) for c in x]
+    for k in range(h[2] - R, h[2] + R + 1):
+        for j in range(h[1] - R, h[1] + R + 1):
+            for i in range(h[0] - R, h[0] + R + 1):
+                d = np.array([i + 0.5 - x[0], j + 0.5 - x[1], k + 0.5 - x[2]])
+                if (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2] <= r_k * r_k:
+                    out.append(((k + g, j + g, i + g), d))
+    return out
+
+
+def test_snr_covered_fraction(orc):
+    """sub = 1: the kernel is the 123 centre members of an r = 3 ball (a
+    remnant at a cell centre), V_snr = 123; with 16^3 sample points per cell
+    the covered volume approaches 4/3 pi r^3 (within 0.5%) wherever the
+    remnant sits, and cells wholly inside count 1."""
+    w = snr_uniform(24, 1.0, [(12.5, 12.5, 12.5)], sub=1)
+    _, info = snr_fields(orc, w)
+    assert info[0, 0] == 123.0
+    for pos in [(12.5, 12.5, 12.5), (12.0, 12.0, 12.0), (12.31, 11.77, 12.9)]:
+        w = snr_uniform(24, 1.0, [pos], sub=16)
+        B, info = snr_fields(orc, w)
+        assert abs(info[0, 0] - 4.0 / 3.0 * math.pi * 27.0) < 0.005 * 113.1
+        # the mass share of a cell wholly inside the ball is a whole cell's
+        c = [int(math.floor(p)) + 4 for p in pos]
+        assert B[0, c[2], c[1], c[0]] == pytest.approx(W.SNR_M_EJ / info[0, 0], rel=1e-15)
+
+
+def regime_density(target, r_k=3.0, sub=1, m_ej=W.SNR_M_EJ):
+    """Uniform gas density at which R_M = M_snr / M_sf equals `target` for a
+    centred remnant with sub = 1 (V_snr = 123), by bisection with libm's pow."""
+    V = 123.0
+
+    def rm(rho):
+        msnr = rho * V + m_ej
+        nh = msnr / V * W.SNR_NH_PER_RHO
+        return msnr / (1679.0 * nh ** -0.26)
+    lo, hi = 1e-8, 1e6
+    for _ in range(200):
+        mid = math.sqrt(lo * hi)
+        lo, hi = (mid, hi) if rm(mid) < target else (lo, mid)
+    return lo
+
+
+@pytest.mark.parametrize("mode", ["f64", "fix64"])
+def test_snr_regimes_and_terminal_momentum(orc, mode):
+    """Eqs. "dp" and "psnr" at chosen n_H: uniform gas at rest, a remnant at
+    rest at a cell centre.  MC: |p_rad| = 2.8e4 n_H^-0.17 (code units);
+    ST: sqrt(2 M_ej eps_K E_sn); EJ: 0.  The radial momentum per cell is
+    |p_rad| / N along the cell's direction (N = 123 members, none at the
+    centre cell), so sum |dp| V = |p_rad| (1 - 1/N) and sum dp = 0; the
+    mass and energy totals are M_ej and E_sn (exact in fixed point); the
+    thresholds 1 and 0.027 are strict from below."""
+    x = (12.5, 12.5, 12.5)
+    cells = kernel_cells(x, 3.0, 24, 4)
+    assert len(cells) == 123
+    for target, regime in ((3.0, "MC"), (1.0 + 1e-4, "MC"), (1.0 - 1e-4, "ST"), (0.2, "ST"),
+                           (0.027 + 1e-5, "ST"), (0.027 - 1e-5, "EJ"), (0.005, "EJ")):
+        rho = regime_density(target)
+        w = snr_uniform(24, rho, [x])
+        B, info = snr_fields(orc, w, mode)
+        msnr = rho * 123.0 + W.SNR_M_EJ
+        nh = msnr / 123.0 * W.SNR_NH_PER_RHO
+        # the kernel sums lie on the 2^-40 grid: 123 roundings of at most 2^-41
+        assert info[1, 0] == pytest.approx(msnr, rel=1e-12, abs=123 * 2.0 ** -41)
+        assert info[2, 0] == pytest.approx(nh, rel=1e-12)
+        P = {"MC": 2.8e4 * nh ** -0.17, "ST": math.sqrt(2 * W.SNR_M_EJ * 0.28 * W.SNR_E_SN),
+             "EJ": 0.0}[regime]
+        assert info[3, 0] == pytest.approx(P, rel=1e-12, abs=0.0), (target, regime)
+        dp = np.stack([B[1 + a] for a in range(3)])
+        mag = np.sqrt((dp * dp).sum(axis=0))
+        tol = 1e-12 if mode == "f64" else 1e-9
+        assert mag.sum() == pytest.approx(P * (1.0 - 1.0 / 123.0), rel=tol, abs=1e-9)
+        for a in range(3):
+            assert abs(dp[a].sum()) <= 1e-9 * max(P, 1.0)
+        # each cell's momentum points away from the remnant, |p_rad| / N long
+        for (k, j, i), d in cells[:20]:
+            L = math.sqrt(float(d @ d))
+            if L > 0:
+                assert np.allclose(dp[:, k, j, i], P / 123.0 * d / L, rtol=1e-12, atol=1e-9)
+        if mode == "fix64":
+            assert B[0].sum() * Q == round(W.SNR_M_EJ * Q)
+            assert B[4].sum() * Q == round(W.SNR_E_SN * Q)
+        else:
+            assert B[0].sum() == pytest.approx(W.SNR_M_EJ, rel=1e-14)
+            assert B[4].sum() == pytest.approx(W.SNR_E_SN, rel=1e-14)
+
+
+def test_snr_galilean_covariance(orc):
+    """Boosting gas and remnant by u (sub = 1, closed forms per cell): the
+    mass deposit is unchanged, the momentum deposit gains d rho u (eq. "du":
+    rho_new v_COM - rho v with v_COM and v shifted by u), and the energy
+    deposit gains a (E_kin' - E_kin) + u . p_rad with a = 1/N and
+    p_rad = |p_rad| / N along the cell's direction."""
+    x = (12.3, 11.8, 12.6)
+    cells = kernel_cells(x, 3.0, 24, 4)
+    N = len(cells)
+    rho = regime_density(3.0)
+    v_s = np.array([0.7, -0.4, 0.2])
+    u = np.array([3.0, -1.5, 2.0])
+    w0 = snr_uniform(24, rho, [x], v_s=tuple(v_s), u_gas=(0.2, 0.1, -0.3))
+    w1 = snr_uniform(24, rho, [x], v_s=tuple(v_s + u), u_gas=tuple(np.array([0.2, 0.1, -0.3]) + u))
+    B0, i0 = snr_fields(orc, w0)
+    B1, i1 = snr_fields(orc, w1)
+    P = i0[3, 0]
+    assert P > 0 and i1[3, 0] == P
+    assert np.array_equal(B0[0], B1[0])
+    dEkin = 0.5 * W.SNR_M_EJ * (float((v_s + u) @ (v_s + u)) - float(v_s @ v_s))
+    for (k, j, i), d in cells:
+        dr = B0[0, k, j, i]
+        assert dr == pytest.approx(W.SNR_M_EJ / N, rel=1e-14)
+        for a in range(3):
+            assert B1[1 + a, k, j, i] - B0[1 + a, k, j, i] == pytest.approx(dr * u[a], rel=1e-9,
+                                                                          abs=1e-9)
+        L = math.sqrt(float(d @ d))
+        prad = P / N * d / L if L > 0 else np.zeros(3)
+        want = dEkin / N + float(u @ prad)
+        assert B1[4, k, j, i] - B0[4, k, j, i] == pytest.approx(want, rel=1e-9, abs=1e-6)
+
+
+def test_snr_momentum_conservation_symmetric_kernel(orc):
+    """A remnant at a cell centre in inhomogeneous, moving gas (sub = 4):
+    the covered fractions and the radial directions are symmetric, so the
+    radial momenta cancel and sum dp V = M_ej v_s (the gas within the kernel
+    is brought to v_COM, which conserves its covered momentum)."""
+    rng = np.random.default_rng(5)
+    w = snr_uniform(24, 1.0, [(12.5, 12.5, 12.5)], v_s=(1.5, -2.0, 0.5), sub=4)
+    st = w.state.reshape(5, -1).copy()
+    st[0] = np.exp(rng.standard_normal(st.shape[1]))
+    v = rng.standard_normal((3, st.shape[1]))
+    st[1:4] = st[0] * v
+    st[4] = st[0] * (1.0 + 0.5 * (v * v).sum(axis=0))
+    w = w.with_state(st.reshape(-1))
+    for rho_scale in (1.0, 30.0):
+        ws = w.with_state((st * np.array([[rho_scale]] * 5)).reshape(-1))
+        B, info = snr_fields(orc, ws)
+        assert info[3, 0] > 0
+        tot = [B[1 + a].sum() for a in range(3)]
+        want = W.SNR_M_EJ * np.array([1.5, -2.0, 0.5])
+        assert np.allclose(tot, want, rtol=1e-10, atol=1e-8 * max(info[3, 0], 1.0))
+
+
+def test_snr_superposition_and_permutation_fixed_point(orc):
+    """Each remnant reads the state before the step, so in fixed point the
+    deposit of several overlapping remnants is the sum of their single
+    deposits, and it does not depend on their order."""
+    pts = [(10.2, 11.7, 12.1), (12.9, 12.4, 10.8), (11.1, 13.3, 12.6)]
+    w = W.snr_box(nx=24, n_snr=3, seed=11)
+    w = dataclasses.replace(w, snr=W._one_box(np.array(pts), {k: v[:3] for k, v in
+                                                              w.snr.fields.items()
+                                                              if k not in "xyz"}))
+    mesh = orc.Mesh.of(w)
+
+    def dep(ww):
+        b, _, _ = orc.deposit(ww, "fix64", mesh)
+        orc.deposit_snr(ww, "fix64", b, mesh)
+        return b
+
+    full = dep(w)
+    parts = []
+    for s in range(3):
+        f = {k: v[s:s + 1] for k, v in w.snr.fields.items()}
+        parts.append(dep(dataclasses.replace(w, snr=W.Particles(f, np.array([0, 1])))))
+    assert np.array_equal(full, parts[0] + parts[1] + parts[2])
+    perm = [2, 0, 1]
+    f = {k: v[perm] for k, v in w.snr.fields.items()}
+    assert np.array_equal(full, dep(dataclasses.replace(w, snr=W.Particles(f, np.array([0, 3])))))
+
+
+def test_snr_limiter_binds_and_floor_holds(orc):
+    """Remnants near the density steps of the slab workload: the energy
+    limiter (eq. "lambda") binds on real radial momentum, and after the step
+    every cell keeps e_int >= 0; the three regimes all occur."""
+    w = W.snr_box()
+    r = orc.step(w, "f64")
+    assert r["counters"]["lam"] > 0
+    info = r["snr_info"]
+    rm = info[1] / (1679.0 * info[2] ** -0.26)
+    assert (rm > 1).any() and ((rm > 0.027) & (rm <= 1)).any() and (rm <= 0.027).any()
+    st = r["state"].reshape(5, -1)
+    eint = st[4] - 0.5 * (st[1:4] ** 2).sum(axis=0) / st[0]
+    assert (eint >= -1e-9 * np.abs(st[4])).all()
+
+
+def test_snr_multibox_equals_single_box(orc):
+    """The same gas and remnants on a 3 x 3 x 3 tiling with uneven boxes
+    (kernels crossing faces, edges and the periodic boundary) give, in fixed
+    point, exactly the single box's state."""
+    mb = W.snr_box(nb=3)
+    sb = W.snr_box(nb=1)
+    a = orc.step(mb, "fix64")
+    b = orc.step(sb, "fix64")
+    X = mb.domain[0]
+    assert np.array_equal(to_global(mb, a["state"]), b["state"].reshape(5, X, X, X))
+    assert a["counters"] == b["counters"]
+
+
+def test_snr_parameter_errors(orc):
+    w = snr_uniform(16, 1.0, [(8.5, 8.5, 8.5)])
+    for bad in (dict(sub=3), dict(sub=0), dict(r_k=-1.0), dict(nh_per_rho=0.0),
+                dict(msf_coef=-1.0), dict(sub=32)):
+        ww = dataclasses.replace(w, snr_params=dataclasses.replace(w.snr_params, **bad))
+        with pytest.raises(RuntimeError):
+            snr_fields(orc, ww)
+    # a kernel reaching past the ghost zone: from x = 15.9, sample points of
+    # cell 20 lie within 4.9, five cells beyond the host cell with g = 4
+    ww = snr_uniform(16, 1.0, [(15.9, 8.5, 8.5)], r_k=4.9)
+    with pytest.raises(RuntimeError):
+        snr_fields(orc, ww)
+
+
+@pytest.mark.parametrize("mode", ["f64", "fix64"])
+def test_snr_radial_momentum_with_covered_fractions(orc, mode):
+    """sub = 4, a remnant at rest at a cell centre in uniform gas at rest: each
+    cell receives |p_rad| w / V_snr along its direction, so
+    sum |dp| V = |p_rad| (V_snr - V) / V_snr (the centre cell, wholly covered,
+    has no direction), and the mass shares w M_ej / V_snr sum to M_ej."""
+    rho = regime_density(3.0)
+    w = snr_uniform(24, rho, [(12.5, 12.5, 12.5)], sub=4)
+    B, info = snr_fields(orc, w, mode)
+    P, Vsnr = info[3, 0], info[0, 0]
+    assert P > 0 and 110.0 < Vsnr < 116.0
+    dp = np.stack([B[1 + a] for a in range(3)])
+    mag = np.sqrt((dp * dp).sum(axis=0))
+    tol = 1e-12 if mode == "f64" else 1e-9
+    assert mag.sum() == pytest.approx(P * (Vsnr - 1.0) / Vsnr, rel=tol)
+    # partially covered cells: |dp| / d rho = |p_rad| / M_ej wherever both are set
+    sel = (B[0] > 0) & (mag > 0)
+    assert np.allclose(mag[sel] / B[0][sel], P / W.SNR_M_EJ, rtol=1e-6)
+    frac = B[0][sel] * Vsnr / W.SNR_M_EJ
+    assert (frac < 0.999).sum() > 50  # fractional cells present
