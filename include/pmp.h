@@ -335,6 +335,23 @@ int pmp_sink_create(pmp_ctx *ctx, void *state, const void *buf, const pmp_sinks 
                     double r_k, const pmp_limits *limits, int64_t max_new, double *out,
                     int64_t *work, void *stream);
 
+/* pmp_sink_create for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * passes and results, with the key list and rank accumulators held in a
+ * static device array of the library (2 * 65536 + 1 int64, 1 MiB, one copy
+ * per GPU, kept until the process ends) instead of a caller's work array.
+ *   count  device int64 [1]: receives the number of qualifying cells (as
+ *          work[0] of pmp_sink_create); nothing is created when it exceeds
+ *          max_new.
+ * Other arguments and limits as pmp_sink_create (max_new at most 65536,
+ * else PMP_EINVAL).  Calls no hipMalloc, hipFree or allocating routine.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (on different streams, or from several threads) race and must be
+ * serialised by the caller. */
+int pmp_sink_create_noalloc(pmp_ctx *ctx, void *state, const void *buf,
+                            const pmp_sinks *existing, double r_k, const pmp_limits *limits,
+                            int64_t max_new, double *out, int64_t *count, void *stream);
+
 /* One whole step: deposit, fold, sink update (if sinks), apply.  sink_out
  * (device) is four float64 arrays [4][sinks->n] (dm, dpx, dpy, dpz) or NULL
  * without sinks. */

@@ -122,6 +122,8 @@ SIGNATURES = [
     ("pmp_apply", _I, [_VP, _VP, _VP, C.POINTER(pmp_limits), _VP, _VP]),
     ("pmp_sink_create", _I, [_VP, _VP, _VP, C.POINTER(pmp_sinks), C.c_double,
                              C.POINTER(pmp_limits), C.c_int64, _VP, _VP, _VP]),
+    ("pmp_sink_create_noalloc", _I, [_VP, _VP, _VP, C.POINTER(pmp_sinks), C.c_double,
+                                     C.POINTER(pmp_limits), C.c_int64, _VP, _VP, _VP]),
     ("pmp_step", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
                       C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP, _VP]),
     ("pmp_step_per_box", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
@@ -319,6 +321,20 @@ class Context:
               None if ex is None else C.byref(ex), float(r_k), C.byref(lim), int(max_new),
               _ptr(out), _ptr(work), _stream(stream))
         return out, work
+
+    def sink_create_noalloc(self, r_k, rho_tr, max_new, buf=True, limits=None, existing=None,
+                            stream=None):
+        """pmp_sink_create_noalloc: as sink_create, with the library's static
+        scratch; returns (out [7][max_new], count [1]) device arrays."""
+        import torch
+        out = torch.zeros(7 * max(int(max_new), 1), dtype=torch.float64, device=self.device)
+        count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        lim = limits_of(self.w.limits, rho_tr) if limits is None else limits_of(limits)
+        ex = self._positions(existing)
+        _call("pmp_sink_create_noalloc", self.h, _ptr(self.state),
+              _ptr(self.buf) if buf else None, None if ex is None else C.byref(ex), float(r_k),
+              C.byref(lim), int(max_new), _ptr(out), _ptr(count), _stream(stream))
+        return out, count
 
     def _positions(self, existing):
         """pmp_sinks holding only the positions of ``existing`` (see sink_create)."""

@@ -7,12 +7,19 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "pmp_internal.h"
 
 using namespace pmp;
+
+// Scratch of pmp_sink_create_noalloc: the creation passes' key list and rank
+// accumulators (count, kCreateMax keys, kCreateMax ranks).  Every GPU the
+// library runs on holds its own copy until the process ends; host code uses
+// only the per-device address from hipGetSymbolAddress (noalloc_scratch).
+static __device__ __align__(256) long long scratch[2 * kCreateMax + 1];
 
 namespace {
 
@@ -34,6 +41,28 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess)                                                                  \
       return fail(PMP_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));             \
   } while (0)
+
+// Device address of `scratch` per device, looked up once per device (with
+// that device current) by pmp_create.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+long long* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(int device, long long** out) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(PMP_EDEVICE, "device %d outside the scratch table (%d devices)", device,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PMP_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = (long long*)p;
+  }
+  *out = g_scratch_ptr[device];
+  return PMP_OK;
+}
 
 template <class T> hipError_t dev_alloc(T** p, size_t count) {
   return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
@@ -117,6 +146,7 @@ struct pmp_ctx {
   std::vector<DevBox> dboxes;
   long long state_elems = 0, buffer_elems = 0, owned_cells = 0, shell_cells = 0;
   bool tiles_domain = false;  // the boxes (disjoint, inside the domain) own every cell
+  long long* noalloc_scratch = nullptr;  // this device's `scratch` (pmp_sink_create_noalloc)
   int nseg = 0;
   // device allocations
   DevBox* d_boxes = nullptr;
@@ -1024,6 +1054,10 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
     delete c;
     return fail(PMP_EDEVICE, "no HIP device");
   }
+  if (noalloc_scratch(c->device, &c->noalloc_scratch) != PMP_OK) {
+    delete c;
+    return PMP_EDEVICE;
+  }
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) ==
           hipSuccess && ncu > 0)
@@ -1289,7 +1323,7 @@ int pmp_apply(pmp_ctx* c, void* state, const void* buf, const pmp_limits* limits
 
 namespace {
 
-// Argument checks of the sink creation entry point; E receives
+// Argument checks shared by the two sink creation entry points; E receives
 // the existing sinks' positions.
 int create_checks(const pmp_ctx* c, const void* state, const pmp_sinks* existing, double r_k,
                   const pmp_limits* limits, int64_t max_new, const double* out, SinkPos& E) {
@@ -1333,6 +1367,22 @@ int pmp_sink_create(pmp_ctx* c, void* state, const void* buf, const pmp_sinks* e
   if (!work) return fail(PMP_EINVAL, "work is NULL");
   PMP_HIP(launch_sink_create(c->mesh(), state, buf, E, r_k, to_limits(c, limits),
                              (long long)max_new, out, (long long*)work, (hipStream_t)stream));
+  return PMP_OK;
+}
+
+int pmp_sink_create_noalloc(pmp_ctx* c, void* state, const void* buf,
+                            const pmp_sinks* existing, double r_k, const pmp_limits* limits,
+                            int64_t max_new, double* out, int64_t* count, void* stream) {
+  SinkPos E;
+  int rc = create_checks(c, state, existing, r_k, limits, max_new, out, E);
+  if (rc) return rc;
+  if (!count) return fail(PMP_EINVAL, "count is NULL");
+  if (!c->noalloc_scratch) return fail(PMP_EDEVICE, "no scratch address for this device");
+  hipStream_t s = (hipStream_t)stream;
+  long long* work = c->noalloc_scratch;  // count, keys, ranks (2 kCreateMax + 1)
+  PMP_HIP(launch_sink_create(c->mesh(), state, buf, E, r_k, to_limits(c, limits),
+                             (long long)max_new, out, work, s));
+  PMP_HIP(hipMemcpyAsync(count, work, sizeof(long long), hipMemcpyDeviceToDevice, s));
   return PMP_OK;
 }
 
