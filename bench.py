@@ -132,7 +132,8 @@ def kernel_method_bytes(w, acc, counts, F, fused):
 def touched_counts(B, w, acc):
     """Unique (cell, field) pairs each particle kind writes, counted as the
     nonzero buffer entries after depositing that kind alone (all
-    contributions are positive)."""
+    contributions are positive), on the direct path so that the timed
+    kernels' profile holds only the timed launches."""
     import dataclasses
     import torch
     counts = {}
@@ -146,6 +147,7 @@ def touched_counts(B, w, acc):
         if kind != "sinks" and w.sinks is not None:
             wk = dataclasses.replace(wk, sinks=None)
         ctx = B.Context(wk, acc)
+        ctx.set_tuning(deposit_path=0)
         ctx.deposit()
         torch.cuda.synchronize()
         counts["sink" if kind == "sinks" else kind] = int(torch.count_nonzero(ctx.buf).item())
@@ -523,7 +525,9 @@ def main():
                     help="gas state type (the workload's FP32 draw, promoted for f64)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
-    ap.add_argument("--no-calib", action="store_true")
+    ap.add_argument("--no-calib", action="store_true", help="skip the copy and atomic peaks")
+    ap.add_argument("--no-atomics", action="store_true", help="skip the atomic peaks")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 path")
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--set", default="", help="tuning overrides, e.g. deposit_path=0,tile_x=32")
     ap.add_argument("--no-autotune", action="store_true",
@@ -639,18 +643,21 @@ def main():
             modes["f64r_state_" + str(w.state.dtype)] = run_mode(
                 B, w, "f64r", counts, args, {"deposit_path": 1}, False, max(5, args.steps // 2))
         out["modes"] = modes
+        out["reproducibility"] = repro_rates(B, w, args.channels)
+        log(f"reproducibility: {out['reproducibility']}")
+    if not args.no_plain:
         # the plain FP64 path: zero fill, direct global atomics, separate
         # fold and apply, no binning or fusion
-        plain = run_mode(B, w, "f64", counts, args, {"deposit_path": 0, "fuse_apply": 0},
+        wp = w if args.state == "f64" else w32.with_state(w32.state.astype(np.float64))
+        plain = run_mode(B, wp, "f64", counts, args, {"deposit_path": 0, "fuse_apply": 0},
                          False, max(5, args.steps // 2))
         out["plain_f64"] = plain
         out["speedup_vs_plain_f64"] = plain["ms_per_step"] / ms
         log(f"plain f64: {plain['ms_per_step']:.4f} ms")
-        out["reproducibility"] = repro_rates(B, w, args.channels)
-        log(f"reproducibility: {out['reproducibility']}")
     if not args.no_calib:
         out["copy_GBps"] = copy_gbps(B)
         log(f"copy: {out['copy_GBps']}")
+    if not args.no_calib and not args.no_atomics:
         rates = atomic_rates(B)
         out["atomics_per_s"] = rates
         log(f"atomics: {rates}")
