@@ -129,6 +129,25 @@ typedef struct {
   double r_max;                         /* host: largest r, for the ghost check */
 } pmp_sn;
 
+/* Supernova remnants with the variant of the TIGRESS prescription of
+ * Sec. 3.2.1 (eqs. "du", "dp", "psnr"), deposited by pmp_deposit_snr.  Code
+ * units throughout: nh_per_rho converts a mass density to the number density
+ * of H nuclei in cm^-3 (1 / (mu_H m_H)); msf_coef and psnr_coef are the
+ * shell-formation mass and the terminal momentum at n_H = 1 cm^-3 (1679 Msun
+ * and 2.8e5 Msun km/s in the paper); eps_k the kinetic fraction of the
+ * Sedov-Taylor phase (0.28). */
+typedef struct {
+  const double *x, *y, *z;        /* device [n]: position (cells) */
+  const double *m, *e;            /* device [n]: ejecta mass M_ej, supernova energy E_sn */
+  const double *vx, *vy, *vz;     /* device [n]: velocity of the exploding particle */
+  int64_t n;
+  const int64_t *box_off;         /* device [nbox+1] */
+  double r_k;                     /* kernel radius r_K (cells), 0 .. 16 */
+  int32_t sub;                    /* sample points per axis for the covered fraction:
+                                     1, 2, 4, 8 or 16 */
+  double nh_per_rho, msf_coef, psnr_coef, eps_k;  /* > 0, > 0, >= 0, >= 0, finite */
+} pmp_snr;
+
 /* Sink request rates (pmp_sinks.rate). */
 typedef enum {
   PMP_SINK_FRACTION = 0,  /* the fraction a of the kernel gas mass, Gaussian width r_gauss */
@@ -277,6 +296,37 @@ int pmp_deposit(pmp_ctx *ctx, void *buf, const void *state, const pmp_cic *cic,
                 const pmp_sn *sn, const pmp_sinks *sinks, const pmp_limits *limits,
                 void *stream);
 
+/* Step 1 for supernova remnants (Sec. 3.2.1, eqs. "du", "dp", "psnr"):
+ * adds each remnant's deposition function to a buffer that pmp_deposit has
+ * filled (call it after pmp_deposit, before pmp_ghost_fold).  Per remnant s:
+ *   kernel   cells with a covered fraction w > 0, w = the share of the cell's
+ *            sub^3 sub-cell centres within r_K (squared distance <= r_K^2);
+ *            the host cell alone (w = 1) when no sample point is that close;
+ *   sums     on the 2^-40 grid: V_snr = sum w V, M_gas = sum w rho V,
+ *            P_gas = sum w p V, the state read in place in the box that owns
+ *            each (periodically wrapped) cell;
+ *   regime   M_snr = M_gas + M_ej, n_H = nh_per_rho M_snr / V_snr,
+ *            R_M = M_snr / (msf_coef n_H^-0.26); |p_rad| = psnr_coef
+ *            n_H^-0.17 if R_M > 1 (MC), sqrt(2 M_ej eps_k E_sn) if
+ *            0.027 < R_M <= 1 (ST), else 0 (EJ);
+ *   deposit  v_COM = (P_gas + M_ej v_s) / M_snr, E_kin = M_ej |v_s|^2 / 2; per
+ *            cell with a = w / V_snr and rhat the unit vector from the
+ *            remnant to the cell centre (0 at the remnant):
+ *            d rho = a M_ej, d p = w ((rho + M_ej / V_snr) v_COM - p) +
+ *            a |p_rad| rhat, d E = a (E_sn + E_kin) + v_COM . a |p_rad| rhat.
+ * The powers come from the library's own log and exp (same bits as the
+ * reference implementation).  In PMP_ACC_FIX64 every term is rounded on the
+ * 2^-40 grid and the rounding residues of the mass and of the injected energy
+ * go to the host cell (else the first kernel cell in (k, j, i) order), so
+ * they land exactly.  The layout needs the rho, momentum and E channels.
+ * state (device) is the state the deposit reads (before the step); info
+ * (device float64 [4][n], may be NULL) receives V_snr, M_snr, n_H and
+ * |p_rad| per remnant.  Errors: PMP_EINVAL (arguments, missing channels),
+ * PMP_ERANGE (floor(r_K + 1 - 1/(2 sub)) > ghost width),
+ * PMP_EUNSUPPORTED (PMP_ACC_F64R). */
+int pmp_deposit_snr(pmp_ctx *ctx, void *buf, const void *state, const pmp_snr *snr,
+                    double *info, void *stream);
+
 /* Step 2 (Sec. 2.2; App. A.2).  Adds every ghost cell into the owned cell of
  * the box that holds its periodic image; each owned cell gathers its
  * contributions in one fixed order (source box lo z, y, x, then periodic
@@ -406,7 +456,7 @@ int pmp_autotune(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic, const
  * per phase.  pmp_profile_end synchronises, writes the summed kernel time in
  * milliseconds and the launch count of each phase to the host arrays ms and
  * launches [PMP_NPHASE] (either may be NULL) and stops profiling. */
-#define PMP_NPHASE 9
+#define PMP_NPHASE 10
 #define PMP_PHASE_ZERO 0          /* direct path: zero fill of the buffer */
 #define PMP_PHASE_CIC 1           /* direct path: CIC atomics */
 #define PMP_PHASE_SN 2            /* direct path: supernova atomics */
@@ -421,6 +471,7 @@ int pmp_autotune(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic, const
 #define PMP_PHASE_TILE 8          /* binned path: the tile kernel alone (LDS
                                      accumulation and store; in a fused step also
                                      the interior cells' limiter + apply) */
+#define PMP_PHASE_SNR 9           /* supernova remnants (pmp_deposit_snr) */
 int pmp_profile_begin(pmp_ctx *ctx, int max_launches);
 int pmp_profile_end(pmp_ctx *ctx, double *ms, int64_t *launches);
 

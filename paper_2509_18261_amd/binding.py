@@ -56,6 +56,14 @@ class pmp_sn(C.Structure):
                 ("r_max", C.c_double)]
 
 
+class pmp_snr(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("m", C.c_void_p),
+                ("e", C.c_void_p), ("vx", C.c_void_p), ("vy", C.c_void_p), ("vz", C.c_void_p),
+                ("n", C.c_int64), ("box_off", C.c_void_p), ("r_k", C.c_double),
+                ("sub", C.c_int32), ("nh_per_rho", C.c_double), ("msf_coef", C.c_double),
+                ("psnr_coef", C.c_double), ("eps_k", C.c_double)]
+
+
 PMP_SINK_FRACTION, PMP_SINK_BONDI = 0, 1
 
 
@@ -102,8 +110,9 @@ class pmp_tuning(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
-NPHASE = 9
-PHASES = ["zero", "cic", "sn", "sink_deposit", "fold", "sink_update", "apply", "bin", "tile"]
+NPHASE = 10
+PHASES = ["zero", "cic", "sn", "sink_deposit", "fold", "sink_update", "apply", "bin", "tile",
+          "snr"]
 
 _VP, _I = C.c_void_p, C.c_int
 # (name, restype, argtypes) for every exported function of include/pmp.h
@@ -116,6 +125,7 @@ SIGNATURES = [
     ("pmp_set_workspace", _I, [_VP, _VP, C.c_size_t]),
     ("pmp_deposit", _I, [_VP, _VP, _VP, C.POINTER(pmp_cic), C.POINTER(pmp_sn),
                          C.POINTER(pmp_sinks), C.POINTER(pmp_limits), _VP]),
+    ("pmp_deposit_snr", _I, [_VP, _VP, _VP, C.POINTER(pmp_snr), _VP, _VP]),
     ("pmp_ghost_fold", _I, [_VP, _VP, _VP]),
     ("pmp_sink_update", _I, [_VP, _VP, _VP, C.POINTER(pmp_sinks), C.POINTER(pmp_limits),
                              _VP, _VP, _VP, _VP, _VP]),
@@ -228,6 +238,13 @@ class Context:
         rate = int(getattr(w, "sink_rate", PMP_SINK_FRACTION))
         names = ["x", "y", "z", "a"] + (["m", "vx", "vy", "vz"] if rate == PMP_SINK_BONDI else [])
         self.sinks = self._kind(w.sinks, names, pmp_sinks)
+        self.snr = self._kind(getattr(w, "snr", None),
+                              ["x", "y", "z", "m", "e", "vx", "vy", "vz"], pmp_snr)
+        if self.snr is not None:
+            P = w.snr_params
+            self.snr.r_k, self.snr.sub = float(P.r_k), int(P.sub)
+            self.snr.nh_per_rho, self.snr.msf_coef = float(P.nh_per_rho), float(P.msf_coef)
+            self.snr.psnr_coef, self.snr.eps_k = float(P.psnr_coef), float(P.eps_k)
         self.sink_out = None
         if self.sinks is not None:
             self.sinks.r_k = float(w.r_k)
@@ -286,6 +303,13 @@ class Context:
     def deposit(self, stream=None):
         _call("pmp_deposit", self.h, _ptr(self.buf), _ptr(self.state), self._r(self.cic),
               self._r(self.sn), self._r(self.sinks), C.byref(self.lim), _stream(stream))
+
+    def deposit_snr(self, info=None, stream=None):
+        """Add the supernova remnants (TIGRESS variant) to the deposited buffer."""
+        if self.snr is None:
+            return
+        _call("pmp_deposit_snr", self.h, _ptr(self.buf), _ptr(self.state), C.byref(self.snr),
+              _ptr(info), _stream(stream))
 
     def ghost_fold(self, stream=None):
         _call("pmp_ghost_fold", self.h, _ptr(self.buf), _stream(stream))
@@ -439,6 +463,8 @@ def channel_bits(w, channels):
         ch |= PMP_CH_RHO | PMP_CH_E
     if w.nfield == 6:
         ch |= PMP_CH_K
+    if getattr(w, "snr", None) is not None and w.snr.n > 0:
+        ch |= PMP_CH_RHO | PMP_CH_MOM | PMP_CH_E
     return ch or PMP_CH_RHO
 
 

@@ -1301,6 +1301,42 @@ int pmp_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, co
   return do_deposit(c, buf, state, cic, sn, sinks, limits, (hipStream_t)stream);
 }
 
+int pmp_deposit_snr(pmp_ctx* c, void* buf, const void* state, const pmp_snr* snr,
+                    double* info, void* stream) {
+  if (!c) return fail(PMP_EINVAL, "NULL context");
+  if (!buf || !state || !snr) return fail(PMP_EINVAL, "buffer, state and remnants must be non-NULL");
+  if (c->acc == PMP_ACC_F64R)
+    return fail(PMP_EUNSUPPORTED, "supernova remnants: not in the reproducibility mode");
+  if (snr->n < 0) return fail(PMP_EINVAL, "supernova remnants: negative count");
+  if (snr->n == 0) return PMP_OK;
+  if (!snr->x || !snr->y || !snr->z || !snr->m || !snr->e || !snr->vx || !snr->vy || !snr->vz ||
+      !snr->box_off)
+    return fail(PMP_EINVAL, "supernova remnant arrays must be non-NULL");
+  if (!(snr->r_k >= 0.0) || !(snr->r_k <= 16.0)) return fail(PMP_EINVAL, "r_k must lie in [0, 16]");
+  if (snr->sub < 1 || snr->sub > 16 || (snr->sub & (snr->sub - 1)) != 0)
+    return fail(PMP_EINVAL, "sub must be 1, 2, 4, 8 or 16");
+  if (!(snr->nh_per_rho > 0.0) || !(snr->msf_coef > 0.0) || !(snr->psnr_coef >= 0.0) ||
+      !(snr->eps_k >= 0.0) || !std::isfinite(snr->nh_per_rho) || !std::isfinite(snr->msf_coef) ||
+      !std::isfinite(snr->psnr_coef) || !std::isfinite(snr->eps_k))
+    return fail(PMP_EINVAL, "bad remnant parameters (nh_per_rho, msf_coef > 0; psnr_coef, eps_k >= 0)");
+  for (int f = 0; f < 5; ++f)
+    if (c->slot[f] < 0)
+      return fail(PMP_EINVAL, "supernova remnants need the rho, momentum and E channels");
+  if (std::floor(snr->r_k + 1.0 - 0.5 / snr->sub) > c->ghost)
+    return fail(PMP_ERANGE, "remnant kernel reach exceeds the ghost width %d", c->ghost);
+  SnrArgs A{};
+  A.x = snr->x; A.y = snr->y; A.z = snr->z; A.m = snr->m; A.e = snr->e;
+  A.vx = snr->vx; A.vy = snr->vy; A.vz = snr->vz;
+  A.n = snr->n;
+  A.box_off = (const long long*)snr->box_off;
+  A.r_k = snr->r_k; A.sub = snr->sub;
+  A.nh_per_rho = snr->nh_per_rho; A.msf_coef = snr->msf_coef;
+  A.psnr_coef = snr->psnr_coef; A.eps_k = snr->eps_k;
+  PhaseTimer t(c, PMP_PHASE_SNR, (hipStream_t)stream);
+  PMP_HIP(launch_snr_deposit(c->mesh(), A, state, buf, info, (hipStream_t)stream));
+  return PMP_OK;
+}
+
 int pmp_ghost_fold(pmp_ctx* c, void* buf, void* stream) {
   if (!c || !buf) return fail(PMP_EINVAL, "NULL argument");
   return do_fold(c, buf, (hipStream_t)stream);

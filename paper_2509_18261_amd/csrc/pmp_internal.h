@@ -260,6 +260,17 @@ hipError_t launch_sink_update(const Mesh& M, const Particles& P, const void* sta
                               const void* buf, const double* sink_scratch, const SinkParams& K,
                               const Limits& L, double* dm, double* dpx, double* dpy,
                               double* dpz, hipStream_t s);
+// Supernova remnants with the TIGRESS-variant deposit (pmp_snr).
+struct SnrArgs {
+  const double *x, *y, *z, *m, *e, *vx, *vy, *vz;
+  long long n;
+  const long long* box_off;
+  double r_k, nh_per_rho, msf_coef, psnr_coef, eps_k;
+  int sub;
+};
+hipError_t launch_snr_deposit(const Mesh& M, const SnrArgs& A, const void* state, void* buf,
+                              double* info, hipStream_t s);
+
 // Largest output list of one sink creation call (the index sort is
 // quadratic in the number of new sinks).
 constexpr long long kCreateMax = 65536;

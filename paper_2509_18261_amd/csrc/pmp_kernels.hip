@@ -65,6 +65,48 @@ __device__ double kernel_exp(double x) {
   return ldexp(p, (int)k);
 }
 
+// Natural logarithm for the power laws of the supernova-remnant deposit
+// (Sec. 3.2.1: M_sf and P_snr), from the series ln m = 2 atanh(s) =
+// 2 (s + s^3/3 + ... + s^23/23), s = (m - 1)/(m + 1), on m in [sqrt(1/2),
+// sqrt(2)) after x = m 2^e (|s| <= 0.172, omitted terms below 2^-60
+// relative), Horner's rule, plus e ln 2 with the head/tail split of
+// kernel_exp (e * head exact).
+__device__ double kernel_log(double x) {
+  if (x != x || x < 0.0) return __builtin_nan("");
+  if (x == 0.0) return -__builtin_huge_val();
+  if (__builtin_isinf(x)) return x;
+  int e;
+  double m = frexp(x, &e);
+  if (m < 0x1.6a09e667f3bcdp-1) {  // sqrt(1/2), rounded to double
+    m = m * 2.0;
+    e = e - 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double s2 = s * s;
+  double t = 1.0 / 23.0;
+  t = t * s2 + 1.0 / 21.0;
+  t = t * s2 + 1.0 / 19.0;
+  t = t * s2 + 1.0 / 17.0;
+  t = t * s2 + 1.0 / 15.0;
+  t = t * s2 + 1.0 / 13.0;
+  t = t * s2 + 1.0 / 11.0;
+  t = t * s2 + 1.0 / 9.0;
+  t = t * s2 + 1.0 / 7.0;
+  t = t * s2 + 1.0 / 5.0;
+  t = t * s2 + 1.0 / 3.0;
+  t = t * s2 + 1.0;
+  const double lnm = (2.0 * s) * t;
+  const double ln2_head = 0x1.62e42ffp-1;
+  const double ln2_tail = -0x1.718432a1b0e26p-35;
+  const double k = (double)e;
+  return k * ln2_head + (k * ln2_tail + lnm);
+}
+
+// x^a = exp(a ln x), x > 0.
+__device__ __forceinline__ double kernel_pow(double x, double a) {
+  return kernel_exp(a * kernel_log(x));
+}
+
 __device__ __forceinline__ void raise_flag(DevStatus* st, unsigned f) {
   atomicOr(&st->flags, f);
 }
@@ -1061,6 +1103,249 @@ __global__ __launch_bounds__(kSinkBlock) void k_sink_update(Mesh M, Particles P,
       dpx[s] = sx;
       dpy[s] = sy;
       dpz[s] = sz;
+    }
+  }
+}
+
+// ----------------------------------------- supernova remnants (TIGRESS)
+
+// Sample points of cell (i, j, k) within the sphere of squared radius r2
+// around (x, y, z): the centres of its ns^3 sub-cells of edge 1/ns (ns a
+// power of two, so every coordinate is exact), each tested as
+// (dx^2 + dy^2) + dz^2 <= r2.
+__device__ __forceinline__ int covered_samples(double x, double y, double z, double r2, int i,
+                                               int j, int k, int ns) {
+  int c = 0;
+  const double inv = 1.0 / (double)ns;  // a power of two: exact
+  for (int c3 = 0; c3 < ns; ++c3) {
+    const double dz = ((double)k + ((double)c3 + 0.5) * inv) - z;
+    const double dz2 = dz * dz;
+    for (int c2 = 0; c2 < ns; ++c2) {
+      const double dy = ((double)j + ((double)c2 + 0.5) * inv) - y;
+      const double dy2 = dy * dy;
+      for (int c1 = 0; c1 < ns; ++c1) {
+        const double dx = ((double)i + ((double)c1 + 0.5) * inv) - x;
+        c += ((dx * dx + dy2) + dz2 <= r2) ? 1 : 0;
+      }
+    }
+  }
+  return c;
+}
+
+// Supernova remnants with the variant of the TIGRESS prescription of
+// Sec. 3.2.1 (eqs. "du", "dp", "psnr").  One workgroup per remnant; lanes
+// over the candidate cells [floor(x - r_K) - 1, floor(x + r_K) + 1]^3.
+//   kernel   cells with a covered fraction w = (sample points within r_K) /
+//            sub^3 > 0, or the host cell alone (w = 1) if there are none;
+//   sums     V_snr = sum w V, M_gas = sum w rho V, P_gas = sum w p V on the
+//            2^-40 grid (exact and order-free), the state read in the box
+//            that owns each (periodically wrapped) cell;
+//   scalars  M_snr = M_gas + M_ej, n_H = (M_snr / V_snr) nh_per_rho,
+//            R_M = M_snr / (msf_coef n_H^-0.26), |p_rad| = psnr_coef
+//            n_H^-0.17 (R_M > 1), sqrt(2 M_ej eps_K E_sn) (0.027 < R_M <= 1)
+//            or 0, v_COM = (P_gas + M_ej v_s) / M_snr, E_kin = M_ej |v_s|^2/2;
+//   deposit  per cell, a = w / V_snr and rhat from the remnant to the cell
+//            centre (0 at the remnant): d rho = a M_ej, d p = w ((rho + M_ej /
+//            V_snr) v_COM - p) + a |p_rad| rhat, d E = a (E_sn + E_kin) +
+//            v_COM . (a |p_rad| rhat), added to the remnant's own box (its
+//            ghost zone where the kernel leaves the box).
+// Fixed point rounds every term on the 2^-40 grid; the mass and the injected
+// energy keep the remainder rule (the residues of rint(M_ej / V 2^40) and
+// rint((E_sn + E_kin) / V 2^40) to the host cell if it is a kernel cell,
+// else to the first in (k, j, i) order).  info (nullable) [4][n]: V_snr,
+// M_snr, n_H, |p_rad|.
+template <int ACC, class S>
+__global__ __launch_bounds__(kSinkBlock) void k_snr_deposit(Mesh M, SnrArgs A,
+                                                    const S* __restrict__ state,
+                                                    typename AccT<ACC>::T* __restrict__ buf,
+                                                    double* __restrict__ info) {
+  constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
+  using T = typename AccT<ACC>::T;
+  const int lane = threadIdx.x;
+  const int g = M.ghost;
+  const double r2 = A.r_k * A.r_k;
+  const int ns = A.sub;
+  const double nsamp = (double)ns * (double)ns * (double)ns;
+  for (long long s = blockIdx.x; s < A.n; s += gridDim.x) {
+    const DevBox B = M.all_boxes[particle_box(A.box_off, M.nbox, s)];
+    const double x = A.x[s], y = A.y[s], z = A.z[s];
+    int h[3];
+    if (!host_cell(B, x, y, z, h)) {
+      if (lane == 0) raise_flag(M.status, PMP_FLAG_OUTSIDE);
+      continue;
+    }
+    const double Mej = A.m[s], Esn = A.e[s];
+    const double vs[3] = {A.vx[s], A.vy[s], A.vz[s]};
+    int lo[3];
+    const double pos[3] = {x, y, z};
+    for (int a = 0; a < 3; ++a) lo[a] = (int)floor(pos[a] - A.r_k) - 1;
+    const int cx = (int)floor(x + A.r_k) + 1 - lo[0] + 1;
+    const int cy = (int)floor(y + A.r_k) + 1 - lo[1] + 1;
+    const int cz = (int)floor(z + A.r_k) + 1 - lo[2] + 1;
+    const int cxy = cx * cy, total = cxy * cz;
+    // the kernel: some sample point within r_K (the host cell's nearest one
+    // is the usual witness), else the host cell alone
+    int any = covered_samples(x, y, z, r2, h[0], h[1], h[2], ns) > 0;
+    if (!any) {
+      for (int t = lane; t < total && !any; t += kSinkBlock) {
+        const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
+        any = covered_samples(x, y, z, r2, lo[0] + ii, lo[1] + jj, lo[2] + kk, ns) > 0;
+      }
+      any = block_max(any);
+    }
+    const bool alone = !any;
+    long long qV = 0, qM = 0, qx = 0, qy = 0, qz = 0;
+    bool ok = true, reach_bad = false;
+    int first = 0x7fffffff, hostm = 0;
+    for (int t = lane; t < total; t += kSinkBlock) {
+      const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
+      const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
+      const bool is_host = (i == h[0] && j == h[1] && k == h[2]);
+      double w;
+      if (alone) {
+        if (!is_host) continue;
+        w = 1.0;
+      } else {
+        const int c = covered_samples(x, y, z, r2, i, j, k, ns);
+        if (c == 0) continue;
+        w = (double)c / nsamp;
+      }
+      first = min(first, t);
+      hostm |= is_host ? 1 : 0;
+      CellLoc Lc;
+      if (!locate(M, i, j, k, Lc)) {
+        reach_bad = true;
+        continue;
+      }
+      const long long c0 = Lc.s, nc = Lc.B->ncell;
+      long long a0, a1, a2, a3, a4;
+      if (!quantise(w * M.V, a0) || !quantise((w * (double)state[c0]) * M.V, a1) ||
+          !quantise((w * (double)state[c0 + nc]) * M.V, a2) ||
+          !quantise((w * (double)state[c0 + 2 * nc]) * M.V, a3) ||
+          !quantise((w * (double)state[c0 + 3 * nc]) * M.V, a4)) {
+        ok = false;
+        continue;
+      }
+      qV += a0; qM += a1; qx += a2; qy += a3; qz += a4;
+    }
+    qV = block_sum(qV);
+    qM = block_sum(qM);
+    qx = block_sum(qx);
+    qy = block_sum(qy);
+    qz = block_sum(qz);
+    const double Vsnr = (double)qV * kFixInv;
+    if (!(Vsnr > 0.0)) {
+      if (lane == 0) raise_flag(M.status, PMP_FLAG_NAN);
+      continue;
+    }
+    const double Msnr = (double)qM * kFixInv + Mej;
+    const double nH = (Msnr / Vsnr) * A.nh_per_rho;
+    const double Msf = A.msf_coef * kernel_pow(nH, -0.26);
+    const double RM = Msnr / Msf;
+    double P = 0.0;
+    if (RM > 1.0) P = A.psnr_coef * kernel_pow(nH, -0.17);
+    else if (RM > 0.027) P = sqrt(((2.0 * Mej) * A.eps_k) * Esn);
+    const double vc[3] = {((double)qx * kFixInv + Mej * vs[0]) / Msnr,
+                          ((double)qy * kFixInv + Mej * vs[1]) / Msnr,
+                          ((double)qz * kFixInv + Mej * vs[2]) / Msnr};
+    const double Ekin = (0.5 * Mej) * ((vs[0] * vs[0] + vs[1] * vs[1]) + vs[2] * vs[2]);
+    const double Eall = Esn + Ekin;
+    const double dens_ej = Mej / Vsnr;
+    if (info != nullptr && lane == 0) {
+      info[s] = Vsnr;
+      info[A.n + s] = Msnr;
+      info[2 * A.n + s] = nH;
+      info[3 * A.n + s] = P;
+    }
+    T* f0 = buf + B.boff + M.slot[0] * B.npad;
+    T* f1 = buf + B.boff + M.slot[1] * B.npad;
+    T* f2 = buf + B.boff + M.slot[2] * B.npad;
+    T* f3 = buf + B.boff + M.slot[3] * B.npad;
+    T* f4 = buf + B.boff + M.slot[4] * B.npad;
+    long long qr_sum = 0, qe_sum = 0;
+    for (int t = lane; t < total; t += kSinkBlock) {
+      const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
+      const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
+      double w;
+      if (alone) {
+        if (!(i == h[0] && j == h[1] && k == h[2])) continue;
+        w = 1.0;
+      } else {
+        const int c = covered_samples(x, y, z, r2, i, j, k, ns);
+        if (c == 0) continue;
+        w = (double)c / nsamp;
+      }
+      CellLoc Lc;
+      long long idx;
+      if (!locate(M, i, j, k, Lc) || !pad_index(B, g, i, j, k, idx)) {
+        reach_bad = true;
+        continue;
+      }
+      const long long c0 = Lc.s, nc = Lc.B->ncell;
+      const double rho = (double)state[c0];
+      const double pc[3] = {(double)state[c0 + nc], (double)state[c0 + 2 * nc],
+                            (double)state[c0 + 3 * nc]};
+      const double aw = w / Vsnr;
+      const double dr = aw * Mej;
+      const double d[3] = {((double)i + 0.5) - x, ((double)j + 0.5) - y,
+                           ((double)k + 0.5) - z};
+      const double len = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+      const double pr = aw * P;
+      double prad[3], dp[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        prad[a] = (len > 0.0) ? pr * (d[a] / len) : 0.0;
+        dp[a] = w * ((rho + dens_ej) * vc[a] - pc[a]) + prad[a];
+      }
+      const double einj = aw * Eall;
+      const double ecross = (vc[0] * prad[0] + vc[1] * prad[1]) + vc[2] * prad[2];
+      if constexpr (FIXED) {
+        long long q0, q1, q2, q3, q4, q5;
+        if (!quantise(dr, q0) || !quantise(dp[0], q1) || !quantise(dp[1], q2) ||
+            !quantise(dp[2], q3) || !quantise(einj, q4) || !quantise(ecross, q5)) {
+          ok = false;
+          continue;
+        }
+        gadd_fix(f0 + idx, q0);
+        gadd_fix(f1 + idx, q1);
+        gadd_fix(f2 + idx, q2);
+        gadd_fix(f3 + idx, q3);
+        gadd_fix(f4 + idx, (long long)((unsigned long long)q4 + (unsigned long long)q5));
+        qr_sum += q0;
+        qe_sum += q4;
+      } else {
+        gadd(f0 + idx, dr);
+        gadd(f1 + idx, dp[0]);
+        gadd(f2 + idx, dp[1]);
+        gadd(f3 + idx, dp[2]);
+        gadd(f4 + idx, einj + ecross);
+      }
+    }
+    if (reach_bad) raise_flag(M.status, PMP_FLAG_REACH);
+    if constexpr (FIXED) {
+      qr_sum = block_sum(qr_sum);
+      qe_sum = block_sum(qe_sum);
+      first = block_min(first);
+      hostm = block_max(hostm);
+      if (lane == 0) {
+        long long Qr, Qe;
+        if (ok && quantise(Mej / M.V, Qr) && quantise(Eall / M.V, Qe)) {
+          int ti = h[0], tj = h[1], tk = h[2];
+          if (!hostm) {
+            const int kk = first / cxy, rem = first - kk * cxy, jj = rem / cx;
+            ti = lo[0] + (rem - jj * cx); tj = lo[1] + jj; tk = lo[2] + kk;
+          }
+          long long idx;
+          if (pad_index(B, g, ti, tj, tk, idx)) {
+            gadd_fix(f0 + idx, (long long)((unsigned long long)Qr - (unsigned long long)qr_sum));
+            gadd_fix(f4 + idx, (long long)((unsigned long long)Qe - (unsigned long long)qe_sum));
+          }
+        } else {
+          raise_flag(M.status, PMP_FLAG_OVERFLOW);
+        }
+      }
+    } else {
+      if (!ok) raise_flag(M.status, PMP_FLAG_OVERFLOW);
     }
   }
 }
@@ -2645,6 +2930,30 @@ hipError_t launch_sink_deposit(const Mesh& M, const Particles& P, const void* st
       f32 ? sink_dep<PMP_ACC_FIX64, float>(M, P, state, buf, scratch, K, tr, nullptr, s)
           : sink_dep<PMP_ACC_FIX64, double>(M, P, state, buf, scratch, K, tr, nullptr, s);
   }
+  return hipGetLastError();
+}
+
+template <int ACC, class S>
+static void snr_dep(const Mesh& M, const SnrArgs& A, const void* state, void* buf, double* info,
+                    hipStream_t s) {
+  const int grid = grid_for(A.n, 1, 65536);
+  hipLaunchKernelGGL((k_snr_deposit<ACC, S>), dim3(grid), dim3(kSinkBlock), 0, s, M, A,
+                     (const S*)state, (typename AccT<ACC>::T*)buf, info);
+}
+
+hipError_t launch_snr_deposit(const Mesh& M, const SnrArgs& A, const void* state, void* buf,
+                              double* info, hipStream_t s) {
+  if (A.n <= 0) return hipSuccess;
+  const bool f32 = (M.state == PMP_STATE_F32);
+#define PMP_SNR(ACC)                                                               \
+  (f32 ? snr_dep<ACC, float>(M, A, state, buf, info, s)                            \
+       : snr_dep<ACC, double>(M, A, state, buf, info, s))
+  switch (M.acc) {
+    case PMP_ACC_F32: PMP_SNR(PMP_ACC_F32); break;
+    case PMP_ACC_F64: PMP_SNR(PMP_ACC_F64); break;
+    default: PMP_SNR(PMP_ACC_FIX64);
+  }
+#undef PMP_SNR
   return hipGetLastError();
 }
 

@@ -42,6 +42,8 @@ STRUCTS = {
     "pmp_sn": ["x", "y", "z", "m", "e", "r", "n", "box_off", "r_max"],
     "pmp_sinks": ["x", "y", "z", "a", "n", "box_off", "r_k", "r_gauss", "rate", "m", "vx",
                   "vy", "vz", "G", "dt", "gamma", "lambda"],
+    "pmp_snr": ["x", "y", "z", "m", "e", "vx", "vy", "vz", "n", "box_off", "r_k", "sub",
+                "nh_per_rho", "msf_coef", "psnr_coef", "eps_k"],
     "pmp_limits": ["rho_floor", "rho_tr", "cap", "eint_mode", "truelove_J", "G", "gamma"],
     "pmp_status": ["flags", "reserved", "touched", "bind", "lam", "fall"],
     "pmp_tuning": ["deposit_path", "tile_x", "tile_yz", "tile_block", "block", "grid_per_cu",
