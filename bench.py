@@ -229,7 +229,7 @@ def sink_create_rate(B, w, acc, channels, reps=10):
         ctx.state.copy_(base)
         torch.cuda.synchronize()
         t0.record()
-        out, work = ctx.sink_create(w.r_k, rho_tr, max_new)
+        out, work = ctx.sink_create(w.r_k, rho_tr, max_new, existing="workload")
         t1.record()
         torch.cuda.synchronize()
         if r:  # the first call warms up
@@ -243,6 +243,45 @@ def sink_create_rate(B, w, acc, channels, reps=10):
     return {"ms_per_call": round(ms, 4), "new_sinks": n, "rho_tr": rho_tr, "r_k": w.r_k,
             "algo_GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
             "kernels": "k_create_find+k_create_rank+k_create_apply"}
+
+
+def snr_rate(B, reps=10):
+    """Supernova remnants (TIGRESS variant, pmp_deposit_snr) on a 256^3 slab
+    box (mean densities 0.05, 1 and 30: all three regimes), FP64 state and
+    buffer, 20000 remnants, r_K = 3, 4^3 sample points per cell: the call
+    alone, after a deposit, averaged over `reps` calls."""
+    import numpy as np
+    import torch
+    from paper_2509_18261_amd import workloads as W
+    w = W.snr_box(nx=256, n_snr=20000, seed=31, dtype=np.float64)
+    ctx = B.Context(w, "f64", channels="all")
+    ctx.deposit()
+    info = torch.zeros(4 * w.snr.n, dtype=torch.float64, device="cuda")
+    ctx.deposit_snr(info)
+    torch.cuda.synchronize()
+    ctx.profile_begin(reps)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        ctx.deposit_snr(info)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    ph = ctx.profile_end()
+    inf = info.cpu().numpy().reshape(4, -1)
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    rm = inf[1] / (1679.0 * inf[2] ** -0.26)
+    kern_ms = ph["snr"][0] / ph["snr"][1] if "snr" in ph else None
+    return {"workload": w.name, "ms_per_call": round(ms, 4), "kernel_ms": kern_ms,
+            "remnants_per_s": w.snr.n / (ms * 1e-3), "sub": w.snr_params.sub,
+            "r_k": w.snr_params.r_k,
+            "regimes": {"MC": int((rm > 1).sum()), "ST": int(((rm > 0.027) & (rm <= 1)).sum()),
+                        "EJ": int((rm <= 0.027).sum())},
+            "kernel": "k_snr_deposit (one workgroup per remnant: 9^3 candidate cells x 4^3 "
+                      "sample points, twice; bound by the sample tests, not by memory)"}
 
 
 def copy_gbps(B, nbytes=1 << 30, reps=10):
@@ -529,6 +568,8 @@ def main():
     ap.add_argument("--no-atomics", action="store_true", help="skip the atomic peaks")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 path")
     ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the supernova-remnant and sink-creation legs")
     ap.add_argument("--set", default="", help="tuning overrides, e.g. deposit_path=0,tile_x=32")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the library's autotuner (default: tune, cached per shape)")
@@ -686,6 +727,14 @@ def main():
         out["c5_batched"] = c5_batched(B, args)
         log(f"c5 batched: graph {out['c5_batched']['graph_ms_per_step']:.3f} ms, per-box "
             f"{out['c5_batched']['per_box_launch_ms_per_step']:.3f} ms")
+    if not args.no_next:
+        out["snr_deposit"] = snr_rate(B)
+        log(f"supernova remnants: {out['snr_deposit']}")
+        if not (w.sinks is not None and w.sinks.n and w.nbox == 1):
+            wc = W.c3()
+            out["sink_create"] = {"workload": wc.name,
+                                  **sink_create_rate(B, wc, "f32", args.channels)}
+            log(f"sink creation: {out['sink_create']}")
     if not args.no_cpu:
         log("cpu baseline (serial oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, nparts)

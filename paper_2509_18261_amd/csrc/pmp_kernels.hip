@@ -2129,6 +2129,7 @@ struct L2Geom {
   const int* hist1;
   int nb, nblk0, nblk1, shift;
   long long ntiles;
+  long long cap0, cap1;  // entry capacity of each kind (level 1 drops entries past it)
 };
 
 __device__ __forceinline__ void bucket_range(const L2Geom& G, int cc, long long& start,
@@ -2138,8 +2139,12 @@ __device__ __forceinline__ void bucket_range(const L2Geom& G, int cc, long long&
   const int* H = kind ? G.hist1 + (long long)G.nb * G.nblk0 : G.hist1;
   const int nblk = kind ? G.nblk1 : G.nblk0;
   const long long base = H[0];
-  start = (long long)H[(long long)c * nblk] - base;
-  end = (long long)H[(long long)(c + 1) * nblk] - base;
+  // level 1 wrote only the entries below the capacity (and flagged the
+  // rest): the bucket holds the part of its range below it, so the slices,
+  // the level-2 histogram and the tile offsets never count dropped entries
+  const long long cap = kind ? G.cap1 : G.cap0;
+  start = min((long long)H[(long long)c * nblk] - base, cap);
+  end = min((long long)H[(long long)(c + 1) * nblk] - base, cap);
 }
 
 // One block: slices per bucket, their exclusive prefix (slice_base), and the
@@ -2784,6 +2789,8 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
   G.nblk1 = nbs;
   G.shift = S;
   G.ntiles = T.ntiles;
+  G.cap0 = bw.cic_cap;
+  G.cap1 = bw.sn_cap;
   hipLaunchKernelGGL(k_l2_plan, dim3(1), dim3(1024), 0, s, G, bw.slice_base, bw.cic_off,
                      bw.sn_off, bw.heavy_count);
   // hist2 is written in full for the slices in use ((slices in use) << S

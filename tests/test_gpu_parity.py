@@ -700,3 +700,87 @@ def test_truelove_per_cell_changes_the_limiter(B, orc):
     base = orc.step(w, "fix64")["counters"]
     got, ref = check(B, orc, truelove(w), "fix64")
     assert ref["counters"]["touched"] > base["touched"] or ref["counters"]["bind"] != base["bind"]
+
+
+# ------------------------------------------------- status flags and ties
+
+def _add_particle(P, pos, **fields):
+    """A single-box particle kind with one more particle appended."""
+    f = {k: np.concatenate([v, [fields.get(k, v[0])]]) for k, v in P.fields.items()}
+    for a, k in enumerate(("x", "y", "z")):
+        f[k][-1] = pos[a]
+    return W.Particles(f, np.array([0, P.n + 1], dtype=np.int64))
+
+
+def _flags(got):
+    return got["status"]["flags"]
+
+
+@pytest.mark.parametrize("path", [1, 0])
+def test_overflow_flag_skips_the_contribution(B, orc, path):
+    """A fixed-point contribution beyond 2^62 on the 2^-40 grid (a CIC mass of
+    1e7 at a cell centre: one contribution of 1e7 per unit volume) is skipped
+    and raises OVERFLOW; everything else equals the oracle without it."""
+    w = W.c2(nx=24)
+    bad = dataclasses.replace(w, cic=_add_particle(w.cic, (12.5, 7.5, 3.5), m=1e7))
+    say(f"case overflow path={path}")
+    got = run_gpu(B, bad, "fix64", tuning={"deposit_path": path})
+    assert _flags(got) & 0x4, got["status"]
+    ref = orc.step(w, "fix64", want_eta=True)
+    got["status"]["flags"] &= ~0x4
+    compare(w, "fix64", got, ref)
+
+
+@pytest.mark.parametrize("acc", ["fix64", "f32"])
+@pytest.mark.parametrize("path", [1, 0])
+def test_nan_particles_flagged_and_skipped(B, orc, path, acc):
+    """A CIC particle with a NaN mass and a supernova with a NaN energy are
+    skipped and raise NAN; the rest equals the oracle without them."""
+    w = W.c2(nx=24)
+    bad = dataclasses.replace(w, cic=_add_particle(w.cic, (3.2, 4.4, 5.6), m=float("nan")),
+                              sn=_add_particle(w.sn, (10.1, 11.2, 12.3), e=float("nan")))
+    say(f"case nan path={path} acc={acc}")
+    got = run_gpu(B, bad, acc, tuning={"deposit_path": path})
+    assert _flags(got) & 0x8, got["status"]
+    ref = orc.step(w, "fix64" if acc == "fix64" else "f64", want_eta=True)
+    got["status"]["flags"] &= ~0x8
+    compare(w, acc, got, ref)
+
+
+def test_capacity_flag_when_radius_bound_is_wrong(B):
+    """The binned path sizes its supernova entry lists from pmp_sn.r_max; a
+    caller that declares r_max = 0 for radius-4 supernovae overflows them:
+    the entries past the capacity are skipped (never read) and CAPACITY is
+    raised; the deposit completes and the deposited total falls short."""
+    import torch
+    w = W.c2(nx=24)
+    tun = dict(deposit_path=1, tile_x=16, tile_yz=2, tile_block=64)
+    sums = []
+    for r_max in (4.0, 0.0):
+        ctx = B.Context(w, "fix64", channels="all")
+        ctx.set_tuning(**tun)
+        ctx.sn.r_max = r_max
+        say(f"case capacity r_max={r_max}")
+        ctx.deposit()
+        torch.cuda.synchronize()
+        sums.append((ctx.buf.cpu().numpy().sum(), ctx.status()))
+        ctx.close()
+    assert sums[0][1]["flags"] == 0, sums[0][1]
+    assert sums[1][1]["flags"] & 0x20, sums[1][1]
+    assert sums[1][0] < sums[0][0]
+
+
+@pytest.mark.parametrize("path", [1, 0])
+def test_fixed_point_remainder_at_an_exact_tie(B, orc, path):
+    """CIC particles on cell corners (f = 1/2 on every axis: eight equal
+    weights) with masses whose eighths are not on the 2^-40 grid: the
+    rounding residue goes to the host cell, as in the oracle, bit for bit."""
+    rng = np.random.default_rng(4)
+    pos = np.array([[5.0, 6.0, 7.0], [1.0, 1.0, 1.0], [16.0, 3.0, 9.0], [8.0, 8.0, 8.0]])
+    m = np.array([0.3, 0.7, 1.0 / 3.0, 0.1])
+    domain, lo, n = W.single_box(16)
+    w = W.Workload("ties", domain, lo, n, 2, 1.0,
+                   W.gas_state(rng, 16 ** 3, np.float64).reshape(-1),
+                   cic=W._one_box(pos % 16, {"m": m}))
+    say(f"case tie path={path}")
+    check(B, orc, w, "fix64", tuning={"deposit_path": path})
