@@ -57,7 +57,7 @@ def record_bytes(w):
     return sum(P.n * nb for P, nb in ((w.cic, 32), (w.sn, 48), (w.sinks, 32)) if P is not None)
 
 
-def method_bytes(w, acc, counts, F):
+def method_bytes(w, acc, counts, F, applied=None):
     """The method's own HBM bytes per step (Sec. 2.2 Steps 1-5 as written,
     every phase separate, only the F buffer channels the particle kinds
     deposit into; no binning or scratch traffic, nothing fused):
@@ -66,9 +66,11 @@ def method_bytes(w, acc, counts, F):
       deposit   2 b_acc per unique touched (cell, channel) (read-modify-write);
       sinks     5 b_state per sink-kernel cell (the state the request reads);
       fold      3 b_acc per ghost cell and channel (ghost in, owner in/out);
-      apply     per owned cell 5 b_state in (the energy limiter needs |p|^2),
-                rho and E out (2 b_state) and the F channels in; the momentum
-                out (3 b_state) only in cells a sink removes from (no kind
+      apply     per owned cell the F channels in; per updated cell (some
+                channel nonzero, counted by applied_cells; a cell without an
+                update keeps its state) 5 b_state in (the energy limiter
+                needs |p|^2) and rho and E out (2 b_state); the momentum out
+                (3 b_state) only in cells a sink removes from (no kind
                 deposits momentum, so elsewhere it does not change);
       sink update: 64 B per sink (record, gains out) and per kernel cell
                 4 b_state (rho, p) + b_acc (K).
@@ -84,14 +86,15 @@ def method_bytes(w, acc, counts, F):
         "records": record_bytes(w),
         "deposit": 2 * ba * touched + 5 * bs * ks,
         "fold": 3 * ba * F * (padded - owned),
-        "apply": owned * (7 * bs + F * ba) + 3 * bs * ks,
+        "apply": owned * F * ba + 7 * bs * (owned if applied is None else applied["total"]) +
+                 3 * bs * ks,
         "sink_update": (w.sinks.n * 64 + ks * (4 * bs + ba)) if w.sinks is not None else 0,
     }
     out["total"] = sum(out.values())
     return out
 
 
-def kernel_method_bytes(w, acc, counts, F, fused):
+def kernel_method_bytes(w, acc, counts, F, fused, applied=None):
     """The method's bytes that each kernel of the timed step carries (the
     terms of method_bytes assigned to the kernel that does that work).
     Binned path: the tile pass does the zero fill, reads the records and
@@ -104,19 +107,21 @@ def kernel_method_bytes(w, acc, counts, F, fused):
     ba = acc_bytes(acc)
     bs = np.dtype(w.state.dtype).itemsize
     owned, padded, interior = _shape(w)
-    cell_apply = 7 * bs + F * ba
+    if applied is None:
+        applied = {"interior": interior, "shell": owned - interior, "total": owned}
     dep = 2 * ba * (counts.get("cic", 0) + counts.get("sn", 0))
     out = {
         "tile": padded * F * ba + record_bytes(w) - (w.sinks.n * 32 if w.sinks else 0) + dep,
         "zero": padded * F * ba,
         "fold": 3 * ba * F * (padded - owned),
-        "apply": owned * cell_apply + 3 * bs * counts.get("sink", 0),
+        "apply": owned * F * ba + 7 * bs * applied["total"] + 3 * bs * counts.get("sink", 0),
         "bin": 0,
     }
     if fused:
         out["tile"] = (padded - interior) * F * ba + record_bytes(w) + dep + \
-            interior * cell_apply
-        out["fold"] = 3 * ba * F * (padded - owned) + (owned - interior) * cell_apply
+            interior * F * ba + 7 * bs * applied["interior"]
+        out["fold"] = 3 * ba * F * (padded - owned) + (owned - interior) * F * ba + \
+            7 * bs * applied["shell"]
         out["apply"] = 0
     if w.cic is not None and w.cic.n:
         out["cic"] = w.cic.n * 32 + 2 * ba * counts["cic"]
@@ -155,6 +160,43 @@ def touched_counts(B, w, acc):
         del ctx
         torch.cuda.empty_cache()
     return counts
+
+
+def applied_cells(B, w, acc):
+    """Owned cells whose folded buffer is nonzero in some channel: the cells
+    Steps 3 + 5 update (a cell without an update keeps its state), split into
+    those at least g from every face of their box (the fused tile pass
+    applies them) and the rest.  Counted after a deposit and fold on the
+    direct path."""
+    import numpy as np
+    import torch
+    ctx = B.Context(w, acc, channels="all")
+    ctx.set_tuning(deposit_path=0)
+    ctx.deposit()
+    ctx.ghost_fold()
+    torch.cuda.synchronize()
+    g = w.ghost
+    F = len(ctx.fields)
+    inner = shell = 0
+    off = 0
+    for n in w.n.astype(np.int64):
+        p = n + 2 * g
+        npad = int(np.prod(p))
+        blk = ctx.buf[off: off + F * npad].view(F, int(p[2]), int(p[1]), int(p[0]))
+        own = (blk[:, g:g + n[2], g:g + n[1], g:g + n[0]] != 0).any(dim=0)
+        tot = int(own.sum().item())
+        if (n > 2 * g).all():
+            core = own[g:n[2] - g, g:n[1] - g, g:n[0] - g]
+            ci = int(core.sum().item())
+        else:
+            ci = 0
+        inner += ci
+        shell += tot - ci
+        off += F * npad
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return {"interior": inner, "shell": shell, "total": inner + shell}
 
 
 def run_steps(ctx, steps, warmup, profile=True):
@@ -510,7 +552,8 @@ def is_fused(tun, w, nparts):
         (w.sinks is None or w.sinks.n == 0) and nparts > 0
 
 
-def run_mode(B, w, acc, counts_acc, args, overrides=None, autotune_on=True, steps=None):
+def run_mode(B, w, acc, counts_acc, args, overrides=None, autotune_on=True, steps=None,
+             applied=None):
     """A timed run of one (state, accumulator) mode: ms per step (graph),
     the per-kernel table and the step's method bytes."""
     import torch
@@ -523,8 +566,8 @@ def run_mode(B, w, acc, counts_acc, args, overrides=None, autotune_on=True, step
     del ctx
     torch.cuda.empty_cache()
     fused = is_fused(tun, w, nparts)
-    mb = method_bytes(w, acc, counts_acc, nchan)
-    table = phase_table(phases, kernel_method_bytes(w, acc, counts_acc, nchan, fused))
+    mb = method_bytes(w, acc, counts_acc, nchan, applied)
+    table = phase_table(phases, kernel_method_bytes(w, acc, counts_acc, nchan, fused, applied))
     return {"ms_per_step": ms, "eager_ms_per_step": eager_ms, "spread": spread,
             "particles_per_s": nparts / (ms * 1e-3), "cells_per_s": w.owned_cells / (ms * 1e-3),
             "state": str(w.state.dtype), "acc": acc, "tuning": tun, "autotune": tuned,
@@ -597,12 +640,15 @@ def main():
     nparts = sum(P.n for P in (w.cic, w.sn, w.sinks) if P is not None)
     counts = touched_counts(B, w, args.acc)
     log("touched (cell, channel) pairs:", counts)
+    applied = applied_cells(B, w, args.acc)
+    log("updated cells:", applied)
     overrides = {}
     for kv in filter(None, args.set.split(",")):
         k, v = kv.split("=")
         overrides[k.strip()] = int(v)
 
-    head = run_mode(B, w, args.acc, counts, args, overrides, not args.no_autotune)
+    head = run_mode(B, w, args.acc, counts, args, overrides, not args.no_autotune,
+                    applied=applied)
     ms = head["ms_per_step"]
     log(f"step {ms:.4f} ms (graph), {head['eager_ms_per_step']:.4f} ms (eager); "
         f"flags {head['status_flags']}")
@@ -624,7 +670,7 @@ def main():
     kname = KERNELS[dom]
     if dom == "fold" and head["fused_apply"]:
         kname = "k_fold_apply"
-    mb = method_bytes(w, args.acc, counts, head["buffer_channels"])
+    mb = method_bytes(w, args.acc, counts, head["buffer_channels"], applied)
     step_gbps = mb["total"] / (ms * 1e-3) / 1e9
     out = {
         "metric": "particle-deposits/s and mesh cells applied/s; % HBM roofline vs plain FP64",
@@ -657,6 +703,7 @@ def main():
                      "avg_launch_ms": d["avg_ms"]},
         # the whole step: the method's own bytes (every phase separate, the
         # deposited channels only) over the step time
+        "updated_cells": applied,
         "step_roofline": {"bound": "hbm", "achieved": round(step_gbps, 1),
                           "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                           "frac": round(step_gbps / HBM_PEAK_GBPS, 4),
@@ -678,11 +725,13 @@ def main():
                 continue
             # the same particles touch the same (cell, channel) pairs in every mode
             modes[f"{acc}_state_{wm.state.dtype}"] = run_mode(B, wm, acc, counts, args, None,
-                                                              True, max(5, args.steps // 2))
+                                                              True, max(5, args.steps // 2),
+                                                              applied)
             log(f"mode {acc}: {modes[f'{acc}_state_{wm.state.dtype}']['ms_per_step']:.4f} ms")
         if w.sinks is None or w.sinks.n == 0:
             modes["f64r_state_" + str(w.state.dtype)] = run_mode(
-                B, w, "f64r", counts, args, {"deposit_path": 1}, False, max(5, args.steps // 2))
+                B, w, "f64r", counts, args, {"deposit_path": 1}, False, max(5, args.steps // 2),
+                applied)
         out["modes"] = modes
         out["reproducibility"] = repro_rates(B, w, args.channels)
         log(f"reproducibility: {out['reproducibility']}")
@@ -691,7 +740,7 @@ def main():
         # fold and apply, no binning or fusion
         wp = w if args.state == "f64" else w32.with_state(w32.state.astype(np.float64))
         plain = run_mode(B, wp, "f64", counts, args, {"deposit_path": 0, "fuse_apply": 0},
-                         False, max(5, args.steps // 2))
+                         False, max(5, args.steps // 2), applied)
         out["plain_f64"] = plain
         out["speedup_vs_plain_f64"] = plain["ms_per_step"] / ms
         log(f"plain f64: {plain['ms_per_step']:.4f} ms")

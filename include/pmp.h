@@ -223,7 +223,8 @@ typedef struct {
                             their stencil touches, each tile accumulated in
                             LDS by one workgroup and stored once (no global
                             atomics, no separate zero fill) */
-  int32_t tile_x;        /* tile edge along x: 16, 32 or 64 cells */
+  int32_t tile_x;        /* tile edge along x: 16, 32, 64, 128 or 256 cells (long x
+                            tiles give long contiguous state rows in the fused apply) */
   int32_t tile_yz;       /* tile edge along y and z: 2, 4 or 8 cells */
   int32_t tile_block;    /* threads per tile workgroup: 64 .. 1024 */
   int32_t block;         /* threads per block of the streaming kernels */

@@ -793,7 +793,9 @@ int orc_sink_update(const orc_mesh *M, int mode, const double *state, const void
  *    energy of the cell before the update (the paper's C_V T);
  *  - if even lambda = 0 violates the floor, E is raised to the floor and the
  *    cell is counted (the paper does not treat this case).
- * Step 5 then writes U + Delta U^lim. */
+ * Step 5 then writes U + Delta U^lim.  A cell whose buffer is zero in every
+ * channel receives no update: it keeps its state as it is (eta = 1), whether
+ * or not that state meets the floors. */
 int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
               const orc_limits *L, double *eta, orc_counters *cnt) {
   int rc = check_mesh(M);
@@ -822,6 +824,12 @@ int orc_apply(const orc_mesh *M, int mode, double *state, const void *buf,
           double DE = buf_value(mode, buf, buf_index(M, &G, b, 4, gi, gj, gk));
           double K = 0.0;
           if (M->nfield == 6) K = buf_value(mode, buf, buf_index(M, &G, b, 5, gi, gj, gk));
+          if (Dr == 0.0 && qx == 0.0 && qy == 0.0 && qz == 0.0 && DE == 0.0 && K == 0.0) {
+            /* no particle reaches the cell: Step 5 adds a zero update and the
+             * limiters, which act on updates, leave it alone (eta = 1) */
+            if (eta) eta[ecell + c] = 1.0;
+            continue;
+          }
           double Kl = 0.0;
           if (K > 0.0)
             Kl = limited_removal(K, rho, truelove_rho(L, M->dx, rho, px, py, pz, E), L);

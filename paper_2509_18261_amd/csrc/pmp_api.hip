@@ -1575,7 +1575,7 @@ int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
   if (t->deposit_path < 0 || t->deposit_path > 1) return fail(PMP_EINVAL, "deposit_path 0 or 1");
   if (c->acc == PMP_ACC_F64R && t->deposit_path != 1)
     return fail(PMP_EINVAL, "the reproducibility mode runs on the binned path (deposit_path 1)");
-  if (!pow2_in(t->tile_x, 16, 64)) return fail(PMP_EINVAL, "tile_x must be 16, 32 or 64");
+  if (!pow2_in(t->tile_x, 16, 256)) return fail(PMP_EINVAL, "tile_x must be 16, 32, 64, 128 or 256");
   if (!pow2_in(t->tile_yz, 2, 8)) return fail(PMP_EINVAL, "tile_yz must be 2, 4 or 8");
   if (!pow2_in(t->tile_block, 64, 1024)) return fail(PMP_EINVAL, "tile_block 64..1024, power of 2");
   if (!pow2_in(t->block, 64, 1024)) return fail(PMP_EINVAL, "block 64..1024, power of 2");
@@ -1633,7 +1633,8 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
   if (has_sn) add(0, base.tile_x, base.tile_yz, base.tile_block, 16, 0, 0);
   const int shapes[][3] = {{64, 4, 128}, {64, 4, 256}, {32, 4, 128}, {32, 8, 256},
                            {16, 8, 256}, {64, 2, 128}, {16, 4, 128}, {32, 4, 256},
-                           {64, 8, 256}, {64, 8, 512}};
+                           {64, 8, 256}, {64, 8, 512}, {128, 4, 256}, {128, 4, 512},
+                           {256, 4, 256}, {256, 4, 512}, {256, 2, 256}};
   // the fused apply only applies to steps without sinks
   for (int fuse = has_sinks ? 0 : 1; fuse >= 0; --fuse)
     for (const auto& sh : shapes) add(1, sh[0], sh[1], sh[2], 64, 0, fuse);

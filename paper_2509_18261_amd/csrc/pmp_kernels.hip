@@ -1465,11 +1465,14 @@ struct ApplyCounts {
 // cell's rho, the other state fields follow at multiples of stride; (Dr, q,
 // DE, K) is the folded buffer.  Returns eta = Kl / K (1 when K = 0).  Reads
 // all five fields (the energy limiter needs |p|^2); writes rho and E, and
-// the momentum only where it changes.
+// the momentum only where it changes.  A cell whose update is zero in every
+// channel is left alone: Step 5 adds nothing and the limiters act on
+// updates (its state is neither read nor written).
 template <class S>
 __device__ __forceinline__ double apply_cell(S* st, long long stride, double Dr, double qx,
                                              double qy, double qz, double DE, double K,
                                              const Limits& L, ApplyCounts& cnt) {
+  if (Dr == 0.0 && qx == 0.0 && qy == 0.0 && qz == 0.0 && DE == 0.0 && K == 0.0) return 1.0;
   const double rho = (double)st[0];
   const double px = (double)st[stride];
   const double py = (double)st[2 * stride];
@@ -1536,6 +1539,7 @@ __device__ __forceinline__ double apply_cell(S* st, long long stride, double Dr,
 template <class S>
 __device__ __forceinline__ void apply_cell_nosrc(S* st, long long stride, double Dr, double DE,
                                                  const Limits& L, ApplyCounts& cnt) {
+  if (Dr == 0.0 && DE == 0.0) return;  // no update: the cell is left alone
   const double rho = (double)st[0];
   if (!(rho != 0.0 && rho == rho) || L.eint_mode != 0) {
     apply_cell(st, stride, Dr, 0.0, 0.0, 0.0, DE, 0.0, L, cnt);

@@ -235,6 +235,9 @@ SHAPES = [
     # lanes per supernova in the member count
     {"deposit_path": 1, "count_lanes": 1},
     {"deposit_path": 1, "count_lanes": 16},
+    # long x tiles
+    {"deposit_path": 1, "tile_x": 128, "tile_yz": 2, "tile_block": 256},
+    {"deposit_path": 1, "tile_x": 256, "tile_yz": 4, "tile_block": 512},
 ]
 
 

@@ -1430,3 +1430,38 @@ def test_snr_radial_momentum_with_covered_fractions(orc, mode):
     assert np.allclose(mag[sel] / B[0][sel], P / W.SNR_M_EJ, rtol=1e-6)
     frac = B[0][sel] * Vsnr / W.SNR_M_EJ
     assert (frac < 0.999).sum() > 50  # fractional cells present
+
+
+@pytest.mark.parametrize("mode", ["f64", "fix64"])
+def test_cells_without_an_update_keep_their_state(orc, mode):
+    """Step 5 adds a zero update to a cell no particle reaches, and the limiters
+    act on updates: such a cell keeps its state bit for bit (eta = 1, nothing
+    counted), even where that state violates the energy floor; a touched cell
+    with the same violating state is lifted to the floor and counted."""
+    rng = np.random.default_rng(12)
+    n = 64
+    rho = np.exp(rng.standard_normal(n))
+    v = rng.standard_normal((3, n))
+    p = rho * v
+    E = 0.5 * (p * p).sum(0) / rho * np.where(np.arange(n) % 2 == 0, 0.5, 2.0)  # even: e_int < 0
+    state = np.concatenate([rho, p[0], p[1], p[2], E])
+    for eint_mode in (0, 1):
+        w = W.Workload("u", *W.single_box(n, 1, 1), 0, 1.0, state.copy(),
+                       limits=W.Limits(eint_mode=eint_mode))
+        touched = np.arange(n) % 4 < 2  # every other pair: one violating, one valid
+        q = np.zeros(5 * n)
+        q[0:n] = np.where(touched, 0.25, 0.0)
+        q[4 * n:5 * n] = np.where(touched, 0.5, 0.0)
+        buf = (np.rint(q * Q).astype(np.int64) if mode == "fix64" else q)
+        st, eta, cnt = orc.apply(w, mode, buf, want_eta=True)
+        st = st.reshape(5, n)
+        ref = state.reshape(5, n)
+        assert np.array_equal(st[:, ~touched], ref[:, ~touched])
+        assert np.all(eta == 1.0)
+        # untouched cells that violate the floor still do; touched ones meet it
+        e_old = ref[4] - 0.5 * (ref[1:4] ** 2).sum(0) / ref[0]
+        assert (e_old[~touched] < 0).sum() == (~touched).sum() // 2
+        if eint_mode == 0:
+            e1 = st[4] - 0.5 * (st[1:4] ** 2).sum(0) / st[0]
+            assert np.all(e1[touched] >= -1e-12 * st[4][touched])
+            assert cnt["fall"] > 0
