@@ -209,6 +209,15 @@ __device__ __forceinline__ int small_div(int t, int d, float inv) {
   return q;
 }
 
+// Offsets (ii, jj, kk) of entry t of a cube walked in (k, j, i) order with i
+// fastest, cx cells along x and cxy per z plane; t < 2^22.
+__device__ __forceinline__ void cube_cell(int t, int cx, int cxy, int& ii, int& jj, int& kk) {
+  kk = small_div(t, cxy, 1.0f / (float)cxy);
+  const int rem = t - kk * cxy;
+  jj = small_div(rem, cx, 1.0f / (float)cx);
+  ii = rem - jj * cx;
+}
+
 // accumulator element types
 template <int ACC> struct AccT;
 template <> struct AccT<PMP_ACC_F32> { using T = float; };
@@ -785,7 +794,8 @@ __device__ void bondi_request(const Mesh& M, const S* __restrict__ state, const 
   const double r2 = K.r_k * K.r_k;
   long long qn = 0, qm = 0, qx = 0, qy = 0, qz = 0, qc = 0;
   for (int t = threadIdx.x; t < total; t += kSinkBlock) {
-    const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
+    int ii, jj, kk;
+    cube_cell(t, cx, cxy, ii, jj, kk);
     const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
     const double d2 = dist2(x, y, z, i, j, k);
     if (!(d2 <= r2)) continue;
@@ -895,7 +905,8 @@ __global__ __launch_bounds__(kSinkBlock) void k_sink_deposit(Mesh M, Particles P
     const double g2 = racc * racc;
     long long wq = 0, mq = 0;
     for (int t = lane; t < total; t += kSinkBlock) {
-      const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
+      int ii, jj, kk;
+      cube_cell(t, cx, cxy, ii, jj, kk);
       const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
       const double d2 = dist2(x, y, z, i, j, k);
       if (!(d2 <= r2)) continue;
@@ -928,7 +939,8 @@ __global__ __launch_bounds__(kSinkBlock) void k_sink_deposit(Mesh M, Particles P
     long long qreq = 0;
     int first = 0x7fffffff, hostm = 0;
     for (int t = lane; t < total; t += kSinkBlock) {
-      const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
+      int ii, jj, kk;
+      cube_cell(t, cx, cxy, ii, jj, kk);
       const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
       const double d2 = dist2(x, y, z, i, j, k);
       if (!(d2 <= r2)) continue;
@@ -970,8 +982,9 @@ __global__ __launch_bounds__(kSinkBlock) void k_sink_deposit(Mesh M, Particles P
         if (ok && quantise(Mreq / M.V, Q)) {
           int ti = h[0], tj = h[1], tk = h[2];
           if (!hostm) {
-            const int kk = first / cxy, rem = first - kk * cxy, jj = rem / cx;
-            ti = lo[0] + (rem - jj * cx); tj = lo[1] + jj; tk = lo[2] + kk;
+            int ii, jj, kk;
+            cube_cell(first, cx, cxy, ii, jj, kk);
+            ti = lo[0] + ii; tj = lo[1] + jj; tk = lo[2] + kk;
           }
           long long idx;
           if (pad_index(B, g, ti, tj, tk, idx)) gadd_fix(f5 + idx, Q - qreq);
@@ -1043,7 +1056,8 @@ __global__ __launch_bounds__(kSinkBlock) void k_sink_update(Mesh M, Particles P,
       const int cxy = cx * cy;
       const int total = cxy * (hi[2] - lo[2] + 1);
       for (int t = lane; t < total; t += kSinkBlock) {
-        const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
+        int ii, jj, kk;
+        cube_cell(t, cx, cxy, ii, jj, kk);
         const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
         const double d2 = dist2(x, y, z, i, j, k);
         if (!(d2 <= r2)) continue;
@@ -1188,7 +1202,8 @@ __global__ __launch_bounds__(kSinkBlock) void k_snr_deposit(Mesh M, SnrArgs A,
     int any = covered_samples(x, y, z, r2, h[0], h[1], h[2], ns) > 0;
     if (!any) {
       for (int t = lane; t < total && !any; t += kSinkBlock) {
-        const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
+        int ii, jj, kk;
+        cube_cell(t, cx, cxy, ii, jj, kk);
         any = covered_samples(x, y, z, r2, lo[0] + ii, lo[1] + jj, lo[2] + kk, ns) > 0;
       }
       any = block_max(any);
@@ -1198,7 +1213,8 @@ __global__ __launch_bounds__(kSinkBlock) void k_snr_deposit(Mesh M, SnrArgs A,
     bool ok = true, reach_bad = false;
     int first = 0x7fffffff, hostm = 0;
     for (int t = lane; t < total; t += kSinkBlock) {
-      const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
+      int ii, jj, kk;
+      cube_cell(t, cx, cxy, ii, jj, kk);
       const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
       const bool is_host = (i == h[0] && j == h[1] && k == h[2]);
       double w;
@@ -1264,7 +1280,8 @@ __global__ __launch_bounds__(kSinkBlock) void k_snr_deposit(Mesh M, SnrArgs A,
     T* f4 = buf + B.boff + M.slot[4] * B.npad;
     long long qr_sum = 0, qe_sum = 0;
     for (int t = lane; t < total; t += kSinkBlock) {
-      const int kk = t / cxy, rem = t - kk * cxy, jj = rem / cx, ii = rem - jj * cx;
+      int ii, jj, kk;
+      cube_cell(t, cx, cxy, ii, jj, kk);
       const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
       double w;
       if (alone) {
@@ -1332,8 +1349,9 @@ __global__ __launch_bounds__(kSinkBlock) void k_snr_deposit(Mesh M, SnrArgs A,
         if (ok && quantise(Mej / M.V, Qr) && quantise(Eall / M.V, Qe)) {
           int ti = h[0], tj = h[1], tk = h[2];
           if (!hostm) {
-            const int kk = first / cxy, rem = first - kk * cxy, jj = rem / cx;
-            ti = lo[0] + (rem - jj * cx); tj = lo[1] + jj; tk = lo[2] + kk;
+            int ii, jj, kk;
+            cube_cell(first, cx, cxy, ii, jj, kk);
+            ti = lo[0] + ii; tj = lo[1] + jj; tk = lo[2] + kk;
           }
           long long idx;
           if (pad_index(B, g, ti, tj, tk, idx)) {
@@ -3059,10 +3077,12 @@ __global__ __launch_bounds__(256) void k_create_find(Mesh M, const S* __restrict
       const S* st = state + B.soff + c;
       rho = (double)st[0];
       if (rho > truelove_at(L, st, B.ncell)) {
-        const long long row = c / B.n[0];
-        const int li = (int)(c - row * B.n[0]);
-        const int lk = (int)(row / B.n[1]);
-        const int lj = (int)(row - (long long)lk * B.n[1]);
+        // box cells < 2^31: 32-bit quotients
+        const unsigned cu = (unsigned)c, nx = (unsigned)B.n[0], ny = (unsigned)B.n[1];
+        const unsigned row = cu / nx;
+        const int li = (int)(cu - row * nx);
+        const int lk = (int)(row / ny);
+        const int lj = (int)(row - (unsigned)lk * ny);
         gi = B.lo[0] + li;
         gj = B.lo[1] + lj;
         gk = B.lo[2] + lk;
