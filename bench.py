@@ -94,15 +94,17 @@ def method_bytes(w, acc, counts, F, applied=None):
     return out
 
 
-def kernel_method_bytes(w, acc, counts, F, fused, applied=None):
+def kernel_method_bytes(w, acc, counts, F, fused, applied=None, owner=False):
     """The method's bytes that each kernel of the timed step carries (the
     terms of method_bytes assigned to the kernel that does that work).
     Binned path: the tile pass does the zero fill, reads the records and
     performs every deposit read-modify-write (in LDS; counted as the method's
     HBM bytes all the same); fused (no sinks), it also applies the interior
     cells (owned, at least g from every face), and the shell kernel folds and
-    applies the rest.  Direct path: zero fill, CIC and supernova atomics,
-    fold, apply, one kernel each."""
+    applies the rest.  On owner tiles (fuse_apply 2: no ghost zone, no fold)
+    the tile pass does all of Steps 1-5 and carries all of the step's bytes.
+    Direct path: zero fill, CIC and supernova atomics, fold, apply, one
+    kernel each."""
     import numpy as np
     ba = acc_bytes(acc)
     bs = np.dtype(w.state.dtype).itemsize
@@ -123,6 +125,9 @@ def kernel_method_bytes(w, acc, counts, F, fused, applied=None):
         out["fold"] = 3 * ba * F * (padded - owned) + (owned - interior) * F * ba + \
             7 * bs * applied["shell"]
         out["apply"] = 0
+    if owner:
+        out["tile"] = method_bytes(w, acc, counts, F, applied)["total"]
+        out["fold"] = 0
     if w.cic is not None and w.cic.n:
         out["cic"] = w.cic.n * 32 + 2 * ba * counts["cic"]
     if w.sn is not None and w.sn.n:
@@ -566,12 +571,16 @@ def run_mode(B, w, acc, counts_acc, args, overrides=None, autotune_on=True, step
     del ctx
     torch.cuda.empty_cache()
     fused = is_fused(tun, w, nparts)
+    # owner tiles: the library ran the fold-free step (no fold launch)
+    owner = fused and tun.get("fuse_apply") == 2 and "fold" not in phases
     mb = method_bytes(w, acc, counts_acc, nchan, applied)
-    table = phase_table(phases, kernel_method_bytes(w, acc, counts_acc, nchan, fused, applied))
+    table = phase_table(phases, kernel_method_bytes(w, acc, counts_acc, nchan, fused, applied,
+                                                    owner))
     return {"ms_per_step": ms, "eager_ms_per_step": eager_ms, "spread": spread,
             "particles_per_s": nparts / (ms * 1e-3), "cells_per_s": w.owned_cells / (ms * 1e-3),
             "state": str(w.state.dtype), "acc": acc, "tuning": tun, "autotune": tuned,
-            "fused_apply": fused, "buffer_channels": nchan, "phases": table,
+            "fused_apply": 2 if owner else int(fused), "buffer_channels": nchan,
+            "phases": table,
             "step_method_bytes": mb["total"],
             "step_method_frac": mb["total"] / (ms * 1e-3) / (HBM_PEAK_GBPS * 1e9),
             "status_flags": st["flag_names"]}

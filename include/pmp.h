@@ -242,7 +242,18 @@ typedef struct {
                             least g from every box face (no ghost image reaches
                             them), then folds and applies the shell cells in one
                             kernel; results are those of the separate calls.
-                            The buffer's interior cells are left unwritten. */
+                            The buffer's interior cells are left unwritten.
+                            2: owner tiles, no ghost zone and no fold: tiles
+                            cover owned cells only, each particle is binned into
+                            every tile (of any box) that a periodic image of its
+                            stencil reaches, and the tile pass applies every
+                            owned cell from its complete LDS sum (Steps 2, 3
+                            and 5 fused; the same sums as the fold, added in
+                            another order: fixed point bit for bit, floats
+                            rounded once).  The buffer is not written.  Needs
+                            every tile extent along an axis to be at most the
+                            domain less 2g cells, and not PMP_ACC_F64R; where
+                            that does not hold the step runs as with 1. */
   int32_t count_lanes;   /* binned path: lanes counting one supernova's sphere
                             members (its candidate rows dealt round them):
                             1, 2, 4, 8 or 16 */
@@ -462,8 +473,9 @@ int pmp_autotune(pmp_ctx *ctx, void *state, void *buf, const pmp_cic *cic, const
 #define PMP_PHASE_CIC 1           /* direct path: CIC atomics */
 #define PMP_PHASE_SN 2            /* direct path: supernova atomics */
 #define PMP_PHASE_SINK_DEPOSIT 3
-#define PMP_PHASE_FOLD 4          /* ghost fold; in a fused step (fuse_apply), the
-                                     shell cells' fold + limiter + apply */
+#define PMP_PHASE_FOLD 4          /* ghost fold; in a fused step (fuse_apply 1), the
+                                     shell cells' fold + limiter + apply (none
+                                     with owner tiles) */
 #define PMP_PHASE_SINK_UPDATE 5
 #define PMP_PHASE_APPLY 6
 #define PMP_PHASE_BIN 7           /* binned path: two-level sort of (particle, tile)

@@ -168,6 +168,12 @@ struct pmp_ctx {
   long long* d_tile_prefix = nullptr;
   int* d_tiles_axis = nullptr;
   TileGeo* d_tile_geo = nullptr;
+  // owner tiles of the same edge (fold-free step), when they fit the layout
+  bool owner_ok = false;
+  long long ontiles = 0;
+  long long* d_otile_prefix = nullptr;
+  int* d_otiles_axis = nullptr;
+  TileGeo* d_otile_geo = nullptr;
   BinWork bw{};
   long long bw_hist = 0, bw_blocks = 0, bw_tiles = 0, bw_nsn = 0, bw_hist2 = 0,
             bw_slice_base = 0, bw_partial = 0;
@@ -225,15 +231,16 @@ struct pmp_ctx {
     return M;
   }
   size_t acc_bytes() const { return acc == PMP_ACC_F32 ? 4 : 8; }
-  TileGrid tiles() const {
+  TileGrid tiles(bool owner = false) const {
     TileGrid T;
     for (int a = 0; a < 3; ++a) T.t[a] = tile_dims[a];
-    T.tile_prefix = d_tile_prefix;
-    T.tiles_axis = d_tiles_axis;
-    T.geo = d_tile_geo;
-    T.ntiles = ntiles;
-    T.gx = ghost;
-    T.wx = tile_dims[0] + 2 * ghost;
+    T.owner = owner ? 1 : 0;
+    T.tile_prefix = owner ? d_otile_prefix : d_tile_prefix;
+    T.tiles_axis = owner ? d_otiles_axis : d_tiles_axis;
+    T.geo = owner ? d_otile_geo : d_tile_geo;
+    T.ntiles = owner ? ontiles : ntiles;
+    T.gx = owner ? 0 : ghost;
+    T.wx = tile_dims[0] + 2 * T.gx;
     return T;
   }
 };
@@ -311,6 +318,9 @@ void release(pmp_ctx* c) {
   (void)hipFree(c->d_tile_prefix);
   (void)hipFree(c->d_tiles_axis);
   (void)hipFree(c->d_tile_geo);
+  (void)hipFree(c->d_otile_prefix);
+  (void)hipFree(c->d_otiles_axis);
+  (void)hipFree(c->d_otile_geo);
   (void)hipFree(c->d_zone_off);
   (void)hipFree(c->d_zone_seg);
   (void)hipFree(c->d_own_start);
@@ -320,11 +330,32 @@ void release(pmp_ctx* c) {
   if (!c->ws) free_bin_work(c);
 }
 
-// Tiles of edge (tx, tyz, tyz) over every padded box.
-int build_tiles(pmp_ctx* c, int tx, int tyz) {
+// Owner tiles of edge (tx, tyz, tyz) need every tile extent along an axis to
+// be at most domain - 2g cells (a stencil then meets one periodic image of a
+// tile at most, and never two images of one cell).
+bool owner_tiles_fit(const pmp_ctx* c, int tx, int tyz) {
   const int t[3] = {tx, tyz, tyz};
-  std::vector<long long> prefix(c->nbox + 1, 0);
-  std::vector<int> axis(3 * (size_t)c->nbox);
+  for (int a = 0; a < 3; ++a) {
+    int widest = 0;
+    for (int b = 0; b < c->nbox; ++b) widest = std::max(widest, std::min(t[a], c->dboxes[b].n[a]));
+    if (widest > c->domain[a] - 2 * c->ghost) return false;
+  }
+  return true;
+}
+
+// Tiles of edge (tx, tyz, tyz): over every padded box, or (owner) over the
+// owned cells of every box.
+struct HostGrid {
+  std::vector<long long> prefix;
+  std::vector<int> axis;
+  std::vector<TileGeo> geo;
+};
+
+int make_grid(const pmp_ctx* c, int tx, int tyz, bool owner, HostGrid& H) {
+  const int t[3] = {tx, tyz, tyz};
+  const int g0 = c->ghost;
+  H.prefix.assign(c->nbox + 1, 0);
+  H.axis.assign(3 * (size_t)c->nbox, 0);
   for (int b = 0; b < c->nbox; ++b) {
     // the tile pass indexes a tile's cells by 32-bit offsets from its origin
     const DevBox& db = c->dboxes[b];
@@ -333,71 +364,114 @@ int build_tiles(pmp_ctx* c, int tx, int tyz) {
                   b, tyz, db.p[0], db.p[1], tyz);
     long long n = 1;
     for (int a = 0; a < 3; ++a) {
-      const int p = c->dboxes[b].p[a];
+      const int p = db.p[a];
       // x: boundaries on owned cells g + k t (first and last take the ghosts)
-      axis[3 * b + a] = (a == 0) ? (c->dboxes[b].n[0] + t[0] - 1) / t[0] : (p + t[a] - 1) / t[a];
-      n *= axis[3 * b + a];
+      H.axis[3 * b + a] =
+          (a == 0 || owner) ? (db.n[a] + t[a] - 1) / t[a] : (p + t[a] - 1) / t[a];
+      n *= H.axis[3 * b + a];
     }
-    prefix[b + 1] = prefix[b] + n;
+    H.prefix[b + 1] = H.prefix[b] + n;
   }
-  if (2 * prefix[c->nbox] + 1 >= (1ll << 31))
-    return fail(PMP_ERANGE, "too many tiles (%lld); use larger tiles", prefix[c->nbox]);
+  if (2 * H.prefix[c->nbox] + 1 >= (1ll << 31))
+    return fail(PMP_ERANGE, "too many tiles (%lld); use larger tiles", H.prefix[c->nbox]);
   // per-tile geometry, in tile order (x fastest within a box)
-  std::vector<TileGeo> geo((size_t)prefix[c->nbox]);
+  H.geo.assign((size_t)H.prefix[c->nbox], TileGeo{});
   for (int b = 0; b < c->nbox; ++b) {
     const DevBox& d = c->dboxes[b];
-    const int* ax = &axis[3 * (size_t)b];
-    long long q = prefix[b];
+    const int* ax = &H.axis[3 * (size_t)b];
+    long long q = H.prefix[b];
     for (int tz = 0; tz < ax[2]; ++tz)
       for (int ty = 0; ty < ax[1]; ++ty)
-        for (int tx = 0; tx < ax[0]; ++tx, ++q) {
-          TileGeo& G = geo[(size_t)q];
+        for (int tx_ = 0; tx_ < ax[0]; ++tx_, ++q) {
+          TileGeo& G = H.geo[(size_t)q];
           std::memset(&G, 0, sizeof G);
-          const int tc[3] = {tx, ty, tz};
+          const int tc[3] = {tx_, ty, tz};
           G.boff = d.boff;
           G.soff = d.soff;
           G.b = b;
           for (int a = 0; a < 3; ++a) {
             G.p[a] = d.p[a];
-            if (a == 0) {
-              const int g0 = c->ghost;
-              G.o[0] = (tx == 0) ? 0 : g0 + tx * t[0];
-              const int end = (tx == ax[0] - 1) ? d.p[0] : g0 + (tx + 1) * t[0];
+            if (owner) {
+              // owned cells [tc t, (tc + 1) t) of the box; padded-local origin
+              G.o[a] = g0 + tc[a] * t[a];
+              G.ext[a] = std::min(t[a], d.n[a] - tc[a] * t[a]);
+            } else if (a == 0) {
+              G.o[0] = (tx_ == 0) ? 0 : g0 + tx_ * t[0];
+              const int end = (tx_ == ax[0] - 1) ? d.p[0] : g0 + (tx_ + 1) * t[0];
               G.ext[0] = end - G.o[0];
             } else {
               G.o[a] = tc[a] * t[a];
               G.ext[a] = std::min(t[a], d.p[a] - G.o[a]);
             }
-            G.glo[a] = G.o[a] - c->ghost + d.lo[a];
+            G.glo[a] = G.o[a] - g0 + d.lo[a];
           }
         }
   }
+  return PMP_OK;
+}
+
+int upload_grid(const HostGrid& H, long long** dp, int** da, TileGeo** dt) {
+  *dp = nullptr;
+  *da = nullptr;
+  *dt = nullptr;
+  hipError_t e = dev_alloc(dp, H.prefix.size());
+  if (e == hipSuccess) e = dev_alloc(da, H.axis.size());
+  if (e == hipSuccess) e = dev_alloc(dt, std::max<size_t>(H.geo.size(), 1));
+  if (e == hipSuccess)
+    e = hipMemcpy(*dp, H.prefix.data(), sizeof(long long) * H.prefix.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(*da, H.axis.data(), sizeof(int) * H.axis.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !H.geo.empty())
+    e = hipMemcpy(*dt, H.geo.data(), sizeof(TileGeo) * H.geo.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(*dp);
+    (void)hipFree(*da);
+    (void)hipFree(*dt);
+    return fail(PMP_EDEVICE, "tile grid: %s", hipGetErrorString(e));
+  }
+  return PMP_OK;
+}
+
+// Both tile grids for edge (tx, tyz, tyz); the owner grid only where owner
+// tiles fit the layout.
+int build_tiles(pmp_ctx* c, int tx, int tyz) {
+  HostGrid H, O;
+  if (int rc = make_grid(c, tx, tyz, false, H)) return rc;
+  const bool own = owner_tiles_fit(c, tx, tyz);
+  if (own)
+    if (int rc = make_grid(c, tx, tyz, true, O)) return rc;
   long long* dp = nullptr;
   int* da = nullptr;
   TileGeo* dt = nullptr;
-  hipError_t e = dev_alloc(&dp, prefix.size());
-  if (e == hipSuccess) e = dev_alloc(&da, axis.size());
-  if (e == hipSuccess) e = dev_alloc(&dt, std::max<size_t>(geo.size(), 1));
-  if (e == hipSuccess)
-    e = hipMemcpy(dp, prefix.data(), sizeof(long long) * prefix.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(da, axis.data(), sizeof(int) * axis.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !geo.empty())
-    e = hipMemcpy(dt, geo.data(), sizeof(TileGeo) * geo.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(dp);
-    (void)hipFree(da);
-    (void)hipFree(dt);
-    return fail(PMP_EDEVICE, "tile grid: %s", hipGetErrorString(e));
-  }
+  long long* op = nullptr;
+  int* oa = nullptr;
+  TileGeo* ot = nullptr;
+  if (int rc = upload_grid(H, &dp, &da, &dt)) return rc;
+  if (own)
+    if (int rc = upload_grid(O, &op, &oa, &ot)) {
+      (void)hipFree(dp);
+      (void)hipFree(da);
+      (void)hipFree(dt);
+      return rc;
+    }
   (void)hipFree(c->d_tile_prefix);
   (void)hipFree(c->d_tiles_axis);
   (void)hipFree(c->d_tile_geo);
+  (void)hipFree(c->d_otile_prefix);
+  (void)hipFree(c->d_otiles_axis);
+  (void)hipFree(c->d_otile_geo);
   c->d_tile_prefix = dp;
   c->d_tiles_axis = da;
   c->d_tile_geo = dt;
-  for (int a = 0; a < 3; ++a) c->tile_dims[a] = t[a];
-  c->ntiles = prefix[c->nbox];
+  c->d_otile_prefix = op;
+  c->d_otiles_axis = oa;
+  c->d_otile_geo = ot;
+  c->owner_ok = own;
+  for (int a = 0; a < 3; ++a) c->tile_dims[a] = tx;
+  c->tile_dims[1] = c->tile_dims[2] = tyz;
+  c->ntiles = H.prefix[c->nbox];
+  c->ontiles = own ? O.prefix[c->nbox] : 0;
   return PMP_OK;
 }
 
@@ -583,17 +657,42 @@ struct BinSizes {
             sn_cap = 0, hist2 = 0, blocks2 = 0, slice_base = 0, n_sn = 0;
 };
 
+// The step runs on owner tiles (no ghost zone, no fold): tuning fuse_apply 2
+// where the owner tiles fit the layout, the binned path, no reproducibility
+// mode.  (Steps with sinks never do.)
+bool owner_step(const pmp_ctx* c) {
+  return c->tune.fuse_apply == 2 && c->owner_ok && c->tune.deposit_path == 1 &&
+         c->acc != PMP_ACC_F64R;
+}
+
 int bin_sizes(const pmp_ctx* c, long long n_cic, long long n_sn, double r_max, BinSizes& z) {
   const int* t = c->tile_dims;
   const long long span = 2 * (long long)std::ceil(std::max(r_max, 0.0)) + 3;
-  const long long maxt = tiles_for(span, t[0]) * tiles_for(span, t[1]) * tiles_for(span, t[2]);
+  long long maxt = tiles_for(span, t[0]) * tiles_for(span, t[1]) * tiles_for(span, t[2]);
+  if (owner_step(c)) {
+    // owner tiles: per axis the span splits into segments at box faces and
+    // at the periodic wrap, each adding at most two tiles (never more tiles
+    // than cells)
+    long long m = 1;
+    for (int a = 0; a < 3; ++a) {
+      long long seg = 2;
+      if (c->nbox > 1 || c->d_own_start) {
+        int edge = c->domain[a];
+        for (const auto& b : c->hboxes) edge = std::min(edge, b.n[a]);
+        seg = (span - 1) / std::max(edge, 1) + 2;
+      }
+      m *= std::min<long long>(span, (span + t[a] - 1) / t[a] + 2 * seg - 1);
+    }
+    maxt = std::max(maxt, m);
+  }
   const long long nbc = (n_cic + kBinChunkCic - 1) / kBinChunkCic;
   const long long nbs = (n_sn + kBinChunkSn - 1) / kBinChunkSn;
   const long long cic_cap = std::max<long long>(8 * n_cic, 1);
   const long long sn_cap = std::max<long long>(maxt * n_sn, 1);
   const long long full_slices = (cic_cap + kSlice - 1) / kSlice + (sn_cap + kSlice - 1) / kSlice;
   // coarse buckets of 2^shift consecutive tiles (at most 1024 buckets, at
-  // most 8192 tiles per bucket): the shift that minimises the histogram work,
+  // most 8192 tiles per bucket; sized for the padded grid, which never has
+  // fewer tiles than the owner grid): the shift that minimises the histogram work,
   // level 1 (nb x blocks counts, written one cache line apart, weighted 4)
   // plus level 2 (2^shift x slices counts, zeroed and scanned)
   int shift = -1;
@@ -886,11 +985,13 @@ SinkParams sink_params(const pmp_ctx* c, const pmp_sinks* p) {
 }
 
 // fuse_state non-null (a step without sinks): the binned path also applies
-// the interior cells; *fused tells whether it did.
+// the interior cells, or, on owner tiles (owner), every owned cell; *fused
+// tells which it did (0: none, 1: the interior cells, 2: every cell).
 int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, const pmp_sn* sn,
                const pmp_sinks* sinks, const pmp_limits* limits, hipStream_t s,
-               void* fuse_state = nullptr, bool* fused = nullptr) {
-  if (fused) *fused = false;
+               void* fuse_state = nullptr, int* fused = nullptr, bool owner = false) {
+  if (fused) *fused = 0;
+  if (!fuse_state) owner = false;
   if (!buf) return fail(PMP_EINVAL, "buffer is NULL");
   c->ws_sink_bytes = 0;  // a workspace holds this deposit's sink scratch first, if any
   const bool has_cic = cic && cic->n > 0;
@@ -927,7 +1028,7 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
     if (rc) return rc;
     const Particles pc = has_cic ? from_cic(cic) : Particles{};
     const Particles ps = has_sn ? from_sn(sn) : Particles{};
-    const TileGrid T = c->tiles();
+    const TileGrid T = c->tiles(owner);
     {
       PhaseTimer t(c, PMP_PHASE_BIN, s);
       PMP_HIP(launch_bin(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
@@ -945,7 +1046,7 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
       }
       PMP_HIP(launch_tile_deposit(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
                                   buf, c->tune, fuse_state, L, s));
-      if (fused) *fused = fuse_state != nullptr;
+      if (fused) *fused = !fuse_state ? 0 : (owner ? 2 : 1);
     }
   } else {
     {
@@ -1007,10 +1108,12 @@ int do_fold(pmp_ctx* c, void* buf, hipStream_t s) {
 int do_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn* sn,
             const pmp_sinks* sinks, const pmp_limits* limits, double* sink_out, hipStream_t s) {
   const bool has_sinks = sinks && sinks->n > 0;
-  bool fused = false;
+  int fused = 0;
   int rc = do_deposit(c, buf, state, cic, sn, sinks, limits, s,
-                      (!has_sinks && c->tune.fuse_apply && state) ? state : nullptr, &fused);
+                      (!has_sinks && c->tune.fuse_apply && state) ? state : nullptr, &fused,
+                      owner_step(c));
   if (rc) return rc;
+  if (fused == 2) return PMP_OK;  // owner tiles: every owned cell is done
   if (fused) {
     // interior cells are done; fold and apply the shell
     PhaseTimer t(c, PMP_PHASE_FOLD, s);
@@ -1586,7 +1689,7 @@ int pmp_set_tuning(pmp_ctx* c, const pmp_tuning* t) {
     return fail(PMP_EINVAL, "tile_grid_per_cu 0..64");
   if (t->chunk_cic < 64 || t->chunk_cic > (1 << 24)) return fail(PMP_EINVAL, "chunk_cic 64..2^24");
   if (t->chunk_sn < 16 || t->chunk_sn > (1 << 24)) return fail(PMP_EINVAL, "chunk_sn 16..2^24");
-  if (t->fuse_apply != 0 && t->fuse_apply != 1) return fail(PMP_EINVAL, "fuse_apply 0 or 1");
+  if (t->fuse_apply < 0 || t->fuse_apply > 2) return fail(PMP_EINVAL, "fuse_apply 0, 1 or 2");
   if (t->count_lanes != 1 && t->count_lanes != 2 && t->count_lanes != 4 && t->count_lanes != 8 &&
       t->count_lanes != 16)
     return fail(PMP_EINVAL, "count_lanes 1, 2, 4, 8 or 16");
@@ -1635,9 +1738,13 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
                            {16, 8, 256}, {64, 2, 128}, {16, 4, 128}, {32, 4, 256},
                            {64, 8, 256}, {64, 8, 512}, {128, 4, 256}, {128, 4, 512},
                            {256, 4, 256}, {256, 4, 512}, {256, 2, 256}};
-  // the fused apply only applies to steps without sinks
-  for (int fuse = has_sinks ? 0 : 1; fuse >= 0; --fuse)
-    for (const auto& sh : shapes) add(1, sh[0], sh[1], sh[2], 64, 0, fuse);
+  // the fused apply only applies to steps without sinks; owner tiles (2)
+  // where they fit the layout
+  for (int fuse = has_sinks ? 0 : 2; fuse >= 0; --fuse)
+    for (const auto& sh : shapes) {
+      if (fuse == 2 && (c->acc == PMP_ACC_F64R || !owner_tiles_fit(c, sh[0], sh[1]))) continue;
+      add(1, sh[0], sh[1], sh[2], 64, 0, fuse);
+    }
   // the caller's state is left as it was: candidates run on a copy
   const size_t sbytes = (size_t)c->state_elems * (c->state == PMP_STATE_F32 ? 4 : 8);
   void* work = nullptr;

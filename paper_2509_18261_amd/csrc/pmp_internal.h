@@ -116,6 +116,15 @@ struct Particles {
 // [k == 0 ? 0 : g + k*TX, k == ntx-1 ? p : g + (k+1)*TX) with ntx =
 // ceil(n/TX), so the first and last take the ghost slabs (width <= TX + 2g).
 // Global tile id = tile_prefix[b] + (tz*nty + ty)*ntx + tx.
+//
+// Owner tiles (the fold-free step): tiles cover the owned cells only, [t*T,
+// (t+1)*T) clipped to the box along every axis.  A particle is binned into
+// every owner tile its stencil reaches after wrapping the stencil's cells
+// periodically, in whichever box owns them, so a tile receives every
+// contribution to its cells: what the ghost zones and the fold would carry is
+// added where it lands.  Valid when no tile along an axis is wider than the
+// domain less 2g cells: then a stencil (at most 2g + 1 cells per axis) meets
+// at most one periodic image of a tile, and never holds two images of a cell.
 // Geometry of one tile, fixed by the layout and the tile shape.
 struct alignas(16) TileGeo {
   long long boff;  // buffer offset of the tile's box
@@ -124,7 +133,7 @@ struct alignas(16) TileGeo {
   int o[3];        // tile origin, padded-local
   int ext[3];      // cells of the tile inside the padded box
   int b;           // box
-  int glo[3];      // global cell of the tile origin
+  int glo[3];      // global cell of the tile origin (owner tiles: in [0, domain))
   int pad;
 };
 
@@ -136,6 +145,7 @@ struct TileGrid {
   long long ntiles;
   int gx;                         // ghost width (x tile boundaries at gx + k*TX)
   int wx;                         // widest x tile, TX + 2 gx (LDS row width)
+  int owner;                      // 1: owner tiles (gx = 0, wx = TX)
 };
 
 // A supernova as prepared once by the binning pass; tile entry lists hold
@@ -147,7 +157,8 @@ struct SnPk {
   double vr, ve;
   long long remr, reme;  // fixed point: Q(m / V) - N Q(m / (N V)), same for e
   int n;                 // sphere members (-1: host cell only, 0: skipped)
-  int ti, tj, tk;        // padded-local remainder cell (ti < 0: none in the box)
+  int ti, tj, tk;        // padded-local remainder cell (owner tiles: its periodic image,
+                         // global); ti < 0: none in the box
 };
 
 // A supernova entry of one tile as the tile pass holds it in LDS: the row
@@ -156,7 +167,8 @@ struct alignas(16) SnTile {
   double x, y, z, r2;     // centre and r^2
   double vr, ve;          // member share (for fixed point: the quanta's bits)
   int lo, hi;             // candidate cells along x, global (host cell alone: that cell)
-  int host;               // the host cell alone takes the deposit
+  int host;               // bit 0: the host cell alone takes the deposit; owner tiles:
+                          // bits 1 + 2a, 2 + 2a the tile image along axis a (+D, -D)
   unsigned rows;          // candidate tile rows: vlo | vhi << 8 | wlo << 16 | whi << 24
 };
 
@@ -204,9 +216,12 @@ constexpr int kTileSnBatch = 64;
 // LDS of one tile workgroup: two accumulator channels of the widest tile
 // (tx + 2g cells along x) with rows padded by one cell (and their two error
 // bounds in the reproducibility mode), then one batch of supernova entries.
-__host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz, int g, bool bounds) {
-  return (bounds ? 4ll : 2ll) * (tx + 2 * g + 1) * tyz * tyz * 8 +
+__host__ __device__ constexpr long long tile_lds_bytes_wx(int wx, int tyz, bool bounds) {
+  return (bounds ? 4ll : 2ll) * (wx + 1) * tyz * tyz * 8 +
          (long long)kTileSnBatch * (long long)sizeof(SnTile);
+}
+__host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz, int g, bool bounds) {
+  return tile_lds_bytes_wx(tx + 2 * g, tyz, bounds);
 }
 
 constexpr int kBinChunkCic = 1024;  // CIC particles per level-1 block
@@ -229,7 +244,8 @@ hipError_t launch_tile_prep(const Mesh& M, const TileGrid& T, const Particles* c
 // state non-null: the step's Steps 3 + 5 are fused in for owned cells at
 // least g from every face of their box (no ghost image reaches them); those
 // cells' buffer entries are left unwritten, and launch_fold_apply finishes
-// the shell cells.
+// the shell cells.  With owner tiles (T.owner) state must be non-null: every
+// owned cell is applied and the buffer is not written at all.
 hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles* cic,
                                const Particles* sn, const BinWork& bw, void* buf,
                                const pmp_tuning& t, void* state, const Limits& L,

@@ -1741,6 +1741,110 @@ __device__ __forceinline__ long long tile_id(const TileGrid& T, int b, int tx, i
   return T.tile_prefix[b] + ((long long)tz * ta[1] + ty) * ta[0] + tx;
 }
 
+// Owner tiles: calls f(tile id) once for every owner tile holding a cell of
+// the global cell range [lo, hi] of a particle's own frame (hi - lo < domain
+// per axis, lo > -domain) after wrapping it periodically.  Per axis the range
+// wraps into at most two pieces; for each combination of pieces the boxes
+// that meet it come from the owner index, each taken once, by the bin that
+// holds the lowest cell of its intersection with the piece.  Distinct pieces
+// never share a tile (the owner-tile condition), so each tile comes once.
+template <class F>
+__device__ __forceinline__ void owner_tiles(const Mesh& M, const TileGrid& T, const int lo[3],
+                                            const int hi[3], F&& f) {
+  int pl[3][2], ph[3][2], np[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int D = M.domain[a], l = lo[a], h = hi[a];
+    np[a] = 1;
+    if (l < 0 && h < 0) {
+      pl[a][0] = l + D; ph[a][0] = h + D;
+    } else if (l < 0) {
+      pl[a][0] = 0; ph[a][0] = h; pl[a][1] = l + D; ph[a][1] = D - 1; np[a] = 2;
+    } else if (l >= D) {
+      pl[a][0] = l - D; ph[a][0] = h - D;
+    } else if (h >= D) {
+      pl[a][0] = l; ph[a][0] = D - 1; pl[a][1] = 0; ph[a][1] = h - D; np[a] = 2;
+    } else {
+      pl[a][0] = l; ph[a][0] = h;
+    }
+  }
+  auto box_tiles = [&](int b, const DevBox& B, const int il[3], const int ih[3]) {
+    int tlo[3], thi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      tlo[a] = (il[a] - B.lo[a]) / T.t[a];
+      thi[a] = (ih[a] - B.lo[a]) / T.t[a];
+    }
+    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
+      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
+        for (int tx = tlo[0]; tx <= thi[0]; ++tx) f((int)tile_id(T, b, tx, ty, tz));
+  };
+  for (int cz = 0; cz < np[2]; ++cz)
+    for (int cy = 0; cy < np[1]; ++cy)
+      for (int cx = 0; cx < np[0]; ++cx) {
+        const int rl[3] = {pl[0][cx], pl[1][cy], pl[2][cz]};
+        const int rh[3] = {ph[0][cx], ph[1][cy], ph[2][cz]};
+        if (M.own_start == nullptr) {
+          // one box covers the domain
+          box_tiles(0, M.all_boxes[0], rl, rh);
+          continue;
+        }
+        int bl[3], bh[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          bl[a] = rl[a] / M.own_bin[a];
+          bh[a] = rh[a] / M.own_bin[a];
+        }
+        for (int bz = bl[2]; bz <= bh[2]; ++bz)
+          for (int by = bl[1]; by <= bh[1]; ++by)
+            for (int bx = bl[0]; bx <= bh[0]; ++bx) {
+              const int bin = (bz * M.own_dims[1] + by) * M.own_dims[0] + bx;
+              const int bb[3] = {bx, by, bz};
+              for (int q = M.own_start[bin]; q < M.own_start[bin + 1]; ++q) {
+                const int b = M.own_box[q];
+                const DevBox& B = M.all_boxes[b];
+                int il[3], ih[3];
+                bool hit = true;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                  il[a] = max(rl[a], B.lo[a]);
+                  ih[a] = min(rh[a], B.lo[a] + B.n[a] - 1);
+                  hit = hit && il[a] <= ih[a] && il[a] / M.own_bin[a] == bb[a];
+                }
+                if (hit) box_tiles(b, B, il, ih);
+              }
+            }
+      }
+}
+
+// Calls f(tile id) for every tile holding a cell of the padded-local range
+// [lo, hi] of box B (clipped to the padded box): the tiles of B itself, or,
+// with owner tiles, the owner tiles of whichever boxes own those cells.
+template <bool OWN, class F>
+__device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T, int b,
+                                               const DevBox& B, const int lo[3], const int hi[3],
+                                               F&& f) {
+  if constexpr (!OWN) {
+    int tlo[3], thi[3];
+    if (!tile_range(B, T, lo, hi, tlo, thi)) return;
+    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
+      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
+        for (int tx = tlo[0]; tx <= thi[0]; ++tx) f((int)tile_id(T, b, tx, ty, tz));
+    return;
+  } else {
+  const int g = M.ghost;
+  int gl[3], gh[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int l = max(lo[a], 0), h = min(hi[a], B.p[a] - 1);
+    if (l > h) return;
+    gl[a] = l - g + B.lo[a];
+    gh[a] = h - g + B.lo[a];
+  }
+  owner_tiles(M, T, gl, gh, f);
+  }
+}
+
 // Exclusive scan of count[0, n) into offset[0, n] (offset[n] = total) in
 // three launches; count is cleared on the way (it becomes the fill cursor).
 constexpr int kScanBlock = 1024;
@@ -1832,7 +1936,7 @@ __device__ __forceinline__ int hist_col(int blk, int nblk) {
   return x * k + min(x, r) + (blk >> 3);
 }
 
-template <bool SCATTER>
+template <bool SCATTER, bool OWN>
 __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T,
                                        const Particles& P, int shift, int nb,
                                        int* __restrict__ hist, int nblk,
@@ -1874,23 +1978,28 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
     int hc[3];
     if (!host_cell(B, x, y, z, hc)) { outside = true; continue; }
     if (!isfinite(m)) { nan = true; continue; }
-    int lo[3], hi[3], tlo[3], thi[3];
+    int lo[3], hi[3];
     cic_box(B, g, x, y, z, lo, hi);
-    if (!tile_range(B, T, lo, hi, tlo, thi)) continue;
-    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
-      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
-        for (int tx = tlo[0]; tx <= thi[0]; ++tx) {
-          const int t = (int)tile_id(T, b, tx, ty, tz);
-          const int pos = atomicAdd(h + (t >> shift), 1);
-          if (SCATTER) {
-            if (pos < cap) {
-              tmp[pos] = make_double4(x, y, z, m);
-              tmp_tile[pos] = t;
-            } else {
-              full = true;
-            }
-          }
+    auto put = [&](int t) {
+      const int pos = atomicAdd(h + (t >> shift), 1);
+      if (SCATTER) {
+        if (pos < cap) {
+          tmp[pos] = make_double4(x, y, z, m);
+          tmp_tile[pos] = t;
+        } else {
+          full = true;
         }
+      }
+    };
+    if constexpr (OWN) {
+      particle_tiles<true>(M, T, b, B, lo, hi, put);
+    } else {
+      int tlo[3], thi[3];
+      if (!tile_range(B, T, lo, hi, tlo, thi)) continue;
+      for (int tz = tlo[2]; tz <= thi[2]; ++tz)
+        for (int ty = tlo[1]; ty <= thi[1]; ++ty)
+          for (int tx = tlo[0]; tx <= thi[0]; ++tx) put((int)tile_id(T, b, tx, ty, tz));
+    }
   }
   if (!SCATTER) {
     if (outside) raise_flag(M.status, PMP_FLAG_OUTSIDE);
@@ -1903,11 +2012,12 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
   }
 }
 
-// Tiles a supernova's deposit touches: those of its sphere's candidate box,
-// or of the host cell alone when N < 0.
-__device__ __forceinline__ bool sn_tiles(const Mesh& M, const TileGrid& T, const DevBox& B,
-                                         double x, double y, double z, double r, int N,
-                                         int tlo[3], int thi[3]) {
+// Calls f(tile id) for the tiles a supernova's deposit touches: those of its
+// sphere's candidate box, or of the host cell alone when N < 0.
+template <bool OWN, class F>
+__device__ __forceinline__ void sn_tiles(const Mesh& M, const TileGrid& T, int b,
+                                         const DevBox& B, double x, double y, double z,
+                                         double r, int N, F&& f) {
   const int g = M.ghost;
   int slo[3], shi[3];
   if (N < 0) {
@@ -1916,7 +2026,7 @@ __device__ __forceinline__ bool sn_tiles(const Mesh& M, const TileGrid& T, const
   } else {
     sphere_box(B, g, x, y, z, r, slo, shi);
   }
-  return tile_range(B, T, slo, shi, tlo, thi);
+  particle_tiles<OWN>(M, T, b, B, slo, shi, f);
 }
 
 // Supernova members, before binning: L lanes per particle (256 / L particles
@@ -1927,7 +2037,8 @@ __device__ __forceinline__ bool sn_tiles(const Mesh& M, const TileGrid& T, const
 // member, else the first member in (k, j, i) order); the first lane writes
 // the particle's SnPk.
 template <int L>
-__global__ __launch_bounds__(256) void k_sn_count(Mesh M, Particles P, SnPk* __restrict__ pk) {
+__global__ __launch_bounds__(256) void k_sn_count(Mesh M, Particles P, SnPk* __restrict__ pk,
+                                                  int wrap) {
   const int g = M.ghost;
   const long long p0 = (long long)blockIdx.x * (256 / L);
   const long long p1 = min(p0 + 256 / L, P.n);
@@ -2030,9 +2141,16 @@ __global__ __launch_bounds__(256) void k_sn_count(Mesh M, Particles P, SnPk* __r
     if (N > 0 && !hm) sphere_key_cell(Sp, key, ti, tj, tk);
     long long idx;
     if (pad_index(B, g, ti, tj, tk, idx)) {
-      R.ti = ti - B.lo[0] + g;
-      R.tj = tj - B.lo[1] + g;
-      R.tk = tk - B.lo[2] + g;
+      if (wrap) {
+        // owner tiles: the cell's periodic image, global
+        R.ti = imod(ti, M.domain[0]);
+        R.tj = imod(tj, M.domain[1]);
+        R.tk = imod(tk, M.domain[2]);
+      } else {
+        R.ti = ti - B.lo[0] + g;
+        R.tj = tj - B.lo[1] + g;
+        R.tk = tk - B.lo[2] + g;
+      }
     }
     if (out && sub == 0) raise_flag(M.status, PMP_FLAG_REACH);
   }
@@ -2043,6 +2161,7 @@ __global__ __launch_bounds__(256) void k_sn_count(Mesh M, Particles P, SnPk* __r
 // Level 1, supernovae, histogram pass: one thread per particle counts it
 // into the buckets of every tile its sphere touches (kBinChunkSn particles
 // per block; skipped particles have n = 0).
+template <bool OWN>
 __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGrid& T,
                                            const Particles& P, int shift, int nb,
                                            int* __restrict__ hist, int nblk,
@@ -2061,12 +2180,8 @@ __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGri
     if (N == 0) continue;
     const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
     const DevBox B = M.boxes[b];
-    int tlo[3], thi[3];
-    if (!sn_tiles(M, T, B, R.x, R.y, R.z, R.r, N, tlo, thi)) continue;
-    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
-      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
-        for (int tx = tlo[0]; tx <= thi[0]; ++tx)
-          atomicAdd(h + ((int)tile_id(T, b, tx, ty, tz) >> shift), 1);
+    sn_tiles<OWN>(M, T, b, B, R.x, R.y, R.z, R.r, N,
+                  [&](int t) { atomicAdd(h + (t >> shift), 1); });
   }
   __syncthreads();
   for (int c = threadIdx.x; c < nb; c += blockDim.x) hist[(long long)c * nblk + col] = h[c];
@@ -2074,6 +2189,7 @@ __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGri
 
 // Level 1, supernovae, scatter pass: one thread per particle writes its
 // (particle, tile) entries at the positions the scanned histograms give.
+template <bool OWN>
 __device__ __forceinline__ void l1_sn_scatter(int blk, const Mesh& M, const TileGrid& T,
                                               const Particles& P, int shift, int nb,
                                               int* __restrict__ hist, int nblk,
@@ -2095,36 +2211,33 @@ __device__ __forceinline__ void l1_sn_scatter(int blk, const Mesh& M, const Tile
     if (N == 0) continue;
     const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
     const DevBox B = M.boxes[b];
-    int tlo[3], thi[3];
-    if (!sn_tiles(M, T, B, R.x, R.y, R.z, R.r, N, tlo, thi)) continue;
-    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
-      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
-        for (int tx = tlo[0]; tx <= thi[0]; ++tx) {
-          const int id = (int)tile_id(T, b, tx, ty, tz);
-          const int pos = atomicAdd(h + (id >> shift), 1);
-          if (pos < cap) {
-            tmp[pos] = (int)p;
-            tmp_tile[pos] = id;
-          } else {
-            full = true;
-          }
-        }
+    sn_tiles<OWN>(M, T, b, B, R.x, R.y, R.z, R.r, N, [&](int id) {
+      const int pos = atomicAdd(h + (id >> shift), 1);
+      if (pos < cap) {
+        tmp[pos] = (int)p;
+        tmp_tile[pos] = id;
+      } else {
+        full = true;
+      }
+    });
   }
   if (full) raise_flag(M.status, PMP_FLAG_CAPACITY);
 }
 
 // Level 1 for both kinds in one launch: blocks [0, nbc) take CIC chunks,
 // the rest supernova chunks.
+template <bool OWN>
 __global__ __launch_bounds__(256) void k_l1_hist(Mesh M, TileGrid T, Particles C, Particles Sn,
                                                 int shift, int nb, int* __restrict__ hc, int nbc,
                                                 int* __restrict__ hs, int nbs,
                                                 const SnPk* __restrict__ pk) {
   if ((int)blockIdx.x < nbc)
-    l1_cic<false>(blockIdx.x, M, T, C, shift, nb, hc, nbc, nullptr, nullptr, 0);
+    l1_cic<false, OWN>(blockIdx.x, M, T, C, shift, nb, hc, nbc, nullptr, nullptr, 0);
   else
-    l1_sn_hist(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk);
+    l1_sn_hist<OWN>(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk);
 }
 
+template <bool OWN>
 __global__ __launch_bounds__(256) void k_l1_scatter(Mesh M, TileGrid T, Particles C,
                                                    Particles Sn, int shift, int nb,
                                                    int* __restrict__ hc, int nbc,
@@ -2135,9 +2248,9 @@ __global__ __launch_bounds__(256) void k_l1_scatter(Mesh M, TileGrid T, Particle
                                                    int* __restrict__ stmp,
                                                    int* __restrict__ stmp_tile, long long scap) {
   if ((int)blockIdx.x < nbc)
-    l1_cic<true>(blockIdx.x, M, T, C, shift, nb, hc, nbc, ctmp, ctmp_tile, ccap);
+    l1_cic<true, OWN>(blockIdx.x, M, T, C, shift, nb, hc, nbc, ctmp, ctmp_tile, ccap);
   else
-    l1_sn_scatter(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk, stmp, stmp_tile, scap);
+    l1_sn_scatter<OWN>(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk, stmp, stmp_tile, scap);
 }
 
 // Level 2: one workgroup per coarse bucket sorts the bucket's records by
@@ -2382,6 +2495,33 @@ template <> __device__ __forceinline__ long long from_lds<long long>(unsigned lo
 }
 template <class T> __device__ __forceinline__ T from_lds(double v) { return (T)v; }
 
+// Owner tiles: cell index i of a particle's frame (-domain <= i < 2 domain)
+// wrapped into [0, domain).
+__device__ __forceinline__ int wrap_once(int i, int D) {
+  return i < 0 ? i + D : (i >= D ? i - D : i);
+}
+
+// Owner tiles: the origin, in a particle's frame, of the periodic image of
+// a tile [glo, glo + ext) that meets the particle's candidate cells [lo, hi]
+// along axis a, and its code (1: + D, 2: - D) in bits 1 + 2a of `code`.
+__device__ __forceinline__ int image_origin(int lo, int hi, int glo, int ext, int D, int a,
+                                            int& code) {
+  if (hi < glo) {
+    code |= 2 << (1 + 2 * a);
+    return glo - D;
+  }
+  if (lo >= glo + ext) {
+    code |= 1 << (1 + 2 * a);
+    return glo + D;
+  }
+  return glo;
+}
+
+__device__ __forceinline__ int image_shift(int code, int a, int glo, int D) {
+  const int c = (code >> (1 + 2 * a)) & 3;
+  return c == 1 ? glo + D : (c == 2 ? glo - D : glo);
+}
+
 // One workgroup per work unit (a whole tile, or one chunk of a split tile):
 // CIC entries one per thread; supernovae in batches of up to one wavefront:
 // one lane per entry gathers its particle's record, clips the sphere's
@@ -2392,7 +2532,7 @@ template <class T> __device__ __forceinline__ T from_lds(double v) { return (T)v
 // shares and fixed-point remainders are the same as in the direct kernels.
 // (7 waves per SIMD: the register budget that keeps the LDS-limited
 // occupancy of the common tile shapes without spilling)
-template <int ACC, int TYZ>
+template <int ACC, int TYZ, bool OWN>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void k_tile_deposit(Mesh M, TileGrid T,
                                                       const int* __restrict__ coff,
                                                       const double4* __restrict__ crec,
@@ -2501,9 +2641,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
           E.ve = R.ve;
           E.lo = Sp.lo[0];
           E.hi = Sp.hi[0];
-          E.host = R.n < 0;
+          const bool host = R.n < 0;
           int lo1 = Sp.lo[1], hi1 = Sp.hi[1], lo2 = Sp.lo[2], hi2 = Sp.hi[2];
-          if (E.host) {
+          if (host) {
             // the host cell alone
             E.lo = E.hi = (int)floor(R.x);
             lo1 = hi1 = (int)floor(R.y);
@@ -2511,16 +2651,28 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
           } else if (R.n == 0) {
             hi1 = lo1 - 1;
           }
+          // the tile's origin in the supernova's frame: with owner tiles, the
+          // periodic image of the tile that the candidate box meets (one at
+          // most), kept as two bits per axis beside the host bit
+          int gl1 = G.glo[1], gl2 = G.glo[2];
+          E.host = host;
+          if constexpr (OWN) {
+            const int gl0 = image_origin(E.lo, E.hi, G.glo[0], G.ext[0], M.domain[0], 0, E.host);
+            gl1 = image_origin(lo1, hi1, G.glo[1], G.ext[1], M.domain[1], 1, E.host);
+            gl2 = image_origin(lo2, hi2, G.glo[2], G.ext[2], M.domain[2], 2, E.host);
+            (void)gl0;
+          }
           // candidate rows inside the tile: v in [vlo, vhi], w in [wlo, whi]
-          const int vlo = max(lo1 - G.glo[1], 0), vhi = min(hi1 - G.glo[1], G.ext[1] - 1);
-          const int wlo = max(lo2 - G.glo[2], 0), whi = min(hi2 - G.glo[2], G.ext[2] - 1);
+          const int vlo = max(lo1 - gl1, 0), vhi = min(hi1 - gl1, G.ext[1] - 1);
+          const int wlo = max(lo2 - gl2, 0), whi = min(hi2 - gl2, G.ext[2] - 1);
           E.rows = (vlo <= vhi && wlo <= whi)
                        ? (unsigned)(vlo | (vhi << 8) | (wlo << 16) | (whi << 24))
                        : 0x000000ffu;
           bent[q] = E;
           if constexpr (FIXED) {
             // the remainder, at its cell when the cell is in this tile
-            const int lu = R.ti - G.o[0], lv = R.tj - G.o[1], lw = R.tk - G.o[2];
+            const int* ro = OWN ? G.glo : G.o;
+            const int lu = R.ti - ro[0], lv = R.tj - ro[1], lw = R.tk - ro[2];
             if (R.ti >= 0 && (unsigned)lu < (unsigned)G.ext[0] &&
                 (unsigned)lv < (unsigned)G.ext[1] && (unsigned)lw < (unsigned)G.ext[2]) {
               const int tgt = (lw * TY + lv) * TXP + lu;
@@ -2536,6 +2688,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
           const double4 CR = crec[e];
           const int h[3] = {(int)floor(CR.x), (int)floor(CR.y), (int)floor(CR.z)};
           auto add = [&](int i, int j, int k, auto v) {
+            if constexpr (OWN) {
+              // owner tiles: the cell's periodic image
+              i = wrap_once(i, M.domain[0]);
+              j = wrap_once(j, M.domain[1]);
+              k = wrap_once(k, M.domain[2]);
+            }
             const int u = i - G.glo[0], vv = j - G.glo[1], w = k - G.glo[2];
             if ((unsigned)u < (unsigned)G.ext[0] && (unsigned)vv < (unsigned)G.ext[1] &&
                 (unsigned)w < (unsigned)G.ext[2]) {
@@ -2556,19 +2714,25 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
         const int v = sl & (TY - 1), w = sl >> YSH;
         const unsigned rr = E.rows;
         int a = 1, b = 0;
+        int gl0 = G.glo[0], gl1 = G.glo[1], gl2 = G.glo[2];
+        if constexpr (OWN) {
+          gl0 = image_shift(E.host, 0, gl0, M.domain[0]);
+          gl1 = image_shift(E.host, 1, gl1, M.domain[1]);
+          gl2 = image_shift(E.host, 2, gl2, M.domain[2]);
+        }
         if (v < (int)(rr & 255u) || v > (int)((rr >> 8) & 255u) || w < (int)((rr >> 16) & 255u) ||
             w > (int)(rr >> 24)) {
           // not a candidate row (an empty range is stored as vlo = 255 > vhi)
-        } else if (E.host) {
+        } else if (E.host & 1) {
           a = b = E.lo;
         } else {
           // rows whose rounded dy^2 + dz^2 exceeds r^2 hold no member
-          const double dy = ((double)(G.glo[1] + v) + 0.5) - E.y;
-          const double dz = ((double)(G.glo[2] + w) + 0.5) - E.z;
+          const double dy = ((double)(gl1 + v) + 0.5) - E.y;
+          const double dz = ((double)(gl2 + w) + 0.5) - E.z;
           const double y2 = dy * dy, z2 = dz * dz;
           if (y2 + z2 <= E.r2) row_run(E.x, E.r2, E.lo, E.hi, y2, z2, a, b);
         }
-        const int ua = max(a - G.glo[0], 0), ub = min(b - G.glo[0], G.ext[0] - 1);
+        const int ua = max(a - gl0, 0), ub = min(b - gl0, G.ext[0] - 1);
         LT* r0 = a0 + (w * TY + v) * TXP;
         LT* r4 = a4 + (w * TY + v) * TXP;
         if constexpr (FIXED) {
@@ -2657,9 +2821,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
         const OutT vr = sr >= 0 ? from_lds<OutT>(r0) : (OutT)0;
         const OutT ve = se >= 0 ? from_lds<OutT>(r4) : (OutT)0;
         // owned-local coordinates: interior when g <= . < n - g on every axis
+        // (with owner tiles every cell is owned and its sum complete)
         const int ox = ox0 + u, oy = oy0 + v, oz = oz0 + w;
-        if (state && ox >= g && ox < n0 - g && oy >= g && oy < n1 - g && oz >= g &&
-            oz < n2 - g) {
+        if (OWN || (state && ox >= g && ox < n0 - g && oy >= g && oy < n1 - g && oz >= g &&
+                    oz < n2 - g)) {
           const long long si = tso + ((w * n1 + v) * n0 + u);
           if (M.state == PMP_STATE_F32)
             apply_cell_nosrc((float*)state + si, ncell, to_f64(vr), to_f64(ve), L, cnt);
@@ -2781,28 +2946,41 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
   if (has_s) {
     const unsigned grid = (unsigned)((sn->n * count_lanes + 255) / 256);
     switch (count_lanes) {
-      case 1: hipLaunchKernelGGL(k_sn_count<1>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk); break;
-      case 2: hipLaunchKernelGGL(k_sn_count<2>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk); break;
-      case 8: hipLaunchKernelGGL(k_sn_count<8>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk); break;
-      case 16: hipLaunchKernelGGL(k_sn_count<16>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk); break;
-      default: hipLaunchKernelGGL(k_sn_count<4>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk);
+      case 1: hipLaunchKernelGGL(k_sn_count<1>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk, T.owner); break;
+      case 2: hipLaunchKernelGGL(k_sn_count<2>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk, T.owner); break;
+      case 8: hipLaunchKernelGGL(k_sn_count<8>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk, T.owner); break;
+      case 16: hipLaunchKernelGGL(k_sn_count<16>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk, T.owner); break;
+      default: hipLaunchKernelGGL(k_sn_count<4>, dim3(grid), dim3(256), 0, s, M, *sn, bw.sn_pk, T.owner);
     }
   }
-  if (has_c || has_s)
-    hipLaunchKernelGGL(k_l1_hist, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
-                       has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc, hs,
-                       nbs, (const SnPk*)bw.sn_pk);
+  if (has_c || has_s) {
+    if (T.owner)
+      hipLaunchKernelGGL(k_l1_hist<true>, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
+                         has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc,
+                         hs, nbs, (const SnPk*)bw.sn_pk);
+    else
+      hipLaunchKernelGGL(k_l1_hist<false>, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
+                         has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc,
+                         hs, nbs, (const SnPk*)bw.sn_pk);
+  }
   // exclusive scan of both kinds' histograms, in place; hist[n] = total
   const int nblocks = (int)((n + kScanBlock - 1) / kScanBlock);
   hipLaunchKernelGGL(k_scan_local, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist, bw.hist,
                      bw.block_sums, n, (const int*)nullptr, 0);
   hipLaunchKernelGGL(k_scan_finish, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist,
                      (const int*)bw.block_sums, n, (const int*)nullptr, 0);
-  if (has_c || has_s)
-    hipLaunchKernelGGL(k_l1_scatter, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
-                       has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc, hs,
-                       nbs, bw.cic_tmp, bw.cic_tmp_tile, bw.cic_cap, (const SnPk*)bw.sn_pk,
-                       bw.sn_tmp, bw.sn_tmp_tile, bw.sn_cap);
+  if (has_c || has_s) {
+    if (T.owner)
+      hipLaunchKernelGGL(k_l1_scatter<true>, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
+                         has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc,
+                         hs, nbs, bw.cic_tmp, bw.cic_tmp_tile, bw.cic_cap,
+                         (const SnPk*)bw.sn_pk, bw.sn_tmp, bw.sn_tmp_tile, bw.sn_cap);
+    else
+      hipLaunchKernelGGL(k_l1_scatter<false>, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
+                         has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc,
+                         hs, nbs, bw.cic_tmp, bw.cic_tmp_tile, bw.cic_cap,
+                         (const SnPk*)bw.sn_pk, bw.sn_tmp, bw.sn_tmp_tile, bw.sn_cap);
+  }
   // level 2: balanced slices of every bucket, both kinds
   L2Geom G;
   G.hist1 = bw.hist;
@@ -2859,26 +3037,35 @@ hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles
   const int* coff = (cic && cic->n > 0) ? bw.cic_off : nullptr;
   const int* soff = (sn && sn->n > 0) ? bw.sn_off : nullptr;
   const int block = t.tile_block;
-  const size_t lds = (size_t)tile_lds_bytes(T.t[0], T.t[1], M.ghost, M.acc == PMP_ACC_F64R);
+  const size_t lds = (size_t)tile_lds_bytes_wx(T.wx, T.t[1], M.acc == PMP_ACC_F64R);
   long long grid = T.ntiles;
   if (t.tile_grid_per_cu > 0)
     grid = std::min<long long>(grid, (long long)M.num_cu * t.tile_grid_per_cu);
   if (grid < 1) grid = 1;
   if (grid > 0x7fffffffll) grid = 0x7fffffffll;
-#define PMP_TILE(ACC, TT, TYZ)                                                                \
-  hipLaunchKernelGGL((k_tile_deposit<ACC, TYZ>), dim3((unsigned)grid), dim3(block), lds, s, M, \
-                     T, coff, (const double4*)bw.cic_rec, bw.cic_cap, soff,                   \
+#define PMP_TILE(ACC, TT, TYZ, OWN)                                                           \
+  hipLaunchKernelGGL((k_tile_deposit<ACC, TYZ, OWN>), dim3((unsigned)grid), dim3(block), lds, \
+                     s, M, T, coff, (const double4*)bw.cic_rec, bw.cic_cap, soff,             \
                      (const int*)bw.sn_rec, (const SnPk*)bw.sn_pk, bw.sn_cap, t.chunk_cic,    \
                      t.chunk_sn,                                                              \
                      (const int*)bw.heavy_base, (const int2*)bw.heavy_unit,                   \
                      (const int*)bw.heavy_count, bw.arrive, bw.partial, bw.slot_cap,          \
                      (TT*)buf, state, L)
-#define PMP_TILE_ACC(TYZ)                                      \
-  switch (M.acc) {                                             \
-    case PMP_ACC_F32: PMP_TILE(PMP_ACC_F32, float, TYZ); break; \
-    case PMP_ACC_F64: PMP_TILE(PMP_ACC_F64, double, TYZ); break; \
-    case PMP_ACC_F64R: PMP_TILE(PMP_ACC_F64R, double, TYZ); break; \
-    default: PMP_TILE(PMP_ACC_FIX64, long long, TYZ);          \
+  // owner tiles: no reproducibility-mode variant (its bounds need the fold's order)
+#define PMP_TILE_ACC(TYZ)                                                       \
+  if (T.owner) {                                                                \
+    switch (M.acc) {                                                            \
+      case PMP_ACC_F32: PMP_TILE(PMP_ACC_F32, float, TYZ, true); break;         \
+      case PMP_ACC_F64: PMP_TILE(PMP_ACC_F64, double, TYZ, true); break;        \
+      default: PMP_TILE(PMP_ACC_FIX64, long long, TYZ, true);                   \
+    }                                                                           \
+  } else {                                                                      \
+    switch (M.acc) {                                                            \
+      case PMP_ACC_F32: PMP_TILE(PMP_ACC_F32, float, TYZ, false); break;        \
+      case PMP_ACC_F64: PMP_TILE(PMP_ACC_F64, double, TYZ, false); break;       \
+      case PMP_ACC_F64R: PMP_TILE(PMP_ACC_F64R, double, TYZ, false); break;     \
+      default: PMP_TILE(PMP_ACC_FIX64, long long, TYZ, false);                  \
+    }                                                                           \
   }
   switch (T.t[1]) {
     case 2: PMP_TILE_ACC(2); break;

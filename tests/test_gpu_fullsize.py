@@ -171,3 +171,52 @@ def test_full_size_sink_create_after_step(B, orc):
     assert n == n_ref
     assert np.array_equal(got[:, :n], out_ref[:, :n])
     assert np.array_equal(st, s64.astype(np.float32))
+
+
+def step_state(B, w, acc, tuning):
+    import torch
+    ctx = B.Context(w, acc)
+    ctx.set_tuning(**tuning)
+    ctx.profile_begin(4)
+    ctx.step()
+    torch.cuda.synchronize()
+    phases = ctx.profile_end()
+    out = {"state": ctx.state.cpu().numpy(), "status": ctx.status(), "phases": phases}
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+OWNER_FULL = {
+    # the benchmark's default workload and tile shape, FP64 state
+    "c4": (lambda: (lambda w: w.with_state(w.state.astype(np.float64)))(W.c4()),
+           {"tile_x": 64, "tile_yz": 4, "tile_block": 256}, ("fix64", "f64")),
+    "c5": (W.c5, {"tile_x": 32, "tile_yz": 4, "tile_block": 128}, ("fix64", "f32")),
+}
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", list(OWNER_FULL))
+def test_full_size_owner_tiles_step(B, orc, name):
+    """The fold-free step (owner tiles, fuse_apply 2) at full size against the
+    oracle's step: fixed point bit for bit with the limiter counters, floats
+    per field within their tolerance; no fold launch."""
+    make, shape, accs = OWNER_FULL[name]
+    w = make()
+    tun = {"deposit_path": 1, "fuse_apply": 2, "chunk_cic": 16384, "chunk_sn": 2048, **shape}
+    for acc in accs:
+        say(f"full-size {w.name}: owner tiles, {acc}, {shape}")
+        got = step_state(B, w, acc, tun)
+        assert got["status"]["flags"] in (0, 0x10), got["status"]
+        assert "fold" not in got["phases"], got["phases"]
+        ref = orc.step(w, "fix64" if acc == "fix64" else "f64")
+        sdt = got["state"].dtype
+        if acc == "fix64":
+            assert np.array_equal(got["state"], ref["state"].astype(sdt))
+            for k in ("touched", "bind", "lam", "fall"):
+                assert got["status"][k] == ref["counters"][k], (k, got["status"])
+        else:
+            e = per_field_rel(w, got["state"], ref["state"].astype(sdt), 5, 0)
+            say(f"  state max rel {e:.3e}")
+            assert e <= max(1e-6 if acc == "f32" else 1e-12, float(np.finfo(sdt).eps))

@@ -382,14 +382,16 @@ def step_vs_oracle(B, orc, w, acc, channels="all", tuning=None):
     ctx = B.Context(w, acc, channels=channels)
     if tuning:
         ctx.set_tuning(**tuning)
+    ctx.profile_begin(16)
     ctx.step()
     torch.cuda.synchronize()
+    phases = ctx.profile_end()
     got = ctx.state.cpu().numpy()
     st = ctx.status()
     ctx.close()
     assert st["flags"] in (0, 0x10), st
     ref = orc.step(w, "fix64" if acc == "fix64" else "f64", want_eta=True)
-    out = {"status": st, "oracle_counters": ref["counters"]}
+    out = {"status": st, "oracle_counters": ref["counters"], "phases": phases}
     if acc == "fix64":
         assert np.array_equal(got, ref["state"].astype(got.dtype))
         for k in ("touched", "bind", "lam", "fall"):
@@ -401,7 +403,7 @@ def step_vs_oracle(B, orc, w, acc, channels="all", tuning=None):
     return out
 
 
-@pytest.mark.parametrize("fuse", [1, 0])
+@pytest.mark.parametrize("fuse", [2, 1, 0])
 @pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
 @pytest.mark.parametrize("idx", range(5))
 def test_step_edge_layouts(B, orc, idx, acc, fuse):
@@ -412,7 +414,82 @@ def test_step_edge_layouts(B, orc, idx, acc, fuse):
     step_vs_oracle(B, orc, w, acc, tuning={"deposit_path": 1, "fuse_apply": fuse})
 
 
-@pytest.mark.parametrize("fuse", [1, 0])
+def owner_tiles_fit(w, tx, tyz):
+    """Owner tiles fit a layout when no tile along an axis is wider than the
+    domain less 2g cells (the library's own rule)."""
+    t = (tx, tyz, tyz)
+    n = w.n.astype(np.int64)
+    return all(max(min(t[a], int(v)) for v in n[:, a]) <= int(w.domain[a]) - 2 * w.ghost
+               for a in range(3))
+
+
+OWNER_CASES = {
+    "edge_multibox": lambda: edge_workloads()[0],
+    "edge_corners": lambda: edge_workloads()[2],
+    "c2_40": lambda: W.c2(nx=40),
+    "c4_48": lambda: W.c4(nx=48),
+    "c5_4": lambda: W.c5(nb=4),
+    "c4_40": lambda: W.c4(nx=40, seed=7),
+}
+
+
+@pytest.mark.parametrize("split", [False, True])
+@pytest.mark.parametrize("shape", [(16, 4), (32, 2)])
+@pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
+@pytest.mark.parametrize("name", list(OWNER_CASES))
+def test_step_owner_tiles(B, orc, name, acc, shape, split):
+    """The fold-free step (fuse_apply 2): tiles over owned cells only, each
+    particle binned into every tile a periodic image of its stencil reaches,
+    every owned cell applied from its complete LDS sum; no fold launch, and
+    the oracle's step (fixed point bit for bit, with its limiter counters)."""
+    w = OWNER_CASES[name]()
+    tx, tyz = shape
+    assert owner_tiles_fit(w, tx, tyz)
+    tun = {"deposit_path": 1, "fuse_apply": 2, "tile_x": tx, "tile_yz": tyz}
+    if split:
+        tun.update(chunk_cic=64, chunk_sn=16)
+    say(f"owner tiles {w.name} acc={acc} tile {tx}x{tyz} split={split}")
+    out = step_vs_oracle(B, orc, w, acc, tuning=tun)
+    assert "fold" not in out["phases"] and "tile" in out["phases"], out["phases"]
+
+
+@pytest.mark.parametrize("idx", [1, 4])
+def test_step_owner_tiles_fall_back(B, orc, idx):
+    """Layouts the owner tiles do not fit (a domain under 2g + tile cells
+    along an axis) run fuse_apply 2 as the fused step with a fold."""
+    w = edge_workloads()[idx]
+    assert not owner_tiles_fit(w, 16, 2)
+    out = step_vs_oracle(B, orc, w, "fix64",
+                         tuning={"deposit_path": 1, "fuse_apply": 2, "tile_x": 16, "tile_yz": 2})
+    assert "fold" in out["phases"], out["phases"]
+
+
+def test_graph_owner_tiles(B):
+    """A captured multi-box graph of fold-free steps replays like eager steps."""
+    import torch
+    w = W.c5(nb=3, n_total=30000)
+    tun = {"deposit_path": 1, "fuse_apply": 2, "tile_x": 16, "tile_yz": 4}
+    assert owner_tiles_fit(w, 16, 4)
+    eager = B.Context(w, "fix64")
+    eager.set_tuning(**tun)
+    eager.step()
+    eager.step()
+    torch.cuda.synchronize()
+    ref = eager.state.cpu().numpy()
+    eager.close()
+    g = B.Context(w, "fix64")
+    g.set_tuning(**tun)
+    g.graph_build(2)
+    for _ in range(3):
+        g.reset_state()
+        torch.cuda.synchronize()
+        g.graph_launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(g.state.cpu().numpy(), ref)
+    g.close()
+
+
+@pytest.mark.parametrize("fuse", [2, 1, 0])
 @pytest.mark.parametrize("eint_mode", [0, 1])
 @pytest.mark.parametrize("acc", ["fix64", "f32"])
 def test_step_energy_floor(B, orc, acc, eint_mode, fuse):
@@ -431,8 +508,12 @@ def test_step_energy_floor(B, orc, acc, eint_mode, fuse):
                             limits=dataclasses.replace(w.limits, eint_mode=eint_mode))
     for channels in ("auto", "all"):
         say(f"energy floor acc={acc} eint_mode={eint_mode} fuse={fuse} channels={channels}")
-        out = step_vs_oracle(B, orc, w, acc, channels=channels,
-                             tuning={"deposit_path": 1, "fuse_apply": fuse})
+        tun = {"deposit_path": 1, "fuse_apply": fuse}
+        if fuse == 2:
+            tun["tile_x"] = 16  # owner tiles: at most domain - 2g cells wide
+            assert owner_tiles_fit(w, 16, 4)
+        out = step_vs_oracle(B, orc, w, acc, channels=channels, tuning=tun)
+        assert ("fold" in out["phases"]) == (fuse != 2), out["phases"]
         assert out["oracle_counters"]["fall"] > 1000, out
         if acc == "f32":
             # decided in FP64 from FP32 deposits, cells at the limiter's edge may
