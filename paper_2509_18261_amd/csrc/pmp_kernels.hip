@@ -1841,6 +1841,22 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
     gl[a] = l - g + B.lo[a];
     gh[a] = h - g + B.lo[a];
   }
+  // most stencils lie in their own box's owned cells: its tiles, directly
+  bool home = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) home = home && gl[a] >= B.lo[a] && gh[a] < B.lo[a] + B.n[a];
+  if (home) {
+    int tlo[3], thi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      tlo[a] = (gl[a] - B.lo[a]) / T.t[a];
+      thi[a] = (gh[a] - B.lo[a]) / T.t[a];
+    }
+    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
+      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
+        for (int tx = tlo[0]; tx <= thi[0]; ++tx) f((int)tile_id(T, b, tx, ty, tz));
+    return;
+  }
   owner_tiles(M, T, gl, gh, f);
   }
 }
