@@ -192,6 +192,7 @@ struct pmp_ctx {
   ZoneSeg* d_zone_seg = nullptr;
   int* d_own_start = nullptr;  // owner index (multi-box layouts), see Mesh
   int* d_own_box = nullptr;
+  int* d_nbr = nullptr;        // neighbour table (owner tiles), see Mesh
   int own_bin[3] = {1, 1, 1}, own_dims[3] = {1, 1, 1};
   int2* d_apply_chunks = nullptr;
   int2* d_fold_chunks = nullptr;
@@ -228,6 +229,7 @@ struct pmp_ctx {
       M.own_bin[a] = own_bin[a];
       M.own_dims[a] = own_dims[a];
     }
+    M.nbr = d_nbr;
     return M;
   }
   size_t acc_bytes() const { return acc == PMP_ACC_F32 ? 4 : 8; }
@@ -325,6 +327,7 @@ void release(pmp_ctx* c) {
   (void)hipFree(c->d_zone_seg);
   (void)hipFree(c->d_own_start);
   (void)hipFree(c->d_own_box);
+  (void)hipFree(c->d_nbr);
   (void)hipFree(c->d_apply_chunks);
   (void)hipFree(c->d_fold_chunks);
   if (!c->ws) free_bin_work(c);
@@ -931,6 +934,58 @@ void build_owner_index(pmp_ctx* c, std::vector<int>& start, std::vector<int>& bo
   for (const auto& v : bins) boxes.insert(boxes.end(), v.begin(), v.end());
 }
 
+// Neighbour table for owner tiles (see Mesh::nbr): for every box and each of
+// the 27 directions, the boxes whose owned cells meet the region next to the
+// box in that direction, found through the box index over the region's
+// periodic pieces.
+void build_neighbour_table(const pmp_ctx* c, std::vector<int>& nbr) {
+  const int g = c->ghost;
+  BoxIndex idx;
+  idx.build(c->hboxes, c->domain);
+  nbr.assign(27 * (size_t)c->nbox, -1);
+  for (int b = 0; b < c->nbox; ++b) {
+    const HostBox& B = c->hboxes[b];
+    for (int d = 0; d < 27; ++d) {
+      const int dir[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+      // the region per axis, then its pieces inside [0, D)
+      int pl[3][2], ph[3][2], np[3];
+      bool empty = false;
+      for (int a = 0; a < 3; ++a) {
+        const int D = c->domain[a];
+        int r0, r1;
+        if (dir[a] < 0) { r0 = B.lo[a] - g; r1 = B.lo[a] - 1; }
+        else if (dir[a] > 0) { r0 = B.lo[a] + B.n[a]; r1 = B.lo[a] + B.n[a] + g - 1; }
+        else { r0 = B.lo[a]; r1 = B.lo[a] + B.n[a] - 1; }
+        if (r1 < r0) { empty = true; break; }
+        if (r1 - r0 + 1 >= D) { pl[a][0] = 0; ph[a][0] = D - 1; np[a] = 1; continue; }
+        const int l = ((r0 % D) + D) % D, h = l + (r1 - r0);
+        if (h < D) { pl[a][0] = l; ph[a][0] = h; np[a] = 1; }
+        else { pl[a][0] = l; ph[a][0] = D - 1; pl[a][1] = 0; ph[a][1] = h - D; np[a] = 2; }
+      }
+      if (empty) continue;
+      int found = -1, count = 0;
+      for (int cz = 0; cz < np[2]; ++cz)
+        for (int cy = 0; cy < np[1]; ++cy)
+          for (int cx = 0; cx < np[0]; ++cx) {
+            const int lo[3] = {pl[0][cx], pl[1][cy], pl[2][cz]};
+            const int hi[3] = {ph[0][cx] + 1, ph[1][cy] + 1, ph[2][cz] + 1};
+            idx.query(lo, hi, [&](int q) {
+              const HostBox& Q = c->hboxes[q];
+              for (int a = 0; a < 3; ++a)
+                if (Q.lo[a] >= hi[a] || Q.lo[a] + Q.n[a] <= lo[a]) return;
+              if (q != found) {
+                found = q;
+                ++count;
+              }
+            });
+          }
+      // (a box met through two pieces counts once: pieces are visited one
+      // after another, so a repeat of the last box found is not counted)
+      nbr[27 * (size_t)b + d] = count == 0 ? -1 : (count == 1 ? found : -2);
+    }
+  }
+}
+
 int check_sinks(const pmp_ctx* c, const pmp_sinks* k) {
   if (k->rate != PMP_SINK_FRACTION && k->rate != PMP_SINK_BONDI)
     return fail(PMP_EINVAL, "sink rate %d is not a pmp_sink_rate_t", (int)k->rate);
@@ -1308,6 +1363,11 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
     build_owner_index(c, own_start, own_box);
     upload(&c->d_own_start, own_start);
     upload(&c->d_own_box, own_box);
+  }
+  {
+    std::vector<int> nbr;
+    build_neighbour_table(c, nbr);
+    upload(&c->d_nbr, nbr);
   }
   upload(&c->d_apply_chunks, apply_chunks);
   upload(&c->d_fold_chunks, fold_chunks);

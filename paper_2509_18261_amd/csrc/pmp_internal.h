@@ -95,6 +95,12 @@ struct Mesh {
   const int* own_start;
   const int* own_box;
   int own_bin[3], own_dims[3];
+  // Neighbour table for owner tiles: nbr[27 b + d], d = 9 (dz + 1) + 3 (dy
+  // + 1) + (dx + 1), is the one box whose owned cells meet the region next
+  // to box b in direction (dx, dy, dz) (per axis: the g cells below the box,
+  // the box's own extent, or the g cells above it, wrapped periodically); -1
+  // when no box does, -2 when several do.
+  const int* nbr;
 };
 
 struct Particles {

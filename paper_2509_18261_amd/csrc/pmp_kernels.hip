@@ -1745,27 +1745,32 @@ __device__ __forceinline__ long long tile_id(const TileGrid& T, int b, int tx, i
 // the global cell range [lo, hi] of a particle's own frame (hi - lo < domain
 // per axis, lo > -domain) after wrapping it periodically.  Per axis the range
 // wraps into at most two pieces; for each combination of pieces the boxes
-// that meet it come from the owner index, each taken once, by the bin that
-// holds the lowest cell of its intersection with the piece.  Distinct pieces
-// never share a tile (the owner-tile condition), so each tile comes once.
+// that meet it are box `only` (when the caller knows that no other box owns
+// any of these cells), or come from the owner index, each taken once, by the
+// bin that holds the lowest cell of its intersection with the piece.
+// Distinct pieces never share a tile (the owner-tile condition), so each
+// tile comes once.
 template <class F>
 __device__ __forceinline__ void owner_tiles(const Mesh& M, const TileGrid& T, const int lo[3],
-                                            const int hi[3], F&& f) {
-  int pl[3][2], ph[3][2], np[3];
+                                            const int hi[3], int only, F&& f) {
+  // per axis: pieces (l0, h0) and, when the range wraps, (l1, h1)
+  int l0[3], h0[3], l1[3], h1[3], np[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int D = M.domain[a], l = lo[a], h = hi[a];
     np[a] = 1;
+    l1[a] = 0;
+    h1[a] = -1;
     if (l < 0 && h < 0) {
-      pl[a][0] = l + D; ph[a][0] = h + D;
+      l0[a] = l + D; h0[a] = h + D;
     } else if (l < 0) {
-      pl[a][0] = 0; ph[a][0] = h; pl[a][1] = l + D; ph[a][1] = D - 1; np[a] = 2;
+      l0[a] = 0; h0[a] = h; l1[a] = l + D; h1[a] = D - 1; np[a] = 2;
     } else if (l >= D) {
-      pl[a][0] = l - D; ph[a][0] = h - D;
+      l0[a] = l - D; h0[a] = h - D;
     } else if (h >= D) {
-      pl[a][0] = l; ph[a][0] = D - 1; pl[a][1] = 0; ph[a][1] = h - D; np[a] = 2;
+      l0[a] = l; h0[a] = D - 1; l1[a] = 0; h1[a] = h - D; np[a] = 2;
     } else {
-      pl[a][0] = l; ph[a][0] = h;
+      l0[a] = l; h0[a] = h;
     }
   }
   auto box_tiles = [&](int b, const DevBox& B, const int il[3], const int ih[3]) {
@@ -1779,42 +1784,54 @@ __device__ __forceinline__ void owner_tiles(const Mesh& M, const TileGrid& T, co
       for (int ty = tlo[1]; ty <= thi[1]; ++ty)
         for (int tx = tlo[0]; tx <= thi[0]; ++tx) f((int)tile_id(T, b, tx, ty, tz));
   };
-  for (int cz = 0; cz < np[2]; ++cz)
-    for (int cy = 0; cy < np[1]; ++cy)
-      for (int cx = 0; cx < np[0]; ++cx) {
-        const int rl[3] = {pl[0][cx], pl[1][cy], pl[2][cz]};
-        const int rh[3] = {ph[0][cx], ph[1][cy], ph[2][cz]};
-        if (M.own_start == nullptr) {
-          // one box covers the domain
-          box_tiles(0, M.all_boxes[0], rl, rh);
-          continue;
-        }
-        int bl[3], bh[3];
+  const int ncomb = np[0] * np[1] * np[2];
+#pragma unroll 1
+  for (int c = 0; c < ncomb; ++c) {
+    const int cx = c % np[0], cy = (c / np[0]) % np[1], cz = c / (np[0] * np[1]);
+    const int rl[3] = {cx ? l1[0] : l0[0], cy ? l1[1] : l0[1], cz ? l1[2] : l0[2]};
+    const int rh[3] = {cx ? h1[0] : h0[0], cy ? h1[1] : h0[1], cz ? h1[2] : h0[2]};
+    if (only >= 0 || M.own_start == nullptr) {
+      // the one box that can own these cells (one box covers the domain, or
+      // the neighbour table names it)
+      const int b = only >= 0 ? only : 0;
+      const DevBox& B = M.all_boxes[b];
+      int il[3], ih[3];
+      bool hit = true;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          bl[a] = rl[a] / M.own_bin[a];
-          bh[a] = rh[a] / M.own_bin[a];
-        }
-        for (int bz = bl[2]; bz <= bh[2]; ++bz)
-          for (int by = bl[1]; by <= bh[1]; ++by)
-            for (int bx = bl[0]; bx <= bh[0]; ++bx) {
-              const int bin = (bz * M.own_dims[1] + by) * M.own_dims[0] + bx;
-              const int bb[3] = {bx, by, bz};
-              for (int q = M.own_start[bin]; q < M.own_start[bin + 1]; ++q) {
-                const int b = M.own_box[q];
-                const DevBox& B = M.all_boxes[b];
-                int il[3], ih[3];
-                bool hit = true;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                  il[a] = max(rl[a], B.lo[a]);
-                  ih[a] = min(rh[a], B.lo[a] + B.n[a] - 1);
-                  hit = hit && il[a] <= ih[a] && il[a] / M.own_bin[a] == bb[a];
-                }
-                if (hit) box_tiles(b, B, il, ih);
-              }
-            }
+      for (int a = 0; a < 3; ++a) {
+        il[a] = max(rl[a], B.lo[a]);
+        ih[a] = min(rh[a], B.lo[a] + B.n[a] - 1);
+        hit = hit && il[a] <= ih[a];
       }
+      if (hit) box_tiles(b, B, il, ih);
+      continue;
+    }
+    int bl[3], bh[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      bl[a] = rl[a] / M.own_bin[a];
+      bh[a] = rh[a] / M.own_bin[a];
+    }
+    for (int bz = bl[2]; bz <= bh[2]; ++bz)
+      for (int by = bl[1]; by <= bh[1]; ++by)
+        for (int bx = bl[0]; bx <= bh[0]; ++bx) {
+          const int bin = (bz * M.own_dims[1] + by) * M.own_dims[0] + bx;
+          const int bb[3] = {bx, by, bz};
+          for (int q = M.own_start[bin]; q < M.own_start[bin + 1]; ++q) {
+            const int b = M.own_box[q];
+            const DevBox& B = M.all_boxes[b];
+            int il[3], ih[3];
+            bool hit = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              il[a] = max(rl[a], B.lo[a]);
+              ih[a] = min(rh[a], B.lo[a] + B.n[a] - 1);
+              hit = hit && il[a] <= ih[a] && il[a] / M.own_bin[a] == bb[a];
+            }
+            if (hit) box_tiles(b, B, il, ih);
+          }
+        }
+  }
 }
 
 // Calls f(tile id) for every tile holding a cell of the padded-local range
@@ -1841,11 +1858,21 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
     gl[a] = l - g + B.lo[a];
     gh[a] = h - g + B.lo[a];
   }
-  // most stencils lie in their own box's owned cells: its tiles, directly
-  bool home = true;
+  // split the range at the faces of its own box: the part inside takes the
+  // box's tiles directly, a part beyond a face, edge or corner the tiles of
+  // the one box the neighbour table names for that direction (or, where
+  // several boxes meet there, those the owner index finds)
+  int hin[3];
+  unsigned parts = 0;  // bit 3a + p: part p (below, inside, above) of axis a is not empty
 #pragma unroll
-  for (int a = 0; a < 3; ++a) home = home && gl[a] >= B.lo[a] && gh[a] < B.lo[a] + B.n[a];
-  if (home) {
+  for (int a = 0; a < 3; ++a) {
+    hin[a] = B.lo[a] + B.n[a] - 1;
+    parts |= (unsigned)(gl[a] < B.lo[a]) << (3 * a);
+    parts |= (unsigned)(gl[a] <= hin[a] && gh[a] >= B.lo[a]) << (3 * a + 1);
+    parts |= (unsigned)(gh[a] > hin[a]) << (3 * a + 2);
+  }
+  if (parts == (2u | (2u << 3) | (2u << 6))) {
+    // inside its own box: that box's tiles, directly
     int tlo[3], thi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -1857,7 +1884,22 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
         for (int tx = tlo[0]; tx <= thi[0]; ++tx) f((int)tile_id(T, b, tx, ty, tz));
     return;
   }
-  owner_tiles(M, T, gl, gh, f);
+#pragma unroll 1
+  for (int d = 0; d < 27; ++d) {
+    const int pd[3] = {d % 3, (d / 3) % 3, d / 9};
+    bool any = true;
+    int rl[3], rh[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      any = any && ((parts >> (3 * a + pd[a])) & 1u);
+      rl[a] = pd[a] == 0 ? gl[a] : (pd[a] == 1 ? max(gl[a], B.lo[a]) : max(gl[a], hin[a] + 1));
+      rh[a] = pd[a] == 0 ? min(gh[a], B.lo[a] - 1) : (pd[a] == 1 ? min(gh[a], hin[a]) : gh[a]);
+    }
+    if (!any) continue;
+    const int nb = d == 13 ? b : M.nbr[27 * b + d];
+    if (nb == -1) continue;  // no box owns cells there
+    owner_tiles(M, T, rl, rh, nb, f);
+  }
   }
 }
 
@@ -1971,29 +2013,15 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
   int bb0, bb1;
   block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
   bool outside = false, nan = false, full = false;
-  // the thread's particles are loaded together, then binned one by one
   constexpr int UNR = kBinChunkCic / 256;
-  double px[UNR], py[UNR], pz[UNR], pm[UNR];
-#pragma unroll
-  for (int u = 0; u < UNR; ++u) {
-    const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
-    if (p < p1) {
-      px[u] = P.x[p];
-      py[u] = P.y[p];
-      pz[u] = P.z[p];
-      pm[u] = P.a[p];
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < UNR; ++u) {
-    const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
-    if (p >= p1) continue;
+  // owner tiles, one particle: its tiles, counted (and with SCATTER, its
+  // entries written)
+  auto bin_one = [&](long long p, double x, double y, double z, double m) {
     const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
     const DevBox B = M.boxes[b];
-    const double x = px[u], y = py[u], z = pz[u], m = pm[u];
     int hc[3];
-    if (!host_cell(B, x, y, z, hc)) { outside = true; continue; }
-    if (!isfinite(m)) { nan = true; continue; }
+    if (!host_cell(B, x, y, z, hc)) { outside = true; return; }
+    if (!isfinite(m)) { nan = true; return; }
     int lo[3], hi[3];
     cic_box(B, g, x, y, z, lo, hi);
     auto put = [&](int t) {
@@ -2007,14 +2035,55 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
         }
       }
     };
-    if constexpr (OWN) {
-      particle_tiles<true>(M, T, b, B, lo, hi, put);
-    } else {
-      int tlo[3], thi[3];
+    particle_tiles<true>(M, T, b, B, lo, hi, put);
+  };
+  if constexpr (OWN) {
+    // owner tiles: one particle at a time (the enumeration is long code)
+#pragma unroll 1
+    for (int u = 0; u < UNR; ++u) {
+      const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
+      if (p < p1) bin_one(p, P.x[p], P.y[p], P.z[p], P.a[p]);
+    }
+  } else {
+    // the thread's particles are loaded together, then binned one by one
+    double px[UNR], py[UNR], pz[UNR], pm[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
+      if (p < p1) {
+        px[u] = P.x[p];
+        py[u] = P.y[p];
+        pz[u] = P.z[p];
+        pm[u] = P.a[p];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
+      if (p >= p1) continue;
+      const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
+      const DevBox B = M.boxes[b];
+      const double x = px[u], y = py[u], z = pz[u], m = pm[u];
+      int hc[3];
+      if (!host_cell(B, x, y, z, hc)) { outside = true; continue; }
+      if (!isfinite(m)) { nan = true; continue; }
+      int lo[3], hi[3], tlo[3], thi[3];
+      cic_box(B, g, x, y, z, lo, hi);
       if (!tile_range(B, T, lo, hi, tlo, thi)) continue;
       for (int tz = tlo[2]; tz <= thi[2]; ++tz)
         for (int ty = tlo[1]; ty <= thi[1]; ++ty)
-          for (int tx = tlo[0]; tx <= thi[0]; ++tx) put((int)tile_id(T, b, tx, ty, tz));
+          for (int tx = tlo[0]; tx <= thi[0]; ++tx) {
+            const int t = (int)tile_id(T, b, tx, ty, tz);
+            const int pos = atomicAdd(h + (t >> shift), 1);
+            if (SCATTER) {
+              if (pos < cap) {
+                tmp[pos] = make_double4(x, y, z, m);
+                tmp_tile[pos] = t;
+              } else {
+                full = true;
+              }
+            }
+          }
     }
   }
   if (!SCATTER) {

@@ -423,7 +423,48 @@ def owner_tiles_fit(w, tx, tyz):
                for a in range(3))
 
 
+def irregular_layout(seed=13, dtype=np.float64):
+    """Boxes that are not a rectilinear grid: box 0 meets three boxes across
+    its +x face (and, periodically, across its -x face), so a stencil there
+    finds its tiles through the owner index; CIC and supernovae, some on the
+    faces and edges."""
+    rng = np.random.default_rng(seed)
+    domain = (24, 16, 16)
+    lo = np.array([[0, 0, 0], [12, 0, 0], [12, 8, 0], [12, 8, 8]], np.int32)
+    n = np.array([[12, 16, 16], [12, 8, 16], [12, 8, 8], [12, 8, 8]], np.int32)
+    ncell = int(np.prod(domain))
+    state = W.pack_by_box(W.gas_state(rng, ncell, dtype), n)
+
+    def group(pos, fields):
+        cell = np.floor(pos).astype(np.int64)
+        box = np.full(len(pos), -1)
+        for b in range(len(lo)):
+            inside = np.all((cell >= lo[b]) & (cell < lo[b] + n[b]), axis=1)
+            box[inside] = b
+        assert (box >= 0).all()
+        order = np.argsort(box, kind="stable")
+        off = np.concatenate([[0], np.cumsum(np.bincount(box, minlength=len(lo)))])
+        out = {"x": pos[order, 0].copy(), "y": pos[order, 1].copy(), "z": pos[order, 2].copy()}
+        for k, v in fields.items():
+            out[k] = np.asarray(v, np.float64)[order].copy()
+        return W.Particles(out, off.astype(np.int64))
+
+    def positions(count):
+        p = rng.uniform(0, 1, (count, 3)) * np.array(domain)
+        faces = rng.random(count) < 0.5
+        p[faces, 0] = rng.choice([0.0, 11.7, 12.0, 23.9], faces.sum())
+        edge = rng.random(count) < 0.3
+        p[edge, 1] = rng.choice([7.9, 8.0, 15.95], edge.sum())
+        return np.mod(p, np.array(domain, np.float64))
+
+    pc, ps = positions(400), positions(60)
+    return W.Workload("irregular", domain, lo, n, 2, 1.0, state,
+                      cic=group(pc, W.cic_fields(rng, len(pc))),
+                      sn=group(ps, W.sn_fields(len(ps), 1.7)))
+
+
 OWNER_CASES = {
+    "irregular": irregular_layout,
     "edge_multibox": lambda: edge_workloads()[0],
     "edge_corners": lambda: edge_workloads()[2],
     "c2_40": lambda: W.c2(nx=40),
