@@ -1858,21 +1858,11 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
     gl[a] = l - g + B.lo[a];
     gh[a] = h - g + B.lo[a];
   }
-  // split the range at the faces of its own box: the part inside takes the
-  // box's tiles directly, a part beyond a face, edge or corner the tiles of
-  // the one box the neighbour table names for that direction (or, where
-  // several boxes meet there, those the owner index finds)
-  int hin[3];
-  unsigned parts = 0;  // bit 3a + p: part p (below, inside, above) of axis a is not empty
+  // inside its own box's owned cells: that box's tiles, directly
+  bool home = true;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    hin[a] = B.lo[a] + B.n[a] - 1;
-    parts |= (unsigned)(gl[a] < B.lo[a]) << (3 * a);
-    parts |= (unsigned)(gl[a] <= hin[a] && gh[a] >= B.lo[a]) << (3 * a + 1);
-    parts |= (unsigned)(gh[a] > hin[a]) << (3 * a + 2);
-  }
-  if (parts == (2u | (2u << 3) | (2u << 6))) {
-    // inside its own box: that box's tiles, directly
+  for (int a = 0; a < 3; ++a) home = home && gl[a] >= B.lo[a] && gh[a] < B.lo[a] + B.n[a];
+  if (home) {
     int tlo[3], thi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -1884,22 +1874,53 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
         for (int tx = tlo[0]; tx <= thi[0]; ++tx) f((int)tile_id(T, b, tx, ty, tz));
     return;
   }
+  // the boxes that can own its cells: per direction the range reaches
+  // beyond the box's faces, edges and corners, the one box the neighbour
+  // table names; each distinct box then takes the whole range (its owned
+  // cells clip it), so a box meets the range once.  Where several boxes
+  // meet one direction, or more than kNbrList boxes are found, the owner
+  // index takes the whole range.
+  constexpr int kNbrList = 8;
+  int list[kNbrList];
+  int count = 0;
+  bool general = false;
 #pragma unroll 1
-  for (int d = 0; d < 27; ++d) {
+  for (int d = 0; d < 27 && !general; ++d) {
     const int pd[3] = {d % 3, (d / 3) % 3, d / 9};
     bool any = true;
-    int rl[3], rh[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      any = any && ((parts >> (3 * a + pd[a])) & 1u);
-      rl[a] = pd[a] == 0 ? gl[a] : (pd[a] == 1 ? max(gl[a], B.lo[a]) : max(gl[a], hin[a] + 1));
-      rh[a] = pd[a] == 0 ? min(gh[a], B.lo[a] - 1) : (pd[a] == 1 ? min(gh[a], hin[a]) : gh[a]);
+      const int lo_in = B.lo[a], hi_in = B.lo[a] + B.n[a] - 1;
+      any = any && (pd[a] == 0 ? gl[a] < lo_in
+                               : (pd[a] == 1 ? gl[a] <= hi_in && gh[a] >= lo_in : gh[a] > hi_in));
     }
     if (!any) continue;
     const int nb = d == 13 ? b : M.nbr[27 * b + d];
     if (nb == -1) continue;  // no box owns cells there
-    owner_tiles(M, T, rl, rh, nb, f);
+    if (nb == -2) {
+      general = true;
+      break;
+    }
+    bool seen = false;
+#pragma unroll
+    for (int q = 0; q < kNbrList; ++q) seen = seen || (q < count && list[q] == nb);
+    if (seen) continue;
+    if (count == kNbrList) {
+      general = true;
+      break;
+    }
+#pragma unroll
+    for (int q = 0; q < kNbrList; ++q)
+      if (q == count) list[q] = nb;
+    ++count;
   }
+  if (general) {
+    owner_tiles(M, T, gl, gh, -1, f);
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < kNbrList; ++q)
+    if (q < count) owner_tiles(M, T, gl, gh, list[q], f);
   }
 }
 
@@ -2014,76 +2035,84 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
   block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
   bool outside = false, nan = false, full = false;
   constexpr int UNR = kBinChunkCic / 256;
-  // owner tiles, one particle: its tiles, counted (and with SCATTER, its
-  // entries written)
-  auto bin_one = [&](long long p, double x, double y, double z, double m) {
+  // the thread's particles are loaded together, then binned one by one
+  double px[UNR], py[UNR], pz[UNR], pm[UNR];
+#pragma unroll
+  for (int u = 0; u < UNR; ++u) {
+    const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
+    if (p < p1) {
+      px[u] = P.x[p];
+      py[u] = P.y[p];
+      pz[u] = P.z[p];
+      pm[u] = P.a[p];
+    }
+  }
+  unsigned slow = 0;  // owner tiles: particles whose stencil leaves their box
+#pragma unroll
+  for (int u = 0; u < UNR; ++u) {
+    const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
+    if (p >= p1) continue;
     const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
     const DevBox B = M.boxes[b];
+    const double x = px[u], y = py[u], z = pz[u], m = pm[u];
     int hc[3];
-    if (!host_cell(B, x, y, z, hc)) { outside = true; return; }
-    if (!isfinite(m)) { nan = true; return; }
-    int lo[3], hi[3];
+    if (!host_cell(B, x, y, z, hc)) { outside = true; continue; }
+    if (!isfinite(m)) { nan = true; continue; }
+    int lo[3], hi[3], tlo[3], thi[3];
     cic_box(B, g, x, y, z, lo, hi);
-    auto put = [&](int t) {
-      const int pos = atomicAdd(h + (t >> shift), 1);
-      if (SCATTER) {
-        if (pos < cap) {
-          tmp[pos] = make_double4(x, y, z, m);
-          tmp_tile[pos] = t;
-        } else {
-          full = true;
-        }
-      }
-    };
-    particle_tiles<true>(M, T, b, B, lo, hi, put);
-  };
-  if constexpr (OWN) {
-    // owner tiles: one particle at a time (the enumeration is long code)
-#pragma unroll 1
-    for (int u = 0; u < UNR; ++u) {
-      const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
-      if (p < p1) bin_one(p, P.x[p], P.y[p], P.z[p], P.a[p]);
-    }
-  } else {
-    // the thread's particles are loaded together, then binned one by one
-    double px[UNR], py[UNR], pz[UNR], pm[UNR];
+    if constexpr (OWN) {
+      // inside its box's owned cells: that box's owner tiles; else later
+      bool home = true;
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
-      if (p < p1) {
-        px[u] = P.x[p];
-        py[u] = P.y[p];
-        pz[u] = P.z[p];
-        pm[u] = P.a[p];
+      for (int a = 0; a < 3; ++a) {
+        home = home && lo[a] >= g && hi[a] < B.n[a] + g;
+        tlo[a] = (lo[a] - g) / T.t[a];
+        thi[a] = (hi[a] - g) / T.t[a];
       }
-    }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
-      if (p >= p1) continue;
-      const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
-      const DevBox B = M.boxes[b];
-      const double x = px[u], y = py[u], z = pz[u], m = pm[u];
-      int hc[3];
-      if (!host_cell(B, x, y, z, hc)) { outside = true; continue; }
-      if (!isfinite(m)) { nan = true; continue; }
-      int lo[3], hi[3], tlo[3], thi[3];
-      cic_box(B, g, x, y, z, lo, hi);
+      if (!home) {
+        slow |= 1u << u;
+        continue;
+      }
+    } else {
       if (!tile_range(B, T, lo, hi, tlo, thi)) continue;
-      for (int tz = tlo[2]; tz <= thi[2]; ++tz)
-        for (int ty = tlo[1]; ty <= thi[1]; ++ty)
-          for (int tx = tlo[0]; tx <= thi[0]; ++tx) {
-            const int t = (int)tile_id(T, b, tx, ty, tz);
-            const int pos = atomicAdd(h + (t >> shift), 1);
-            if (SCATTER) {
-              if (pos < cap) {
-                tmp[pos] = make_double4(x, y, z, m);
-                tmp_tile[pos] = t;
-              } else {
-                full = true;
-              }
+    }
+    for (int tz = tlo[2]; tz <= thi[2]; ++tz)
+      for (int ty = tlo[1]; ty <= thi[1]; ++ty)
+        for (int tx = tlo[0]; tx <= thi[0]; ++tx) {
+          const int t = (int)tile_id(T, b, tx, ty, tz);
+          const int pos = atomicAdd(h + (t >> shift), 1);
+          if (SCATTER) {
+            if (pos < cap) {
+              tmp[pos] = make_double4(x, y, z, m);
+              tmp_tile[pos] = t;
+            } else {
+              full = true;
             }
           }
+        }
+  }
+  if constexpr (OWN) {
+    // stencils that reach other boxes or wrap: one at a time (long code)
+#pragma unroll 1
+    for (int u = 0; u < UNR; ++u) {
+      if (!((slow >> u) & 1u)) continue;
+      const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
+      const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
+      const DevBox B = M.boxes[b];
+      const double x = P.x[p], y = P.y[p], z = P.z[p], m = P.a[p];
+      int lo[3], hi[3];
+      cic_box(B, g, x, y, z, lo, hi);
+      particle_tiles<true>(M, T, b, B, lo, hi, [&](int t) {
+        const int pos = atomicAdd(h + (t >> shift), 1);
+        if (SCATTER) {
+          if (pos < cap) {
+            tmp[pos] = make_double4(x, y, z, m);
+            tmp_tile[pos] = t;
+          } else {
+            full = true;
+          }
+        }
+      });
     }
   }
   if (!SCATTER) {

@@ -423,15 +423,23 @@ def owner_tiles_fit(w, tx, tyz):
                for a in range(3))
 
 
-def irregular_layout(seed=13, dtype=np.float64):
-    """Boxes that are not a rectilinear grid: box 0 meets three boxes across
-    its +x face (and, periodically, across its -x face), so a stencil there
-    finds its tiles through the owner index; CIC and supernovae, some on the
-    faces and edges."""
+def irregular_layout(seed=13, dtype=np.float64, kind="three"):
+    """Boxes that are not a rectilinear grid, with CIC and supernovae, some
+    on the faces and edges.  "three": box 0 meets three boxes across its +x
+    face (and, periodically, across its -x face), so a stencil there finds its
+    tiles through the owner index.  "misaligned": the box beyond the +x faces
+    of boxes 0 and 1 spans both, so its tiles straddle their y faces."""
     rng = np.random.default_rng(seed)
-    domain = (24, 16, 16)
-    lo = np.array([[0, 0, 0], [12, 0, 0], [12, 8, 0], [12, 8, 8]], np.int32)
-    n = np.array([[12, 16, 16], [12, 8, 16], [12, 8, 8], [12, 8, 8]], np.int32)
+    if kind == "three":
+        domain = (24, 16, 16)
+        lo = np.array([[0, 0, 0], [12, 0, 0], [12, 8, 0], [12, 8, 8]], np.int32)
+        n = np.array([[12, 16, 16], [12, 8, 16], [12, 8, 8], [12, 8, 8]], np.int32)
+        face_y = [7.9, 8.0, 15.95]
+    else:
+        domain = (24, 24, 16)
+        lo = np.array([[0, 0, 0], [0, 10, 0], [12, 0, 0]], np.int32)
+        n = np.array([[12, 10, 16], [12, 14, 16], [12, 24, 16]], np.int32)
+        face_y = [9.6, 10.0, 10.3, 23.9]
     ncell = int(np.prod(domain))
     state = W.pack_by_box(W.gas_state(rng, ncell, dtype), n)
 
@@ -454,17 +462,18 @@ def irregular_layout(seed=13, dtype=np.float64):
         faces = rng.random(count) < 0.5
         p[faces, 0] = rng.choice([0.0, 11.7, 12.0, 23.9], faces.sum())
         edge = rng.random(count) < 0.3
-        p[edge, 1] = rng.choice([7.9, 8.0, 15.95], edge.sum())
+        p[edge, 1] = rng.choice(face_y, edge.sum())
         return np.mod(p, np.array(domain, np.float64))
 
     pc, ps = positions(400), positions(60)
-    return W.Workload("irregular", domain, lo, n, 2, 1.0, state,
+    return W.Workload(f"irregular_{kind}", domain, lo, n, 2, 1.0, state,
                       cic=group(pc, W.cic_fields(rng, len(pc))),
                       sn=group(ps, W.sn_fields(len(ps), 1.7)))
 
 
 OWNER_CASES = {
     "irregular": irregular_layout,
+    "misaligned": lambda: irregular_layout(seed=14, kind="misaligned"),
     "edge_multibox": lambda: edge_workloads()[0],
     "edge_corners": lambda: edge_workloads()[2],
     "c2_40": lambda: W.c2(nx=40),
