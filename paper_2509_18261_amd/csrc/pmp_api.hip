@@ -174,6 +174,7 @@ struct pmp_ctx {
   long long* d_otile_prefix = nullptr;
   int* d_otiles_axis = nullptr;
   TileGeo* d_otile_geo = nullptr;
+  NbrBox* d_onbr = nullptr;  // [27 nbox] neighbour table on the owner grid
   BinWork bw{};
   long long bw_hist = 0, bw_blocks = 0, bw_tiles = 0, bw_nsn = 0, bw_hist2 = 0,
             bw_slice_base = 0, bw_partial = 0;
@@ -192,7 +193,7 @@ struct pmp_ctx {
   ZoneSeg* d_zone_seg = nullptr;
   int* d_own_start = nullptr;  // owner index (multi-box layouts), see Mesh
   int* d_own_box = nullptr;
-  int* d_nbr = nullptr;        // neighbour table (owner tiles), see Mesh
+  std::vector<int> h_nbr;      // neighbour boxes per direction (owner tiles), see NbrBox
   int own_bin[3] = {1, 1, 1}, own_dims[3] = {1, 1, 1};
   int2* d_apply_chunks = nullptr;
   int2* d_fold_chunks = nullptr;
@@ -229,7 +230,6 @@ struct pmp_ctx {
       M.own_bin[a] = own_bin[a];
       M.own_dims[a] = own_dims[a];
     }
-    M.nbr = d_nbr;
     return M;
   }
   size_t acc_bytes() const { return acc == PMP_ACC_F32 ? 4 : 8; }
@@ -242,6 +242,7 @@ struct pmp_ctx {
     T.geo = owner ? d_otile_geo : d_tile_geo;
     T.ntiles = owner ? ontiles : ntiles;
     T.gx = owner ? 0 : ghost;
+    T.nbr = owner ? d_onbr : nullptr;
     T.wx = tile_dims[0] + 2 * T.gx;
     return T;
   }
@@ -327,7 +328,7 @@ void release(pmp_ctx* c) {
   (void)hipFree(c->d_zone_seg);
   (void)hipFree(c->d_own_start);
   (void)hipFree(c->d_own_box);
-  (void)hipFree(c->d_nbr);
+  (void)hipFree(c->d_onbr);
   (void)hipFree(c->d_apply_chunks);
   (void)hipFree(c->d_fold_chunks);
   if (!c->ws) free_bin_work(c);
@@ -450,20 +451,52 @@ int build_tiles(pmp_ctx* c, int tx, int tyz) {
   long long* op = nullptr;
   int* oa = nullptr;
   TileGeo* ot = nullptr;
+  NbrBox* on = nullptr;
   if (int rc = upload_grid(H, &dp, &da, &dt)) return rc;
-  if (own)
-    if (int rc = upload_grid(O, &op, &oa, &ot)) {
+  if (own) {
+    int rc = upload_grid(O, &op, &oa, &ot);
+    if (!rc) {
+      // the neighbour table with each neighbour's owner tiles
+      std::vector<NbrBox> nb(27 * (size_t)c->nbox);
+      for (size_t q = 0; q < nb.size(); ++q) {
+        NbrBox& R = nb[q];
+        std::memset(&R, 0, sizeof R);
+        R.id = c->h_nbr[q];
+        if (R.id < 0) continue;
+        const DevBox& d = c->dboxes[R.id];
+        for (int a = 0; a < 3; ++a) {
+          R.lo[a] = d.lo[a];
+          R.n[a] = d.n[a];
+          R.tax[a] = O.axis[3 * (size_t)R.id + a];
+        }
+        R.tprefix = (int)O.prefix[R.id];
+      }
+      hipError_t e = dev_alloc(&on, nb.size());
+      if (e == hipSuccess)
+        e = hipMemcpy(on, nb.data(), sizeof(NbrBox) * nb.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        (void)hipFree(on);
+        (void)hipFree(op);
+        (void)hipFree(oa);
+        (void)hipFree(ot);
+        rc = fail(PMP_EDEVICE, "neighbour table: %s", hipGetErrorString(e));
+      }
+    }
+    if (rc) {
       (void)hipFree(dp);
       (void)hipFree(da);
       (void)hipFree(dt);
       return rc;
     }
+  }
   (void)hipFree(c->d_tile_prefix);
   (void)hipFree(c->d_tiles_axis);
   (void)hipFree(c->d_tile_geo);
   (void)hipFree(c->d_otile_prefix);
   (void)hipFree(c->d_otiles_axis);
   (void)hipFree(c->d_otile_geo);
+  (void)hipFree(c->d_onbr);
+  c->d_onbr = on;
   c->d_tile_prefix = dp;
   c->d_tiles_axis = da;
   c->d_tile_geo = dt;
@@ -1364,11 +1397,6 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
     upload(&c->d_own_start, own_start);
     upload(&c->d_own_box, own_box);
   }
-  {
-    std::vector<int> nbr;
-    build_neighbour_table(c, nbr);
-    upload(&c->d_nbr, nbr);
-  }
   upload(&c->d_apply_chunks, apply_chunks);
   upload(&c->d_fold_chunks, fold_chunks);
   if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(DevStatus));
@@ -1390,6 +1418,7 @@ int pmp_create(pmp_ctx** out, const pmp_layout* L) {
   c->tune.chunk_sn = 512;
   c->tune.fuse_apply = 1;
   c->tune.count_lanes = 4;
+  build_neighbour_table(c, c->h_nbr);
   {
     int rc = build_tiles(c, c->tune.tile_x, c->tune.tile_yz);
     if (rc) {

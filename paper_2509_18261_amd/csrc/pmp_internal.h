@@ -95,12 +95,6 @@ struct Mesh {
   const int* own_start;
   const int* own_box;
   int own_bin[3], own_dims[3];
-  // Neighbour table for owner tiles: nbr[27 b + d], d = 9 (dz + 1) + 3 (dy
-  // + 1) + (dx + 1), is the one box whose owned cells meet the region next
-  // to box b in direction (dx, dy, dz) (per axis: the g cells below the box,
-  // the box's own extent, or the g cells above it, wrapped periodically); -1
-  // when no box does, -2 when several do.
-  const int* nbr;
 };
 
 struct Particles {
@@ -143,6 +137,19 @@ struct alignas(16) TileGeo {
   int pad;
 };
 
+// Owner tiles: the box whose owned cells meet the region next to box b in
+// direction (dx, dy, dz), d = 9 (dz + 1) + 3 (dy + 1) + (dx + 1) (per axis:
+// the g cells below the box, the box's own extent, or the g cells above it,
+// wrapped periodically), with what the binning needs of it: id -1 when no
+// box does, -2 when several do (then the owner index is walked).
+struct alignas(16) NbrBox {
+  int id;
+  int lo[3], n[3];
+  int tprefix;  // its first owner tile
+  int tax[3];   // its owner tiles per axis
+  int pad;
+};
+
 struct TileGrid {
   int t[3];                       // tile edge per axis (TX, TY, TZ)
   const long long* tile_prefix;   // [nbox+1] device
@@ -152,6 +159,7 @@ struct TileGrid {
   int gx;                         // ghost width (x tile boundaries at gx + k*TX)
   int wx;                         // widest x tile, TX + 2 gx (LDS row width)
   int owner;                      // 1: owner tiles (gx = 0, wx = TX)
+  const NbrBox* nbr;              // owner tiles: [27 nbox] neighbour table
 };
 
 // A supernova as prepared once by the binning pass; tile entry lists hold

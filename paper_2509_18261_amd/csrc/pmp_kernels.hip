@@ -1745,14 +1745,13 @@ __device__ __forceinline__ long long tile_id(const TileGrid& T, int b, int tx, i
 // the global cell range [lo, hi] of a particle's own frame (hi - lo < domain
 // per axis, lo > -domain) after wrapping it periodically.  Per axis the range
 // wraps into at most two pieces; for each combination of pieces the boxes
-// that meet it are box `only` (when the caller knows that no other box owns
-// any of these cells), or come from the owner index, each taken once, by the
-// bin that holds the lowest cell of its intersection with the piece.
-// Distinct pieces never share a tile (the owner-tile condition), so each
-// tile comes once.
+// that meet it come from the owner index, each taken once, by the bin that
+// holds the lowest cell of its intersection with the piece.  Distinct pieces
+// never share a tile (the owner-tile condition), so each tile comes once.
+// (owner_tiles_of below does the same for one known box.)
 template <class F>
 __device__ __forceinline__ void owner_tiles(const Mesh& M, const TileGrid& T, const int lo[3],
-                                            const int hi[3], int only, F&& f) {
+                                            const int hi[3], F&& f) {
   // per axis: pieces (l0, h0) and, when the range wraps, (l1, h1)
   int l0[3], h0[3], l1[3], h1[3], np[3];
 #pragma unroll
@@ -1790,10 +1789,9 @@ __device__ __forceinline__ void owner_tiles(const Mesh& M, const TileGrid& T, co
     const int cx = c % np[0], cy = (c / np[0]) % np[1], cz = c / (np[0] * np[1]);
     const int rl[3] = {cx ? l1[0] : l0[0], cy ? l1[1] : l0[1], cz ? l1[2] : l0[2]};
     const int rh[3] = {cx ? h1[0] : h0[0], cy ? h1[1] : h0[1], cz ? h1[2] : h0[2]};
-    if (only >= 0 || M.own_start == nullptr) {
-      // the one box that can own these cells (one box covers the domain, or
-      // the neighbour table names it)
-      const int b = only >= 0 ? only : 0;
+    if (M.own_start == nullptr) {
+      // one box covers the domain
+      const int b = 0;
       const DevBox& B = M.all_boxes[b];
       int il[3], ih[3];
       bool hit = true;
@@ -1832,6 +1830,39 @@ __device__ __forceinline__ void owner_tiles(const Mesh& M, const TileGrid& T, co
           }
         }
   }
+}
+
+// Owner tiles: calls f(tile id) once for every owner tile of box R holding a
+// cell of the global range [lo, hi] (as owner_tiles) after wrapping it.
+template <class F>
+__device__ __forceinline__ void owner_tiles_of(const Mesh& M, const NbrBox& R, const TileGrid& T,
+                                               const int lo[3], const int hi[3], F&& f) {
+  int tl[3][2], th[3][2], np[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int D = M.domain[a];
+    // the range's periodic images that meet the box: shifts -D, 0, +D
+    np[a] = 0;
+#pragma unroll
+    for (int k = -1; k <= 1; ++k) {
+      const int l = max(lo[a] + k * D, R.lo[a]), h = min(hi[a] + k * D, R.lo[a] + R.n[a] - 1);
+      if (l <= h && np[a] < 2) {
+        tl[a][np[a]] = (l - R.lo[a]) / T.t[a];
+        th[a][np[a]] = (h - R.lo[a]) / T.t[a];
+        ++np[a];
+      }
+    }
+  }
+  for (int cz = 0; cz < np[2]; ++cz)
+    for (int cy = 0; cy < np[1]; ++cy)
+      for (int cx = 0; cx < np[0]; ++cx) {
+        const int x0 = cx ? tl[0][1] : tl[0][0], x1 = cx ? th[0][1] : th[0][0];
+        const int y0 = cy ? tl[1][1] : tl[1][0], y1 = cy ? th[1][1] : th[1][0];
+        const int z0 = cz ? tl[2][1] : tl[2][0], z1 = cz ? th[2][1] : th[2][0];
+        for (int tz = z0; tz <= z1; ++tz)
+          for (int ty = y0; ty <= y1; ++ty)
+            for (int tx = x0; tx <= x1; ++tx) f(R.tprefix + (tz * R.tax[1] + ty) * R.tax[0] + tx);
+      }
 }
 
 // Calls f(tile id) for every tile holding a cell of the padded-local range
@@ -1876,13 +1907,13 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
   }
   // the boxes that can own its cells: per direction the range reaches
   // beyond the box's faces, edges and corners, the one box the neighbour
-  // table names; each distinct box then takes the whole range (its owned
-  // cells clip it), so a box meets the range once.  Where several boxes
-  // meet one direction, or more than kNbrList boxes are found, the owner
-  // index takes the whole range.
-  constexpr int kNbrList = 8;
-  int list[kNbrList];
-  int count = 0;
+  // table names (with its owner tiles); each distinct box then takes the
+  // whole range (its owned cells clip it), so a box meets the range once.
+  // Where several boxes meet one direction, or more than four boxes are
+  // found, the owner index takes the whole range.
+  // (first the directions and their box ids, at most four distinct boxes
+  // kept as scalars; then each box's record again, from the cache)
+  int i0 = -1, i1 = -1, i2 = -1, i3 = -1, d0 = 0, d1 = 0, d2 = 0, d3 = 0, count = 0;
   bool general = false;
 #pragma unroll 1
   for (int d = 0; d < 27 && !general; ++d) {
@@ -1895,32 +1926,29 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
                                : (pd[a] == 1 ? gl[a] <= hi_in && gh[a] >= lo_in : gh[a] > hi_in));
     }
     if (!any) continue;
-    const int nb = d == 13 ? b : M.nbr[27 * b + d];
-    if (nb == -1) continue;  // no box owns cells there
-    if (nb == -2) {
-      general = true;
-      break;
+    const int id = T.nbr[27 * b + d].id;
+    if (id == -1) continue;  // no box owns cells there
+    if (id == -2 || count == 4) {
+      general = general || id == -2 || (id != i0 && id != i1 && id != i2 && id != i3);
+      continue;
     }
-    bool seen = false;
-#pragma unroll
-    for (int q = 0; q < kNbrList; ++q) seen = seen || (q < count && list[q] == nb);
-    if (seen) continue;
-    if (count == kNbrList) {
-      general = true;
-      break;
-    }
-#pragma unroll
-    for (int q = 0; q < kNbrList; ++q)
-      if (q == count) list[q] = nb;
+    if (id == i0 || id == i1 || id == i2 || id == i3) continue;
+    if (count == 0) { i0 = id; d0 = d; }
+    else if (count == 1) { i1 = id; d1 = d; }
+    else if (count == 2) { i2 = id; d2 = d; }
+    else { i3 = id; d3 = d; }
     ++count;
   }
   if (general) {
-    owner_tiles(M, T, gl, gh, -1, f);
+    owner_tiles(M, T, gl, gh, f);
     return;
   }
-#pragma unroll
-  for (int q = 0; q < kNbrList; ++q)
-    if (q < count) owner_tiles(M, T, gl, gh, list[q], f);
+#pragma unroll 1
+  for (int q = 0; q < count; ++q) {
+    const int d = q == 0 ? d0 : (q == 1 ? d1 : (q == 2 ? d2 : d3));
+    const NbrBox R = T.nbr[27 * b + d];
+    owner_tiles_of(M, R, T, gl, gh, f);
+  }
   }
 }
 
