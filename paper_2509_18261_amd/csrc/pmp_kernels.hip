@@ -2120,11 +2120,23 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
         }
   }
   if constexpr (OWN) {
-    // stencils that reach other boxes or wrap: one at a time (long code)
+    // stencils that reach other boxes or wrap (long code, long load
+    // chains): gathered into a block-wide list and taken one per thread
+    __shared__ int s_slow[kBinChunkCic];
+    __shared__ int s_nslow;
+    if (threadIdx.x == 0) s_nslow = 0;
+    __syncthreads();
+    if (slow) {
+      int at = atomicAdd(&s_nslow, __popc(slow));
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+        if ((slow >> u) & 1u) s_slow[at++] = (int)threadIdx.x + u * (int)blockDim.x;
+    }
+    __syncthreads();
+    const int nslow = s_nslow;
 #pragma unroll 1
-    for (int u = 0; u < UNR; ++u) {
-      if (!((slow >> u) & 1u)) continue;
-      const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
+    for (int i = threadIdx.x; i < nslow; i += blockDim.x) {
+      const long long p = p0 + s_slow[i];
       const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
       const DevBox B = M.boxes[b];
       const double x = P.x[p], y = P.y[p], z = P.z[p], m = P.a[p];
