@@ -514,6 +514,30 @@ def test_step_owner_tiles_fall_back(B, orc, idx):
     assert "fold" in out["phases"], out["phases"]
 
 
+@pytest.mark.parametrize("case", ["f64r", "sinks"])
+def test_owner_tiles_not_taken(B, orc, case):
+    """fuse_apply 2 in the reproducibility mode (its bounds follow the fold's
+    order) and in steps with sinks runs the ghost-zone step with its fold."""
+    import torch
+    if case == "f64r":
+        w = W.c2(nx=40)
+        ctx = B.Context(w, "f64r", channels="all")
+    else:
+        w = SMALL["c3_40"]()
+        ctx = B.Context(w, "fix64", channels="all")
+    ctx.set_tuning(deposit_path=1, fuse_apply=2, tile_x=16, tile_yz=4)
+    assert owner_tiles_fit(w, 16, 4)
+    ctx.profile_begin(16)
+    ctx.step()
+    torch.cuda.synchronize()
+    phases = ctx.profile_end()
+    got = ctx.state.cpu().numpy()
+    ctx.close()
+    assert "fold" in phases, phases
+    if case == "sinks":
+        assert np.array_equal(got, orc.step(w, "fix64")["state"].astype(got.dtype))
+
+
 def test_graph_owner_tiles(B):
     """A captured multi-box graph of fold-free steps replays like eager steps."""
     import torch
