@@ -3419,11 +3419,11 @@ __global__ __launch_bounds__(256) void k_create_find(Mesh M, const S* __restrict
       rho = (double)st[0];
       if (rho > truelove_at(L, st, B.ncell)) {
         // box cells < 2^31: 32-bit quotients
-        const unsigned cu = (unsigned)c, nx = (unsigned)B.n[0], ny = (unsigned)B.n[1];
-        const unsigned row = cu / nx;
-        const int li = (int)(cu - row * nx);
-        const int lk = (int)(row / ny);
-        const int lj = (int)(row - (unsigned)lk * ny);
+        const unsigned cu = (unsigned)c, bnx = (unsigned)B.n[0], bny = (unsigned)B.n[1];
+        const unsigned row = cu / bnx;
+        const int li = (int)(cu - row * bnx);
+        const int lk = (int)(row / bny);
+        const int lj = (int)(row - (unsigned)lk * bny);
         gi = B.lo[0] + li;
         gj = B.lo[1] + lj;
         gk = B.lo[2] + lk;
