@@ -102,9 +102,12 @@ def kernel_method_bytes(w, acc, counts, F, fused, applied=None, owner=False):
     HBM bytes all the same); fused (no sinks), it also applies the interior
     cells (owned, at least g from every face), and the shell kernel folds and
     applies the rest.  On owner tiles (fuse_apply 2: no ghost zone, no fold)
-    the tile pass does all of Steps 1-5 and carries all of the step's bytes.
-    Direct path: zero fill, CIC and supernova atomics, fold, apply, one
-    kernel each."""
+    the tile pass processes every owned cell as the fused pass processes the
+    interior ones: records, deposits, each owned cell's buffer value and the
+    updated cells' state; the zero fill and the fold, which it never
+    performs, stay out of its bytes (they remain in the step's).  Direct
+    path: zero fill, CIC and supernova atomics, fold, apply, one kernel
+    each."""
     import numpy as np
     ba = acc_bytes(acc)
     bs = np.dtype(w.state.dtype).itemsize
@@ -126,7 +129,7 @@ def kernel_method_bytes(w, acc, counts, F, fused, applied=None, owner=False):
             7 * bs * applied["shell"]
         out["apply"] = 0
     if owner:
-        out["tile"] = method_bytes(w, acc, counts, F, applied)["total"]
+        out["tile"] = record_bytes(w) + dep + owned * F * ba + 7 * bs * applied["total"]
         out["fold"] = 0
     if w.cic is not None and w.cic.n:
         out["cic"] = w.cic.n * 32 + 2 * ba * counts["cic"]
