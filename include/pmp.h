@@ -250,10 +250,14 @@ typedef struct {
                             owned cell from its complete LDS sum (Steps 2, 3
                             and 5 fused; the same sums as the fold, added in
                             another order: fixed point bit for bit, floats
-                            rounded once).  The buffer is not written.  Needs
-                            every tile extent along an axis to be at most the
-                            domain less 2g cells, and not PMP_ACC_F64R; where
-                            that does not hold the step runs as with 1. */
+                            rounded once).  The buffer is not written; in a
+                            step with sinks the tile pass stores the owned
+                            cells, the sinks add their removal to the owning
+                            cells, and the sink update and apply follow with
+                            no fold.  Needs every tile extent along an axis to
+                            be at most the domain less 2g cells, the binned
+                            path and not PMP_ACC_F64R; where that does not hold
+                            the step runs as with 1. */
   int32_t count_lanes;   /* binned path: lanes counting one supernova's sphere
                             members (its candidate rows dealt round them):
                             1, 2, 4, 8 or 16 */

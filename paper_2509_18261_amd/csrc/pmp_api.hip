@@ -1073,13 +1073,15 @@ SinkParams sink_params(const pmp_ctx* c, const pmp_sinks* p) {
 }
 
 // fuse_state non-null (a step without sinks): the binned path also applies
-// the interior cells, or, on owner tiles (owner), every owned cell; *fused
-// tells which it did (0: none, 1: the interior cells, 2: every cell).
+// the interior cells, or, on owner tiles (owner), every owned cell.  On owner
+// tiles without fuse_state (a step with sinks) the tile pass stores the owned
+// cells only and the sinks add to their owning cells, so no fold is needed.
+// *fused tells what was done (0: a ghost-zoned buffer to fold, 1: the
+// interior cells applied, 2: every cell applied, 3: owned cells complete).
 int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, const pmp_sn* sn,
                const pmp_sinks* sinks, const pmp_limits* limits, hipStream_t s,
                void* fuse_state = nullptr, int* fused = nullptr, bool owner = false) {
   if (fused) *fused = 0;
-  if (!fuse_state) owner = false;
   if (!buf) return fail(PMP_EINVAL, "buffer is NULL");
   c->ws_sink_bytes = 0;  // a workspace holds this deposit's sink scratch first, if any
   const bool has_cic = cic && cic->n > 0;
@@ -1110,6 +1112,9 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
     if (rc) return rc;
   }
   const Mesh M = c->mesh();
+  // owner tiles need the binned path (with no particles to bin, the zero
+  // fill and the fold stand)
+  owner = owner && c->tune.deposit_path == 1 && (has_cic || has_sn);
   if (c->tune.deposit_path == 1 && (has_cic || has_sn)) {
     int rc = ensure_bin_work(c, has_cic ? cic->n : 0, has_sn ? sn->n : 0,
                              has_sn ? sn->r_max : 0.0, s);
@@ -1134,7 +1139,7 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
       }
       PMP_HIP(launch_tile_deposit(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
                                   buf, c->tune, fuse_state, L, s));
-      if (fused) *fused = !fuse_state ? 0 : (owner ? 2 : 1);
+      if (fused) *fused = owner ? (fuse_state ? 2 : 3) : (fuse_state ? 1 : 0);
     }
   } else {
     {
@@ -1152,8 +1157,10 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
   }
   if (has_sink) {
     PhaseTimer t(c, PMP_PHASE_SINK_DEPOSIT, s);
-    PMP_HIP(launch_sink_deposit(M, from_sinks(sinks), state, buf, c->d_sink_scratch,
-                                sink_params(c, sinks), to_limits(c, limits), c->d_bound, s));
+    SinkParams K = sink_params(c, sinks);
+    K.owner = owner ? 1 : 0;
+    PMP_HIP(launch_sink_deposit(M, from_sinks(sinks), state, buf, c->d_sink_scratch, K,
+                                to_limits(c, limits), c->d_bound, s));
   }
   return PMP_OK;
 }
@@ -1202,14 +1209,16 @@ int do_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn
                       owner_step(c));
   if (rc) return rc;
   if (fused == 2) return PMP_OK;  // owner tiles: every owned cell is done
-  if (fused) {
+  if (fused == 1) {
     // interior cells are done; fold and apply the shell
     PhaseTimer t(c, PMP_PHASE_FOLD, s);
     PMP_HIP(launch_fold_apply(c->mesh(), state, buf, to_limits(c, limits), s));
     return PMP_OK;
   }
-  rc = do_fold(c, buf, s);
-  if (rc) return rc;
+  if (fused != 3) {  // owner tiles hold every contribution in the owned cells
+    rc = do_fold(c, buf, s);
+    if (rc) return rc;
+  }
   if (sinks && sinks->n > 0) {
     if (!sink_out) return fail(PMP_EINVAL, "sinks given but sink_out is NULL");
     const long long n = sinks->n;

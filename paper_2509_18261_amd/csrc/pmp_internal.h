@@ -277,6 +277,7 @@ struct SinkParams {
   double r_k, r_gauss, dx;
   double G, dt, gamma, lambda;
   int rate;
+  int owner;  // the deposit adds to the owning box's cell (owner tiles: no fold follows)
 };
 
 // The sink scratch holds kSinkScratch doubles per sink: the kernel weight

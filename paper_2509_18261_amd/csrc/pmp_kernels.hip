@@ -699,6 +699,16 @@ __device__ __forceinline__ bool locate(const Mesh& M, int i, int j, int k, CellL
   return locate_wrapped(M, w, L);
 }
 
+// Element of channel ch (its buffer slot) of the located cell in its owning
+// box's padded buffer.
+template <class T>
+__device__ __forceinline__ T* owner_elem(const Mesh& M, T* buf, const CellLoc& Lc, int ch) {
+  const DevBox& Bo = *Lc.B;
+  const int g = M.ghost;
+  return buf + Bo.boff + M.slot[ch] * Bo.npad +
+         ((long long)(Lc.l[2] + g) * Bo.p[1] + (Lc.l[1] + g)) * Bo.p[0] + (Lc.l[0] + g);
+}
+
 // Box of sink s: the b with off[b] <= s < off[b + 1] (empty boxes skipped).
 __device__ __forceinline__ int particle_box(const long long* off, int nbox, long long s) {
   int lo = 0, hi = nbox - 1;
@@ -958,18 +968,23 @@ __global__ __launch_bounds__(kSinkBlock) void k_sink_deposit(Mesh M, Particles P
       const double kc = (tr > kreq) ? tr : kreq;
       long long idx;
       if (!pad_index(B, g, i, j, k, idx)) { reach_bad = true; continue; }
+      // the cell's element: in the home box's padded buffer (the fold moves
+      // ghost cells later), or, on owner tiles, in the owning box's (no fold
+      // follows)
+      T* dst = f5 + idx;
+      if (K.owner) dst = owner_elem(M, buf, Lc, 5);
       if constexpr (FIXED) {
         long long q1, q2;
         if (!quantise(kc, q1) || !quantise(kreq, q2)) { ok = false; continue; }
-        gadd_fix(f5 + idx, q1);
+        gadd_fix(dst, q1);
         qreq += q2;
       } else if constexpr (ACC == PMP_ACC_F64R) {
         // the element's error bound (same index as the buffer) grows by
         // eps |sum after the addition| (the atomic returns the sum before)
-        const double old = atomicAdd(f5 + idx, kc);
-        atomicAdd(bound + (f5 + idx - buf), kEps * fabs(old + kc));
+        const double old = atomicAdd(dst, kc);
+        atomicAdd(bound + (dst - buf), kEps * fabs(old + kc));
       } else {
-        gadd(f5 + idx, kc);
+        gadd(dst, kc);
       }
     }
     if (reach_bad) raise_flag(M.status, PMP_FLAG_REACH);
@@ -987,7 +1002,11 @@ __global__ __launch_bounds__(kSinkBlock) void k_sink_deposit(Mesh M, Particles P
             ti = lo[0] + ii; tj = lo[1] + jj; tk = lo[2] + kk;
           }
           long long idx;
-          if (pad_index(B, g, ti, tj, tk, idx)) gadd_fix(f5 + idx, Q - qreq);
+          if (pad_index(B, g, ti, tj, tk, idx)) {
+            CellLoc Lr;
+            if (!K.owner) gadd_fix(f5 + idx, Q - qreq);
+            else if (locate(M, ti, tj, tk, Lr)) gadd_fix(owner_elem(M, buf, Lr, 5), Q - qreq);
+          }
         } else {
           raise_flag(M.status, PMP_FLAG_OVERFLOW);
         }
@@ -2975,10 +2994,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
         const OutT vr = sr >= 0 ? from_lds<OutT>(r0) : (OutT)0;
         const OutT ve = se >= 0 ? from_lds<OutT>(r4) : (OutT)0;
         // owned-local coordinates: interior when g <= . < n - g on every axis
-        // (with owner tiles every cell is owned and its sum complete)
+        // (with owner tiles every cell is owned and its sum complete: applied,
+        // or, in a step with sinks, stored for the sink passes and the apply)
         const int ox = ox0 + u, oy = oy0 + v, oz = oz0 + w;
-        if (OWN || (state && ox >= g && ox < n0 - g && oy >= g && oy < n1 - g && oz >= g &&
-                    oz < n2 - g)) {
+        if (state && (OWN || (ox >= g && ox < n0 - g && oy >= g && oy < n1 - g && oz >= g &&
+                              oz < n2 - g))) {
           const long long si = tso + ((w * n1 + v) * n0 + u);
           if (M.state == PMP_STATE_F32)
             apply_cell_nosrc((float*)state + si, ncell, to_f64(vr), to_f64(ve), L, cnt);

@@ -514,28 +514,62 @@ def test_step_owner_tiles_fall_back(B, orc, idx):
     assert "fold" in out["phases"], out["phases"]
 
 
-@pytest.mark.parametrize("case", ["f64r", "sinks"])
-def test_owner_tiles_not_taken(B, orc, case):
+def test_owner_tiles_not_in_reproducibility_mode(B):
     """fuse_apply 2 in the reproducibility mode (its bounds follow the fold's
-    order) and in steps with sinks runs the ghost-zone step with its fold."""
+    order) runs the ghost-zone step with its fold."""
     import torch
-    if case == "f64r":
-        w = W.c2(nx=40)
-        ctx = B.Context(w, "f64r", channels="all")
-    else:
-        w = SMALL["c3_40"]()
-        ctx = B.Context(w, "fix64", channels="all")
+    w = W.c2(nx=40)
+    ctx = B.Context(w, "f64r", channels="all")
     ctx.set_tuning(deposit_path=1, fuse_apply=2, tile_x=16, tile_yz=4)
     assert owner_tiles_fit(w, 16, 4)
     ctx.profile_begin(16)
     ctx.step()
     torch.cuda.synchronize()
     phases = ctx.profile_end()
-    got = ctx.state.cpu().numpy()
     ctx.close()
     assert "fold" in phases, phases
-    if case == "sinks":
-        assert np.array_equal(got, orc.step(w, "fix64")["state"].astype(got.dtype))
+
+
+OWNER_SINK_CASES = ["c3_40", "c3bh_40", "c3tl_40", "c5s_4", "c5sbh_4", "c5sbhtl_4"]
+
+
+@pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
+@pytest.mark.parametrize("name", OWNER_SINK_CASES)
+def test_step_owner_tiles_with_sinks(B, orc, name, acc):
+    """Steps with sinks on owner tiles: the tile pass stores the owned cells,
+    the sinks add their removal to the owning cells, no fold runs, then the
+    sink update and the apply; the oracle's state and sink gains (fixed point
+    bit for bit)."""
+    import torch
+    w = SMALL[name]()
+    assert owner_tiles_fit(w, 16, 4)
+    say(f"owner tiles with sinks {w.name} acc={acc}")
+    ctx = B.Context(w, acc, channels="all")
+    ctx.set_tuning(deposit_path=1, fuse_apply=2, tile_x=16, tile_yz=4)
+    ctx.profile_begin(16)
+    ctx.step()
+    torch.cuda.synchronize()
+    phases = ctx.profile_end()
+    got = ctx.state.cpu().numpy()
+    st = ctx.status()
+    sink = ctx.sink_out.cpu().numpy()
+    ctx.close()
+    assert "fold" not in phases and "sink_deposit" in phases, phases
+    assert st["flags"] in (0, 0x10), st
+    ref = orc.step(w, "fix64" if acc == "fix64" else "f64", want_eta=True)
+    k = w.sinks.n
+    if acc == "fix64":
+        assert np.array_equal(got, ref["state"].astype(got.dtype))
+        for i, a in enumerate(ref["sink_d"]):
+            assert np.array_equal(sink[i * k:(i + 1) * k], a)
+        for key in ("touched", "bind", "lam", "fall"):
+            assert st[key] == ref["counters"][key], (key, st, ref["counters"])
+    else:
+        for f, (x, r) in enumerate(zip(field_views(w, got, "state"),
+                                       field_views(w, ref["state"].astype(got.dtype), "state"))):
+            assert rel_err(x, r) <= max(TOL[acc], float(np.finfo(got.dtype).eps)), f
+        for i, a in enumerate(ref["sink_d"]):
+            assert rel_err(sink[i * k:(i + 1) * k], a) <= max(TOL[acc], 1e-9), i
 
 
 def test_graph_owner_tiles(B):
