@@ -1836,10 +1836,11 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
                            {16, 8, 256}, {64, 2, 128}, {16, 4, 128}, {32, 4, 256},
                            {64, 8, 256}, {64, 8, 512}, {128, 4, 256}, {128, 4, 512},
                            {256, 4, 256}, {256, 4, 512}, {256, 2, 256}};
-  // the fused apply only applies to steps without sinks; owner tiles (2)
-  // where they fit the layout
-  for (int fuse = has_sinks ? 0 : 2; fuse >= 0; --fuse)
+  // the interior-fused apply (1) only applies to steps without sinks; owner
+  // tiles (2) wherever they fit the layout
+  for (int fuse = 2; fuse >= 0; --fuse)
     for (const auto& sh : shapes) {
+      if (fuse == 1 && has_sinks) continue;
       if (fuse == 2 && (c->acc == PMP_ACC_F64R || !owner_tiles_fit(c, sh[0], sh[1]))) continue;
       add(1, sh[0], sh[1], sh[2], 64, 0, fuse);
     }
