@@ -433,12 +433,30 @@ def batched_comparison(ctx, args, eager_ms):
     torch.cuda.synchronize()
     per_box_ms = t0.elapsed_time(t1) / pb_steps
     log(f"per-box launches: {per_box_ms:.3f} ms/step")
+    # the per-box baseline runs the direct path (zero fill, global atomics,
+    # fold, apply); the same path batched (one launch per kernel over every
+    # box, eager) separates the gain of batching from that of the binned path
+    d = tun.as_dict()
+    ctx.set_tuning(**{**d, "deposit_path": 0, "fuse_apply": 0})
+    ctx.step()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(pb_steps):
+        ctx.step()
+    t1.record()
+    torch.cuda.synchronize()
+    direct_ms = t0.elapsed_time(t1) / pb_steps
+    ctx.set_tuning(**d)
+    log(f"batched direct path: {direct_ms:.3f} ms/step")
     return {"boxes": ctx.w.nbox, "eager_batched_ms_per_step": eager_ms,
             "graph_ms_per_step": graph_ms, "graph_steps": n,
             "per_box_launch_ms_per_step": per_box_ms,
             "per_box_launches_per_step": 5 * ctx.w.nbox,
             "speedup_graph_vs_per_box": per_box_ms / graph_ms,
-            "tuning": tun.as_dict()}
+            "batched_direct_path_ms_per_step": direct_ms,
+            "speedup_batching_direct_path": per_box_ms / direct_ms,
+            "speedup_binned_vs_direct_batched": direct_ms / eager_ms,
+            "tuning": d}
 
 
 def repro_rates(B, w, channels):
