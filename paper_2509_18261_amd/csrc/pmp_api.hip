@@ -267,6 +267,7 @@ void free_bin_work(pmp_ctx* c) {
   (void)hipFree(w.hist2);
   (void)hipFree(w.block_sums2);
   (void)hipFree(w.heavy_base);
+  (void)hipFree(w.sink_flag);
   (void)hipFree(w.heavy_unit);
   (void)hipFree(w.heavy_count);
   (void)hipFree(w.arrive);
@@ -784,6 +785,7 @@ size_t carve_bin(const BinSizes& z, char* base, BinWork* w) {
   take(W.cic_off, z.tiles1);
   take(W.sn_off, z.tiles1);
   take(W.heavy_base, z.tiles1);
+  take(W.sink_flag, z.tiles1);
   take(partial, z.partial);
   W.partial = partial;
   take(W.heavy_unit, z.slot_cap);
@@ -857,6 +859,7 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
     rc = regrow(&w.cic_off, 0, c->ntiles + 1);
     if (!rc) rc = regrow(&w.sn_off, 0, c->ntiles + 1);
     if (!rc) rc = regrow(&w.heavy_base, 0, c->ntiles + 1);
+    if (!rc) rc = regrow(&w.sink_flag, 0, c->ntiles + 1);
     if (!rc) c->bw_tiles = c->ntiles + 1;
   }
   if (!rc && partial > c->bw_partial) {
@@ -1072,12 +1075,15 @@ SinkParams sink_params(const pmp_ctx* c, const pmp_sinks* p) {
   return K;
 }
 
-// fuse_state non-null (a step without sinks): the binned path also applies
-// the interior cells, or, on owner tiles (owner), every owned cell.  On owner
-// tiles without fuse_state (a step with sinks) the tile pass stores the owned
-// cells only and the sinks add to their owning cells, so no fold is needed.
-// *fused tells what was done (0: a ghost-zoned buffer to fold, 1: the
-// interior cells applied, 2: every cell applied, 3: owned cells complete).
+// fuse_state non-null: the binned path also applies the interior cells (a
+// step without sinks), or, on owner tiles (owner), every owned cell, except,
+// in a step with sinks, the tiles a sink kernel may reach: those are stored,
+// the sinks add to their owning cells, and they are applied after the sink
+// update.  On owner tiles without fuse_state the tile pass stores every
+// owned cell.  No fold is needed on owner tiles.  *fused tells what was done
+// (0: a ghost-zoned buffer to fold, 1: the interior cells applied, 2: every
+// cell applied, 3: owned cells complete, 4: every cell applied but those of
+// the flagged tiles, which are complete).
 int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, const pmp_sn* sn,
                const pmp_sinks* sinks, const pmp_limits* limits, hipStream_t s,
                void* fuse_state = nullptr, int* fused = nullptr, bool owner = false) {
@@ -1122,12 +1128,15 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
     const Particles pc = has_cic ? from_cic(cic) : Particles{};
     const Particles ps = has_sn ? from_sn(sn) : Particles{};
     const TileGrid T = c->tiles(owner);
+    const bool flagged = owner && has_sink && fuse_state;
     {
       PhaseTimer t(c, PMP_PHASE_BIN, s);
       PMP_HIP(launch_bin(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
                          c->tune.count_lanes, s));
       PMP_HIP(launch_tile_prep(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
                                c->tune, s));
+      if (flagged)
+        PMP_HIP(launch_sink_tiles(M, T, from_sinks(sinks), sinks->r_k, c->bw.sink_flag, s));
     }
     {
       PhaseTimer t(c, PMP_PHASE_TILE, s);
@@ -1138,8 +1147,9 @@ int do_deposit(pmp_ctx* c, void* buf, const void* state, const pmp_cic* cic, con
         L = to_limits(c, limits);
       }
       PMP_HIP(launch_tile_deposit(M, T, has_cic ? &pc : nullptr, has_sn ? &ps : nullptr, c->bw,
-                                  buf, c->tune, fuse_state, L, s));
-      if (fused) *fused = owner ? (fuse_state ? 2 : 3) : (fuse_state ? 1 : 0);
+                                  buf, c->tune, fuse_state, L, s,
+                                  flagged ? c->bw.sink_flag : nullptr));
+      if (fused) *fused = owner ? (fuse_state ? (flagged ? 4 : 2) : 3) : (fuse_state ? 1 : 0);
     }
   } else {
     {
@@ -1203,10 +1213,11 @@ int do_fold(pmp_ctx* c, void* buf, hipStream_t s) {
 int do_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn* sn,
             const pmp_sinks* sinks, const pmp_limits* limits, double* sink_out, hipStream_t s) {
   const bool has_sinks = sinks && sinks->n > 0;
+  const bool owner = owner_step(c);
   int fused = 0;
   int rc = do_deposit(c, buf, state, cic, sn, sinks, limits, s,
-                      (!has_sinks && c->tune.fuse_apply && state) ? state : nullptr, &fused,
-                      owner_step(c));
+                      ((!has_sinks && c->tune.fuse_apply) || owner) && state ? state : nullptr,
+                      &fused, owner);
   if (rc) return rc;
   if (fused == 2) return PMP_OK;  // owner tiles: every owned cell is done
   if (fused == 1) {
@@ -1215,7 +1226,7 @@ int do_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn
     PMP_HIP(launch_fold_apply(c->mesh(), state, buf, to_limits(c, limits), s));
     return PMP_OK;
   }
-  if (fused != 3) {  // owner tiles hold every contribution in the owned cells
+  if (fused != 3 && fused != 4) {  // owner tiles hold every contribution in the owned cells
     rc = do_fold(c, buf, s);
     if (rc) return rc;
   }
@@ -1225,6 +1236,13 @@ int do_step(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const pmp_sn
     rc = do_sink_update(c, state, buf, sinks, limits, sink_out, sink_out + n, sink_out + 2 * n,
                         sink_out + 3 * n, s);
     if (rc) return rc;
+  }
+  if (fused == 4) {
+    // owner tiles with sinks: the tiles a sink kernel may reach, now
+    PhaseTimer t(c, PMP_PHASE_APPLY, s);
+    PMP_HIP(launch_apply_tiles(c->mesh(), c->tiles(true), state, buf, c->bw.sink_flag,
+                               to_limits(c, limits), s));
+    return PMP_OK;
   }
   return do_apply(c, state, buf, limits, nullptr, s);
 }

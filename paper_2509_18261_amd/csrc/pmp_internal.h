@@ -216,6 +216,7 @@ struct BinWork {
   // workgroups (chunk slots); each chunk leaves its LDS partial tile in
   // `partial` and the last one to finish combines them in chunk order
   int* heavy_base;      // [ntiles] first chunk slot of a split tile, or -1
+  int* sink_flag;       // [ntiles] owner tiles with sinks: 1 where a sink kernel may reach
   int2* heavy_unit;     // [slot_cap] (tile, chunk) of each slot; tile -1: unused
   int* heavy_count;     // [1] chunk slots claimed this step (may exceed slot_cap)
   int* arrive;          // [slot_cap] finished chunks, at the tile's first slot
@@ -258,12 +259,13 @@ hipError_t launch_tile_prep(const Mesh& M, const TileGrid& T, const Particles* c
 // state non-null: the step's Steps 3 + 5 are fused in for owned cells at
 // least g from every face of their box (no ghost image reaches them); those
 // cells' buffer entries are left unwritten, and launch_fold_apply finishes
-// the shell cells.  With owner tiles (T.owner) state must be non-null: every
-// owned cell is applied and the buffer is not written at all.
+// the shell cells.  With owner tiles (T.owner) every owned cell is applied
+// and the buffer is not written, except in the tiles sink_flag marks (and
+// with state null, in every tile), which are stored for the sink passes.
 hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles* cic,
                                const Particles* sn, const BinWork& bw, void* buf,
                                const pmp_tuning& t, void* state, const Limits& L,
-                               hipStream_t s);
+                               hipStream_t s, const int* sink_flag = nullptr);
 // Steps 2 + 3 + 5 for the shell cells only (after a fused tile pass).
 hipError_t launch_fold_apply(const Mesh& M, void* state, const void* buf, const Limits& L,
                              hipStream_t s);
@@ -284,6 +286,15 @@ struct SinkParams {
 // sum W, the requested mass and r_acc^2.
 constexpr int kSinkScratch = 3;
 
+// Owner tiles in a step with sinks: flags every owner tile a sink's kernel
+// may reach (conservatively: its kernel cube widened by one cell), after
+// clearing them all.
+hipError_t launch_sink_tiles(const Mesh& M, const TileGrid& T, const Particles& sinks, double r_k,
+                             int* flag, hipStream_t s);
+// Steps 3 + 5 for the cells of the flagged owner tiles (the others were
+// applied by the tile pass).
+hipError_t launch_apply_tiles(const Mesh& M, const TileGrid& T, void* state, const void* buf,
+                              const int* flag, const Limits& L, hipStream_t s);
 hipError_t launch_sink_deposit(const Mesh& M, const Particles& P, const void* state,
                                void* buf, double* sink_scratch, const SinkParams& K,
                                const Limits& L, double* bound, hipStream_t s);

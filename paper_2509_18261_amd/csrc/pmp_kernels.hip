@@ -2721,7 +2721,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
                                                       void* __restrict__ partial_v,
                                                       long long slot_cap,
                                                       typename AccT<ACC>::T* __restrict__ buf,
-                                                      void* __restrict__ state, Limits L) {
+                                                      void* __restrict__ state, Limits L,
+                                                      const int* __restrict__ sink_flag) {
   using OutT = typename AccT<ACC>::T;
   constexpr bool FIXED = (ACC == PMP_ACC_FIX64);
   constexpr bool BOUNDS = (ACC == PMP_ACC_F64R);  // error bounds beside the sums
@@ -2969,6 +2970,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
     // ghost image reaches them)
     OutT* f0 = buf + G.boff;
     const long long np = (long long)G.p[0] * G.p[1] * G.p[2];
+    // owner tiles a sink kernel may reach keep their cells for the sink
+    // passes: stored, applied after the sink update
+    const bool apply_here = state && !(OWN && sink_flag && sink_flag[tile]);
     const int n0 = G.p[0] - 2 * g, n1 = G.p[1] - 2 * g, n2 = G.p[2] - 2 * g;
     const long long ncell = (long long)n0 * n1 * n2;
     const int sr = M.slot[0], se = M.slot[4];
@@ -2997,8 +3001,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
         // (with owner tiles every cell is owned and its sum complete: applied,
         // or, in a step with sinks, stored for the sink passes and the apply)
         const int ox = ox0 + u, oy = oy0 + v, oz = oz0 + w;
-        if (state && (OWN || (ox >= g && ox < n0 - g && oy >= g && oy < n1 - g && oz >= g &&
-                              oz < n2 - g))) {
+        if (apply_here && (OWN || (ox >= g && ox < n0 - g && oy >= g && oy < n1 - g &&
+                                   oz >= g && oz < n2 - g))) {
           const long long si = tso + ((w * n1 + v) * n0 + u);
           if (M.state == PMP_STATE_F32)
             apply_cell_nosrc((float*)state + si, ncell, to_f64(vr), to_f64(ve), L, cnt);
@@ -3024,6 +3028,68 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
     __syncthreads();
   }
   if (state) flush_counts(M, cnt);
+}
+
+// Owner tiles in a step with sinks: every owner tile a sink's kernel may
+// reach is flagged (the kernel's cells lie within floor(r_K) + 1 cells of the
+// host cell; the cube is widened by one more, and a flag too many only moves
+// a tile's apply after the sink update).  Sinks outside their box are left
+// to the deposit kernel, which flags them.
+__global__ __launch_bounds__(256) void k_sink_tiles(Mesh M, TileGrid T, Particles P, int reach,
+                                                   int* __restrict__ flag) {
+  const int g = M.ghost;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < P.n;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int b = particle_box(P.box_off, M.nbox, s);
+    const DevBox B = M.boxes[b];
+    int h[3];
+    if (!host_cell(B, P.x[s], P.y[s], P.z[s], h)) continue;
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = h[a] - reach - 1 - B.lo[a] + g;
+      hi[a] = h[a] + reach + 1 - B.lo[a] + g;
+    }
+    particle_tiles<true>(M, T, b, B, lo, hi, [&](int t) { flag[t] = 1; });
+  }
+}
+
+// Steps 3 + 5 for the cells of the flagged owner tiles, after the sink
+// update: one workgroup per tile (unflagged tiles return at once), each
+// cell's buffer channels read from its owned place, the limiter and the
+// update as in k_apply.
+template <class S, int ACC>
+__global__ __launch_bounds__(256) void k_apply_tiles(Mesh M, TileGrid T, S* __restrict__ state,
+                                                     const typename AccT<ACC>::T* __restrict__ buf,
+                                                     const int* __restrict__ flag, Limits L) {
+  const int g = M.ghost;
+  ApplyCounts cnt;
+  const int s0 = M.slot[0], s1 = M.slot[1], s2 = M.slot[2], s3 = M.slot[3], s4 = M.slot[4],
+            s5 = M.slot[5];
+  for (long long t = blockIdx.x; t < T.ntiles; t += gridDim.x) {
+    if (!flag[t]) continue;
+    const TileGeo G = T.geo[t];
+    const int n0 = G.p[0] - 2 * g, n1 = G.p[1] - 2 * g, n2 = G.p[2] - 2 * g;
+    const long long ncell = (long long)n0 * n1 * n2;
+    const long long np = (long long)G.p[0] * G.p[1] * G.p[2];
+    const int e0 = G.ext[0], e01 = G.ext[0] * G.ext[1], total = e01 * G.ext[2];
+    for (int c = threadIdx.x; c < total; c += blockDim.x) {
+      int u, v, w;
+      cube_cell(c, e0, e01, u, v, w);
+      // owned-local cell, its padded buffer index and its state index
+      const int ox = G.o[0] - g + u, oy = G.o[1] - g + v, oz = G.o[2] - g + w;
+      const long long bi = G.boff + ((long long)(oz + g) * G.p[1] + (oy + g)) * G.p[0] + (ox + g);
+      const long long si = G.soff + ((long long)oz * n1 + oy) * n0 + ox;
+      const double Dr = s0 >= 0 ? to_f64(buf[bi + s0 * np]) : 0.0;
+      const double qx = s1 >= 0 ? to_f64(buf[bi + s1 * np]) : 0.0;
+      const double qy = s2 >= 0 ? to_f64(buf[bi + s2 * np]) : 0.0;
+      const double qz = s3 >= 0 ? to_f64(buf[bi + s3 * np]) : 0.0;
+      const double DE = s4 >= 0 ? to_f64(buf[bi + s4 * np]) : 0.0;
+      const double K = s5 >= 0 ? to_f64(buf[bi + s5 * np]) : 0.0;
+      (void)apply_cell(state + si, ncell, Dr, qx, qy, qz, DE, K, L, cnt);
+    }
+  }
+  flush_counts(M, cnt);
 }
 
 inline int grid_for(long long n, int block, int cap) {
@@ -3204,10 +3270,43 @@ hipError_t launch_tile_prep(const Mesh& M, const TileGrid& T, const Particles* c
   return hipGetLastError();
 }
 
+hipError_t launch_sink_tiles(const Mesh& M, const TileGrid& T, const Particles& sinks, double r_k,
+                             int* flag, hipStream_t s) {
+  // clear with a kernel (the step may be captured into a graph)
+  hipError_t e = launch_zero(flag, T.ntiles * (long long)sizeof(int), 256, s);
+  if (e != hipSuccess || sinks.n <= 0) return e;
+  const int reach = (int)floor(r_k) + 1;
+  hipLaunchKernelGGL(k_sink_tiles, dim3(grid_for(sinks.n, 256, M.num_cu * 4)), dim3(256), 0, s, M,
+                     T, sinks, reach, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_tiles(const Mesh& M, const TileGrid& T, void* state, const void* buf,
+                              const int* flag, const Limits& L, hipStream_t s) {
+  const int grid = grid_for(T.ntiles, 1, M.num_cu * 32);
+#define PMP_AT(S, ACC, TT)                                                                    \
+  hipLaunchKernelGGL((k_apply_tiles<S, ACC>), dim3(grid), dim3(256), 0, s, M, T, (S*)state,   \
+                     (const TT*)buf, flag, L)
+  const bool f32 = M.state == PMP_STATE_F32;
+  switch (M.acc) {
+    case PMP_ACC_F32:
+      if (f32) PMP_AT(float, PMP_ACC_F32, float); else PMP_AT(double, PMP_ACC_F32, float);
+      break;
+    case PMP_ACC_F64:
+      if (f32) PMP_AT(float, PMP_ACC_F64, double); else PMP_AT(double, PMP_ACC_F64, double);
+      break;
+    default:
+      if (f32) PMP_AT(float, PMP_ACC_FIX64, long long);
+      else PMP_AT(double, PMP_ACC_FIX64, long long);
+  }
+#undef PMP_AT
+  return hipGetLastError();
+}
+
 hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles* cic,
                                const Particles* sn, const BinWork& bw, void* buf,
                                const pmp_tuning& t, void* state, const Limits& L,
-                               hipStream_t s) {
+                               hipStream_t s, const int* sink_flag) {
   const int* coff = (cic && cic->n > 0) ? bw.cic_off : nullptr;
   const int* soff = (sn && sn->n > 0) ? bw.sn_off : nullptr;
   const int block = t.tile_block;
@@ -3224,7 +3323,7 @@ hipError_t launch_tile_deposit(const Mesh& M, const TileGrid& T, const Particles
                      t.chunk_sn,                                                              \
                      (const int*)bw.heavy_base, (const int2*)bw.heavy_unit,                   \
                      (const int*)bw.heavy_count, bw.arrive, bw.partial, bw.slot_cap,          \
-                     (TT*)buf, state, L)
+                     (TT*)buf, state, L, sink_flag)
   // owner tiles: no reproducibility-mode variant (its bounds need the fold's order)
 #define PMP_TILE_ACC(TYZ)                                                       \
   if (T.owner) {                                                                \
