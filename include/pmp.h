@@ -251,10 +251,10 @@ typedef struct {
                             and 5 fused; the same sums as the fold, added in
                             another order: fixed point bit for bit, floats
                             rounded once).  The buffer is not written; in a
-                            step with sinks the tile pass stores the owned
-                            cells, the sinks add their removal to the owning
-                            cells, and the sink update and apply follow with
-                            no fold.  Needs every tile extent along an axis to
+                            step with sinks the tiles a sink kernel may reach
+                            are stored instead, the sinks add their removal
+                            to the owning cells, and after the sink update
+                            those tiles are applied; no fold runs.  Needs every tile extent along an axis to
                             be at most the domain less 2g cells, the binned
                             path and not PMP_ACC_F64R; where that does not hold
                             the step runs as with 1. */
