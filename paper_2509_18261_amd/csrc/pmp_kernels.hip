@@ -1885,9 +1885,10 @@ __device__ __forceinline__ void owner_tiles_of(const Mesh& M, const NbrBox& R, c
 }
 
 // Calls f(tile id) for every tile holding a cell of the padded-local range
-// [lo, hi] of box B (clipped to the padded box): the tiles of B itself, or,
-// with owner tiles, the owner tiles of whichever boxes own those cells.
-template <bool OWN, class F>
+// [lo, hi] of box B (clipped to the padded box): the tiles of B itself (OWN
+// 0), or the owner tiles of whichever boxes own those cells (OWN 1; OWN 2
+// when one box covers the domain, so that box owns every cell).
+template <int OWN, class F>
 __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T, int b,
                                                const DevBox& B, const int lo[3], const int hi[3],
                                                F&& f) {
@@ -1922,6 +1923,20 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
     for (int tz = tlo[2]; tz <= thi[2]; ++tz)
       for (int ty = tlo[1]; ty <= thi[1]; ++ty)
         for (int tx = tlo[0]; tx <= thi[0]; ++tx) f((int)tile_id(T, b, tx, ty, tz));
+    return;
+  }
+  if constexpr (OWN == 2) {
+    // one box covers the domain: its tiles, through the range's images
+    NbrBox R;
+    R.id = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      R.lo[a] = B.lo[a];
+      R.n[a] = B.n[a];
+      R.tax[a] = T.tiles_axis[a];
+    }
+    R.tprefix = 0;
+    owner_tiles_of(M, R, T, gl, gh, f);
     return;
   }
   // the boxes that can own its cells: per direction the range reaches
@@ -2062,7 +2077,7 @@ __device__ __forceinline__ int hist_col(int blk, int nblk) {
   return x * k + min(x, r) + (blk >> 3);
 }
 
-template <bool SCATTER, bool OWN>
+template <bool SCATTER, int OWN>
 __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T,
                                        const Particles& P, int shift, int nb,
                                        int* __restrict__ hist, int nblk,
@@ -2161,7 +2176,7 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
       const double x = P.x[p], y = P.y[p], z = P.z[p], m = P.a[p];
       int lo[3], hi[3];
       cic_box(B, g, x, y, z, lo, hi);
-      particle_tiles<true>(M, T, b, B, lo, hi, [&](int t) {
+      particle_tiles<OWN>(M, T, b, B, lo, hi, [&](int t) {
         const int pos = atomicAdd(h + (t >> shift), 1);
         if (SCATTER) {
           if (pos < cap) {
@@ -2187,7 +2202,7 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
 
 // Calls f(tile id) for the tiles a supernova's deposit touches: those of its
 // sphere's candidate box, or of the host cell alone when N < 0.
-template <bool OWN, class F>
+template <int OWN, class F>
 __device__ __forceinline__ void sn_tiles(const Mesh& M, const TileGrid& T, int b,
                                          const DevBox& B, double x, double y, double z,
                                          double r, int N, F&& f) {
@@ -2334,7 +2349,7 @@ __global__ __launch_bounds__(256) void k_sn_count(Mesh M, Particles P, SnPk* __r
 // Level 1, supernovae, histogram pass: one thread per particle counts it
 // into the buckets of every tile its sphere touches (kBinChunkSn particles
 // per block; skipped particles have n = 0).
-template <bool OWN>
+template <int OWN>
 __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGrid& T,
                                            const Particles& P, int shift, int nb,
                                            int* __restrict__ hist, int nblk,
@@ -2362,7 +2377,7 @@ __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGri
 
 // Level 1, supernovae, scatter pass: one thread per particle writes its
 // (particle, tile) entries at the positions the scanned histograms give.
-template <bool OWN>
+template <int OWN>
 __device__ __forceinline__ void l1_sn_scatter(int blk, const Mesh& M, const TileGrid& T,
                                               const Particles& P, int shift, int nb,
                                               int* __restrict__ hist, int nblk,
@@ -2399,7 +2414,7 @@ __device__ __forceinline__ void l1_sn_scatter(int blk, const Mesh& M, const Tile
 
 // Level 1 for both kinds in one launch: blocks [0, nbc) take CIC chunks,
 // the rest supernova chunks.
-template <bool OWN>
+template <int OWN>
 __global__ __launch_bounds__(256) void k_l1_hist(Mesh M, TileGrid T, Particles C, Particles Sn,
                                                 int shift, int nb, int* __restrict__ hc, int nbc,
                                                 int* __restrict__ hs, int nbs,
@@ -2410,7 +2425,7 @@ __global__ __launch_bounds__(256) void k_l1_hist(Mesh M, TileGrid T, Particles C
     l1_sn_hist<OWN>(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk);
 }
 
-template <bool OWN>
+template <int OWN>
 __global__ __launch_bounds__(256) void k_l1_scatter(Mesh M, TileGrid T, Particles C,
                                                    Particles Sn, int shift, int nb,
                                                    int* __restrict__ hc, int nbc,
@@ -3050,7 +3065,7 @@ __global__ __launch_bounds__(256) void k_sink_tiles(Mesh M, TileGrid T, Particle
       lo[a] = h[a] - reach - 1 - B.lo[a] + g;
       hi[a] = h[a] + reach + 1 - B.lo[a] + g;
     }
-    particle_tiles<true>(M, T, b, B, lo, hi, [&](int t) { flag[t] = 1; });
+    particle_tiles<1>(M, T, b, B, lo, hi, [&](int t) { flag[t] = 1; });
   }
 }
 
@@ -3194,14 +3209,14 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
     }
   }
   if (has_c || has_s) {
-    if (T.owner)
-      hipLaunchKernelGGL(k_l1_hist<true>, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
-                         has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc,
-                         hs, nbs, (const SnPk*)bw.sn_pk);
-    else
-      hipLaunchKernelGGL(k_l1_hist<false>, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
-                         has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc,
-                         hs, nbs, (const SnPk*)bw.sn_pk);
+#define PMP_L1H(OWN)                                                                        \
+  hipLaunchKernelGGL(k_l1_hist<OWN>, dim3(nbc + nbs), dim3(256), lds1, s, M, T,               \
+                     has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc, hs, \
+                     nbs, (const SnPk*)bw.sn_pk)
+    if (!T.owner) PMP_L1H(0);
+    else if (M.own_start == nullptr) PMP_L1H(2);  // one box covers the domain
+    else PMP_L1H(1);
+#undef PMP_L1H
   }
   // exclusive scan of both kinds' histograms, in place; hist[n] = total
   const int nblocks = (int)((n + kScanBlock - 1) / kScanBlock);
@@ -3210,16 +3225,15 @@ hipError_t launch_bin(const Mesh& M, const TileGrid& T, const Particles* cic,
   hipLaunchKernelGGL(k_scan_finish, dim3(nblocks), dim3(kScanBlock), 0, s, bw.hist,
                      (const int*)bw.block_sums, n, (const int*)nullptr, 0);
   if (has_c || has_s) {
-    if (T.owner)
-      hipLaunchKernelGGL(k_l1_scatter<true>, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
-                         has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc,
-                         hs, nbs, bw.cic_tmp, bw.cic_tmp_tile, bw.cic_cap,
-                         (const SnPk*)bw.sn_pk, bw.sn_tmp, bw.sn_tmp_tile, bw.sn_cap);
-    else
-      hipLaunchKernelGGL(k_l1_scatter<false>, dim3(nbc + nbs), dim3(256), lds1, s, M, T,
-                         has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc,
-                         hs, nbs, bw.cic_tmp, bw.cic_tmp_tile, bw.cic_cap,
-                         (const SnPk*)bw.sn_pk, bw.sn_tmp, bw.sn_tmp_tile, bw.sn_cap);
+#define PMP_L1S(OWN)                                                                        \
+  hipLaunchKernelGGL(k_l1_scatter<OWN>, dim3(nbc + nbs), dim3(256), lds1, s, M, T,            \
+                     has_c ? *cic : Particles{}, has_s ? *sn : Particles{}, S, nb, hc, nbc, hs, \
+                     nbs, bw.cic_tmp, bw.cic_tmp_tile, bw.cic_cap, (const SnPk*)bw.sn_pk,       \
+                     bw.sn_tmp, bw.sn_tmp_tile, bw.sn_cap)
+    if (!T.owner) PMP_L1S(0);
+    else if (M.own_start == nullptr) PMP_L1S(2);
+    else PMP_L1S(1);
+#undef PMP_L1S
   }
   // level 2: balanced slices of every bucket, both kinds
   L2Geom G;
