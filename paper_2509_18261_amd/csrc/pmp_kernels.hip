@@ -1949,30 +1949,35 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
   // kept as scalars; then each box's record again, from the cache)
   int i0 = -1, i1 = -1, i2 = -1, i3 = -1, d0 = 0, d1 = 0, d2 = 0, d3 = 0, count = 0;
   bool general = false;
-#pragma unroll 1
-  for (int d = 0; d < 27 && !general; ++d) {
-    const int pd[3] = {d % 3, (d / 3) % 3, d / 9};
-    bool any = true;
+  // per axis the range meets a run of the parts below (0), inside (1) and
+  // above (2) the box: only those directions are visited
+  int plo[3], phi[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int lo_in = B.lo[a], hi_in = B.lo[a] + B.n[a] - 1;
-      any = any && (pd[a] == 0 ? gl[a] < lo_in
-                               : (pd[a] == 1 ? gl[a] <= hi_in && gh[a] >= lo_in : gh[a] > hi_in));
-    }
-    if (!any) continue;
-    const int id = T.nbr[27 * b + d].id;
-    if (id == -1) continue;  // no box owns cells there
-    if (id == -2 || count == 4) {
-      general = general || id == -2 || (id != i0 && id != i1 && id != i2 && id != i3);
-      continue;
-    }
-    if (id == i0 || id == i1 || id == i2 || id == i3) continue;
-    if (count == 0) { i0 = id; d0 = d; }
-    else if (count == 1) { i1 = id; d1 = d; }
-    else if (count == 2) { i2 = id; d2 = d; }
-    else { i3 = id; d3 = d; }
-    ++count;
+  for (int a = 0; a < 3; ++a) {
+    const int lo_in = B.lo[a], hi_in = B.lo[a] + B.n[a] - 1;
+    plo[a] = gl[a] < lo_in ? 0 : (gl[a] <= hi_in ? 1 : 2);
+    phi[a] = gh[a] > hi_in ? 2 : (gh[a] >= lo_in ? 1 : 0);
   }
+#pragma unroll 1
+  for (int pz = plo[2]; pz <= phi[2]; ++pz)
+#pragma unroll 1
+    for (int py = plo[1]; py <= phi[1]; ++py)
+#pragma unroll 1
+      for (int px = plo[0]; px <= phi[0]; ++px) {
+        const int d = (pz * 3 + py) * 3 + px;
+        const int id = T.nbr[27 * b + d].id;
+        if (id == -1) continue;  // no box owns cells there
+        if (id == -2 || count == 4) {
+          general = general || id == -2 || (id != i0 && id != i1 && id != i2 && id != i3);
+          continue;
+        }
+        if (id == i0 || id == i1 || id == i2 || id == i3) continue;
+        if (count == 0) { i0 = id; d0 = d; }
+        else if (count == 1) { i1 = id; d1 = d; }
+        else if (count == 2) { i2 = id; d2 = d; }
+        else { i3 = id; d3 = d; }
+        ++count;
+      }
   if (general) {
     owner_tiles(M, T, gl, gh, f);
     return;
