@@ -2419,8 +2419,10 @@ __device__ __forceinline__ void l1_sn_scatter(int blk, const Mesh& M, const Tile
 
 // Level 1 for both kinds in one launch: blocks [0, nbc) take CIC chunks,
 // the rest supernova chunks.
+// (register budgets: the owner-tile variants' neighbour lookups would
+// otherwise cost a wave per SIMD; the padded variants fit them already)
 template <int OWN>
-__global__ __launch_bounds__(256) void k_l1_hist(Mesh M, TileGrid T, Particles C, Particles Sn,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_l1_hist(Mesh M, TileGrid T, Particles C, Particles Sn,
                                                 int shift, int nb, int* __restrict__ hc, int nbc,
                                                 int* __restrict__ hs, int nbs,
                                                 const SnPk* __restrict__ pk) {
@@ -2431,7 +2433,7 @@ __global__ __launch_bounds__(256) void k_l1_hist(Mesh M, TileGrid T, Particles C
 }
 
 template <int OWN>
-__global__ __launch_bounds__(256) void k_l1_scatter(Mesh M, TileGrid T, Particles C,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_l1_scatter(Mesh M, TileGrid T, Particles C,
                                                    Particles Sn, int shift, int nb,
                                                    int* __restrict__ hc, int nbc,
                                                    int* __restrict__ hs, int nbs,
