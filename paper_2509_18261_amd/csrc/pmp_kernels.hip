@@ -2587,10 +2587,44 @@ __device__ __forceinline__ void l2_scatter_slice(int qg, int kind, const L2Geom&
     if (q == 0 && f < nf) off[t0 + f] = v;
   }
   __syncthreads();
-  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const int tl = tmp_tile[e];
-    const int pos = atomicAdd(h + (tl - t0), 1);
-    if (pos < cap) rec[pos] = tmp[e];
+  // four entries per thread in flight: their tiles and records are loaded
+  // together, then ranked and stored
+  // (records as plain scalars: arrays of vector-type records would live in
+  // scratch)
+  constexpr int U = 4;
+  constexpr bool QUAD = std::is_same<Rec, double4>::value;
+  const long long stride = blockDim.x;
+  for (long long e = e0 + threadIdx.x; e < e1; e += U * stride) {
+    int tl[U] = {0, 0, 0, 0};
+    double rx[U] = {0.0, 0.0, 0.0, 0.0}, ry[U] = {0.0, 0.0, 0.0, 0.0},
+           rz[U] = {0.0, 0.0, 0.0, 0.0}, rw[U] = {0.0, 0.0, 0.0, 0.0};
+    int ri[U] = {0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long eu = e + u * stride;
+      if (eu < e1) {
+        tl[u] = tmp_tile[eu];
+        if constexpr (QUAD) {
+          const double4 v = tmp[eu];
+          rx[u] = v.x;
+          ry[u] = v.y;
+          rz[u] = v.z;
+          rw[u] = v.w;
+        } else {
+          ri[u] = tmp[eu];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (e + u * stride < e1) {
+        const int pos = atomicAdd(h + (tl[u] - t0), 1);
+        if (pos < cap) {
+          if constexpr (QUAD) rec[pos] = make_double4(rx[u], ry[u], rz[u], rw[u]);
+          else rec[pos] = ri[u];
+        }
+      }
+    }
   }
   __syncthreads();
 }
