@@ -235,7 +235,10 @@ struct pmp_ctx {
   size_t acc_bytes() const { return acc == PMP_ACC_F32 ? 4 : 8; }
   TileGrid tiles(bool owner = false) const {
     TileGrid T;
-    for (int a = 0; a < 3; ++a) T.t[a] = tile_dims[a];
+    for (int a = 0; a < 3; ++a) {
+      T.t[a] = tile_dims[a];
+      T.ts[a] = __builtin_ctz((unsigned)tile_dims[a]);
+    }
     T.owner = owner ? 1 : 0;
     T.tile_prefix = owner ? d_otile_prefix : d_tile_prefix;
     T.tiles_axis = owner ? d_otiles_axis : d_tiles_axis;

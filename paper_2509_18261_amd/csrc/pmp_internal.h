@@ -151,7 +151,8 @@ struct alignas(16) NbrBox {
 };
 
 struct TileGrid {
-  int t[3];                       // tile edge per axis (TX, TY, TZ)
+  int t[3];                       // tile edge per axis (TX, TY, TZ), powers of two
+  int ts[3];                      // log2 t: a non-negative offset's tile is offset >> ts
   const long long* tile_prefix;   // [nbox+1] device
   const int* tiles_axis;          // [nbox][3] device: tiles per axis
   const TileGeo* geo;             // [ntiles] device

@@ -1744,12 +1744,12 @@ __device__ __forceinline__ bool tile_range(const DevBox& B, const TileGrid& T, c
     if (l > h) return false;
     if (a == 0) {
       // x boundaries at gx + k TX; the first and last tiles take the ghosts
-      const int ntx = (B.n[0] + T.t[0] - 1) / T.t[0];
-      tlo[0] = min(max(l - T.gx, 0) / T.t[0], ntx - 1);
-      thi[0] = min(max(h - T.gx, 0) / T.t[0], ntx - 1);
+      const int ntx = (B.n[0] + T.t[0] - 1) >> T.ts[0];
+      tlo[0] = min(max(l - T.gx, 0) >> T.ts[0], ntx - 1);
+      thi[0] = min(max(h - T.gx, 0) >> T.ts[0], ntx - 1);
     } else {
-      tlo[a] = l / T.t[a];
-      thi[a] = h / T.t[a];
+      tlo[a] = l >> T.ts[a];
+      thi[a] = h >> T.ts[a];
     }
   }
   return true;
@@ -1795,8 +1795,8 @@ __device__ __forceinline__ void owner_tiles(const Mesh& M, const TileGrid& T, co
     int tlo[3], thi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      tlo[a] = (il[a] - B.lo[a]) / T.t[a];
-      thi[a] = (ih[a] - B.lo[a]) / T.t[a];
+      tlo[a] = (il[a] - B.lo[a]) >> T.ts[a];
+      thi[a] = (ih[a] - B.lo[a]) >> T.ts[a];
     }
     for (int tz = tlo[2]; tz <= thi[2]; ++tz)
       for (int ty = tlo[1]; ty <= thi[1]; ++ty)
@@ -1866,8 +1866,8 @@ __device__ __forceinline__ void owner_tiles_of(const Mesh& M, const NbrBox& R, c
     for (int k = -1; k <= 1; ++k) {
       const int l = max(lo[a] + k * D, R.lo[a]), h = min(hi[a] + k * D, R.lo[a] + R.n[a] - 1);
       if (l <= h && np[a] < 2) {
-        tl[a][np[a]] = (l - R.lo[a]) / T.t[a];
-        th[a][np[a]] = (h - R.lo[a]) / T.t[a];
+        tl[a][np[a]] = (l - R.lo[a]) >> T.ts[a];
+        th[a][np[a]] = (h - R.lo[a]) >> T.ts[a];
         ++np[a];
       }
     }
@@ -1917,8 +1917,8 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
     int tlo[3], thi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      tlo[a] = (gl[a] - B.lo[a]) / T.t[a];
-      thi[a] = (gh[a] - B.lo[a]) / T.t[a];
+      tlo[a] = (gl[a] - B.lo[a]) >> T.ts[a];
+      thi[a] = (gh[a] - B.lo[a]) >> T.ts[a];
     }
     for (int tz = tlo[2]; tz <= thi[2]; ++tz)
       for (int ty = tlo[1]; ty <= thi[1]; ++ty)
@@ -2133,8 +2133,8 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         home = home && lo[a] >= g && hi[a] < B.n[a] + g;
-        tlo[a] = (lo[a] - g) / T.t[a];
-        thi[a] = (hi[a] - g) / T.t[a];
+        tlo[a] = (lo[a] - g) >> T.ts[a];  // used only when home (offsets >= 0)
+        thi[a] = (hi[a] - g) >> T.ts[a];
       }
       if (!home) {
         slow |= 1u << u;
