@@ -241,6 +241,8 @@ __host__ __device__ constexpr long long tile_lds_bytes(int tx, int tyz, int g, b
 }
 
 constexpr int kBinChunkCic = 1024;  // CIC particles per level-1 block
+constexpr int kChunkBits = 10;      // log2 kBinChunkCic
+static_assert(kBinChunkCic == 1 << kChunkBits, "chunk bits");
 constexpr int kBinChunkSn = 256;    // supernovae per level-1 block (one per thread)
 
 // Kernel launchers: all enqueue on `s` and return hipError_t of the launch.

@@ -1891,7 +1891,7 @@ __device__ __forceinline__ void owner_tiles_of(const Mesh& M, const NbrBox& R, c
 template <int OWN, class F>
 __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T, int b,
                                                const DevBox& B, const int lo[3], const int hi[3],
-                                               F&& f) {
+                                               F&& f, const NbrBox* nbr = nullptr) {
   if constexpr (!OWN) {
     int tlo[3], thi[3];
     if (!tile_range(B, T, lo, hi, tlo, thi)) return;
@@ -1947,6 +1947,8 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
   // found, the owner index takes the whole range.
   // (first the directions and their box ids, at most four distinct boxes
   // kept as scalars; then each box's record again, from the cache)
+  // box b's 27 records (nbr: a copy staged in LDS by the caller)
+  const NbrBox* nb = nbr ? nbr : T.nbr + 27 * b;
   int i0 = -1, i1 = -1, i2 = -1, i3 = -1, d0 = 0, d1 = 0, d2 = 0, d3 = 0, count = 0;
   bool general = false;
   // per axis the range meets a run of the parts below (0), inside (1) and
@@ -1965,7 +1967,7 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
 #pragma unroll 1
       for (int px = plo[0]; px <= phi[0]; ++px) {
         const int d = (pz * 3 + py) * 3 + px;
-        const int id = T.nbr[27 * b + d].id;
+        const int id = nb[d].id;
         if (id == -1) continue;  // no box owns cells there
         if (id == -2 || count == 4) {
           general = general || id == -2 || (id != i0 && id != i1 && id != i2 && id != i3);
@@ -1985,7 +1987,7 @@ __device__ __forceinline__ void particle_tiles(const Mesh& M, const TileGrid& T,
 #pragma unroll 1
   for (int q = 0; q < count; ++q) {
     const int d = q == 0 ? d0 : (q == 1 ? d1 : (q == 2 ? d2 : d3));
-    const NbrBox R = T.nbr[27 * b + d];
+    const NbrBox R = nb[d];
     owner_tiles_of(M, R, T, gl, gh, f);
   }
   }
@@ -2082,12 +2084,25 @@ __device__ __forceinline__ int hist_col(int blk, int nblk) {
   return x * k + min(x, r) + (blk >> 3);
 }
 
+// Owner tiles on several boxes: a level-1 block stages the neighbour records
+// of its first kNbrCache boxes in LDS, so that the lookups of stencils that
+// leave their box read LDS instead of waiting on global loads.
+constexpr int kNbrCache = 4;
+__device__ __forceinline__ void stage_nbr(const TileGrid& T, int bb0, int bb1, NbrBox* s) {
+  const int n = 27 * min(bb1 - bb0 + 1, kNbrCache);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = T.nbr[27 * bb0 + i];
+}
+__device__ __forceinline__ const NbrBox* nbr_of(const TileGrid& T, const NbrBox* s, int bb0,
+                                                int b) {
+  return (b - bb0 < kNbrCache) ? s + 27 * (b - bb0) : T.nbr + 27 * b;
+}
+
 template <bool SCATTER, int OWN>
 __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T,
                                        const Particles& P, int shift, int nb,
                                        int* __restrict__ hist, int nblk,
                                        double4* __restrict__ tmp, int* __restrict__ tmp_tile,
-                                       long long cap) {
+                                       long long cap, NbrBox* s_nbr) {
   extern __shared__ int h[];
   const int g = M.ghost;
   const int col = hist_col(blk, nblk);
@@ -2100,6 +2115,7 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
   const long long p1 = min(p0 + kBinChunkCic, P.n);
   int bb0, bb1;
   block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
+  if constexpr (OWN == 1) stage_nbr(T, bb0, bb1, s_nbr);  // read after the barriers below
   bool outside = false, nan = false, full = false;
   constexpr int UNR = kBinChunkCic / 256;
   // the thread's particles are loaded together, then binned one by one
@@ -2115,6 +2131,7 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
     }
   }
   unsigned slow = 0;  // owner tiles: particles whose stencil leaves their box
+  int sbox[UNR] = {};  // and their boxes (offsets from bb0)
 #pragma unroll
   for (int u = 0; u < UNR; ++u) {
     const long long p = p0 + threadIdx.x + (long long)u * blockDim.x;
@@ -2138,6 +2155,7 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
       }
       if (!home) {
         slow |= 1u << u;
+        sbox[u] = b - bb0;
         continue;
       }
     } else {
@@ -2169,14 +2187,16 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
       int at = atomicAdd(&s_nslow, __popc(slow));
 #pragma unroll
       for (int u = 0; u < UNR; ++u)
-        if ((slow >> u) & 1u) s_slow[at++] = (int)threadIdx.x + u * (int)blockDim.x;
+        if ((slow >> u) & 1u)
+          s_slow[at++] = ((int)threadIdx.x + u * (int)blockDim.x) | (sbox[u] << kChunkBits);
     }
     __syncthreads();
     const int nslow = s_nslow;
 #pragma unroll 1
     for (int i = threadIdx.x; i < nslow; i += blockDim.x) {
-      const long long p = p0 + s_slow[i];
-      const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
+      const int sv = s_slow[i];
+      const long long p = p0 + (sv & (kBinChunkCic - 1));
+      const int b = bb0 + (sv >> kChunkBits);
       const DevBox B = M.boxes[b];
       const double x = P.x[p], y = P.y[p], z = P.z[p], m = P.a[p];
       int lo[3], hi[3];
@@ -2191,7 +2211,7 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
             full = true;
           }
         }
-      });
+      }, OWN == 1 ? nbr_of(T, s_nbr, bb0, b) : nullptr);
     }
   }
   if (!SCATTER) {
@@ -2210,7 +2230,7 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
 template <int OWN, class F>
 __device__ __forceinline__ void sn_tiles(const Mesh& M, const TileGrid& T, int b,
                                          const DevBox& B, double x, double y, double z,
-                                         double r, int N, F&& f) {
+                                         double r, int N, F&& f, const NbrBox* nbr = nullptr) {
   const int g = M.ghost;
   int slo[3], shi[3];
   if (N < 0) {
@@ -2219,7 +2239,7 @@ __device__ __forceinline__ void sn_tiles(const Mesh& M, const TileGrid& T, int b
   } else {
     sphere_box(B, g, x, y, z, r, slo, shi);
   }
-  particle_tiles<OWN>(M, T, b, B, slo, shi, f);
+  particle_tiles<OWN>(M, T, b, B, slo, shi, f, nbr);
 }
 
 // Supernova members, before binning: L lanes per particle (256 / L particles
@@ -2358,7 +2378,7 @@ template <int OWN>
 __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGrid& T,
                                            const Particles& P, int shift, int nb,
                                            int* __restrict__ hist, int nblk,
-                                           const SnPk* __restrict__ pk) {
+                                           const SnPk* __restrict__ pk, NbrBox* s_nbr) {
   extern __shared__ int h[];
   const int col = hist_col(blk, nblk);
   for (int c = threadIdx.x; c < nb; c += blockDim.x) h[c] = 0;
@@ -2366,6 +2386,7 @@ __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGri
   const long long p1 = min(p0 + kBinChunkSn, P.n);
   int bb0, bb1;
   block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
+  if constexpr (OWN == 1) stage_nbr(T, bb0, bb1, s_nbr);
   __syncthreads();
   for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
     const SnPk& R = pk[p];
@@ -2374,7 +2395,8 @@ __device__ __forceinline__ void l1_sn_hist(int blk, const Mesh& M, const TileGri
     const int b = (bb0 == bb1) ? bb0 : find_box_in(P.box_off, bb0, bb1, p);
     const DevBox B = M.boxes[b];
     sn_tiles<OWN>(M, T, b, B, R.x, R.y, R.z, R.r, N,
-                  [&](int t) { atomicAdd(h + (t >> shift), 1); });
+                  [&](int t) { atomicAdd(h + (t >> shift), 1); },
+                  OWN == 1 ? nbr_of(T, s_nbr, bb0, b) : nullptr);
   }
   __syncthreads();
   for (int c = threadIdx.x; c < nb; c += blockDim.x) hist[(long long)c * nblk + col] = h[c];
@@ -2387,7 +2409,8 @@ __device__ __forceinline__ void l1_sn_scatter(int blk, const Mesh& M, const Tile
                                               const Particles& P, int shift, int nb,
                                               int* __restrict__ hist, int nblk,
                                               const SnPk* __restrict__ pk, int* __restrict__ tmp,
-                                              int* __restrict__ tmp_tile, long long cap) {
+                                              int* __restrict__ tmp_tile, long long cap,
+                                              NbrBox* s_nbr) {
   extern __shared__ int h[];
   const int col = hist_col(blk, nblk);
   for (int c = threadIdx.x; c < nb; c += blockDim.x)
@@ -2396,6 +2419,7 @@ __device__ __forceinline__ void l1_sn_scatter(int blk, const Mesh& M, const Tile
   const long long p1 = min(p0 + kBinChunkSn, P.n);
   int bb0, bb1;
   block_box_range(P.box_off, M.nbox, p0, p1, bb0, bb1);
+  if constexpr (OWN == 1) stage_nbr(T, bb0, bb1, s_nbr);
   __syncthreads();
   bool full = false;
   for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
@@ -2412,7 +2436,7 @@ __device__ __forceinline__ void l1_sn_scatter(int blk, const Mesh& M, const Tile
       } else {
         full = true;
       }
-    });
+    }, OWN == 1 ? nbr_of(T, s_nbr, bb0, b) : nullptr);
   }
   if (full) raise_flag(M.status, PMP_FLAG_CAPACITY);
 }
@@ -2426,10 +2450,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
                                                 int shift, int nb, int* __restrict__ hc, int nbc,
                                                 int* __restrict__ hs, int nbs,
                                                 const SnPk* __restrict__ pk) {
+  __shared__ NbrBox s_nbr[OWN == 1 ? 27 * kNbrCache : 1];
   if ((int)blockIdx.x < nbc)
-    l1_cic<false, OWN>(blockIdx.x, M, T, C, shift, nb, hc, nbc, nullptr, nullptr, 0);
+    l1_cic<false, OWN>(blockIdx.x, M, T, C, shift, nb, hc, nbc, nullptr, nullptr, 0, s_nbr);
   else
-    l1_sn_hist<OWN>(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk);
+    l1_sn_hist<OWN>(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk, s_nbr);
 }
 
 template <int OWN>
@@ -2442,10 +2467,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
                                                    const SnPk* __restrict__ pk,
                                                    int* __restrict__ stmp,
                                                    int* __restrict__ stmp_tile, long long scap) {
+  __shared__ NbrBox s_nbr[OWN == 1 ? 27 * kNbrCache : 1];
   if ((int)blockIdx.x < nbc)
-    l1_cic<true, OWN>(blockIdx.x, M, T, C, shift, nb, hc, nbc, ctmp, ctmp_tile, ccap);
+    l1_cic<true, OWN>(blockIdx.x, M, T, C, shift, nb, hc, nbc, ctmp, ctmp_tile, ccap, s_nbr);
   else
-    l1_sn_scatter<OWN>(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk, stmp, stmp_tile, scap);
+    l1_sn_scatter<OWN>(blockIdx.x - nbc, M, T, Sn, shift, nb, hs, nbs, pk, stmp, stmp_tile, scap,
+                       s_nbr);
 }
 
 // Level 2: one workgroup per coarse bucket sorts the bucket's records by
