@@ -3117,23 +3117,33 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) void 
 // reach is flagged (the kernel's cells lie within floor(r_K) + 1 cells of the
 // host cell; the cube is widened by one more, and a flag too many only moves
 // a tile's apply after the sink update).  Sinks outside their box are left
-// to the deposit kernel, which flags them.
+// to the deposit kernel, which flags them.  kSinkPlaneLanes threads per
+// sink, each taking every kSinkPlaneLanes-th z plane of the sink's cube (the
+// planes' tiles together are the cube's), so that sinks whose cube meets
+// several boxes are not walked by one thread each.
+constexpr int kSinkPlaneLanes = 16;
 __global__ __launch_bounds__(256) void k_sink_tiles(Mesh M, TileGrid T, Particles P, int reach,
                                                    int* __restrict__ flag) {
   const int g = M.ghost;
-  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < P.n;
-       s += (long long)gridDim.x * blockDim.x) {
+  const int side = 2 * reach + 3;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < P.n * kSinkPlaneLanes;
+       q += (long long)gridDim.x * blockDim.x) {
+    const long long s = q / kSinkPlaneLanes;
+    const int lane = (int)(q % kSinkPlaneLanes);
     const int b = particle_box(P.box_off, M.nbox, s);
     const DevBox B = M.boxes[b];
     int h[3];
     if (!host_cell(B, P.x[s], P.y[s], P.z[s], h)) continue;
     int lo[3], hi[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 2; ++a) {
       lo[a] = h[a] - reach - 1 - B.lo[a] + g;
       hi[a] = h[a] + reach + 1 - B.lo[a] + g;
     }
-    particle_tiles<1>(M, T, b, B, lo, hi, [&](int t) { flag[t] = 1; });
+    for (int dz = lane; dz < side; dz += kSinkPlaneLanes) {
+      lo[2] = hi[2] = h[2] - reach - 1 + dz - B.lo[2] + g;
+      particle_tiles<1>(M, T, b, B, lo, hi, [&](int t) { flag[t] = 1; });
+    }
   }
 }
 
@@ -3358,8 +3368,8 @@ hipError_t launch_sink_tiles(const Mesh& M, const TileGrid& T, const Particles& 
   hipError_t e = launch_zero(flag, T.ntiles * (long long)sizeof(int), 256, s);
   if (e != hipSuccess || sinks.n <= 0) return e;
   const int reach = (int)floor(r_k) + 1;
-  hipLaunchKernelGGL(k_sink_tiles, dim3(grid_for(sinks.n, 256, M.num_cu * 4)), dim3(256), 0, s, M,
-                     T, sinks, reach, flag);
+  hipLaunchKernelGGL(k_sink_tiles, dim3(grid_for(sinks.n * kSinkPlaneLanes, 256, M.num_cu * 16)),
+                     dim3(256), 0, s, M, T, sinks, reach, flag);
   return hipGetLastError();
 }
 
