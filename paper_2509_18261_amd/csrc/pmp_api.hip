@@ -842,10 +842,10 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
                     cic_cap > c->bw.cic_cap || sn_cap > c->bw.sn_cap || n_sn > c->bw_nsn ||
                     hist2 > c->bw_hist2 || 2 * nb + 1 > c->bw_slice_base ||
                     partial > c->bw_partial;
-  if (!grow) {
-    c->bw.max_slices = (c->bw_hist2 - 1) >> shift;
-    return PMP_OK;
-  }
+  // launches are sized by this deposit's slices, not by the scratch's
+  // capacity (which keeps the largest size seen)
+  c->bw.max_slices = (hist2 - 1) >> shift;
+  if (!grow) return PMP_OK;
   if (capturing(s)) return fail(PMP_EINVAL, "binned-deposit scratch must be sized before capture");
   PMP_HIP(hipStreamSynchronize(s));
   BinWork& w = c->bw;
@@ -901,7 +901,6 @@ int ensure_bin_work(pmp_ctx* c, long long n_cic, long long n_sn, double r_max, h
     if (!rc) c->bw_nsn = n_sn;
   }
   if (rc) free_bin_work(c);  // a failed allocation leaves no half-sized scratch behind
-  else c->bw.max_slices = (c->bw_hist2 - 1) >> shift;
   return rc;
 }
 
@@ -1915,8 +1914,12 @@ int pmp_autotune(pmp_ctx* c, void* state, void* buf, const pmp_cic* cic, const p
       best_t = cand_t;
     }
   };
-  // stage 1: path, tile shape, workgroup size, fused apply
+  // stage 1: path, tile shape, workgroup size, fused apply; the list is
+  // timed twice, forwards then backwards, and each candidate keeps its better
+  // time (a single timing of the best shape was now and then slow enough to
+  // lose to a shape 8% slower)
   for (size_t i = 0; i < cand.size() && rc == PMP_OK; ++i) time_one(cand[i]);
+  for (size_t i = cand.size(); i-- > 0 && rc == PMP_OK;) time_one(cand[i]);
   // stage 2, binned path: the split thresholds (clustered inputs) and the
   // persistent grid cap, around the stage-1 winner
   if (rc == PMP_OK && best_t.deposit_path == 1) {
