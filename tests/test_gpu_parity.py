@@ -253,6 +253,35 @@ def test_launch_shape_invariance_fixed_point(B, orc):
         assert np.array_equal(base["state"], other["state"])
 
 
+def test_scratch_grown_by_another_shape(B, orc):
+    """One context bins with a many-tile shape first (its scratch grows to
+    that shape's histograms), then with a large-tile shape: the second
+    deposit's launches are sized by its own slices, and its buffer equals the
+    oracle's and a fresh context's bit for bit (fixed point)."""
+    import torch
+    w = W.c4(nx=48)
+    small = {"deposit_path": 1, "tile_x": 16, "tile_yz": 2}
+    large = {"deposit_path": 1, "tile_x": 64, "tile_yz": 8}
+    ctx = B.Context(w, "fix64")
+    ctx.set_tuning(**small)
+    ctx.deposit()
+    first = ctx.buf.cpu().numpy().copy()
+    ctx.set_tuning(**large)
+    ctx.deposit()
+    torch.cuda.synchronize()
+    second = ctx.buf.cpu().numpy().copy()
+    fields = ctx.fields
+    st = ctx.status()
+    ctx.close()
+    assert st["flags"] in (0, 0x10), st
+    assert np.array_equal(first, second)
+    got = expand_channels(w, second, fields)
+    fresh = run_gpu(B, w, "fix64", tuning=large)
+    assert np.array_equal(got, fresh["buf_deposit"])
+    ref = orc.step(w, "fix64", want_eta=False)
+    assert np.array_equal(got, ref["buf_deposit"])
+
+
 def test_tiled_paths_multibox(B, orc):
     """Tile shapes on an uneven multi-box layout, every mode against the oracle."""
     w = W.c5(nb=3, n_total=20000)
