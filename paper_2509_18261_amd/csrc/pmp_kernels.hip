@@ -2183,12 +2183,16 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
     __shared__ int s_nslow;
     if (threadIdx.x == 0) s_nslow = 0;
     __syncthreads();
+    // the box offset rides in the high bits when the block's box range fits
+    // them (block-uniform), else the box is searched again
+    const bool packed = bb1 - bb0 < (1 << (31 - kChunkBits));
     if (slow) {
       int at = atomicAdd(&s_nslow, __popc(slow));
 #pragma unroll
       for (int u = 0; u < UNR; ++u)
         if ((slow >> u) & 1u)
-          s_slow[at++] = ((int)threadIdx.x + u * (int)blockDim.x) | (sbox[u] << kChunkBits);
+          s_slow[at++] =
+              ((int)threadIdx.x + u * (int)blockDim.x) | (packed ? sbox[u] << kChunkBits : 0);
     }
     __syncthreads();
     const int nslow = s_nslow;
@@ -2196,7 +2200,7 @@ __device__ __forceinline__ void l1_cic(int blk, const Mesh& M, const TileGrid& T
     for (int i = threadIdx.x; i < nslow; i += blockDim.x) {
       const int sv = s_slow[i];
       const long long p = p0 + (sv & (kBinChunkCic - 1));
-      const int b = bb0 + (sv >> kChunkBits);
+      const int b = packed ? bb0 + (sv >> kChunkBits) : find_box_in(P.box_off, bb0, bb1, p);
       const DevBox B = M.boxes[b];
       const double x = P.x[p], y = P.y[p], z = P.z[p], m = P.a[p];
       int lo[3], hi[3];
