@@ -139,6 +139,10 @@ SMALL = {
     "c5sbh_4": lambda: W.c5s(nb=4, bondi=True),
     "c3tl_40": lambda: truelove(W.c3(nx=40, n_sink=48)),
     "c5sbhtl_4": lambda: truelove(W.c5s(nb=4, bondi=True), G=0.04),
+    # wide sink kernels (r_K = 7, ghost 7): the owner-tile sink flags walk
+    # 19 planes per sink, more than the 16 threads a sink gets
+    "c3_40_rk7": lambda: dataclasses.replace(W.c3(nx=40, n_sink=48), ghost=7, r_k=7.0,
+                                            r_gauss=3.0),
 }
 
 
@@ -559,7 +563,7 @@ def test_owner_tiles_not_in_reproducibility_mode(B):
     assert "fold" in phases, phases
 
 
-OWNER_SINK_CASES = ["c3_40", "c3bh_40", "c3tl_40", "c5s_4", "c5sbh_4", "c5sbhtl_4"]
+OWNER_SINK_CASES = ["c3_40", "c3bh_40", "c3tl_40", "c5s_4", "c5sbh_4", "c5sbhtl_4", "c3_40_rk7"]
 
 
 @pytest.mark.parametrize("acc", ["fix64", "f64", "f32"])
