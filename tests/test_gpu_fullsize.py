@@ -193,6 +193,8 @@ OWNER_FULL = {
     "c4": (lambda: (lambda w: w.with_state(w.state.astype(np.float64)))(W.c4()),
            {"tile_x": 64, "tile_yz": 4, "tile_block": 256}, ("fix64", "f64")),
     "c5": (W.c5, {"tile_x": 32, "tile_yz": 4, "tile_block": 128}, ("fix64", "f32")),
+    # with 1024 sinks across the boxes: flagged tiles applied after the sink update
+    "c5s": (W.c5s, {"tile_x": 32, "tile_yz": 4, "tile_block": 128}, ("fix64",)),
 }
 
 
